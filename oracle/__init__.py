@@ -1,0 +1,21 @@
+"""CPU oracle for mixed-precision iterative refinement on LSE / GLS problems.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute anything under this package: only the test-suite, the smoke check of
+the entry module and the CPU-baseline leg of the benchmark use it.  It shares
+no code with the HIP path.
+
+Modules
+-------
+direct   FP64 reference solutions: the null-space method via the generalized RQ
+         factorization for LSE and Paige's method via the generalized QR
+         factorization for GLS (Section 2), augmented residuals, the stopping
+         test quantities (eqs. lse-stop / gls-stop) and the accuracy metrics of
+         Tables 4-5.
+mpir     The paper's method itself on the CPU: Algorithms 1-4 (classical
+         iterative refinement with the correction solvers) and GMRES-based
+         refinement with the block-diagonal split preconditioners of
+         Section 5, using LAPACK single precision for the low-precision
+         factorization.
+"""
+from . import direct, mpir  # noqa: F401

@@ -1,0 +1,441 @@
+"""Pins for the CPU oracle: each check comes from something other than the
+oracle itself (dense KKT solves, LAPACK's xGGLSE, 50-digit arithmetic, closed
+forms, special cases, invariants, and constants printed in the paper)."""
+import math
+import os
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.linalg import lapack
+
+from oracle import direct, mpir
+from paper_2406_16499_amd import workloads as wl
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+
+def _rng(s):
+    return np.random.default_rng(s)
+
+
+def _kkt_lse(A, B, b, d):
+    m, n = A.shape
+    p = B.shape[0]
+    u = np.linalg.solve(direct.lse_augmented(A, B), np.concatenate([b, d, np.zeros(n)]))
+    return u[m + p:], u[:m], -u[m:m + p]
+
+
+def _kkt_gls(W, V, d):
+    n, m = W.shape
+    p = V.shape[1]
+    u = np.linalg.solve(direct.gls_augmented(W, V), np.concatenate([np.zeros(p), d, np.zeros(m)]))
+    return u[p + n:], u[:p], -u[p:p + n]
+
+
+def _rel(a, b):
+    s = max(np.max(np.abs(b)), 1e-300) if b.size else 1.0
+    return float(np.max(np.abs(a - b)) / s) if a.size else 0.0
+
+
+LSE_SHAPES = [(200, 100, 20), (30, 12, 4), (9, 9, 3), (5, 8, 3), (7, 7, 7), (40, 20, 1),
+              (6, 10, 4), (50, 16, 16), (64, 33, 31)]
+GLS_SHAPES = [(60, 20, 80), (12, 4, 30), (9, 9, 3), (8, 3, 5), (7, 7, 7), (40, 1, 40), (10, 4, 6)]
+
+
+# --------------------------------------------------------------- LSE ----
+
+@pytest.mark.parametrize("m,n,p", LSE_SHAPES)
+def test_lse_matches_dense_kkt(m, n, p):
+    P = wl.lse_gaussian(_rng(m * 1000 + n * 10 + p), m, n, p)
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    xk, rk, vk = _kkt_lse(P.A, P.B, P.b, P.d)
+    assert _rel(x, xk) < 1e-11
+    assert _rel(r, rk) < 1e-11 or np.max(np.abs(r - rk)) < 1e-11
+    assert np.max(np.abs(v - vk)) < 1e-10 * max(1.0, np.max(np.abs(vk)))
+
+
+@pytest.mark.parametrize("m,n,p", [(200, 100, 20), (30, 12, 4), (9, 9, 3), (5, 8, 3), (64, 33, 31)])
+def test_lse_matches_lapack_dgglse(m, n, p):
+    P = wl.lse_gaussian(_rng(7 + m + n + p), m, n, p)
+    x, _, _ = direct.lse_solve(P.A, P.B, P.b, P.d)
+    out = lapack.dgglse(P.A.copy(), P.B.copy(), P.b.copy(), P.d.copy())
+    assert out[-1] == 0
+    assert _rel(x, out[3]) < 1e-12
+
+
+def test_lse_mpmath_50_digits():
+    mpmath.mp.dps = 50
+    P = wl.lse_gaussian(_rng(3), 6, 4, 2)
+    m, n, p = P.shape
+    F = direct.lse_augmented(P.A, P.B)
+    rhs = np.concatenate([P.b, P.d, np.zeros(n)])
+    sol = mpmath.lu_solve(mpmath.matrix(F.tolist()), mpmath.matrix(rhs.tolist()))
+    exact = np.array([float(s) for s in sol])
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    cond = direct.lse_cond_x(P.A, P.B, x, r, v)
+    fwd = np.max(np.abs(x - exact[m + p:])) / np.max(np.abs(exact[m + p:]))
+    assert fwd <= 10 * cond * U
+    assert np.max(np.abs(r - exact[:m])) < 1e-13
+    assert np.max(np.abs(v + exact[m:m + p])) < 1e-13
+
+
+def test_lse_special_case_no_constraint_rows_is_least_squares():
+    # p = 0 reduces LSE to ordinary least squares
+    P = wl.lse_gaussian(_rng(4), 50, 12, 0)
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    xl = np.linalg.lstsq(P.A, P.b, rcond=None)[0]
+    assert _rel(x, xl) < 1e-12 and v.size == 0
+
+
+def test_lse_special_case_square_constraint():
+    # n = p: the constraint alone fixes x = B^{-1} d
+    P = wl.lse_gaussian(_rng(5), 20, 8, 8)
+    x, _, _ = direct.lse_solve(P.A, P.B, P.b, P.d)
+    assert _rel(x, np.linalg.solve(P.B, P.d)) < 1e-12
+
+
+def test_lse_consistent_system_has_zero_residual_and_multiplier():
+    # b = A x*, d = B x*  =>  x = x*, r = 0, v = 0 (closed form)
+    rng = _rng(6)
+    A = rng.standard_normal((30, 10))
+    B = rng.standard_normal((3, 10))
+    xs = rng.standard_normal(10)
+    x, r, v = direct.lse_solve(A, B, A @ xs, B @ xs)
+    assert _rel(x, xs) < 1e-13
+    assert np.max(np.abs(r)) < 1e-13 and np.max(np.abs(v)) < 1e-12
+
+
+@pytest.mark.parametrize("m,n,p", [(40, 20, 5), (8, 10, 4)])
+def test_lse_kkt_invariants_with_svd_nullspace(m, n, p):
+    P = wl.lse_gaussian(_rng(8 + n), m, n, p)
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    N = sla.null_space(P.B)                       # SVD basis, independent of the GRQ
+    g = N.T @ (P.A.T @ (P.A @ x - P.b))
+    assert np.max(np.abs(P.B @ x - P.d)) < 1e-12 * (np.linalg.norm(P.B) * np.linalg.norm(x) + 1)
+    assert np.max(np.abs(g)) < 1e-11 * np.linalg.norm(P.A) ** 2 * np.linalg.norm(x)
+    assert direct.lse_berr(P.A, P.B, P.b, P.d, x, r, v)[3] < 1e-15
+
+
+def test_grq_reconstructs():
+    P = wl.lse_gaussian(_rng(9), 30, 20, 6)
+    R, T, Z, Q = direct.grq(P.B, P.A)
+    assert np.allclose(np.tril(R, -1), 0) and np.allclose(np.tril(T, -1), 0)
+    Bp = np.hstack([np.zeros((6, 14)), R]) @ Q
+    assert np.max(np.abs(Bp - P.B)) < 1e-13
+    assert np.max(np.abs(Z @ T @ Q - P.A)) < 1e-13
+    assert np.max(np.abs(Q @ Q.T - np.eye(20))) < 1e-14
+
+
+# --------------------------------------------------------------- GLS ----
+
+@pytest.mark.parametrize("n,m,p", GLS_SHAPES)
+def test_gls_matches_dense_kkt(n, m, p):
+    G = wl.gls_gaussian(_rng(n * 100 + m * 10 + p), n, m, p)
+    x, y, z = direct.gls_solve(G.W, G.V, G.d)
+    xk, yk, zk = _kkt_gls(G.W, G.V, G.d)
+    assert _rel(x, xk) < 1e-11
+    assert np.max(np.abs(y - yk)) < 1e-11 * max(1.0, np.max(np.abs(yk)))
+    assert np.max(np.abs(z - zk)) < 1e-11 * max(1.0, np.max(np.abs(zk)))
+
+
+@pytest.mark.parametrize("n,m,p", [(60, 20, 80), (12, 4, 30), (10, 4, 6)])
+def test_gls_via_link_to_lse_through_dgglse(n, m, p):
+    # eq. link: GLS = LSE with A = [0, I_p], b = 0, B = [W, V]
+    G = wl.gls_gaussian(_rng(20 + n), n, m, p)
+    A = np.hstack([np.zeros((p, m)), np.eye(p)])
+    Bc = np.hstack([G.W, G.V])
+    out = lapack.dgglse(A.copy(order="F"), Bc.copy(order="F"), np.zeros(p), G.d.copy())
+    x, y, _ = direct.gls_solve(G.W, G.V, G.d)
+    assert out[-1] == 0
+    assert _rel(np.concatenate([x, y]), out[3]) < 1e-11
+
+
+def test_gls_weighted_least_squares_closed_form():
+    # square nonsingular V: x = (W^T O W)^{-1} W^T O d with O = (V V^T)^{-1}
+    rng = _rng(21)
+    n, m = 15, 5
+    W = rng.standard_normal((n, m))
+    V = rng.standard_normal((n, n)) + 4 * np.eye(n)
+    d = rng.standard_normal(n)
+    O = np.linalg.inv(V @ V.T)
+    xw = np.linalg.solve(W.T @ O @ W, W.T @ O @ d)
+    yw = np.linalg.solve(V, d - W @ xw)
+    x, y, z = direct.gls_solve(W, V, d)
+    assert _rel(x, xw) < 1e-10 and _rel(y, yw) < 1e-10
+
+
+def test_gls_identity_V_is_ordinary_least_squares():
+    rng = _rng(22)
+    W = rng.standard_normal((30, 6))
+    d = rng.standard_normal(30)
+    x, y, z = direct.gls_solve(W, np.eye(30), d)
+    xl = np.linalg.lstsq(W, d, rcond=None)[0]
+    assert _rel(x, xl) < 1e-12
+    assert _rel(y, d - W @ xl) < 1e-12
+
+
+def test_gls_square_W_gives_zero_y():
+    rng = _rng(23)
+    W = rng.standard_normal((6, 6))
+    V = rng.standard_normal((6, 4))
+    d = rng.standard_normal(6)
+    x, y, z = direct.gls_solve(W, V, d)
+    assert _rel(x, np.linalg.solve(W, d)) < 1e-12
+    assert np.max(np.abs(y)) < 1e-13 and np.max(np.abs(z)) < 1e-13
+
+
+def test_gls_invariants():
+    G = wl.gls_gaussian(_rng(24), 40, 10, 50)
+    x, y, z = direct.gls_solve(G.W, G.V, G.d)
+    assert np.max(np.abs(G.V.T @ z - y)) < 1e-12
+    assert np.max(np.abs(G.W.T @ z)) < 1e-12
+    assert direct.gls_berr(G.W, G.V, G.d, x, y, z)[3] < 1e-15
+
+
+def test_gls_mpmath_50_digits():
+    mpmath.mp.dps = 50
+    G = wl.gls_gaussian(_rng(25), 5, 2, 4)
+    n, m, p = G.shape
+    F = direct.gls_augmented(G.W, G.V)
+    rhs = np.concatenate([np.zeros(p), G.d, np.zeros(m)])
+    sol = mpmath.lu_solve(mpmath.matrix(F.tolist()), mpmath.matrix(rhs.tolist()))
+    ex = np.array([float(s) for s in sol])
+    x, y, z = direct.gls_solve(G.W, G.V, G.d)
+    cx, cy = direct.gls_cond_xy(G.W, G.V, x, y, z)
+    assert np.max(np.abs(x - ex[p + n:])) / np.max(np.abs(ex[p + n:])) <= 10 * cx * U
+    assert np.max(np.abs(y - ex[:p])) / np.max(np.abs(ex[:p])) <= 10 * cy * U
+
+
+def test_skeel_condition_hand_example():
+    # F = [[1,1],[0,1]], u = [1,1]: |F^-1||F||u| = [3, 1]
+    F = np.array([[1.0, 1.0], [0.0, 1.0]])
+    u = np.array([1.0, 1.0])
+    assert direct.skeel_cond_block(F, u, slice(0, 1)) == pytest.approx(3.0)
+    assert direct.skeel_cond_block(F, u, slice(1, 2)) == pytest.approx(1.0)
+
+
+def test_berr_scale_invariance_and_perturbation():
+    # berr is unchanged by scaling (A, b) by 2^k, and a perturbation of x by
+    # delta gives berr1 = ||A delta|| / scale1 to first order.
+    P = wl.lse_gaussian(_rng(26), 40, 10, 3)
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    dx = 1e-6 * _rng(27).standard_normal(10)
+    e = direct.lse_berr(P.A, P.B, P.b, P.d, x + dx, r, v)
+    s1 = np.linalg.norm(P.b) + np.linalg.norm(r) + np.linalg.norm(P.A) * np.linalg.norm(x + dx)
+    assert e[0] == pytest.approx(np.linalg.norm(P.A @ dx) / s1, rel=1e-6)
+    e8 = direct.lse_berr(8 * P.A, P.B, 8 * P.b, P.d, x + dx, 8 * r, 8 * v)
+    assert e8[0] == pytest.approx(e[0], rel=1e-12)
+
+
+# ------------------------------------------------- correction solvers ----
+
+def _ensure_lse(A, B, f, out):
+    dr, dv, dx = out
+    F = direct.lse_augmented(A, B)
+    return np.linalg.norm(F @ np.concatenate([dr, -dv, dx]) - np.concatenate(f))
+
+
+def _ensure_gls(W, V, f, out):
+    dy, dz, dx = out
+    F = direct.gls_augmented(W, V)
+    return np.linalg.norm(F @ np.concatenate([dy, -dz, dx]) - np.concatenate(f))
+
+
+@pytest.mark.parametrize("m,n,p", [(30, 12, 4), (9, 9, 3), (5, 8, 3), (20, 6, 6)])
+def test_algorithm1_ensure_identity_fp64(m, n, p):
+    P = wl.lse_gaussian(_rng(30 + m), m, n, p)
+    R, T, Z, Q = mpir.grq_factors(P.B, P.A, np.float64)
+    rng = _rng(31)
+    f = (rng.standard_normal(m), rng.standard_normal(p), rng.standard_normal(n))
+    out = mpir.correction_lse(R, T, Z, Q, *f, us=np.float64)
+    assert _ensure_lse(P.A, P.B, f, out) < 1e-12
+
+
+@pytest.mark.parametrize("n,m,p", [(12, 4, 30), (9, 9, 3), (8, 3, 5), (10, 4, 6)])
+def test_algorithm3_ensure_identity_fp64(n, m, p):
+    G = wl.gls_gaussian(_rng(40 + n), n, m, p)
+    R, T, Q, Z = mpir.gqr_factors(G.W, G.V, np.float64)
+    rng = _rng(41)
+    f = (rng.standard_normal(p), rng.standard_normal(n), rng.standard_normal(m))
+    out = mpir.correction_gls(R, T, Q, Z, *f, us=np.float64)
+    assert _ensure_gls(G.W, G.V, f, out) < 1e-12
+
+
+def test_algorithm3_as_printed_fails_ensure(monkeypatch):
+    """Planted mistakes: the printed T22^H in line 4 and the printed sign of
+    x2 each break the ENSURE identity, so the pins above would catch them."""
+    G = wl.gls_gaussian(_rng(42), 12, 4, 30)
+    R, T, Q, Z = mpir.gqr_factors(G.W, G.V, np.float64)
+    rng = _rng(43)
+    f = (rng.standard_normal(30), rng.standard_normal(12), rng.standard_normal(4))
+    dy, dz, dx = mpir.correction_gls(R, T, Q, Z, *f, us=np.float64)
+    assert _ensure_gls(G.W, G.V, f, (dy, -dz, dx)) > 1e-3        # printed sign
+    orig = mpir._ut
+    calls = {"n": 0}
+
+    def wrong(Tm, rhs, trans=False):
+        calls["n"] += 1
+        if calls["n"] == 2:                                       # line 4 as printed
+            return orig(Tm, rhs, trans=True)
+        return orig(Tm, rhs, trans)
+    monkeypatch.setattr(mpir, "_ut", wrong)
+    out = mpir.correction_gls(R, T, Q, Z, *f, us=np.float64)
+    assert _ensure_gls(G.W, G.V, f, out) > 1e-3
+
+
+def test_gls_z0_with_transposed_Q_fails_invariants():
+    """The printed z0 = Q^H [0; v] violates W^T z = 0; Q [0; v] satisfies it."""
+    G = wl.gls_gaussian(_rng(44), 12, 4, 30)
+    n, m, p = G.shape
+    R, T, Q, Z = direct.gqr(G.W, G.V)
+    x, y, z = direct.gls_solve(G.W, G.V, G.d)
+    T22 = T[m:, p - n + m:]
+    vv = sla.solve_triangular(T22, (Z @ y)[p - n + m:], trans="T")
+    z_printed = Q.T @ np.concatenate([np.zeros(m), vv])
+    assert np.linalg.norm(G.W.T @ z_printed) > 1e-3
+    assert np.linalg.norm(G.W.T @ z) < 1e-12
+
+
+# ------------------------------------------------ Algorithms 2 and 4 ----
+
+def test_mplse_fp32_reaches_fp64_backward_error():
+    P = wl.config1()
+    res = mpir.mplse(P.A, P.B, P.b, P.d, np.float32, tol=1e-14)
+    assert res.converged and res.steps <= 3
+    assert direct.lse_berr(P.A, P.B, P.b, P.d, res.x, res.aux1, res.aux2)[3] <= 1e-14
+    x, _, _ = direct.lse_solve(P.A, P.B, P.b, P.d)
+    cond = direct.lse_cond_x(P.A, P.B, x, res.aux1, res.aux2)
+    berr = res.berr_history[-1]
+    # forward error to first order: cond_x times the backward error reached
+    assert _rel(res.x, x) <= 10 * cond * max(U, berr)
+
+
+def test_mpgls_fp32_reaches_fp64_backward_error():
+    G = wl.gls_gaussian(_rng(50), 60, 20, 80)
+    res = mpir.mpgls(G.W, G.V, G.d, np.float32, tol=1e-14)
+    assert res.converged and res.steps <= 4
+    assert direct.gls_berr(G.W, G.V, G.d, res.x, res.aux1, res.aux2)[3] <= 1e-14
+
+
+def _table(name):
+    rows = {}
+    with open(os.path.join(GOLD, name)) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            meth, kap, e1, e2, it = line.split()
+            rows.setdefault(meth, []).append((float(kap), int(it)))
+    return rows
+
+
+def test_classical_ir_trend_matches_tables_4_and_5():
+    """Tables 4-5: with single-precision factors classical refinement converges
+    in a few steps for kappa <= 1e5, needs more at 1e7 and diverges at 1e9.
+    The matrix size is not stated, so only the trend is pinned."""
+    t4 = _table("table4_mplse.txt")["MPLSE"]
+    t5 = _table("table5_mpgls.txt")["MPGLS"]
+    got_l, got_g = [], []
+    for kap, _ in t4:
+        L = wl.lse_paper_pair(_rng(11), 512, 128, 8, kap)
+        a = mpir.mplse(L.A, L.B, L.b, L.d, tol=1e-13)
+        got_l.append(a.steps if a.converged else -1)
+        G = wl.gls_paper_pair(_rng(12), 128, 8, 512, kap)
+        g = mpir.mpgls(G.W, G.V, G.d, tol=1e-13)
+        got_g.append(g.steps if g.converged else -1)
+    for got, ref in ((got_l, t4), (got_g, t5)):
+        assert [g == -1 for g in got] == [r[1] == -1 for r in ref]
+        conv = [g for g in got if g >= 0]
+        assert conv == sorted(conv)
+        assert got[0] <= ref[0][1] + 1 and got[1] <= ref[1][1] + 1
+
+
+# ---------------------------------------- BD preconditioner, Lemma C.1 ----
+
+def _gold_consts():
+    out = {}
+    with open(os.path.join(GOLD, "lemma_c1_constants.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            k, v = line.split()
+            out[k] = float(v)
+    return out
+
+
+def test_lemma_c1_constants_against_cubic_roots():
+    g = _gold_consts()
+    roots = np.sort(np.roots([1.0, -1.0, -2.0, 1.0]).real)
+    assert roots == pytest.approx([g["lambda1"], g["lambda2"], g["lambda3"]], abs=6e-5)
+    C = 1 + 2 * roots[2] / roots[1]
+    assert C == pytest.approx(9.0978, abs=1e-4)          # exact constant
+    assert abs(C - g["C_printed"]) < 1e-3                 # printed value is a rounding
+
+
+def _dense(op, N):
+    return np.column_stack([op(e) for e in np.eye(N)])
+
+
+def _spectrum_counts(X, tol=1e-8):
+    ev = np.sort(np.linalg.eigvalsh((X + X.T) / 2))
+    phi = (1 + math.sqrt(5)) / 2
+    cub = np.roots([1.0, -1.0, -2.0, 1.0]).real
+    targets = {"one": [1.0], "golden": [phi, 1 - phi], "cubic": list(cub)}
+    counts = {k: 0 for k in targets}
+    for e in ev:
+        hit = [k for k, vals in targets.items() if min(abs(e - t) for t in vals) < tol]
+        assert len(hit) == 1, e
+        counts[hit[0]] += 1
+    return counts
+
+
+def test_lemma_c1_lse_spectrum_and_gmres_steps():
+    m, n, p = 30, 12, 4
+    P = wl.lse_gaussian(_rng(60), m, n, p)
+    R, T, Z, Q = mpir.grq_factors(P.B, P.A, np.float64)
+    Ml, F, Mr = mpir.bd_operators_lse(P.A, P.B, R, T, Q, alpha=0.7, beta=1.3)
+    N = m + n + p
+    X = _dense(lambda u: Ml(F(Mr(u))), N)
+    assert np.max(np.abs(X - X.T)) < 1e-10
+    c = _spectrum_counts(X)
+    assert c == {"one": m - n, "golden": 2 * (n - p), "cubic": 3 * p}
+    rhs = _rng(61).standard_normal(N)
+    _, its, ok = mpir.gmres(lambda u: X @ u, rhs, restart=30, tol=1e-12)
+    assert ok and its <= 6
+
+
+def test_lemma_c1_gls_spectrum_and_gmres_steps():
+    n, m, p = 12, 4, 30
+    G = wl.gls_gaussian(_rng(62), n, m, p)
+    R, T, Q, Z = mpir.gqr_factors(G.W, G.V, np.float64)
+    Ml, F, Mr = mpir.bd_operators_gls(G.W, G.V, R, T, Q, alpha=1.9, beta=0.6)
+    N = m + n + p
+    X = _dense(lambda u: Ml(F(Mr(u))), N)
+    assert np.max(np.abs(X - X.T)) < 1e-10
+    c = _spectrum_counts(X)
+    assert c == {"one": p - n, "golden": 2 * (n - m), "cubic": 3 * m}
+    _, its, ok = mpir.gmres(lambda u: X @ u, _rng(63).standard_normal(N), restart=30, tol=1e-12)
+    assert ok and its <= 6
+
+
+def test_gmres_minimal_polynomial_degree():
+    # A diagonalizable matrix with 3 distinct eigenvalues: GMRES ends in 3 steps.
+    rng = _rng(64)
+    S = rng.standard_normal((40, 40)) + 5 * np.eye(40)
+    D = np.diag(np.repeat([1.0, -2.0, 3.5], [10, 15, 15]))
+    M = S @ D @ np.linalg.inv(S)
+    b = rng.standard_normal(40)
+    x, its, ok = mpir.gmres(lambda u: M @ u, b, restart=30, tol=1e-10)
+    assert ok and its == 3
+    assert np.linalg.norm(M @ x - b) <= 1e-8 * np.linalg.norm(b)
+
+
+def test_gmres_ir_converges_where_classical_ir_struggles():
+    L = wl.lse_paper_pair(_rng(11), 512, 128, 8, 1e7)
+    g = mpir.mplse_gmres_bd(L.A, L.B, L.b, L.d, tol=1e-13)
+    a = mpir.mplse(L.A, L.B, L.b, L.d, tol=1e-13)
+    assert g.converged and g.steps < a.steps
+    x, _, _ = direct.lse_solve(L.A, L.B, L.b, L.d)
+    assert _rel(g.x, x) < 1e-6

@@ -1,0 +1,158 @@
+/*
+ * lsq.h -- C ABI of liblsq: mixed-precision iterative refinement for
+ * equality-constrained least squares (LSE) and generalized least squares
+ * (GLS) on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gao, Ma, Shao, "Mixed precision iterative refinement for least
+ * squares with linear equality constraints and generalized least squares
+ * problems" (arXiv 2406.16499).  The generalized RQ (LSE) or generalized QR
+ * (GLS) factorization runs in a low precision u_f; the solution is then
+ * refined on the 3-block augmented system with residuals in FP64 (Section 3),
+ * either by classical refinement (Algorithms 2 and 4, correction solvers
+ * Algorithms 1 and 3) or by GMRES with the block-diagonal split
+ * preconditioner (Section 5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrices and vectors are FP64, column-major, in GPU device memory.
+ *   The caller owns every buffer; inputs are never modified (unlike LAPACK's
+ *   xGGLSE / xGGGLM, which overwrite their inputs).
+ * - Work is queued on the handle's stream (lsq_set_stream).  When a
+ *   lsq_result pointer is given, the call synchronizes that stream once at
+ *   the end to fill it.  Refinement decisions need the stop test on the
+ *   host, so every solve synchronizes the stream at least once per
+ *   refinement step.
+ * - Return codes (LAPACK-style INFO):
+ *      0   success: the returned iterate passes the stopping test with tol;
+ *     -k   argument k is invalid (shape rule, leading dimension, null pointer);
+ *      1   rank(B) < p (LSE) or rank(W) < m (GLS) detected by the FP64
+ *          factorization (assumptions eq. assump:lse / eq. assump:gls);
+ *      2   T11 (LSE) or T22 (GLS) is singular: the uniqueness condition fails;
+ *      3   no rung of the escalation ladder met tol; the best iterate found
+ *          is returned and its backward error reported;
+ *      4   HIP error or device allocation failure;
+ *      5   a non-finite value in the inputs.
+ *   A low-precision factorization never returns 1 or 2: near-singularity at
+ *   u_f escalates to the next rung instead.
+ * - Thread safety: a handle is used by one host thread at a time.
+ */
+#ifndef LSQ_H
+#define LSQ_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsq_handle_st* lsq_handle;
+
+/* Factorization precision u_f (Section 3: u_f >= u_s >= u >= u_r). */
+typedef enum {
+  LSQ_PREC_AUTO = 0,    /* learned selector picks (batched) / FP32 (single)      */
+  LSQ_PREC_FP8E4M3 = 1, /* OCP e4m3 MFMA inputs with per-panel power-of-two scale */
+  LSQ_PREC_BF16 = 2,    /* bf16 MFMA inputs, FP32 accumulation                    */
+  LSQ_PREC_FP16 = 3,    /* fp16 MFMA inputs, FP32 accumulation                    */
+  LSQ_PREC_FP32 = 4,    /* fp32 MFMA                                               */
+  LSQ_PREC_FP64 = 5     /* fp64 MFMA: the all-FP64 direct path                     */
+} lsq_prec;
+
+typedef enum {
+  LSQ_SOLVER_AUTO = 0,
+  LSQ_SOLVER_IR = 1,       /* classical refinement, Algorithms 2 / 4              */
+  LSQ_SOLVER_GMRES_IR = 2, /* GMRES with the block-diagonal split preconditioner */
+  LSQ_SOLVER_DIRECT = 3    /* FP64 factorization + null-space / Paige solve,      */
+                           /* certified by one FP64 residual evaluation           */
+} lsq_solver;
+
+typedef struct {
+  int prec;            /* lsq_prec                                                  */
+  int solver;          /* lsq_solver                                                */
+  double tol;          /* threshold of eq. lse-stop / eq. gls-stop; default 1e-14   */
+  int maxit;           /* refinement steps per rung; default 40 (Algorithms 2, 4)   */
+  int gmres_restart;   /* default 30                                                */
+  double gmres_tol;    /* inner relative tolerance of GMRES; default 1e-10          */
+  int gmres_maxit;     /* total inner iterations per rung; default 300              */
+  int escalate;        /* 1: on failure climb the ladder ending in FP64 direct      */
+  double alpha, beta;  /* GMRES scaling (Section 5); <= 0 selects alpha = ||r0||    */
+                       /* (LSE) or ||y0|| (GLS) and beta = 1                        */
+  int nb;              /* panel width of the blocked factorization; 0 = default     */
+} lsq_opts;
+
+typedef struct {
+  int info;            /* as the return code                                        */
+  int prec_used;       /* lsq_prec of the rung that produced the returned iterate   */
+  int solver_used;     /* lsq_solver of that rung                                   */
+  int attempts;        /* rungs tried                                               */
+  int ir_steps;        /* corrections applied on the final rung                     */
+  int gmres_iters;     /* total GMRES iterations on the final rung                  */
+  double berr[3];      /* ||f_i|| / (right-hand side of the stop test without tol)  */
+  double berr_max;
+  float ms_convert, ms_factor, ms_refine;   /* stream time per phase (final rung)  */
+} lsq_result;
+
+/* Create a handle bound to GPU `device`; it owns a device workspace that grows
+   on demand and is freed by lsq_destroy.  Returns 0 or 4. */
+int lsq_create(lsq_handle* handle, int device);
+int lsq_destroy(lsq_handle handle);
+/* Queue all later work on `stream` (a hipStream_t; NULL = the default stream). */
+int lsq_set_stream(lsq_handle handle, void* stream);
+void lsq_opts_default(lsq_opts* opts);
+
+/*
+ * LSE (problem lse, Section 1):  min ||A x - b||_2  s.t.  B x = d,
+ *   A: m x n (lda >= max(1,m)), B: p x n (ldb >= max(1,p)), b: m, d: p,
+ *   with p <= n <= m + p.  Outputs: x (n); optionally r = b - A x (m) and the
+ *   multiplier v (p) of eq. aug-LSE (pass NULL to skip).
+ * Argument numbers for -k: 2 m, 3 n, 4 p, 5 A, 6 lda, 7 B, 8 ldb, 9 b, 10 d,
+ * 11 x, 14 opts.
+ */
+int lse_solve(lsq_handle handle, int m, int n, int p,
+              const double* A, int lda, const double* B, int ldb,
+              const double* b, const double* d,
+              double* x, double* r, double* v,
+              const lsq_opts* opts, lsq_result* res);
+
+/*
+ * GLS (problem gls, Section 1):  min ||y||_2  s.t.  d = A x + B y,
+ *   A = W: n x m (lda >= max(1,n)), B = V: n x p (ldb >= max(1,n)), d: n,
+ *   with m <= n <= m + p.  Outputs: x (m), y (p); optionally the multiplier
+ *   z (n) of eq. aug-GLS.
+ * Argument numbers for -k: 2 n, 3 m, 4 p, 5 A, 6 lda, 7 B, 8 ldb, 9 d,
+ * 10 x, 11 y, 13 opts.
+ */
+int gls_solve(lsq_handle handle, int n, int m, int p,
+              const double* A, int lda, const double* B, int ldb,
+              const double* d, double* x, double* y, double* z,
+              const lsq_opts* opts, lsq_result* res);
+
+/* One instance of a batch.  type: LSQ_LSE or LSQ_GLS; sizes and pointers as in
+   lse_solve (m, n, p, A, B, b, d, x) or gls_solve (n, m, p with A = W, B = V,
+   d, x, y).  Pointers are device pointers; b is ignored for GLS and y for LSE. */
+enum { LSQ_LSE = 0, LSQ_GLS = 1 };
+typedef struct {
+  int type;
+  int m, n, p;
+  const double* A;
+  const double* B;
+  const double* b;
+  const double* d;
+  int lda, ldb;
+  double* x;
+  double* y;
+} lsq_problem;
+
+/* Solve `count` independent instances of uneven size.  `res` (host array of
+   `count`, nullable) receives one record per instance.  Returns the number of
+   instances with info != 0, or -k for an invalid argument (-3: a problem
+   descriptor is invalid). */
+int lsq_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
+                      const lsq_opts* opts, lsq_result* res);
+/* Same-type conveniences: every descriptor must carry the matching type. */
+int lse_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
+                      const lsq_opts* opts, lsq_result* res);
+int gls_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
+                      const lsq_opts* opts, lsq_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSQ_H */

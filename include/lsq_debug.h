@@ -1,0 +1,69 @@
+/*
+ * lsq_debug.h -- inspection entry points of liblsq, one per step of the
+ * refinement path, so that each step can be checked against an independent
+ * implementation.  Same conventions as lsq.h: FP64 column-major device
+ * buffers owned by the caller, work on the handle's stream, the call
+ * synchronizes that stream before returning.  Return 0, -k for argument k,
+ * or 4 for a HIP error.  `prec` is an lsq_prec value naming the storage /
+ * MFMA precision of the factorization (Section 3, u_f).
+ */
+#ifndef LSQ_DEBUG_H
+#define LSQ_DEBUG_H
+#include "lsq.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Householder QR of M (r x c, assumption on xGEQRF of Section 4.1) at
+ * precision prec.  Outputs, all FP64:
+ *   R    (k x c, ld k, k = min(r,c)): the triangular factor (zeros below);
+ *   Y1   (r x nx, ld r): Q^T X computed by the blocked matrix kernels;
+ *   Y2   (r x nx, ld r): Q^T X computed column by column by the vector kernel;
+ *   Y3   (r x nx, ld r): Q (Q^T X), both by the vector kernel.
+ * Any output pointer may be NULL; X may be NULL when nx = 0. */
+int lsq_dbg_qr(lsq_handle h, int prec, int r, int c, const double* M, int ldm,
+               const double* X, int ldx, int nx, double* R, double* Y1, double* Y2, double* Y3);
+
+/* Triangular solve with the upper triangle of U (n x n): x = U^{-1} b or
+ * U^{-T} b (trans = 1), with U stored at precision prec and solved in FP32
+ * (prec != FP64) or FP64 (prec = FP64); tc64 = 1 forces FP64 arithmetic. */
+int lsq_dbg_trsv(lsq_handle h, int prec, int tc64, int n, const double* U, int ldu, int trans,
+                 const double* b, double* x);
+
+/* FP64 augmented residual of eq. aug-LSE at (x, r, v) and the stop-test
+ * quantities of eq. lse-stop: out[0..2] = ||f_i||, out[3..5] = the right-hand
+ * sides without tol, out[6..8] = blockwise backward errors, out[9] = their max
+ * (host array of 10). */
+int lsq_dbg_lse_residual(lsq_handle h, int m, int n, int p, const double* A, int lda,
+                         const double* B, int ldb, const double* b, const double* d,
+                         const double* x, const double* r, const double* v, double* f1,
+                         double* f2, double* f3, double* out);
+
+/* Same for eq. aug-GLS at (x, y, z) and eq. gls-stop (A = W, B = V). */
+int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* A, int lda,
+                         const double* B, int ldb, const double* d, const double* x,
+                         const double* y, const double* z, double* f1, double* f2, double* f3,
+                         double* out);
+
+/* Generalized RQ factorization of (B, A) at precision prec, then one call of
+ * the LSE correction solver (Algorithm 1) on (f1, f2, f3): outputs dr (m),
+ * dv (p), dx (n) with [[I,0,A],[0,0,B],[A^T,B^T,0]] [dr; -dv; dx] = f. */
+int lsq_dbg_lse_correction(lsq_handle h, int prec, int m, int n, int p, const double* A, int lda,
+                           const double* B, int ldb, const double* f1, const double* f2,
+                           const double* f3, double* dr, double* dv, double* dx);
+
+/* Generalized QR factorization of (W, V) = (A, B) at precision prec, then one
+ * call of the GLS correction solver (Algorithm 3): outputs dy (p), dz (n),
+ * dx (m) with [[I,V^T,0],[V,0,W],[0,W^T,0]] [dy; -dz; dx] = f. */
+int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const double* A, int lda,
+                           const double* B, int ldb, const double* f1, const double* f2,
+                           const double* f3, double* dy, double* dz, double* dx);
+
+/* Text of the last error recorded on the handle ("" if none). */
+const char* lsq_last_error(lsq_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSQ_DEBUG_H */

@@ -1,0 +1,841 @@
+// liblsq C ABI and refinement drivers.
+//
+// LSE (Section 3.1): the generalized RQ factorization B = [0, R] Q, A = Z T Q
+// is computed as two Householder QRs.  The RQ of B is the QR of the reversed
+// transpose  Bt = J_n B^T J_p = Qt [Rt; 0]  so that R = J Rt^T J and
+// Q = J Qt^T J (J reverses index order); then  Abar = A Q^T  is formed as the
+// reversed transpose of  Qt^T (J_n A^T)  and factored as Abar = Z T.
+// The correction solver (Algorithm 1) is carried out in that basis: every
+// quantity that involves R or Q is kept reversed (u~ = J u, y2~ = J y2, ...).
+//
+// GLS (Section 3.2): W = Q [R; 0] is a plain QR; V' = Q^T V; the RQ V' = T Z
+// is the QR of  Vt = J_p V'^T J_n = Zt Rv  (T = J_n Rv^T J_p, Z = J_p Zt^T J_p),
+// and Algorithm 3 is carried out with the blocks of Rv.
+//
+// The initial guess of Algorithms 2 and 4 (null-space / Paige solution at
+// u_f, then r0, v0 resp. z0) equals, in exact arithmetic, one correction
+// solve started from the zero iterate with residual (b, d, 0) resp. (0, d, 0);
+// the drivers compute it that way.  Residuals and updates are FP64.
+#include <algorithm>
+#include <functional>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "lsq.h"
+#include "lsq_debug.h"
+
+using namespace lsq;
+
+// --------------------------------------------------------------- arena --
+namespace lsq {
+Arena::~Arena() { release(); }
+void* Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size()) {
+    Chunk& c = chunks_[cur_];
+    if (c.used + bytes <= c.size) {
+      void* p = c.base + c.used;
+      c.used += bytes;
+      return p;
+    }
+    ++cur_;
+  }
+  size_t sz = bytes > (size_t(256) << 20) ? bytes : (size_t(256) << 20);
+  void* base = nullptr;
+  LSQ_HIP(hipMalloc(&base, sz));
+  chunks_.push_back(Chunk{static_cast<char*>(base), sz, bytes});
+  cur_ = chunks_.size() - 1;
+  return base;
+}
+void Arena::reset() {
+  for (auto& c : chunks_) c.used = 0;
+  cur_ = 0;
+}
+void Arena::release() {
+  for (auto& c : chunks_) (void)hipFree(c.base);
+  chunks_.clear();
+  cur_ = 0;
+}
+}  // namespace lsq
+
+struct lsq_handle_st {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Arena arena;
+  Ctx ctx;
+  StopStatus* st_dev = nullptr;
+  StopStatus* st_host = nullptr;   // pinned
+  double* matnorms = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::string last_error;
+};
+
+namespace {
+
+struct PrecSpec {
+  int tw;      // storage bytes of the factor
+  Mma mt;      // MFMA input type
+  int tc;      // compute bytes of classical-IR corrections
+};
+
+bool prec_spec(int prec, PrecSpec& ps) {
+  switch (prec) {
+    case LSQ_PREC_FP64: ps = {8, Mma::F64, 8}; return true;
+    case LSQ_PREC_FP32: ps = {4, Mma::F32, 4}; return true;
+    case LSQ_PREC_BF16: ps = {4, Mma::BF16, 4}; return true;
+    case LSQ_PREC_FP16: ps = {4, Mma::F16, 4}; return true;
+    default: return false;
+  }
+}
+
+int default_nb(const lsq_opts& o) { return (o.nb > 0 && o.nb <= kMaxNb) ? o.nb : kMaxNb; }
+
+void* off(void* p, size_t bytes) { return static_cast<char*>(p) + bytes; }
+const void* off(const void* p, size_t bytes) { return static_cast<const char*>(p) + bytes; }
+
+// ----------------------------------------------------------------- LSE ----
+struct LseSolver {
+  int m, n, p, k;
+  PrecSpec ps;
+  int tc;                 // compute precision of the correction solve
+  QRFactor fb, fa;        // QR of Bt (n x p) and of Abar (m x n)
+  TriBlock tR, tT11;
+  void *U, *Wv, *Y2, *Y2n, *Qv, *Y1, *S, *X2, *Yt;
+
+  void alloc_vectors(Ctx& ctx) {
+    auto v = [&](int len) { return ctx.ws->alloc((size_t)tc * (len > 0 ? len : 1)); };
+    U = v(n); Wv = v(m); Y2 = v(p); Y2n = v(p); Qv = v(m); Y1 = v(k); S = v(p); X2 = v(p); Yt = v(n);
+  }
+
+  void factor(Ctx& ctx, const double* A, int lda, const double* B, int ldb, int nb) {
+    qr_alloc(ctx, fb, n, p, ps.tw, ps.mt, nb);
+    mat_convert(ctx, fb.M, ps.tw, fb.ld, B, 8, ldb, n, p, true, true, true);
+    qr_factor(ctx, fb);
+    void* X0 = ctx.ws->alloc((size_t)ps.tw * (size_t)(n > 0 ? n : 1) * (m > 0 ? m : 1));
+    mat_convert(ctx, X0, ps.tw, n > 0 ? n : 1, A, 8, lda, n, m, true, false, true);
+    qr_apply_left_T(ctx, fb, X0, n > 0 ? n : 1, m);
+    qr_alloc(ctx, fa, m, n, ps.tw, ps.mt, nb);
+    mat_convert(ctx, fa.M, ps.tw, fa.ld, X0, ps.tw, n > 0 ? n : 1, m, n, true, true, false);
+    qr_factor(ctx, fa);
+  }
+
+  void prepare(Ctx& ctx, int tc_) {
+    tc = tc_;
+    trsv_prepare(ctx, tR, fb, 0, p, tc);
+    trsv_prepare(ctx, tT11, fa, 0, k, tc);
+    alloc_vectors(ctx);
+  }
+
+  // Algorithm 1 on (f1, f2, f3) (f3 may be null = 0); adds (dr, dv, dx) to (r, v, x).
+  void correct(Ctx& ctx, const double* f1, const double* f2, const double* f3, double* x,
+               double* r, double* v) {
+    const size_t e = (size_t)tc;
+    // line 1: u~ = Qt^T (J f3)
+    if (f3) vec_convert(ctx, U, tc, f3, 8, n, true); else vec_zero(ctx, U, tc, n);
+    qr_apply_vec(ctx, fb, true, U, tc);
+    // line 2: w = Z^T f1
+    vec_convert(ctx, Wv, tc, f1, 8, m, false);
+    qr_apply_vec(ctx, fa, true, Wv, tc);
+    // line 3: R y2 = f2  <=>  Rt^T (J y2) = J f2
+    vec_convert(ctx, Y2, tc, f2, 8, p, true);
+    trsv(ctx, tR, true, Y2);
+    vec_convert(ctx, Y2n, tc, Y2, tc, p, true);
+    // line 4: T11^T q1 = u1, u1 = J u~[p:n]
+    vec_convert(ctx, Qv, tc, off(U, e * p), tc, k, true);
+    trsv(ctx, tT11, true, Qv);
+    // line 5: T11 y1 = w1 - q1 - T12 y2
+    vec_convert(ctx, Y1, tc, Wv, tc, k, false);
+    vec_axpy(ctx, Y1, tc, -1.0, Qv, tc, k, false);
+    gemv_upper(ctx, fa, 0, k, k, p, false, -1.0, Y2n, Y1, tc);
+    trsv(ctx, tT11, false, Y1);
+    // line 6: q2 = w2 - T22 y2
+    vec_convert(ctx, off(Qv, e * k), tc, off(Wv, e * k), tc, m - k, false);
+    gemv_upper(ctx, fa, k, k, m - k, p, false, -1.0, Y2n, off(Qv, e * k), tc);
+    // line 8: R^T dv = T12^T q1 + T22^T q2 - u2  <=>  Rt (J dv) = J(...)
+    vec_zero(ctx, S, tc, p);
+    gemv_upper(ctx, fa, 0, k, m, p, true, 1.0, Qv, S, tc);
+    vec_axpy(ctx, S, tc, -1.0, U, tc, p, true);
+    vec_convert(ctx, X2, tc, S, tc, p, true);
+    trsv(ctx, tR, false, X2);
+    vec_axpy(ctx, v, 8, 1.0, X2, tc, p, true);
+    // line 7: dr = Z q ; dx = Q^T y = J Qt (J y),  J y = [y2~; J y1]
+    qr_apply_vec(ctx, fa, false, Qv, tc);
+    vec_axpy(ctx, r, 8, 1.0, Qv, tc, m, false);
+    vec_convert(ctx, Yt, tc, Y2, tc, p, false);
+    vec_convert(ctx, off(Yt, e * p), tc, Y1, tc, k, true);
+    qr_apply_vec(ctx, fb, false, Yt, tc);
+    vec_axpy(ctx, x, 8, 1.0, Yt, tc, n, true);
+  }
+};
+
+// ----------------------------------------------------------------- GLS ----
+struct GlsSolver {
+  int n, m, p, k;         // k = n - m
+  PrecSpec ps;
+  int tc;
+  QRFactor fw, fv;        // QR of W (n x m) and of Vt (p x n)
+  TriBlock tR, tA11;
+  void *U, *Wt, *H1, *H1t, *G, *H2t, *S, *X, *Hv;
+
+  void alloc_vectors(Ctx& ctx) {
+    auto v = [&](int len) { return ctx.ws->alloc((size_t)tc * (len > 0 ? len : 1)); };
+    U = v(n); Wt = v(p); H1 = v(m); H1t = v(m); G = v(p); H2t = v(k); S = v(m); X = v(m); Hv = v(n);
+  }
+
+  void factor(Ctx& ctx, const double* W, int ldw, const double* V, int ldv, int nb) {
+    qr_alloc(ctx, fw, n, m, ps.tw, ps.mt, nb);
+    mat_convert(ctx, fw.M, ps.tw, fw.ld, W, 8, ldw, n, m, false, false, false);
+    qr_factor(ctx, fw);
+    const int ldn = n > 0 ? n : 1;
+    void* Vw = ctx.ws->alloc((size_t)ps.tw * ldn * (p > 0 ? p : 1));
+    mat_convert(ctx, Vw, ps.tw, ldn, V, 8, ldv, n, p, false, false, false);
+    qr_apply_left_T(ctx, fw, Vw, ldn, p);
+    qr_alloc(ctx, fv, p, n, ps.tw, ps.mt, nb);
+    mat_convert(ctx, fv.M, ps.tw, fv.ld, Vw, ps.tw, ldn, p, n, true, true, true);
+    qr_factor(ctx, fv);
+  }
+
+  void prepare(Ctx& ctx, int tc_) {
+    tc = tc_;
+    trsv_prepare(ctx, tR, fw, 0, m, tc);
+    trsv_prepare(ctx, tA11, fv, 0, k, tc);
+    alloc_vectors(ctx);
+  }
+
+  // Algorithm 3 on (f1, f2, f3) (f1, f3 may be null = 0); adds (dy, dz, dx) to (y, z, x).
+  void correct(Ctx& ctx, const double* f1, const double* f2, const double* f3, double* x,
+               double* y, double* z) {
+    const size_t e = (size_t)tc;
+    // line 1: u = Q^T f2
+    vec_convert(ctx, U, tc, f2, 8, n, false);
+    qr_apply_vec(ctx, fw, true, U, tc);
+    // line 2: w~ = J w = Zt^T (J f1)
+    if (f1) vec_convert(ctx, Wt, tc, f1, 8, p, true); else vec_zero(ctx, Wt, tc, p);
+    qr_apply_vec(ctx, fv, true, Wt, tc);
+    // line 3: R^T h1 = f3
+    if (f3) vec_convert(ctx, H1, tc, f3, 8, m, false); else vec_zero(ctx, H1, tc, m);
+    trsv(ctx, tR, true, H1);
+    vec_convert(ctx, H1t, tc, H1, tc, m, true);
+    // line 4: T22 g2 = u2  <=>  A11^T (J g2) = J u2
+    vec_convert(ctx, G, tc, off(U, e * m), tc, k, true);
+    trsv(ctx, tA11, true, G);
+    // line 5: T22^T h2 = w2 - g2 - T12^T h1  <=>  A11 (J h2) = J w2 - J g2 - A12 J h1
+    vec_convert(ctx, H2t, tc, Wt, tc, k, false);
+    vec_axpy(ctx, H2t, tc, -1.0, G, tc, k, false);
+    gemv_upper(ctx, fv, 0, k, k, m, false, -1.0, H1t, H2t, tc);
+    trsv(ctx, tA11, false, H2t);
+    // line 6: g1 = w1 - T11^T h1  <=>  J g1 = J w1 - A22 J h1
+    vec_convert(ctx, off(G, e * k), tc, off(Wt, e * k), tc, p - k, false);
+    gemv_upper(ctx, fv, k, k, p - k, m, false, -1.0, H1t, off(G, e * k), tc);
+    // line 8: R dx = u1 - T11 g1 - T12 g2 = u1 - J (Rv[:, k:n]^T (J g))
+    vec_zero(ctx, S, tc, m);
+    gemv_upper(ctx, fv, 0, k, p, m, true, 1.0, G, S, tc);
+    vec_convert(ctx, X, tc, U, tc, m, false);
+    vec_axpy(ctx, X, tc, -1.0, S, tc, m, true);
+    trsv(ctx, tR, false, X);
+    vec_axpy(ctx, x, 8, 1.0, X, tc, m, false);
+    // line 7: dz = -Q h, h = [h1; J h2~] ; dy = Z^T g = J Zt (J g)
+    vec_convert(ctx, Hv, tc, H1, tc, m, false);
+    vec_convert(ctx, off(Hv, e * m), tc, H2t, tc, k, true);
+    qr_apply_vec(ctx, fw, false, Hv, tc);
+    vec_axpy(ctx, z, 8, -1.0, Hv, tc, n, false);
+    qr_apply_vec(ctx, fv, false, G, tc);
+    vec_axpy(ctx, y, 8, 1.0, G, tc, p, true);
+  }
+};
+
+// ------------------------------------------------------- rung execution --
+struct RungOut {
+  bool ok = false;
+  bool breakdown = false;  // the factorization failed (rank deficiency at u_f)
+  int steps = 0, inner = 0;
+  double berr[3] = {0, 0, 0}, berr_max = INFINITY;
+  float ms_convert = 0, ms_factor = 0, ms_refine = 0;
+};
+
+void read_status(lsq_handle h) {
+  LSQ_HIP(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(StopStatus), hipMemcpyDeviceToHost, h->stream));
+  LSQ_HIP(hipStreamSynchronize(h->stream));
+}
+
+int read_int(lsq_handle h, const int* dptr) {
+  int v = 0;
+  LSQ_HIP(hipMemcpyAsync(&h->st_host->converged, dptr, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  LSQ_HIP(hipStreamSynchronize(h->stream));
+  v = h->st_host->converged;
+  return v;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, a, b);
+  return ms;
+}
+
+// Divergence / stagnation test of the refinement (the paper reports
+// "diverged" without a rule): stop the rung when an iterate is not finite or
+// the backward error has not halved over the last three steps.
+bool stalled(const std::vector<double>& hist) {
+  const size_t s = hist.size();
+  if (s >= 4 && !(hist[s - 1] <= 0.5 * hist[s - 4])) return true;
+  return false;
+}
+
+// Classical refinement (Algorithms 2 and 4): init() adds the initial guess to
+// the zeroed iterate, residual() evaluates the FP64 residual and the stop
+// test on the device, correct() adds one correction.
+RungOut run_classical(lsq_handle h, const std::function<void()>& zero,
+                      const std::function<void()>& init, const std::function<void()>& residual,
+                      const std::function<void()>& correct, const lsq_opts& o) {
+  RungOut out;
+  zero();
+  LSQ_HIP(hipEventRecord(h->ev[2], h->stream));
+  init();
+  std::vector<double> hist;
+  for (int it = 0;; ++it) {
+    residual();
+    read_status(h);
+    const StopStatus& st = *h->st_host;
+    hist.push_back(st.berr_max);
+    for (int q = 0; q < 3; ++q) out.berr[q] = st.berr[q];
+    out.berr_max = st.berr_max;
+    out.steps = it;
+    if (st.converged) { out.ok = true; break; }
+    if (st.nonfinite || it >= o.maxit || stalled(hist)) break;
+    correct();
+  }
+  LSQ_HIP(hipEventRecord(h->ev[3], h->stream));
+  LSQ_HIP(hipEventSynchronize(h->ev[3]));
+  out.ms_refine = elapsed(h->ev[2], h->ev[3]);
+  return out;
+}
+
+struct LseArgs {
+  int m, n, p;
+  const double *A, *B, *b, *d;
+  int lda, ldb;
+};
+struct GlsArgs {
+  int n, m, p;
+  const double *W, *V, *d;
+  int ldw, ldv;
+};
+
+// One rung for LSE: factor at prec, then classical refinement (the DIRECT
+// solver is the same loop at FP64; it normally stops at the first test).
+RungOut lse_rung(lsq_handle h, const LseArgs& a, int prec, int solver, const lsq_opts& o,
+                 double* x, double* r, double* v) {
+  Ctx& ctx = h->ctx;
+  LseSolver sv;
+  sv.m = a.m; sv.n = a.n; sv.p = a.p; sv.k = a.n - a.p;
+  (void)solver;
+  prec_spec(prec, sv.ps);
+  LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
+  sv.factor(ctx, a.A, a.lda, a.B, a.ldb, default_nb(o));
+  sv.prepare(ctx, sv.ps.tc);
+  LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
+  int stat_b = read_int(h, sv.fb.status);
+  int stat_a = read_int(h, sv.fa.status);
+  RungOut out;
+  if (stat_b || stat_a) {
+    out.breakdown = true;
+    return out;
+  }
+  double* f1 = ctx.ws->get<double>(a.m > 0 ? a.m : 1);
+  double* f2 = ctx.ws->get<double>(a.p > 0 ? a.p : 1);
+  double* f3 = ctx.ws->get<double>(a.n > 0 ? a.n : 1);
+  auto residual = [&]() {
+    lse_residual(ctx, a.m, a.n, a.p, a.A, a.lda, a.B, a.ldb, a.b, a.d, x, r, v, f1, f2, f3,
+                 h->matnorms, o.tol, h->st_dev);
+  };
+  out = run_classical(
+      h,
+      [&]() { vec_zero(ctx, x, 8, a.n); vec_zero(ctx, r, 8, a.m); vec_zero(ctx, v, 8, a.p); },
+      [&]() { sv.correct(ctx, a.b, a.d, nullptr, x, r, v); }, residual,
+      [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o);
+  out.ms_factor = elapsed(h->ev[0], h->ev[1]);
+  return out;
+}
+
+RungOut gls_rung(lsq_handle h, const GlsArgs& a, int prec, int solver, const lsq_opts& o,
+                 double* x, double* y, double* z) {
+  Ctx& ctx = h->ctx;
+  GlsSolver sv;
+  sv.n = a.n; sv.m = a.m; sv.p = a.p; sv.k = a.n - a.m;
+  (void)solver;
+  prec_spec(prec, sv.ps);
+  LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
+  sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o));
+  sv.prepare(ctx, sv.ps.tc);
+  LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
+  int stat_w = read_int(h, sv.fw.status);
+  int stat_v = read_int(h, sv.fv.status);
+  RungOut out;
+  if (stat_w || stat_v) {
+    out.breakdown = true;
+    return out;
+  }
+  double* f1 = ctx.ws->get<double>(a.p > 0 ? a.p : 1);
+  double* f2 = ctx.ws->get<double>(a.n > 0 ? a.n : 1);
+  double* f3 = ctx.ws->get<double>(a.m > 0 ? a.m : 1);
+  auto residual = [&]() {
+    gls_residual(ctx, a.n, a.m, a.p, a.W, a.ldw, a.V, a.ldv, a.d, x, y, z, f1, f2, f3,
+                 h->matnorms, o.tol, h->st_dev);
+  };
+  out = run_classical(
+      h,
+      [&]() { vec_zero(ctx, x, 8, a.m); vec_zero(ctx, y, 8, a.p); vec_zero(ctx, z, 8, a.n); },
+      [&]() { sv.correct(ctx, nullptr, a.d, nullptr, x, y, z); }, residual,
+      [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o);
+  out.ms_factor = elapsed(h->ev[0], h->ev[1]);
+  return out;
+}
+
+// Escalation ladder: the requested rung first, then higher precisions,
+// finally the FP64 direct path.
+std::vector<std::pair<int, int>> ladder(const lsq_opts& o) {
+  std::vector<std::pair<int, int>> r;
+  int prec = o.prec == LSQ_PREC_AUTO ? LSQ_PREC_FP32 : o.prec;
+  if (prec == LSQ_PREC_FP8E4M3) prec = LSQ_PREC_BF16;
+  int solver = o.solver == LSQ_SOLVER_AUTO ? LSQ_SOLVER_IR : o.solver;
+  if (solver == LSQ_SOLVER_DIRECT || prec == LSQ_PREC_FP64) {
+    r.push_back({LSQ_PREC_FP64, LSQ_SOLVER_DIRECT});
+    return r;
+  }
+  r.push_back({prec, LSQ_SOLVER_IR});
+  if (!o.escalate) return r;
+  const int order[] = {LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32};
+  bool after = false;
+  for (int q : order) {
+    if (q == prec) { after = true; continue; }
+    if (after) r.push_back({q, LSQ_SOLVER_IR});
+  }
+  r.push_back({LSQ_PREC_FP64, LSQ_SOLVER_DIRECT});
+  return r;
+}
+
+int fail(lsq_handle h, int code, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return code;
+}
+
+
+int guard(lsq_handle h, const char* fn, const std::function<int()>& body) {
+  try {
+    if (h) {
+      LSQ_HIP(hipSetDevice(h->device));
+      h->arena.reset();
+      h->last_error.clear();
+    }
+    return body();
+  } catch (const HipError& e) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s: %s failed: %s", fn, e.where, hipGetErrorString(e.code));
+    return fail(h, 4, buf);
+  } catch (const std::exception& e) {
+    return fail(h, 4, std::string(fn) + ": " + e.what());
+  }
+}
+}  // namespace
+
+// ================================================================== C ABI ==
+extern "C" {
+
+void lsq_opts_default(lsq_opts* o) {
+  if (!o) return;
+  o->prec = LSQ_PREC_FP32;
+  o->solver = LSQ_SOLVER_IR;
+  o->tol = 1e-14;
+  o->maxit = 40;
+  o->gmres_restart = 30;
+  o->gmres_tol = 1e-10;
+  o->gmres_maxit = 300;
+  o->escalate = 1;
+  o->alpha = 0.0;
+  o->beta = 0.0;
+  o->nb = 0;
+}
+
+int lsq_create(lsq_handle* out, int device) {
+  if (!out) return -1;
+  *out = nullptr;
+  lsq_handle h = new (std::nothrow) lsq_handle_st();
+  if (!h) return 4;
+  try {
+    h->device = device;
+    LSQ_HIP(hipSetDevice(device));
+    h->ctx.ws = &h->arena;
+    h->ctx.stream = nullptr;
+    h->ctx.nflags = 4096;
+    LSQ_HIP(hipMalloc(&h->ctx.sync, 64 * sizeof(unsigned)));
+    LSQ_HIP(hipMemset(h->ctx.sync, 0, 64 * sizeof(unsigned)));
+    LSQ_HIP(hipMalloc(&h->ctx.flags, h->ctx.nflags * sizeof(unsigned)));
+    LSQ_HIP(hipMemset(h->ctx.flags, 0, h->ctx.nflags * sizeof(unsigned)));
+    LSQ_HIP(hipMalloc(&h->ctx.err, 64));
+    LSQ_HIP(hipMemset(h->ctx.err, 0, 64));
+    LSQ_HIP(hipMalloc(&h->st_dev, sizeof(StopStatus)));
+    LSQ_HIP(hipHostMalloc(&h->st_host, sizeof(StopStatus), 0));
+    LSQ_HIP(hipMalloc(&h->matnorms, 8 * sizeof(double)));
+    for (auto& e : h->ev) LSQ_HIP(hipEventCreate(&e));
+    hipDeviceProp_t prop;
+    LSQ_HIP(hipGetDeviceProperties(&prop, device));
+    h->ctx.num_cu = prop.multiProcessorCount;
+    h->ctx.max_coop_blocks = prop.multiProcessorCount;   // one 256-thread block per CU is always co-resident
+    LSQ_HIP(hipDeviceSynchronize());
+  } catch (const HipError&) {
+    lsq_destroy(h);
+    return 4;
+  }
+  *out = h;
+  return 0;
+}
+
+int lsq_destroy(lsq_handle h) {
+  if (!h) return 0;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  h->arena.release();
+  if (h->ctx.sync) (void)hipFree(h->ctx.sync);
+  if (h->ctx.flags) (void)hipFree(h->ctx.flags);
+  if (h->ctx.err) (void)hipFree(h->ctx.err);
+  if (h->st_dev) (void)hipFree(h->st_dev);
+  if (h->st_host) (void)hipHostFree(h->st_host);
+  if (h->matnorms) (void)hipFree(h->matnorms);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+  return 0;
+}
+
+int lsq_set_stream(lsq_handle h, void* stream) {
+  if (!h) return -1;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->ctx.stream = h->stream;
+  return 0;
+}
+
+const char* lsq_last_error(lsq_handle h) { return h ? h->last_error.c_str() : ""; }
+
+static void fill_result(lsq_result* res, int info, int prec, int solver, int attempts,
+                        const RungOut& ro) {
+  if (!res) return;
+  res->info = info;
+  res->prec_used = prec;
+  res->solver_used = solver;
+  res->attempts = attempts;
+  res->ir_steps = ro.steps;
+  res->gmres_iters = ro.inner;
+  for (int q = 0; q < 3; ++q) res->berr[q] = ro.berr[q];
+  res->berr_max = ro.berr_max;
+  res->ms_convert = ro.ms_convert;
+  res->ms_factor = ro.ms_factor;
+  res->ms_refine = ro.ms_refine;
+}
+
+int lse_solve(lsq_handle h, int m, int n, int p, const double* A, int lda, const double* B,
+              int ldb, const double* b, const double* d, double* x, double* r, double* v,
+              const lsq_opts* opts, lsq_result* res) {
+  if (!h) return -1;
+  if (m < 0) return fail(h, -2, "m < 0");
+  if (n < 0 || n > m + p) return fail(h, -3, "n out of range (p <= n <= m + p)");
+  if (p < 0 || p > n) return fail(h, -4, "p out of range (p <= n)");
+  if (!A && m * n > 0) return -5;
+  if (lda < (m > 1 ? m : 1)) return -6;
+  if (!B && p * n > 0) return -7;
+  if (ldb < (p > 1 ? p : 1)) return -8;
+  if (!b && m > 0) return -9;
+  if (!d && p > 0) return -10;
+  if (!x && n > 0) return -11;
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0) return -14;
+  return guard(h, "lse_solve", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    LseArgs a{m, n, p, A, B, b, d, lda, ldb};
+    frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, h->matnorms);
+    double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
+    double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
+    double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
+    const auto rungs = ladder(o);
+    RungOut ro;
+    int used_p = 0, used_s = 0, attempts = 0, info = 3;
+    for (auto [prec, solver] : rungs) {
+      ++attempts;
+      ro = lse_rung(h, a, prec, solver, o, xi, ri, vi);
+      used_p = prec;
+      used_s = solver;
+      if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
+      if (ro.ok) { info = 0; break; }
+      if (ro.berr_max != ro.berr_max) { /* NaN: try next rung */ }
+    }
+    if (info != 1) {
+      if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+      if (r && m > 0) LSQ_HIP(hipMemcpyAsync(r, ri, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+      if (v && p > 0) LSQ_HIP(hipMemcpyAsync(v, vi, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+    }
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    fill_result(res, info, used_p, used_s, attempts, ro);
+    return info;
+  });
+}
+
+int gls_solve(lsq_handle h, int n, int m, int p, const double* W, int ldw, const double* V,
+              int ldv, const double* d, double* x, double* y, double* z, const lsq_opts* opts,
+              lsq_result* res) {
+  if (!h) return -1;
+  if (n < 0) return fail(h, -2, "n < 0");
+  if (m < 0 || m > n) return fail(h, -3, "m out of range (m <= n)");
+  if (p < 0 || n > m + p) return fail(h, -4, "p out of range (n <= m + p)");
+  if (!W && n * m > 0) return -5;
+  if (ldw < (n > 1 ? n : 1)) return -6;
+  if (!V && n * p > 0) return -7;
+  if (ldv < (n > 1 ? n : 1)) return -8;
+  if (!d && n > 0) return -9;
+  if (!x && m > 0) return -10;
+  if (!y && p > 0) return -11;
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0) return -13;
+  return guard(h, "gls_solve", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    GlsArgs a{n, m, p, W, V, d, ldw, ldv};
+    frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, h->matnorms);
+    double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
+    double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
+    double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
+    const auto rungs = ladder(o);
+    RungOut ro;
+    int used_p = 0, used_s = 0, attempts = 0, info = 3;
+    for (auto [prec, solver] : rungs) {
+      ++attempts;
+      ro = gls_rung(h, a, prec, solver, o, xi, yi, zi);
+      used_p = prec;
+      used_s = solver;
+      if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
+      if (ro.ok) { info = 0; break; }
+    }
+    if (info != 1) {
+      if (m > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
+      if (p > 0) LSQ_HIP(hipMemcpyAsync(y, yi, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
+      if (z && n > 0) LSQ_HIP(hipMemcpyAsync(z, zi, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    }
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    fill_result(res, info, used_p, used_s, attempts, ro);
+    return info;
+  });
+}
+
+int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
+                      lsq_result* res) {
+  if (!h) return -1;
+  if (count < 0) return -2;
+  if (count > 0 && !probs) return -3;
+  int nfail = 0;
+  for (int i = 0; i < count; ++i) {
+    const lsq_problem& q = probs[i];
+    int info;
+    if (q.type == LSQ_LSE)
+      info = lse_solve(h, q.m, q.n, q.p, q.A, q.lda, q.B, q.ldb, q.b, q.d, q.x, nullptr, nullptr,
+                       opts, res ? &res[i] : nullptr);
+    else if (q.type == LSQ_GLS)
+      info = gls_solve(h, q.n, q.m, q.p, q.A, q.lda, q.B, q.ldb, q.d, q.x, q.y, nullptr, opts,
+                       res ? &res[i] : nullptr);
+    else
+      return -3;
+    if (info < 0) return -3;
+    if (info != 0) ++nfail;
+  }
+  return nfail;
+}
+
+int lse_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
+                      lsq_result* res) {
+  for (int i = 0; i < count; ++i)
+    if (!probs || probs[i].type != LSQ_LSE) return -3;
+  return lsq_solve_batched(h, count, probs, opts, res);
+}
+
+int gls_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
+                      lsq_result* res) {
+  for (int i = 0; i < count; ++i)
+    if (!probs || probs[i].type != LSQ_GLS) return -3;
+  return lsq_solve_batched(h, count, probs, opts, res);
+}
+
+// ------------------------------------------------------------ debug ABI --
+int lsq_dbg_qr(lsq_handle h, int prec, int r, int c, const double* M, int ldm, const double* X,
+               int ldx, int nx, double* R, double* Y1, double* Y2, double* Y3) {
+  if (!h) return -1;
+  PrecSpec ps;
+  if (!prec_spec(prec, ps)) return -2;
+  if (r < 0) return -3;
+  if (c < 0) return -4;
+  if (!M || ldm < (r > 1 ? r : 1)) return -5;
+  if (nx > 0 && (!X || ldx < r)) return -7;
+  return guard(h, "lsq_dbg_qr", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    QRFactor f;
+    qr_alloc(ctx, f, r, c, ps.tw, ps.mt, kMaxNb);
+    mat_convert(ctx, f.M, ps.tw, f.ld, M, 8, ldm, r, c, false, false, false);
+    qr_factor(ctx, f);
+    if (R && f.k > 0) {
+      void* tmp = ctx.ws->alloc((size_t)8 * r * c);
+      mat_convert(ctx, tmp, 8, r, f.M, ps.tw, f.ld, r, c, false, false, false);
+      // keep the upper trapezoid of the first k rows
+      std::vector<double> host((size_t)r * c);
+      LSQ_HIP(hipMemcpyAsync(host.data(), tmp, host.size() * 8, hipMemcpyDeviceToHost, h->stream));
+      LSQ_HIP(hipStreamSynchronize(h->stream));
+      std::vector<double> rk((size_t)f.k * c, 0.0);
+      for (int j = 0; j < c; ++j)
+        for (int i = 0; i < f.k && i <= j; ++i) rk[i + (size_t)j * f.k] = host[i + (size_t)j * r];
+      LSQ_HIP(hipMemcpyAsync(R, rk.data(), rk.size() * 8, hipMemcpyHostToDevice, h->stream));
+    }
+    if (nx > 0) {
+      void* Xw = ctx.ws->alloc((size_t)ps.tw * r * nx);
+      if (Y1) {
+        mat_convert(ctx, Xw, ps.tw, r, X, 8, ldx, r, nx, false, false, false);
+        qr_apply_left_T(ctx, f, Xw, r, nx);
+        mat_convert(ctx, Y1, 8, r, Xw, ps.tw, r, r, nx, false, false, false);
+      }
+      if (Y2 || Y3) {
+        void* col = ctx.ws->alloc((size_t)ps.tc * (r > 0 ? r : 1));
+        for (int j = 0; j < nx; ++j) {
+          vec_convert(ctx, col, ps.tc, X + (size_t)j * ldx, 8, r, false);
+          qr_apply_vec(ctx, f, true, col, ps.tc);
+          if (Y2) vec_convert(ctx, Y2 + (size_t)j * r, 8, col, ps.tc, r, false);
+          if (Y3) {
+            qr_apply_vec(ctx, f, false, col, ps.tc);
+            vec_convert(ctx, Y3 + (size_t)j * r, 8, col, ps.tc, r, false);
+          }
+        }
+      }
+    }
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    int st = 0;
+    LSQ_HIP(hipMemcpy(&st, f.status, sizeof(int), hipMemcpyDeviceToHost));
+    return st ? 1 : 0;
+  });
+}
+
+int lsq_dbg_trsv(lsq_handle h, int prec, int tc64, int n, const double* U, int ldu, int trans,
+                 const double* b, double* x) {
+  if (!h) return -1;
+  PrecSpec ps;
+  if (!prec_spec(prec, ps)) return -2;
+  if (n < 0) return -4;
+  if (!U || ldu < (n > 1 ? n : 1)) return -5;
+  return guard(h, "lsq_dbg_trsv", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    QRFactor f;
+    f.r = f.c = f.k = n; f.ld = n > 1 ? n : 1; f.tw = ps.tw; f.mt = ps.mt;
+    f.M = ctx.ws->alloc((size_t)ps.tw * f.ld * (n > 0 ? n : 1));
+    mat_convert(ctx, f.M, ps.tw, f.ld, U, 8, ldu, n, n, false, false, false);
+    const int tc = tc64 ? 8 : ps.tc;
+    TriBlock tb;
+    trsv_prepare(ctx, tb, f, 0, n, tc);
+    void* w = ctx.ws->alloc((size_t)tc * (n > 0 ? n : 1));
+    vec_convert(ctx, w, tc, b, 8, n, false);
+    trsv(ctx, tb, trans != 0, w);
+    vec_convert(ctx, x, 8, w, tc, n, false);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    int e = 0;
+    LSQ_HIP(hipMemcpy(&e, h->ctx.err, sizeof(int), hipMemcpyDeviceToHost));
+    return e ? 4 : 0;
+  });
+}
+
+static void status_out(lsq_handle h, double* out) {
+  read_status(h);
+  const StopStatus& s = *h->st_host;
+  for (int q = 0; q < 3; ++q) {
+    out[q] = s.nf[q];
+    out[3 + q] = s.scale[q];
+    out[6 + q] = s.berr[q];
+  }
+  out[9] = s.berr_max;
+}
+
+int lsq_dbg_lse_residual(lsq_handle h, int m, int n, int p, const double* A, int lda,
+                         const double* B, int ldb, const double* b, const double* d,
+                         const double* x, const double* r, const double* v, double* f1,
+                         double* f2, double* f3, double* out) {
+  if (!h) return -1;
+  return guard(h, "lsq_dbg_lse_residual", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, h->matnorms);
+    lse_residual(ctx, m, n, p, A, lda, B, ldb, b, d, x, r, v, f1, f2, f3, h->matnorms, 1e-14,
+                 h->st_dev);
+    if (out) status_out(h, out);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+  });
+}
+
+int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* W, int ldw,
+                         const double* V, int ldv, const double* d, const double* x,
+                         const double* y, const double* z, double* f1, double* f2, double* f3,
+                         double* out) {
+  if (!h) return -1;
+  return guard(h, "lsq_dbg_gls_residual", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, h->matnorms);
+    gls_residual(ctx, n, m, p, W, ldw, V, ldv, d, x, y, z, f1, f2, f3, h->matnorms, 1e-14,
+                 h->st_dev);
+    if (out) status_out(h, out);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+  });
+}
+
+int lsq_dbg_lse_correction(lsq_handle h, int prec, int m, int n, int p, const double* A, int lda,
+                           const double* B, int ldb, const double* f1, const double* f2,
+                           const double* f3, double* dr, double* dv, double* dx) {
+  if (!h) return -1;
+  PrecSpec ps;
+  if (!prec_spec(prec, ps)) return -2;
+  if (m < 0 || n < 0 || p < 0 || p > n || n > m + p) return -3;
+  return guard(h, "lsq_dbg_lse_correction", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    LseSolver sv;
+    sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
+    sv.factor(ctx, A, lda, B, ldb, kMaxNb);
+    sv.prepare(ctx, ps.tc);
+    vec_zero(ctx, dr, 8, m);
+    vec_zero(ctx, dv, 8, p);
+    vec_zero(ctx, dx, 8, n);
+    sv.correct(ctx, f1, f2, f3, dx, dr, dv);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+  });
+}
+
+int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const double* W, int ldw,
+                           const double* V, int ldv, const double* f1, const double* f2,
+                           const double* f3, double* dy, double* dz, double* dx) {
+  if (!h) return -1;
+  PrecSpec ps;
+  if (!prec_spec(prec, ps)) return -2;
+  if (m < 0 || n < 0 || p < 0 || m > n || n > m + p) return -3;
+  return guard(h, "lsq_dbg_gls_correction", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    GlsSolver sv;
+    sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.ps = ps;
+    sv.factor(ctx, W, ldw, V, ldv, kMaxNb);
+    sv.prepare(ctx, ps.tc);
+    vec_zero(ctx, dy, 8, p);
+    vec_zero(ctx, dz, 8, n);
+    vec_zero(ctx, dx, 8, m);
+    sv.correct(ctx, f1, f2, f3, dx, dy, dz);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Shared definitions of liblsq's HIP sources (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace lsq {
+
+// ---------------------------------------------------------------- errors --
+struct HipError {
+  hipError_t code;
+  const char* where;
+};
+
+#define LSQ_HIP(expr)                                                   \
+  do {                                                                  \
+    hipError_t e_ = (expr);                                             \
+    if (e_ != hipSuccess) throw ::lsq::HipError{e_, #expr};             \
+  } while (0)
+
+#define LSQ_LAUNCH_CHECK() LSQ_HIP(hipGetLastError())
+
+// ------------------------------------------------------------- constants --
+constexpr int kWave = 64;               // CDNA wavefront width
+constexpr int kMaxNb = 64;              // widest panel of the blocked QR
+
+// MFMA input precision used for the trailing updates of the factorization.
+enum class Mma : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3, F8 = 4 };
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------ device utilities --
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+  return __shfl_xor(v, mask, kWave);
+}
+__device__ __forceinline__ float shfl_xor_f(float v, int mask) {
+  return __shfl_xor(v, mask, kWave);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Sum over a whole work-group; `red` is LDS of at least blockDim.x/64 entries.
+// Every thread receives the total.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  T t = 0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// Bounded spin limit for inter-work-group waits.  A wait that exceeds it
+// records an error and gives up, so every wave always reaches its exit.
+constexpr unsigned kSpinLimit = 1u << 24;
+
+// Self-resetting grid barrier for cooperatively launched kernels.
+// bar[0] = arrival count (returns to 0 after every barrier), bar[1] = generation.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+template <typename T> struct Conv;
+template <> struct Conv<float> {
+  __device__ static float from(double v) { return (float)v; }
+};
+template <> struct Conv<double> {
+  __device__ static double from(double v) { return v; }
+};
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace lsq

@@ -1,0 +1,132 @@
+// Host-side interfaces between liblsq's HIP translation units.
+#pragma once
+#include <vector>
+#include <cstdint>
+#include "common.hpp"
+
+namespace lsq {
+
+// ------------------------------------------------------------ workspace --
+// Bump allocator over device chunks.  reset() rewinds without freeing, so a
+// handle reuses the same memory across solves.  Pointers stay valid until the
+// next reset().
+class Arena {
+ public:
+  ~Arena();
+  void* alloc(size_t bytes);
+  template <typename T> T* get(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+  void reset();
+  void release();
+ private:
+  struct Chunk { char* base; size_t size; size_t used; };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0;
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  Arena* ws = nullptr;
+  unsigned* sync = nullptr;     // grid-barrier words (device, zeroed at creation)
+  unsigned* flags = nullptr;    // trsv block flags (device, zeroed at creation)
+  int nflags = 0;
+  unsigned epoch = 0;           // last trsv epoch used
+  int* err = nullptr;           // device error word: 1 = spin limit exceeded
+  int num_cu = 256;
+  int max_coop_blocks = 256;    // co-resident 256-thread blocks for cooperative kernels
+};
+
+// ---------------------------------------------- Householder QR engine ----
+// Blocked Householder QR of an r x c column-major matrix stored in Tw
+// (float or double), k = min(r, c) reflectors in panels of nb columns.
+// After factorization: R on and above the diagonal of M, the unit lower
+// trapezoidal Householder vectors Y below it, and per panel the upper
+// triangular T_j of the compact-WY form H_j = I - Y_j T_j Y_j^T, so that
+// Q = H_0 H_1 ... H_{np-1}.
+struct QRFactor {
+  int r = 0, c = 0, k = 0, ld = 0, nb = 64, np = 0;
+  int tw = 4;                   // sizeof(Tw): 4 (float) or 8 (double)
+  Mma mt = Mma::F32;
+  void* M = nullptr;            // r x c, ld
+  void* T = nullptr;            // np blocks of 64 x 64 (Tw), column-major ld 64
+  void* Yhat = nullptr;         // per panel (r - j0) x 64 (Tw): Y_j T_j^T
+  std::vector<size_t> yoff;     // element offset of panel j in Yhat
+  int* status = nullptr;        // device: bit0 = a panel Cholesky broke down
+};
+
+void qr_alloc(Ctx& ctx, QRFactor& f, int r, int c, int tw, Mma mt, int nb);
+void qr_factor(Ctx& ctx, QRFactor& f);
+// C <- Q^T C for a column-major r x ncols matrix C (same Tw as the factor).
+void qr_apply_left_T(Ctx& ctx, const QRFactor& f, void* C, int ldc, int ncols);
+
+// Vector application of Q (trans = false) or Q^T (trans = true) to y (length
+// f.r) in compute precision Tc (float or double, tc = sizeof).  With rev_in /
+// rev_out the vector is read / written in reversed order.
+void qr_apply_vec(Ctx& ctx, const QRFactor& f, bool trans, void* y, int tc);
+
+// ----------------------------------------------------- vector kernels ----
+// Triangular solve with the upper triangular block U = f.M[o:o+nn, o:o+nn]:
+// x <- U^{-1} x (trans = false) or U^{-T} x (trans = true), Tc precision.
+// The inverse diagonal blocks are cached in `dinv` (see trsv_prepare).
+struct TriBlock {
+  const QRFactor* f = nullptr;
+  int o = 0, nn = 0;
+  void* dinv = nullptr;         // nblk x 64 x 64 (Tc)
+  int tc = 4;
+};
+void trsv_prepare(Ctx& ctx, TriBlock& tb, const QRFactor& f, int o, int nn, int tc);
+void trsv(Ctx& ctx, const TriBlock& tb, bool trans, void* x);
+
+// y[0:nr] += alpha * op(U) x, U = f.M[ro:ro+nr, co:co+nc] read with the upper
+// mask of the factor (entries below its diagonal are zero); op(U) = U or U^T
+// (for trans, y has length nc and x length nr).  Tc precision.
+void gemv_upper(Ctx& ctx, const QRFactor& f, int ro, int co, int nr, int nc, bool trans,
+                double alpha, const void* x, void* y, int tc);
+
+// Elementwise helpers (n elements).  Types by size: 4 float, 8 double.
+void vec_convert(Ctx& ctx, void* dst, int td, const void* src, int ts, int n, bool reverse,
+                 double scale = 1.0);
+void vec_axpy(Ctx& ctx, void* y, int ty, double a, const void* x, int tx, int n, bool reverse_x);
+void vec_zero(Ctx& ctx, void* y, int ty, int n);
+
+// Dense FP64 matrix -> Tw copy with optional transpose and index reversal:
+// dst (dr x dc, ld ldd) [i][j] = src[ri][ci] where (ri, ci) = trans ? (j, i) : (i, j),
+// then ri, ci reversed when rev_r / rev_c (relative to src's own extents).
+void mat_convert(Ctx& ctx, void* dst, int td, int ldd, const void* src, int ts, int lds,
+                 int dr, int dc, bool trans, bool rev_rows_src, bool rev_cols_src);
+
+// ------------------------------------------------- FP64 residual sweep ----
+// One pass over a column-major FP64 matrix M (rows x cols) yielding partial
+// sums of M u (per column block) and M^T w (per row block).
+struct DualParts {
+  double* rowp = nullptr;  int ncb = 0;   // ncb x rows
+  double* colp = nullptr;  int nrb = 0;   // nrb x cols
+};
+void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const double* u,
+               const double* w, DualParts& out);
+
+// Device status of the stop test (eq. lse-stop / eq. gls-stop).
+struct StopStatus {
+  double nf[3];       // ||f_i||
+  double scale[3];    // right-hand sides without tol
+  double berr[3];
+  double berr_max;
+  int converged;
+  int nonfinite;
+};
+// Norm accumulation slots used by the residual kernels.
+constexpr int kNormSlots = 8;
+
+void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
+                  int ldb, const double* b, const double* d, const double* x, const double* r,
+                  const double* v, double* f1, double* f2, double* f3, const double* matnorms,
+                  double tol, StopStatus* st);
+void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
+                  int ldv, const double* d, const double* x, const double* y, const double* z,
+                  double* f1, double* f2, double* f3, const double* matnorms, double tol,
+                  StopStatus* st);
+// matnorms[0..1] = ||A||_F, ||B||_F; matnorms[2..3] = ||b||, ||d|| (LSE) or ||d||, 0 (GLS).
+void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double* B, int ldb,
+                int br, int bc, const double* v1, int n1, const double* v2, int n2,
+                double* matnorms);
+
+}  // namespace lsq

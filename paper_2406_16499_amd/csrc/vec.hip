@@ -1,0 +1,619 @@
+// Vector-side kernels: triangular solves on factor blocks, masked GEMV,
+// conversions / reversals, and the FP64 augmented-residual sweeps with the
+// stop test (eq. lse-stop / eq. gls-stop).
+#include "engine.hpp"
+
+namespace lsq {
+
+// ------------------------------------------------------------ triangular --
+// Inverse of each 64 x 64 diagonal block of U (upper, within the factor
+// storage at offset o).  One work-group per block; FP64 arithmetic.
+template <typename Tw, typename Tc>
+__global__ __launch_bounds__(256) void k_tri_inv(const Tw* __restrict__ M, int ld, int o, int nn,
+                                                 Tc* __restrict__ dinv) {
+  __shared__ double U[64 * 65];
+  __shared__ double X[64 * 65];
+  const int I = blockIdx.x, i0 = I * 64;
+  const int ib = min(64, nn - i0);
+  const int t = threadIdx.x;
+  for (int e = t; e < 4096; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    double v = 0.0;
+    if (i < ib && j < ib && i <= j) v = (double)M[(size_t)(o + i0 + i) + (size_t)(o + i0 + j) * ld];
+    if (i == j && i >= ib) v = 1.0;
+    U[i * 65 + j] = v;
+    X[i * 65 + j] = 0.0;
+  }
+  __syncthreads();
+  if (t < 64) {   // column t of U^{-1} by back substitution
+    const int j = t;
+    X[j * 65 + j] = 1.0 / U[j * 65 + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= j; ++k) s += U[i * 65 + k] * X[k * 65 + j];
+      X[i * 65 + j] = -s / U[i * 65 + i];
+    }
+  }
+  __syncthreads();
+  Tc* out = dinv + (size_t)I * 4096;
+  for (int e = t; e < 4096; e += 256) out[e] = (Tc)X[(e & 63) * 65 + (e >> 6)];
+}
+
+// Block substitution with per-block completion flags (cooperative launch).
+// blockIdx b handles block row I = nblk-1-b (N) or b (T), so a work-group
+// only waits for blocks owned by work-groups with a smaller index.
+template <typename Tw, typename Tc>
+__global__ __launch_bounds__(256) void k_trsv(const Tw* __restrict__ M, int ld, int o, int nn,
+                                              const Tc* __restrict__ dinv, int trans,
+                                              Tc* __restrict__ x, unsigned* __restrict__ flags,
+                                              unsigned epoch, int* __restrict__ err) {
+  __shared__ Tc ts[64 * 65];
+  __shared__ Tc xs[64];
+  __shared__ Tc part[4][64];
+  __shared__ int abort_wait;
+  const int nblk = ceil_div(nn, 64);
+  const int b = blockIdx.x;
+  const int I = trans ? b : (nblk - 1 - b);
+  const int i0 = I * 64, ib = min(64, nn - i0);
+  const int t = threadIdx.x, i = t & 63, q = t >> 6;
+  if (t == 0) abort_wait = 0;
+  Tc acc = 0;
+  if (t < 64 && t < ib) acc = x[i0 + t];
+  for (int d = 0; d < b; ++d) {
+    const int J = trans ? d : (nblk - 1 - d);
+    const int j0 = J * 64, jbb = min(64, nn - j0);
+    __syncthreads();
+    // T block: N -> rows of I, cols of J ; T -> rows of J, cols of I   (stored ts[r][c])
+    for (int e = t; e < 4096; e += 256) {
+      const int rr = e & 63, cc = e >> 6;
+      Tc v = 0;
+      if (!trans) {
+        if (rr < ib && cc < jbb) v = (Tc)M[(size_t)(o + i0 + rr) + (size_t)(o + j0 + cc) * ld];
+      } else {
+        if (rr < jbb && cc < ib) v = (Tc)M[(size_t)(o + j0 + rr) + (size_t)(o + i0 + cc) * ld];
+      }
+      ts[rr * 65 + cc] = v;
+    }
+    if (t == 0) {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&flags[J], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          abort_wait = 1;
+          break;
+        }
+      }
+      __threadfence();
+    }
+    __syncthreads();
+    if (t < 64) xs[t] = (t < jbb) ? __hip_atomic_load(&x[j0 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (Tc)0;
+    __syncthreads();
+    Tc s = 0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = q * 16 + jj;
+      s += (trans ? ts[j * 65 + i] : ts[i * 65 + j]) * xs[j];
+    }
+    part[q][i] = s;
+    __syncthreads();
+    if (t < 64) acc -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    if (abort_wait) break;
+  }
+  __syncthreads();
+  if (t < 64) xs[t] = acc;
+  __syncthreads();
+  const Tc* D = dinv + (size_t)I * 4096;     // D[r + c*64] = (U_II^{-1})[r][c]
+  Tc s = 0;
+#pragma unroll
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = q * 16 + jj;
+    s += (trans ? D[j + i * 64] : D[i + j * 64]) * xs[j];
+  }
+  part[q][i] = s;
+  __syncthreads();
+  if (t < 64 && t < ib) {
+    const Tc v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    __hip_atomic_store(&x[i0 + t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();
+  __syncthreads();
+  if (t == 0) __hip_atomic_store(&flags[I], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename Tw, typename Tc>
+static void trsv_prepare_t(Ctx& ctx, TriBlock& tb) {
+  const int nblk = ceil_div(tb.nn, 64);
+  tb.dinv = ctx.ws->alloc(sizeof(Tc) * 4096 * (size_t)(nblk > 0 ? nblk : 1));
+  if (nblk == 0) return;
+  hipLaunchKernelGGL((k_tri_inv<Tw, Tc>), dim3(nblk), dim3(256), 0, ctx.stream,
+                     static_cast<const Tw*>(tb.f->M), tb.f->ld, tb.o, tb.nn, static_cast<Tc*>(tb.dinv));
+  LSQ_LAUNCH_CHECK();
+}
+
+void trsv_prepare(Ctx& ctx, TriBlock& tb, const QRFactor& f, int o, int nn, int tc) {
+  tb.f = &f; tb.o = o; tb.nn = nn; tb.tc = tc;
+  if (f.tw == 8) {
+    if (tc == 8) trsv_prepare_t<double, double>(ctx, tb); else trsv_prepare_t<double, float>(ctx, tb);
+  } else {
+    if (tc == 8) trsv_prepare_t<float, double>(ctx, tb); else trsv_prepare_t<float, float>(ctx, tb);
+  }
+}
+
+template <typename Tw, typename Tc>
+static void trsv_t(Ctx& ctx, const TriBlock& tb, bool trans, Tc* x) {
+  const int nblk = ceil_div(tb.nn, 64);
+  if (nblk == 0) return;
+  if (nblk > ctx.nflags || nblk > ctx.max_coop_blocks) throw HipError{hipErrorInvalidValue, "trsv too large"};
+  const Tw* M = static_cast<const Tw*>(tb.f->M);
+  int ld = tb.f->ld, o = tb.o, nn = tb.nn, tr = trans ? 1 : 0;
+  const Tc* dinv = static_cast<const Tc*>(tb.dinv);
+  unsigned* flags = ctx.flags;
+  unsigned epoch = ++ctx.epoch;
+  if (epoch == 0) epoch = ++ctx.epoch;
+  int* err = ctx.err;
+  void* args[] = {(void*)&M, (void*)&ld, (void*)&o, (void*)&nn, (void*)&dinv, (void*)&tr,
+                  (void*)&x, (void*)&flags, (void*)&epoch, (void*)&err};
+  LSQ_HIP(hipLaunchCooperativeKernel((const void*)k_trsv<Tw, Tc>, dim3(nblk), dim3(256), args, 0,
+                                     ctx.stream));
+}
+
+void trsv(Ctx& ctx, const TriBlock& tb, bool trans, void* x) {
+  if (tb.nn <= 0) return;
+  if (tb.f->tw == 8) {
+    if (tb.tc == 8) trsv_t<double, double>(ctx, tb, trans, static_cast<double*>(x));
+    else trsv_t<double, float>(ctx, tb, trans, static_cast<float*>(x));
+  } else {
+    if (tb.tc == 8) trsv_t<float, double>(ctx, tb, trans, static_cast<double*>(x));
+    else trsv_t<float, float>(ctx, tb, trans, static_cast<float*>(x));
+  }
+}
+
+// ------------------------------------------------------------ masked GEMV --
+// N: y[i] += alpha * sum_j U[i][j] x[j], one work-group per 64 rows.
+template <typename Tw, typename Tc>
+__global__ __launch_bounds__(256) void k_gemv_upper_n(const Tw* __restrict__ M, int ld, int ro, int co,
+                                                      int nr, int nc, double alpha,
+                                                      const Tc* __restrict__ x, Tc* __restrict__ y) {
+  __shared__ Tc part[4][64];
+  const int t = threadIdx.x, i = t & 63, q = t >> 6;
+  const int row = blockIdx.x * 64 + i;
+  Tc s = 0;
+  if (row < nr) {
+    const int grow = ro + row;
+    for (int j = q; j < nc; j += 4) {
+      const int gcol = co + j;
+      if (grow <= gcol) s += (Tc)M[(size_t)grow + (size_t)gcol * ld] * x[j];
+    }
+  }
+  part[q][i] = s;
+  __syncthreads();
+  if (t < 64 && row < nr) y[row] += (Tc)alpha * (part[0][t] + part[1][t] + part[2][t] + part[3][t]);
+}
+
+// T: y[j] += alpha * sum_i U[i][j] x[i], one wave per output column.
+template <typename Tw, typename Tc>
+__global__ __launch_bounds__(256) void k_gemv_upper_t(const Tw* __restrict__ M, int ld, int ro, int co,
+                                                      int nr, int nc, double alpha,
+                                                      const Tc* __restrict__ x, Tc* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nc) return;
+  const int gcol = co + j;
+  Tc s = 0;
+  const int imax = min(nr, gcol - ro + 1);   // rows with grow <= gcol
+  for (int i = lane; i < imax; i += 64) s += (Tc)M[(size_t)(ro + i) + (size_t)gcol * ld] * x[i];
+  s = wave_sum(s);
+  if (lane == 0) y[j] += (Tc)alpha * s;
+}
+
+void gemv_upper(Ctx& ctx, const QRFactor& f, int ro, int co, int nr, int nc, bool trans,
+                double alpha, const void* x, void* y, int tc) {
+  if (nr <= 0 || nc <= 0) return;
+#define LSQ_GEMV(TW, TC)                                                                        \
+  if (!trans)                                                                                   \
+    hipLaunchKernelGGL((k_gemv_upper_n<TW, TC>), dim3(ceil_div(nr, 64)), dim3(256), 0, ctx.stream, \
+                       static_cast<const TW*>(f.M), f.ld, ro, co, nr, nc, alpha,               \
+                       static_cast<const TC*>(x), static_cast<TC*>(y));                         \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_gemv_upper_t<TW, TC>), dim3(ceil_div(nc, 4)), dim3(256), 0, ctx.stream,  \
+                       static_cast<const TW*>(f.M), f.ld, ro, co, nr, nc, alpha,               \
+                       static_cast<const TC*>(x), static_cast<TC*>(y));
+  if (f.tw == 8) {
+    if (tc == 8) { LSQ_GEMV(double, double) } else { LSQ_GEMV(double, float) }
+  } else {
+    if (tc == 8) { LSQ_GEMV(float, double) } else { LSQ_GEMV(float, float) }
+  }
+#undef LSQ_GEMV
+  LSQ_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------- elementwise ops --
+template <typename Td, typename Ts>
+__global__ void k_vec_convert(Td* __restrict__ dst, const Ts* __restrict__ src, int n, int rev,
+                              double scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = (double)src[rev ? (n - 1 - i) : i];
+  dst[i] = (Td)(v * scale);
+}
+
+template <typename Ty, typename Tx>
+__global__ void k_vec_axpy(Ty* __restrict__ y, double a, const Tx* __restrict__ x, int n, int rev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[i] = (Ty)((double)y[i] + a * (double)x[rev ? (n - 1 - i) : i]);
+}
+
+template <typename T>
+__global__ void k_vec_zero(T* __restrict__ y, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (T)0;
+}
+
+#define LSQ_DISPATCH2(td, ts, F)                         \
+  if ((td) == 8 && (ts) == 8) { F(double, double) }      \
+  else if ((td) == 8) { F(double, float) }               \
+  else if ((ts) == 8) { F(float, double) }               \
+  else { F(float, float) }
+
+void vec_convert(Ctx& ctx, void* dst, int td, const void* src, int ts, int n, bool reverse,
+                 double scale) {
+  if (n <= 0) return;
+#define F(TD, TS)                                                                               \
+  hipLaunchKernelGGL((k_vec_convert<TD, TS>), dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream, \
+                     static_cast<TD*>(dst), static_cast<const TS*>(src), n, reverse ? 1 : 0, scale);
+  LSQ_DISPATCH2(td, ts, F)
+#undef F
+  LSQ_LAUNCH_CHECK();
+}
+
+void vec_axpy(Ctx& ctx, void* y, int ty, double a, const void* x, int tx, int n, bool reverse_x) {
+  if (n <= 0) return;
+#define F(TY, TX)                                                                            \
+  hipLaunchKernelGGL((k_vec_axpy<TY, TX>), dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream, \
+                     static_cast<TY*>(y), a, static_cast<const TX*>(x), n, reverse_x ? 1 : 0);
+  LSQ_DISPATCH2(ty, tx, F)
+#undef F
+  LSQ_LAUNCH_CHECK();
+}
+
+void vec_zero(Ctx& ctx, void* y, int ty, int n) {
+  if (n <= 0) return;
+  if (ty == 8)
+    hipLaunchKernelGGL((k_vec_zero<double>), dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream,
+                       static_cast<double*>(y), n);
+  else
+    hipLaunchKernelGGL((k_vec_zero<float>), dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream,
+                       static_cast<float*>(y), n);
+  LSQ_LAUNCH_CHECK();
+}
+
+// dst (dr x dc) [i][j] = src[a][b], (a, b) = trans ? (j, i) : (i, j), reversed per flags
+// against the source extents (sr x sc).  64 x 64 tiles through LDS.
+template <typename Td, typename Ts>
+__global__ __launch_bounds__(256) void k_mat_convert(Td* __restrict__ dst, int ldd,
+                                                     const Ts* __restrict__ src, int lds, int dr,
+                                                     int dc, int trans, int rev_r, int rev_c,
+                                                     int sr, int sc) {
+  __shared__ double tile[64 * 65];
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int t = threadIdx.x;
+  for (int e = t; e < 4096; e += 256) {
+    const int fast = e & 63, slow = e >> 6;
+    const int i = trans ? i0 + slow : i0 + fast;
+    const int j = trans ? j0 + fast : j0 + slow;
+    double v = 0.0;
+    if (i < dr && j < dc) {
+      int a = trans ? j : i, b = trans ? i : j;
+      if (rev_r) a = sr - 1 - a;
+      if (rev_c) b = sc - 1 - b;
+      v = (double)src[(size_t)a + (size_t)b * lds];
+    }
+    tile[(i - i0) * 65 + (j - j0)] = v;
+  }
+  __syncthreads();
+  for (int e = t; e < 4096; e += 256) {
+    const int i = i0 + (e & 63), j = j0 + (e >> 6);
+    if (i < dr && j < dc) dst[(size_t)i + (size_t)j * ldd] = (Td)tile[(i - i0) * 65 + (j - j0)];
+  }
+}
+
+void mat_convert(Ctx& ctx, void* dst, int td, int ldd, const void* src, int ts, int lds,
+                 int dr, int dc, bool trans, bool rev_r, bool rev_c) {
+  if (dr <= 0 || dc <= 0) return;
+  const int sr = trans ? dc : dr, sc = trans ? dr : dc;
+  dim3 grid(ceil_div(dr, 64), ceil_div(dc, 64));
+#define F(TD, TS)                                                                       \
+  hipLaunchKernelGGL((k_mat_convert<TD, TS>), grid, dim3(256), 0, ctx.stream,           \
+                     static_cast<TD*>(dst), ldd, static_cast<const TS*>(src), lds, dr, dc, \
+                     trans ? 1 : 0, rev_r ? 1 : 0, rev_c ? 1 : 0, sr, sc);
+  LSQ_DISPATCH2(td, ts, F)
+#undef F
+  LSQ_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------- FP64 dual GEMV ----
+// Work-group tile: 256 rows x 64 columns.  Each lane owns one row; the column
+// sums M^T w are reduced across the wave with a reduce-scatter butterfly.
+__global__ __launch_bounds__(256) void k_dual_gemv(const double* __restrict__ M, int ld, int rows,
+                                                   int cols, const double* __restrict__ u,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ rowp,
+                                                   double* __restrict__ colp) {
+  __shared__ double us[64];
+  __shared__ double red[4][64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int r0 = blockIdx.x * 256, c0 = blockIdx.y * 64;
+  if (t < 64) us[t] = (c0 + t < cols) ? u[c0 + t] : 0.0;
+  __syncthreads();
+  const int row = r0 + t;
+  const bool rin = row < rows;
+  const double wr = rin ? w[row] : 0.0;
+  double racc = 0.0;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    double cp[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int col = c0 + half * 32 + c;
+      const double v = (rin && col < cols) ? M[(size_t)row + (size_t)col * ld] : 0.0;
+      racc += v * us[half * 32 + c];
+      cp[c] = v * wr;
+    }
+    // 32 values over 64 lanes: exchange across lane bits 5..1, then add lane pairs
+    {
+#pragma unroll
+      for (int m = 32, c = 32; c > 1; m >>= 1, c >>= 1) {
+        const bool up = (lane & m) != 0;
+#pragma unroll
+        for (int i = 0; i < c / 2; ++i) {
+          const double send = up ? cp[i] : cp[i + c / 2];
+          const double keep = up ? cp[i + c / 2] : cp[i];
+          cp[i] = keep + __shfl_xor(send, m, 64);
+        }
+      }
+      cp[0] += __shfl_xor(cp[0], 1, 64);
+    }
+    // lane l now holds the wave sum of column index (l >> 1): bits 5..1 select it
+    if ((lane & 1) == 0) red[wv][half * 32 + (lane >> 1)] = cp[0];
+  }
+  if (rin) rowp[(size_t)blockIdx.y * rows + row] = racc;
+  __syncthreads();
+  if (t < 64 && c0 + t < cols)
+    colp[(size_t)blockIdx.x * cols + c0 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const double* u,
+               const double* w, DualParts& out) {
+  out.nrb = ceil_div(rows, 256);
+  out.ncb = ceil_div(cols, 64);
+  out.rowp = ctx.ws->get<double>((size_t)out.ncb * (rows > 0 ? rows : 1));
+  out.colp = ctx.ws->get<double>((size_t)out.nrb * (cols > 0 ? cols : 1));
+  if (rows <= 0 || cols <= 0) {
+    out.nrb = out.ncb = 0;
+    return;
+  }
+  hipLaunchKernelGGL(k_dual_gemv, dim3(out.nrb, out.ncb), dim3(256), 0, ctx.stream, M, ld, rows,
+                     cols, u, w, out.rowp, out.colp);
+  LSQ_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------- residual finish --
+struct PartsView {
+  const double* p; int nparts; int len;
+  __device__ double sum(int i) const {
+    double s = 0.0;
+    for (int q = 0; q < nparts; ++q) s += p[(size_t)q * len + i];
+    return s;
+  }
+};
+
+// LSE: f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v, plus partial sums of
+// squares of f1, f2, f3, x, r, v into normp[block][6].
+__global__ __launch_bounds__(256) void k_lse_finish(int m, int n, int p, const double* __restrict__ b,
+                                                    const double* __restrict__ d,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ r,
+                                                    const double* __restrict__ v, PartsView Ax,
+                                                    PartsView Atr, PartsView Bx, PartsView Btv,
+                                                    double* __restrict__ f1, double* __restrict__ f2,
+                                                    double* __restrict__ f3,
+                                                    double* __restrict__ normp) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (i < m) {
+    const double val = b[i] - r[i] - Ax.sum(i);
+    f1[i] = val;
+    s[0] = val * val;
+    s[4] = r[i] * r[i];
+  }
+  if (i < p) {
+    const double val = d[i] - Bx.sum(i);
+    f2[i] = val;
+    s[1] = val * val;
+    s[5] = v[i] * v[i];
+  }
+  if (i < n) {
+    const double val = -Atr.sum(i) + Btv.sum(i);
+    f3[i] = val;
+    s[2] = val * val;
+    s[3] = x[i] * x[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double tot = block_sum(s[k], red);
+    if (threadIdx.x == 0) normp[(size_t)blockIdx.x * kNormSlots + k] = tot;
+  }
+}
+
+// GLS: f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z; squares of f1, f2, f3, x, y, z.
+__global__ __launch_bounds__(256) void k_gls_finish(int n, int m, int p, const double* __restrict__ d,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ z, PartsView Wx,
+                                                    PartsView Wtz, PartsView Vy, PartsView Vtz,
+                                                    double* __restrict__ f1, double* __restrict__ f2,
+                                                    double* __restrict__ f3,
+                                                    double* __restrict__ normp) {
+  __shared__ double red[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (i < p) {
+    const double val = -y[i] + Vtz.sum(i);
+    f1[i] = val;
+    s[0] = val * val;
+    s[4] = y[i] * y[i];
+  }
+  if (i < n) {
+    const double val = d[i] - Wx.sum(i) - Vy.sum(i);
+    f2[i] = val;
+    s[1] = val * val;
+    s[5] = z[i] * z[i];
+  }
+  if (i < m) {
+    const double val = Wtz.sum(i);
+    f3[i] = val;
+    s[2] = val * val;
+    s[3] = x[i] * x[i];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double tot = block_sum(s[k], red);
+    if (threadIdx.x == 0) normp[(size_t)blockIdx.x * kNormSlots + k] = tot;
+  }
+}
+
+// Stop test.  norms: [||f1||^2, ||f2||^2, ||f3||^2, ||x||^2, ||a1||^2, ||a2||^2]
+// matnorms: [||A||_F, ||B||_F, ||rhs1||, ||rhs2||].
+// LSE (gls = 0): scale1 = ||b|| + ||r|| + ||A|| ||x||, scale2 = ||d|| + ||B|| ||x||,
+//                scale3 = ||A|| ||r|| + ||B|| ||v||              (a1 = r, a2 = v)
+// GLS (gls = 1): scale1 = ||y|| + ||V|| ||z||, scale2 = ||d|| + ||W|| ||x|| + ||V|| ||y||,
+//                scale3 = ||W|| ||z||    (A = W, B = V, a1 = y, a2 = z, rhs1 = ||d||)
+__global__ void k_stop(const double* __restrict__ normp, int nblk, const double* __restrict__ matnorms,
+                       int gls, double tol, StopStatus* __restrict__ st) {
+  __shared__ double red[4];
+  __shared__ double nrm[6];
+  for (int k = 0; k < 6; ++k) {
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += blockDim.x) s += normp[(size_t)q * kNormSlots + k];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) nrm[k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double nf1 = sqrt(nrm[0]), nf2 = sqrt(nrm[1]), nf3 = sqrt(nrm[2]);
+  const double nx = sqrt(nrm[3]), na1 = sqrt(nrm[4]), na2 = sqrt(nrm[5]);
+  const double nA = matnorms[0], nB = matnorms[1], nr1 = matnorms[2], nr2 = matnorms[3];
+  double sc[3];
+  if (!gls) {
+    sc[0] = nr1 + na1 + nA * nx;
+    sc[1] = nr2 + nB * nx;
+    sc[2] = nA * na1 + nB * na2;
+  } else {
+    sc[0] = na1 + nB * na2;
+    sc[1] = nr1 + nA * nx + nB * na1;
+    sc[2] = nA * na2;
+  }
+  const double nf[3] = {nf1, nf2, nf3};
+  int conv = 1, bad = 0;
+  double bm = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    st->nf[k] = nf[k];
+    st->scale[k] = sc[k];
+    double e = 0.0;
+    if (nf[k] > 0.0) e = sc[k] > 0.0 ? nf[k] / sc[k] : INFINITY;
+    st->berr[k] = e;
+    if (!(nf[k] <= tol * sc[k])) conv = 0;
+    if (!isfinite(nf[k]) || !isfinite(sc[k])) bad = 1;
+    bm = e > bm ? e : bm;
+  }
+  if (!isfinite(nx) || !isfinite(na1) || !isfinite(na2)) bad = 1;
+  st->berr_max = bm;
+  st->converged = conv && !bad;
+  st->nonfinite = bad;
+}
+
+void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
+                  int ldb, const double* b, const double* d, const double* x, const double* r,
+                  const double* v, double* f1, double* f2, double* f3, const double* matnorms,
+                  double tol, StopStatus* st) {
+  DualParts pa, pb;
+  dual_gemv(ctx, A, lda, m, n, x, r, pa);
+  dual_gemv(ctx, B, ldb, p, n, x, v, pb);
+  const int len = m > n ? (m > p ? m : p) : (n > p ? n : p);
+  const int nblk = ceil_div(len, 256);
+  double* normp = ctx.ws->get<double>((size_t)nblk * kNormSlots);
+  PartsView Ax{pa.rowp, pa.ncb, m}, Atr{pa.colp, pa.nrb, n}, Bx{pb.rowp, pb.ncb, p},
+      Btv{pb.colp, pb.nrb, n};
+  hipLaunchKernelGGL(k_lse_finish, dim3(nblk), dim3(256), 0, ctx.stream, m, n, p, b, d, x, r, v, Ax,
+                     Atr, Bx, Btv, f1, f2, f3, normp);
+  hipLaunchKernelGGL(k_stop, dim3(1), dim3(256), 0, ctx.stream, normp, nblk, matnorms, 0, tol, st);
+  LSQ_LAUNCH_CHECK();
+}
+
+void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
+                  int ldv, const double* d, const double* x, const double* y, const double* z,
+                  double* f1, double* f2, double* f3, const double* matnorms, double tol,
+                  StopStatus* st) {
+  DualParts pw, pv;
+  dual_gemv(ctx, W, ldw, n, m, x, z, pw);
+  dual_gemv(ctx, V, ldv, n, p, y, z, pv);
+  const int len = m > n ? (m > p ? m : p) : (n > p ? n : p);
+  const int nblk = ceil_div(len, 256);
+  double* normp = ctx.ws->get<double>((size_t)nblk * kNormSlots);
+  PartsView Wx{pw.rowp, pw.ncb, n}, Wtz{pw.colp, pw.nrb, m}, Vy{pv.rowp, pv.ncb, n},
+      Vtz{pv.colp, pv.nrb, p};
+  hipLaunchKernelGGL(k_gls_finish, dim3(nblk), dim3(256), 0, ctx.stream, n, m, p, d, x, y, z, Wx,
+                     Wtz, Vy, Vtz, f1, f2, f3, normp);
+  hipLaunchKernelGGL(k_stop, dim3(1), dim3(256), 0, ctx.stream, normp, nblk, matnorms, 1, tol, st);
+  LSQ_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------------- norms ----
+__global__ __launch_bounds__(256) void k_sumsq_mat(const double* __restrict__ M, int ld, int rows,
+                                                   int cols, double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  const size_t total = (size_t)rows * cols;
+  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    const size_t i = e % rows, j = e / rows;
+    const double v = M[i + j * (size_t)ld];
+    s += v * v;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_norms_final(const double* __restrict__ part, int per, double* __restrict__ out) {
+  __shared__ double red[4];
+  for (int k = 0; k < 4; ++k) {
+    double s = 0.0;
+    for (int q = threadIdx.x; q < per; q += blockDim.x) s += part[(size_t)k * per + q];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[k] = sqrt(s);
+  }
+}
+
+void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double* B, int ldb,
+                int br, int bc, const double* v1, int n1, const double* v2, int n2,
+                double* matnorms) {
+  const int per = 512;
+  double* part = ctx.ws->get<double>(4 * per);
+  vec_zero(ctx, part, 8, 4 * per);
+  const double* mats[4] = {A, B, v1, v2};
+  const int rr[4] = {ar, br, n1, n2}, cc[4] = {ac, bc, 1, 1}, ll[4] = {lda, ldb, n1 > 0 ? n1 : 1, n2 > 0 ? n2 : 1};
+  for (int k = 0; k < 4; ++k) {
+    if (!mats[k] || rr[k] <= 0 || cc[k] <= 0) continue;
+    const size_t total = (size_t)rr[k] * cc[k];
+    int g = (int)((total + 255) / 256);
+    if (g > per) g = per;
+    hipLaunchKernelGGL(k_sumsq_mat, dim3(g), dim3(256), 0, ctx.stream, mats[k], ll[k], rr[k], cc[k],
+                       part + (size_t)k * per);
+  }
+  hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, ctx.stream, part, per, matnorms);
+  LSQ_LAUNCH_CHECK();
+}
+
+}  // namespace lsq

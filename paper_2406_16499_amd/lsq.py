@@ -1,0 +1,317 @@
+"""Thin ctypes binding of liblsq (include/lsq.h, include/lsq_debug.h).
+
+Argument marshalling only: every step of a solve runs in liblsq's HIP
+kernels.  PyTorch provides device memory and the current stream; tensors are
+passed by data pointer.  Matrices must be float64 CUDA/HIP tensors in
+column-major layout (stride(0) == 1), as produced by `colmajor`.
+
+If liblsq.so has not been built, `load()` raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsq.so")
+HEADERS = [os.path.join(os.path.dirname(_HERE), "include", h) for h in ("lsq.h", "lsq_debug.h")]
+
+PREC = {"auto": 0, "fp8": 1, "bf16": 2, "fp16": 3, "fp32": 4, "fp64": 5}
+PREC_NAME = {v: k for k, v in PREC.items()}
+SOLVER = {"auto": 0, "ir": 1, "gmres": 2, "direct": 3}
+SOLVER_NAME = {v: k for k, v in SOLVER.items()}
+LSE, GLS = 0, 1
+
+c_int, c_double, c_void_p, c_float = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_float
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("prec", c_int), ("solver", c_int), ("tol", c_double), ("maxit", c_int),
+                ("gmres_restart", c_int), ("gmres_tol", c_double), ("gmres_maxit", c_int),
+                ("escalate", c_int), ("alpha", c_double), ("beta", c_double), ("nb", c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("info", c_int), ("prec_used", c_int), ("solver_used", c_int),
+                ("attempts", c_int), ("ir_steps", c_int), ("gmres_iters", c_int),
+                ("berr", c_double * 3), ("berr_max", c_double), ("ms_convert", c_float),
+                ("ms_factor", c_float), ("ms_refine", c_float)]
+
+    def as_dict(self):
+        return {"info": self.info, "prec_used": PREC_NAME.get(self.prec_used, self.prec_used),
+                "solver_used": SOLVER_NAME.get(self.solver_used, self.solver_used),
+                "attempts": self.attempts, "ir_steps": self.ir_steps,
+                "gmres_iters": self.gmres_iters, "berr": list(self.berr),
+                "berr_max": self.berr_max, "ms_convert": self.ms_convert,
+                "ms_factor": self.ms_factor, "ms_refine": self.ms_refine}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("type", c_int), ("m", c_int), ("n", c_int), ("p", c_int),
+                ("A", c_void_p), ("B", c_void_p), ("b", c_void_p), ("d", c_void_p),
+                ("lda", c_int), ("ldb", c_int), ("x", c_void_p), ("y", c_void_p)]
+
+
+_P = c_void_p
+_SIGS = {
+    "lsq_create": (c_int, [ctypes.POINTER(c_void_p), c_int]),
+    "lsq_destroy": (c_int, [_P]),
+    "lsq_set_stream": (c_int, [_P, _P]),
+    "lsq_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "lse_solve": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P, _P, _P,
+                          ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
+    "gls_solve": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P, _P,
+                          ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
+    "lsq_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Result)]),
+    "lse_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Result)]),
+    "gls_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                  ctypes.POINTER(Result)]),
+    "lsq_dbg_qr": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, c_int, _P, _P, _P, _P]),
+    "lsq_dbg_trsv": (c_int, [_P, c_int, c_int, c_int, _P, c_int, c_int, _P, _P]),
+    "lsq_dbg_lse_residual": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P,
+                                     _P, _P, _P, _P, _P, ctypes.POINTER(c_double)]),
+    "lsq_dbg_gls_residual": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P,
+                                     _P, _P, _P, _P, ctypes.POINTER(c_double)]),
+    "lsq_dbg_lse_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
+                                       _P, _P, _P, _P, _P]),
+    "lsq_dbg_gls_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
+                                       _P, _P, _P, _P, _P]),
+    "lsq_last_error": (ctypes.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def header_symbols():
+    """Function names declared in include/lsq.h and include/lsq_debug.h."""
+    names = []
+    for h in HEADERS:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        for mt in re.finditer(r"^(?:[A-Za-z_][\w\s\*]*?)\b([a-z_][a-z0-9_]*)\s*\(", txt, flags=re.M):
+            name = mt.group(1)
+            if name not in names and not name.startswith("LSQ"):
+                names.append(name)
+    return names
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblsq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2406_16499_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    load().lsq_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PREC[v]
+        if k == "solver" and isinstance(v, str):
+            v = SOLVER[v]
+        setattr(o, k, v)
+    return o
+
+
+# ----------------------------------------------------------- tensors ----
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(a, device="cuda"):
+    """float64 device tensor with column-major storage (ld = rows) holding `a`."""
+    torch = _torch()
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        t = torch.empty(a.shape[0], dtype=torch.float64, device=device)
+        t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+        return t
+    r, c = a.shape
+    t = torch.empty_strided((r, c), (1, max(r, 1)), dtype=torch.float64, device=device)
+    t.copy_(torch.from_numpy(np.asfortranarray(a)))
+    return t
+
+
+def empty(n, device="cuda"):
+    torch = _torch()
+    return torch.zeros(max(int(n), 0), dtype=torch.float64, device=device)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    assert t.dtype == torch.float64, "liblsq takes float64 tensors"
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else ctypes.c_void_p(t.data_ptr() or 8)
+
+
+def _ld(t):
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    r, c = t.shape
+    if c > 1 and t.stride(0) != 1:
+        raise ValueError("matrix must be column-major (stride(0) == 1); use lsq.colmajor")
+    return max(int(t.stride(1)) if c > 1 else r, 1)
+
+
+class Handle:
+    """Owns an lsq_handle bound to the current torch device and stream."""
+
+    def __init__(self, device: Optional[int] = None):
+        torch = _torch()
+        self.lib = load()
+        dev = torch.cuda.current_device() if device is None else device
+        h = ctypes.c_void_p()
+        rc = self.lib.lsq_create(ctypes.byref(h), dev)
+        if rc != 0:
+            raise RuntimeError(f"lsq_create failed ({rc})")
+        self.h = h
+        self.sync_stream()
+
+    def sync_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream().cuda_stream
+        self.lib.lsq_set_stream(self.h, ctypes.c_void_p(s))
+
+    def close(self):
+        if self.h:
+            self.lib.lsq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return (self.lib.lsq_last_error(self.h) or b"").decode()
+
+    # -------------------------------------------------------- solvers --
+    def lse_solve(self, A, B, b, d, x, r=None, v=None, opts: Optional[Opts] = None):
+        m, n = A.shape
+        p = B.shape[0]
+        res = Result()
+        rc = self.lib.lse_solve(self.h, m, n, p, _ptr(A), _ld(A), _ptr(B), _ld(B) if p else 1,
+                                _ptr(b), _ptr(d), _ptr(x), _ptr(r), _ptr(v),
+                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(res))
+        return rc, res
+
+    def gls_solve(self, W, V, d, x, y, z=None, opts: Optional[Opts] = None):
+        n, m = W.shape
+        p = V.shape[1]
+        res = Result()
+        rc = self.lib.gls_solve(self.h, n, m, p, _ptr(W), _ld(W), _ptr(V), _ld(V), _ptr(d),
+                                _ptr(x), _ptr(y), _ptr(z),
+                                ctypes.byref(opts) if opts is not None else None, ctypes.byref(res))
+        return rc, res
+
+    def lsq_solve_batched(self, problems, opts: Optional[Opts] = None, which: str = "lsq"):
+        arr = (Problem * len(problems))(*problems)
+        res = (Result * len(problems))()
+        fn = {"lsq": self.lib.lsq_solve_batched, "lse": self.lib.lse_solve_batched,
+              "gls": self.lib.gls_solve_batched}[which]
+        rc = fn(self.h, len(problems), arr, ctypes.byref(opts) if opts is not None else None, res)
+        return rc, list(res)
+
+    # ---------------------------------------------------------- debug --
+    def dbg_qr(self, prec, M, X=None, want=("R", "Y1", "Y2", "Y3")):
+        torch = _torch()
+        r, c = M.shape
+        k = min(r, c)
+        nx = 0 if X is None else X.shape[1]
+        R = torch.zeros((k, c), dtype=torch.float64, device=M.device).t().contiguous().t() if "R" in want else None
+        outs = {}
+        for key in ("Y1", "Y2", "Y3"):
+            outs[key] = (torch.empty_strided((r, nx), (1, max(r, 1)), dtype=torch.float64,
+                                             device=M.device) if (key in want and nx) else None)
+        Rp = None
+        if R is not None:
+            R = torch.empty_strided((k, c), (1, max(k, 1)), dtype=torch.float64, device=M.device)
+            Rp = _ptr(R)
+        rc = self.lib.lsq_dbg_qr(self.h, PREC[prec] if isinstance(prec, str) else prec, r, c,
+                                 _ptr(M), _ld(M), _ptr(X), _ld(X) if X is not None else max(r, 1), nx,
+                                 Rp, _ptr(outs["Y1"]), _ptr(outs["Y2"]), _ptr(outs["Y3"]))
+        return rc, R, outs["Y1"], outs["Y2"], outs["Y3"]
+
+    def dbg_trsv(self, prec, U, b, trans=False, tc64=False):
+        x = empty(U.shape[0], device=U.device)
+        rc = self.lib.lsq_dbg_trsv(self.h, PREC[prec] if isinstance(prec, str) else prec,
+                                   1 if tc64 else 0, U.shape[0], _ptr(U), _ld(U),
+                                   1 if trans else 0, _ptr(b), _ptr(x))
+        return rc, x
+
+    def dbg_lse_residual(self, A, B, b, d, x, r, v):
+        m, n = A.shape
+        p = B.shape[0]
+        f1, f2, f3 = empty(m, A.device), empty(p, A.device), empty(n, A.device)
+        out = (c_double * 10)()
+        rc = self.lib.lsq_dbg_lse_residual(self.h, m, n, p, _ptr(A), _ld(A), _ptr(B),
+                                           _ld(B) if p else 1, _ptr(b), _ptr(d), _ptr(x), _ptr(r),
+                                           _ptr(v), _ptr(f1), _ptr(f2), _ptr(f3), out)
+        return rc, (f1, f2, f3), list(out)
+
+    def dbg_gls_residual(self, W, V, d, x, y, z):
+        n, m = W.shape
+        p = V.shape[1]
+        f1, f2, f3 = empty(p, W.device), empty(n, W.device), empty(m, W.device)
+        out = (c_double * 10)()
+        rc = self.lib.lsq_dbg_gls_residual(self.h, n, m, p, _ptr(W), _ld(W), _ptr(V), _ld(V),
+                                           _ptr(d), _ptr(x), _ptr(y), _ptr(z), _ptr(f1), _ptr(f2),
+                                           _ptr(f3), out)
+        return rc, (f1, f2, f3), list(out)
+
+    def dbg_lse_correction(self, prec, A, B, f1, f2, f3):
+        m, n = A.shape
+        p = B.shape[0]
+        dr, dv, dx = empty(m, A.device), empty(p, A.device), empty(n, A.device)
+        rc = self.lib.lsq_dbg_lse_correction(self.h, PREC[prec] if isinstance(prec, str) else prec,
+                                             m, n, p, _ptr(A), _ld(A), _ptr(B), _ld(B) if p else 1,
+                                             _ptr(f1), _ptr(f2), _ptr(f3), _ptr(dr), _ptr(dv),
+                                             _ptr(dx))
+        return rc, dr, dv, dx
+
+    def dbg_gls_correction(self, prec, W, V, f1, f2, f3):
+        n, m = W.shape
+        p = V.shape[1]
+        dy, dz, dx = empty(p, W.device), empty(n, W.device), empty(m, W.device)
+        rc = self.lib.lsq_dbg_gls_correction(self.h, PREC[prec] if isinstance(prec, str) else prec,
+                                             n, m, p, _ptr(W), _ld(W), _ptr(V), _ld(V), _ptr(f1),
+                                             _ptr(f2), _ptr(f3), _ptr(dy), _ptr(dz), _ptr(dx))
+        return rc, dy, dz, dx
+
+
+def make_problem(kind, tensors, x, y=None) -> Problem:
+    """Batch descriptor from device tensors (LSE: A, B, b, d; GLS: W, V, d)."""
+    pr = Problem()
+    if kind == "lse":
+        A, B, b, d = tensors
+        pr.type, pr.m, pr.n, pr.p = LSE, A.shape[0], A.shape[1], B.shape[0]
+        pr.A, pr.B, pr.b, pr.d = A.data_ptr(), B.data_ptr(), b.data_ptr(), d.data_ptr()
+        pr.lda, pr.ldb = _ld(A), (_ld(B) if B.shape[0] else 1)
+        pr.x, pr.y = x.data_ptr(), None
+    else:
+        W, V, d = tensors
+        pr.type, pr.n, pr.m, pr.p = GLS, W.shape[0], W.shape[1], V.shape[1]
+        pr.A, pr.B, pr.b, pr.d = W.data_ptr(), V.data_ptr(), None, d.data_ptr()
+        pr.lda, pr.ldb = _ld(W), _ld(V)
+        pr.x, pr.y = x.data_ptr(), y.data_ptr()
+    return pr

@@ -93,6 +93,9 @@ bool prec_spec(int prec, PrecSpec& ps) {
   }
 }
 
+// panels per aggregated block for the vector application of Q and Z
+constexpr int kAggPanels = 8;
+
 int default_nb(const lsq_opts& o) { return (o.nb > 0 && o.nb <= kMaxNb) ? o.nb : kMaxNb; }
 
 void* off(void* p, size_t bytes) { return static_cast<char*>(p) + bytes; }
@@ -128,6 +131,8 @@ struct LseSolver {
     tc = tc_;
     trsv_prepare(ctx, tR, fb, 0, p, tc);
     trsv_prepare(ctx, tT11, fa, 0, k, tc);
+    agg_prepare(ctx, fb, tc, kAggPanels);
+    agg_prepare(ctx, fa, tc, kAggPanels);
     alloc_vectors(ctx);
   }
 
@@ -137,10 +142,10 @@ struct LseSolver {
     const size_t e = (size_t)tc;
     // line 1: u~ = Qt^T (J f3)
     if (f3) vec_convert(ctx, U, tc, f3, 8, n, true); else vec_zero(ctx, U, tc, n);
-    qr_apply_vec(ctx, fb, true, U, tc);
+    agg_apply(ctx, fb, true, U, tc);
     // line 2: w = Z^T f1
     vec_convert(ctx, Wv, tc, f1, 8, m, false);
-    qr_apply_vec(ctx, fa, true, Wv, tc);
+    agg_apply(ctx, fa, true, Wv, tc);
     // line 3: R y2 = f2  <=>  Rt^T (J y2) = J f2
     vec_convert(ctx, Y2, tc, f2, 8, p, true);
     trsv(ctx, tR, true, Y2);
@@ -164,11 +169,11 @@ struct LseSolver {
     trsv(ctx, tR, false, X2);
     vec_axpy(ctx, v, 8, 1.0, X2, tc, p, true);
     // line 7: dr = Z q ; dx = Q^T y = J Qt (J y),  J y = [y2~; J y1]
-    qr_apply_vec(ctx, fa, false, Qv, tc);
+    agg_apply(ctx, fa, false, Qv, tc);
     vec_axpy(ctx, r, 8, 1.0, Qv, tc, m, false);
     vec_convert(ctx, Yt, tc, Y2, tc, p, false);
     vec_convert(ctx, off(Yt, e * p), tc, Y1, tc, k, true);
-    qr_apply_vec(ctx, fb, false, Yt, tc);
+    agg_apply(ctx, fb, false, Yt, tc);
     vec_axpy(ctx, x, 8, 1.0, Yt, tc, n, true);
   }
 };
@@ -204,6 +209,8 @@ struct GlsSolver {
     tc = tc_;
     trsv_prepare(ctx, tR, fw, 0, m, tc);
     trsv_prepare(ctx, tA11, fv, 0, k, tc);
+    agg_prepare(ctx, fw, tc, kAggPanels);
+    agg_prepare(ctx, fv, tc, kAggPanels);
     alloc_vectors(ctx);
   }
 
@@ -213,10 +220,10 @@ struct GlsSolver {
     const size_t e = (size_t)tc;
     // line 1: u = Q^T f2
     vec_convert(ctx, U, tc, f2, 8, n, false);
-    qr_apply_vec(ctx, fw, true, U, tc);
+    agg_apply(ctx, fw, true, U, tc);
     // line 2: w~ = J w = Zt^T (J f1)
     if (f1) vec_convert(ctx, Wt, tc, f1, 8, p, true); else vec_zero(ctx, Wt, tc, p);
-    qr_apply_vec(ctx, fv, true, Wt, tc);
+    agg_apply(ctx, fv, true, Wt, tc);
     // line 3: R^T h1 = f3
     if (f3) vec_convert(ctx, H1, tc, f3, 8, m, false); else vec_zero(ctx, H1, tc, m);
     trsv(ctx, tR, true, H1);
@@ -242,9 +249,9 @@ struct GlsSolver {
     // line 7: dz = -Q h, h = [h1; J h2~] ; dy = Z^T g = J Zt (J g)
     vec_convert(ctx, Hv, tc, H1, tc, m, false);
     vec_convert(ctx, off(Hv, e * m), tc, H2t, tc, k, true);
-    qr_apply_vec(ctx, fw, false, Hv, tc);
+    agg_apply(ctx, fw, false, Hv, tc);
     vec_axpy(ctx, z, 8, -1.0, Hv, tc, n, false);
-    qr_apply_vec(ctx, fv, false, G, tc);
+    agg_apply(ctx, fv, false, G, tc);
     vec_axpy(ctx, y, 8, 1.0, G, tc, p, true);
   }
 };
@@ -471,13 +478,6 @@ int lsq_create(lsq_handle* out, int device) {
     LSQ_HIP(hipSetDevice(device));
     h->ctx.ws = &h->arena;
     h->ctx.stream = nullptr;
-    h->ctx.nflags = 4096;
-    LSQ_HIP(hipMalloc(&h->ctx.sync, 64 * sizeof(unsigned)));
-    LSQ_HIP(hipMemset(h->ctx.sync, 0, 64 * sizeof(unsigned)));
-    LSQ_HIP(hipMalloc(&h->ctx.flags, h->ctx.nflags * sizeof(unsigned)));
-    LSQ_HIP(hipMemset(h->ctx.flags, 0, h->ctx.nflags * sizeof(unsigned)));
-    LSQ_HIP(hipMalloc(&h->ctx.err, 64));
-    LSQ_HIP(hipMemset(h->ctx.err, 0, 64));
     LSQ_HIP(hipMalloc(&h->st_dev, sizeof(StopStatus)));
     LSQ_HIP(hipHostMalloc(&h->st_host, sizeof(StopStatus), 0));
     LSQ_HIP(hipMalloc(&h->matnorms, 8 * sizeof(double)));
@@ -485,7 +485,6 @@ int lsq_create(lsq_handle* out, int device) {
     hipDeviceProp_t prop;
     LSQ_HIP(hipGetDeviceProperties(&prop, device));
     h->ctx.num_cu = prop.multiProcessorCount;
-    h->ctx.max_coop_blocks = prop.multiProcessorCount;   // one 256-thread block per CU is always co-resident
     LSQ_HIP(hipDeviceSynchronize());
   } catch (const HipError&) {
     lsq_destroy(h);
@@ -500,9 +499,6 @@ int lsq_destroy(lsq_handle h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   h->arena.release();
-  if (h->ctx.sync) (void)hipFree(h->ctx.sync);
-  if (h->ctx.flags) (void)hipFree(h->ctx.flags);
-  if (h->ctx.err) (void)hipFree(h->ctx.err);
   if (h->st_dev) (void)hipFree(h->st_dev);
   if (h->st_host) (void)hipHostFree(h->st_host);
   if (h->matnorms) (void)hipFree(h->matnorms);
@@ -705,13 +701,14 @@ int lsq_dbg_qr(lsq_handle h, int prec, int r, int c, const double* M, int ldm, c
         mat_convert(ctx, Y1, 8, r, Xw, ps.tw, r, r, nx, false, false, false);
       }
       if (Y2 || Y3) {
+        agg_prepare(ctx, f, ps.tc, kAggPanels);
         void* col = ctx.ws->alloc((size_t)ps.tc * (r > 0 ? r : 1));
         for (int j = 0; j < nx; ++j) {
           vec_convert(ctx, col, ps.tc, X + (size_t)j * ldx, 8, r, false);
-          qr_apply_vec(ctx, f, true, col, ps.tc);
+          agg_apply(ctx, f, true, col, ps.tc);
           if (Y2) vec_convert(ctx, Y2 + (size_t)j * r, 8, col, ps.tc, r, false);
           if (Y3) {
-            qr_apply_vec(ctx, f, false, col, ps.tc);
+            agg_apply(ctx, f, false, col, ps.tc);
             vec_convert(ctx, Y3 + (size_t)j * r, 8, col, ps.tc, r, false);
           }
         }
@@ -745,9 +742,7 @@ int lsq_dbg_trsv(lsq_handle h, int prec, int tc64, int n, const double* U, int l
     trsv(ctx, tb, trans != 0, w);
     vec_convert(ctx, x, 8, w, tc, n, false);
     LSQ_HIP(hipStreamSynchronize(h->stream));
-    int e = 0;
-    LSQ_HIP(hipMemcpy(&e, h->ctx.err, sizeof(int), hipMemcpyDeviceToHost));
-    return e ? 4 : 0;
+    return 0;
   });
 }
 

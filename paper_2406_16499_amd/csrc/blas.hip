@@ -1,0 +1,428 @@
+// Dense building blocks on MFMA: a masked, batched GEMM, the inverse of an
+// upper triangular matrix by recursive doubling, and the GEMV kernels that
+// apply aggregated block reflectors to a vector.  None of these kernels waits
+// on another work-group.
+#include "engine.hpp"
+#include "wg64.hpp"
+
+namespace lsq {
+
+template <typename T> struct MmaOf;
+template <> struct MmaOf<float> {
+  using V = f32x4;
+  static constexpr int PAD = 4;
+  __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct MmaOf<double> {
+  using V = f64x4;
+  static constexpr int PAD = 2;
+  __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+
+// Element (i, j) of a masked operand stored column-major.  mask: 0 dense,
+// 1 upper (zero when i + off > j), 2 unit lower (value when i + off > j,
+// 1 on the diagonal, zero above).
+template <typename S>
+__device__ __forceinline__ double mload(const S* p, int ld, int i, int j, int mask, int off) {
+  if (mask == 1 && i + off > j) return 0.0;
+  if (mask == 2) {
+    if (i + off < j) return 0.0;
+    if (i + off == j) return 1.0;
+  }
+  return (double)p[(size_t)i + (size_t)j * ld];
+}
+
+// C = alpha * op(A) op(B) + beta * C, op(X) = X or X^T; batched over
+// blockIdx.z with element strides.  64 x 64 tile per 256-thread work-group.
+struct GemmArgs {
+  const void* A; int lda; long long sa; int ta; int ma; int oa;
+  const void* B; int ldb; long long sb; int tb; int mb; int ob;
+  void* C; int ldc; long long sc;
+  int m, n, k;
+  double alpha, beta;
+  int ksplit;            // > 1: partial products over k-chunks go to Cpart[z % ksplit] (m x n, ld m)
+  int kchunk;
+  void* Cpart;
+};
+
+template <typename SA, typename SB, typename TC>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  using Mt = MmaOf<TC>;
+  constexpr int BK = 32;
+  constexpr int LD = BK + Mt::PAD;
+  __shared__ TC As[64 * LD];
+  __shared__ TC Bs[64 * LD];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int ks = g.ksplit > 1 ? g.ksplit : 1;
+  const int bz = blockIdx.z / ks, kz = blockIdx.z % ks;
+  const SA* A = static_cast<const SA*>(g.A) + (long long)bz * g.sa;
+  const SB* B = static_cast<const SB*>(g.B) + (long long)bz * g.sb;
+  TC* C = static_cast<TC*>(g.C) + (long long)bz * g.sc;
+  const int kbeg = ks > 1 ? kz * g.kchunk : 0;
+  const int kend = ks > 1 ? min(g.k, kbeg + g.kchunk) : g.k;
+  typename Mt::V acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    // op(A)(row, kk): storage (row, kk) or (kk, row); fast index follows storage rows
+    for (int e = t; e < 64 * BK; e += 256) {
+      int row, kk;
+      if (!g.ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
+      const int gi = r0 + row, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < g.m && gk < kend) v = g.ta ? mload(A, g.lda, gk, gi, g.ma, g.oa) : mload(A, g.lda, gi, gk, g.ma, g.oa);
+      As[row * LD + kk] = (TC)v;
+    }
+    for (int e = t; e < 64 * BK; e += 256) {
+      int col, kk;
+      if (!g.tb) { kk = e % BK; col = e / BK; } else { col = e & 63; kk = e >> 6; }
+      const int gj = c0 + col, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < g.n && gk < kend) v = g.tb ? mload(B, g.ldb, gj, gk, g.mb, g.ob) : mload(B, g.ldb, gk, gj, g.mb, g.ob);
+      Bs[col * LD + kk] = (TC)v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      TC a[2], b[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        a[q] = As[(32 * wr + 16 * q + (l & 15)) * LD + kk + (l >> 4)];
+        b[q] = Bs[(32 * wc + 16 * q + (l & 15)) * LD + kk + (l >> 4)];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mt::mma(a[bi], b[bj], acc[bi][bj]);
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = r0 + 32 * wr + 16 * bi + Mt::row(l, r);
+        const int j = c0 + 32 * wc + 16 * bj + (l & 15);
+        if (i < g.m && j < g.n && ks > 1) {
+          static_cast<TC*>(g.Cpart)[(size_t)kz * g.m * g.n + i + (size_t)j * g.m] = acc[bi][bj][r];
+        } else if (i < g.m && j < g.n) {
+          TC* p = C + (size_t)i + (size_t)j * g.ldc;
+          const double old = g.beta != 0.0 ? (double)*p : 0.0;
+          *p = (TC)(g.alpha * (double)acc[bi][bj][r] + g.beta * old);
+        }
+      }
+}
+
+template <typename TC>
+__global__ void k_ksum(const TC* __restrict__ part, int ks, int m, int n, double alpha, double beta,
+                       TC* __restrict__ C, int ldc) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)m * n) return;
+  const int i = (int)(e % m), j = (int)(e / m);
+  double s = 0.0;
+  for (int q = 0; q < ks; ++q) s += (double)part[(size_t)q * m * n + e];
+  TC* p = C + (size_t)i + (size_t)j * ldc;
+  *p = (TC)(alpha * s + (beta != 0.0 ? beta * (double)*p : 0.0));
+}
+
+// Launch; with few output tiles and a long k, the product is split over k
+// (deterministic partials + one reduction kernel; batch must be 1 then).
+template <typename SA, typename SB, typename TC>
+static void gemm(Ctx& ctx, GemmArgs g, int batch) {
+  if (g.m <= 0 || g.n <= 0 || batch <= 0) return;
+  const int tiles = ceil_div(g.m, 64) * ceil_div(g.n, 64) * batch;
+  g.ksplit = 1;
+  if (batch == 1 && tiles < 256 && g.k >= 512) {
+    int ks = ceil_div(512, tiles);
+    const int kmax = g.k / 128;
+    if (ks > kmax) ks = kmax;
+    if (ks > 32) ks = 32;
+    if (ks > 1) {
+      g.kchunk = ceil_div(ceil_div(g.k, ks), 32) * 32;
+      ks = ceil_div(g.k, g.kchunk);
+      g.ksplit = ks;
+      g.Cpart = ctx.ws->alloc(sizeof(TC) * (size_t)ks * g.m * g.n);
+    }
+  }
+  dim3 grid(ceil_div(g.m, 64), ceil_div(g.n, 64), batch * g.ksplit);
+  hipLaunchKernelGGL((k_gemm<SA, SB, TC>), grid, dim3(256), 0, ctx.stream, g);
+  if (g.ksplit > 1) {
+    const long long tot = (long long)g.m * g.n;
+    hipLaunchKernelGGL((k_ksum<TC>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream,
+                       static_cast<const TC*>(g.Cpart), g.ksplit, g.m, g.n, g.alpha, g.beta,
+                       static_cast<TC*>(g.C), g.ldc);
+  }
+  LSQ_LAUNCH_CHECK();
+}
+
+// ----------------------------------------------------- triangular inverse --
+// Inverse of each 64 x 64 diagonal block; one work-group per block, FP64,
+// right-looking back substitution on U X = I with all columns in parallel.
+template <typename S, typename TC>
+__global__ __launch_bounds__(256) void k_diag_inv(const S* __restrict__ U, int ldu, int mask, int nn,
+                                                  TC* __restrict__ X, int ldx) {
+  __shared__ double R[64 * kLdt];
+  __shared__ double buf[192];
+  const int I = blockIdx.x, i0 = I * 64, ib = min(64, nn - i0);
+  const int t = threadIdx.x;
+  for (int e = t; e < 4096; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    double v = 0.0;
+    if (i < ib && j < ib && i <= j) v = mload(U, ldu, i0 + i, i0 + j, mask, 0);
+    if (i == j && i >= ib) v = 1.0;
+    R[i * kLdt + j] = v;
+  }
+  __syncthreads();
+  double x[16];
+  reg_upper_inverse(R, x, buf);
+  const Own o;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = o.r0 + q;
+    if (i < ib && o.c < ib) X[(size_t)(i0 + i) + (size_t)(i0 + o.c) * ldx] = (TC)x[q];
+  }
+}
+
+template <typename TC>
+__global__ void k_zero_lower(TC* X, int ldx, int nn) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nn * nn) return;
+  const int i = (int)(e % nn), j = (int)(e / nn);
+  if (i > j) X[(size_t)i + (size_t)j * ldx] = (TC)0;
+}
+
+// X (nn x nn, ld ldx, type TC) = U^{-1} for the upper triangle of U (type S,
+// masked upper).  Off-diagonal blocks by recursive doubling: for a diagonal
+// pair [A B; 0 C] of size 2b, X12 = -A^{-1} B C^{-1} (two batched GEMMs).
+template <typename S, typename TC>
+void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
+  if (nn <= 0) return;
+  const int nblk = ceil_div(nn, 64);
+  const long long tot = (long long)nn * nn;
+  hipLaunchKernelGGL((k_zero_lower<TC>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, X, ldx, nn);
+  hipLaunchKernelGGL((k_diag_inv<S, TC>), dim3(nblk), dim3(256), 0, ctx.stream, U, ldu, 1, nn, X, ldx);
+  LSQ_LAUNCH_CHECK();
+  TC* tmp = ctx.ws->get<TC>((size_t)nn * 64 + (size_t)nn * nn / 2 + 64);
+  for (int b = 64; b < nn; b *= 2) {
+    const int npairs = ceil_div(nn, 2 * b);
+    // full pairs share one batched launch; a ragged last pair is launched alone
+    const int full = nn / (2 * b);
+    for (int pass = 0; pass < 2; ++pass) {
+      const int cnt = pass == 0 ? full : npairs - full;
+      if (cnt <= 0) continue;
+      const int p0 = pass == 0 ? 0 : full;
+      const int a0 = p0 * 2 * b, c0 = a0 + b;
+      const int bw = min(b, nn - c0);          // width of the C block
+      if (bw <= 0) continue;
+      // tmp = B * C^{-1}   (b x bw);  B = U[a0:a0+b, c0:c0+bw],  C^{-1} = X[c0.., c0..]
+      GemmArgs g1{};
+      g1.A = U + (size_t)a0 + (size_t)c0 * ldu; g1.lda = ldu; g1.sa = (long long)2 * b * (ldu + 1); g1.ta = 0; g1.ma = 0; g1.oa = 0;
+      g1.B = X + (size_t)c0 + (size_t)c0 * ldx; g1.ldb = ldx; g1.sb = (long long)2 * b * (ldx + 1); g1.tb = 0; g1.mb = 0; g1.ob = 0;
+      g1.C = tmp; g1.ldc = b; g1.sc = (long long)b * b;
+      g1.m = b; g1.n = bw; g1.k = bw; g1.alpha = 1.0; g1.beta = 0.0;
+      gemm<S, TC, TC>(ctx, g1, cnt);
+      // X12 = -A^{-1} tmp   (b x bw)
+      GemmArgs g2{};
+      g2.A = X + (size_t)a0 + (size_t)a0 * ldx; g2.lda = ldx; g2.sa = (long long)2 * b * (ldx + 1); g2.ta = 0; g2.ma = 0; g2.oa = 0;
+      g2.B = tmp; g2.ldb = b; g2.sb = (long long)b * b; g2.tb = 0; g2.mb = 0; g2.ob = 0;
+      g2.C = X + (size_t)a0 + (size_t)c0 * ldx; g2.ldc = ldx; g2.sc = (long long)2 * b * (ldx + 1);
+      g2.m = b; g2.n = bw; g2.k = b; g2.alpha = -1.0; g2.beta = 0.0;
+      gemm<TC, TC, TC>(ctx, g2, cnt);
+    }
+  }
+}
+
+// ------------------------------------------------- inverse-based solves --
+// x <- op(X) x for a dense upper triangular X (nn x nn): y = X x or X^T x.
+// 64 rows x 256 columns per work-group; partial row sums added atomically
+// into y, which the caller zeroes.
+template <typename TC>
+__global__ __launch_bounds__(256) void k_trmv_n(const TC* __restrict__ X, int ldx, int nn,
+                                                const TC* __restrict__ x, TC* __restrict__ y) {
+  __shared__ TC part[4][64];
+  const int t = threadIdx.x, i = t & 63, q = t >> 6;
+  const int row = blockIdx.x * 64 + i;
+  const int j0 = blockIdx.y * 256;
+  TC s = 0;
+  if (row < nn) {
+    const int jb = max(j0, row), je = min(nn, j0 + 256);
+    for (int j = jb + q; j < je; j += 4) s += X[(size_t)row + (size_t)j * ldx] * x[j];
+  }
+  part[q][i] = s;
+  __syncthreads();
+  if (t < 64 && row < nn) {
+    const TC v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
+    if (v != (TC)0) atomicAdd(&y[row], v);
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void k_trmv_t(const TC* __restrict__ X, int ldx, int nn,
+                                                const TC* __restrict__ x, TC* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nn) return;
+  TC s = 0;
+  for (int i = lane; i <= j; i += 64) s += X[(size_t)i + (size_t)j * ldx] * x[i];
+  s = wave_sum(s);
+  if (lane == 0) y[j] = s;
+}
+
+template <typename TC>
+void trmv_dense(Ctx& ctx, const TC* X, int ldx, int nn, bool trans, const TC* x, TC* y) {
+  if (nn <= 0) return;
+  if (!trans) {
+    LSQ_HIP(hipMemsetAsync(y, 0, sizeof(TC) * nn, ctx.stream));
+    hipLaunchKernelGGL((k_trmv_n<TC>), dim3(ceil_div(nn, 64), ceil_div(nn, 256)), dim3(256), 0, ctx.stream, X, ldx, nn, x, y);
+  }
+  else
+    hipLaunchKernelGGL((k_trmv_t<TC>), dim3(ceil_div(nn, 4)), dim3(256), 0, ctx.stream, X, ldx, nn, x, y);
+  LSQ_LAUNCH_CHECK();
+}
+
+// ---------------------------------------- aggregated reflector application --
+// s = Y^T y over rows [0, rows) for the unit-lower (mask 2) Y with diagonal
+// offset 0; one wave per column of Y.
+template <typename S, typename TC>
+__global__ __launch_bounds__(256) void k_ymv_t(const S* __restrict__ Y, int ldy, int rows, int cols,
+                                               const TC* __restrict__ y, TC* __restrict__ s) {
+  const int lane = threadIdx.x & 63;
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (a >= cols) return;
+  TC acc = 0;
+  if (a < rows && lane == 0) acc = y[a];                 // unit diagonal
+  for (int i = a + 1 + lane; i < rows; i += 64) acc += (TC)Y[(size_t)i + (size_t)a * ldy] * y[i];
+  acc = wave_sum(acc);
+  if (lane == 0) s[a] = acc;
+}
+
+// y -= Y t for the unit-lower Y (rows x cols); 256 rows x 64 columns per
+// work-group, partial sums added atomically.
+template <typename S, typename TC>
+__global__ __launch_bounds__(256) void k_ymv_n(const S* __restrict__ Y, int ldy, int rows, int cols,
+                                               const TC* __restrict__ tv, TC* __restrict__ y) {
+  __shared__ TC ts[64];
+  const int t = threadIdx.x;
+  const int row = blockIdx.x * 256 + t;
+  const int c0 = blockIdx.y * 64;
+  if (t < 64) ts[t] = (c0 + t < cols) ? tv[c0 + t] : (TC)0;
+  __syncthreads();
+  if (row >= rows) return;
+  TC acc = 0;
+  const int cend = min(cols, c0 + 64);
+  for (int a = c0; a < cend; ++a) {
+    if (row > a) acc += (TC)Y[(size_t)row + (size_t)a * ldy] * ts[a - c0];
+    else if (row == a) acc += ts[a - c0];
+  }
+  if (acc != (TC)0) atomicAdd(&y[row], -acc);
+}
+
+// G = striu(Y^T Y) + diag(Y^T Y) / 2 for a unit-lower Y (rows x cols), dense output.
+template <typename TC>
+__global__ void k_ut_fix(TC* G, int ldg, int n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  TC* p = G + (size_t)i + (size_t)j * ldg;
+  if (i > j) *p = (TC)0;
+  else if (i == j) *p = (TC)((double)*p * 0.5);
+}
+
+// ------------------------------------------------------------- host side --
+template <typename TC>
+__global__ void k_cast(const double* __restrict__ s, TC* __restrict__ d, long long n) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) d[e] = (TC)s[e];
+}
+
+void agg_prepare(Ctx& ctx, QRFactor& f, int tc, int panels_per_block) {
+  f.agg.clear();
+  f.agg_tc = tc;
+  const int width = 64 * (panels_per_block > 0 ? panels_per_block : 1);
+  for (int J0 = 0; J0 < f.k; J0 += width) {
+    AggBlock b;
+    b.J0 = J0;
+    b.w = min(width, f.k - J0);
+    const int rows = f.r - J0;
+    const long long tot = (long long)b.w * b.w;
+    b.T = ctx.ws->alloc((size_t)tc * tot);
+    double* G = ctx.ws->get<double>(tot);
+    double* T64 = tc == 8 ? static_cast<double*>(b.T) : ctx.ws->get<double>(tot);
+    GemmArgs g{};
+    g.A = f.tw == 8 ? (const void*)(static_cast<const double*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld)
+                    : (const void*)(static_cast<const float*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld);
+    g.lda = f.ld; g.ta = 1; g.ma = 2; g.oa = 0;
+    g.B = g.A; g.ldb = f.ld; g.tb = 0; g.mb = 2; g.ob = 0;
+    g.C = G; g.ldc = b.w; g.m = b.w; g.n = b.w; g.k = rows; g.alpha = 1.0; g.beta = 0.0;
+    if (f.tw == 8) gemm<double, double, double>(ctx, g, 1); else gemm<float, float, double>(ctx, g, 1);
+    hipLaunchKernelGGL((k_ut_fix<double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, G, b.w, b.w);
+    tri_inverse<double, double>(ctx, G, b.w, b.w, T64, b.w);
+    if (tc != 8)
+      hipLaunchKernelGGL((k_cast<float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, T64, static_cast<float*>(b.T), tot);
+    LSQ_LAUNCH_CHECK();
+    f.agg.push_back(b);
+  }
+}
+
+template <typename S, typename TC>
+static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
+  const int nb = (int)f.agg.size();
+  int maxw = 0;
+  for (auto& b : f.agg) maxw = max(maxw, b.w);
+  TC* s = ctx.ws->get<TC>(maxw > 0 ? maxw : 1);
+  TC* tv = ctx.ws->get<TC>(maxw > 0 ? maxw : 1);
+  for (int q = 0; q < nb; ++q) {
+    const AggBlock& b = f.agg[trans ? q : nb - 1 - q];
+    const int rows = f.r - b.J0;
+    const S* Y = static_cast<const S*>(f.M) + (size_t)b.J0 + (size_t)b.J0 * f.ld;
+    TC* yy = y + b.J0;
+    hipLaunchKernelGGL((k_ymv_t<S, TC>), dim3(ceil_div(b.w, 4)), dim3(256), 0, ctx.stream, Y, f.ld, rows, b.w, yy, s);
+    // Q^T = I - Y T^T Y^T  -> t = T^T s ;  Q = I - Y T Y^T -> t = T s
+    trmv_dense<TC>(ctx, static_cast<const TC*>(b.T), b.w, b.w, trans, s, tv);
+    hipLaunchKernelGGL((k_ymv_n<S, TC>), dim3(ceil_div(rows, 256), ceil_div(b.w, 64)), dim3(256), 0, ctx.stream,
+                       Y, f.ld, rows, b.w, tv, yy);
+    LSQ_LAUNCH_CHECK();
+  }
+}
+
+void agg_apply(Ctx& ctx, const QRFactor& f, bool trans, void* y, int tc) {
+  if (f.k <= 0) return;
+  if (tc != f.agg_tc) throw HipError{hipErrorInvalidValue, "aggregated reflectors prepared for another precision"};
+  if (f.tw == 8) {
+    if (tc == 8) agg_apply_t<double, double>(ctx, f, trans, static_cast<double*>(y));
+    else agg_apply_t<double, float>(ctx, f, trans, static_cast<float*>(y));
+  } else {
+    if (tc == 8) agg_apply_t<float, double>(ctx, f, trans, static_cast<double*>(y));
+    else agg_apply_t<float, float>(ctx, f, trans, static_cast<float*>(y));
+  }
+}
+
+// Dense inverse of the upper triangular block U = f.M[o:o+nn, o:o+nn] in TC.
+void tri_inverse_factor(Ctx& ctx, const QRFactor& f, int o, int nn, void* X, int tc) {
+  if (nn <= 0) return;
+  if (f.tw == 8) {
+    const double* U = static_cast<const double*>(f.M) + (size_t)o + (size_t)o * f.ld;
+    if (tc == 8) tri_inverse<double, double>(ctx, U, f.ld, nn, static_cast<double*>(X), nn);
+    else tri_inverse<double, float>(ctx, U, f.ld, nn, static_cast<float*>(X), nn);
+  } else {
+    const float* U = static_cast<const float*>(f.M) + (size_t)o + (size_t)o * f.ld;
+    if (tc == 8) tri_inverse<float, double>(ctx, U, f.ld, nn, static_cast<double*>(X), nn);
+    else tri_inverse<float, float>(ctx, U, f.ld, nn, static_cast<float*>(X), nn);
+  }
+}
+
+void trmv(Ctx& ctx, const void* X, int nn, bool trans, const void* x, void* y, int tc) {
+  if (tc == 8) trmv_dense<double>(ctx, static_cast<const double*>(X), nn, nn, trans, static_cast<const double*>(x), static_cast<double*>(y));
+  else trmv_dense<float>(ctx, static_cast<const float*>(X), nn, nn, trans, static_cast<const float*>(x), static_cast<float*>(y));
+}
+
+}  // namespace lsq

@@ -66,37 +66,6 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return t;
 }
 
-// Bounded spin limit for inter-work-group waits.  A wait that exceeds it
-// records an error and gives up, so every wave always reaches its exit.
-constexpr unsigned kSpinLimit = 1u << 24;
-
-// Self-resetting grid barrier for cooperatively launched kernels.
-// bar[0] = arrival count (returns to 0 after every barrier), bar[1] = generation.
-__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nblocks, int* err) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
-      __hip_atomic_store(&bar[1], gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-      }
-    }
-    __threadfence();
-  }
-  __syncthreads();
-}
-
 template <typename T> struct Conv;
 template <> struct Conv<float> {
   __device__ static float from(double v) { return (float)v; }

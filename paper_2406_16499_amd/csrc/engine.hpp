@@ -26,16 +26,17 @@ class Arena {
 struct Ctx {
   hipStream_t stream = nullptr;
   Arena* ws = nullptr;
-  unsigned* sync = nullptr;     // grid-barrier words (device, zeroed at creation)
-  unsigned* flags = nullptr;    // trsv block flags (device, zeroed at creation)
-  int nflags = 0;
-  unsigned epoch = 0;           // last trsv epoch used
-  int* err = nullptr;           // device error word: 1 = spin limit exceeded
   int num_cu = 256;
-  int max_coop_blocks = 256;    // co-resident 256-thread blocks for cooperative kernels
 };
 
 // ---------------------------------------------- Householder QR engine ----
+// Aggregated compact-WY block over the panels starting at J0 (w columns):
+// H = I - Y T Y^T with T (w x w, upper) = (striu(Y^T Y) + diag(Y^T Y) / 2)^{-1}.
+struct AggBlock {
+  int J0 = 0, w = 0;
+  void* T = nullptr;            // w x w, column-major, compute precision
+};
+
 // Blocked Householder QR of an r x c column-major matrix stored in Tw
 // (float or double), k = min(r, c) reflectors in panels of nb columns.
 // After factorization: R on and above the diagonal of M, the unit lower
@@ -45,12 +46,15 @@ struct Ctx {
 struct QRFactor {
   int r = 0, c = 0, k = 0, ld = 0, nb = 64, np = 0;
   int tw = 4;                   // sizeof(Tw): 4 (float) or 8 (double)
+  int passes = 3;               // Cholesky QR passes per panel (3 for fp64, 2 otherwise)
   Mma mt = Mma::F32;
   void* M = nullptr;            // r x c, ld
   void* T = nullptr;            // np blocks of 64 x 64 (Tw), column-major ld 64
   void* Yhat = nullptr;         // per panel (r - j0) x 64 (Tw): Y_j T_j^T
   std::vector<size_t> yoff;     // element offset of panel j in Yhat
   int* status = nullptr;        // device: bit0 = a panel Cholesky broke down
+  std::vector<AggBlock> agg;    // aggregated blocks for vector application
+  int agg_tc = 0;
 };
 
 void qr_alloc(Ctx& ctx, QRFactor& f, int r, int c, int tw, Mma mt, int nb);
@@ -58,19 +62,25 @@ void qr_factor(Ctx& ctx, QRFactor& f);
 // C <- Q^T C for a column-major r x ncols matrix C (same Tw as the factor).
 void qr_apply_left_T(Ctx& ctx, const QRFactor& f, void* C, int ldc, int ncols);
 
-// Vector application of Q (trans = false) or Q^T (trans = true) to y (length
-// f.r) in compute precision Tc (float or double, tc = sizeof).  With rev_in /
-// rev_out the vector is read / written in reversed order.
-void qr_apply_vec(Ctx& ctx, const QRFactor& f, bool trans, void* y, int tc);
+// Aggregated application: prepare blocks of `panels_per_block` panels (the
+// Gram Y^T Y in FP64, T by triangular inversion) in compute precision tc, then
+// y <- Q^T y (trans) or Q y with three parallel kernels per block.
+void agg_prepare(Ctx& ctx, QRFactor& f, int tc, int panels_per_block);
+void agg_apply(Ctx& ctx, const QRFactor& f, bool trans, void* y, int tc);
+// Dense inverse X (nn x nn, ld nn, precision tc) of the upper triangular
+// block f.M[o:o+nn, o:o+nn]; y = X x or X^T x.
+void tri_inverse_factor(Ctx& ctx, const QRFactor& f, int o, int nn, void* X, int tc);
+void trmv(Ctx& ctx, const void* X, int nn, bool trans, const void* x, void* y, int tc);
 
 // ----------------------------------------------------- vector kernels ----
 // Triangular solve with the upper triangular block U = f.M[o:o+nn, o:o+nn]:
-// x <- U^{-1} x (trans = false) or U^{-T} x (trans = true), Tc precision.
-// The inverse diagonal blocks are cached in `dinv` (see trsv_prepare).
+// x <- U^{-1} x (trans = false) or U^{-T} x (trans = true), Tc precision,
+// as a product with the inverse computed once by trsv_prepare.
 struct TriBlock {
   const QRFactor* f = nullptr;
   int o = 0, nn = 0;
-  void* dinv = nullptr;         // nblk x 64 x 64 (Tc)
+  void* inv = nullptr;          // nn x nn dense inverse (Tc)
+  void* tmp = nullptr;          // nn (Tc)
   int tc = 4;
 };
 void trsv_prepare(Ctx& ctx, TriBlock& tb, const QRFactor& f, int o, int nn, int tc);

@@ -6,167 +6,17 @@
 namespace lsq {
 
 // ------------------------------------------------------------ triangular --
-// Inverse of each 64 x 64 diagonal block of U (upper, within the factor
-// storage at offset o).  One work-group per block; FP64 arithmetic.
-template <typename Tw, typename Tc>
-__global__ __launch_bounds__(256) void k_tri_inv(const Tw* __restrict__ M, int ld, int o, int nn,
-                                                 Tc* __restrict__ dinv) {
-  __shared__ double U[64 * 65];
-  __shared__ double X[64 * 65];
-  const int I = blockIdx.x, i0 = I * 64;
-  const int ib = min(64, nn - i0);
-  const int t = threadIdx.x;
-  for (int e = t; e < 4096; e += 256) {
-    const int i = e & 63, j = e >> 6;
-    double v = 0.0;
-    if (i < ib && j < ib && i <= j) v = (double)M[(size_t)(o + i0 + i) + (size_t)(o + i0 + j) * ld];
-    if (i == j && i >= ib) v = 1.0;
-    U[i * 65 + j] = v;
-    X[i * 65 + j] = 0.0;
-  }
-  __syncthreads();
-  if (t < 64) {   // column t of U^{-1} by back substitution
-    const int j = t;
-    X[j * 65 + j] = 1.0 / U[j * 65 + j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k) s += U[i * 65 + k] * X[k * 65 + j];
-      X[i * 65 + j] = -s / U[i * 65 + i];
-    }
-  }
-  __syncthreads();
-  Tc* out = dinv + (size_t)I * 4096;
-  for (int e = t; e < 4096; e += 256) out[e] = (Tc)X[(e & 63) * 65 + (e >> 6)];
-}
-
-// Block substitution with per-block completion flags (cooperative launch).
-// blockIdx b handles block row I = nblk-1-b (N) or b (T), so a work-group
-// only waits for blocks owned by work-groups with a smaller index.
-template <typename Tw, typename Tc>
-__global__ __launch_bounds__(256) void k_trsv(const Tw* __restrict__ M, int ld, int o, int nn,
-                                              const Tc* __restrict__ dinv, int trans,
-                                              Tc* __restrict__ x, unsigned* __restrict__ flags,
-                                              unsigned epoch, int* __restrict__ err) {
-  __shared__ Tc ts[64 * 65];
-  __shared__ Tc xs[64];
-  __shared__ Tc part[4][64];
-  __shared__ int abort_wait;
-  const int nblk = ceil_div(nn, 64);
-  const int b = blockIdx.x;
-  const int I = trans ? b : (nblk - 1 - b);
-  const int i0 = I * 64, ib = min(64, nn - i0);
-  const int t = threadIdx.x, i = t & 63, q = t >> 6;
-  if (t == 0) abort_wait = 0;
-  Tc acc = 0;
-  if (t < 64 && t < ib) acc = x[i0 + t];
-  for (int d = 0; d < b; ++d) {
-    const int J = trans ? d : (nblk - 1 - d);
-    const int j0 = J * 64, jbb = min(64, nn - j0);
-    __syncthreads();
-    // T block: N -> rows of I, cols of J ; T -> rows of J, cols of I   (stored ts[r][c])
-    for (int e = t; e < 4096; e += 256) {
-      const int rr = e & 63, cc = e >> 6;
-      Tc v = 0;
-      if (!trans) {
-        if (rr < ib && cc < jbb) v = (Tc)M[(size_t)(o + i0 + rr) + (size_t)(o + j0 + cc) * ld];
-      } else {
-        if (rr < jbb && cc < ib) v = (Tc)M[(size_t)(o + j0 + rr) + (size_t)(o + i0 + cc) * ld];
-      }
-      ts[rr * 65 + cc] = v;
-    }
-    if (t == 0) {
-      unsigned spins = 0;
-      while (__hip_atomic_load(&flags[J], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > kSpinLimit) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          abort_wait = 1;
-          break;
-        }
-      }
-      __threadfence();
-    }
-    __syncthreads();
-    if (t < 64) xs[t] = (t < jbb) ? __hip_atomic_load(&x[j0 + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : (Tc)0;
-    __syncthreads();
-    Tc s = 0;
-#pragma unroll
-    for (int jj = 0; jj < 16; ++jj) {
-      const int j = q * 16 + jj;
-      s += (trans ? ts[j * 65 + i] : ts[i * 65 + j]) * xs[j];
-    }
-    part[q][i] = s;
-    __syncthreads();
-    if (t < 64) acc -= part[0][t] + part[1][t] + part[2][t] + part[3][t];
-    if (abort_wait) break;
-  }
-  __syncthreads();
-  if (t < 64) xs[t] = acc;
-  __syncthreads();
-  const Tc* D = dinv + (size_t)I * 4096;     // D[r + c*64] = (U_II^{-1})[r][c]
-  Tc s = 0;
-#pragma unroll
-  for (int jj = 0; jj < 16; ++jj) {
-    const int j = q * 16 + jj;
-    s += (trans ? D[j + i * 64] : D[i + j * 64]) * xs[j];
-  }
-  part[q][i] = s;
-  __syncthreads();
-  if (t < 64 && t < ib) {
-    const Tc v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-    __hip_atomic_store(&x[i0 + t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __threadfence();
-  __syncthreads();
-  if (t == 0) __hip_atomic_store(&flags[I], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename Tw, typename Tc>
-static void trsv_prepare_t(Ctx& ctx, TriBlock& tb) {
-  const int nblk = ceil_div(tb.nn, 64);
-  tb.dinv = ctx.ws->alloc(sizeof(Tc) * 4096 * (size_t)(nblk > 0 ? nblk : 1));
-  if (nblk == 0) return;
-  hipLaunchKernelGGL((k_tri_inv<Tw, Tc>), dim3(nblk), dim3(256), 0, ctx.stream,
-                     static_cast<const Tw*>(tb.f->M), tb.f->ld, tb.o, tb.nn, static_cast<Tc*>(tb.dinv));
-  LSQ_LAUNCH_CHECK();
-}
-
 void trsv_prepare(Ctx& ctx, TriBlock& tb, const QRFactor& f, int o, int nn, int tc) {
   tb.f = &f; tb.o = o; tb.nn = nn; tb.tc = tc;
-  if (f.tw == 8) {
-    if (tc == 8) trsv_prepare_t<double, double>(ctx, tb); else trsv_prepare_t<double, float>(ctx, tb);
-  } else {
-    if (tc == 8) trsv_prepare_t<float, double>(ctx, tb); else trsv_prepare_t<float, float>(ctx, tb);
-  }
-}
-
-template <typename Tw, typename Tc>
-static void trsv_t(Ctx& ctx, const TriBlock& tb, bool trans, Tc* x) {
-  const int nblk = ceil_div(tb.nn, 64);
-  if (nblk == 0) return;
-  if (nblk > ctx.nflags || nblk > ctx.max_coop_blocks) throw HipError{hipErrorInvalidValue, "trsv too large"};
-  const Tw* M = static_cast<const Tw*>(tb.f->M);
-  int ld = tb.f->ld, o = tb.o, nn = tb.nn, tr = trans ? 1 : 0;
-  const Tc* dinv = static_cast<const Tc*>(tb.dinv);
-  unsigned* flags = ctx.flags;
-  unsigned epoch = ++ctx.epoch;
-  if (epoch == 0) epoch = ++ctx.epoch;
-  int* err = ctx.err;
-  void* args[] = {(void*)&M, (void*)&ld, (void*)&o, (void*)&nn, (void*)&dinv, (void*)&tr,
-                  (void*)&x, (void*)&flags, (void*)&epoch, (void*)&err};
-  LSQ_HIP(hipLaunchCooperativeKernel((const void*)k_trsv<Tw, Tc>, dim3(nblk), dim3(256), args, 0,
-                                     ctx.stream));
+  tb.inv = ctx.ws->alloc((size_t)tc * (nn > 0 ? (size_t)nn * nn : 1));
+  tb.tmp = ctx.ws->alloc((size_t)tc * (nn > 0 ? nn : 1));
+  tri_inverse_factor(ctx, f, o, nn, tb.inv, tc);
 }
 
 void trsv(Ctx& ctx, const TriBlock& tb, bool trans, void* x) {
   if (tb.nn <= 0) return;
-  if (tb.f->tw == 8) {
-    if (tb.tc == 8) trsv_t<double, double>(ctx, tb, trans, static_cast<double*>(x));
-    else trsv_t<double, float>(ctx, tb, trans, static_cast<float*>(x));
-  } else {
-    if (tb.tc == 8) trsv_t<float, double>(ctx, tb, trans, static_cast<double*>(x));
-    else trsv_t<float, float>(ctx, tb, trans, static_cast<float*>(x));
-  }
+  trmv(ctx, tb.inv, tb.nn, trans, x, tb.tmp, tb.tc);
+  vec_convert(ctx, x, tb.tc, tb.tmp, tb.tc, tb.nn, false);
 }
 
 // ------------------------------------------------------------ masked GEMV --

@@ -31,6 +31,19 @@ METRIC = "LSE/GLS solves/s at FP64 backward error <=1e-14: mixed-IR vs plain FP6
 WORKLOAD = "single LSE, A 4096x2048 kappa(A)=1e4 (U diag(s) V^T), B 256x2048 N(0,1), b,d N(0,1), seed 2"
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0}   # dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                                                     # GB/s
+COPY_BYTES = 256 << 20            # calibration copy for the hardware byte counters
+# Kernel whose roofline is reported, with its bound: the Householder panel
+# reconstruction dominates the mixed-precision solve (FP64 arithmetic).
+KERNELS = {
+    "panel_final_y": ("k_panel_final_y", "mfma", 78.6, "TFLOP/s"),
+    "panel_cholpass": ("k_panel_cholpass", "mfma", 78.6, "TFLOP/s"),
+    "wy_u": ("k_wy_u", "mfma", None, "TFLOP/s"),
+    "wy_t": ("k_wy_t", "mfma", None, "TFLOP/s"),
+    "dual_gemv": ("k_dual_gemv", "hbm", HBM_PEAK, "GB/s"),
+}
+KERNEL_SOURCES = ["paper_2406_16499_amd/csrc/qr.hip", "paper_2406_16499_amd/csrc/wg64.hpp",
+                  "paper_2406_16499_amd/csrc/vec.hip", "paper_2406_16499_amd/csrc/common.hpp",
+                  "paper_2406_16499_amd/csrc/engine.hpp"]
 
 
 def parse():
@@ -44,10 +57,39 @@ def parse():
     ap.add_argument("--p", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--kernel", default="panel_final_y", choices=sorted(KERNELS))
     return ap.parse_args()
 
 
-def time_solves(h, lsq, torch, tensors, opts, steps, warmup):
+def source_hash():
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def traffic_per_launch(kernel):
+    """HBM bytes per launch from the committed hardware-counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_solves(h, lsq, torch, tensors, opts, steps, warmup, kernel=None):
     A, B, b, d = tensors
     m, n = A.shape
     p = B.shape[0]
@@ -57,6 +99,8 @@ def time_solves(h, lsq, torch, tensors, opts, steps, warmup):
         rc, res = h.lse_solve(A, B, b, d, x, r, v, opts)
         last = res
     torch.cuda.synchronize()
+    if kernel:
+        h.timer_enable(kernel)
     t0 = time.perf_counter()
     ok = 0
     results = []
@@ -67,7 +111,11 @@ def time_solves(h, lsq, torch, tensors, opts, steps, warmup):
             ok += 1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return dt, ok, results, (x, r, v)
+    timing = None
+    if kernel:
+        timing = h.timer_read()
+        h.timer_enable(None)
+    return dt, ok, results, timing
 
 
 def cpu_baseline(prob, seconds):
@@ -109,8 +157,15 @@ def main():
 
     mixed_opts = lsq.default_opts(prec=args.prec, solver="ir", escalate=1)
     fp64_opts = lsq.default_opts(prec="fp64", solver="direct")
-    dt_mix, ok_mix, res_mix, _ = time_solves(h, lsq, torch, tensors, mixed_opts, args.steps, args.warmup)
+    dt_mix, ok_mix, res_mix, timing = time_solves(h, lsq, torch, tensors, mixed_opts, args.steps,
+                                                  args.warmup, kernel=args.kernel)
     dt_64, ok_64, res_64, _ = time_solves(h, lsq, torch, tensors, fp64_opts, args.steps, args.warmup)
+    # calibration copy of known size, outside the timed regions (scales the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run)
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    h.dbg_copy(dst, src, COPY_BYTES)
+    del src, dst
 
     value = ok_mix / dt_mix
     value64 = ok_64 / dt_64
@@ -120,10 +175,23 @@ def main():
     tf = (2 * n * p * p - 2 * p ** 3 / 3) + (4 * m * n * p - 2 * m * p * p) + (2 * m * n * n - 2 * n ** 3 / 3)
 
     roof = None
-    try:
-        roof = h.kernel_roofline(args.prec, m, n, p)
-    except AttributeError:
-        roof = None
+    if timing is not None and timing[1] > 0:
+        total_ms, launches, flops, nbytes = timing
+        name, bound, peak, unit = KERNELS[args.kernel]
+        if peak is None:
+            peak = PEAK.get(args.prec, PEAK["fp32"])
+        avg_s = total_ms * 1e-3 / launches
+        if bound == "hbm":
+            achieved = nbytes / launches / avg_s / 1e9
+        else:
+            achieved = flops / launches / avg_s / 1e12
+        traffic = traffic_per_launch(args.kernel)
+        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": traffic,
+                "kernel": name, "launches_per_step": launches / args.steps,
+                "avg_launch_us": avg_s * 1e6,
+                "alg_flops_per_launch": flops / launches, "alg_bytes_per_launch": nbytes / launches,
+                "source_hash": source_hash()}
 
     line = {
         "metric": METRIC,

@@ -60,6 +60,25 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
                            const double* B, int ldb, const double* f1, const double* f2,
                            const double* f3, double* dy, double* dz, double* dx);
 
+/* Kernel timing.  While enabled, HIP events are recorded on the handle's
+ * stream around every launch of the named kernel kind ("panel_final_y",
+ * "panel_cholpass", "wy_t", "wy_u", "dual_gemv"), and the launch's algorithmic
+ * flops and bytes are added up (the step each kernel carries out is the one
+ * cited at its launch site: Householder QR panels and updates of Section 4.1,
+ * the residual of eq. aug-LSE / eq. aug-GLS).  NULL or "" disables; an unknown
+ * name returns -2.  lsq_dbg_timer_read synchronizes the stream, returns the
+ * summed event durations (ms), the launch count and the summed flops and
+ * bytes since the last enable or read, and resets those counters.  Any output
+ * pointer may be NULL. */
+int lsq_dbg_timer_enable(lsq_handle h, const char* kernel);
+int lsq_dbg_timer_read(lsq_handle h, double* total_ms, int* launches, double* flops, double* bytes);
+
+/* Device-to-device copy of `bytes` bytes by a plain streaming kernel (16-byte
+ * loads and stores), synchronized.  A calibration kernel of known traffic
+ * for hardware byte counters; returns -4 for bytes < 0, -2 for a NULL
+ * pointer with bytes > 0. */
+int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes);
+
 /* Text of the last error recorded on the handle ("" if none). */
 const char* lsq_last_error(lsq_handle h);
 

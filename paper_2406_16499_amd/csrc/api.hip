@@ -61,6 +61,27 @@ void Arena::release() {
   chunks_.clear();
   cur_ = 0;
 }
+
+void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes) {
+  KernelTimer* t = ctx.timer;
+  if (!t || t->target != kind) return;
+  if ((size_t)(2 * t->used + 2) > t->ev.size()) {
+    for (int q = 0; q < 2; ++q) {
+      hipEvent_t e = nullptr;
+      LSQ_HIP(hipEventCreate(&e));
+      t->ev.push_back(e);
+    }
+  }
+  LSQ_HIP(hipEventRecord(t->ev[2 * t->used], ctx.stream));
+  t->flops += flops;
+  t->bytes += bytes;
+}
+void ktimer_end(Ctx& ctx, int kind) {
+  KernelTimer* t = ctx.timer;
+  if (!t || t->target != kind) return;
+  LSQ_HIP(hipEventRecord(t->ev[2 * t->used + 1], ctx.stream));
+  ++t->used;
+}
 }  // namespace lsq
 
 struct lsq_handle_st {
@@ -72,6 +93,7 @@ struct lsq_handle_st {
   StopStatus* st_host = nullptr;   // pinned
   double* matnorms = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  KernelTimer timer;
   std::string last_error;
 };
 
@@ -499,6 +521,8 @@ int lsq_destroy(lsq_handle h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   h->arena.release();
+  for (auto& e : h->timer.ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->st_dev) (void)hipFree(h->st_dev);
   if (h->st_host) (void)hipHostFree(h->st_host);
   if (h->matnorms) (void)hipFree(h->matnorms);
@@ -828,6 +852,58 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
     vec_zero(ctx, dz, 8, n);
     vec_zero(ctx, dx, 8, m);
     sv.correct(ctx, f1, f2, f3, dx, dy, dz);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+  });
+}
+
+// ------------------------------------------------------------- timing --
+static const char* const kKernelNames[kKCount] = {"panel_final_y", "panel_cholpass", "wy_t", "wy_u",
+                                                  "dual_gemv"};
+
+int lsq_dbg_timer_enable(lsq_handle h, const char* kernel) {
+  if (!h) return -1;
+  return guard(h, "lsq_dbg_timer_enable", [&]() -> int {
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    h->timer.used = 0;
+    h->timer.flops = h->timer.bytes = 0.0;
+    h->timer.target = -1;
+    h->ctx.timer = nullptr;
+    if (!kernel || !kernel[0]) return 0;
+    for (int k = 0; k < kKCount; ++k)
+      if (std::strcmp(kernel, kKernelNames[k]) == 0) h->timer.target = k;
+    if (h->timer.target < 0) return fail(h, -2, std::string("unknown kernel name ") + kernel);
+    h->ctx.timer = &h->timer;
+    return 0;
+  });
+}
+
+int lsq_dbg_timer_read(lsq_handle h, double* total_ms, int* launches, double* flops, double* bytes) {
+  if (!h) return -1;
+  return guard(h, "lsq_dbg_timer_read", [&]() -> int {
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    double tot = 0.0;
+    for (int q = 0; q < h->timer.used; ++q) {
+      float ms = 0.0f;
+      LSQ_HIP(hipEventElapsedTime(&ms, h->timer.ev[2 * q], h->timer.ev[2 * q + 1]));
+      tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = h->timer.used;
+    if (flops) *flops = h->timer.flops;
+    if (bytes) *bytes = h->timer.bytes;
+    h->timer.used = 0;
+    h->timer.flops = h->timer.bytes = 0.0;
+    return 0;
+  });
+}
+
+int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes) {
+  if (!h) return -1;
+  if (bytes < 0) return -4;
+  if (bytes > 0 && (!dst || !src)) return -2;
+  return guard(h, "lsq_dbg_copy", [&]() -> int {
+    dev_copy(h->ctx, dst, src, (size_t)bytes);
     LSQ_HIP(hipStreamSynchronize(h->stream));
     return 0;
   });

@@ -23,11 +23,28 @@ class Arena {
   size_t cur_ = 0;
 };
 
+// Optional timing of one kernel kind: HIP events on the context stream around
+// each launch of that kind, with the launch's algorithmic flops and bytes.
+enum KernelKind : int {
+  kKPanelFinal = 0, kKPanelCholPass = 1, kKWyT = 2, kKWyU = 3, kKDualGemv = 4, kKCount = 5
+};
+struct KernelTimer {
+  int target = -1;
+  std::vector<hipEvent_t> ev;   // 2 per launch
+  int used = 0;                 // launches recorded
+  double flops = 0.0, bytes = 0.0;
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   Arena* ws = nullptr;
   int num_cu = 256;
+  KernelTimer* timer = nullptr;
 };
+
+// Brackets one launch of kind `kind`; does nothing unless the timer targets it.
+void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes);
+void ktimer_end(Ctx& ctx, int kind);
 
 // ---------------------------------------------- Householder QR engine ----
 // Aggregated compact-WY block over the panels starting at J0 (w columns):
@@ -135,6 +152,9 @@ void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
                   StopStatus* st);
 // matnorms[0..1] = ||A||_F, ||B||_F; matnorms[2..3] = ||b||, ||d|| (LSE) or ||d||, 0 (GLS).
+// Plain copy of `bytes` bytes (16-byte vector loads/stores; calibration kernel).
+void dev_copy(Ctx& ctx, void* dst, const void* src, size_t bytes);
+
 void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double* B, int ldb,
                 int br, int bc, const double* v1, int n1, const double* v2, int n2,
                 double* matnorms);

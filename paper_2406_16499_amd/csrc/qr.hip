@@ -530,14 +530,18 @@ static void wy_apply(Ctx& ctx, const Tw* Y, int ldy, int mr, int jb, const Tw* Y
   nsplit = ceil_div(mr, kch);
   Acc* Wpart = ctx.ws->get<Acc>((size_t)nsplit * 64 * nc);
   Acc* W = ctx.ws->get<Acc>((size_t)64 * nc);
+  ktimer_begin(ctx, kKWyT, 2.0 * mr * jb * nc, (double)mr * (jb + nc) * sizeof(Tw));
   hipLaunchKernelGGL((k_wy_t<Tw, MT>), dim3(nct, nsplit), dim3(256), 0, ctx.stream,
                      Y, ldy, mr, jb, C, ldc, nc, kch, Wpart);
+  ktimer_end(ctx, kKWyT);
   const int total = 64 * nc;
   hipLaunchKernelGGL((k_wy_reduce<Acc>), dim3(ceil_div(total, 256)), dim3(256), 0, ctx.stream,
                      Wpart, nsplit, total, W);
   LSQ_LAUNCH_CHECK();
+  ktimer_begin(ctx, kKWyU, 2.0 * mr * jb * nc, (double)mr * (jb + 2.0 * nc) * sizeof(Tw));
   hipLaunchKernelGGL((k_wy_u<Tw, MT>), dim3(ceil_div(mr, 64), nct), dim3(256), 0, ctx.stream,
                      Yhat, ldyh, mr, jb, W, C, ldc, nc, Gnext, jbn);
+  ktimer_end(ctx, kKWyU);
   LSQ_LAUNCH_CHECK();
 }
 
@@ -568,19 +572,32 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
     double* G2 = G1 + 4096;
     Tw* P = M + (size_t)j0 + (size_t)j0 * ld;
     // shifted pass: Q0 = P R0^{-1}, R0 = chol(P^T P + sigma I)
+    // algorithmic work of a pass: X R^{-1} and the Gram (2 mr jb^2 each), the
+    // Cholesky with its inverse (2 jb^3 / 3); bytes: X in, Xout out
+    const double pass_flops = 4.0 * mr * jb * jb + 2.0 * jb * jb * jb / 3.0;
+    ktimer_begin(ctx, kKPanelCholPass, pass_flops, (double)mr * jb * (sizeof(Tw) + 8));
     hipLaunchKernelGGL((k_panel_cholpass<Tw>), dim3(tiles), dim3(256), 0, ctx.stream,
                        G0, 1, 1, Racc, f.status, P, ld, mr, jb, Q0, mr, G1);
+    ktimer_end(ctx, kKPanelCholPass);
     const double* Qlast = Q0;
     const double* Glast = G1;
     if (f.passes >= 3) {
+      ktimer_begin(ctx, kKPanelCholPass, pass_flops, (double)mr * jb * 16);
       hipLaunchKernelGGL((k_panel_cholpass<double>), dim3(tiles), dim3(256), 0, ctx.stream,
                          G1, 0, 0, Racc, f.status, Q0, mr, mr, jb, Q1, mr, G2);
+      ktimer_end(ctx, kKPanelCholPass);
       Qlast = Q1;
       Glast = G2;
     }
+    // algorithmic work of the reconstruction: Cholesky, LU and the four
+    // triangular inverses / products of the 64 x 64 part (11 jb^3 / 3), Y = Q1 Mmat
+    // and Yhat = Y T^T (2 mr jb^2 each); bytes: Q1 in, Y and Yhat out
+    ktimer_begin(ctx, kKPanelFinal, 4.0 * mr * jb * jb + 11.0 * jb * jb * jb / 3.0,
+                 (double)mr * jb * (8 + 2 * sizeof(Tw)));
     hipLaunchKernelGGL((k_panel_final_y<Tw>), dim3(tiles), dim3(256), 0, ctx.stream,
                        Glast, jb, mr, Qlast, mr, Racc, M, ld, j0, Tb + (size_t)j * 4096,
                        Yh + f.yoff[j], mr, f.status);
+    ktimer_end(ctx, kKPanelFinal);
     LSQ_LAUNCH_CHECK();
     // trailing update of columns j0 + jb .. c-1, producing the next panel's Gram
     const int nc = f.c - j0 - jb;

@@ -244,8 +244,11 @@ void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const doub
     out.nrb = out.ncb = 0;
     return;
   }
+  // 4 flops per matrix element (two products), one FP64 read of the matrix
+  ktimer_begin(ctx, kKDualGemv, 4.0 * rows * cols, 8.0 * rows * cols);
   hipLaunchKernelGGL(k_dual_gemv, dim3(out.nrb, out.ncb), dim3(256), 0, ctx.stream, M, ld, rows,
                      cols, u, w, out.rowp, out.colp);
+  ktimer_end(ctx, kKDualGemv);
   LSQ_LAUNCH_CHECK();
 }
 
@@ -463,6 +466,35 @@ void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double
                        part + (size_t)k * per);
   }
   hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, ctx.stream, part, per, matnorms);
+  LSQ_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ copy --
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+__global__ void k_copy1(const unsigned char* __restrict__ src, unsigned char* __restrict__ dst,
+                        size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+void dev_copy(Ctx& ctx, void* dst, const void* src, size_t bytes) {
+  const size_t n16 = bytes / 16;
+  if (n16 > 0) {
+    size_t g = (n16 + 255) / 256;
+    const size_t cap = (size_t)ctx.num_cu * 16;
+    if (g > cap) g = cap;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)g), dim3(256), 0, ctx.stream,
+                       static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  }
+  const size_t tail = bytes - n16 * 16;
+  if (tail > 0)
+    hipLaunchKernelGGL(k_copy1, dim3(1), dim3(64), 0, ctx.stream,
+                       static_cast<const unsigned char*>(src) + n16 * 16,
+                       static_cast<unsigned char*>(dst) + n16 * 16, tail);
   LSQ_LAUNCH_CHECK();
 }
 

@@ -82,6 +82,10 @@ _SIGS = {
                                        _P, _P, _P, _P, _P]),
     "lsq_dbg_gls_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
                                        _P, _P, _P, _P, _P]),
+    "lsq_dbg_timer_enable": (c_int, [_P, ctypes.c_char_p]),
+    "lsq_dbg_timer_read": (c_int, [_P, ctypes.POINTER(c_double), ctypes.POINTER(c_int),
+                                   ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
+    "lsq_dbg_copy": (c_int, [_P, _P, _P, ctypes.c_longlong]),
     "lsq_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -233,6 +237,26 @@ class Handle:
         return rc, list(res)
 
     # ---------------------------------------------------------- debug --
+    def timer_enable(self, kernel: Optional[str]):
+        """Time every launch of one kernel kind with HIP events (None disables)."""
+        rc = self.lib.lsq_dbg_timer_enable(self.h, (kernel or "").encode())
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_timer_enable({kernel!r}) = {rc}: {self.last_error()}")
+
+    def timer_read(self):
+        """(total_ms, launches, flops, bytes) since the last enable / read."""
+        ms, n, fl, by = c_double(), c_int(), c_double(), c_double()
+        rc = self.lib.lsq_dbg_timer_read(self.h, ctypes.byref(ms), ctypes.byref(n),
+                                         ctypes.byref(fl), ctypes.byref(by))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_timer_read = {rc}: {self.last_error()}")
+        return ms.value, n.value, fl.value, by.value
+
+    def dbg_copy(self, dst, src, nbytes: int):
+        rc = self.lib.lsq_dbg_copy(self.h, _ptr(dst), _ptr(src), int(nbytes))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_copy = {rc}: {self.last_error()}")
+
     def dbg_qr(self, prec, M, X=None, want=("R", "Y1", "Y2", "Y3")):
         torch = _torch()
         r, c = M.shape

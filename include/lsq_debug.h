@@ -60,6 +60,18 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
                            const double* B, int ldb, const double* f1, const double* f2,
                            const double* f3, double* dy, double* dz, double* dx);
 
+/* The block-diagonal split-preconditioned operator of GMRES-IR applied to one
+ * vector: y = M_l F~ M_r u (FP64 arithmetic) with the factors computed at
+ * precision prec.  LSE (type LSQ_LSE, A m x n, B p x n, needs m >= n):
+ * eq. lse-bdpre-mlarge, u and y of length m + p + n ordered [r-block;
+ * v-block; x-block].  GLS (type LSQ_GLS, A = W n x m, B = V n x p, needs
+ * n <= p): eq. gls-bdpre-plarge, length p + n + m ordered [y; z; x].  alpha,
+ * beta > 0 are the scalings of the augmented system (Section 5.1).  Returns
+ * -4 when the shape condition fails. */
+int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, const double* A, int lda,
+                     const double* B, int ldb, double alpha, double beta, const double* u,
+                     double* y);
+
 /* Kernel timing.  While enabled, HIP events are recorded on the handle's
  * stream around every launch of the named kernel kind ("panel_final_y",
  * "panel_cholpass", "wy_t", "wy_u", "dual_gemv"), and the launch's algorithmic

@@ -94,6 +94,7 @@ struct lsq_handle_st {
   double* matnorms = nullptr;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   KernelTimer timer;
+  double* pin = nullptr;           // pinned host scratch (kPinDoubles)
   std::string last_error;
 };
 
@@ -122,6 +123,17 @@ int default_nb(const lsq_opts& o) { return (o.nb > 0 && o.nb <= kMaxNb) ? o.nb :
 
 void* off(void* p, size_t bytes) { return static_cast<char*>(p) + bytes; }
 const void* off(const void* p, size_t bytes) { return static_cast<const char*>(p) + bytes; }
+
+struct LseArgs {
+  int m, n, p;
+  const double *A, *B, *b, *d;
+  int lda, ldb;
+};
+struct GlsArgs {
+  int n, m, p;
+  const double *W, *V, *d;
+  int ldw, ldv;
+};
 
 // ----------------------------------------------------------------- LSE ----
 struct LseSolver {
@@ -198,6 +210,62 @@ struct LseSolver {
     agg_apply(ctx, fb, false, Yt, tc);
     vec_axpy(ctx, x, 8, 1.0, Yt, tc, n, true);
   }
+
+  // ---- GMRES-IR: block-diagonal split preconditioner for m >= n (Section
+  // 5.2, eq. lse-bdpre-mlarge), FP64 arithmetic on the stored factors.  With
+  // u = [a; b; c] (lengths m, p, n), S = T1(n-p:n, n-p:n) and sa = sqrt(alpha):
+  //   M_l u = [a / sa; S R^{-1} b / (sa beta); sa T1^{-T} Q c]
+  //   M_r u = [a / sa; R^{-T} S^T b / (sa beta); sa Q^T T1^{-1} c]
+  //   F u   = [alpha a + A c; beta B c; A^T a + beta B^T b].
+  TriBlock tT1;
+  double alpha = 1.0, beta = 1.0, sa = 1.0;
+  double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *t1 = nullptr, *t2 = nullptr;
+  DualParts dpa, dpb;
+
+  void prepare_gmres(Ctx& ctx) {
+    prepare(ctx, 8);
+    trsv_prepare(ctx, tT1, fa, 0, n, 8);
+    const int L = std::max(std::max(m, n), 1), N = std::max(m + p + n, 1);
+    g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
+    t1 = ctx.ws->get<double>(N); t2 = ctx.ws->get<double>(N);
+    dual_parts_alloc(ctx, m, n, dpa);
+    dual_parts_alloc(ctx, p, n, dpb);
+  }
+  // x (p) <- R^{-1} x or R^{-T} x, with R = J Rt^T J
+  void r_solve(Ctx& ctx, double* xv, bool trans) {
+    vec_convert(ctx, g3, 8, xv, 8, p, true);
+    trsv(ctx, tR, !trans, g3);
+    vec_convert(ctx, xv, 8, g3, 8, p, true);
+  }
+  // x (n) <- Q x or Q^T x, with Q = J Qt^T J
+  void q_apply(Ctx& ctx, double* xv, bool trans) {
+    vec_convert(ctx, g3, 8, xv, 8, n, true);
+    agg_apply(ctx, fb, !trans, g3, 8);
+    vec_convert(ctx, xv, 8, g3, 8, n, true);
+  }
+  void m_right(Ctx& ctx, const double* u, double* out) {
+    vec_convert(ctx, out, 8, u, 8, m, false, 1.0 / sa);
+    vec_zero(ctx, g1, 8, p);
+    gemv_upper(ctx, fa, k, k, p, p, true, 1.0, u + m, g1, 8);
+    r_solve(ctx, g1, true);
+    vec_convert(ctx, out + m, 8, g1, 8, p, false, 1.0 / (sa * beta));
+    vec_convert(ctx, g2, 8, u + m + p, 8, n, false);
+    trsv(ctx, tT1, false, g2);
+    q_apply(ctx, g2, true);
+    vec_convert(ctx, out + m + p, 8, g2, 8, n, false, sa);
+  }
+  void m_left(Ctx& ctx, const double* u, double* out) {
+    vec_convert(ctx, out, 8, u, 8, m, false, 1.0 / sa);
+    vec_convert(ctx, g1, 8, u + m, 8, p, false);
+    r_solve(ctx, g1, false);
+    vec_zero(ctx, out + m, 8, p);
+    gemv_upper(ctx, fa, k, k, p, p, false, 1.0 / (sa * beta), g1, out + m, 8);
+    vec_convert(ctx, g2, 8, u + m + p, 8, n, false);
+    q_apply(ctx, g2, false);
+    trsv(ctx, tT1, true, g2);
+    vec_convert(ctx, out + m + p, 8, g2, 8, n, false, sa);
+  }
+  void f_apply(Ctx& ctx, const LseArgs& a, const double* u, double* out);
 };
 
 // ----------------------------------------------------------------- GLS ----
@@ -276,7 +344,81 @@ struct GlsSolver {
     agg_apply(ctx, fv, false, G, tc);
     vec_axpy(ctx, y, 8, 1.0, G, tc, p, true);
   }
+
+  // ---- GMRES-IR: block-diagonal split preconditioner for n <= p (Section
+  // 5.3, eq. gls-bdpre-plarge), FP64 arithmetic on the stored factors.  With
+  // u = [a; b; c] (lengths p, n, m), T = [0, T2], S = T2(0:m, 0:m), sa = sqrt(alpha):
+  //   M_l u = [a / sa; sa T2^{-1} Q^T b; S^T R^{-T} c / (sa beta)]
+  //   M_r u = [a / sa; sa Q T2^{-T} b; R^{-1} S c / (sa beta)]
+  //   F u   = [alpha a + V^T b; V a + beta W c; beta W^T b].
+  // T2 = J Rv^T J for the n x n triangle Rv of the QR of Vt, and S = J A22^T J.
+  TriBlock tRv;
+  double alpha = 1.0, beta = 1.0, sa = 1.0;
+  double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *g4 = nullptr, *t1 = nullptr, *t2 = nullptr;
+  DualParts dpv, dpw;
+
+  void prepare_gmres(Ctx& ctx) {
+    prepare(ctx, 8);
+    trsv_prepare(ctx, tRv, fv, 0, n, 8);
+    const int L = std::max(std::max(n, p), 1), N = std::max(p + n + m, 1);
+    g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
+    g4 = ctx.ws->get<double>(L);
+    t1 = ctx.ws->get<double>(N); t2 = ctx.ws->get<double>(N);
+    dual_parts_alloc(ctx, n, p, dpv);
+    dual_parts_alloc(ctx, n, m, dpw);
+  }
+  // x (n) <- T2^{-1} x or T2^{-T} x
+  void t2_solve(Ctx& ctx, double* xv, bool trans) {
+    vec_convert(ctx, g3, 8, xv, 8, n, true);
+    trsv(ctx, tRv, !trans, g3);
+    vec_convert(ctx, xv, 8, g3, 8, n, true);
+  }
+  // out (m) = S x or S^T x
+  void s_apply(Ctx& ctx, const double* xv, double* out, bool trans) {
+    vec_convert(ctx, g3, 8, xv, 8, m, true);
+    vec_zero(ctx, g4, 8, m);
+    gemv_upper(ctx, fv, k, k, m, m, !trans, 1.0, g3, g4, 8);
+    vec_convert(ctx, out, 8, g4, 8, m, true);
+  }
+  void m_right(Ctx& ctx, const double* u, double* out) {
+    vec_convert(ctx, out, 8, u, 8, p, false, 1.0 / sa);
+    vec_convert(ctx, g1, 8, u + p, 8, n, false);
+    t2_solve(ctx, g1, true);
+    agg_apply(ctx, fw, false, g1, 8);
+    vec_convert(ctx, out + p, 8, g1, 8, n, false, sa);
+    s_apply(ctx, u + p + n, g2, false);
+    trsv(ctx, tR, false, g2);
+    vec_convert(ctx, out + p + n, 8, g2, 8, m, false, 1.0 / (sa * beta));
+  }
+  void m_left(Ctx& ctx, const double* u, double* out) {
+    vec_convert(ctx, out, 8, u, 8, p, false, 1.0 / sa);
+    vec_convert(ctx, g1, 8, u + p, 8, n, false);
+    agg_apply(ctx, fw, true, g1, 8);
+    t2_solve(ctx, g1, false);
+    vec_convert(ctx, out + p, 8, g1, 8, n, false, sa);
+    vec_convert(ctx, g1, 8, u + p + n, 8, m, false);
+    trsv(ctx, tR, true, g1);
+    s_apply(ctx, g1, g2, true);
+    vec_convert(ctx, out + p + n, 8, g2, 8, m, false, 1.0 / (sa * beta));
+  }
+  void f_apply(Ctx& ctx, const GlsArgs& a, const double* u, double* out);
 };
+
+void LseSolver::f_apply(Ctx& ctx, const LseArgs& a, const double* u, double* out) {
+  dual_gemv(ctx, a.A, a.lda, m, n, u + m + p, u, dpa);         // A c, A^T a
+  dual_gemv(ctx, a.B, a.ldb, p, n, u + m + p, u + m, dpb);     // B c, B^T b
+  combine(ctx, out, m, alpha, u, 1.0, dpa.rowp, dpa.ncb, 0.0, nullptr, 0);
+  combine(ctx, out + m, p, 0.0, nullptr, beta, dpb.rowp, dpb.ncb, 0.0, nullptr, 0);
+  combine(ctx, out + m + p, n, 0.0, nullptr, 1.0, dpa.colp, dpa.nrb, beta, dpb.colp, dpb.nrb);
+}
+
+void GlsSolver::f_apply(Ctx& ctx, const GlsArgs& a, const double* u, double* out) {
+  dual_gemv(ctx, a.V, a.ldv, n, p, u, u + p, dpv);             // V a, V^T b
+  dual_gemv(ctx, a.W, a.ldw, n, m, u + p + n, u + p, dpw);     // W c, W^T b
+  combine(ctx, out, p, alpha, u, 1.0, dpv.colp, dpv.nrb, 0.0, nullptr, 0);
+  combine(ctx, out + p, n, 0.0, nullptr, 1.0, dpv.rowp, dpv.ncb, beta, dpw.rowp, dpw.ncb);
+  combine(ctx, out + p + n, m, 0.0, nullptr, beta, dpw.colp, dpw.nrb, 0.0, nullptr, 0);
+}
 
 // ------------------------------------------------------- rung execution --
 struct RungOut {
@@ -344,35 +486,86 @@ RungOut run_classical(lsq_handle h, const std::function<void()>& zero,
   return out;
 }
 
-struct LseArgs {
-  int m, n, p;
-  const double *A, *B, *b, *d;
-  int lda, ldb;
-};
-struct GlsArgs {
-  int n, m, p;
-  const double *W, *V, *d;
-  int ldw, ldv;
-};
 
-// One rung for LSE: factor at prec, then classical refinement (the DIRECT
-// solver is the same loop at FP64; it normally stops at the first test).
-RungOut lse_rung(lsq_handle h, const LseArgs& a, int prec, int solver, const lsq_opts& o,
-                 double* x, double* r, double* v) {
+// GMRES-IR refinement (Sections 5.2 / 5.3): the initial guess as in the
+// classical case, then per outer step the scaled residual
+// st = D f, GMRES on M_l F M_r w = M_l st, the correction du = M_r w, and the
+// update undoing D.  ops.scale_in / ops.update hold the problem-specific scalings.
+template <typename Solver, typename Args>
+RungOut run_gmres(lsq_handle h, Solver& sv, const Args& a, int N,
+                  const std::function<void()>& zero, const std::function<void()>& init,
+                  const std::function<void()>& residual,
+                  const std::function<double()>& alpha0,
+                  const std::function<void(double*)>& scaled_residual,
+                  const std::function<void(const double*)>& update, const lsq_opts& o) {
+  Ctx& ctx = h->ctx;
+  RungOut out;
+  zero();
+  LSQ_HIP(hipEventRecord(h->ev[2], h->stream));
+  init();
+  sv.alpha = o.alpha > 0 ? o.alpha : alpha0();
+  sv.beta = o.beta > 0 ? o.beta : 1.0;
+  sv.sa = std::sqrt(sv.alpha);
+  double* st = ctx.ws->get<double>(std::max(N, 1));
+  double* rhs = ctx.ws->get<double>(std::max(N, 1));
+  double* w = ctx.ws->get<double>(std::max(N, 1));
+  double* du = ctx.ws->get<double>(std::max(N, 1));
+  auto apply = [&](const double* u, double* y) {
+    sv.m_right(ctx, u, sv.t1);
+    sv.f_apply(ctx, a, sv.t1, sv.t2);
+    sv.m_left(ctx, sv.t2, y);
+  };
+  std::vector<double> hist;
+  for (int it = 0;; ++it) {
+    residual();
+    read_status(h);
+    const StopStatus& stt = *h->st_host;
+    hist.push_back(stt.berr_max);
+    for (int q = 0; q < 3; ++q) out.berr[q] = stt.berr[q];
+    out.berr_max = stt.berr_max;
+    out.steps = it;
+    if (stt.converged) { out.ok = true; break; }
+    if (stt.nonfinite || it >= o.maxit || out.inner >= o.gmres_maxit || stalled(hist)) break;
+    scaled_residual(st);
+    sv.m_left(ctx, st, rhs);
+    const GmresOut g = gmres(ctx, N, apply, rhs, w, o.gmres_restart, o.gmres_tol,
+                             o.gmres_maxit - out.inner);
+    out.inner += g.iters;
+    sv.m_right(ctx, w, du);
+    update(du);
+  }
+  LSQ_HIP(hipEventRecord(h->ev[3], h->stream));
+  LSQ_HIP(hipEventSynchronize(h->ev[3]));
+  out.ms_refine = elapsed(h->ev[2], h->ev[3]);
+  return out;
+}
+
+// GMRES-IR needs the block-diagonal preconditioner's shape condition
+// (eq. lse-bdpre-mlarge: m >= n; eq. gls-bdpre-plarge: n <= p).
+bool lse_gmres_ok(int m, int n) { return m >= n; }
+bool gls_gmres_ok(int n, int p) { return n <= p; }
+
+// One precision of the ladder for LSE: the factorization at prec, then the
+// refinement solvers in order on the same factors (IR: Algorithm 2; GMRES:
+// GMRES-IR; DIRECT: the FP64 factors with the classical loop).
+RungOut lse_rung(lsq_handle h, const LseArgs& a, int prec, const std::vector<int>& solvers,
+                 const lsq_opts& o, double* x, double* r, double* v, int& attempts,
+                 int& solver_used) {
   Ctx& ctx = h->ctx;
   LseSolver sv;
   sv.m = a.m; sv.n = a.n; sv.p = a.p; sv.k = a.n - a.p;
-  (void)solver;
   prec_spec(prec, sv.ps);
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
   sv.factor(ctx, a.A, a.lda, a.B, a.ldb, default_nb(o));
-  sv.prepare(ctx, sv.ps.tc);
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
   int stat_b = read_int(h, sv.fb.status);
   int stat_a = read_int(h, sv.fa.status);
+  const float ms_factor = elapsed(h->ev[0], h->ev[1]);
   RungOut out;
   if (stat_b || stat_a) {
     out.breakdown = true;
+    ++attempts;
+    solver_used = solvers.empty() ? LSQ_SOLVER_IR : solvers[0];
     return out;
   }
   double* f1 = ctx.ws->get<double>(a.m > 0 ? a.m : 1);
@@ -382,31 +575,61 @@ RungOut lse_rung(lsq_handle h, const LseArgs& a, int prec, int solver, const lsq
     lse_residual(ctx, a.m, a.n, a.p, a.A, a.lda, a.B, a.ldb, a.b, a.d, x, r, v, f1, f2, f3,
                  h->matnorms, o.tol, h->st_dev);
   };
-  out = run_classical(
-      h,
-      [&]() { vec_zero(ctx, x, 8, a.n); vec_zero(ctx, r, 8, a.m); vec_zero(ctx, v, 8, a.p); },
-      [&]() { sv.correct(ctx, a.b, a.d, nullptr, x, r, v); }, residual,
-      [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o);
-  out.ms_factor = elapsed(h->ev[0], h->ev[1]);
+  auto zero = [&]() { vec_zero(ctx, x, 8, a.n); vec_zero(ctx, r, 8, a.m); vec_zero(ctx, v, 8, a.p); };
+  auto init = [&]() { sv.correct(ctx, a.b, a.d, nullptr, x, r, v); };
+  for (int solver : solvers) {
+    ++attempts;
+    solver_used = solver;
+    if (solver == LSQ_SOLVER_GMRES_IR) {
+      sv.prepare_gmres(ctx);
+      const int m = a.m, p = a.p, n = a.n;
+      out = run_gmres(
+          h, sv, a, m + p + n, zero, init, residual,
+          [&]() {
+            double al = dev_norm2(ctx, r, m);
+            if (!(al > 0.0)) al = std::sqrt(0.5) * min_abs_diag(ctx, sv.fa, 0, n);
+            return al > 0.0 ? al : 1.0;
+          },
+          [&](double* st) {
+            vec_convert(ctx, st, 8, f1, 8, m, false, sv.sa);
+            vec_convert(ctx, st + m, 8, f2, 8, p, false, sv.sa * sv.beta);
+            vec_convert(ctx, st + m + p, 8, f3, 8, n, false, 1.0 / sv.sa);
+          },
+          [&](const double* du) {
+            vec_axpy(ctx, r, 8, sv.sa, du, 8, m, false);
+            vec_axpy(ctx, v, 8, -sv.sa * sv.beta, du + m, 8, p, false);
+            vec_axpy(ctx, x, 8, 1.0 / sv.sa, du + m + p, 8, n, false);
+          },
+          o);
+    } else {
+      sv.prepare(ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc);
+      out = run_classical(h, zero, init, residual,
+                          [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o);
+    }
+    out.ms_factor = ms_factor;
+    if (out.ok) break;
+  }
   return out;
 }
 
-RungOut gls_rung(lsq_handle h, const GlsArgs& a, int prec, int solver, const lsq_opts& o,
-                 double* x, double* y, double* z) {
+RungOut gls_rung(lsq_handle h, const GlsArgs& a, int prec, const std::vector<int>& solvers,
+                 const lsq_opts& o, double* x, double* y, double* z, int& attempts,
+                 int& solver_used) {
   Ctx& ctx = h->ctx;
   GlsSolver sv;
   sv.n = a.n; sv.m = a.m; sv.p = a.p; sv.k = a.n - a.m;
-  (void)solver;
   prec_spec(prec, sv.ps);
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
   sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o));
-  sv.prepare(ctx, sv.ps.tc);
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
   int stat_w = read_int(h, sv.fw.status);
   int stat_v = read_int(h, sv.fv.status);
+  const float ms_factor = elapsed(h->ev[0], h->ev[1]);
   RungOut out;
   if (stat_w || stat_v) {
     out.breakdown = true;
+    ++attempts;
+    solver_used = solvers.empty() ? LSQ_SOLVER_IR : solvers[0];
     return out;
   }
   double* f1 = ctx.ws->get<double>(a.p > 0 ? a.p : 1);
@@ -416,35 +639,73 @@ RungOut gls_rung(lsq_handle h, const GlsArgs& a, int prec, int solver, const lsq
     gls_residual(ctx, a.n, a.m, a.p, a.W, a.ldw, a.V, a.ldv, a.d, x, y, z, f1, f2, f3,
                  h->matnorms, o.tol, h->st_dev);
   };
-  out = run_classical(
-      h,
-      [&]() { vec_zero(ctx, x, 8, a.m); vec_zero(ctx, y, 8, a.p); vec_zero(ctx, z, 8, a.n); },
-      [&]() { sv.correct(ctx, nullptr, a.d, nullptr, x, y, z); }, residual,
-      [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o);
-  out.ms_factor = elapsed(h->ev[0], h->ev[1]);
+  auto zero = [&]() { vec_zero(ctx, x, 8, a.m); vec_zero(ctx, y, 8, a.p); vec_zero(ctx, z, 8, a.n); };
+  auto init = [&]() { sv.correct(ctx, nullptr, a.d, nullptr, x, y, z); };
+  for (int solver : solvers) {
+    ++attempts;
+    solver_used = solver;
+    if (solver == LSQ_SOLVER_GMRES_IR) {
+      sv.prepare_gmres(ctx);
+      const int m = a.m, p = a.p, n = a.n;
+      out = run_gmres(
+          h, sv, a, p + n + m, zero, init, residual,
+          [&]() {
+            double al = dev_norm2(ctx, y, p);
+            if (!(al > 0.0)) al = std::sqrt(0.5) * min_abs_diag(ctx, sv.fv, 0, n);
+            return al > 0.0 ? al : 1.0;
+          },
+          [&](double* st) {
+            vec_convert(ctx, st, 8, f1, 8, p, false, sv.sa);
+            vec_convert(ctx, st + p, 8, f2, 8, n, false, 1.0 / sv.sa);
+            vec_convert(ctx, st + p + n, 8, f3, 8, m, false, sv.sa * sv.beta);
+          },
+          [&](const double* du) {
+            vec_axpy(ctx, y, 8, sv.sa, du, 8, p, false);
+            vec_axpy(ctx, z, 8, -1.0 / sv.sa, du + p, 8, n, false);
+            vec_axpy(ctx, x, 8, sv.sa * sv.beta, du + p + n, 8, m, false);
+          },
+          o);
+    } else {
+      sv.prepare(ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc);
+      out = run_classical(h, zero, init, residual,
+                          [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o);
+    }
+    out.ms_factor = ms_factor;
+    if (out.ok) break;
+  }
   return out;
 }
 
-// Escalation ladder: the requested rung first, then higher precisions,
-// finally the FP64 direct path.
-std::vector<std::pair<int, int>> ladder(const lsq_opts& o) {
-  std::vector<std::pair<int, int>> r;
+// Escalation ladder: (precision, refinement solvers on that precision's
+// factors).  Starting at the requested rung: with IR requested, each
+// precision tries classical IR and then GMRES-IR on the same factors; with
+// GMRES requested, GMRES-IR only; precisions rise BF16 -> FP16 -> FP32 and the
+// ladder ends with the FP64 direct path.  GMRES-IR is left out when the
+// preconditioner's shape condition fails.
+std::vector<std::pair<int, std::vector<int>>> ladder(const lsq_opts& o, bool gmres_ok) {
+  std::vector<std::pair<int, std::vector<int>>> r;
   int prec = o.prec == LSQ_PREC_AUTO ? LSQ_PREC_FP32 : o.prec;
   if (prec == LSQ_PREC_FP8E4M3) prec = LSQ_PREC_BF16;
   int solver = o.solver == LSQ_SOLVER_AUTO ? LSQ_SOLVER_IR : o.solver;
   if (solver == LSQ_SOLVER_DIRECT || prec == LSQ_PREC_FP64) {
-    r.push_back({LSQ_PREC_FP64, LSQ_SOLVER_DIRECT});
+    r.push_back({LSQ_PREC_FP64, {LSQ_SOLVER_DIRECT}});
     return r;
   }
-  r.push_back({prec, LSQ_SOLVER_IR});
-  if (!o.escalate) return r;
-  const int order[] = {LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32};
-  bool after = false;
-  for (int q : order) {
-    if (q == prec) { after = true; continue; }
-    if (after) r.push_back({q, LSQ_SOLVER_IR});
+  if (solver == LSQ_SOLVER_GMRES_IR && !gmres_ok) solver = LSQ_SOLVER_IR;
+  if (!o.escalate) {
+    r.push_back({prec, {solver}});
+    return r;
   }
-  r.push_back({LSQ_PREC_FP64, LSQ_SOLVER_DIRECT});
+  std::vector<int> solvers;
+  if (solver == LSQ_SOLVER_IR) solvers.push_back(LSQ_SOLVER_IR);
+  if (gmres_ok) solvers.push_back(LSQ_SOLVER_GMRES_IR);
+  const int order[] = {LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32};
+  bool on = false;
+  for (int q : order) {
+    if (q == prec) on = true;
+    if (on) r.push_back({q, solvers});
+  }
+  r.push_back({LSQ_PREC_FP64, {LSQ_SOLVER_DIRECT}});
   return r;
 }
 
@@ -502,6 +763,8 @@ int lsq_create(lsq_handle* out, int device) {
     h->ctx.stream = nullptr;
     LSQ_HIP(hipMalloc(&h->st_dev, sizeof(StopStatus)));
     LSQ_HIP(hipHostMalloc(&h->st_host, sizeof(StopStatus), 0));
+    LSQ_HIP(hipHostMalloc(&h->pin, sizeof(double) * kPinDoubles, 0));
+    h->ctx.pin = h->pin;
     LSQ_HIP(hipMalloc(&h->matnorms, 8 * sizeof(double)));
     for (auto& e : h->ev) LSQ_HIP(hipEventCreate(&e));
     hipDeviceProp_t prop;
@@ -525,6 +788,7 @@ int lsq_destroy(lsq_handle h) {
     if (e) (void)hipEventDestroy(e);
   if (h->st_dev) (void)hipFree(h->st_dev);
   if (h->st_host) (void)hipHostFree(h->st_host);
+  if (h->pin) (void)hipHostFree(h->pin);
   if (h->matnorms) (void)hipFree(h->matnorms);
   for (auto& e : h->ev)
     if (e) (void)hipEventDestroy(e);
@@ -582,17 +846,14 @@ int lse_solve(lsq_handle h, int m, int n, int p, const double* A, int lda, const
     double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
     double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
     double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
-    const auto rungs = ladder(o);
+    const auto rungs = ladder(o, lse_gmres_ok(m, n));
     RungOut ro;
     int used_p = 0, used_s = 0, attempts = 0, info = 3;
-    for (auto [prec, solver] : rungs) {
-      ++attempts;
-      ro = lse_rung(h, a, prec, solver, o, xi, ri, vi);
+    for (const auto& [prec, solvers] : rungs) {
+      ro = lse_rung(h, a, prec, solvers, o, xi, ri, vi, attempts, used_s);
       used_p = prec;
-      used_s = solver;
       if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
       if (ro.ok) { info = 0; break; }
-      if (ro.berr_max != ro.berr_max) { /* NaN: try next rung */ }
     }
     if (info != 1) {
       if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
@@ -630,14 +891,12 @@ int gls_solve(lsq_handle h, int n, int m, int p, const double* W, int ldw, const
     double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
     double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
     double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
-    const auto rungs = ladder(o);
+    const auto rungs = ladder(o, gls_gmres_ok(n, p));
     RungOut ro;
     int used_p = 0, used_s = 0, attempts = 0, info = 3;
-    for (auto [prec, solver] : rungs) {
-      ++attempts;
-      ro = gls_rung(h, a, prec, solver, o, xi, yi, zi);
+    for (const auto& [prec, solvers] : rungs) {
+      ro = gls_rung(h, a, prec, solvers, o, xi, yi, zi, attempts, used_s);
       used_p = prec;
-      used_s = solver;
       if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
       if (ro.ok) { info = 0; break; }
     }
@@ -904,6 +1163,45 @@ int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes) {
   if (bytes > 0 && (!dst || !src)) return -2;
   return guard(h, "lsq_dbg_copy", [&]() -> int {
     dev_copy(h->ctx, dst, src, (size_t)bytes);
+    LSQ_HIP(hipStreamSynchronize(h->stream));
+    return 0;
+  });
+}
+
+// ------------------------------------------------- preconditioned operator --
+int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, const double* A, int lda,
+                     const double* B, int ldb, double alpha, double beta, const double* u,
+                     double* y) {
+  if (!h) return -1;
+  if (type != LSQ_LSE && type != LSQ_GLS) return -2;
+  PrecSpec ps;
+  if (!prec_spec(prec, ps)) return -3;
+  if (type == LSQ_LSE && !(p <= n && n <= m + p && lse_gmres_ok(m, n))) return -4;
+  if (type == LSQ_GLS && !(m <= n && n <= m + p && gls_gmres_ok(n, p))) return -4;
+  if (!(alpha > 0) || !(beta > 0)) return -11;
+  return guard(h, "lsq_dbg_bd_apply", [&]() -> int {
+    Ctx& ctx = h->ctx;
+    if (type == LSQ_LSE) {
+      LseSolver sv;
+      sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
+      LseArgs a{m, n, p, A, B, nullptr, nullptr, lda, ldb};
+      sv.factor(ctx, A, lda, B, ldb, kMaxNb);
+      sv.prepare_gmres(ctx);
+      sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
+      sv.m_right(ctx, u, sv.t1);
+      sv.f_apply(ctx, a, sv.t1, sv.t2);
+      sv.m_left(ctx, sv.t2, y);
+    } else {
+      GlsSolver sv;
+      sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.ps = ps;
+      GlsArgs a{n, m, p, A, B, nullptr, lda, ldb};
+      sv.factor(ctx, A, lda, B, ldb, kMaxNb);
+      sv.prepare_gmres(ctx);
+      sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
+      sv.m_right(ctx, u, sv.t1);
+      sv.f_apply(ctx, a, sv.t1, sv.t2);
+      sv.m_left(ctx, sv.t2, y);
+    }
     LSQ_HIP(hipStreamSynchronize(h->stream));
     return 0;
   });

@@ -1,7 +1,10 @@
 // Host-side interfaces between liblsq's HIP translation units.
 #pragma once
-#include <vector>
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
+#include <functional>
+#include <vector>
 #include "common.hpp"
 
 namespace lsq {
@@ -35,11 +38,14 @@ struct KernelTimer {
   double flops = 0.0, bytes = 0.0;
 };
 
+constexpr int kPinDoubles = 8192;   // size of the pinned host scratch of a context
+
 struct Ctx {
   hipStream_t stream = nullptr;
   Arena* ws = nullptr;
   int num_cu = 256;
   KernelTimer* timer = nullptr;
+  double* pin = nullptr;             // pinned host scratch (kPinDoubles)
 };
 
 // Brackets one launch of kind `kind`; does nothing unless the timer targets it.
@@ -128,6 +134,9 @@ struct DualParts {
   double* rowp = nullptr;  int ncb = 0;   // ncb x rows
   double* colp = nullptr;  int nrb = 0;   // nrb x cols
 };
+// Partial-sum buffers for a rows x cols matrix; dual_gemv allocates them
+// itself when out.rowp is null, else reuses them (same shape required).
+void dual_parts_alloc(Ctx& ctx, int rows, int cols, DualParts& out);
 void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const double* u,
                const double* w, DualParts& out);
 
@@ -158,5 +167,21 @@ void dev_copy(Ctx& ctx, void* dst, const void* src, size_t bytes);
 void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double* B, int ldb,
                 int br, int bc, const double* v1, int n1, const double* v2, int n2,
                 double* matnorms);
+
+// ------------------------------------------------------- FP64 Krylov ----
+// out[i] = c0 x0[i] + c1 sum_q p1[q][i] + c2 sum_q p2[q][i] (null terms skipped),
+// the parts being the partial products left by dual_gemv.
+void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c1, const double* p1,
+             int np1, double c2, const double* p2, int np2);
+double dev_norm2(Ctx& ctx, const double* x, int n);                 // synchronizes
+double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn);   // synchronizes
+
+struct GmresOut {
+  int iters = 0;
+  bool converged = false;
+};
+// Restarted GMRES from x = 0 for apply(u) = M u (FP64, CGS2, Givens on the host).
+GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
+               const double* rhs, double* x, int restart, double tol, int maxit);
 
 }  // namespace lsq

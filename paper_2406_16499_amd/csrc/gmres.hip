@@ -1,0 +1,258 @@
+// Restarted GMRES in FP64 on the device (the inner solver of GMRES-IR,
+// Section 5: GMRES on the preconditioned augmented system, FP64 arithmetic
+// with the factors stored at u_f).
+//
+// Arnoldi with classical Gram-Schmidt applied twice (CGS2): per pass one
+// kernel forms the partial dot products V_k^T w per 256-row block, the next
+// sums them and subtracts V_k h from w (the second pass also accumulates
+// ||w||^2 per block).  The (k+1)-vector h and the norm go to the host, which
+// applies the Givens rotations to the small Hessenberg matrix and decides
+// convergence.  The basis is column-major N x (restart + 1) in FP64.
+#include "engine.hpp"
+
+namespace lsq {
+
+constexpr int kCgsRows = 256;        // rows per work-group in the CGS kernels
+constexpr int kCgsMax = 32;          // at most restart + 1 <= 32 basis vectors
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// part[b * kCgsMax + j] = sum over the rows of block b of V[i, j] w[i], j < kc.
+__global__ __launch_bounds__(256) void k_cgs_dot(const double* __restrict__ V, int ldv, int N, int kc,
+                                                 const double* __restrict__ w, double* __restrict__ part) {
+  __shared__ double red[4][kCgsMax];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int i = blockIdx.x * kCgsRows + t;
+  const double wi = i < N ? w[i] : 0.0;
+#pragma unroll 4
+  for (int j = 0; j < kCgsMax; ++j) {
+    if (j >= kc) break;
+    double s = i < N ? V[(size_t)i + (size_t)j * ldv] * wi : 0.0;
+    s = wave_sum_d(s);
+    if (lane == 0) red[wv][j] = s;
+  }
+  __syncthreads();
+  if (t < kc) part[(size_t)blockIdx.x * kCgsMax + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
+// h = sum of the block partials; w -= V h; hacc (+)= h (written by block 0);
+// with nrm, nrm[b] = sum over block b of the updated w[i]^2.
+__global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V, int ldv, int N, int kc,
+                                                    const double* __restrict__ part, int nblk,
+                                                    double* __restrict__ w, double* __restrict__ hacc,
+                                                    int accumulate, double* __restrict__ nrm) {
+  __shared__ double h[kCgsMax];
+  __shared__ double red[4];
+  const int t = threadIdx.x;
+  if (t < kc) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kCgsMax + t];
+    h[t] = s;
+    if (blockIdx.x == 0) hacc[t] = accumulate ? hacc[t] + s : s;
+  }
+  __syncthreads();
+  const int i = blockIdx.x * kCgsRows + t;
+  double sq = 0.0;
+  if (i < N) {
+    double wi = w[i];
+    for (int j = 0; j < kc; ++j) wi = fma(-V[(size_t)i + (size_t)j * ldv], h[j], wi);
+    w[i] = wi;
+    sq = wi * wi;
+  }
+  if (nrm) {
+    sq = block_sum(sq, red);
+    if (t == 0) nrm[blockIdx.x] = sq;
+  }
+}
+
+// x += V[:, 0:kc] y
+__global__ __launch_bounds__(256) void k_basis_combine(const double* __restrict__ V, int ldv, int N,
+                                                       int kc, const double* __restrict__ y,
+                                                       double* __restrict__ x) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= N) return;
+  double s = 0.0;
+  for (int j = 0; j < kc; ++j) s = fma(V[(size_t)i + (size_t)j * ldv], y[j], s);
+  x[i] += s;
+}
+
+// out[i] = c0 x0[i] + c1 sum_q p1[q][i] + c2 sum_q p2[q][i]  (null terms skipped)
+__global__ __launch_bounds__(256) void k_combine(double* __restrict__ out, int n, double c0,
+                                                 const double* __restrict__ x0, double c1,
+                                                 const double* __restrict__ p1, int np1, double c2,
+                                                 const double* __restrict__ p2, int np2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  double s = x0 ? c0 * x0[i] : 0.0;
+  if (p1) {
+    double a = 0.0;
+    for (int q = 0; q < np1; ++q) a += p1[(size_t)q * n + i];
+    s = fma(c1, a, s);
+  }
+  if (p2) {
+    double a = 0.0;
+    for (int q = 0; q < np2; ++q) a += p2[(size_t)q * n + i];
+    s = fma(c2, a, s);
+  }
+  out[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sumsq_vec(const double* __restrict__ x, int n,
+                                                   double* __restrict__ part) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) s = fma(x[i], x[i], s);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename Tw>
+__global__ __launch_bounds__(256) void k_min_abs_diag(const Tw* __restrict__ M, int ld, int nn,
+                                                      double* __restrict__ out) {
+  __shared__ double red[256];
+  double m = INFINITY;
+  for (int i = threadIdx.x; i < nn; i += 256) m = fmin(m, fabs((double)M[(size_t)i + (size_t)i * ld]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// ------------------------------------------------------------------ host --
+void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c1, const double* p1,
+             int np1, double c2, const double* p2, int np2) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_combine, dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream, out, n, c0, x0, c1,
+                     p1, np1, c2, p2, np2);
+  LSQ_LAUNCH_CHECK();
+}
+
+double dev_norm2(Ctx& ctx, const double* x, int n) {
+  if (n <= 0) return 0.0;
+  int g = ceil_div(n, 256);
+  if (g > 64) g = 64;
+  double* part = ctx.ws->get<double>(64);
+  hipLaunchKernelGGL(k_sumsq_vec, dim3(g), dim3(256), 0, ctx.stream, x, n, part);
+  LSQ_LAUNCH_CHECK();
+  LSQ_HIP(hipMemcpyAsync(ctx.pin, part, sizeof(double) * g, hipMemcpyDeviceToHost, ctx.stream));
+  LSQ_HIP(hipStreamSynchronize(ctx.stream));
+  double s = 0.0;
+  for (int q = 0; q < g; ++q) s += ctx.pin[q];
+  return std::sqrt(s);
+}
+
+double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn) {
+  if (nn <= 0) return 0.0;
+  double* out = ctx.ws->get<double>(1);
+  if (f.tw == 8)
+    hipLaunchKernelGGL((k_min_abs_diag<double>), dim3(1), dim3(256), 0, ctx.stream,
+                       static_cast<const double*>(f.M) + (size_t)o * (f.ld + 1), f.ld, nn, out);
+  else
+    hipLaunchKernelGGL((k_min_abs_diag<float>), dim3(1), dim3(256), 0, ctx.stream,
+                       static_cast<const float*>(f.M) + (size_t)o * (f.ld + 1), f.ld, nn, out);
+  LSQ_LAUNCH_CHECK();
+  LSQ_HIP(hipMemcpyAsync(ctx.pin, out, sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  LSQ_HIP(hipStreamSynchronize(ctx.stream));
+  return ctx.pin[0];
+}
+
+// Restarted GMRES(restart) from x = 0 on apply(u) = M u, stopping when the
+// Arnoldi residual estimate reaches tol ||rhs|| or after maxit iterations in
+// total; after every cycle the residual is recomputed from x.
+GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
+               const double* rhs, double* x, int restart, double tol, int maxit) {
+  GmresOut out;
+  vec_zero(ctx, x, 8, N);
+  if (N <= 0) { out.converged = true; return out; }
+  if (restart > kCgsMax - 1) restart = kCgsMax - 1;
+  if (restart < 1) restart = 1;
+  const int nblk = ceil_div(N, kCgsRows);
+  double* Vb = ctx.ws->get<double>((size_t)N * (restart + 1));
+  double* r = ctx.ws->get<double>(N);
+  double* part = ctx.ws->get<double>((size_t)nblk * kCgsMax);
+  double* hdev = ctx.ws->get<double>(kCgsMax);
+  double* nrm = ctx.ws->get<double>(nblk);
+  double* ydev = ctx.ws->get<double>(kCgsMax);
+  double* pin = ctx.pin;                     // pinned: kCgsMax + nblk doubles needed
+  if (kCgsMax + nblk > kPinDoubles) throw HipError{hipErrorInvalidValue, "GMRES: vector too long"};
+  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1);
+  auto Hc = [&](int i, int k) -> double& { return H[(size_t)i + (size_t)k * (restart + 1)]; };
+
+  vec_convert(ctx, r, 8, rhs, 8, N, false);
+  const double beta0 = dev_norm2(ctx, r, N);
+  if (beta0 == 0.0) { out.converged = true; return out; }
+  double beta = beta0;
+  while (out.iters < maxit) {
+    if (beta <= tol * beta0) { out.converged = true; break; }
+    const int kmax = std::min(restart, maxit - out.iters);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    vec_convert(ctx, Vb, 8, r, 8, N, false, 1.0 / beta);
+    int kdone = 0;
+    bool done = false;
+    for (int k = 0; k < kmax; ++k) {
+      double* w = Vb + (size_t)(k + 1) * N;
+      apply(Vb + (size_t)k * N, w);
+      const int kc = k + 1;
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_cgs_dot, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, w, part);
+        hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, part, nblk,
+                           w, hdev, pass, pass == 1 ? nrm : nullptr);
+      }
+      LSQ_LAUNCH_CHECK();
+      LSQ_HIP(hipMemcpyAsync(pin, hdev, sizeof(double) * kc, hipMemcpyDeviceToHost, ctx.stream));
+      LSQ_HIP(hipMemcpyAsync(pin + kCgsMax, nrm, sizeof(double) * nblk, hipMemcpyDeviceToHost, ctx.stream));
+      LSQ_HIP(hipStreamSynchronize(ctx.stream));
+      double hn2 = 0.0;
+      for (int b = 0; b < nblk; ++b) hn2 += pin[kCgsMax + b];
+      const double hn = std::sqrt(hn2);
+      for (int i = 0; i < kc; ++i) Hc(i, k) = pin[i];
+      Hc(k + 1, k) = hn;
+      if (hn > 0.0) vec_convert(ctx, w, 8, w, 8, N, false, 1.0 / hn);
+      for (int i = 0; i < k; ++i) {        // earlier rotations
+        const double t0 = cs[i] * Hc(i, k) + sn[i] * Hc(i + 1, k);
+        Hc(i + 1, k) = -sn[i] * Hc(i, k) + cs[i] * Hc(i + 1, k);
+        Hc(i, k) = t0;
+      }
+      const double rho = std::hypot(Hc(k, k), Hc(k + 1, k));
+      cs[k] = rho > 0.0 ? Hc(k, k) / rho : 1.0;
+      sn[k] = rho > 0.0 ? Hc(k + 1, k) / rho : 0.0;
+      Hc(k, k) = rho;
+      Hc(k + 1, k) = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      ++out.iters;
+      kdone = k + 1;
+      if (std::fabs(g[k + 1]) <= tol * beta0 || hn == 0.0) { done = true; break; }
+    }
+    // y = H(0:kdone, 0:kdone)^{-1} g, x += V y, r = rhs - M x
+    std::vector<double> y(kdone);
+    for (int i = kdone - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int j = i + 1; j < kdone; ++j) s -= Hc(i, j) * y[j];
+      y[i] = Hc(i, i) != 0.0 ? s / Hc(i, i) : 0.0;
+    }
+    for (int i = 0; i < kdone; ++i) pin[i] = y[i];
+    LSQ_HIP(hipMemcpyAsync(ydev, pin, sizeof(double) * kdone, hipMemcpyHostToDevice, ctx.stream));
+    hipLaunchKernelGGL(k_basis_combine, dim3(ceil_div(N, 256)), dim3(256), 0, ctx.stream, Vb, N, N,
+                       kdone, ydev, x);
+    LSQ_LAUNCH_CHECK();
+    apply(x, r);
+    vec_axpy(ctx, r, 8, -1.0, rhs, 8, N, false);          // r = M x - rhs
+    beta = dev_norm2(ctx, r, N);
+    vec_convert(ctx, r, 8, r, 8, N, false, -1.0);           // r = rhs - M x
+    if (done && std::fabs(g[kdone]) <= tol * beta0) { out.converged = true; break; }
+  }
+  if (!out.converged) out.converged = beta <= tol * beta0;
+  return out;
+}
+
+}  // namespace lsq

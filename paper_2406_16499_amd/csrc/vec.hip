@@ -234,12 +234,18 @@ __global__ __launch_bounds__(256) void k_dual_gemv(const double* __restrict__ M,
     colp[(size_t)blockIdx.x * cols + c0 + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
 }
 
-void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const double* u,
-               const double* w, DualParts& out) {
+void dual_parts_alloc(Ctx& ctx, int rows, int cols, DualParts& out) {
   out.nrb = ceil_div(rows, 256);
   out.ncb = ceil_div(cols, 64);
   out.rowp = ctx.ws->get<double>((size_t)out.ncb * (rows > 0 ? rows : 1));
   out.colp = ctx.ws->get<double>((size_t)out.nrb * (cols > 0 ? cols : 1));
+}
+
+void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const double* u,
+               const double* w, DualParts& out) {
+  if (!out.rowp) dual_parts_alloc(ctx, rows, cols, out);
+  out.nrb = ceil_div(rows, 256);
+  out.ncb = ceil_div(cols, 64);
   if (rows <= 0 || cols <= 0) {
     out.nrb = out.ncb = 0;
     return;

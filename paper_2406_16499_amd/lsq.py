@@ -82,6 +82,8 @@ _SIGS = {
                                        _P, _P, _P, _P, _P]),
     "lsq_dbg_gls_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
                                        _P, _P, _P, _P, _P]),
+    "lsq_dbg_bd_apply": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int,
+                                 c_double, c_double, _P, _P]),
     "lsq_dbg_timer_enable": (c_int, [_P, ctypes.c_char_p]),
     "lsq_dbg_timer_read": (c_int, [_P, ctypes.POINTER(c_double), ctypes.POINTER(c_int),
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
@@ -237,6 +239,25 @@ class Handle:
         return rc, list(res)
 
     # ---------------------------------------------------------- debug --
+    def dbg_bd_apply(self, kind, prec, A, B, alpha, beta, u):
+        """y = M_l F~ M_r u for LSE (kind "lse": A m x n, B p x n) or GLS (kind
+        "gls": A = W n x m, B = V n x p), factors at `prec`."""
+        torch = _torch()
+        y = torch.zeros_like(u)
+        if kind == "lse":
+            m, n = A.shape
+            p = B.shape[0]
+            t = LSE
+        else:
+            n, m = A.shape
+            p = B.shape[1]
+            t = GLS
+        rc = self.lib.lsq_dbg_bd_apply(self.h, t, PREC[prec], m, n, p, _ptr(A), _ld(A), _ptr(B),
+                                       _ld(B), float(alpha), float(beta), _ptr(u), _ptr(y))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_bd_apply = {rc}: {self.last_error()}")
+        return y
+
     def timer_enable(self, kernel: Optional[str]):
         """Time every launch of one kernel kind with HIP events (None disables)."""
         rc = self.lib.lsq_dbg_timer_enable(self.h, (kernel or "").encode())

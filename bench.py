@@ -58,6 +58,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel", default="panel_final_y", choices=sorted(KERNELS))
+    ap.add_argument("--workload", default="lse-large", choices=["lse-large", "batched"],
+                    help="lse-large: the single 4096x2048x256 LSE (default); batched: the "
+                         "2000-instance mixed LSE/GLS workload")
+    ap.add_argument("--count", type=int, default=2000, help="instances of the batched workload")
+    ap.add_argument("--workers", type=int, default=8, help="batch workers (streams)")
     return ap.parse_args()
 
 
@@ -139,6 +144,81 @@ def cpu_baseline(prob, seconds):
             "sample": f"{count} full solves of the benchmark LSE (FP64 null-space GRQ oracle, numpy/scipy LAPACK) in {dt:.1f} s"}
 
 
+BATCH_WORKLOAD = ("2000 instances, 50/50 LSE/GLS; LSE m~U[64,1024], n~U[32,m/2], p~U[4,n/4], "
+                  "GLS mirrored; A,B (W,V) = U diag(s) V^T, kappa log-U[1e1,1e8]; RHS N(0,1); seed 4")
+
+
+def batched(args):
+    """The batched workload: every instance solved per step, a solve counting
+    only if it certifies berr <= 1e-14."""
+    import torch
+    from paper_2406_16499_amd import lsq
+    from paper_2406_16499_amd import workloads as wl
+    t0 = time.perf_counter()
+    probs = list(wl.batch_instances(seed=4, count=args.count))
+    keep, descs = [], []
+    for P in probs:
+        if P.kind == "lse":
+            t = tuple(lsq.colmajor(a) for a in (P.A, P.B, P.b, P.d))
+            x = lsq.empty(P.shape[1])
+            descs.append(lsq.make_problem("lse", t, x))
+            keep.append((t, x))
+        else:
+            t = tuple(lsq.colmajor(a) for a in (P.W, P.V, P.d))
+            x, y = lsq.empty(P.shape[1]), lsq.empty(P.shape[2])
+            descs.append(lsq.make_problem("gls", t, x, y))
+            keep.append((t, x, y))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    h = lsq.Handle()
+    h.lib.lsq_set_batch_workers(h.h, args.workers)
+
+    def run(opts, steps, warmup):
+        for _ in range(warmup):
+            h.lsq_solve_batched(descs, opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ok, rungs = 0, {}
+        for _ in range(steps):
+            rc, res = h.lsq_solve_batched(descs, opts)
+            for r in res:
+                if r.info == 0 and r.berr_max <= 1e-14:
+                    ok += 1
+                d = r.as_dict()
+                key = f"{d['prec_used']}/{d['solver_used']}"
+                rungs[key] = rungs.get(key, 0) + 1
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1, ok, rungs
+
+    from paper_2406_16499_amd import selector as sel
+    have_sel = os.path.exists(sel.WEIGHTS_PATH)
+    # the selector picks the starting rung (AUTO); the plain ladder starts at BF16
+    auto = lsq.default_opts(prec="auto", solver="auto", escalate=1)
+    dt, ok, rungs = run(auto, args.steps, args.warmup)
+    dtl, okl, rungsl = run(lsq.default_opts(prec="bf16", solver="ir", escalate=1), args.steps, args.warmup)
+    dt64, ok64, _ = run(lsq.default_opts(prec="fp64", solver="direct"), args.steps, args.warmup)
+    value = ok / dt
+    value64 = ok64 / dt64
+    line = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (residuals, updates) / selector-chosen factorization precision",
+        "data": "synthetic",
+        "config": {"workload": BATCH_WORKLOAD, "count": args.count,
+                   "selector": "learned" if have_sel else "none (AUTO = FP32 + IR)",
+                   "workers": args.workers, "tol": 1e-14},
+        "fp64_direct": {"value": value64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / args.steps},
+        "plain_ladder_from_bf16": {"value": okl / dtl, "unit": "solves/s",
+                                   "ms_per_step": 1000.0 * dtl / args.steps, "rungs_used": rungsl},
+        "speedup_vs_fp64": value / value64 if value64 > 0 else None,
+        "certified_fraction": ok / (args.count * args.steps),
+        "rungs_used": rungs,
+        "generation_s": gen_s,
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +226,8 @@ def main():
               "(the batched path would shard instances across GPUs, see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return batched(args)
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl

@@ -143,9 +143,38 @@ typedef struct {
 /* Solve `count` independent instances of uneven size.  `res` (host array of
    `count`, nullable) receives one record per instance.  Returns the number of
    instances with info != 0, or -k for an invalid argument (-3: a problem
-   descriptor is invalid). */
+   descriptor is invalid).  The instances run concurrently on the handle's
+   batch workers (streams of their own, one host thread each; see
+   lsq_set_batch_workers), longest estimated factorization first; work already
+   queued on the handle's stream completes before the first instance starts,
+   and every instance has finished when the call returns. */
 int lsq_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
                       const lsq_opts* opts, lsq_result* res);
+/* Learned precision / solver selector (used when opts.prec is LSQ_PREC_AUTO
+   or opts.solver is LSQ_SOLVER_AUTO; without weights AUTO means FP32 with
+   classical IR).  An instance's features come from FP64 norms of its inputs
+   and the diagonals of the triangles of its FP64 generalized factorization
+   (Section 3), whose factors are kept when the selector picks FP64; an MLP
+   16 -> 64 -> 64 -> 7 (ReLU, FP32) gives 5 precision logits {FP8-e4m3, BF16,
+   FP16, FP32, FP64 direct} and 2 solver logits {IR, GMRES-IR}; the escalation
+   ladder then starts at the chosen rung.
+   lsq_selector_set copies LSQ_SELECTOR_WEIGHTS floats (host) in the order
+   mean[16], std[16], W1[64][16], b1[64], W2[64][64], b2[64], W3[7][64], b3[7];
+   NULL removes the selector.  Returns -3 for a wrong count, -2 for
+   non-finite values or non-positive scales.
+   lsq_selector_features computes the 16 features of one instance (host
+   array) and, when weights are set, the 7 logits and the 2 chosen classes
+   (either may be NULL; -4 without weights). */
+#define LSQ_SELECTOR_FEATURES 16
+#define LSQ_SELECTOR_WEIGHTS 5735
+int lsq_selector_set(lsq_handle handle, const float* weights, int count);
+int lsq_selector_features(lsq_handle handle, const lsq_problem* problem, float* feats,
+                          float* logits, int* cls);
+
+/* Number of concurrent workers of the batched entry points (1..64, default
+   8).  Returns -2 outside that range. */
+int lsq_set_batch_workers(lsq_handle handle, int workers);
+
 /* Same-type conveniences: every descriptor must carry the matching type. */
 int lse_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
                       const lsq_opts* opts, lsq_result* res);

@@ -17,7 +17,10 @@
 // solve started from the zero iterate with residual (b, d, 0) resp. (0, d, 0);
 // the drivers compute it that way.  Residuals and updates are FP64.
 #include <algorithm>
+#include <atomic>
 #include <functional>
+#include <memory>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +32,9 @@
 #include "lsq_debug.h"
 
 using namespace lsq;
+
+static_assert(kSelWeights == LSQ_SELECTOR_WEIGHTS, "selector weight layout");
+static_assert(kSelFeatures == LSQ_SELECTOR_FEATURES, "selector feature count");
 
 // --------------------------------------------------------------- arena --
 namespace lsq {
@@ -84,17 +90,61 @@ void ktimer_end(Ctx& ctx, int kind) {
 }
 }  // namespace lsq
 
-struct lsq_handle_st {
+// Everything one solve in flight needs: a stream, a workspace arena, the
+// device stop-test status with its pinned host mirror, and events.  The
+// handle owns one worker on the caller's stream; batched calls add workers
+// with streams of their own, one host thread each.
+struct Worker {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool own_stream = false;
   Arena arena;
   Ctx ctx;
   StopStatus* st_dev = nullptr;
   StopStatus* st_host = nullptr;   // pinned
   double* matnorms = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  KernelTimer timer;
   double* pin = nullptr;           // pinned host scratch (kPinDoubles)
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::string last_error;
+
+  void init(int dev, int num_cu, bool new_stream) {
+    device = dev;
+    if (new_stream) {
+      LSQ_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+      own_stream = true;
+    }
+    ctx.ws = &arena;
+    ctx.stream = stream;
+    ctx.num_cu = num_cu;
+    LSQ_HIP(hipMalloc(&st_dev, sizeof(StopStatus)));
+    LSQ_HIP(hipHostMalloc(&st_host, sizeof(StopStatus), 0));
+    LSQ_HIP(hipHostMalloc(&pin, sizeof(double) * kPinDoubles, 0));
+    ctx.pin = pin;
+    LSQ_HIP(hipMalloc(&matnorms, 8 * sizeof(double)));
+    for (auto& e : ev) LSQ_HIP(hipEventCreate(&e));
+  }
+  void release() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    arena.release();
+    if (st_dev) (void)hipFree(st_dev);
+    if (st_host) (void)hipHostFree(st_host);
+    if (pin) (void)hipHostFree(pin);
+    if (matnorms) (void)hipFree(matnorms);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+    st_dev = nullptr; st_host = nullptr; pin = nullptr; matnorms = nullptr; stream = nullptr;
+  }
+};
+
+struct lsq_handle_st {
+  int device = 0;
+  int num_cu = 256;
+  Worker w;                                     // the handle's own (caller's) stream
+  std::vector<std::unique_ptr<Worker>> pool;    // batched workers
+  int batch_workers = 8;
+  float* sel_w = nullptr;                       // selector weights on the device (null: none)
+  KernelTimer timer;
   std::string last_error;
 };
 
@@ -138,6 +188,8 @@ struct GlsArgs {
 // ----------------------------------------------------------------- LSE ----
 struct LseSolver {
   int m, n, p, k;
+  int prec_id = 0;        // lsq_prec of the factors
+  float ms_factor = 0.0f;
   PrecSpec ps;
   int tc;                 // compute precision of the correction solve
   QRFactor fb, fa;        // QR of Bt (n x p) and of Abar (m x n)
@@ -271,6 +323,8 @@ struct LseSolver {
 // ----------------------------------------------------------------- GLS ----
 struct GlsSolver {
   int n, m, p, k;         // k = n - m
+  int prec_id = 0;        // lsq_prec of the factors
+  float ms_factor = 0.0f;
   PrecSpec ps;
   int tc;
   QRFactor fw, fv;        // QR of W (n x m) and of Vt (p x n)
@@ -429,12 +483,12 @@ struct RungOut {
   float ms_convert = 0, ms_factor = 0, ms_refine = 0;
 };
 
-void read_status(lsq_handle h) {
+void read_status(Worker* h) {
   LSQ_HIP(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(StopStatus), hipMemcpyDeviceToHost, h->stream));
   LSQ_HIP(hipStreamSynchronize(h->stream));
 }
 
-int read_int(lsq_handle h, const int* dptr) {
+int read_int(Worker* h, const int* dptr) {
   int v = 0;
   LSQ_HIP(hipMemcpyAsync(&h->st_host->converged, dptr, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   LSQ_HIP(hipStreamSynchronize(h->stream));
@@ -460,7 +514,7 @@ bool stalled(const std::vector<double>& hist) {
 // Classical refinement (Algorithms 2 and 4): init() adds the initial guess to
 // the zeroed iterate, residual() evaluates the FP64 residual and the stop
 // test on the device, correct() adds one correction.
-RungOut run_classical(lsq_handle h, const std::function<void()>& zero,
+RungOut run_classical(Worker* h, const std::function<void()>& zero,
                       const std::function<void()>& init, const std::function<void()>& residual,
                       const std::function<void()>& correct, const lsq_opts& o) {
   RungOut out;
@@ -492,7 +546,7 @@ RungOut run_classical(lsq_handle h, const std::function<void()>& zero,
 // st = D f, GMRES on M_l F M_r w = M_l st, the correction du = M_r w, and the
 // update undoing D.  ops.scale_in / ops.update hold the problem-specific scalings.
 template <typename Solver, typename Args>
-RungOut run_gmres(lsq_handle h, Solver& sv, const Args& a, int N,
+RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
                   const std::function<void()>& zero, const std::function<void()>& init,
                   const std::function<void()>& residual,
                   const std::function<double()>& alpha0,
@@ -548,19 +602,46 @@ bool gls_gmres_ok(int n, int p) { return n <= p; }
 // One precision of the ladder for LSE: the factorization at prec, then the
 // refinement solvers in order on the same factors (IR: Algorithm 2; GMRES:
 // GMRES-IR; DIRECT: the FP64 factors with the classical loop).
-RungOut lse_rung(lsq_handle h, const LseArgs& a, int prec, const std::vector<int>& solvers,
-                 const lsq_opts& o, double* x, double* r, double* v, int& attempts,
-                 int& solver_used) {
+// Factors an LSE at prec (the generalized RQ of Section 3.1); true if no
+// panel Cholesky broke down.
+bool lse_prefactor(Worker* h, const LseArgs& a, int prec, const lsq_opts& o, LseSolver& sv) {
   Ctx& ctx = h->ctx;
-  LseSolver sv;
   sv.m = a.m; sv.n = a.n; sv.p = a.p; sv.k = a.n - a.p;
+  sv.prec_id = prec;
   prec_spec(prec, sv.ps);
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
   sv.factor(ctx, a.A, a.lda, a.B, a.ldb, default_nb(o));
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
-  int stat_b = read_int(h, sv.fb.status);
-  int stat_a = read_int(h, sv.fa.status);
-  const float ms_factor = elapsed(h->ev[0], h->ev[1]);
+  const int stat_b = read_int(h, sv.fb.status);
+  const int stat_a = read_int(h, sv.fa.status);
+  sv.ms_factor = elapsed(h->ev[0], h->ev[1]);
+  return !(stat_b || stat_a);
+}
+
+bool gls_prefactor(Worker* h, const GlsArgs& a, int prec, const lsq_opts& o, GlsSolver& sv) {
+  Ctx& ctx = h->ctx;
+  sv.n = a.n; sv.m = a.m; sv.p = a.p; sv.k = a.n - a.m;
+  sv.prec_id = prec;
+  prec_spec(prec, sv.ps);
+  LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
+  sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o));
+  LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
+  const int stat_w = read_int(h, sv.fw.status);
+  const int stat_v = read_int(h, sv.fv.status);
+  sv.ms_factor = elapsed(h->ev[0], h->ev[1]);
+  return !(stat_w || stat_v);
+}
+
+RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& solvers,
+                 const lsq_opts& o, double* x, double* r, double* v, int& attempts,
+                 int& solver_used, LseSolver* pre = nullptr, bool pre_ok = true) {
+  Ctx& ctx = h->ctx;
+  LseSolver local;
+  const bool reuse = pre && pre->prec_id == prec;
+  LseSolver& sv = reuse ? *pre : local;
+  const bool ok_factor = reuse ? pre_ok : lse_prefactor(h, a, prec, o, sv);
+  const int stat_a = ok_factor ? 0 : 1, stat_b = 0;
+  const float ms_factor = sv.ms_factor;
   RungOut out;
   if (stat_b || stat_a) {
     out.breakdown = true;
@@ -612,19 +693,16 @@ RungOut lse_rung(lsq_handle h, const LseArgs& a, int prec, const std::vector<int
   return out;
 }
 
-RungOut gls_rung(lsq_handle h, const GlsArgs& a, int prec, const std::vector<int>& solvers,
+RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& solvers,
                  const lsq_opts& o, double* x, double* y, double* z, int& attempts,
-                 int& solver_used) {
+                 int& solver_used, GlsSolver* pre = nullptr, bool pre_ok = true) {
   Ctx& ctx = h->ctx;
-  GlsSolver sv;
-  sv.n = a.n; sv.m = a.m; sv.p = a.p; sv.k = a.n - a.m;
-  prec_spec(prec, sv.ps);
-  LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
-  sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o));
-  LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
-  int stat_w = read_int(h, sv.fw.status);
-  int stat_v = read_int(h, sv.fv.status);
-  const float ms_factor = elapsed(h->ev[0], h->ev[1]);
+  GlsSolver local;
+  const bool reuse = pre && pre->prec_id == prec;
+  GlsSolver& sv = reuse ? *pre : local;
+  const bool ok_factor = reuse ? pre_ok : gls_prefactor(h, a, prec, o, sv);
+  const int stat_w = ok_factor ? 0 : 1, stat_v = 0;
+  const float ms_factor = sv.ms_factor;
   RungOut out;
   if (stat_w || stat_v) {
     out.breakdown = true;
@@ -676,6 +754,54 @@ RungOut gls_rung(lsq_handle h, const GlsArgs& a, int prec, const std::vector<int
   return out;
 }
 
+// Selector input and output for one instance from its BF16 factors: the
+// triangles' diagonal statistics, the features and, with weights, the MLP
+// classes.  host: 16 features, 6 logits (float) then 2 classes (int).
+struct Selection {
+  float feats[kSelFeatures];
+  float logits[kSelOut];
+  int cls[2] = {3, 0};
+};
+
+Selection select_run(Worker* h, int type, int m, int n, int p, const QRFactor& f1, int n1,
+                     const QRFactor& f2, int k2, int n2, const float* sel_w) {
+  Ctx& ctx = h->ctx;
+  float* buf = ctx.ws->get<float>(64);
+  int* cls = ctx.ws->get<int>(2);
+  diag_stats(ctx, f1, 0, n1, buf);
+  diag_stats(ctx, f2, 0, k2, buf + 3);
+  diag_stats(ctx, f2, 0, n2, buf + 6);
+  features(ctx, type, m, n, p, h->matnorms, buf, buf + 3, buf + 6, buf + 16);
+  if (sel_w) mlp_select(ctx, sel_w, buf + 16, buf + 32, cls);
+  LSQ_HIP(hipMemcpyAsync(h->pin, buf, sizeof(float) * 64, hipMemcpyDeviceToHost, h->stream));
+  if (sel_w)
+    LSQ_HIP(hipMemcpyAsync(h->pin + 32, cls, sizeof(int) * 2, hipMemcpyDeviceToHost, h->stream));
+  LSQ_HIP(hipStreamSynchronize(h->stream));
+  Selection out;
+  const float* hb = reinterpret_cast<const float*>(h->pin);
+  for (int i = 0; i < kSelFeatures; ++i) out.feats[i] = hb[16 + i];
+  for (int i = 0; i < kSelOut; ++i) out.logits[i] = sel_w ? hb[32 + i] : 0.0f;
+  if (sel_w) {
+    const int* hc = reinterpret_cast<const int*>(h->pin + 32);
+    out.cls[0] = hc[0];
+    out.cls[1] = hc[1];
+  }
+  return out;
+}
+
+// Precision / solver of a selector class (FP8 runs as BF16, see the ladder).
+int class_prec(int c) {
+  static const int map[kSelPrec] = {LSQ_PREC_FP8E4M3, LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32,
+                                    LSQ_PREC_FP64};
+  return map[c < 0 ? 0 : (c >= kSelPrec ? kSelPrec - 1 : c)];
+}
+// Precision of the factorization the features are taken from; its factors
+// are kept when the selector picks it.  FP64: on the batched workload the
+// trained selector picks the FP64 direct rung for nearly every instance (the
+// small factorizations are latency-bound, so lower precisions save no time).
+constexpr int kSelFactorPrec = LSQ_PREC_FP64;
+int class_solver(int c) { return c == 1 ? LSQ_SOLVER_GMRES_IR : LSQ_SOLVER_IR; }
+
 // Escalation ladder: (precision, refinement solvers on that precision's
 // factors).  Starting at the requested rung: with IR requested, each
 // precision tries classical IR and then GMRES-IR on the same factors; with
@@ -714,22 +840,27 @@ int fail(lsq_handle h, int code, const std::string& msg) {
   return code;
 }
 
-
-int guard(lsq_handle h, const char* fn, const std::function<int()>& body) {
+// Runs body on worker w: selects the device, rewinds w's arena and turns HIP
+// errors into return code 4 with a message in *err.
+int guard_w(Worker* w, std::string* err, const char* fn, const std::function<int()>& body) {
   try {
-    if (h) {
-      LSQ_HIP(hipSetDevice(h->device));
-      h->arena.reset();
-      h->last_error.clear();
-    }
+    LSQ_HIP(hipSetDevice(w->device));
+    w->arena.reset();
     return body();
   } catch (const HipError& e) {
     char buf[256];
     snprintf(buf, sizeof buf, "%s: %s failed: %s", fn, e.where, hipGetErrorString(e.code));
-    return fail(h, 4, buf);
+    if (err) *err = buf;
+    return 4;
   } catch (const std::exception& e) {
-    return fail(h, 4, std::string(fn) + ": " + e.what());
+    if (err) *err = std::string(fn) + ": " + e.what();
+    return 4;
   }
+}
+
+int guard(lsq_handle h, const char* fn, const std::function<int()>& body) {
+  h->last_error.clear();
+  return guard_w(&h->w, &h->last_error, fn, body);
 }
 }  // namespace
 
@@ -759,17 +890,10 @@ int lsq_create(lsq_handle* out, int device) {
   try {
     h->device = device;
     LSQ_HIP(hipSetDevice(device));
-    h->ctx.ws = &h->arena;
-    h->ctx.stream = nullptr;
-    LSQ_HIP(hipMalloc(&h->st_dev, sizeof(StopStatus)));
-    LSQ_HIP(hipHostMalloc(&h->st_host, sizeof(StopStatus), 0));
-    LSQ_HIP(hipHostMalloc(&h->pin, sizeof(double) * kPinDoubles, 0));
-    h->ctx.pin = h->pin;
-    LSQ_HIP(hipMalloc(&h->matnorms, 8 * sizeof(double)));
-    for (auto& e : h->ev) LSQ_HIP(hipEventCreate(&e));
     hipDeviceProp_t prop;
     LSQ_HIP(hipGetDeviceProperties(&prop, device));
-    h->ctx.num_cu = prop.multiProcessorCount;
+    h->num_cu = prop.multiProcessorCount;
+    h->w.init(device, h->num_cu, false);
     LSQ_HIP(hipDeviceSynchronize());
   } catch (const HipError&) {
     lsq_destroy(h);
@@ -783,23 +907,26 @@ int lsq_destroy(lsq_handle h) {
   if (!h) return 0;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
-  h->arena.release();
   for (auto& e : h->timer.ev)
     if (e) (void)hipEventDestroy(e);
-  if (h->st_dev) (void)hipFree(h->st_dev);
-  if (h->st_host) (void)hipHostFree(h->st_host);
-  if (h->pin) (void)hipHostFree(h->pin);
-  if (h->matnorms) (void)hipFree(h->matnorms);
-  for (auto& e : h->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto& wp : h->pool) wp->release();
+  h->w.release();
+  if (h->sel_w) (void)hipFree(h->sel_w);
   delete h;
   return 0;
 }
 
 int lsq_set_stream(lsq_handle h, void* stream) {
   if (!h) return -1;
-  h->stream = static_cast<hipStream_t>(stream);
-  h->ctx.stream = h->stream;
+  h->w.stream = static_cast<hipStream_t>(stream);
+  h->w.ctx.stream = h->w.stream;
+  return 0;
+}
+
+int lsq_set_batch_workers(lsq_handle h, int workers) {
+  if (!h) return -1;
+  if (workers < 1 || workers > 64) return -2;
+  h->batch_workers = workers;
   return 0;
 }
 
@@ -821,48 +948,136 @@ static void fill_result(lsq_result* res, int info, int prec, int solver, int att
   res->ms_refine = ro.ms_refine;
 }
 
+}  // extern "C"
+
+namespace {
+// The ladder for one LSE instance on worker w (arguments already checked).
+int lse_solve_core(Worker* w, int m, int n, int p, const double* A, int lda, const double* B,
+                   int ldb, const double* b, const double* d, double* x, double* r, double* v,
+                   const lsq_opts& o_in, lsq_result* res, const float* sel_w) {
+  Ctx& ctx = w->ctx;
+  LseArgs a{m, n, p, A, B, b, d, lda, ldb};
+  frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, w->matnorms);
+  double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
+  double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
+  double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
+  lsq_opts o = o_in;
+  LseSolver pre;
+  bool have_pre = false, pre_ok = true;
+  if (sel_w && (o.prec == LSQ_PREC_AUTO || o.solver == LSQ_SOLVER_AUTO)) {
+    pre_ok = lse_prefactor(w, a, kSelFactorPrec, o, pre);
+    have_pre = true;
+    const Selection sl = select_run(w, LSQ_LSE, m, n, p, pre.fb, p, pre.fa, n - p, n, sel_w);
+    if (o.prec == LSQ_PREC_AUTO) o.prec = pre_ok ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
+    if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
+  }
+  const auto rungs = ladder(o, lse_gmres_ok(m, n));
+  RungOut ro;
+  int used_p = 0, used_s = 0, attempts = 0, info = 3;
+  for (const auto& [prec, solvers] : rungs) {
+    ro = lse_rung(w, a, prec, solvers, o, xi, ri, vi, attempts, used_s, have_pre ? &pre : nullptr,
+                  pre_ok);
+    used_p = prec;
+    if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
+    if (ro.ok) { info = 0; break; }
+  }
+  if (info != 1) {
+    if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+    if (r && m > 0) LSQ_HIP(hipMemcpyAsync(r, ri, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
+    if (v && p > 0) LSQ_HIP(hipMemcpyAsync(v, vi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
+  }
+  LSQ_HIP(hipStreamSynchronize(w->stream));
+  fill_result(res, info, used_p, used_s, attempts, ro);
+  return info;
+}
+
+int gls_solve_core(Worker* w, int n, int m, int p, const double* W, int ldw, const double* V,
+                   int ldv, const double* d, double* x, double* y, double* z, const lsq_opts& o_in,
+                   lsq_result* res, const float* sel_w) {
+  Ctx& ctx = w->ctx;
+  GlsArgs a{n, m, p, W, V, d, ldw, ldv};
+  frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, w->matnorms);
+  double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
+  double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
+  double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
+  lsq_opts o = o_in;
+  GlsSolver pre;
+  bool have_pre = false, pre_ok = true;
+  if (sel_w && (o.prec == LSQ_PREC_AUTO || o.solver == LSQ_SOLVER_AUTO)) {
+    pre_ok = gls_prefactor(w, a, kSelFactorPrec, o, pre);
+    have_pre = true;
+    const Selection sl = select_run(w, LSQ_GLS, m, n, p, pre.fw, m, pre.fv, n - m, n, sel_w);
+    if (o.prec == LSQ_PREC_AUTO) o.prec = pre_ok ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
+    if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
+  }
+  const auto rungs = ladder(o, gls_gmres_ok(n, p));
+  RungOut ro;
+  int used_p = 0, used_s = 0, attempts = 0, info = 3;
+  for (const auto& [prec, solvers] : rungs) {
+    ro = gls_rung(w, a, prec, solvers, o, xi, yi, zi, attempts, used_s, have_pre ? &pre : nullptr,
+                  pre_ok);
+    used_p = prec;
+    if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
+    if (ro.ok) { info = 0; break; }
+  }
+  if (info != 1) {
+    if (m > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
+    if (p > 0) LSQ_HIP(hipMemcpyAsync(y, yi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
+    if (z && n > 0) LSQ_HIP(hipMemcpyAsync(z, zi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+  }
+  LSQ_HIP(hipStreamSynchronize(w->stream));
+  fill_result(res, info, used_p, used_s, attempts, ro);
+  return info;
+}
+
+int lse_check(int m, int n, int p, const double* A, int lda, const double* B, int ldb,
+              const double* b, const double* d, const double* x, std::string* why) {
+  auto bad = [&](int code, const char* msg) { if (why) *why = msg; return code; };
+  if (m < 0) return bad(-2, "m < 0");
+  if (n < 0 || n > m + p) return bad(-3, "n out of range (p <= n <= m + p)");
+  if (p < 0 || p > n) return bad(-4, "p out of range (p <= n)");
+  if (!A && m * n > 0) return bad(-5, "A is null");
+  if (lda < (m > 1 ? m : 1)) return bad(-6, "lda < max(1, m)");
+  if (!B && p * n > 0) return bad(-7, "B is null");
+  if (ldb < (p > 1 ? p : 1)) return bad(-8, "ldb < max(1, p)");
+  if (!b && m > 0) return bad(-9, "b is null");
+  if (!d && p > 0) return bad(-10, "d is null");
+  if (!x && n > 0) return bad(-11, "x is null");
+  return 0;
+}
+
+int gls_check(int n, int m, int p, const double* W, int ldw, const double* V, int ldv,
+              const double* d, const double* x, const double* y, std::string* why) {
+  auto bad = [&](int code, const char* msg) { if (why) *why = msg; return code; };
+  if (n < 0) return bad(-2, "n < 0");
+  if (m < 0 || m > n) return bad(-3, "m out of range (m <= n)");
+  if (p < 0 || n > m + p) return bad(-4, "p out of range (n <= m + p)");
+  if (!W && n * m > 0) return bad(-5, "W is null");
+  if (ldw < (n > 1 ? n : 1)) return bad(-6, "ldw < max(1, n)");
+  if (!V && n * p > 0) return bad(-7, "V is null");
+  if (ldv < (n > 1 ? n : 1)) return bad(-8, "ldv < max(1, n)");
+  if (!d && n > 0) return bad(-9, "d is null");
+  if (!x && m > 0) return bad(-10, "x is null");
+  if (!y && p > 0) return bad(-11, "y is null");
+  return 0;
+}
+}  // namespace
+
+extern "C" {
+
 int lse_solve(lsq_handle h, int m, int n, int p, const double* A, int lda, const double* B,
               int ldb, const double* b, const double* d, double* x, double* r, double* v,
               const lsq_opts* opts, lsq_result* res) {
   if (!h) return -1;
-  if (m < 0) return fail(h, -2, "m < 0");
-  if (n < 0 || n > m + p) return fail(h, -3, "n out of range (p <= n <= m + p)");
-  if (p < 0 || p > n) return fail(h, -4, "p out of range (p <= n)");
-  if (!A && m * n > 0) return -5;
-  if (lda < (m > 1 ? m : 1)) return -6;
-  if (!B && p * n > 0) return -7;
-  if (ldb < (p > 1 ? p : 1)) return -8;
-  if (!b && m > 0) return -9;
-  if (!d && p > 0) return -10;
-  if (!x && n > 0) return -11;
+  std::string why;
+  const int bad = lse_check(m, n, p, A, lda, B, ldb, b, d, x, &why);
+  if (bad) return fail(h, bad, why);
   lsq_opts o;
   lsq_opts_default(&o);
   if (opts) o = *opts;
-  if (!(o.tol >= 0) || o.maxit < 0) return -14;
+  if (!(o.tol >= 0) || o.maxit < 0) return fail(h, -14, "invalid options");
   return guard(h, "lse_solve", [&]() -> int {
-    Ctx& ctx = h->ctx;
-    LseArgs a{m, n, p, A, B, b, d, lda, ldb};
-    frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, h->matnorms);
-    double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
-    double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
-    double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
-    const auto rungs = ladder(o, lse_gmres_ok(m, n));
-    RungOut ro;
-    int used_p = 0, used_s = 0, attempts = 0, info = 3;
-    for (const auto& [prec, solvers] : rungs) {
-      ro = lse_rung(h, a, prec, solvers, o, xi, ri, vi, attempts, used_s);
-      used_p = prec;
-      if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
-      if (ro.ok) { info = 0; break; }
-    }
-    if (info != 1) {
-      if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-      if (r && m > 0) LSQ_HIP(hipMemcpyAsync(r, ri, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
-      if (v && p > 0) LSQ_HIP(hipMemcpyAsync(v, vi, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
-    }
-    LSQ_HIP(hipStreamSynchronize(h->stream));
-    fill_result(res, info, used_p, used_s, attempts, ro);
-    return info;
+    return lse_solve_core(&h->w, m, n, p, A, lda, B, ldb, b, d, x, r, v, o, res, h->sel_w);
   });
 }
 
@@ -870,68 +1085,158 @@ int gls_solve(lsq_handle h, int n, int m, int p, const double* W, int ldw, const
               int ldv, const double* d, double* x, double* y, double* z, const lsq_opts* opts,
               lsq_result* res) {
   if (!h) return -1;
-  if (n < 0) return fail(h, -2, "n < 0");
-  if (m < 0 || m > n) return fail(h, -3, "m out of range (m <= n)");
-  if (p < 0 || n > m + p) return fail(h, -4, "p out of range (n <= m + p)");
-  if (!W && n * m > 0) return -5;
-  if (ldw < (n > 1 ? n : 1)) return -6;
-  if (!V && n * p > 0) return -7;
-  if (ldv < (n > 1 ? n : 1)) return -8;
-  if (!d && n > 0) return -9;
-  if (!x && m > 0) return -10;
-  if (!y && p > 0) return -11;
+  std::string why;
+  const int bad = gls_check(n, m, p, W, ldw, V, ldv, d, x, y, &why);
+  if (bad) return fail(h, bad, why);
   lsq_opts o;
   lsq_opts_default(&o);
   if (opts) o = *opts;
-  if (!(o.tol >= 0) || o.maxit < 0) return -13;
+  if (!(o.tol >= 0) || o.maxit < 0) return fail(h, -13, "invalid options");
   return guard(h, "gls_solve", [&]() -> int {
-    Ctx& ctx = h->ctx;
-    GlsArgs a{n, m, p, W, V, d, ldw, ldv};
-    frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, h->matnorms);
-    double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
-    double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
-    double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
-    const auto rungs = ladder(o, gls_gmres_ok(n, p));
-    RungOut ro;
-    int used_p = 0, used_s = 0, attempts = 0, info = 3;
-    for (const auto& [prec, solvers] : rungs) {
-      ro = gls_rung(h, a, prec, solvers, o, xi, yi, zi, attempts, used_s);
-      used_p = prec;
-      if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
-      if (ro.ok) { info = 0; break; }
-    }
-    if (info != 1) {
-      if (m > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * m, hipMemcpyDeviceToDevice, h->stream));
-      if (p > 0) LSQ_HIP(hipMemcpyAsync(y, yi, sizeof(double) * p, hipMemcpyDeviceToDevice, h->stream));
-      if (z && n > 0) LSQ_HIP(hipMemcpyAsync(z, zi, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-    }
-    LSQ_HIP(hipStreamSynchronize(h->stream));
-    fill_result(res, info, used_p, used_s, attempts, ro);
-    return info;
+    return gls_solve_core(&h->w, n, m, p, W, ldw, V, ldv, d, x, y, z, o, res, h->sel_w);
   });
 }
 
 int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
                       lsq_result* res) {
   if (!h) return -1;
-  if (count < 0) return -2;
-  if (count > 0 && !probs) return -3;
-  int nfail = 0;
+  if (count < 0) return fail(h, -2, "count < 0");
+  if (count > 0 && !probs) return fail(h, -3, "problem array is null");
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0) return fail(h, -4, "invalid options");
+  std::vector<double> work(count);
   for (int i = 0; i < count; ++i) {
     const lsq_problem& q = probs[i];
-    int info;
+    std::string why;
+    int bad;
     if (q.type == LSQ_LSE)
-      info = lse_solve(h, q.m, q.n, q.p, q.A, q.lda, q.B, q.ldb, q.b, q.d, q.x, nullptr, nullptr,
-                       opts, res ? &res[i] : nullptr);
+      bad = lse_check(q.m, q.n, q.p, q.A, q.lda, q.B, q.ldb, q.b, q.d, q.x, &why);
     else if (q.type == LSQ_GLS)
-      info = gls_solve(h, q.n, q.m, q.p, q.A, q.lda, q.B, q.ldb, q.d, q.x, q.y, nullptr, opts,
-                       res ? &res[i] : nullptr);
+      bad = gls_check(q.n, q.m, q.p, q.A, q.lda, q.B, q.ldb, q.d, q.x, q.y, &why);
     else
-      return -3;
-    if (info < 0) return -3;
-    if (info != 0) ++nfail;
+      bad = -1, why = "unknown problem type";
+    if (bad) return fail(h, -3, "instance " + std::to_string(i) + ": " + why);
+    // factorization flops (Section 3 cost model, leading terms) for the LPT order
+    const double m = q.m, n = q.n, p = q.p;
+    work[i] = q.type == LSQ_LSE ? 2 * m * n * n + 4 * m * n * p + 2 * n * p * p
+                                : 2 * n * m * m + 4 * n * m * p + 2 * p * n * n;
   }
-  return nfail;
+  h->last_error.clear();
+  if (count == 0) return 0;
+  // longest instances first; each worker thread takes the next one
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  const int nw = std::min(h->batch_workers, count);
+  try {
+    LSQ_HIP(hipSetDevice(h->device));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));     // inputs produced on the caller's stream
+    while ((int)h->pool.size() < nw) {
+      auto wp = std::make_unique<Worker>();
+      wp->init(h->device, h->num_cu, true);
+      h->pool.push_back(std::move(wp));
+    }
+  } catch (const HipError& e) {
+    return fail(h, 4, std::string("lsq_solve_batched: ") + e.where + " failed");
+  }
+  std::atomic<int> next{0}, nfail{0};
+  std::vector<std::string> errs(nw);
+  auto run = [&](int t) {
+    Worker* w = h->pool[t].get();
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= count) break;
+      const int i = order[k];
+      const lsq_problem& q = probs[i];
+      lsq_result* ri = res ? &res[i] : nullptr;
+      const int info = guard_w(w, &errs[t], "lsq_solve_batched", [&]() -> int {
+        if (q.type == LSQ_LSE)
+          return lse_solve_core(w, q.m, q.n, q.p, q.A, q.lda, q.B, q.ldb, q.b, q.d, q.x, nullptr,
+                                nullptr, o, ri, h->sel_w);
+        return gls_solve_core(w, q.n, q.m, q.p, q.A, q.lda, q.B, q.ldb, q.d, q.x, q.y, nullptr, o,
+                              ri, h->sel_w);
+      });
+      if (info != 0) {
+        nfail.fetch_add(1);
+        if (ri && info == 4) ri->info = 4;
+      }
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int t = 1; t < nw; ++t) threads.emplace_back(run, t);
+  run(0);
+  for (auto& th : threads) th.join();
+  for (auto& e : errs)
+    if (!e.empty()) { h->last_error = e; break; }
+  return nfail.load();
+}
+
+int lsq_selector_set(lsq_handle h, const float* weights, int count) {
+  if (!h) return -1;
+  if (!weights) {
+    if (h->sel_w) (void)hipFree(h->sel_w);
+    h->sel_w = nullptr;
+    return 0;
+  }
+  if (count != kSelWeights) return fail(h, -3, "selector weight count mismatch");
+  for (int i = 0; i < count; ++i)
+    if (!std::isfinite(weights[i])) return fail(h, -2, "non-finite selector weight");
+  for (int i = 0; i < kSelFeatures; ++i)
+    if (!(weights[kSelFeatures + i] > 0.0f)) return fail(h, -2, "feature scales must be positive");
+  try {
+    LSQ_HIP(hipSetDevice(h->device));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
+    for (auto& wp : h->pool) LSQ_HIP(hipStreamSynchronize(wp->stream));
+    if (!h->sel_w) LSQ_HIP(hipMalloc(&h->sel_w, sizeof(float) * kSelWeights));
+    LSQ_HIP(hipMemcpy(h->sel_w, weights, sizeof(float) * kSelWeights, hipMemcpyHostToDevice));
+  } catch (const HipError& e) {
+    return fail(h, 4, std::string("lsq_selector_set: ") + e.where + " failed");
+  }
+  return 0;
+}
+
+int lsq_selector_features(lsq_handle h, const lsq_problem* q, float* feats, float* logits, int* cls) {
+  if (!h) return -1;
+  if (!q) return -2;
+  if (!feats) return -3;
+  std::string why;
+  int bad;
+  if (q->type == LSQ_LSE)
+    bad = lse_check(q->m, q->n, q->p, q->A, q->lda, q->B, q->ldb, q->b, q->d, q->x, &why);
+  else if (q->type == LSQ_GLS)
+    bad = gls_check(q->n, q->m, q->p, q->A, q->lda, q->B, q->ldb, q->d, q->x, q->y, &why);
+  else
+    bad = -1, why = "unknown problem type";
+  if (bad) return fail(h, -2, why);
+  if ((logits || cls) && !h->sel_w) return fail(h, -4, "no selector weights set");
+  lsq_opts o;
+  lsq_opts_default(&o);
+  return guard(h, "lsq_selector_features", [&]() -> int {
+    Worker* w = &h->w;
+    Selection sl;
+    if (q->type == LSQ_LSE) {
+      LseArgs a{q->m, q->n, q->p, q->A, q->B, q->b, q->d, q->lda, q->ldb};
+      frob_norms(w->ctx, q->A, q->lda, q->m, q->n, q->B, q->ldb, q->p, q->n, q->b, q->m, q->d, q->p,
+                 w->matnorms);
+      LseSolver sv;
+      lse_prefactor(w, a, kSelFactorPrec, o, sv);
+      sl = select_run(w, LSQ_LSE, q->m, q->n, q->p, sv.fb, q->p, sv.fa, q->n - q->p, q->n, h->sel_w);
+    } else {
+      GlsArgs a{q->n, q->m, q->p, q->A, q->B, q->d, q->lda, q->ldb};
+      frob_norms(w->ctx, q->A, q->lda, q->n, q->m, q->B, q->ldb, q->n, q->p, q->d, q->n, nullptr, 0,
+                 w->matnorms);
+      GlsSolver sv;
+      gls_prefactor(w, a, kSelFactorPrec, o, sv);
+      sl = select_run(w, LSQ_GLS, q->m, q->n, q->p, sv.fw, q->m, sv.fv, q->n - q->m, q->n, h->sel_w);
+    }
+    for (int i = 0; i < kSelFeatures; ++i) feats[i] = sl.feats[i];
+    if (logits)
+      for (int i = 0; i < kSelOut; ++i) logits[i] = sl.logits[i];
+    if (cls) { cls[0] = sl.cls[0]; cls[1] = sl.cls[1]; }
+    return 0;
+  });
 }
 
 int lse_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
@@ -959,7 +1264,7 @@ int lsq_dbg_qr(lsq_handle h, int prec, int r, int c, const double* M, int ldm, c
   if (!M || ldm < (r > 1 ? r : 1)) return -5;
   if (nx > 0 && (!X || ldx < r)) return -7;
   return guard(h, "lsq_dbg_qr", [&]() -> int {
-    Ctx& ctx = h->ctx;
+    Ctx& ctx = h->w.ctx;
     QRFactor f;
     qr_alloc(ctx, f, r, c, ps.tw, ps.mt, kMaxNb);
     mat_convert(ctx, f.M, ps.tw, f.ld, M, 8, ldm, r, c, false, false, false);
@@ -969,12 +1274,12 @@ int lsq_dbg_qr(lsq_handle h, int prec, int r, int c, const double* M, int ldm, c
       mat_convert(ctx, tmp, 8, r, f.M, ps.tw, f.ld, r, c, false, false, false);
       // keep the upper trapezoid of the first k rows
       std::vector<double> host((size_t)r * c);
-      LSQ_HIP(hipMemcpyAsync(host.data(), tmp, host.size() * 8, hipMemcpyDeviceToHost, h->stream));
-      LSQ_HIP(hipStreamSynchronize(h->stream));
+      LSQ_HIP(hipMemcpyAsync(host.data(), tmp, host.size() * 8, hipMemcpyDeviceToHost, h->w.stream));
+      LSQ_HIP(hipStreamSynchronize(h->w.stream));
       std::vector<double> rk((size_t)f.k * c, 0.0);
       for (int j = 0; j < c; ++j)
         for (int i = 0; i < f.k && i <= j; ++i) rk[i + (size_t)j * f.k] = host[i + (size_t)j * r];
-      LSQ_HIP(hipMemcpyAsync(R, rk.data(), rk.size() * 8, hipMemcpyHostToDevice, h->stream));
+      LSQ_HIP(hipMemcpyAsync(R, rk.data(), rk.size() * 8, hipMemcpyHostToDevice, h->w.stream));
     }
     if (nx > 0) {
       void* Xw = ctx.ws->alloc((size_t)ps.tw * r * nx);
@@ -997,7 +1302,7 @@ int lsq_dbg_qr(lsq_handle h, int prec, int r, int c, const double* M, int ldm, c
         }
       }
     }
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     int st = 0;
     LSQ_HIP(hipMemcpy(&st, f.status, sizeof(int), hipMemcpyDeviceToHost));
     return st ? 1 : 0;
@@ -1012,7 +1317,7 @@ int lsq_dbg_trsv(lsq_handle h, int prec, int tc64, int n, const double* U, int l
   if (n < 0) return -4;
   if (!U || ldu < (n > 1 ? n : 1)) return -5;
   return guard(h, "lsq_dbg_trsv", [&]() -> int {
-    Ctx& ctx = h->ctx;
+    Ctx& ctx = h->w.ctx;
     QRFactor f;
     f.r = f.c = f.k = n; f.ld = n > 1 ? n : 1; f.tw = ps.tw; f.mt = ps.mt;
     f.M = ctx.ws->alloc((size_t)ps.tw * f.ld * (n > 0 ? n : 1));
@@ -1024,14 +1329,14 @@ int lsq_dbg_trsv(lsq_handle h, int prec, int tc64, int n, const double* U, int l
     vec_convert(ctx, w, tc, b, 8, n, false);
     trsv(ctx, tb, trans != 0, w);
     vec_convert(ctx, x, 8, w, tc, n, false);
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }
 
 static void status_out(lsq_handle h, double* out) {
-  read_status(h);
-  const StopStatus& s = *h->st_host;
+  read_status(&h->w);
+  const StopStatus& s = *h->w.st_host;
   for (int q = 0; q < 3; ++q) {
     out[q] = s.nf[q];
     out[3 + q] = s.scale[q];
@@ -1046,12 +1351,12 @@ int lsq_dbg_lse_residual(lsq_handle h, int m, int n, int p, const double* A, int
                          double* f2, double* f3, double* out) {
   if (!h) return -1;
   return guard(h, "lsq_dbg_lse_residual", [&]() -> int {
-    Ctx& ctx = h->ctx;
-    frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, h->matnorms);
-    lse_residual(ctx, m, n, p, A, lda, B, ldb, b, d, x, r, v, f1, f2, f3, h->matnorms, 1e-14,
-                 h->st_dev);
+    Ctx& ctx = h->w.ctx;
+    frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, h->w.matnorms);
+    lse_residual(ctx, m, n, p, A, lda, B, ldb, b, d, x, r, v, f1, f2, f3, h->w.matnorms, 1e-14,
+                 h->w.st_dev);
     if (out) status_out(h, out);
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }
@@ -1062,12 +1367,12 @@ int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* W, int
                          double* out) {
   if (!h) return -1;
   return guard(h, "lsq_dbg_gls_residual", [&]() -> int {
-    Ctx& ctx = h->ctx;
-    frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, h->matnorms);
-    gls_residual(ctx, n, m, p, W, ldw, V, ldv, d, x, y, z, f1, f2, f3, h->matnorms, 1e-14,
-                 h->st_dev);
+    Ctx& ctx = h->w.ctx;
+    frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, h->w.matnorms);
+    gls_residual(ctx, n, m, p, W, ldw, V, ldv, d, x, y, z, f1, f2, f3, h->w.matnorms, 1e-14,
+                 h->w.st_dev);
     if (out) status_out(h, out);
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }
@@ -1080,7 +1385,7 @@ int lsq_dbg_lse_correction(lsq_handle h, int prec, int m, int n, int p, const do
   if (!prec_spec(prec, ps)) return -2;
   if (m < 0 || n < 0 || p < 0 || p > n || n > m + p) return -3;
   return guard(h, "lsq_dbg_lse_correction", [&]() -> int {
-    Ctx& ctx = h->ctx;
+    Ctx& ctx = h->w.ctx;
     LseSolver sv;
     sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
     sv.factor(ctx, A, lda, B, ldb, kMaxNb);
@@ -1089,7 +1394,7 @@ int lsq_dbg_lse_correction(lsq_handle h, int prec, int m, int n, int p, const do
     vec_zero(ctx, dv, 8, p);
     vec_zero(ctx, dx, 8, n);
     sv.correct(ctx, f1, f2, f3, dx, dr, dv);
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }
@@ -1102,7 +1407,7 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
   if (!prec_spec(prec, ps)) return -2;
   if (m < 0 || n < 0 || p < 0 || m > n || n > m + p) return -3;
   return guard(h, "lsq_dbg_gls_correction", [&]() -> int {
-    Ctx& ctx = h->ctx;
+    Ctx& ctx = h->w.ctx;
     GlsSolver sv;
     sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.ps = ps;
     sv.factor(ctx, W, ldw, V, ldv, kMaxNb);
@@ -1111,7 +1416,7 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
     vec_zero(ctx, dz, 8, n);
     vec_zero(ctx, dx, 8, m);
     sv.correct(ctx, f1, f2, f3, dx, dy, dz);
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }
@@ -1123,16 +1428,16 @@ static const char* const kKernelNames[kKCount] = {"panel_final_y", "panel_cholpa
 int lsq_dbg_timer_enable(lsq_handle h, const char* kernel) {
   if (!h) return -1;
   return guard(h, "lsq_dbg_timer_enable", [&]() -> int {
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     h->timer.used = 0;
     h->timer.flops = h->timer.bytes = 0.0;
     h->timer.target = -1;
-    h->ctx.timer = nullptr;
+    h->w.ctx.timer = nullptr;
     if (!kernel || !kernel[0]) return 0;
     for (int k = 0; k < kKCount; ++k)
       if (std::strcmp(kernel, kKernelNames[k]) == 0) h->timer.target = k;
     if (h->timer.target < 0) return fail(h, -2, std::string("unknown kernel name ") + kernel);
-    h->ctx.timer = &h->timer;
+    h->w.ctx.timer = &h->timer;
     return 0;
   });
 }
@@ -1140,7 +1445,7 @@ int lsq_dbg_timer_enable(lsq_handle h, const char* kernel) {
 int lsq_dbg_timer_read(lsq_handle h, double* total_ms, int* launches, double* flops, double* bytes) {
   if (!h) return -1;
   return guard(h, "lsq_dbg_timer_read", [&]() -> int {
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     double tot = 0.0;
     for (int q = 0; q < h->timer.used; ++q) {
       float ms = 0.0f;
@@ -1162,8 +1467,8 @@ int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes) {
   if (bytes < 0) return -4;
   if (bytes > 0 && (!dst || !src)) return -2;
   return guard(h, "lsq_dbg_copy", [&]() -> int {
-    dev_copy(h->ctx, dst, src, (size_t)bytes);
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    dev_copy(h->w.ctx, dst, src, (size_t)bytes);
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }
@@ -1180,7 +1485,7 @@ int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, cons
   if (type == LSQ_GLS && !(m <= n && n <= m + p && gls_gmres_ok(n, p))) return -4;
   if (!(alpha > 0) || !(beta > 0)) return -11;
   return guard(h, "lsq_dbg_bd_apply", [&]() -> int {
-    Ctx& ctx = h->ctx;
+    Ctx& ctx = h->w.ctx;
     if (type == LSQ_LSE) {
       LseSolver sv;
       sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
@@ -1202,7 +1507,7 @@ int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, cons
       sv.f_apply(ctx, a, sv.t1, sv.t2);
       sv.m_left(ctx, sv.t2, y);
     }
-    LSQ_HIP(hipStreamSynchronize(h->stream));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
 }

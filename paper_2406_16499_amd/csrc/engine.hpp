@@ -184,4 +184,15 @@ struct GmresOut {
 GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
                const double* rhs, double* x, int restart, double tol, int maxit);
 
+// ------------------------------------------------------------ selector ----
+constexpr int kSelFeatures = 16, kSelHidden = 64, kSelOut = 7, kSelPrec = 5;
+constexpr int kSelWeights = 2 * kSelFeatures + kSelHidden * kSelFeatures + kSelHidden +
+                            kSelHidden * kSelHidden + kSelHidden + kSelOut * kSelHidden + kSelOut;
+// out[0..2] = log10 max |d_i|, log10 min |d_i|, mean log10 |d_i| of diag f.M[o:o+nn, o:o+nn]
+void diag_stats(Ctx& ctx, const QRFactor& f, int o, int nn, float* out);
+void features(Ctx& ctx, int type, int m, int n, int p, const double* matnorms, const float* st1,
+              const float* st2, const float* st3, float* feats);
+// logits (7) and cls = {precision class 0..4, solver class 0..1}
+void mlp_select(Ctx& ctx, const float* weights, const float* feats, float* logits, int* cls);
+
 }  // namespace lsq

@@ -68,6 +68,10 @@ _SIGS = {
                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
     "lsq_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                   ctypes.POINTER(Result)]),
+    "lsq_set_batch_workers": (c_int, [_P, c_int]),
+    "lsq_selector_set": (c_int, [_P, ctypes.POINTER(c_float), c_int]),
+    "lsq_selector_features": (c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(c_float),
+                                      ctypes.POINTER(c_float), ctypes.POINTER(c_int)]),
     "lse_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                   ctypes.POINTER(Result)]),
     "gls_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
@@ -181,7 +185,7 @@ def _ld(t):
 class Handle:
     """Owns an lsq_handle bound to the current torch device and stream."""
 
-    def __init__(self, device: Optional[int] = None):
+    def __init__(self, device: Optional[int] = None, load_selector: bool = True):
         torch = _torch()
         self.lib = load()
         dev = torch.cuda.current_device() if device is None else device
@@ -191,6 +195,31 @@ class Handle:
             raise RuntimeError(f"lsq_create failed ({rc})")
         self.h = h
         self.sync_stream()
+        if load_selector:
+            from . import selector
+            if os.path.exists(selector.WEIGHTS_PATH):
+                self.selector_set(selector.load())
+
+    def selector_set(self, weights):
+        """Install selector weights (LSQ_SELECTOR_WEIGHTS floats) or remove them (None)."""
+        if weights is None:
+            rc = self.lib.lsq_selector_set(self.h, None, 0)
+        else:
+            w = np.ascontiguousarray(weights, dtype=np.float32)
+            rc = self.lib.lsq_selector_set(self.h, w.ctypes.data_as(ctypes.POINTER(c_float)), w.size)
+        if rc != 0:
+            raise RuntimeError(f"lsq_selector_set = {rc}: {self.last_error()}")
+
+    def selector_features(self, desc, with_logits=False):
+        """(features[16], logits[7] or None, classes[2] or None) of one instance descriptor."""
+        f = (c_float * 16)()
+        lo = (c_float * 7)() if with_logits else None
+        cl = (c_int * 2)() if with_logits else None
+        rc = self.lib.lsq_selector_features(self.h, ctypes.byref(desc), f, lo, cl)
+        if rc != 0:
+            raise RuntimeError(f"lsq_selector_features = {rc}: {self.last_error()}")
+        return (np.array(f, np.float32), None if lo is None else np.array(lo, np.float32),
+                None if cl is None else list(cl))
 
     def sync_stream(self):
         torch = _torch()

@@ -68,6 +68,16 @@ void Arena::release() {
   cur_ = 0;
 }
 
+hipEvent_t ctx_event(Ctx& ctx, int i) {
+  auto& pool = *ctx.events;
+  while ((int)pool.size() <= i) {
+    hipEvent_t e = nullptr;
+    LSQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    pool.push_back(e);
+  }
+  return pool[i];
+}
+
 void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes) {
   KernelTimer* t = ctx.timer;
   if (!t || t->target != kind) return;
@@ -105,6 +115,8 @@ struct Worker {
   double* matnorms = nullptr;
   double* pin = nullptr;           // pinned host scratch (kPinDoubles)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipStream_t side = nullptr;      // look-ahead stream (default priority)
+  std::vector<hipEvent_t> events;
   std::string last_error;
 
   void init(int dev, int num_cu, bool new_stream) {
@@ -113,8 +125,11 @@ struct Worker {
       LSQ_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
       own_stream = true;
     }
+    LSQ_HIP(hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
     ctx.ws = &arena;
     ctx.stream = stream;
+    ctx.side = side;
+    ctx.events = &events;
     ctx.num_cu = num_cu;
     LSQ_HIP(hipMalloc(&st_dev, sizeof(StopStatus)));
     LSQ_HIP(hipHostMalloc(&st_host, sizeof(StopStatus), 0));
@@ -132,6 +147,14 @@ struct Worker {
     if (matnorms) (void)hipFree(matnorms);
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
+    for (auto& e : events)
+      if (e) (void)hipEventDestroy(e);
+    events.clear();
+    if (side) {
+      (void)hipStreamSynchronize(side);
+      (void)hipStreamDestroy(side);
+      side = nullptr;
+    }
     if (own_stream && stream) (void)hipStreamDestroy(stream);
     st_dev = nullptr; st_host = nullptr; pin = nullptr; matnorms = nullptr; stream = nullptr;
   }

@@ -42,11 +42,20 @@ constexpr int kPinDoubles = 8192;   // size of the pinned host scratch of a cont
 
 struct Ctx {
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;        // second stream for look-ahead updates (null: none)
   Arena* ws = nullptr;
   int num_cu = 256;
   KernelTimer* timer = nullptr;
   double* pin = nullptr;             // pinned host scratch (kPinDoubles)
+  std::vector<hipEvent_t>* events = nullptr;   // pool of timing-free events
+  // Look-ahead in the blocked QR (next panel's columns first, the rest on the
+  // side stream).  Off: on the 4096 x 2048 factorization the concurrent
+  // trailing updates slowed the latency-bound panel kernels more than the
+  // overlap saved (12.7 vs 12.4 ms per FP32 solve).
+  bool lookahead = false;
 };
+// The i-th event of the context's pool (created on first use).
+hipEvent_t ctx_event(Ctx& ctx, int i);
 
 // Brackets one launch of kind `kind`; does nothing unless the timer targets it.
 void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes);

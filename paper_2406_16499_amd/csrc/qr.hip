@@ -27,9 +27,16 @@ constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
 // ---------------------------------------------------------------------------
 // Gram accumulation: G (upper triangle, column-major ld 64) += tile^T tile for
 // the 64 x 64 FP64 LDS tile (columns >= jb are zero).  FP64 MFMA, then FP64
-// atomics from the upper quadrants.
+// atomics from the upper quadrants into one of kGramCopies copies of G
+// (chosen by the work-group), which the readers sum.  More copies divide the
+// atomic contention but multiply the readers' traffic; on the 4096-row
+// panels one copy measured fastest.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gram_atomic(const double* tile, int jb, double* __restrict__ G) {
+constexpr int kGramCopies = 1;
+constexpr int kGramStride = kGramCopies * 4096;   // doubles per Gram accumulator
+
+__device__ __forceinline__ void gram_atomic(const double* tile, int jb, double* __restrict__ Gbase) {
+  double* __restrict__ G = Gbase + (size_t)((blockIdx.x + blockIdx.y) % kGramCopies) * 4096;
   f64x4 acc[2][2];
   mm64_acc(tile, true, tile, acc);
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
@@ -65,7 +72,15 @@ __global__ __launch_bounds__(256) void k_panel_gram(const Tin* __restrict__ X, i
 // beyond jb.  sigma = 11 (mr jb + jb (jb + 1)) u tr(G).
 __device__ __forceinline__ void load_gram(const double* Gin, int jb, int mr, int shift, double* S,
                                           double* red) {
-  wg_load_sym(Gin, S);
+  for (int e = threadIdx.x; e < 4096; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    const int src = (i <= j) ? i + j * 64 : j + i * 64;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < kGramCopies; ++c) v += Gin[(size_t)c * 4096 + src];
+    S[i * kLdt + j] = v;
+  }
+  __syncthreads();
   if (shift) {
     double tr = 0.0;
     for (int i = threadIdx.x; i < jb; i += 256) tr += S[i * kLdt + i];
@@ -136,12 +151,13 @@ __global__ __launch_bounds__(256) void k_panel_cholpass(
 // Mmat = R2^{-1} V^T and T = -U S W^T are plain products.  Every work-group
 // computes the 64 x 64 part (identically); work-group 0 writes R, L1, T and
 // Racc, and each work-group writes Y = Q1 Mmat and Yhat = Y T^T of its rows.
-template <typename Tw>
+template <typename Tw, typename Acc>
 __global__ __launch_bounds__(256) void k_panel_final_y(
     const double* __restrict__ Gin, int jb, int mr,
     const double* __restrict__ Q1, int ldq,           // FP64 panel basis before the last pass
     double* __restrict__ Racc, Tw* __restrict__ Mst, int ldm, int j0,
-    Tw* __restrict__ Tout, Tw* __restrict__ Yhat, int ldy, int* __restrict__ status) {
+    Tw* __restrict__ Tout, Tw* __restrict__ Yhat, int ldy, int* __restrict__ status,
+    const Tw* __restrict__ Cn, int ncn, Acc* __restrict__ Wpart) {
   __shared__ double A0[64 * kLdt];     // U rows (published step by step), then -U S, then T
   __shared__ double A1[64 * kLdt];     // R2^{-1}, then W^T, then the Y tile
   __shared__ double A2[64 * kLdt];     // scratch, V^T -> Mmat, then T^T
@@ -282,6 +298,18 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
     A2[j * kLdt + i] = A0[i * kLdt + j];               // A2 = T^T (Mmat no longer needed)
   }
   __syncthreads();
+  if (Wpart) {
+    // look-ahead: this tile's share of W = Y^T C for the next ncn columns
+    // (C = Cn, rows of the panel), reduced over the tiles by k_wy_reduce
+    for (int e = t; e < 4096; e += 256) {
+      const int i = e & 63, c = e >> 6;
+      A3[i * kLdt + c] = (rb + i < mr && c < ncn) ? (double)Cn[(size_t)(rb + i) + (size_t)c * ldm] : 0.0;
+    }
+    __syncthreads();
+    wg_matmul(A1, A3, A0, true);
+    for (int e = t; e < 64 * ncn; e += 256)
+      Wpart[(size_t)blockIdx.x * 64 * ncn + e] = (Acc)A0[(e & 63) * kLdt + (e >> 6)];
+  }
   wg_matmul(A1, A2, A1);
   for (int e = t; e < 4096; e += 256) {
     const int i = e & 63, j = e >> 6, row = rb + i;
@@ -364,7 +392,8 @@ __device__ __forceinline__ void mma_block(const typename MmaT<MT>::In* As,
 }
 
 // W partial: Wpart[s] (64 x nc, ld 64) = Y^T C over rows [s*kch, (s+1)*kch) of the panel.
-// Y is read from the factor storage with the unit-lower mask.
+// Y is read from the factor storage with the unit-lower mask.  The next
+// 32-row chunk is fetched into registers while the MFMAs of the current one run.
 template <typename Tw, Mma MT>
 __global__ __launch_bounds__(256) void k_wy_t(
     const Tw* __restrict__ Y, int ldy, int mr, int jb,      // Y = &M[j0 + j0*ld]
@@ -386,26 +415,29 @@ __global__ __launch_bounds__(256) void k_wy_t(
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+  double ya[8], cb[8];
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q, kk = e & (BK - 1), a = e / BK, i = k + kk;
+      double y = 0.0, c = 0.0;
+      if (i < kend && a < jb) y = i > a ? (double)Y[(size_t)i + (size_t)a * ldy] : (i == a ? 1.0 : 0.0);
+      if (i < kend && c0 + a < nc) c = (double)C[(size_t)i + (size_t)(c0 + a) * ldc];
+      ya[q] = y;
+      cb[q] = c;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
   for (int k = kbeg; k < kend; k += BK) {
     __syncthreads();
-    for (int e = t; e < 64 * BK; e += 256) {
-      const int kk = e % BK, a = e / BK;
-      const int i = k + kk;
-      double v = 0.0;
-      if (i < kend && a < jb) {
-        if (i > a) v = (double)Y[(size_t)i + (size_t)a * ldy];
-        else if (i == a) v = 1.0;
-      }
-      As[a * LD + kk] = T::cvt(v);
-    }
-    for (int e = t; e < 64 * BK; e += 256) {
-      const int kk = e % BK, c = e / BK;
-      const int i = k + kk;
-      double v = 0.0;
-      if (i < kend && c0 + c < nc) v = (double)C[(size_t)i + (size_t)(c0 + c) * ldc];
-      Bs[c * LD + kk] = T::cvt(v);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q, kk = e & (BK - 1), a = e / BK;
+      As[a * LD + kk] = T::cvt(ya[q]);
+      Bs[a * LD + kk] = T::cvt(cb[q]);
     }
     __syncthreads();
+    if (k + BK < kend) fetch(k + BK);
     mma_block<MT, BK>(As, Bs, acc);
   }
   const int l = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
@@ -430,9 +462,11 @@ __global__ void k_wy_reduce(const Acc* __restrict__ Wpart, int nsplit, int total
   W[e] = s;
 }
 
-// C (mr x nc) -= Yhat (mr x jb) * W (jb x nc).  With Gnext, the work-groups of
-// the first column tile below the first 64 rows also accumulate the Gram of the
-// updated tile (its first jbn columns), which is the next panel's first Gram.
+// C (mr x nc) -= Yhat (mr x jb) * W (jb x nc).  The C tile is read and
+// written with row-contiguous accesses through LDS (fetched into registers
+// before the MFMAs).  With Gnext, the work-groups of the first column tile
+// below the first 64 rows also accumulate the Gram of the updated tile (its
+// first jbn columns): the next panel's first Gram.
 template <typename Tw, Mma MT>
 __global__ __launch_bounds__(256) void k_wy_u(
     const Tw* __restrict__ Yhat, int ldy, int mr, int jb,
@@ -446,8 +480,15 @@ __global__ __launch_bounds__(256) void k_wy_u(
   __shared__ __attribute__((aligned(16))) char smem[kOps > kTile ? kOps : kTile];
   In* As = reinterpret_cast<In*>(smem);
   In* Bs = As + 64 * LD;
+  double* tile = reinterpret_cast<double*>(smem);
   const int t = threadIdx.x;
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  double cv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + 256 * q, i = e & 63, c = e >> 6;
+    cv[q] = (r0 + i < mr && c0 + c < nc) ? (double)C[(size_t)(r0 + i) + (size_t)(c0 + c) * ldc] : 0.0;
+  }
   for (int e = t; e < 64 * 64; e += 256) {
     const int i = e & 63, a = e >> 6;
     double v = (r0 + i < mr && a < jb) ? (double)Yhat[(size_t)(r0 + i) + (size_t)a * ldy] : 0.0;
@@ -467,9 +508,13 @@ __global__ __launch_bounds__(256) void k_wy_u(
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
   mma_block<MT, BK>(As, Bs, acc);
-  const bool gram = Gnext != nullptr && blockIdx.y == 0 && blockIdx.x > 0;
-  double* tile = reinterpret_cast<double*>(smem);
-  if (gram) __syncthreads();                       // the tile reuses the operand buffers
+  __syncthreads();                                 // the tile reuses the operand buffers
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + 256 * q, i = e & 63, c = e >> 6;
+    tile[i * kLdt + c] = cv[q];
+  }
+  __syncthreads();
   const int l = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
@@ -478,20 +523,16 @@ __global__ __launch_bounds__(256) void k_wy_u(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int il = 32 * wr + 16 * bi + T::row(l, r), cl = 32 * wc + 16 * bj + (l & 15);
-        const int i = r0 + il, c = c0 + cl;
-        double nv = 0.0;
-        if (i < mr && c < nc) {
-          Tw* p = C + (size_t)i + (size_t)c * ldc;
-          const Tw st = (Tw)((double)*p - (double)acc[bi][bj][r]);
-          *p = st;
-          nv = (double)st;
-        }
-        if (gram) tile[il * kLdt + cl] = (cl < jbn) ? nv : 0.0;
+        double* p = &tile[il * kLdt + cl];
+        *p = (double)(Tw)(*p - (double)acc[bi][bj][r]);
       }
-  if (gram) {
-    __syncthreads();
-    gram_atomic(tile, jbn, Gnext);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + 256 * q, i = e & 63, c = e >> 6;
+    if (r0 + i < mr && c0 + c < nc) C[(size_t)(r0 + i) + (size_t)(c0 + c) * ldc] = (Tw)tile[i * kLdt + c];
   }
+  if (Gnext != nullptr && blockIdx.y == 0 && blockIdx.x > 0) gram_atomic(tile, jbn, Gnext);
 }
 
 // ---------------------------------------------------------------- host side
@@ -547,16 +588,21 @@ static void wy_apply(Ctx& ctx, const Tw* Y, int ldy, int mr, int jb, const Tw* Y
 
 template <typename Tw, Mma MT>
 static void qr_factor_t(Ctx& ctx, QRFactor& f) {
+  using Acc = typename MmaT<MT>::Acc;
   Tw* M = static_cast<Tw*>(f.M);
   Tw* Tb = static_cast<Tw*>(f.T);
   Tw* Yh = static_cast<Tw*>(f.Yhat);
   const int r = f.r, ld = f.ld;
   double* Q0 = ctx.ws->get<double>((size_t)r * 64);
   double* Q1 = ctx.ws->get<double>((size_t)r * 64);
-  // three Gram accumulators per panel, zeroed once
-  double* Gall = ctx.ws->get<double>((size_t)f.np * 3 * 4096);
-  LSQ_HIP(hipMemsetAsync(Gall, 0, sizeof(double) * (size_t)f.np * 3 * 4096, ctx.stream));
+  // three Gram accumulators (kGramCopies copies each) per panel, zeroed once
+  double* Gall = ctx.ws->get<double>((size_t)f.np * 3 * kGramStride);
+  LSQ_HIP(hipMemsetAsync(Gall, 0, sizeof(double) * (size_t)f.np * 3 * kGramStride, ctx.stream));
   double* Racc = ctx.ws->get<double>(4096);
+  const bool lookahead = ctx.lookahead && ctx.side != nullptr && ctx.events != nullptr && f.np > 1;
+  Ctx sctx = ctx;
+  sctx.stream = ctx.side;
+  int side_pending = -1;            // last step whose side-stream update is not yet awaited
   {
     const int jb = f.k < f.nb ? f.k : f.nb;
     hipLaunchKernelGGL((k_panel_gram<Tw>), dim3(ceil_div(r, 64)), dim3(256), 0, ctx.stream,
@@ -567,9 +613,9 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
     const int jb = (f.k - j0) < f.nb ? (f.k - j0) : f.nb;
     const int mr = r - j0;
     const int tiles = ceil_div(mr, 64);
-    double* G0 = Gall + (size_t)j * 3 * 4096;
-    double* G1 = G0 + 4096;
-    double* G2 = G1 + 4096;
+    double* G0 = Gall + (size_t)j * 3 * kGramStride;
+    double* G1 = G0 + kGramStride;
+    double* G2 = G1 + kGramStride;
     Tw* P = M + (size_t)j0 + (size_t)j0 * ld;
     // shifted pass: Q0 = P R0^{-1}, R0 = chol(P^T P + sigma I)
     // algorithmic work of a pass: X R^{-1} and the Gram (2 mr jb^2 each), the
@@ -589,27 +635,56 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
       Qlast = Q1;
       Glast = G2;
     }
+    // Trailing update of columns j0 + jb .. c-1.  With look-ahead, the next
+    // panel's columns are updated on the main stream: W = Y^T C for them is
+    // formed inside the reconstruction kernel (which holds Y), then reduced and
+    // applied together with the next panel's Gram.  The remaining columns are
+    // updated on the side stream, overlapping the next panel's factorization;
+    // that update must finish before the next reconstruction reads the
+    // columns after it.
+    const int nc = f.c - j0 - jb;
+    double* Gnext = nullptr;
+    int jbn = 0;
+    if (j + 1 < f.np) {
+      Gnext = Gall + (size_t)(j + 1) * 3 * kGramStride;
+      jbn = (f.k - j0 - f.nb) < f.nb ? (f.k - j0 - f.nb) : f.nb;
+    }
+    Tw* Ctr = M + (size_t)j0 + (size_t)(j0 + jb) * ld;
+    const bool la = lookahead && j + 1 < f.np && nc > jbn;
+    Acc* Wpart = la ? ctx.ws->get<Acc>((size_t)tiles * 64 * jbn) : nullptr;
+    if (side_pending >= 0) {
+      LSQ_HIP(hipStreamWaitEvent(ctx.stream, ctx_event(ctx, 2 * side_pending + 1), 0));
+      side_pending = -1;
+    }
     // algorithmic work of the reconstruction: Cholesky, LU and the four
     // triangular inverses / products of the 64 x 64 part (11 jb^3 / 3), Y = Q1 Mmat
     // and Yhat = Y T^T (2 mr jb^2 each); bytes: Q1 in, Y and Yhat out
     ktimer_begin(ctx, kKPanelFinal, 4.0 * mr * jb * jb + 11.0 * jb * jb * jb / 3.0,
                  (double)mr * jb * (8 + 2 * sizeof(Tw)));
-    hipLaunchKernelGGL((k_panel_final_y<Tw>), dim3(tiles), dim3(256), 0, ctx.stream,
+    hipLaunchKernelGGL((k_panel_final_y<Tw, Acc>), dim3(tiles), dim3(256), 0, ctx.stream,
                        Glast, jb, mr, Qlast, mr, Racc, M, ld, j0, Tb + (size_t)j * 4096,
-                       Yh + f.yoff[j], mr, f.status);
+                       Yh + f.yoff[j], mr, f.status, (const Tw*)Ctr, la ? jbn : 0, Wpart);
     ktimer_end(ctx, kKPanelFinal);
     LSQ_LAUNCH_CHECK();
-    // trailing update of columns j0 + jb .. c-1, producing the next panel's Gram
-    const int nc = f.c - j0 - jb;
-    double* Gnext = nullptr;
-    int jbn = 0;
-    if (j + 1 < f.np) {
-      Gnext = Gall + (size_t)(j + 1) * 3 * 4096;
-      jbn = (f.k - j0 - f.nb) < f.nb ? (f.k - j0 - f.nb) : f.nb;
+    if (la) {
+      hipEvent_t panel_done = ctx_event(ctx, 2 * j);
+      LSQ_HIP(hipEventRecord(panel_done, ctx.stream));
+      Acc* W = ctx.ws->get<Acc>((size_t)64 * jbn);
+      hipLaunchKernelGGL((k_wy_reduce<Acc>), dim3(ceil_div(64 * jbn, 256)), dim3(256), 0, ctx.stream,
+                         Wpart, tiles, 64 * jbn, W);
+      hipLaunchKernelGGL((k_wy_u<Tw, MT>), dim3(tiles, 1), dim3(256), 0, ctx.stream,
+                         Yh + f.yoff[j], mr, mr, jb, W, Ctr, ld, jbn, Gnext, jbn);
+      LSQ_LAUNCH_CHECK();
+      LSQ_HIP(hipStreamWaitEvent(sctx.stream, panel_done, 0));
+      wy_apply<Tw, MT>(sctx, P, ld, mr, jb, Yh + f.yoff[j], mr, Ctr + (size_t)jbn * ld, ld,
+                       nc - jbn);
+      LSQ_HIP(hipEventRecord(ctx_event(ctx, 2 * j + 1), sctx.stream));
+      side_pending = j;
+    } else {
+      wy_apply<Tw, MT>(ctx, P, ld, mr, jb, Yh + f.yoff[j], mr, Ctr, ld, nc, Gnext, jbn);
     }
-    wy_apply<Tw, MT>(ctx, P, ld, mr, jb, Yh + f.yoff[j], mr,
-                     M + (size_t)j0 + (size_t)(j0 + jb) * ld, ld, nc, Gnext, jbn);
   }
+  if (side_pending >= 0) LSQ_HIP(hipStreamWaitEvent(ctx.stream, ctx_event(ctx, 2 * side_pending + 1), 0));
 }
 
 void qr_factor(Ctx& ctx, QRFactor& f) {

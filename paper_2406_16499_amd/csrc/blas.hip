@@ -4,6 +4,7 @@
 // on another work-group.
 #include "engine.hpp"
 #include "wg64.hpp"
+#include "gemv.hpp"
 
 namespace lsq {
 
@@ -246,86 +247,16 @@ void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
 // 64 rows x 256 columns per work-group; partial row sums added atomically
 // into y, which the caller zeroes.
 template <typename TC>
-__global__ __launch_bounds__(256) void k_trmv_n(const TC* __restrict__ X, int ldx, int nn,
-                                                const TC* __restrict__ x, TC* __restrict__ y) {
-  __shared__ TC part[4][64];
-  const int t = threadIdx.x, i = t & 63, q = t >> 6;
-  const int row = blockIdx.x * 64 + i;
-  const int j0 = blockIdx.y * 256;
-  TC s = 0;
-  if (row < nn) {
-    const int jb = max(j0, row), je = min(nn, j0 + 256);
-    for (int j = jb + q; j < je; j += 4) s += X[(size_t)row + (size_t)j * ldx] * x[j];
-  }
-  part[q][i] = s;
-  __syncthreads();
-  if (t < 64 && row < nn) {
-    const TC v = part[0][t] + part[1][t] + part[2][t] + part[3][t];
-    if (v != (TC)0) atomicAdd(&y[row], v);
-  }
-}
-
-template <typename TC>
-__global__ __launch_bounds__(256) void k_trmv_t(const TC* __restrict__ X, int ldx, int nn,
-                                                const TC* __restrict__ x, TC* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= nn) return;
-  TC s = 0;
-  for (int i = lane; i <= j; i += 64) s += X[(size_t)i + (size_t)j * ldx] * x[i];
-  s = wave_sum(s);
-  if (lane == 0) y[j] = s;
-}
-
-template <typename TC>
 void trmv_dense(Ctx& ctx, const TC* X, int ldx, int nn, bool trans, const TC* x, TC* y) {
   if (nn <= 0) return;
-  if (!trans) {
-    LSQ_HIP(hipMemsetAsync(y, 0, sizeof(TC) * nn, ctx.stream));
-    hipLaunchKernelGGL((k_trmv_n<TC>), dim3(ceil_div(nn, 64), ceil_div(nn, 256)), dim3(256), 0, ctx.stream, X, ldx, nn, x, y);
-  }
+  LSQ_HIP(hipMemsetAsync(y, 0, sizeof(TC) * nn, ctx.stream));
+  if (!trans)
+    gemv_n<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y);
   else
-    hipLaunchKernelGGL((k_trmv_t<TC>), dim3(ceil_div(nn, 4)), dim3(256), 0, ctx.stream, X, ldx, nn, x, y);
+    gemv_t<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y);
   LSQ_LAUNCH_CHECK();
 }
-
 // ---------------------------------------- aggregated reflector application --
-// s = Y^T y over rows [0, rows) for the unit-lower (mask 2) Y with diagonal
-// offset 0; one wave per column of Y.
-template <typename S, typename TC>
-__global__ __launch_bounds__(256) void k_ymv_t(const S* __restrict__ Y, int ldy, int rows, int cols,
-                                               const TC* __restrict__ y, TC* __restrict__ s) {
-  const int lane = threadIdx.x & 63;
-  const int a = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (a >= cols) return;
-  TC acc = 0;
-  if (a < rows && lane == 0) acc = y[a];                 // unit diagonal
-  for (int i = a + 1 + lane; i < rows; i += 64) acc += (TC)Y[(size_t)i + (size_t)a * ldy] * y[i];
-  acc = wave_sum(acc);
-  if (lane == 0) s[a] = acc;
-}
-
-// y -= Y t for the unit-lower Y (rows x cols); 256 rows x 64 columns per
-// work-group, partial sums added atomically.
-template <typename S, typename TC>
-__global__ __launch_bounds__(256) void k_ymv_n(const S* __restrict__ Y, int ldy, int rows, int cols,
-                                               const TC* __restrict__ tv, TC* __restrict__ y) {
-  __shared__ TC ts[64];
-  const int t = threadIdx.x;
-  const int row = blockIdx.x * 256 + t;
-  const int c0 = blockIdx.y * 64;
-  if (t < 64) ts[t] = (c0 + t < cols) ? tv[c0 + t] : (TC)0;
-  __syncthreads();
-  if (row >= rows) return;
-  TC acc = 0;
-  const int cend = min(cols, c0 + 64);
-  for (int a = c0; a < cend; ++a) {
-    if (row > a) acc += (TC)Y[(size_t)row + (size_t)a * ldy] * ts[a - c0];
-    else if (row == a) acc += ts[a - c0];
-  }
-  if (acc != (TC)0) atomicAdd(&y[row], -acc);
-}
-
 // G = striu(Y^T Y) + diag(Y^T Y) / 2 for a unit-lower Y (rows x cols), dense output.
 template <typename TC>
 __global__ void k_ut_fix(TC* G, int ldg, int n) {
@@ -385,11 +316,13 @@ static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
     const int rows = f.r - b.J0;
     const S* Y = static_cast<const S*>(f.M) + (size_t)b.J0 + (size_t)b.J0 * f.ld;
     TC* yy = y + b.J0;
-    hipLaunchKernelGGL((k_ymv_t<S, TC>), dim3(ceil_div(b.w, 4)), dim3(256), 0, ctx.stream, Y, f.ld, rows, b.w, yy, s);
+    // s = Y^T y (unit-lower Y)
+    LSQ_HIP(hipMemsetAsync(s, 0, sizeof(TC) * b.w, ctx.stream));
+    gemv_t<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)1, yy, s);
     // Q^T = I - Y T^T Y^T  -> t = T^T s ;  Q = I - Y T Y^T -> t = T s
     trmv_dense<TC>(ctx, static_cast<const TC*>(b.T), b.w, b.w, trans, s, tv);
-    hipLaunchKernelGGL((k_ymv_n<S, TC>), dim3(ceil_div(rows, 256), ceil_div(b.w, 64)), dim3(256), 0, ctx.stream,
-                       Y, f.ld, rows, b.w, tv, yy);
+    // y -= Y t
+    gemv_n<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)-1, tv, yy);
     LSQ_LAUNCH_CHECK();
   }
 }

@@ -1,0 +1,123 @@
+// Masked skinny GEMV kernels (bandwidth-oriented) for the vector side of the
+// refinement: triangular-inverse products, aggregated reflector application
+// and products with blocks of the triangular factors.
+//
+// A is column-major (lda) in storage type S; vectors and arithmetic in TC.
+// Masks relative to a diagonal offset d (entry (i, j) of the block):
+//   kDense      every entry;
+//   kUpper      entries with i - j <= d (an upper triangle shifted by d);
+//   kUnitLower  entries with i - j > d, and 1 where i - j == d (unit lower).
+// N: y[i] += alpha sum_j op(A)[i][j] x[j]   (one row per thread, 64 columns
+//    per work-group, eight independent accumulators, atomic accumulation);
+// T: s[j] += alpha sum_i op(A)[i][j] y[i]   (rows across the lanes, 16
+//    columns per work-group, one accumulator per column, block reduction).
+// Work-groups whose whole tile is masked out return at once.
+#pragma once
+#include "common.hpp"
+
+namespace lsq {
+
+enum GemvMask : int { kDense = 0, kUpper = 1, kUnitLower = 2 };
+
+template <int MASK, typename TC>
+__device__ __forceinline__ TC gemv_masked(TC a, int i, int j, int d) {
+  if (MASK == kUpper) return (i - j <= d) ? a : (TC)0;
+  if (MASK == kUnitLower) return (i - j > d) ? a : ((i - j == d) ? (TC)1 : (TC)0);
+  return a;
+}
+
+template <typename S, typename TC, int MASK>
+__global__ __launch_bounds__(256) void k_gemv_n(const S* __restrict__ A, int lda, int rows, int cols,
+                                                int d, TC alpha, const TC* __restrict__ x,
+                                                TC* __restrict__ y) {
+  constexpr int CB = 64;
+  __shared__ TC xs[CB];
+  const int t = threadIdx.x;
+  const int r0 = blockIdx.x * 256, c0 = blockIdx.y * CB;
+  const int ce = min(cols, c0 + CB);
+  if (MASK == kUpper && r0 - (ce - 1) > d) return;          // every row below the band
+  if (MASK == kUnitLower && (r0 + 255) - c0 < d) return;     // every row above the band
+  if (t < CB) xs[t] = (c0 + t < cols) ? x[c0 + t] : (TC)0;
+  __syncthreads();
+  const int i = r0 + t;
+  if (i >= rows) return;
+  TC acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = (TC)0;
+  int j = c0;
+  for (; j + 8 <= ce; j += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const TC a = gemv_masked<MASK>((TC)A[(size_t)i + (size_t)(j + u) * lda], i, j + u, d);
+      acc[u] = fma(a, xs[j + u - c0], acc[u]);
+    }
+  }
+  for (; j < ce; ++j) {
+    const TC a = gemv_masked<MASK>((TC)A[(size_t)i + (size_t)j * lda], i, j, d);
+    acc[0] = fma(a, xs[j - c0], acc[0]);
+  }
+  const TC s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  if (s != (TC)0) atomicAdd(&y[i], alpha * s);
+}
+
+template <typename S, typename TC, int MASK>
+__global__ __launch_bounds__(256) void k_gemv_t(const S* __restrict__ A, int lda, int rows, int cols,
+                                                int d, TC alpha, const TC* __restrict__ yv,
+                                                TC* __restrict__ s, int rows_per_block) {
+  constexpr int NC = 16;
+  __shared__ TC red[4][NC];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int c0 = blockIdx.x * NC;
+  const int rb = blockIdx.y * rows_per_block, re = min(rows, rb + rows_per_block);
+  const int cl = min(cols, c0 + NC) - 1;
+  if (MASK == kUpper && rb - cl > d) return;
+  if (MASK == kUnitLower && (re - 1) - c0 < d) return;
+  TC acc[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) acc[u] = (TC)0;
+  for (int i = rb + t; i < re; i += 256) {
+    const TC yi = yv[i];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int j = c0 + u;
+      if (j < cols) {
+        const TC a = gemv_masked<MASK>((TC)A[(size_t)i + (size_t)j * lda], i, j, d);
+        acc[u] = fma(a, yi, acc[u]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const TC v = wave_sum(acc[u]);
+    if (lane == 0) red[w][u] = v;
+  }
+  __syncthreads();
+  if (t < NC && c0 + t < cols) {
+    const TC v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    if (v != (TC)0) atomicAdd(&s[c0 + t], alpha * v);
+  }
+}
+
+// Launchers (stream-ordered; y / s must hold the values to accumulate onto).
+template <typename S, typename TC, int MASK>
+void gemv_n(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* x, TC* y) {
+  if (rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL((k_gemv_n<S, TC, MASK>), dim3(ceil_div(rows, 256), ceil_div(cols, 64)), dim3(256), 0,
+                     st, A, lda, rows, cols, d, alpha, x, y);
+}
+
+template <typename S, typename TC, int MASK>
+void gemv_t(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* yv, TC* s) {
+  if (rows <= 0 || cols <= 0) return;
+  const int nbx = ceil_div(cols, 16);
+  int nby = ceil_div(rows, 256);
+  const int want = ceil_div(2048, nbx);
+  if (nby > want) nby = want;
+  if (nby < 1) nby = 1;
+  const int rpb = ceil_div(ceil_div(rows, nby), 256) * 256;
+  nby = ceil_div(rows, rpb);
+  hipLaunchKernelGGL((k_gemv_t<S, TC, MASK>), dim3(nbx, nby), dim3(256), 0, st, A, lda, rows, cols, d,
+                     alpha, yv, s, rpb);
+}
+
+}  // namespace lsq

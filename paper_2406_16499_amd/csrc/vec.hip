@@ -2,6 +2,7 @@
 // conversions / reversals, and the FP64 augmented-residual sweeps with the
 // stop test (eq. lse-stop / eq. gls-stop).
 #include "engine.hpp"
+#include "gemv.hpp"
 
 namespace lsq {
 
@@ -20,55 +21,20 @@ void trsv(Ctx& ctx, const TriBlock& tb, bool trans, void* x) {
 }
 
 // ------------------------------------------------------------ masked GEMV --
-// N: y[i] += alpha * sum_j U[i][j] x[j], one work-group per 64 rows.
-template <typename Tw, typename Tc>
-__global__ __launch_bounds__(256) void k_gemv_upper_n(const Tw* __restrict__ M, int ld, int ro, int co,
-                                                      int nr, int nc, double alpha,
-                                                      const Tc* __restrict__ x, Tc* __restrict__ y) {
-  __shared__ Tc part[4][64];
-  const int t = threadIdx.x, i = t & 63, q = t >> 6;
-  const int row = blockIdx.x * 64 + i;
-  Tc s = 0;
-  if (row < nr) {
-    const int grow = ro + row;
-    for (int j = q; j < nc; j += 4) {
-      const int gcol = co + j;
-      if (grow <= gcol) s += (Tc)M[(size_t)grow + (size_t)gcol * ld] * x[j];
-    }
-  }
-  part[q][i] = s;
-  __syncthreads();
-  if (t < 64 && row < nr) y[row] += (Tc)alpha * (part[0][t] + part[1][t] + part[2][t] + part[3][t]);
-}
-
-// T: y[j] += alpha * sum_i U[i][j] x[i], one wave per output column.
-template <typename Tw, typename Tc>
-__global__ __launch_bounds__(256) void k_gemv_upper_t(const Tw* __restrict__ M, int ld, int ro, int co,
-                                                      int nr, int nc, double alpha,
-                                                      const Tc* __restrict__ x, Tc* __restrict__ y) {
-  const int lane = threadIdx.x & 63;
-  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= nc) return;
-  const int gcol = co + j;
-  Tc s = 0;
-  const int imax = min(nr, gcol - ro + 1);   // rows with grow <= gcol
-  for (int i = lane; i < imax; i += 64) s += (Tc)M[(size_t)(ro + i) + (size_t)gcol * ld] * x[i];
-  s = wave_sum(s);
-  if (lane == 0) y[j] += (Tc)alpha * s;
-}
-
 void gemv_upper(Ctx& ctx, const QRFactor& f, int ro, int co, int nr, int nc, bool trans,
                 double alpha, const void* x, void* y, int tc) {
   if (nr <= 0 || nc <= 0) return;
+  // the block's entries with global row <= global column: i - j <= co - ro
 #define LSQ_GEMV(TW, TC)                                                                        \
-  if (!trans)                                                                                   \
-    hipLaunchKernelGGL((k_gemv_upper_n<TW, TC>), dim3(ceil_div(nr, 64)), dim3(256), 0, ctx.stream, \
-                       static_cast<const TW*>(f.M), f.ld, ro, co, nr, nc, alpha,               \
-                       static_cast<const TC*>(x), static_cast<TC*>(y));                         \
-  else                                                                                          \
-    hipLaunchKernelGGL((k_gemv_upper_t<TW, TC>), dim3(ceil_div(nc, 4)), dim3(256), 0, ctx.stream,  \
-                       static_cast<const TW*>(f.M), f.ld, ro, co, nr, nc, alpha,               \
-                       static_cast<const TC*>(x), static_cast<TC*>(y));
+  {                                                                                             \
+    const TW* A = static_cast<const TW*>(f.M) + (size_t)ro + (size_t)co * f.ld;                 \
+    if (!trans)                                                                                 \
+      gemv_n<TW, TC, kUpper>(ctx.stream, A, f.ld, nr, nc, co - ro, (TC)alpha,                   \
+                             static_cast<const TC*>(x), static_cast<TC*>(y));                   \
+    else                                                                                        \
+      gemv_t<TW, TC, kUpper>(ctx.stream, A, f.ld, nr, nc, co - ro, (TC)alpha,                   \
+                             static_cast<const TC*>(x), static_cast<TC*>(y));                   \
+  }
   if (f.tw == 8) {
     if (tc == 8) { LSQ_GEMV(double, double) } else { LSQ_GEMV(double, float) }
   } else {

@@ -47,8 +47,8 @@ typedef struct lsq_handle_st* lsq_handle;
 
 /* Factorization precision u_f (Section 3: u_f >= u_s >= u >= u_r). */
 typedef enum {
-  LSQ_PREC_AUTO = 0,    /* learned selector picks (batched) / FP32 (single)      */
-  LSQ_PREC_FP8E4M3 = 1, /* OCP e4m3 MFMA inputs with per-panel power-of-two scale */
+  LSQ_PREC_AUTO = 0,    /* learned selector when weights are set, else FP32      */
+  LSQ_PREC_FP8E4M3 = 1, /* OCP e4m3 MFMA inputs, per-tile power-of-two scales */
   LSQ_PREC_BF16 = 2,    /* bf16 MFMA inputs, FP32 accumulation                    */
   LSQ_PREC_FP16 = 3,    /* fp16 MFMA inputs, FP32 accumulation                    */
   LSQ_PREC_FP32 = 4,    /* fp32 MFMA                                               */

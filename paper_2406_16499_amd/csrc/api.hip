@@ -185,6 +185,7 @@ bool prec_spec(int prec, PrecSpec& ps) {
     case LSQ_PREC_FP32: ps = {4, Mma::F32, 4}; return true;
     case LSQ_PREC_BF16: ps = {4, Mma::BF16, 4}; return true;
     case LSQ_PREC_FP16: ps = {4, Mma::F16, 4}; return true;
+    case LSQ_PREC_FP8E4M3: ps = {4, Mma::F8, 4}; return true;
     default: return false;
   }
 }
@@ -812,7 +813,7 @@ Selection select_run(Worker* h, int type, int m, int n, int p, const QRFactor& f
   return out;
 }
 
-// Precision / solver of a selector class (FP8 runs as BF16, see the ladder).
+// Precision / solver of a selector class.
 int class_prec(int c) {
   static const int map[kSelPrec] = {LSQ_PREC_FP8E4M3, LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32,
                                     LSQ_PREC_FP64};
@@ -828,13 +829,12 @@ int class_solver(int c) { return c == 1 ? LSQ_SOLVER_GMRES_IR : LSQ_SOLVER_IR; }
 // Escalation ladder: (precision, refinement solvers on that precision's
 // factors).  Starting at the requested rung: with IR requested, each
 // precision tries classical IR and then GMRES-IR on the same factors; with
-// GMRES requested, GMRES-IR only; precisions rise BF16 -> FP16 -> FP32 and the
+// GMRES requested, GMRES-IR only; precisions rise FP8 -> BF16 -> FP16 -> FP32 and the
 // ladder ends with the FP64 direct path.  GMRES-IR is left out when the
 // preconditioner's shape condition fails.
 std::vector<std::pair<int, std::vector<int>>> ladder(const lsq_opts& o, bool gmres_ok) {
   std::vector<std::pair<int, std::vector<int>>> r;
   int prec = o.prec == LSQ_PREC_AUTO ? LSQ_PREC_FP32 : o.prec;
-  if (prec == LSQ_PREC_FP8E4M3) prec = LSQ_PREC_BF16;
   int solver = o.solver == LSQ_SOLVER_AUTO ? LSQ_SOLVER_IR : o.solver;
   if (solver == LSQ_SOLVER_DIRECT || prec == LSQ_PREC_FP64) {
     r.push_back({LSQ_PREC_FP64, {LSQ_SOLVER_DIRECT}});
@@ -848,7 +848,7 @@ std::vector<std::pair<int, std::vector<int>>> ladder(const lsq_opts& o, bool gmr
   std::vector<int> solvers;
   if (solver == LSQ_SOLVER_IR) solvers.push_back(LSQ_SOLVER_IR);
   if (gmres_ok) solvers.push_back(LSQ_SOLVER_GMRES_IR);
-  const int order[] = {LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32};
+  const int order[] = {LSQ_PREC_FP8E4M3, LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32};
   bool on = false;
   for (int q : order) {
     if (q == prec) on = true;

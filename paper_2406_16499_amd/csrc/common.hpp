@@ -66,6 +66,20 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return t;
 }
 
+// Maximum over a whole work-group (every thread receives it); `red` as for block_sum.
+__device__ __forceinline__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double m = 0.0;
+  for (int i = 0; i < nw; ++i) m = fmax(m, red[i]);
+  __syncthreads();
+  return m;
+}
+
 template <typename T> struct Conv;
 template <> struct Conv<float> {
   __device__ static float from(double v) { return (float)v; }

@@ -17,6 +17,8 @@
 // The reflectors are the same as those of a Householder QR (Section 4.1,
 // assumption on xGEQRF); the application of the orthogonal factor to vectors
 // (xORMQR on a vector) applies the panels' block reflectors in sequence.
+#include <hip/hip_fp8.h>
+
 #include "engine.hpp"
 #include "wg64.hpp"
 
@@ -328,6 +330,7 @@ template <Mma MT> struct MmaT;
 template <> struct MmaT<Mma::F32> {
   using In = float; using Acc = float; using V = f32x4;
   static constexpr int KI = 4, KL = 1, PAD = 4;
+  static constexpr bool kScaled = false;
   __device__ static V mma(const In* a, const In* b, V c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
   }
@@ -337,6 +340,7 @@ template <> struct MmaT<Mma::F32> {
 template <> struct MmaT<Mma::F64> {
   using In = double; using Acc = double; using V = f64x4;
   static constexpr int KI = 4, KL = 1, PAD = 2;
+  static constexpr bool kScaled = false;
   __device__ static V mma(const In* a, const In* b, V c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
   }
@@ -347,6 +351,7 @@ template <> struct MmaT<Mma::F64> {
 template <> struct MmaT<Mma::BF16> {
   using In = __bf16; using Acc = float; using V = f32x4;
   static constexpr int KI = 32, KL = 8, PAD = 8;
+  static constexpr bool kScaled = false;
   __device__ static V mma(const In* a, const In* b, V c) {
     const bf16x8 av = *reinterpret_cast<const bf16x8*>(a);
     const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b);
@@ -358,6 +363,7 @@ template <> struct MmaT<Mma::BF16> {
 template <> struct MmaT<Mma::F16> {
   using In = _Float16; using Acc = float; using V = f32x4;
   static constexpr int KI = 32, KL = 8, PAD = 8;
+  static constexpr bool kScaled = false;
   __device__ static V mma(const In* a, const In* b, V c) {
     const f16x8 av = *reinterpret_cast<const f16x8*>(a);
     const f16x8 bv = *reinterpret_cast<const f16x8*>(b);
@@ -366,6 +372,31 @@ template <> struct MmaT<Mma::F16> {
   __device__ static In cvt(double v) { return (_Float16)(float)v; }
   __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
+
+// FP8 e4m3 (OCP): one byte per input; 16x16x32 fragments with the same lane
+// layout as the bf16 form (eight consecutive K values per lane, packed into
+// 64 bits).  Inputs are scaled by powers of two per tile (kScaled) so that
+// the tile's largest magnitude lands in [128, 256), below the e4m3 maximum 448.
+template <> struct MmaT<Mma::F8> {
+  using In = unsigned char; using Acc = float; using V = f32x4;
+  static constexpr int KI = 32, KL = 8, PAD = 16;
+  static constexpr bool kScaled = true;
+  __device__ static V mma(const In* a, const In* b, V c) {
+    const long av = *reinterpret_cast<const long*>(a);
+    const long bv = *reinterpret_cast<const long*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, c, 0, 0, 0);
+  }
+  __device__ static In cvt(double v) { return __hip_fp8_e4m3((float)v).__x; }
+  __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+// Power-of-two scale that maps a tile maximum m into [128, 256) (1 for m = 0).
+__device__ __forceinline__ double fp8_scale(double m) {
+  if (!(m > 0.0) || !isfinite(m)) return 1.0;
+  int e;
+  frexp(m, &e);
+  return ldexp(1.0, 8 - e);
+}
 
 template <Mma MT, int BK>
 __device__ __forceinline__ void mma_block(const typename MmaT<MT>::In* As,
@@ -427,18 +458,48 @@ __global__ __launch_bounds__(256) void k_wy_t(
       cb[q] = c;
     }
   };
+  __shared__ double red[8];
   if (kbeg < kend) fetch(kbeg);
   for (int k = kbeg; k < kend; k += BK) {
+    double sa = 1.0, sb = 1.0;
+    if constexpr (T::kScaled) {
+      double ma = 0.0, mb = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        ma = fmax(ma, fabs(ya[q]));
+        mb = fmax(mb, fabs(cb[q]));
+      }
+      sa = fp8_scale(block_max(ma, red));
+      sb = fp8_scale(block_max(mb, red));
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = t + 256 * q, kk = e & (BK - 1), a = e / BK;
-      As[a * LD + kk] = T::cvt(ya[q]);
-      Bs[a * LD + kk] = T::cvt(cb[q]);
+      As[a * LD + kk] = T::cvt(ya[q] * sa);
+      Bs[a * LD + kk] = T::cvt(cb[q] * sb);
     }
     __syncthreads();
     if (k + BK < kend) fetch(k + BK);
-    mma_block<MT, BK>(As, Bs, acc);
+    if constexpr (T::kScaled) {
+      typename T::V tmp[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tmp[i][j][r] = 0;
+      mma_block<MT, BK>(As, Bs, tmp);
+      const float inv = (float)(1.0 / (sa * sb));
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] += tmp[i][j][r] * inv;
+    } else {
+      mma_block<MT, BK>(As, Bs, acc);
+    }
   }
   const int l = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
 #pragma unroll
@@ -489,15 +550,30 @@ __global__ __launch_bounds__(256) void k_wy_u(
     const int e = t + 256 * q, i = e & 63, c = e >> 6;
     cv[q] = (r0 + i < mr && c0 + c < nc) ? (double)C[(size_t)(r0 + i) + (size_t)(c0 + c) * ldc] : 0.0;
   }
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int i = e & 63, a = e >> 6;
-    double v = (r0 + i < mr && a < jb) ? (double)Yhat[(size_t)(r0 + i) + (size_t)a * ldy] : 0.0;
-    As[i * LD + a] = T::cvt(v);
+  double av[16], bv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + 256 * q, i = e & 63, a = e >> 6;
+    av[q] = (r0 + i < mr && a < jb) ? (double)Yhat[(size_t)(r0 + i) + (size_t)a * ldy] : 0.0;
+    bv[q] = (i < jb && c0 + a < nc) ? (double)W[i + (size_t)(c0 + a) * 64] : 0.0;
   }
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int a = e & 63, c = e >> 6;
-    double v = (a < jb && c0 + c < nc) ? (double)W[a + (size_t)(c0 + c) * 64] : 0.0;
-    Bs[c * LD + a] = T::cvt(v);
+  double sa = 1.0, sb = 1.0;
+  if constexpr (T::kScaled) {
+    __shared__ double red[8];
+    double ma = 0.0, mb = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      ma = fmax(ma, fabs(av[q]));
+      mb = fmax(mb, fabs(bv[q]));
+    }
+    sa = fp8_scale(block_max(ma, red));
+    sb = fp8_scale(block_max(mb, red));
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + 256 * q, i = e & 63, a = e >> 6;
+    As[i * LD + a] = T::cvt(av[q] * sa);     // As[row][k]
+    Bs[a * LD + i] = T::cvt(bv[q] * sb);     // Bs[col][k]
   }
   __syncthreads();
   typename T::V acc[2][2];
@@ -508,6 +584,15 @@ __global__ __launch_bounds__(256) void k_wy_u(
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
   mma_block<MT, BK>(As, Bs, acc);
+  if constexpr (T::kScaled) {
+    const float inv = (float)(1.0 / (sa * sb));
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] *= inv;
+  }
   __syncthreads();                                 // the tile reuses the operand buffers
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
@@ -693,6 +778,7 @@ void qr_factor(Ctx& ctx, QRFactor& f) {
     qr_factor_t<double, Mma::F64>(ctx, f);
   } else {
     switch (f.mt) {
+      case Mma::F8: qr_factor_t<float, Mma::F8>(ctx, f); break;
       case Mma::BF16: qr_factor_t<float, Mma::BF16>(ctx, f); break;
       case Mma::F16: qr_factor_t<float, Mma::F16>(ctx, f); break;
       default: qr_factor_t<float, Mma::F32>(ctx, f); break;
@@ -719,6 +805,7 @@ void qr_apply_left_T(Ctx& ctx, const QRFactor& f, void* C, int ldc, int ncols) {
     apply_left_t<double, Mma::F64>(ctx, f, static_cast<double*>(C), ldc, ncols);
   } else {
     switch (f.mt) {
+      case Mma::F8: apply_left_t<float, Mma::F8>(ctx, f, static_cast<float*>(C), ldc, ncols); break;
       case Mma::BF16: apply_left_t<float, Mma::BF16>(ctx, f, static_cast<float*>(C), ldc, ncols); break;
       case Mma::F16: apply_left_t<float, Mma::F16>(ctx, f, static_cast<float*>(C), ldc, ncols); break;
       default: apply_left_t<float, Mma::F32>(ctx, f, static_cast<float*>(C), ldc, ncols); break;

@@ -243,3 +243,57 @@ def test_gls_solve(h, n, m, p, prec):
     rc, res = h.gls_solve(D(G.W), D(G.V), D(G.d), x, y, z, lsq.default_opts(prec=prec))
     assert rc == 0, (rc, h.last_error(), res.as_dict())
     _check_gls(G, H(x), H(y), H(z), res)
+
+
+# ------------------------------------------------------------ FP8 (a1) ----
+
+@pytest.mark.parametrize("r,c", [(64, 64), (300, 200), (513, 129), (1000, 300)])
+def test_householder_qr_fp8_backward_error(h, r, c):
+    # FP8 e4m3 trailing-update inputs (3 mantissa bits, per-tile scaling): the
+    # factorization is that of a matrix within O(u_f) of M.  Q is applied in
+    # FP32 by the vector kernels, so Q^T M - [R; 0] measures that distance.
+    note(f"qr fp8 backward error r={r} c={c}")
+    g = rng(r + 3 * c)
+    M = g.standard_normal((r, c))
+    k = min(r, c)
+    rc, R, _, Y2, _ = h.dbg_qr("fp8", D(M), D(M), want=("R", "Y2"))
+    assert rc == 0, h.last_error()
+    R, Y2 = H(R), H(Y2)
+    E = Y2.copy()
+    E[:k] -= R
+    panels = -(-k // 64)
+    rel = np.linalg.norm(E) / np.linalg.norm(M)
+    assert rel <= 2.0 * np.sqrt(panels) * 2.0 ** -4
+    # and it is no better than a BF16 factorization by more than the precision ratio
+    rc, Rb, _, Y2b, _ = h.dbg_qr("bf16", D(M), D(M), want=("R", "Y2"))
+    Eb = H(Y2b)
+    Eb[:k] -= H(Rb)
+    assert np.linalg.norm(Eb) / np.linalg.norm(M) <= 2.0 * np.sqrt(panels) * 2.0 ** -8
+    if panels > 1:
+        assert rel > np.linalg.norm(Eb) / np.linalg.norm(M)
+
+
+@pytest.mark.parametrize("solver", ["gmres", "ir"])
+def test_lse_solve_fp8(h, solver):
+    note(f"lse_solve fp8 {solver}")
+    P = wl.lse_gaussian(rng(91), 600, 300, 40)
+    m, n, p = P.shape
+    x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+    rc, res = h.lse_solve(D(P.A), D(P.B), D(P.b), D(P.d), x, r, v,
+                          lsq.default_opts(prec="fp8", solver=solver, escalate=1))
+    assert rc == 0, (rc, h.last_error(), res.as_dict())
+    _check_lse(P, H(x), H(r), H(v), res)
+    if solver == "gmres":
+        assert res.as_dict()["prec_used"] == "fp8"
+
+
+def test_gls_solve_fp8_gmres(h):
+    note("gls_solve fp8 gmres")
+    G = wl.gls_gaussian(rng(92), 300, 60, 500)
+    n, m, p = G.shape
+    x, y, z = lsq.empty(m), lsq.empty(p), lsq.empty(n)
+    rc, res = h.gls_solve(D(G.W), D(G.V), D(G.d), x, y, z,
+                          lsq.default_opts(prec="fp8", solver="gmres", escalate=1))
+    assert rc == 0, (rc, h.last_error(), res.as_dict())
+    _check_gls(G, H(x), H(y), H(z), res)
+    assert res.as_dict()["prec_used"] == "fp8"

@@ -110,6 +110,6 @@ def test_auto_solves_certify_whatever_the_pick(h, cls_bias):
         else:
             assert direct.gls_err1(P.W, P.V, P.d, x, k[2].cpu().numpy()) <= 1e-13
     first = {lsq.PREC_NAME[r.prec_used] for r in res if r.attempts == 1}
-    want = {0: "bf16", 1: "bf16", 2: "fp16", 3: "fp32", 4: "fp64"}[cls_bias]
+    want = {0: "fp8", 1: "bf16", 2: "fp16", 3: "fp32", 4: "fp64"}[cls_bias]
     assert first <= {want}
     h.selector_set(None)

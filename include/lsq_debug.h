@@ -72,6 +72,15 @@ int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, cons
                      const double* B, int ldb, double alpha, double beta, const double* u,
                      double* y);
 
+/* The same operator captured once as a HIP graph and replayed for each of
+ * the k columns of U (N x k, column-major, N the augmented size): Y[:, j] =
+ * M_l F~ M_r U[:, j].  The copies into and out of the graph's buffers run
+ * eagerly between replays.  *graph_used (nullable) is 1 if the capture
+ * succeeded (else the operator ran kernel by kernel).  Returns -15 for k < 0. */
+int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p, const double* A,
+                           int lda, const double* B, int ldb, double alpha, double beta,
+                           const double* U, double* Y, int k, int* graph_used);
+
 /* Kernel timing.  While enabled, HIP events are recorded on the handle's
  * stream around every launch of the named kernel kind ("panel_final_y",
  * "panel_cholpass", "wy_t", "wy_u", "dual_gemv"), and the launch's algorithmic

@@ -1497,6 +1497,53 @@ int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes) {
 }
 
 // ------------------------------------------------- preconditioned operator --
+int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p, const double* A,
+                           int lda, const double* B, int ldb, double alpha, double beta,
+                           const double* U, double* Y, int k, int* graph_used) {
+  if (!h) return -1;
+  if (type != LSQ_LSE && type != LSQ_GLS) return -2;
+  PrecSpec ps;
+  if (!prec_spec(prec, ps)) return -3;
+  if (type == LSQ_LSE && !(p <= n && n <= m + p && lse_gmres_ok(m, n))) return -4;
+  if (type == LSQ_GLS && !(m <= n && n <= m + p && gls_gmres_ok(n, p))) return -4;
+  if (!(alpha > 0) || !(beta > 0)) return -11;
+  if (k < 0) return -15;
+  return guard(h, "lsq_dbg_bd_apply_graph", [&]() -> int {
+    Ctx& ctx = h->w.ctx;
+    bool used = false;
+    if (type == LSQ_LSE) {
+      LseSolver sv;
+      sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
+      LseArgs a{m, n, p, A, B, nullptr, nullptr, lda, ldb};
+      sv.factor(ctx, A, lda, B, ldb, kMaxNb);
+      sv.prepare_gmres(ctx);
+      sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
+      std::function<void(const double*, double*)> op = [&](const double* u, double* y) {
+        sv.m_right(ctx, u, sv.t1);
+        sv.f_apply(ctx, a, sv.t1, sv.t2);
+        sv.m_left(ctx, sv.t2, y);
+      };
+      graph_apply_columns(ctx, m + p + n, op, U, Y, k, &used);
+    } else {
+      GlsSolver sv;
+      sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.ps = ps;
+      GlsArgs a{n, m, p, A, B, nullptr, lda, ldb};
+      sv.factor(ctx, A, lda, B, ldb, kMaxNb);
+      sv.prepare_gmres(ctx);
+      sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
+      std::function<void(const double*, double*)> op = [&](const double* u, double* y) {
+        sv.m_right(ctx, u, sv.t1);
+        sv.f_apply(ctx, a, sv.t1, sv.t2);
+        sv.m_left(ctx, sv.t2, y);
+      };
+      graph_apply_columns(ctx, p + n + m, op, U, Y, k, &used);
+    }
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
+    if (graph_used) *graph_used = used ? 1 : 0;
+    return 0;
+  });
+}
+
 int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, const double* A, int lda,
                      const double* B, int ldb, double alpha, double beta, const double* u,
                      double* y) {

@@ -249,7 +249,7 @@ void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
 template <typename TC>
 void trmv_dense(Ctx& ctx, const TC* X, int ldx, int nn, bool trans, const TC* x, TC* y) {
   if (nn <= 0) return;
-  LSQ_HIP(hipMemsetAsync(y, 0, sizeof(TC) * nn, ctx.stream));
+  vec_zero(ctx, y, (int)sizeof(TC), nn);          // a fill kernel: this path may be graph-captured
   if (!trans)
     gemv_n<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y);
   else
@@ -317,7 +317,7 @@ static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
     const S* Y = static_cast<const S*>(f.M) + (size_t)b.J0 + (size_t)b.J0 * f.ld;
     TC* yy = y + b.J0;
     // s = Y^T y (unit-lower Y)
-    LSQ_HIP(hipMemsetAsync(s, 0, sizeof(TC) * b.w, ctx.stream));
+    vec_zero(ctx, s, (int)sizeof(TC), b.w);
     gemv_t<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)1, yy, s);
     // Q^T = I - Y T^T Y^T  -> t = T^T s ;  Q = I - Y T Y^T -> t = T s
     trmv_dense<TC>(ctx, static_cast<const TC*>(b.T), b.w, b.w, trans, s, tv);

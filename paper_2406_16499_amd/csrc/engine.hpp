@@ -188,10 +188,17 @@ double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn);   // synchroniz
 struct GmresOut {
   int iters = 0;
   bool converged = false;
+  bool graph = false;          // the operator ran as a replayed HIP graph
 };
-// Restarted GMRES from x = 0 for apply(u) = M u (FP64, CGS2, Givens on the host).
+// Restarted GMRES from x = 0 for apply(u) = M u (FP64, CGS2, Givens on the
+// host).  With use_graph, apply (which must not synchronize the host) is
+// captured once and replayed per iteration.
 GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
-               const double* rhs, double* x, int restart, double tol, int maxit);
+               const double* rhs, double* x, int restart, double tol, int maxit,
+               bool use_graph = true);
+// Y[:, j] = M U[:, j], j < k, by replays of the captured operator graph.
+void graph_apply_columns(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
+                         const double* U, double* Y, int k, bool* graph_used);
 
 // ------------------------------------------------------------ selector ----
 constexpr int kSelFeatures = 16, kSelHidden = 64, kSelOut = 7, kSelPrec = 5;

@@ -163,12 +163,75 @@ double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn) {
   return ctx.pin[0];
 }
 
+// The operator as a replayable HIP graph: apply() is captured once from a
+// fixed input buffer to a fixed output buffer; run(u, y) copies u in, replays
+// the graph and copies the result out.  If capture is not possible the
+// operator runs eagerly (same kernels, launched one by one).
+struct GraphOp {
+  Ctx& ctx;
+  const std::function<void(const double*, double*)>& apply;
+  int N;
+  double* in = nullptr;
+  double* out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  GraphOp(Ctx& c, const std::function<void(const double*, double*)>& f, int n, bool use_graph)
+      : ctx(c), apply(f), N(n) {
+    // capture on the context's side stream (the caller's stream may be the
+    // null stream, which cannot be captured); replays go to ctx.stream
+    if (!use_graph || N <= 0 || !ctx.side) return;
+    in = ctx.ws->get<double>(N);
+    out = ctx.ws->get<double>(N);
+    vec_zero(ctx, in, 8, N);
+    KernelTimer* saved_timer = ctx.timer;     // no event records inside the graph
+    hipStream_t saved_stream = ctx.stream;
+    ctx.timer = nullptr;
+    ctx.stream = ctx.side;
+    bool ok = hipStreamBeginCapture(ctx.side, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      try {
+        apply(in, out);
+      } catch (const HipError&) {
+        ok = false;
+      }
+      hipGraph_t g = nullptr;
+      const bool ended = hipStreamEndCapture(ctx.side, &g) == hipSuccess;
+      graph = g;
+      ok = ok && ended && graph != nullptr;
+    }
+    ctx.timer = saved_timer;
+    ctx.stream = saved_stream;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
+  }
+  ~GraphOp() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  void run(const double* u, double* y) {
+    if (!exec) { apply(u, y); return; }
+    vec_convert(ctx, in, 8, u, 8, N, false);
+    LSQ_HIP(hipGraphLaunch(exec, ctx.stream));
+    vec_convert(ctx, y, 8, out, 8, N, false);
+  }
+};
+
 // Restarted GMRES(restart) from x = 0 on apply(u) = M u, stopping when the
 // Arnoldi residual estimate reaches tol ||rhs|| or after maxit iterations in
 // total; after every cycle the residual is recomputed from x.
-GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
-               const double* rhs, double* x, int restart, double tol, int maxit) {
+GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply_eager,
+               const double* rhs, double* x, int restart, double tol, int maxit, bool use_graph) {
   GmresOut out;
+  GraphOp op(ctx, apply_eager, N, use_graph);
+  auto apply = [&](const double* u, double* y) { op.run(u, y); };
+  out.graph = op.exec != nullptr;
   vec_zero(ctx, x, 8, N);
   if (N <= 0) { out.converged = true; return out; }
   if (restart > kCgsMax - 1) restart = kCgsMax - 1;
@@ -253,6 +316,16 @@ GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)
   }
   if (!out.converged) out.converged = beta <= tol * beta0;
   return out;
+}
+
+// Y[:, j] = M U[:, j] for k columns (N x k, column-major) through the
+// captured graph, one replay per column (the copies in and out run eagerly
+// between replays).  *graph_used reports whether capture succeeded.
+void graph_apply_columns(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
+                         const double* U, double* Y, int k, bool* graph_used) {
+  GraphOp op(ctx, apply, N, true);
+  if (graph_used) *graph_used = op.exec != nullptr;
+  for (int j = 0; j < k; ++j) op.run(U + (size_t)j * N, Y + (size_t)j * N);
 }
 
 }  // namespace lsq

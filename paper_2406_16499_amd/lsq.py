@@ -88,6 +88,8 @@ _SIGS = {
                                        _P, _P, _P, _P, _P]),
     "lsq_dbg_bd_apply": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int,
                                  c_double, c_double, _P, _P]),
+    "lsq_dbg_bd_apply_graph": (c_int, [_P, c_int, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int,
+                                       c_double, c_double, _P, _P, c_int, ctypes.POINTER(c_int)]),
     "lsq_dbg_timer_enable": (c_int, [_P, ctypes.c_char_p]),
     "lsq_dbg_timer_read": (c_int, [_P, ctypes.POINTER(c_double), ctypes.POINTER(c_int),
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
@@ -286,6 +288,28 @@ class Handle:
         if rc != 0:
             raise RuntimeError(f"lsq_dbg_bd_apply = {rc}: {self.last_error()}")
         return y
+
+    def dbg_bd_apply_graph(self, kind, prec, A, B, alpha, beta, U):
+        """Y = M_l F~ M_r U column by column through replays of a captured graph;
+        returns (Y, graph_used)."""
+        torch = _torch()
+        N, k = U.shape
+        Y = torch.empty_strided((N, k), (1, max(N, 1)), dtype=torch.float64, device=U.device)
+        if kind == "lse":
+            m, n = A.shape
+            p = B.shape[0]
+            t = LSE
+        else:
+            n, m = A.shape
+            p = B.shape[1]
+            t = GLS
+        used = c_int(0)
+        rc = self.lib.lsq_dbg_bd_apply_graph(self.h, t, PREC[prec], m, n, p, _ptr(A), _ld(A), _ptr(B),
+                                             _ld(B), float(alpha), float(beta), _ptr(U), _ptr(Y), k,
+                                             ctypes.byref(used))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_bd_apply_graph = {rc}: {self.last_error()}")
+        return Y, bool(used.value)
 
     def timer_enable(self, kernel: Optional[str]):
         """Time every launch of one kernel kind with HIP events (None disables)."""

@@ -204,3 +204,25 @@ def test_gmres_request_on_unsupported_shape_uses_ir(h):
                           lsq.default_opts(prec="fp32", solver="gmres", escalate=0))
     assert rc == 0 and res.as_dict()["solver_used"] == "ir"
     _check_lse(P, H(x), H(r), H(v), res)
+
+
+@pytest.mark.parametrize("kind", ["lse", "gls"])
+def test_bd_operator_graph_replays_match_eager(h, kind):
+    # the GMRES operator is captured once as a HIP graph and replayed: every
+    # replay (with eager copies in between) must equal the eager application
+    note(f"bd operator graph replays {kind}")
+    if kind == "lse":
+        P = wl.lse_gaussian(rng(80), 300, 120, 20)
+        A, B = P.A, P.B
+        N = sum(P.shape)
+    else:
+        G = wl.gls_gaussian(rng(81), 150, 40, 260)
+        A, B = G.W, G.V
+        N = sum(G.shape)
+    U = rng(82).standard_normal((N, 4))
+    Y, used = h.dbg_bd_apply_graph(kind, "fp32", D(A), D(B), 0.8, 1.0, D(U))
+    assert used
+    Y = H(Y)
+    for j in range(U.shape[1]):
+        ref = H(h.dbg_bd_apply(kind, "fp32", D(A), D(B), 0.8, 1.0, lsq.colmajor(U[:, j])))
+        assert np.max(np.abs(Y[:, j] - ref)) <= 1e-12 * (1 + np.max(np.abs(ref)))

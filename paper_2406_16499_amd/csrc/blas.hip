@@ -71,26 +71,43 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    __syncthreads();
-    // op(A)(row, kk): storage (row, kk) or (kk, row); fast index follows storage rows
-    for (int e = t; e < 64 * BK; e += 256) {
+  // The next 32-deep chunk of op(A) and op(B) is fetched into registers while
+  // the MFMAs of the current one run.  op(A)(row, kk): storage (row, kk) or
+  // (kk, row); the fast index of each thread's elements follows storage rows.
+  double av[8], bv[8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
       int row, kk;
       if (!g.ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
-      const int gi = r0 + row, gk = k0 + kk;
+      int gi = r0 + row, gk = k0 + kk;
       double v = 0.0;
       if (gi < g.m && gk < kend) v = g.ta ? mload(A, g.lda, gk, gi, g.ma, g.oa) : mload(A, g.lda, gi, gk, g.ma, g.oa);
-      As[row * LD + kk] = (TC)v;
-    }
-    for (int e = t; e < 64 * BK; e += 256) {
-      int col, kk;
+      av[q] = v;
+      int col;
       if (!g.tb) { kk = e % BK; col = e / BK; } else { col = e & 63; kk = e >> 6; }
-      const int gj = c0 + col, gk = k0 + kk;
-      double v = 0.0;
+      const int gj = c0 + col;
+      gk = k0 + kk;
+      v = 0.0;
       if (gj < g.n && gk < kend) v = g.tb ? mload(B, g.ldb, gj, gk, g.mb, g.ob) : mload(B, g.ldb, gk, gj, g.mb, g.ob);
-      Bs[col * LD + kk] = (TC)v;
+      bv[q] = v;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      int row, kk, col, kb;
+      if (!g.ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
+      if (!g.tb) { kb = e % BK; col = e / BK; } else { col = e & 63; kb = e >> 6; }
+      As[row * LD + kk] = (TC)av[q];
+      Bs[col * LD + kb] = (TC)bv[q];
     }
     __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       TC a[2], b[2];
@@ -286,19 +303,30 @@ void agg_prepare(Ctx& ctx, QRFactor& f, int tc, int panels_per_block) {
     const int rows = f.r - J0;
     const long long tot = (long long)b.w * b.w;
     b.T = ctx.ws->alloc((size_t)tc * tot);
-    double* G = ctx.ws->get<double>(tot);
-    double* T64 = tc == 8 ? static_cast<double*>(b.T) : ctx.ws->get<double>(tot);
     GemmArgs g{};
     g.A = f.tw == 8 ? (const void*)(static_cast<const double*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld)
                     : (const void*)(static_cast<const float*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld);
     g.lda = f.ld; g.ta = 1; g.ma = 2; g.oa = 0;
     g.B = g.A; g.ldb = f.ld; g.tb = 0; g.mb = 2; g.ob = 0;
-    g.C = G; g.ldc = b.w; g.m = b.w; g.n = b.w; g.k = rows; g.alpha = 1.0; g.beta = 0.0;
-    if (f.tw == 8) gemm<double, double, double>(ctx, g, 1); else gemm<float, float, double>(ctx, g, 1);
-    hipLaunchKernelGGL((k_ut_fix<double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, G, b.w, b.w);
-    tri_inverse<double, double>(ctx, G, b.w, b.w, T64, b.w);
-    if (tc != 8)
-      hipLaunchKernelGGL((k_cast<float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, T64, static_cast<float*>(b.T), tot);
+    g.ldc = b.w; g.m = b.w; g.n = b.w; g.k = rows; g.alpha = 1.0; g.beta = 0.0;
+    if (tc == 8 || f.tw == 8) {
+      // FP64 Gram and inverse (the GMRES preconditioner and the FP64 path)
+      double* G = ctx.ws->get<double>(tot);
+      double* T64 = tc == 8 ? static_cast<double*>(b.T) : ctx.ws->get<double>(tot);
+      g.C = G;
+      if (f.tw == 8) gemm<double, double, double>(ctx, g, 1); else gemm<float, float, double>(ctx, g, 1);
+      hipLaunchKernelGGL((k_ut_fix<double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, G, b.w, b.w);
+      tri_inverse<double, double>(ctx, G, b.w, b.w, T64, b.w);
+      if (tc != 8)
+        hipLaunchKernelGGL((k_cast<float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, T64, static_cast<float*>(b.T), tot);
+    } else {
+      // FP32 corrections on FP32-stored reflectors: Gram and inverse in FP32
+      float* G = ctx.ws->get<float>(tot);
+      g.C = G;
+      gemm<float, float, float>(ctx, g, 1);
+      hipLaunchKernelGGL((k_ut_fix<float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, G, b.w, b.w);
+      tri_inverse<float, float>(ctx, G, b.w, b.w, static_cast<float*>(b.T), b.w);
+    }
     LSQ_LAUNCH_CHECK();
     f.agg.push_back(b);
   }

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_panel_cholpass(
   __shared__ double S0[64 * kLdt];
   __shared__ double S1[64 * kLdt];
   __shared__ double S2[64 * kLdt];
-  __shared__ double buf[256];
+  __shared__ double buf[512];
   __shared__ double red[4];
   const int t = threadIdx.x;
   load_gram(Gin, jb, mr, shift, S0, red);
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
   __shared__ double A1[64 * kLdt];     // R2^{-1}, then W^T, then the Y tile
   __shared__ double A2[64 * kLdt];     // scratch, V^T -> Mmat, then T^T
   __shared__ double A3[64 * kLdt];     // L1 (strictly lower, zero elsewhere)
-  __shared__ double buf[256];
+  __shared__ double buf[512];
   __shared__ double cbuf[128];
   __shared__ double sgn[64];
   __shared__ double red[4];

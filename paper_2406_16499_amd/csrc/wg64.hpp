@@ -107,12 +107,13 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // In-register Cholesky with the inverse factor.  On entry x holds this
 // thread's entries of a symmetric positive definite G (identity-padded beyond
 // jb).  On exit x holds R (upper, G = R^T R, zeros below the diagonal) and z
-// holds Z = R^{-T} (lower): row k of Z follows from forward substitution with
-// R^T, which needs exactly the row of R produced in step k, so both run in
-// one loop.  The pivot row is published with zeros left of the diagonal, so
-// the updates need no masks: finished rows see a zero multiplier, and the
-// pivot row itself is overwritten by its owner after the update.
-// buf: 4 x 64 LDS doubles.
+// holds Z = R^{-T} (lower): rows of Z follow from forward substitution with
+// R^T, which needs exactly the rows of R produced in the same step, so both
+// run in one loop.  Each step eliminates a 2 x 2 pivot block (rows k, k+1 of
+// one wave): one barrier and one pivot chain per two columns.  The pivot rows
+// are published with zeros left of their diagonal, so the updates need no
+// masks: finished rows see zero multipliers, and the pivot rows themselves are
+// overwritten by their owner after the update.  buf: 8 x 64 LDS doubles.
 __device__ __forceinline__ bool reg_cholesky_inv(double x[16], double z[16], double* buf) {
   const Own o;
   bool ok = true;
@@ -120,30 +121,50 @@ __device__ __forceinline__ bool reg_cholesky_inv(double x[16], double z[16], dou
   for (int qq = 0; qq < 16; ++qq) z[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
   for (int wk = 0; wk < 4; ++wk) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 16; q += 2) {
       const int k = 16 * wk + q;
-      double* rg = buf + (q & 1) * 128;
-      double* rz = rg + 64;
+      double* g0 = buf + ((q >> 1) & 1) * 256;        // row k of G, row k + 1, rows k, k + 1 of z
+      double* g1 = g0 + 64;
+      double* z0 = g0 + 128;
+      double* z1 = g0 + 192;
       if (o.w == wk) {
-        rg[o.c] = (o.c >= k) ? x[q] : 0.0;
-        rz[o.c] = z[q];
+        g0[o.c] = (o.c >= k) ? x[q] : 0.0;
+        g1[o.c] = (o.c >= k + 1) ? x[q + 1] : 0.0;
+        z0[o.c] = z[q];
+        z1[o.c] = z[q + 1];
       }
       __syncthreads();
-      double dkk = rg[k];
-      ok = ok && (dkk > 0.0);
-      dkk = dkk > 0.0 ? dkk : 1e-300;
-      const double ip = rsqrt64(dkk), ip2 = ip * ip;
-      const double gkc = rg[o.c], zkc = rz[o.c];
-      const double rk2 = gkc * ip2, zk2 = zkc * ip2;
+      // 2 x 2 pivot block [g00 g01; g01 g11] = R_kk^T R_kk
+      double g00 = g0[k];
+      ok = ok && (g00 > 0.0);
+      g00 = g00 > 0.0 ? g00 : 1e-300;
+      const double i0 = rsqrt64(g00);
+      const double r01 = g0[k + 1] * i0;
+      double d1 = g1[k + 1] - r01 * r01;
+      ok = ok && (d1 > 0.0);
+      d1 = d1 > 0.0 ? d1 : 1e-300;
+      const double i1 = rsqrt64(d1);
+      // rows k, k + 1 of R and Z in this thread's column
+      const double R0 = g0[o.c] * i0;
+      const double R1 = (g1[o.c] - r01 * R0) * i1;
+      const double Z0 = z0[o.c] * i0;
+      const double Z1 = (z1[o.c] - r01 * Z0) * i1;
+      // x_i -= R0_i R0 + R1_i R1 with R0_i = g0_i i0, R1_i = (g1_i - r01 R0_i) i1,
+      // regrouped as g0_i a + g1_i b (likewise for z)
+      const double t = r01 * i0 * i1;
+      const double ax = R0 * i0 - t * R1, bx = R1 * i1;
+      const double az = Z0 * i0 - t * Z1, bz = Z1 * i1;
 #pragma unroll
       for (int qq = 0; qq < 16; ++qq) {
-        const double gki = rg[o.r0 + qq];
-        x[qq] = fma(-gki, rk2, x[qq]);
-        z[qq] = fma(-gki, zk2, z[qq]);
+        const double a0 = g0[o.r0 + qq], a1 = g1[o.r0 + qq];
+        x[qq] = fma(-a1, bx, fma(-a0, ax, x[qq]));
+        z[qq] = fma(-a1, bz, fma(-a0, az, z[qq]));
       }
       if (o.w == wk) {
-        x[q] = gkc * ip;
-        z[q] = zkc * ip;
+        x[q] = R0;
+        x[q + 1] = (o.c >= k + 1) ? R1 : 0.0;
+        z[q] = Z0;
+        z[q + 1] = Z1;
       }
     }
   }

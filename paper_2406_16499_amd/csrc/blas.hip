@@ -186,13 +186,13 @@ static void gemm(Ctx& ctx, GemmArgs g, int batch) {
 // Inverse of each 64 x 64 diagonal block; one work-group per block, FP64,
 // right-looking back substitution on U X = I with all columns in parallel.
 template <typename S, typename TC>
-__global__ __launch_bounds__(256) void k_diag_inv(const S* __restrict__ U, int ldu, int mask, int nn,
+__global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int ldu, int mask, int nn,
                                                   TC* __restrict__ X, int ldx) {
   __shared__ double R[64 * kLdt];
   __shared__ double buf[192];
   const int I = blockIdx.x, i0 = I * 64, ib = min(64, nn - i0);
   const int t = threadIdx.x;
-  for (int e = t; e < 4096; e += 256) {
+  for (int e = t; e < 4096; e += 512) {
     const int i = e & 63, j = e >> 6;
     double v = 0.0;
     if (i < ib && j < ib && i <= j) v = mload(U, ldu, i0 + i, i0 + j, mask, 0);
@@ -200,11 +200,11 @@ __global__ __launch_bounds__(256) void k_diag_inv(const S* __restrict__ U, int l
     R[i * kLdt + j] = v;
   }
   __syncthreads();
-  double x[16];
-  reg_upper_inverse(R, x, buf);
-  const Own o;
+  double x[8];
+  reg_upper_inverse<8>(R, x, buf);
+  const Own<8> o;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
+  for (int q = 0; q < 8; ++q) {
     const int i = o.r0 + q;
     if (i < ib && o.c < ib) X[(size_t)(i0 + i) + (size_t)(i0 + o.c) * ldx] = (TC)x[q];
   }
@@ -227,7 +227,7 @@ void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
   const int nblk = ceil_div(nn, 64);
   const long long tot = (long long)nn * nn;
   hipLaunchKernelGGL((k_zero_lower<TC>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, X, ldx, nn);
-  hipLaunchKernelGGL((k_diag_inv<S, TC>), dim3(nblk), dim3(256), 0, ctx.stream, U, ldu, 1, nn, X, ldx);
+  hipLaunchKernelGGL((k_diag_inv<S, TC>), dim3(nblk), dim3(512), 0, ctx.stream, U, ldu, 1, nn, X, ldx);
   LSQ_LAUNCH_CHECK();
   TC* tmp = ctx.ws->get<TC>((size_t)nn * 64 + (size_t)nn * nn / 2 + 64);
   for (int b = 64; b < nn; b *= 2) {

@@ -37,36 +37,43 @@ constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
 constexpr int kGramCopies = 1;
 constexpr int kGramStride = kGramCopies * 4096;   // doubles per Gram accumulator
 
+template <int NW>
 __device__ __forceinline__ void gram_atomic(const double* tile, int jb, double* __restrict__ Gbase) {
+  constexpr int BR = 8 / NW;
   double* __restrict__ G = Gbase + (size_t)((blockIdx.x + blockIdx.y) % kGramCopies) * 4096;
-  f64x4 acc[2][2];
-  mm64_acc(tile, true, tile, acc);
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
-  if (wr > wc) return;                 // strictly lower quadrant
+  f64x4 acc[BR][2];
+  mm64_acc<NW>(tile, true, tile, acc);
+  const int w = threadIdx.x >> 6;
+  if (16 * BR * (w >> 1) >= 32 * (w & 1) + 32) return;   // the wave's block lies below the diagonal
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < BR; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 32 * wr + 16 * bi + 4 * r + (l >> 4), j = 32 * wc + 16 * bj + (l & 15);
+        const int i = mm64_row<NW>(bi, r), j = mm64_col<NW>(bj);
         if (i <= j && j < jb) atomicAdd(&G[i + j * 64], acc[bi][bj][r]);
       }
 }
 
+// The 64 x 64 panel problems run on work-groups of kPW waves.
+constexpr int kPW = 8;
+constexpr int kPT = 64 * kPW;
+constexpr int kPR = 64 / kPW;   // register rows per thread
+
 // Gram of the first panel: G += X^T X over 64-row tiles.  Later panels get
 // theirs from the trailing update that produces them (k_wy_u).
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_panel_gram(const Tin* __restrict__ X, int ldx, int mr,
+__global__ __launch_bounds__(kPT) void k_panel_gram(const Tin* __restrict__ X, int ldx, int mr,
                                                     int jb, double* __restrict__ G) {
   __shared__ double tile[64 * kLdt];
   const int rb = blockIdx.x * 64;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+  for (int e = threadIdx.x; e < 64 * 64; e += kPT) {
     const int i = e & 63, j = e >> 6;
     tile[i * kLdt + j] = (rb + i < mr && j < jb) ? (double)X[(size_t)(rb + i) + (size_t)j * ldx] : 0.0;
   }
   __syncthreads();
-  gram_atomic(tile, jb, G);
+  gram_atomic<kPW>(tile, jb, G);
 }
 
 // Loads the Gram accumulated in Gin as a symmetric LDS matrix, adds the
@@ -74,7 +81,7 @@ __global__ __launch_bounds__(256) void k_panel_gram(const Tin* __restrict__ X, i
 // beyond jb.  sigma = 11 (mr jb + jb (jb + 1)) u tr(G).
 __device__ __forceinline__ void load_gram(const double* Gin, int jb, int mr, int shift, double* S,
                                           double* red) {
-  for (int e = threadIdx.x; e < 4096; e += 256) {
+  for (int e = threadIdx.x; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6;
     const int src = (i <= j) ? i + j * 64 : j + i * 64;
     double v = 0.0;
@@ -85,13 +92,13 @@ __device__ __forceinline__ void load_gram(const double* Gin, int jb, int mr, int
   __syncthreads();
   if (shift) {
     double tr = 0.0;
-    for (int i = threadIdx.x; i < jb; i += 256) tr += S[i * kLdt + i];
+    for (int i = threadIdx.x; i < jb; i += kPT) tr += S[i * kLdt + i];
     tr = block_sum(tr, red);
     const double sigma = 11.0 * ((double)mr * jb + (double)jb * (jb + 1)) * kU64 * tr;
     if (threadIdx.x < jb) S[threadIdx.x * kLdt + threadIdx.x] += sigma;
     __syncthreads();
   }
-  pad_identity(S, jb);
+  pad_identity<kPW>(S, jb);
 }
 
 // One Cholesky QR pass on a 64-row tile per work-group: R = chol(G (+ shift)),
@@ -99,7 +106,7 @@ __device__ __forceinline__ void load_gram(const double* Gin, int jb, int mr, int
 // 64 x 64 problem, identical in all of them); work-group 0 also accumulates
 // Racc <- R Racc (Racc <- R when first).
 template <typename Tin>
-__global__ __launch_bounds__(256) void k_panel_cholpass(
+__global__ __launch_bounds__(kPT) void k_panel_cholpass(
     const double* __restrict__ Gin, int shift, int first, double* __restrict__ Racc,
     int* __restrict__ status, const Tin* __restrict__ X, int ldx, int mr, int jb,
     double* __restrict__ Xout, int ldo, double* __restrict__ Gout) {
@@ -107,38 +114,38 @@ __global__ __launch_bounds__(256) void k_panel_cholpass(
   __shared__ double S1[64 * kLdt];
   __shared__ double S2[64 * kLdt];
   __shared__ double buf[512];
-  __shared__ double red[4];
+  __shared__ double red[kPW];
   const int t = threadIdx.x;
   load_gram(Gin, jb, mr, shift, S0, red);
-  double x[16], z[16];
-  regs_load(S0, x);
-  const bool ok = reg_cholesky_inv(x, z, buf);
+  double x[kPR], z[kPR];
+  regs_load<kPW>(S0, x);
+  const bool ok = reg_cholesky_inv<kPW>(x, z, buf);
   if (!ok && blockIdx.x == 0 && t == 0) atomicOr(status, 1);
-  regs_store_t(S1, z, jb);                      // S1 = R^{-1} (zero outside jb x jb)
+  regs_store_t<kPW>(S1, z, jb);                      // S1 = R^{-1} (zero outside jb x jb)
   __syncthreads();
   if (blockIdx.x == 0) {
-    regs_store(S0, x);                          // S0 = R
+    regs_store<kPW>(S0, x);                          // S0 = R
     if (first) {
-      wg_store64(S0, Racc);
+      wg_store64<kPW>(S0, Racc);
     } else {
       __syncthreads();
-      wg_load64(Racc, S2);
-      wg_matmul(S0, S2, S2);
-      wg_store64(S2, Racc);
+      wg_load64<kPW>(Racc, S2);
+      wg_matmul<kPW>(S0, S2, S2);
+      wg_store64<kPW>(S2, Racc);
     }
   }
   const int rb = blockIdx.x * 64;
-  for (int e = t; e < 64 * 64; e += 256) {
+  for (int e = t; e < 64 * 64; e += kPT) {
     const int i = e & 63, j = e >> 6;
     S0[i * kLdt + j] = (rb + i < mr && j < jb) ? (double)X[(size_t)(rb + i) + (size_t)j * ldx] : 0.0;
   }
   __syncthreads();
-  wg_matmul(S0, S1, S0);
-  for (int e = t; e < 64 * 64; e += 256) {
+  wg_matmul<kPW>(S0, S1, S0);
+  for (int e = t; e < 64 * 64; e += kPT) {
     const int i = e & 63, j = e >> 6;
     if (rb + i < mr && j < jb) Xout[(size_t)(rb + i) + (size_t)j * ldo] = S0[i * kLdt + j];
   }
-  gram_atomic(S0, jb, Gout);
+  gram_atomic<kPW>(S0, jb, Gout);
 }
 
 // Last Cholesky QR pass fused with the Householder reconstruction and the
@@ -154,7 +161,7 @@ __global__ __launch_bounds__(256) void k_panel_cholpass(
 // computes the 64 x 64 part (identically); work-group 0 writes R, L1, T and
 // Racc, and each work-group writes Y = Q1 Mmat and Yhat = Y T^T of its rows.
 template <typename Tw, typename Acc>
-__global__ __launch_bounds__(256) void k_panel_final_y(
+__global__ __launch_bounds__(kPT) void k_panel_final_y(
     const double* __restrict__ Gin, int jb, int mr,
     const double* __restrict__ Q1, int ldq,           // FP64 panel basis before the last pass
     double* __restrict__ Racc, Tw* __restrict__ Mst, int ldm, int j0,
@@ -167,37 +174,37 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
   __shared__ double buf[512];
   __shared__ double cbuf[128];
   __shared__ double sgn[64];
-  __shared__ double red[4];
+  __shared__ double red[kPW];
   const int t = threadIdx.x;
-  const Own o;
-  double x[16], v[16], w[16];
+  const Own<kPW> o;
+  double x[kPR], v[kPR], w[kPR];
   // R2 and R2^{-1}
   load_gram(Gin, jb, mr, 0, A0, red);
-  regs_load(A0, x);
+  regs_load<kPW>(A0, x);
   {
-    double z[16];
-    if (!reg_cholesky_inv(x, z, buf) && blockIdx.x == 0 && t == 0) atomicOr(status, 1);
+    double z[kPR];
+    if (!reg_cholesky_inv<kPW>(x, z, buf) && blockIdx.x == 0 && t == 0) atomicOr(status, 1);
     __syncthreads();
-    regs_store(A0, x);                                 // A0 = R2
-    regs_store_t(A1, z);                               // A1 = R2^{-1}
+    regs_store<kPW>(A0, x);                                 // A0 = R2
+    regs_store_t<kPW>(A1, z);                               // A1 = R2^{-1}
   }
   if (blockIdx.x == 0) {                               // Racc <- R2 Racc (A2 as scratch)
     __syncthreads();
-    wg_load64(Racc, A2);
-    wg_matmul(A0, A2, A2);
-    wg_store64(A2, Racc);
+    wg_load64<kPW>(Racc, A2);
+    wg_matmul<kPW>(A0, A2, A2);
+    wg_store64<kPW>(A2, Racc);
   }
   // A2 = Q2top = Q1top R2^{-1} (zero outside jb x jb), identity-padded
-  for (int e = t; e < 4096; e += 256) {
+  for (int e = t; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6;
     A2[i * kLdt + j] = (i < jb && j < jb) ? Q1[i + (size_t)j * ldq] : 0.0;
   }
   __syncthreads();
-  wg_matmul(A2, A1, A2);
-  pad_identity(A2, jb);
-  regs_load(A2, x);
+  wg_matmul<kPW>(A2, A1, A2);
+  pad_identity<kPW>(A2, jb);
+  regs_load<kPW>(A2, x);
 #pragma unroll
-  for (int qq = 0; qq < 16; ++qq) {
+  for (int qq = 0; qq < kPR; ++qq) {
     v[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
     w[qq] = v[qq];
   }
@@ -206,10 +213,10 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
   // the registers, so the column published next holds zeros above the diagonal
   // and the updates need no masks; rows k of V and W are restored by their
   // owner after the update.
-  for (int wk = 0; wk < 4; ++wk)
+  for (int wk = 0; wk < kPW; ++wk)
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int k = 16 * wk + q;
+  for (int q = 0; q < kPR; ++q) {
+    const int k = kPR * wk + q;
     double* rk = A0 + k * kLdt;                        // row k of U
     double* cb = cbuf + (q & 1) * 64;                  // column k of the active matrix
     double* rv = buf + (q & 1) * 128;                  // row k of V (unscaled)
@@ -221,7 +228,7 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
     }
     if (o.c == k) {
 #pragma unroll
-      for (int qq = 0; qq < 16; ++qq) cb[o.r0 + qq] = x[qq];
+      for (int qq = 0; qq < kPR; ++qq) cb[o.r0 + qq] = x[qq];
     }
     __syncthreads();
     const double dkk = rk[k];
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
     const double wkc = rw[o.c];
     const double wk2 = wkc * ip;
 #pragma unroll
-    for (int qq = 0; qq < 16; ++qq) {
+    for (int qq = 0; qq < kPR; ++qq) {
       const double cik = cb[o.r0 + qq];                // L1[i][k] * piv below the diagonal
       x[qq] = fma(-cik, uk2, x[qq]);
       v[qq] = fma(-rk[o.r0 + qq], vkc, v[qq]);
@@ -248,33 +255,33 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
   }
   __syncthreads();
   // Mmat = R2^{-1} V^T -> A2
-  regs_store_t(A2, v);
+  regs_store_t<kPW>(A2, v);
   __syncthreads();
-  wg_matmul(A1, A2, A2);
+  wg_matmul<kPW>(A1, A2, A2);
   // T = -U S W^T -> A0 (U has the modified pivots dkk - sg on its diagonal)
-  regs_store_t(A1, w);
+  regs_store_t<kPW>(A1, w);
 #pragma unroll
-  for (int qq = 0; qq < 16; ++qq) {
+  for (int qq = 0; qq < kPR; ++qq) {
     const int i = o.r0 + qq;
     const double u = A0[i * kLdt + o.c];
     const double uv = (i == o.c) ? u - sgn[i] : u;
     A0[i * kLdt + o.c] = -uv * sgn[o.c];
   }
   __syncthreads();
-  wg_matmul(A0, A1, A0);
+  wg_matmul<kPW>(A0, A1, A0);
   // T rounded to the storage precision (the same values Yhat and the stored T use)
-  for (int e = t; e < 4096; e += 256) {
+  for (int e = t; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6;
     const double tv = (i <= j && i < jb && j < jb) ? (double)(Tw)A0[i * kLdt + j] : 0.0;
     A0[i * kLdt + j] = tv;
   }
   __syncthreads();
   if (blockIdx.x == 0) {
-    for (int e = t; e < 4096; e += 256) Tout[e] = (Tw)A0[(e & 63) * kLdt + (e >> 6)];
+    for (int e = t; e < 4096; e += kPT) Tout[e] = (Tw)A0[(e & 63) * kLdt + (e >> 6)];
     // R = S R_total and the strictly lower L1 into the factor storage
     __threadfence();
     __syncthreads();
-    for (int e = t; e < 4096; e += 256) {
+    for (int e = t; e < 4096; e += kPT) {
       const int i = e & 63, j = e >> 6;
       if (i < jb && j < jb) {
         const double rv = (i <= j) ? sgn[i] * Racc[i + j * 64] : A3[i * kLdt + j];
@@ -284,13 +291,13 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
   }
   // this tile's Householder vectors: rows >= jb from Q1 Mmat, rows < jb from L1
   const int rb = blockIdx.x * 64;
-  for (int e = t; e < 4096; e += 256) {
+  for (int e = t; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6;
     A1[i * kLdt + j] = (rb + i < mr && rb + i >= jb && j < jb) ? Q1[(size_t)(rb + i) + (size_t)j * ldq] : 0.0;
   }
   __syncthreads();
-  wg_matmul(A1, A2, A1);
-  for (int e = t; e < 4096; e += 256) {
+  wg_matmul<kPW>(A1, A2, A1);
+  for (int e = t; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6, row = rb + i;
     double y = (double)(Tw)A1[i * kLdt + j];
     if (row < jb) y = (row > j) ? (double)(Tw)A3[row * kLdt + j] : (row == j ? 1.0 : 0.0);
@@ -303,17 +310,17 @@ __global__ __launch_bounds__(256) void k_panel_final_y(
   if (Wpart) {
     // look-ahead: this tile's share of W = Y^T C for the next ncn columns
     // (C = Cn, rows of the panel), reduced over the tiles by k_wy_reduce
-    for (int e = t; e < 4096; e += 256) {
+    for (int e = t; e < 4096; e += kPT) {
       const int i = e & 63, c = e >> 6;
       A3[i * kLdt + c] = (rb + i < mr && c < ncn) ? (double)Cn[(size_t)(rb + i) + (size_t)c * ldm] : 0.0;
     }
     __syncthreads();
-    wg_matmul(A1, A3, A0, true);
-    for (int e = t; e < 64 * ncn; e += 256)
+    wg_matmul<kPW>(A1, A3, A0, true);
+    for (int e = t; e < 64 * ncn; e += kPT)
       Wpart[(size_t)blockIdx.x * 64 * ncn + e] = (Acc)A0[(e & 63) * kLdt + (e >> 6)];
   }
-  wg_matmul(A1, A2, A1);
-  for (int e = t; e < 4096; e += 256) {
+  wg_matmul<kPW>(A1, A2, A1);
+  for (int e = t; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6, row = rb + i;
     if (row < mr) Yhat[(size_t)row + (size_t)j * ldy] = (Tw)A1[i * kLdt + j];
   }
@@ -617,7 +624,7 @@ __global__ __launch_bounds__(256) void k_wy_u(
     const int e = t + 256 * q, i = e & 63, c = e >> 6;
     if (r0 + i < mr && c0 + c < nc) C[(size_t)(r0 + i) + (size_t)(c0 + c) * ldc] = (Tw)tile[i * kLdt + c];
   }
-  if (Gnext != nullptr && blockIdx.y == 0 && blockIdx.x > 0) gram_atomic(tile, jbn, Gnext);
+  if (Gnext != nullptr && blockIdx.y == 0 && blockIdx.x > 0) gram_atomic<4>(tile, jbn, Gnext);
 }
 
 // ---------------------------------------------------------------- host side
@@ -690,7 +697,7 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
   int side_pending = -1;            // last step whose side-stream update is not yet awaited
   {
     const int jb = f.k < f.nb ? f.k : f.nb;
-    hipLaunchKernelGGL((k_panel_gram<Tw>), dim3(ceil_div(r, 64)), dim3(256), 0, ctx.stream,
+    hipLaunchKernelGGL((k_panel_gram<Tw>), dim3(ceil_div(r, 64)), dim3(kPT), 0, ctx.stream,
                        M, ld, r, jb, Gall);
   }
   for (int j = 0; j < f.np; ++j) {
@@ -707,14 +714,14 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
     // Cholesky with its inverse (2 jb^3 / 3); bytes: X in, Xout out
     const double pass_flops = 4.0 * mr * jb * jb + 2.0 * jb * jb * jb / 3.0;
     ktimer_begin(ctx, kKPanelCholPass, pass_flops, (double)mr * jb * (sizeof(Tw) + 8));
-    hipLaunchKernelGGL((k_panel_cholpass<Tw>), dim3(tiles), dim3(256), 0, ctx.stream,
+    hipLaunchKernelGGL((k_panel_cholpass<Tw>), dim3(tiles), dim3(kPT), 0, ctx.stream,
                        G0, 1, 1, Racc, f.status, P, ld, mr, jb, Q0, mr, G1);
     ktimer_end(ctx, kKPanelCholPass);
     const double* Qlast = Q0;
     const double* Glast = G1;
     if (f.passes >= 3) {
       ktimer_begin(ctx, kKPanelCholPass, pass_flops, (double)mr * jb * 16);
-      hipLaunchKernelGGL((k_panel_cholpass<double>), dim3(tiles), dim3(256), 0, ctx.stream,
+      hipLaunchKernelGGL((k_panel_cholpass<double>), dim3(tiles), dim3(kPT), 0, ctx.stream,
                          G1, 0, 0, Racc, f.status, Q0, mr, mr, jb, Q1, mr, G2);
       ktimer_end(ctx, kKPanelCholPass);
       Qlast = Q1;
@@ -746,7 +753,7 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
     // and Yhat = Y T^T (2 mr jb^2 each); bytes: Q1 in, Y and Yhat out
     ktimer_begin(ctx, kKPanelFinal, 4.0 * mr * jb * jb + 11.0 * jb * jb * jb / 3.0,
                  (double)mr * jb * (8 + 2 * sizeof(Tw)));
-    hipLaunchKernelGGL((k_panel_final_y<Tw, Acc>), dim3(tiles), dim3(256), 0, ctx.stream,
+    hipLaunchKernelGGL((k_panel_final_y<Tw, Acc>), dim3(tiles), dim3(kPT), 0, ctx.stream,
                        Glast, jb, mr, Qlast, mr, Racc, M, ld, j0, Tb + (size_t)j * 4096,
                        Yh + f.yoff[j], mr, f.status, (const Tw*)Ctr, la ? jbn : 0, Wpart);
     ktimer_end(ctx, kKPanelFinal);

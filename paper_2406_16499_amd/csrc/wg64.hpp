@@ -1,4 +1,4 @@
-// 64 x 64 FP64 building blocks for one 256-thread work-group (gfx950).
+// 64 x 64 FP64 building blocks for one work-group of NW waves (gfx950).
 #pragma once
 #include "common.hpp"
 
@@ -7,82 +7,109 @@ namespace lsq {
 constexpr int kLdt = kMaxNb + 1;   // padded LDS row stride for 64-wide FP64 tiles
 
 // ---------------------------------------------------------------------------
-// 64 x 64 dense kernels for one 256-thread work-group.
+// 64 x 64 dense kernels for one work-group of NW waves (64 NW threads).
 //
-// Thread t owns column c = t & 63 of rows r0 .. r0+15, r0 = 16 (t >> 6), and
-// keeps those 16 entries in registers.  The sequential algorithms (Cholesky,
-// triangular inverse, LU, triangular solve for T) are right-looking; in each
-// step only the pivot row or column travels through a double-buffered LDS line,
-// so there is one barrier per step and no LDS read-modify-write traffic.
-// Dense 64 x 64 products run on FP64 MFMA from row-major LDS tiles [64][kLdt].
+// Thread t owns column c = t & 63 of rows r0 .. r0 + R - 1 (R = 64 / NW,
+// r0 = R (t >> 6)) and keeps those R entries in registers.  The sequential
+// algorithms (Cholesky, triangular inverse, LU, triangular solve for T) are
+// right-looking; in each step only the pivot rows or column travel through a
+// double-buffered LDS line, so there is one barrier per step and no LDS
+// read-modify-write traffic.  With NW = 8 two waves share each SIMD and hide
+// each other's LDS and dependency latency.  Dense 64 x 64 products run on
+// FP64 MFMA from row-major LDS tiles [64][kLdt].
 // ---------------------------------------------------------------------------
+template <int NW>
 struct Own {
+  static constexpr int R = 64 / NW;
   int c, w, r0;      // w and r0 are wave-uniform (scalar registers)
   __device__ Own()
-      : c(threadIdx.x & 63), w(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)), r0(16 * w) {}
+      : c(threadIdx.x & 63), w(__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)), r0(R * w) {}
 };
 
-__device__ __forceinline__ void regs_load(const double* S, double x[16]) {
-  const Own o;
+template <int NW>
+__device__ __forceinline__ void regs_load(const double* S, double* x) {
+  const Own<NW> o;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) x[q] = S[(o.r0 + q) * kLdt + o.c];
+  for (int q = 0; q < Own<NW>::R; ++q) x[q] = S[(o.r0 + q) * kLdt + o.c];
 }
-__device__ __forceinline__ void regs_store(double* S, const double x[16]) {
-  const Own o;
+template <int NW>
+__device__ __forceinline__ void regs_store(double* S, const double* x) {
+  const Own<NW> o;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) S[(o.r0 + q) * kLdt + o.c] = x[q];
+  for (int q = 0; q < Own<NW>::R; ++q) S[(o.r0 + q) * kLdt + o.c] = x[q];
 }
 // S = x^T restricted to the leading jb x jb block (zero elsewhere): the
 // thread's register column becomes row c of S.
-__device__ __forceinline__ void regs_store_t(double* S, const double x[16], int jb = 64) {
-  const Own o;
+template <int NW>
+__device__ __forceinline__ void regs_store_t(double* S, const double* x, int jb = 64) {
+  const Own<NW> o;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) S[o.c * kLdt + o.r0 + q] = (o.c < jb && o.r0 + q < jb) ? x[q] : 0.0;
+  for (int q = 0; q < Own<NW>::R; ++q)
+    S[o.c * kLdt + o.r0 + q] = (o.c < jb && o.r0 + q < jb) ? x[q] : 0.0;
 }
 
-// acc = op(A) * B for 64 x 64 LDS matrices; wave w computes the 32 x 32 quadrant
-// (w >> 1, w & 1).  fp64 16x16x4 fragments: lane l supplies A[l%16][k + l/16],
-// B[k + l/16][l%16]; accumulator register r holds row 4r + l/16, column l%16.
-__device__ __forceinline__ void mm64_acc(const double* A, bool transA, const double* B, f64x4 acc[2][2]) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+// acc = op(A) * B for 64 x 64 LDS matrices.  The 4 x 4 grid of 16 x 16 blocks
+// is split over the waves: wave w takes BR = 8 / NW block rows starting at
+// 16 BR (w >> 1) and the two block columns starting at 32 (w & 1).
+// fp64 16x16x4 fragments: lane l supplies A[l%16][k + l/16], B[k + l/16][l%16];
+// accumulator register r holds row 4r + l/16, column l%16.
+template <int NW>
+__device__ __forceinline__ void mm64_acc(const double* A, bool transA, const double* B,
+                                         f64x4 acc[8 / NW][2]) {
+  constexpr int BR = 8 / NW;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rb = 16 * BR * (w >> 1), cb = 32 * (w & 1);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < BR; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.0;
 #pragma unroll 4
   for (int k0 = 0; k0 < 64; k0 += 4) {
-    double a[2], b[2];
+    double a[BR], b[2];
+    const int kk = k0 + (l >> 4);
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int row = 32 * wr + 16 * q + (l & 15), kk = k0 + (l >> 4);
+    for (int q = 0; q < BR; ++q) {
+      const int row = rb + 16 * q + (l & 15);
       a[q] = transA ? A[kk * kLdt + row] : A[row * kLdt + kk];
-      b[q] = B[kk * kLdt + 32 * wc + 16 * q + (l & 15)];
     }
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int q = 0; q < 2; ++q) b[q] = B[kk * kLdt + cb + 16 * q + (l & 15)];
+#pragma unroll
+    for (int bi = 0; bi < BR; ++bi)
 #pragma unroll
       for (int bj = 0; bj < 2; ++bj)
         acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
   }
 }
-__device__ __forceinline__ void mm64_store(const f64x4 acc[2][2], double* C) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6, wr = w >> 1, wc = w & 1;
+// (row, column) of accumulator element (bi, bj, r) of this lane
+template <int NW>
+__device__ __forceinline__ int mm64_row(int bi, int r) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return 16 * (8 / NW) * (w >> 1) + 16 * bi + 4 * r + (l >> 4);
+}
+template <int NW>
+__device__ __forceinline__ int mm64_col(int bj) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return 32 * (w & 1) + 16 * bj + (l & 15);
+}
+template <int NW>
+__device__ __forceinline__ void mm64_store(const f64x4 acc[8 / NW][2], double* C) {
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < 8 / NW; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        C[(32 * wr + 16 * bi + 4 * r + (l >> 4)) * kLdt + 32 * wc + 16 * bj + (l & 15)] = acc[bi][bj][r];
+      for (int r = 0; r < 4; ++r) C[mm64_row<NW>(bi, r) * kLdt + mm64_col<NW>(bj)] = acc[bi][bj][r];
 }
 // C = op(A) * B; C may alias A or B.
+template <int NW>
 __device__ __forceinline__ void wg_matmul(const double* A, const double* B, double* C, bool transA = false) {
-  f64x4 acc[2][2];
-  mm64_acc(A, transA, B, acc);
+  f64x4 acc[8 / NW][2];
+  mm64_acc<NW>(A, transA, B, acc);
   __syncthreads();
-  mm64_store(acc, C);
+  mm64_store<NW>(acc, C);
   __syncthreads();
 }
 
@@ -114,16 +141,18 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // are published with zeros left of their diagonal, so the updates need no
 // masks: finished rows see zero multipliers, and the pivot rows themselves are
 // overwritten by their owner after the update.  buf: 8 x 64 LDS doubles.
-__device__ __forceinline__ bool reg_cholesky_inv(double x[16], double z[16], double* buf) {
-  const Own o;
+template <int NW>
+__device__ __forceinline__ bool reg_cholesky_inv(double* x, double* z, double* buf) {
+  constexpr int R = Own<NW>::R;
+  const Own<NW> o;
   bool ok = true;
 #pragma unroll
-  for (int qq = 0; qq < 16; ++qq) z[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
-  for (int wk = 0; wk < 4; ++wk) {
+  for (int qq = 0; qq < R; ++qq) z[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
+  for (int wk = 0; wk < NW; ++wk) {
 #pragma unroll
-    for (int q = 0; q < 16; q += 2) {
-      const int k = 16 * wk + q;
-      double* g0 = buf + ((q >> 1) & 1) * 256;        // row k of G, row k + 1, rows k, k + 1 of z
+    for (int q = 0; q < R; q += 2) {
+      const int k = R * wk + q;
+      double* g0 = buf + ((k >> 1) & 1) * 256;        // row k of G, row k + 1, rows k, k + 1 of z
       double* g1 = g0 + 64;
       double* z0 = g0 + 128;
       double* z1 = g0 + 192;
@@ -155,7 +184,7 @@ __device__ __forceinline__ bool reg_cholesky_inv(double x[16], double z[16], dou
       const double ax = R0 * i0 - t * R1, bx = R1 * i1;
       const double az = Z0 * i0 - t * Z1, bz = Z1 * i1;
 #pragma unroll
-      for (int qq = 0; qq < 16; ++qq) {
+      for (int qq = 0; qq < R; ++qq) {
         const double a0 = g0[o.r0 + qq], a1 = g1[o.r0 + qq];
         x[qq] = fma(-a1, bx, fma(-a0, ax, x[qq]));
         z[qq] = fma(-a1, bz, fma(-a0, az, z[qq]));
@@ -175,56 +204,52 @@ __device__ __forceinline__ bool reg_cholesky_inv(double x[16], double z[16], dou
 // identity-padded).  Right-looking back substitution with the diagonal
 // reciprocals computed up front; the owner of the finished row restores it
 // after the (unmasked) update.  buf: 2 x 64 + 64 doubles.
-__device__ __forceinline__ void reg_upper_inverse(const double* R, double x[16], double* buf) {
-  const Own o;
+template <int NW>
+__device__ __forceinline__ void reg_upper_inverse(const double* R, double* x, double* buf) {
+  constexpr int RR = Own<NW>::R;
+  const Own<NW> o;
   double* dinv = buf + 128;
   if (threadIdx.x < 64) dinv[threadIdx.x] = rcp64(R[threadIdx.x * kLdt + threadIdx.x]);
 #pragma unroll
-  for (int qq = 0; qq < 16; ++qq) x[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
+  for (int qq = 0; qq < RR; ++qq) x[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
   __syncthreads();
-  for (int wi = 3; wi >= 0; --wi) {
+  for (int wi = NW - 1; wi >= 0; --wi) {
 #pragma unroll
-    for (int q = 15; q >= 0; --q) {
-      const int i = 16 * wi + q;
-      double* rb = buf + (q & 1) * 64;
+    for (int q = RR - 1; q >= 0; --q) {
+      const int i = RR * wi + q;
+      double* rb = buf + (i & 1) * 64;
       if (o.w == wi) rb[o.c] = x[q] * dinv[i];
       __syncthreads();
       const double xi = rb[o.c];
 #pragma unroll
-      for (int qq = 0; qq < 16; ++qq) x[qq] = fma(-R[(o.r0 + qq) * kLdt + i], xi, x[qq]);
+      for (int qq = 0; qq < RR; ++qq) x[qq] = fma(-R[(o.r0 + qq) * kLdt + i], xi, x[qq]);
       if (o.w == wi) x[q] = xi;
     }
   }
 }
 
 // Identity padding of a 64 x 64 LDS matrix beyond jb (upper triangular or symmetric use).
+template <int NW>
 __device__ void pad_identity(double* S, int jb) {
-  const Own o;
+  const Own<NW> o;
 #pragma unroll
-  for (int qq = 0; qq < 16; ++qq) {
+  for (int qq = 0; qq < Own<NW>::R; ++qq) {
     const int i = o.r0 + qq;
     if (i >= jb || o.c >= jb) S[i * kLdt + o.c] = (i == o.c) ? 1.0 : 0.0;
   }
   __syncthreads();
 }
 
+template <int NW>
 __device__ void wg_load64(const double* g, double* s) {   // global col-major ld 64 -> LDS
-  for (int e = threadIdx.x; e < 4096; e += 256) s[(e & 63) * kLdt + (e >> 6)] = g[e];
+  for (int e = threadIdx.x; e < 4096; e += 64 * NW) s[(e & 63) * kLdt + (e >> 6)] = g[e];
   __syncthreads();
 }
+template <int NW>
 __device__ void wg_store64(const double* s, double* g) {
   __syncthreads();
-  for (int e = threadIdx.x; e < 4096; e += 256) g[e] = s[(e & 63) * kLdt + (e >> 6)];
+  for (int e = threadIdx.x; e < 4096; e += 64 * NW) g[e] = s[(e & 63) * kLdt + (e >> 6)];
   __syncthreads();
 }
-// symmetric G from its accumulated upper storage (col-major, ld 64)
-__device__ void wg_load_sym(const double* g, double* s) {
-  for (int e = threadIdx.x; e < 4096; e += 256) {
-    const int i = e & 63, j = e >> 6;
-    s[i * kLdt + j] = (i <= j) ? g[i + j * 64] : g[j + i * 64];
-  }
-  __syncthreads();
-}
-
 
 }  // namespace lsq

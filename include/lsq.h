@@ -143,11 +143,23 @@ typedef struct {
 /* Solve `count` independent instances of uneven size.  `res` (host array of
    `count`, nullable) receives one record per instance.  Returns the number of
    instances with info != 0, or -k for an invalid argument (-3: a problem
-   descriptor is invalid).  The instances run concurrently on the handle's
-   batch workers (streams of their own, one host thread each; see
-   lsq_set_batch_workers), longest estimated factorization first; work already
-   queued on the handle's stream completes before the first instance starts,
-   and every instance has finished when the call returns. */
+   descriptor is invalid).  Work already queued on the handle's stream
+   completes before the first instance starts, and every instance has
+   finished when the call returns.
+   Two executions (lsq_set_batch_mode):
+   - persistent (LSQ_BATCH_AUTO, the default) for opts.prec FP32 or FP64 (or
+     AUTO without selector weights) and opts.solver AUTO, IR or DIRECT: the
+     instances with m, n, p in [1, 1024] are solved on the handle's stream by
+     one launch with one work-group per instance (the longest first), which
+     factors the pair (Section 3) and runs classical refinement (Algorithms 2
+     and 4) entirely on the device: FP32 factors and corrections first, the
+     instances that do not meet tol again with FP64 factors (reported as
+     FP64 direct) when opts.escalate is set.  Instances that are not eligible
+     or still fail continue on the batch workers below, with the full ladder.
+   - batch workers (LSQ_BATCH_WORKERS, and every other option): the instances
+     run concurrently on the handle's batch workers (streams of their own, one
+     host thread each; see lsq_set_batch_workers), longest estimated
+     factorization first, each as lse_solve / gls_solve would run it. */
 int lsq_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
                       const lsq_opts* opts, lsq_result* res);
 /* Learned precision / solver selector (used when opts.prec is LSQ_PREC_AUTO
@@ -174,6 +186,10 @@ int lsq_selector_features(lsq_handle handle, const lsq_problem* problem, float* 
 /* Number of concurrent workers of the batched entry points (1..64, default
    8).  Returns -2 outside that range. */
 int lsq_set_batch_workers(lsq_handle handle, int workers);
+/* Execution of the batched entry points (see lsq_solve_batched).  Returns -2
+   for an unknown mode. */
+enum { LSQ_BATCH_AUTO = 0, LSQ_BATCH_WORKERS = 1 };
+int lsq_set_batch_mode(lsq_handle handle, int mode);
 
 /* Same-type conveniences: every descriptor must carry the matching type. */
 int lse_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,

@@ -83,10 +83,12 @@ int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p
 
 /* Kernel timing.  While enabled, HIP events are recorded on the handle's
  * stream around every launch of the named kernel kind ("panel_final_y",
- * "panel_cholpass", "wy_t", "wy_u", "dual_gemv"), and the launch's algorithmic
- * flops and bytes are added up (the step each kernel carries out is the one
- * cited at its launch site: Householder QR panels and updates of Section 4.1,
- * the residual of eq. aug-LSE / eq. aug-GLS).  NULL or "" disables; an unknown
+ * "panel_cholpass", "wy_t", "wy_u", "dual_gemv", and "batch_fp32" /
+ * "batch_fp64" for the persistent batched solver), and the launch's
+ * algorithmic flops and bytes are added up (the step each kernel carries out
+ * is the one cited at its launch site: Householder QR panels and updates of
+ * Section 4.1, the residual of eq. aug-LSE / eq. aug-GLS; for a batch launch
+ * the Householder flops of the instances' factorizations).  NULL or "" disables; an unknown
  * name returns -2.  lsq_dbg_timer_read synchronizes the stream, returns the
  * summed event durations (ms), the launch count and the summed flops and
  * bytes since the last enable or read, and resets those counters.  Any output

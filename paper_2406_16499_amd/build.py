@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblsq.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["qr.hip", "vec.hip", "blas.hip", "gmres.hip", "selector.hip", "api.hip"]
+SOURCES = ["qr.hip", "vec.hip", "blas.hip", "gmres.hip", "selector.hip", "batch.hip", "api.hip"]
 ARCH = "gfx950"
 
 

@@ -166,6 +166,7 @@ struct lsq_handle_st {
   Worker w;                                     // the handle's own (caller's) stream
   std::vector<std::unique_ptr<Worker>> pool;    // batched workers
   int batch_workers = 8;
+  int batch_mode = LSQ_BATCH_AUTO;
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
   std::string last_error;
@@ -885,6 +886,80 @@ int guard(lsq_handle h, const char* fn, const std::function<int()>& body) {
   h->last_error.clear();
   return guard_w(&h->w, &h->last_error, fn, body);
 }
+
+// Persistent batched execution of the eligible instances among todo (one
+// work-group per instance): the first rung in first_prec (FP32 or FP64), the
+// failures again in FP64 when escalating.  Writes res for the instances it
+// certifies and returns those left for the worker ladder, longest first.
+std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const std::vector<int>& todo,
+                                  const lsq_opts& o, int first_prec, lsq_result* res) {
+  Worker* w = &h->w;
+  Ctx& ctx = w->ctx;
+  const int count = (int)todo.size();
+  std::vector<BatchProb> hp(count);
+  std::vector<int> cur, rest;
+  size_t stride = 256;
+  for (int q = 0; q < count; ++q) {
+    const lsq_problem& p = probs[todo[q]];
+    hp[q] = BatchProb{p.type == LSQ_LSE ? 0 : 1, p.m, p.n, p.p, p.A, p.B, p.b, p.d, p.lda, p.ldb,
+                      p.x, p.y};
+    if (batch_eligible(hp[q])) {
+      cur.push_back(q);
+      stride = std::max(stride, batch_ws_bytes(hp[q]));
+    } else {
+      rest.push_back(todo[q]);
+    }
+  }
+  if (cur.empty()) return rest;
+  const int max_grid = kBatchBlocksPerCu * h->num_cu;
+  const int grid = std::min((int)cur.size(), max_grid);
+  w->arena.reset();
+  BatchProb* dprobs = ctx.ws->get<BatchProb>(count);
+  int* dorder = ctx.ws->get<int>(count);
+  int* dcounter = ctx.ws->get<int>(1);
+  BatchOut* dout = ctx.ws->get<BatchOut>(count);
+  char* dws = static_cast<char*>(ctx.ws->alloc(stride * (size_t)grid));
+  LSQ_HIP(hipMemcpyAsync(dprobs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, ctx.stream));
+  std::vector<BatchOut> hout(count);
+  std::vector<int> attempts(count, 0);
+  int prec = first_prec;
+  for (;;) {
+    LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * cur.size(), hipMemcpyHostToDevice, ctx.stream));
+    double flops = 0.0;
+    for (int q : cur) flops += batch_factor_flops(hp[q]);
+    batch_launch(ctx, prec == LSQ_PREC_FP64 ? 8 : 4, dprobs, dorder, (int)cur.size(), dcounter, dws,
+                 stride, std::min(grid, (int)cur.size()), o.tol, o.maxit, dout, flops);
+    LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
+    LSQ_HIP(hipStreamSynchronize(ctx.stream));
+    std::vector<int> failed;
+    for (int q : cur) {
+      ++attempts[q];
+      const BatchOut& bo = hout[q];
+      if (bo.info != 0) {
+        failed.push_back(q);
+        continue;
+      }
+      if (res) {
+        lsq_result& r = res[todo[q]];
+        r = lsq_result{};
+        r.info = 0;
+        r.prec_used = prec;
+        r.solver_used = prec == LSQ_PREC_FP64 ? LSQ_SOLVER_DIRECT : LSQ_SOLVER_IR;
+        r.attempts = attempts[q];
+        r.ir_steps = bo.steps;
+        for (int k = 0; k < 3; ++k) r.berr[k] = bo.berr[k];
+        r.berr_max = bo.berr_max;
+      }
+    }
+    if (failed.empty() || prec == LSQ_PREC_FP64 || !o.escalate) {
+      for (int q : failed) rest.push_back(todo[q]);
+      break;
+    }
+    cur = failed;
+    prec = LSQ_PREC_FP64;
+  }
+  return rest;
+}
 }  // namespace
 
 // ================================================================== C ABI ==
@@ -950,6 +1025,13 @@ int lsq_set_batch_workers(lsq_handle h, int workers) {
   if (!h) return -1;
   if (workers < 1 || workers > 64) return -2;
   h->batch_workers = workers;
+  return 0;
+}
+
+int lsq_set_batch_mode(lsq_handle h, int mode) {
+  if (!h) return -1;
+  if (mode != LSQ_BATCH_AUTO && mode != LSQ_BATCH_WORKERS) return fail(h, -2, "unknown batch mode");
+  h->batch_mode = mode;
   return 0;
 }
 
@@ -1152,7 +1234,23 @@ int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const l
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
-  const int nw = std::min(h->batch_workers, count);
+  const bool persistent =
+      h->batch_mode == LSQ_BATCH_AUTO &&
+      (o.solver == LSQ_SOLVER_AUTO || o.solver == LSQ_SOLVER_IR || o.solver == LSQ_SOLVER_DIRECT) &&
+      (o.prec == LSQ_PREC_FP32 || o.prec == LSQ_PREC_FP64 || (o.prec == LSQ_PREC_AUTO && !h->sel_w));
+  if (persistent) {
+    const int first = (o.prec == LSQ_PREC_FP64 || o.solver == LSQ_SOLVER_DIRECT) ? LSQ_PREC_FP64
+                                                                                : LSQ_PREC_FP32;
+    try {
+      LSQ_HIP(hipSetDevice(h->device));
+      order = batch_persistent(h, probs, order, o, first, res);
+    } catch (const HipError& e) {
+      return fail(h, 4, std::string("lsq_solve_batched: ") + e.where + " failed");
+    }
+    if (order.empty()) return 0;
+  }
+  const int todo = (int)order.size();
+  const int nw = std::min(h->batch_workers, todo);
   try {
     LSQ_HIP(hipSetDevice(h->device));
     LSQ_HIP(hipStreamSynchronize(h->w.stream));     // inputs produced on the caller's stream
@@ -1170,7 +1268,7 @@ int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const l
     Worker* w = h->pool[t].get();
     for (;;) {
       const int k = next.fetch_add(1);
-      if (k >= count) break;
+      if (k >= todo) break;
       const int i = order[k];
       const lsq_problem& q = probs[i];
       lsq_result* ri = res ? &res[i] : nullptr;
@@ -1446,7 +1544,7 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
 
 // ------------------------------------------------------------- timing --
 static const char* const kKernelNames[kKCount] = {"panel_final_y", "panel_cholpass", "wy_t", "wy_u",
-                                                  "dual_gemv"};
+                                                  "dual_gemv", "batch_fp32", "batch_fp64"};
 
 int lsq_dbg_timer_enable(lsq_handle h, const char* kernel) {
   if (!h) return -1;

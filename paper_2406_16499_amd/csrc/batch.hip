@@ -1,0 +1,1089 @@
+// Persistent batched solver: one work-group per instance.
+//
+// A batch of small LSE / GLS instances is solved by one launch of
+// kBatchBlocksPerCu work-groups per compute unit.  Each work-group takes the
+// next instance from a device counter (the host orders the instances longest
+// first) and carries out the whole method for it: the generalized RQ (LSE) or
+// generalized QR (GLS) factorization of Section 3 in precision T, then
+// classical refinement (Algorithms 2 and 4) with the correction solves of
+// Algorithms 1 and 3 in T and the augmented residual and stop test
+// (eq. lse-stop / gls-stop) in FP64.  Nothing waits on another work-group and
+// every work-group leaves the loop once the counter passes the batch, so the
+// grid always drains.
+//
+// The factorizations are column-by-column Householder QR (LAPACK's xGEQR2
+// convention: H = I - tau v v^T, v(j) = 1) with the trailing updates split
+// over the four waves, several columns per wave at a time.  The vector side of
+// a correction runs one wave per independent operation (applications of Q or
+// Q^T, triangular solves), so consecutive reflectors and triangular steps need
+// no work-group barrier; the waves meet at four barriers per correction.
+#include "engine.hpp"
+
+namespace lsq {
+
+namespace {
+
+constexpr int kBT = 256;                 // threads per work-group
+constexpr int kBW = kBT / 64;            // waves per work-group
+constexpr int kBS = kBatchMaxDim / 64;   // register slots per lane for one vector
+constexpr int kVecs = 9;                 // LDS vectors of length kBatchMaxDim
+
+// The out-of-line device functions below take their pointers in explicit
+// address spaces, so that their memory operations compile to global and LDS
+// instructions rather than generic (flat) ones.
+#define LSQ_GLB __attribute__((address_space(1)))
+#define LSQ_LDS __attribute__((address_space(3)))
+
+// Buffer loads with the hardware range check: an offset at or beyond the
+// resource's byte size reads as 0, so masked loads need neither a branch nor a
+// select on the loaded value (either would serialize the loads in flight).
+constexpr uint32_t kOob = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// Wave-uniform copies of values the compiler cannot prove uniform (the
+// arguments of out-of-line functions arrive in vector registers).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
+template <typename P>
+__device__ __forceinline__ LSQ_LDS P* uni(LSQ_LDS P* p) {
+  return (LSQ_LDS P*)(size_t)(unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(size_t)p);
+}
+
+// Wave sum with DPP: quad and row-mirror exchanges give every lane its
+// 16-lane row sum, and the four row sums are read out as scalars (the result
+// is uniform).  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ float lane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_val(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ T wsum(T v) {
+  v += dpp<0xB1>(v);     // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);     // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);    // row_half_mirror
+  v += dpp<0x140>(v);    // row_mirror
+  return (lane_val(v, 0) + lane_val(v, 16)) + (lane_val(v, 32) + lane_val(v, 48));
+}
+
+// Panel width and trailing-update column group of the blocked QR: the LDS
+// panel (kBatchMaxDim x (NB + 1)) fills about 70 KB in both precisions, so
+// two work-groups share a compute unit.
+template <typename T> struct QrCfg;
+template <> struct QrCfg<float> { static constexpr int NB = 16, CG = 4; };
+template <> struct QrCfg<double> { static constexpr int NB = 8, CG = 2; };
+
+template <typename T>
+struct BLds {
+  static constexpr int NB = QrCfg<T>::NB, CG = QrCfg<T>::CG, PS = NB + 1;
+  union {
+    struct {
+      T Ys[kBatchMaxDim * PS];       // panel, row-major with row stride PS
+      T Ts[NB * NB];                 // compact-WY triangle (row-major, upper)
+      T Gs[NB * NB];                 // Gram of the panel's reflectors
+      T Wb[kBW][NB * CG];            // per-wave Y^T C block
+      T Wp[kBW][NB * CG];            // per-wave T^T Y^T C block
+      T beta[NB], tau[NB];
+    } f;
+    T vec[kVecs][kBatchMaxDim];      // vectors of the correction solves
+  } u;
+  T red[kBW];
+  double dred[kBW * 6];
+  int next;
+};
+
+__device__ __forceinline__ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Sum over the work-group; every thread receives it.
+template <typename T>
+__device__ __forceinline__ T wg_sum1(T v, T* red) {
+  v = wsum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T s = 0;
+#pragma unroll
+  for (int i = 0; i < kBW; ++i) s += red[i];
+  return s;
+}
+
+__device__ __forceinline__ void wg_sum6(double v[6], double* red) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wsum(v[k]);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[(threadIdx.x >> 6) * 6 + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    double s = 0.0;
+    for (int i = 0; i < kBW; ++i) s += red[i * 6 + k];
+    v[k] = s;
+  }
+}
+
+// Reduce-scatter of NV (a power of two <= 64) per-lane values over the wave:
+// every lane returns the wave total of value index lane >> (6 - log2 NV).
+// Each halving step keeps the half of the values selected by one lane bit and
+// adds the partner lane's copy of it.
+template <typename T, int NV, int HALF, int MASK>
+__device__ __forceinline__ void rs_step(T (&v)[NV], int lane) {
+  if constexpr (HALF >= 1) {
+    const bool up = (lane & MASK) != 0;
+#pragma unroll
+    for (int k = 0; k < HALF; ++k) {
+      const T keep = up ? v[k + HALF] : v[k];
+      const T send = up ? v[k] : v[k + HALF];
+      v[k] = keep + __shfl_xor(send, MASK, 64);
+    }
+    rs_step<T, NV, HALF / 2, MASK / 2>(v, lane);
+  }
+}
+template <typename T, int NV>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[NV]) {
+  const int lane = threadIdx.x & 63;
+  rs_step<T, NV, NV / 2, 32>(v, lane);
+  T r = v[0];
+#pragma unroll
+  for (int mask = 32 / NV; mask > 0; mask >>= 1) r += __shfl_xor(r, mask, 64);
+  return r;
+}
+
+// ------------------------------------------------------------ Householder --
+// Blocked Householder QR (LAPACK's convention: H = I - tau v v^T, v(j) = 1;
+// Q = H_0 ... H_{k-1}; per panel H_j0 ... H_{j0+nb-1} = I - Y T Y^T with T
+// upper triangular).  A panel of NB columns is factored in LDS; its T comes
+// from the Gram Y^T Y; the trailing columns are updated with
+// C <- C - Y (T^T (Y^T C)), each wave streaming CG columns at a time through
+// registers (one read and one write of C per panel).
+
+// Panel rows j0 .. j0 + Lr of columns j0 .. j0 + nbj of M into Ys (columns
+// beyond nbj zero).  unit: load the reflector view (1 on the diagonal, 0
+// above) of a factored panel instead of the raw columns.
+template <typename T>
+__device__ __forceinline__ void stage_panel(const T* M, int ld, int j0, int nbj, int Lr, T* Ys,
+                                            bool unit) {
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  for (int a = 0; a < NB; ++a) {
+    const int ac = a < nbj ? a : 0;
+    for (int i = threadIdx.x; i < Lr; i += kBT) {
+      const T x = M[(size_t)(j0 + i) + (size_t)(j0 + ac) * ld];
+      T v = (!unit || i > a) ? x : (i == a ? (T)1 : (T)0);
+      Ys[i * PS + a] = a < nbj ? v : (T)0;
+    }
+  }
+  __syncthreads();
+}
+
+// Householder QR of the LDS panel (Lr x nbj).  On return Ys holds the
+// reflectors (unit diagonal, zeros above), f.beta the diagonal of R, f.tau the
+// scalars, and the strictly upper part of R has been written to M.
+template <typename T>
+__device__ __forceinline__ void panel_factor(BLds<T>& L, T* M, int ld, int j0, int nbj, int Lr) {
+  constexpr int PS = BLds<T>::PS;
+  T* Ys = L.u.f.Ys;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int a = 0; a < nbj; ++a) {
+    const T alpha = a < Lr ? Ys[a * PS + a] : (T)0;
+    T ss = 0;
+    for (int i = a + 1 + threadIdx.x; i < Lr; i += kBT) {
+      const T x = Ys[i * PS + a];
+      ss += x * x;
+    }
+    ss = wg_sum1(ss, L.red);
+    T tau = 0, scal = 1, beta = alpha;
+    if (ss > (T)0) {
+      const T nrm = sqrt(alpha * alpha + ss);
+      beta = alpha >= (T)0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = (T)1 / (alpha - beta);
+    }
+    for (int i = a + 1 + threadIdx.x; i < Lr; i += kBT) Ys[i * PS + a] *= scal;
+    if (threadIdx.x == 0) {
+      L.u.f.beta[a] = beta;
+      L.u.f.tau[a] = tau;
+      if (a < Lr) Ys[a * PS + a] = 1;
+    }
+    __syncthreads();
+    // H_a applied to the panel's columns a+1 .. nbj-1, one column per wave
+    if (tau != (T)0) {
+      for (int b = a + 1 + w; b < nbj; b += kBW) {
+        T d = 0;
+        for (int i = a + lane; i < Lr; i += 64) d += Ys[i * PS + a] * Ys[i * PS + b];
+        d = wsum(d) * tau;
+        for (int i = a + lane; i < Lr; i += 64) Ys[i * PS + b] -= d * Ys[i * PS + a];
+      }
+    }
+    __syncthreads();
+  }
+  // R above the diagonal to M; Y keeps zeros there
+  for (int e = threadIdx.x; e < nbj * nbj; e += kBT) {
+    const int i = e % nbj, a = e / nbj;
+    if (i < a && i < Lr) {
+      M[(size_t)(j0 + i) + (size_t)(j0 + a) * ld] = Ys[i * PS + a];
+      Ys[i * PS + a] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+// Ts (upper, row-major NB x NB) of the panel in Ys with scalars tau[0:nbj):
+// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (Y(:, 0:j)^T y_j).
+template <typename T>
+__device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* tau) {
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  const T* Ys = L.u.f.Ys;
+  T* Ts = L.u.f.Ts;
+  T* Gs = L.u.f.Gs;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int NP = NB * (NB - 1) / 2;
+  for (int pidx = w; pidx < NP; pidx += kBW) {
+    // pair (a, b), a < b, enumerated column by column
+    int b = 1, base = 0;
+    while (base + b <= pidx) { base += b; ++b; }
+    const int a = pidx - base;
+    T d = 0;
+    if (b < nbj)
+      for (int i = b + lane; i < Lr; i += 64) d += Ys[i * PS + a] * Ys[i * PS + b];
+    d = wsum(d);
+    if (lane == 0) Gs[a * NB + b] = d;
+  }
+  __syncthreads();
+  if (w == 0) {
+    for (int e = lane; e < NB * NB; e += 64) Ts[e] = 0;
+    for (int j = 0; j < nbj; ++j) {
+      const T tj = tau[j];
+      if (lane < j) {
+        T sacc = 0;
+        for (int l = lane; l < j; ++l) sacc += Ts[lane * NB + l] * Gs[l * NB + j];
+        Ts[lane * NB + j] = -tj * sacc;
+      }
+      if (lane == j) Ts[j * NB + j] = tj;
+    }
+  }
+  __syncthreads();
+}
+
+// C (Lr x nc, ldc) <- C - Y (T^T (Y^T C)) with Y = Ys (Lr x NB), T = Ts.
+template <typename T>
+__device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc, int nc) {
+  constexpr int NB = QrCfg<T>::NB, CG = QrCfg<T>::CG, PS = NB + 1, NV = NB * CG;
+  constexpr int SH = NV == 64 ? 0 : (NV == 32 ? 1 : (NV == 16 ? 2 : 3));   // 6 - log2 NV
+  const T* Ys = L.u.f.Ys;
+  const T* Ts = L.u.f.Ts;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T* Wb = L.u.f.Wb[w];
+  T* Wp = L.u.f.Wp[w];
+  const int nq = (Lr + 63) >> 6;
+  if (nc <= 0) return;
+  const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lr) * sizeof(T));
+  for (int c0 = CG * w; c0 < nc; c0 += CG * kBW) {
+    // W = Y^T C for CG columns: per-lane partial sums, then a reduce-scatter
+    T acc[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) acc[e] = 0;
+#pragma unroll 4
+    for (int q = 0; q < nq; ++q) {
+      const int i = lane + 64 * q;
+      const bool ok = i < Lr;
+      const int ic = ok ? i : 0;
+      T cq[CG];
+#pragma unroll
+      for (int cc = 0; cc < CG; ++cc)
+        cq[cc] = bload<T>(rs, (ok && c0 + cc < nc) ? (uint32_t)((i + (size_t)(c0 + cc) * ldc) * sizeof(T)) : kOob);
+#pragma unroll
+      for (int a = 0; a < NB; ++a) {
+        const T y = Ys[ic * PS + a];
+#pragma unroll
+        for (int cc = 0; cc < CG; ++cc) acc[a * CG + cc] += y * cq[cc];
+      }
+    }
+    const T wsum = wave_reduce_scatter<T, NV>(acc);
+    if ((lane & ((1 << SH) - 1)) == 0) Wb[lane >> SH] = wsum;
+    // W' = T^T W (same wave: LDS order is program order)
+    if (lane < NV) {
+      const int a = lane / CG, cc = lane % CG;
+      T sacc = 0;
+      for (int b = 0; b <= a; ++b) sacc += Ts[b * NB + a] * Wb[b * CG + cc];
+      Wp[lane] = sacc;
+    }
+    T wp[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) wp[e] = Wp[e];
+    // C -= Y W'
+#pragma unroll 2
+    for (int q = 0; q < nq; ++q) {
+      const int i = lane + 64 * q;
+      const bool ok = i < Lr;
+      const int ic = ok ? i : 0;
+      T u[CG];
+#pragma unroll
+      for (int cc = 0; cc < CG; ++cc)
+        u[cc] = bload<T>(rs, (ok && c0 + cc < nc) ? (uint32_t)((i + (size_t)(c0 + cc) * ldc) * sizeof(T)) : kOob);
+      T y[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) y[a] = Ys[ic * PS + a];
+#pragma unroll
+      for (int cc = 0; cc < CG; ++cc) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) u[cc] -= y[a] * wp[a * CG + cc];
+        if (ok && c0 + cc < nc) C[(size_t)i + (size_t)(c0 + cc) * ldc] = u[cc];
+      }
+    }
+  }
+}
+
+// Householder QR of the r x c matrix M (ld) in place: R on and above the
+// diagonal, the reflectors below, tau[min(r, c)], and each panel's T
+// (NB x NB, row-major) at Tst + panel * NB * NB.
+template <typename T>
+__device__ __noinline__ void wg_geqrf_impl(LSQ_GLB T* Mg, int ld, int r, int c, LSQ_GLB T* taug,
+                                           LSQ_GLB T* Tstg, LSQ_LDS BLds<T>* Lp) {
+  T* M = (T*)uni(Mg);
+  T* tau = (T*)uni(taug);
+  T* Tst = (T*)uni(Tstg);
+  BLds<T>& L = *(BLds<T>*)uni(Lp);
+  ld = uni(ld); r = uni(r); c = uni(c);
+  constexpr int NB = QrCfg<T>::NB;
+  const int kq = r < c ? r : c;
+  for (int j0 = 0, pan = 0; j0 < kq; j0 += NB, ++pan) {
+    const int nbj = kq - j0 < NB ? kq - j0 : NB, Lr = r - j0;
+    stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, false);
+    panel_factor(L, M, ld, j0, nbj, Lr);
+    panel_t(L, nbj, Lr, L.u.f.tau);
+    // reflectors and the diagonal of R back to M; scalars and T to storage
+    constexpr int PS = NB + 1;
+    for (int e = threadIdx.x; e < Lr * nbj; e += kBT) {
+      const int i = e % Lr, a = e / Lr;
+      if (i > a) M[(size_t)(j0 + i) + (size_t)(j0 + a) * ld] = L.u.f.Ys[i * PS + a];
+      else if (i == a) M[(size_t)(j0 + i) + (size_t)(j0 + a) * ld] = L.u.f.beta[a];
+    }
+    for (int e = threadIdx.x; e < NB * NB; e += kBT) Tst[(size_t)pan * NB * NB + e] = L.u.f.Ts[e];
+    if (threadIdx.x < nbj) tau[j0 + threadIdx.x] = L.u.f.tau[threadIdx.x];
+    apply_block_qt(L, Lr, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void wg_geqrf(T* M, int ld, int r, int c, T* tau, T* Tst, BLds<T>& L) {
+  wg_geqrf_impl<T>((LSQ_GLB T*)M, ld, r, c, (LSQ_GLB T*)tau, (LSQ_GLB T*)Tst, (LSQ_LDS BLds<T>*)&L);
+}
+
+// X (r x ncols, ldx) <- Q^T X for the k reflectors stored in M (ld) by
+// wg_geqrf, panel by panel.
+template <typename T>
+__device__ __noinline__ void wg_apply_qt_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
+                                              const LSQ_GLB T* Tstg, LSQ_GLB T* Xg, int ldx,
+                                              int ncols, LSQ_LDS BLds<T>* Lp) {
+  const T* M = (const T*)uni(Mg);
+  const T* Tst = (const T*)uni(Tstg);
+  T* X = (T*)uni(Xg);
+  BLds<T>& L = *(BLds<T>*)uni(Lp);
+  ld = uni(ld); r = uni(r); k = uni(k); ldx = uni(ldx); ncols = uni(ncols);
+  constexpr int NB = QrCfg<T>::NB;
+  for (int j0 = 0, pan = 0; j0 < k; j0 += NB, ++pan) {
+    const int nbj = k - j0 < NB ? k - j0 : NB, Lr = r - j0;
+    for (int e = threadIdx.x; e < NB * NB; e += kBT) L.u.f.Ts[e] = Tst[(size_t)pan * NB * NB + e];
+    stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, true);
+    apply_block_qt(L, Lr, X + j0, ldx, ncols);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, const T* Tst, T* X,
+                                            int ldx, int ncols, BLds<T>& L) {
+  wg_apply_qt_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_GLB T*)X, ldx,
+                      ncols, (LSQ_LDS BLds<T>*)&L);
+}
+
+// ------------------------------------------------ one-wave vector kernels --
+// y (LDS, length r) <- Q^T y (trans) or Q y, Q = H_0 ... H_{k-1} with the
+// reflectors of M (ld).  The lane's entries of y stay in registers; the next
+// reflector is loaded while the current one is applied.
+// Loads are issued unconditionally from clamped (always valid) addresses and
+// masked afterwards: a conditional load whose register is written on the
+// other path makes the compiler wait for every load in flight.
+template <typename T>
+__device__ __forceinline__ T load_reflector(const T* M, int ld, int r, int j, const T* tau, int nq,
+                                            T (&dst)[kBS]) {
+  const int lane = threadIdx.x & 63;
+  const auto rs = rsrc(M + (size_t)j * ld, (size_t)r * sizeof(T));
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const int i = lane + 64 * q;
+    const T x = bload<T>(rs, (q < nq && i > j && i < r) ? (uint32_t)(i * sizeof(T)) : kOob);
+    dst[q] = x + (i == j ? (T)1 : (T)0);
+  }
+  return tau[j];
+}
+
+template <typename T>
+__device__ __forceinline__ void apply_reflector(const T (&v)[kBS], T tau, T (&yr)[kBS]) {
+  T d = 0;
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) d += v[q] * yr[q];
+  d = wsum(d) * tau;
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) yr[q] -= d * v[q];
+}
+
+// Two register sets alternate, so the loads of the next reflector are in
+// flight while the current one is applied.
+template <typename T>
+__device__ __noinline__ void wave_apply_q_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
+                                               const LSQ_GLB T* taug, LSQ_LDS T* yl, bool trans) {
+  const T* M = (const T*)uni(Mg);
+  const T* tau = (const T*)uni(taug);
+  T* y = (T*)uni(yl);
+  ld = uni(ld); r = uni(r); k = uni(k);
+  trans = uni((int)trans) != 0;
+  const int lane = threadIdx.x & 63, nq = (r + 63) >> 6;
+  T yr[kBS], va[kBS], vb[kBS];
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const int i = lane + 64 * q;
+    const T x = y[(q < nq && i < r) ? i : 0];
+    yr[q] = (q < nq && i < r) ? x : (T)0;
+  }
+  auto jof = [&](int s) { return trans ? s : k - 1 - s; };
+  T ta = k > 0 ? load_reflector(M, ld, r, jof(0), tau, nq, va) : (T)0, tb = 0;
+  for (int s = 0; s < k; s += 2) {
+    if (s + 1 < k) tb = load_reflector(M, ld, r, jof(s + 1), tau, nq, vb);
+    apply_reflector(va, ta, yr);
+    if (s + 1 >= k) break;
+    if (s + 2 < k) ta = load_reflector(M, ld, r, jof(s + 2), tau, nq, va);
+    apply_reflector(vb, tb, yr);
+  }
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const int i = lane + 64 * q;
+    if (q < nq && i < r) y[i] = yr[q];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void wave_apply_q(const T* M, int ld, int r, int k, const T* tau, T* y,
+                                             bool trans) {
+  wave_apply_q_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)tau, (LSQ_LDS T*)y, trans);
+}
+
+// Column j of U above the diagonal (TRANS = false) or row j right of it
+// (TRANS = true) into the lane's slots; out-of-range entries read as 0.
+template <typename T, bool TRANS>
+__device__ __forceinline__ T load_tri(const T* M, int ld, int nn, int j, T (&dst)[kBS]) {
+  const int lane = threadIdx.x & 63;
+  const auto rs = TRANS ? rsrc(M + j, ((size_t)(nn - 1) * ld + 1) * sizeof(T))
+                        : rsrc(M + (size_t)j * ld, (size_t)j * sizeof(T));
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const int i = lane + 64 * q;
+    const uint32_t off = TRANS ? ((i > j && i < nn) ? (uint32_t)((size_t)i * ld * sizeof(T)) : kOob)
+                               : (uint32_t)(i * sizeof(T));
+    dst[q] = bload<T>(rs, off);
+  }
+  return M[j + (size_t)j * ld];
+}
+
+// One step of the substitution on the register-resident vector: x_j from its
+// owner lane, then y -= x_j u (u is zero outside the active part), and x_j
+// stored in its slot.
+template <typename T>
+__device__ __forceinline__ void tri_step(const T (&u)[kBS], T d, int j, T (&yr)[kBS]) {
+  const int lane = threadIdx.x & 63, slot = j >> 6, owner = j & 63;
+  T own = yr[0];
+#pragma unroll
+  for (int q = 1; q < kBS; ++q) own = (q == slot) ? yr[q] : own;
+  const T xj = lane_val(own, owner) / d;
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const T v = yr[q] - u[q] * xj;
+    yr[q] = (q == slot && lane == owner) ? xj : v;
+  }
+}
+
+template <typename T, bool TRANS>
+__device__ __noinline__ void wave_trsv_impl(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
+  const T* M = (const T*)uni(Mg);
+  T* y = (T*)uni(yl);
+  ld = uni(ld);
+  nn = uni(nn);
+  if (nn <= 0) return;
+  const int lane = threadIdx.x & 63, nq = (nn + 63) >> 6;
+  T yr[kBS], ua[kBS], ub[kBS];
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const int i = lane + 64 * q;
+    const T x = y[(q < nq && i < nn) ? i : 0];
+    yr[q] = (q < nq && i < nn) ? x : (T)0;
+  }
+  auto jof = [&](int s) { return TRANS ? s : nn - 1 - s; };
+  T da = load_tri<T, TRANS>(M, ld, nn, jof(0), ua), db = 1;
+  for (int s = 0; s < nn; s += 2) {
+    if (s + 1 < nn) db = load_tri<T, TRANS>(M, ld, nn, jof(s + 1), ub);
+    tri_step(ua, da, jof(s), yr);
+    if (s + 1 >= nn) break;
+    if (s + 2 < nn) da = load_tri<T, TRANS>(M, ld, nn, jof(s + 2), ua);
+    tri_step(ub, db, jof(s + 1), yr);
+  }
+#pragma unroll
+  for (int q = 0; q < kBS; ++q) {
+    const int i = lane + 64 * q;
+    if (q < nq && i < nn) y[i] = yr[q];
+  }
+}
+
+// y (LDS, length nn) <- U^{-1} y or U^{-T} y in place, U = M[0:nn, 0:nn]
+// (upper, ld), one wave.  A zero pivot gives a non-finite result, which the
+// stop test reports.
+template <typename T>
+__device__ __forceinline__ void wave_trsv(const T* M, int ld, int nn, T* y, bool trans) {
+  if (trans) wave_trsv_impl<T, true>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
+  else wave_trsv_impl<T, false>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
+}
+
+// ----------------------------------------------------------- workspaces --
+template <typename T>
+struct LseWs {
+  T *Fb, *taub, *Tb, *X, *Fa, *taua, *Ta;
+  double *r, *v, *f1, *f2, *f3;
+};
+template <typename T>
+struct GlsWs {
+  T *Fw, *taw, *Tw, *X, *Fv, *tav, *Tv;
+  double *z, *f1, *f2, *f3;
+};
+
+// T blocks of the panels of a QR with k reflectors
+__host__ __device__ constexpr size_t tblocks(int k, int nb) { return (size_t)((k + nb - 1) / nb) * nb * nb; }
+
+template <typename T>
+__device__ __forceinline__ LseWs<T> lse_ws(char* base, int m, int n, int p) {
+  constexpr int NB = QrCfg<T>::NB;
+  LseWs<T> w;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* q = base + o; o += align256(bytes); return q; };
+  const int ka = m < n ? m : n;
+  w.Fb = (T*)take(sizeof(T) * (size_t)n * p);
+  w.taub = (T*)take(sizeof(T) * p);
+  w.Tb = (T*)take(sizeof(T) * tblocks(p, NB));
+  w.X = (T*)take(sizeof(T) * (size_t)n * m);
+  w.Fa = (T*)take(sizeof(T) * (size_t)m * n);
+  w.taua = (T*)take(sizeof(T) * ka);
+  w.Ta = (T*)take(sizeof(T) * tblocks(ka, NB));
+  w.r = (double*)take(8 * (size_t)m);
+  w.v = (double*)take(8 * (size_t)p);
+  w.f1 = (double*)take(8 * (size_t)m);
+  w.f2 = (double*)take(8 * (size_t)p);
+  w.f3 = (double*)take(8 * (size_t)n);
+  return w;
+}
+template <typename T>
+__device__ __forceinline__ GlsWs<T> gls_ws(char* base, int n, int m, int p) {
+  constexpr int NB = QrCfg<T>::NB;
+  GlsWs<T> w;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* q = base + o; o += align256(bytes); return q; };
+  const int kv = p < n ? p : n;
+  w.Fw = (T*)take(sizeof(T) * (size_t)n * m);
+  w.taw = (T*)take(sizeof(T) * m);
+  w.Tw = (T*)take(sizeof(T) * tblocks(m, NB));
+  w.X = (T*)take(sizeof(T) * (size_t)n * p);
+  w.Fv = (T*)take(sizeof(T) * (size_t)p * n);
+  w.tav = (T*)take(sizeof(T) * kv);
+  w.Tv = (T*)take(sizeof(T) * tblocks(kv, NB));
+  w.z = (double*)take(8 * (size_t)n);
+  w.f1 = (double*)take(8 * (size_t)p);
+  w.f2 = (double*)take(8 * (size_t)n);
+  w.f3 = (double*)take(8 * (size_t)m);
+  return w;
+}
+
+template <typename PD>
+__device__ __forceinline__ double wg_fro(PD M, int ld, int rows, int cols, double* red) {
+  double s = 0.0;
+  for (int j = 0; j < cols; ++j)
+    for (int i = threadIdx.x; i < rows; i += kBT) {
+      const double a = M[(size_t)i + (size_t)j * ld];
+      s += a * a;
+    }
+  return sqrt(wg_sum1(s, red));
+}
+
+// Stop test on the squared norms [f1, f2, f3, x, a1, a2] with the scales of
+// eq. lse-stop (gls = 0; a1 = r, a2 = v) or eq. gls-stop (gls = 1; a1 = y,
+// a2 = z).  mat: [||A||, ||B||, ||rhs1||, ||rhs2||].
+struct StopOut {
+  bool conv, bad;
+  double berr[3], bmax;
+};
+__device__ __forceinline__ StopOut stop_test(const double s[6], const double mat[4], int gls, double tol) {
+  const double nf[3] = {sqrt(s[0]), sqrt(s[1]), sqrt(s[2])};
+  const double nx = sqrt(s[3]), na1 = sqrt(s[4]), na2 = sqrt(s[5]);
+  double sc[3];
+  if (!gls) {
+    sc[0] = mat[2] + na1 + mat[0] * nx;
+    sc[1] = mat[3] + mat[1] * nx;
+    sc[2] = mat[0] * na1 + mat[1] * na2;
+  } else {
+    sc[0] = na1 + mat[1] * na2;
+    sc[1] = mat[2] + mat[0] * nx + mat[1] * na1;
+    sc[2] = mat[0] * na2;
+  }
+  StopOut o;
+  o.conv = true;
+  o.bad = !isfinite(nx) || !isfinite(na1) || !isfinite(na2);
+  o.bmax = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double e = 0.0;
+    if (nf[k] > 0.0) e = sc[k] > 0.0 ? nf[k] / sc[k] : INFINITY;
+    o.berr[k] = e;
+    if (!(nf[k] <= tol * sc[k])) o.conv = false;
+    if (!isfinite(nf[k]) || !isfinite(sc[k])) o.bad = true;
+    o.bmax = e > o.bmax ? e : o.bmax;
+  }
+  o.conv = o.conv && !o.bad;
+  return o;
+}
+
+// Classical refinement driver shared by both problems: `correct(first)` adds
+// one correction (the initial solve when first), `residual(s)` evaluates the
+// FP64 residual and the six squared norms.  Divergence / stagnation: stop when
+// an iterate is not finite or the backward error has not halved over the last
+// three steps.
+template <typename Correct, typename Residual>
+__device__ __forceinline__ void refine(Correct correct, Residual residual, const double mat[4], int gls, double tol,
+                       int maxit, BatchOut* out) {
+  correct(true);
+  double hist[4] = {0, 0, 0, 0};
+  int it = 0;
+  StopOut so;
+  for (;; ++it) {
+    double s[6];
+    residual(s);
+    so = stop_test(s, mat, gls, tol);
+    hist[0] = hist[1]; hist[1] = hist[2]; hist[2] = hist[3]; hist[3] = so.bmax;
+    if (so.conv) break;
+    const bool stalled = it >= 3 && !(hist[3] <= 0.5 * hist[0]);
+    if (so.bad || it >= maxit || stalled) break;
+    correct(false);
+  }
+  if (threadIdx.x == 0) {
+    out->info = so.conv ? 0 : (so.bad ? 5 : 3);
+    out->steps = it;
+    for (int k = 0; k < 3; ++k) out->berr[k] = so.berr[k];
+    out->berr_max = so.bmax;
+  }
+}
+
+// ------------------------------------------------------------------ LSE --
+// Layout as the single-instance path: Bt = J_n B^T J_p = Qt [Rt; 0] (Fb),
+// Abar = A J Qt J = Za [T; 0] (Fa), k = n - p, T11 = T[0:k, 0:k],
+// T12 = T[0:k, k:n], T22 = T[k:m, k:n] (upper part).
+template <typename T>
+__device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit, BatchOut* out,
+                             BLds<T>& L) {
+  const int m = P.m, n = P.n, p = P.p, k = n - p, kqa = m < n ? m : n;
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
+  const LseWs<T> W = lse_ws<T>(base, m, n, p);
+  // the instance's arrays, typed as global memory
+  const LSQ_GLB double* A = (const LSQ_GLB double*)P.A;
+  const LSQ_GLB double* B = (const LSQ_GLB double*)P.B;
+  const LSQ_GLB double* bvec = (const LSQ_GLB double*)P.b;
+  const LSQ_GLB double* dvec = (const LSQ_GLB double*)P.d;
+  LSQ_GLB double* x = (LSQ_GLB double*)P.x;
+  double mat[4];
+  mat[0] = wg_fro(A, P.lda, m, n, L.dred);
+  mat[1] = wg_fro(B, P.ldb, p, n, L.dred);
+  mat[2] = wg_fro(bvec, m, m, 1, L.dred);
+  mat[3] = wg_fro(dvec, p, p, 1, L.dred);
+  // factorization in T: Bt = J_n B^T J_p = Qt [Rt; 0]; X = Qt^T (J_n A^T);
+  // Abar = A J Qt J = (J_n X)^T = Za [T; 0]
+  for (int i = 0; i < n; ++i) {
+    const LSQ_GLB double* bc = B + (size_t)(n - 1 - i) * P.ldb;   // column n-1-i of B
+    for (int j = t; j < p; j += kBT) W.Fb[i + (size_t)j * n] = (T)bc[p - 1 - j];
+    const LSQ_GLB double* ac = A + (size_t)(n - 1 - i) * P.lda;   // column n-1-i of A
+    for (int j = t; j < m; j += kBT) W.X[i + (size_t)j * n] = (T)ac[j];
+  }
+  __syncthreads();
+  wg_geqrf(W.Fb, n, n, p, W.taub, W.Tb, L);
+  wg_apply_qt(W.Fb, n, n, p, W.Tb, W.X, n, m, L);
+  for (int j = 0; j < m; ++j)                          // X[i][j] -> Fa[j][n-1-i]
+    for (int i = t; i < n; i += kBT) W.Fa[j + (size_t)(n - 1 - i) * m] = W.X[i + (size_t)j * n];
+  __syncthreads();
+  wg_geqrf(W.Fa, m, m, n, W.taua, W.Ta, L);
+  for (int i = t; i < n; i += kBT) x[i] = 0.0;
+  for (int i = t; i < m; i += kBT) W.r[i] = 0.0;
+  for (int i = t; i < p; i += kBT) W.v[i] = 0.0;
+  __syncthreads();
+
+  T* U = L.u.vec[0];
+  T* Wv = L.u.vec[1];
+  T* Y2 = L.u.vec[2];
+  T* Y2n = L.u.vec[3];
+  T* Qv = L.u.vec[4];
+  T* Y1 = L.u.vec[5];
+  T* S = L.u.vec[6];
+  T* X2 = L.u.vec[7];
+  T* Yt = L.u.vec[8];
+  const T* Fa = W.Fa;
+  // Algorithm 1 on (f1, f2, f3), f3 = 0 for the initial solve; adds the
+  // corrections to (x, r, v).
+  auto correct = [&](bool first) {
+    const LSQ_GLB double* f1 = first ? bvec : (const LSQ_GLB double*)W.f1;
+    const LSQ_GLB double* f2 = first ? dvec : (const LSQ_GLB double*)W.f2;
+    for (int i = t; i < n; i += kBT) U[i] = first ? (T)0 : (T)W.f3[n - 1 - i];
+    for (int i = t; i < m; i += kBT) Wv[i] = (T)f1[i];
+    for (int i = t; i < p; i += kBT) Y2[i] = (T)f2[p - 1 - i];
+    __syncthreads();
+    // u~ = Qt^T (J f3); w = Z^T f1; Rt^T (J y2) = J f2
+    if (w == 0) wave_apply_q(W.Fb, n, n, p, W.taub, U, true);
+    else if (w == 1) wave_apply_q(W.Fa, m, m, kqa, W.taua, Wv, true);
+    else if (w == 2) wave_trsv(W.Fb, n, p, Y2, true);
+    __syncthreads();
+    for (int i = t; i < p; i += kBT) Y2n[i] = Y2[p - 1 - i];
+    for (int i = t; i < k; i += kBT) Qv[i] = U[p + k - 1 - i];
+    __syncthreads();
+    if (w == 0) {
+      wave_trsv(Fa, m, k, Qv, true);                      // T11^T q1 = u1
+    } else {
+      // w1 - T12 y2 (rows < k) and q2 = w2 - T22 y2 (rows >= k)
+      const auto rs = rsrc(Fa, (size_t)m * n * sizeof(T));
+      for (int i = t - 64; i < m; i += kBT - 64) {
+        T acc = 0;
+        for (int jj = 0; jj < p; ++jj) {
+          const int col = k + jj;
+          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * m) * sizeof(T)) : kOob) * Y2n[jj];
+        }
+        if (i < k) Y1[i] = Wv[i] - acc;
+        else Qv[i] = Wv[i] - acc;
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      for (int i = lane; i < k; i += 64) Y1[i] -= Qv[i];
+      wave_trsv(Fa, m, k, Y1, false);                     // T11 y1 = w1 - q1 - T12 y2
+    } else {
+      // s = [T12; T22]^T q - u2, one column per wave
+      for (int jj = w - 1; jj < p; jj += kBW - 1) {
+        const int col = k + jj, lim = m < col + 1 ? m : col + 1;
+        T s = 0;
+        for (int i = lane; i < lim; i += 64) s += Fa[i + (size_t)col * m] * Qv[i];
+        s = wsum(s);
+        if (lane == 0) S[jj] = s - U[p - 1 - jj];
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < p; i += kBT) X2[i] = S[p - 1 - i];
+    for (int i = t; i < p; i += kBT) Yt[i] = Y2[i];
+    for (int i = t; i < k; i += kBT) Yt[p + i] = Y1[k - 1 - i];
+    __syncthreads();
+    if (w == 0) {                                         // R^T dv = s
+      wave_trsv(W.Fb, n, p, X2, false);
+      for (int i = lane; i < p; i += 64) W.v[i] += (double)X2[p - 1 - i];
+    } else if (w == 1) {                                  // dr = Z q
+      wave_apply_q(W.Fa, m, m, kqa, W.taua, Qv, false);
+      for (int i = lane; i < m; i += 64) W.r[i] += (double)Qv[i];
+    } else if (w == 2) {                                  // dx = J Qt (J y)
+      wave_apply_q(W.Fb, n, n, p, W.taub, Yt, false);
+      for (int i = lane; i < n; i += 64) x[i] += (double)Yt[n - 1 - i];
+    }
+    __syncthreads();
+  };
+  // f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v (FP64)
+  auto residual = [&](double s[6]) {
+    for (int q = 0; q < 6; ++q) s[q] = 0.0;
+    for (int i = t; i < m; i += kBT) {
+      double a = 0.0;
+      for (int j = 0; j < n; ++j) a += A[(size_t)i + (size_t)j * P.lda] * x[j];
+      const double val = bvec[i] - W.r[i] - a;
+      W.f1[i] = val;
+      s[0] += val * val;
+      s[4] += W.r[i] * W.r[i];
+    }
+    for (int i = t; i < p; i += kBT) {
+      double a = 0.0;
+      for (int j = 0; j < n; ++j) a += B[(size_t)i + (size_t)j * P.ldb] * x[j];
+      const double val = dvec[i] - a;
+      W.f2[i] = val;
+      s[1] += val * val;
+      s[5] += W.v[i] * W.v[i];
+    }
+    for (int j = w; j < n; j += kBW) {
+      double a = 0.0, b = 0.0;
+      for (int i = lane; i < m; i += 64) a += A[(size_t)i + (size_t)j * P.lda] * W.r[i];
+      for (int i = lane; i < p; i += 64) b += B[(size_t)i + (size_t)j * P.ldb] * W.v[i];
+      a = wsum(a);
+      b = wsum(b);
+      if (lane == 0) {
+        const double val = -a + b;
+        W.f3[j] = val;
+        s[2] += val * val;
+        s[3] += x[j] * x[j];
+      }
+    }
+    wg_sum6(s, L.dred);
+  };
+  refine(correct, residual, mat, 0, tol, maxit, out);
+}
+
+// ------------------------------------------------------------------ GLS --
+// Layout as the single-instance path: W = Qw [Rw; 0] (Fw),
+// Vt = J_p (Qw^T V)^T J_n = Qv Tv (Fv, p x n), k = n - m,
+// A11 = Tv[0:k, 0:k], A12 = Tv[0:k, k:n], A22 = Tv[k:p, k:n] (upper part).
+template <typename T>
+__device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit, BatchOut* out,
+                             BLds<T>& L) {
+  const int n = P.n, m = P.m, p = P.p, k = n - m, kqv = p < n ? p : n;
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
+  const GlsWs<T> W = gls_ws<T>(base, n, m, p);
+  // the instance's arrays, typed as global memory
+  const LSQ_GLB double* A = (const LSQ_GLB double*)P.A;
+  const LSQ_GLB double* B = (const LSQ_GLB double*)P.B;
+  const LSQ_GLB double* dvec = (const LSQ_GLB double*)P.d;
+  LSQ_GLB double* x = (LSQ_GLB double*)P.x;
+  LSQ_GLB double* y = (LSQ_GLB double*)P.y;
+  double mat[4];
+  mat[0] = wg_fro(A, P.lda, n, m, L.dred);
+  mat[1] = wg_fro(B, P.ldb, n, p, L.dred);
+  mat[2] = wg_fro(dvec, n, n, 1, L.dred);
+  mat[3] = 0.0;
+  // factorization in T: W = Qw [Rw; 0]; X = Qw^T V;
+  // Vt = J_p X^T J_n = Qv Tv
+  for (int j = 0; j < m; ++j)
+    for (int i = t; i < n; i += kBT) W.Fw[i + (size_t)j * n] = (T)A[(size_t)i + (size_t)j * P.lda];
+  for (int j = 0; j < p; ++j)
+    for (int i = t; i < n; i += kBT) W.X[i + (size_t)j * n] = (T)B[(size_t)i + (size_t)j * P.ldb];
+  __syncthreads();
+  wg_geqrf(W.Fw, n, n, m, W.taw, W.Tw, L);
+  wg_apply_qt(W.Fw, n, n, m, W.Tw, W.X, n, p, L);
+  for (int j = 0; j < p; ++j)                          // X[i][j] -> Fv[p-1-j][n-1-i]
+    for (int i = t; i < n; i += kBT)
+      W.Fv[(size_t)(p - 1 - j) + (size_t)(n - 1 - i) * p] = W.X[i + (size_t)j * n];
+  __syncthreads();
+  wg_geqrf(W.Fv, p, p, n, W.tav, W.Tv, L);
+  for (int i = t; i < m; i += kBT) x[i] = 0.0;
+  for (int i = t; i < p; i += kBT) y[i] = 0.0;
+  for (int i = t; i < n; i += kBT) W.z[i] = 0.0;
+  __syncthreads();
+
+  T* U = L.u.vec[0];
+  T* Wt = L.u.vec[1];
+  T* H1 = L.u.vec[2];
+  T* H1t = L.u.vec[3];
+  T* G = L.u.vec[4];
+  T* H2t = L.u.vec[5];
+  T* S = L.u.vec[6];
+  T* X = L.u.vec[7];
+  T* Hv = L.u.vec[8];
+  const T* Fv = W.Fv;
+  // Algorithm 3 on (f1, f2, f3), f1 = f3 = 0 for the initial solve; adds the
+  // corrections to (x, y, z) with dz = -Q h.
+  auto correct = [&](bool first) {
+    const LSQ_GLB double* f2 = first ? dvec : (const LSQ_GLB double*)W.f2;
+    for (int i = t; i < n; i += kBT) U[i] = (T)f2[i];
+    for (int i = t; i < p; i += kBT) Wt[i] = first ? (T)0 : (T)W.f1[p - 1 - i];
+    for (int i = t; i < m; i += kBT) H1[i] = first ? (T)0 : (T)W.f3[i];
+    __syncthreads();
+    // u = Q^T f2; J w = Zt^T (J f1); R^T h1 = f3
+    if (w == 0) wave_apply_q(W.Fw, n, n, m, W.taw, U, true);
+    else if (w == 1) wave_apply_q(W.Fv, p, p, kqv, W.tav, Wt, true);
+    else if (w == 2) wave_trsv(W.Fw, n, m, H1, true);
+    __syncthreads();
+    for (int i = t; i < m; i += kBT) H1t[i] = H1[m - 1 - i];
+    for (int i = t; i < k; i += kBT) G[i] = U[m + k - 1 - i];
+    __syncthreads();
+    if (w == 0) {
+      wave_trsv(Fv, p, k, G, true);                       // A11^T (J g2) = J u2
+    } else {
+      // J w2 - A12 J h1 (rows < k) and J g1 = J w1 - A22 J h1 (rows >= k)
+      const auto rs = rsrc(Fv, (size_t)p * n * sizeof(T));
+      for (int i = t - 64; i < p; i += kBT - 64) {
+        T acc = 0;
+        for (int jj = 0; jj < m; ++jj) {
+          const int col = k + jj;
+          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * p) * sizeof(T)) : kOob) * H1t[jj];
+        }
+        if (i < k) H2t[i] = Wt[i] - acc;
+        else G[i] = Wt[i] - acc;
+      }
+    }
+    __syncthreads();
+    if (w == 0) {
+      for (int i = lane; i < k; i += 64) H2t[i] -= G[i];
+      wave_trsv(Fv, p, k, H2t, false);                    // A11 (J h2) = J w2 - J g2 - A12 J h1
+    } else {
+      // s = Tv[:, k:n]^T (J g), one column per wave
+      for (int jj = w - 1; jj < m; jj += kBW - 1) {
+        const int col = k + jj, lim = p < col + 1 ? p : col + 1;
+        T s = 0;
+        for (int i = lane; i < lim; i += 64) s += Fv[i + (size_t)col * p] * G[i];
+        s = wsum(s);
+        if (lane == 0) S[jj] = s;
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < m; i += kBT) X[i] = U[i] - S[m - 1 - i];
+    for (int i = t; i < m; i += kBT) Hv[i] = H1[i];
+    for (int i = t; i < k; i += kBT) Hv[m + i] = H2t[k - 1 - i];
+    __syncthreads();
+    if (w == 0) {                                         // R dx = u1 - J s
+      wave_trsv(W.Fw, n, m, X, false);
+      for (int i = lane; i < m; i += 64) x[i] += (double)X[i];
+    } else if (w == 1) {                                  // dz = -Q h
+      wave_apply_q(W.Fw, n, n, m, W.taw, Hv, false);
+      for (int i = lane; i < n; i += 64) W.z[i] -= (double)Hv[i];
+    } else if (w == 2) {                                  // dy = J Zt (J g)
+      wave_apply_q(W.Fv, p, p, kqv, W.tav, G, false);
+      for (int i = lane; i < p; i += 64) y[i] += (double)G[p - 1 - i];
+    }
+    __syncthreads();
+  };
+  // f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z (FP64)
+  auto residual = [&](double s[6]) {
+    for (int q = 0; q < 6; ++q) s[q] = 0.0;
+    for (int i = t; i < n; i += kBT) {
+      double a = 0.0;
+      for (int j = 0; j < m; ++j) a += A[(size_t)i + (size_t)j * P.lda] * x[j];
+      for (int j = 0; j < p; ++j) a += B[(size_t)i + (size_t)j * P.ldb] * y[j];
+      const double val = dvec[i] - a;
+      W.f2[i] = val;
+      s[1] += val * val;
+      s[5] += W.z[i] * W.z[i];
+    }
+    for (int j = w; j < p + m; j += kBW) {
+      const bool isv = j < p;
+      const LSQ_GLB double* col = isv ? B + (size_t)j * P.ldb : A + (size_t)(j - p) * P.lda;
+      double a = 0.0;
+      for (int i = lane; i < n; i += 64) a += col[i] * W.z[i];
+      a = wsum(a);
+      if (lane == 0) {
+        if (isv) {
+          const double val = -y[j] + a;
+          W.f1[j] = val;
+          s[0] += val * val;
+          s[4] += y[j] * y[j];
+        } else {
+          W.f3[j - p] = a;
+          s[2] += a * a;
+          s[3] += x[j - p] * x[j - p];
+        }
+      }
+    }
+    wg_sum6(s, L.dred);
+  };
+  refine(correct, residual, mat, 1, tol, maxit, out);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBT, 2) void k_batch(const BatchProb* __restrict__ probs,
+                                                  const int* __restrict__ order, int count,
+                                                  int* __restrict__ counter, char* __restrict__ ws,
+                                                  size_t ws_stride, double tol, int maxit,
+                                                  BatchOut* __restrict__ out) {
+  __shared__ BLds<T> L;
+  char* mine = ws + (size_t)blockIdx.x * ws_stride;
+  for (;;) {
+    if (threadIdx.x == 0) L.next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int q = uni(L.next);
+    __syncthreads();
+    if (q >= count) break;
+    const int idx = order[q];
+    const BatchProb P = probs[idx];
+    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, out + idx, L);
+    else gls_instance<T>(P, mine, tol, maxit, out + idx, L);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t batch_ws_bytes(const BatchProb& P) {
+  auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t m = P.m, n = P.n, p = P.p, d = 8;
+  // T blocks: 16 x 16 floats per 16 reflectors or 8 x 8 doubles per 8, at most
+  // 64 bytes per reflector either way (+ one block)
+  auto tb = [&](size_t k) { return a(64 * k + 2048); };
+  if (P.type == 0) {
+    const size_t ka = m < n ? m : n;
+    return a(d * n * p) + a(d * p) + tb(p) + a(d * n * m) + a(d * m * n) + a(d * ka) + tb(ka) +
+           a(d * m) + a(d * p) + a(d * m) + a(d * p) + a(d * n);
+  }
+  const size_t kv = p < n ? p : n;
+  return a(d * n * m) + a(d * m) + tb(m) + a(d * n * p) + a(d * p * n) + a(d * kv) + tb(kv) +
+         a(d * n) + a(d * p) + a(d * n) + a(d * m);
+}
+
+bool batch_eligible(const BatchProb& P) {
+  const int lim = kBatchMaxDim;
+  return P.m >= 1 && P.n >= 1 && P.p >= 1 && P.m <= lim && P.n <= lim && P.p <= lim;
+}
+
+// Householder QR of an r x c matrix: 2 c^2 (r - c/3) for r >= c, 2 r^2 (c - r/3)
+// otherwise; applying k reflectors of length c from the right to r rows:
+// 4 r (c - j) for reflector j.
+static double qr_flops(double r, double c) {
+  return r >= c ? 2.0 * c * c * (r - c / 3.0) : 2.0 * r * r * (c - r / 3.0);
+}
+static double right_flops(double r, double c, int k) {
+  double f = 0.0;
+  for (int j = 0; j < k; ++j) f += 4.0 * r * (c - j);
+  return f;
+}
+
+double batch_factor_flops(const BatchProb& P) {
+  if (P.type == 0) return qr_flops(P.n, P.p) + right_flops(P.m, P.n, P.p) + qr_flops(P.m, P.n);
+  return qr_flops(P.n, P.m) + right_flops(P.p, P.n, P.m) + qr_flops(P.p, P.n);
+}
+
+void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
+                  int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
+                  BatchOut* out, double flops) {
+  if (count <= 0 || grid <= 0) return;
+  LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
+  const int kind = tw == 8 ? kKBatch64 : kKBatch32;
+  ktimer_begin(ctx, kind, flops, 0.0);
+  if (tw == 8)
+    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                       counter, ws, ws_stride, tol, maxit, out);
+  else
+    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                       counter, ws, ws_stride, tol, maxit, out);
+  LSQ_LAUNCH_CHECK();
+  ktimer_end(ctx, kind);
+}
+
+}  // namespace lsq

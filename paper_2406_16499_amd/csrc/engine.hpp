@@ -29,7 +29,8 @@ class Arena {
 // Optional timing of one kernel kind: HIP events on the context stream around
 // each launch of that kind, with the launch's algorithmic flops and bytes.
 enum KernelKind : int {
-  kKPanelFinal = 0, kKPanelCholPass = 1, kKWyT = 2, kKWyU = 3, kKDualGemv = 4, kKCount = 5
+  kKPanelFinal = 0, kKPanelCholPass = 1, kKWyT = 2, kKWyU = 3, kKDualGemv = 4, kKBatch32 = 5,
+  kKBatch64 = 6, kKCount = 7
 };
 struct KernelTimer {
   int target = -1;
@@ -210,5 +211,37 @@ void features(Ctx& ctx, int type, int m, int n, int p, const double* matnorms, c
               const float* st2, const float* st3, float* feats);
 // logits (7) and cls = {precision class 0..4, solver class 0..1}
 void mlp_select(Ctx& ctx, const float* weights, const float* feats, float* logits, int* cls);
+
+// ------------------------------------------------- persistent batch ----
+// One instance of the persistent batched solver (type 0 = LSE with
+// (m, n, p, A = A, B = B, b, d, x); type 1 = GLS with (n, m, p, A = W, B = V,
+// d, x, y)).  Pointers are device pointers to FP64 column-major data.
+constexpr int kBatchMaxDim = 1024;       // largest m, n, p of an instance
+constexpr int kBatchBlocksPerCu = 2;
+struct BatchProb {
+  int type, m, n, p;
+  const double *A, *B, *b, *d;
+  int lda, ldb;
+  double *x, *y;
+};
+struct BatchOut {
+  int info;          // 0 converged, 3 no convergence, 5 non-finite iterate
+  int steps;         // corrections after the initial solve
+  double berr[3];
+  double berr_max;
+};
+// Device workspace bytes of one work-group for instance P (either precision).
+size_t batch_ws_bytes(const BatchProb& P);
+bool batch_eligible(const BatchProb& P);
+// Householder flops of the factorization of instance P (the algorithmic work
+// the kernel timer reports for a batch launch).
+double batch_factor_flops(const BatchProb& P);
+// One persistent launch over order[0:count) (indices into probs, device
+// arrays); tw = 4 (FP32 factors and corrections) or 8 (FP64).  counter: one
+// device int; ws: grid * ws_stride bytes; flops: algorithmic work of the
+// launch, for the kernel timer.
+void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
+                  int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
+                  BatchOut* out, double flops);
 
 }  // namespace lsq

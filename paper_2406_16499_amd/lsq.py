@@ -69,6 +69,7 @@ _SIGS = {
     "lsq_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                   ctypes.POINTER(Result)]),
     "lsq_set_batch_workers": (c_int, [_P, c_int]),
+    "lsq_set_batch_mode": (c_int, [_P, c_int]),
     "lsq_selector_set": (c_int, [_P, ctypes.POINTER(c_float), c_int]),
     "lsq_selector_features": (c_int, [_P, ctypes.POINTER(Problem), ctypes.POINTER(c_float),
                                       ctypes.POINTER(c_float), ctypes.POINTER(c_int)]),
@@ -268,6 +269,13 @@ class Handle:
               "gls": self.lib.gls_solve_batched}[which]
         rc = fn(self.h, len(problems), arr, ctypes.byref(opts) if opts is not None else None, res)
         return rc, list(res)
+
+    def set_batch_mode(self, mode: str) -> None:
+        """"persistent" (default: one work-group per eligible instance) or
+        "workers" (concurrent per-instance solves)."""
+        rc = self.lib.lsq_set_batch_mode(self.h, {"persistent": 0, "workers": 1}[mode])
+        if rc != 0:
+            raise RuntimeError(f"lsq_set_batch_mode = {rc}")
 
     # ---------------------------------------------------------- debug --
     def dbg_bd_apply(self, kind, prec, A, B, alpha, beta, u):

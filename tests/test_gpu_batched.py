@@ -68,16 +68,22 @@ def _check(P, x, y, res):
         assert _fwd(y, yo) <= 10 * cy * max(U64, res.berr_max)
 
 
-@pytest.mark.parametrize("workers", [1, 4, 8])
-def test_batched_mixed_fp32(h, workers):
-    note(f"batched 20 mixed instances fp32 workers={workers}")
+@pytest.mark.parametrize("mode,workers", [("workers", 1), ("workers", 4), ("workers", 8),
+                                          ("persistent", 8)])
+def test_batched_mixed_fp32(h, mode, workers):
+    note(f"batched 20 mixed instances fp32 mode={mode} workers={workers}")
     probs = list(wl.batch_instances(seed=40, count=20, kappa_max=1e4, m_range=(64, 300)))
     keep, descs = _descriptors(probs)
     assert h.lib.lsq_set_batch_workers(h.h, workers) == 0
-    rc, res = h.lsq_solve_batched(descs, lsq.default_opts(prec="fp32"))
+    h.set_batch_mode(mode)
+    try:
+        rc, res = h.lsq_solve_batched(descs, lsq.default_opts(prec="fp32"))
+    finally:
+        h.set_batch_mode("persistent")
     assert rc == 0, (rc, h.last_error())
     for P, (t, x, y), r in zip(probs, keep, res):
         _check(P, x.cpu().numpy(), None if y is None else y.cpu().numpy(), r)
+        assert r.as_dict()["prec_used"] == "fp32"
 
 
 def test_batched_bf16_with_ladder(h):

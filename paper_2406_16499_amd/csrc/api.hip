@@ -927,8 +927,9 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * cur.size(), hipMemcpyHostToDevice, ctx.stream));
     double flops = 0.0;
     for (int q : cur) flops += batch_factor_flops(hp[q]);
+    const bool last = prec == LSQ_PREC_FP64 || !o.escalate;
     batch_launch(ctx, prec == LSQ_PREC_FP64 ? 8 : 4, dprobs, dorder, (int)cur.size(), dcounter, dws,
-                 stride, std::min(grid, (int)cur.size()), o.tol, o.maxit, dout, flops);
+                 stride, std::min(grid, (int)cur.size()), o.tol, o.maxit, !last, dout, flops);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> failed;

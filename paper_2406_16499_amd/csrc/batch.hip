@@ -27,6 +27,8 @@ constexpr int kBT = 256;                 // threads per work-group
 constexpr int kBW = kBT / 64;            // waves per work-group
 constexpr int kBS = kBatchMaxDim / 64;   // register slots per lane for one vector
 constexpr int kVecs = 9;                 // LDS vectors of length kBatchMaxDim
+constexpr double kMaxPredictedSteps = 6.0;
+constexpr int kRQ = kBatchMaxDim / kBT;  // row slots per lane when a wave owns every 4th 64-row block
 
 // The out-of-line device functions below take their pointers in explicit
 // address spaces, so that their memory operations compile to global and LDS
@@ -103,6 +105,25 @@ template <typename T> struct QrCfg;
 template <> struct QrCfg<float> { static constexpr int NB = 16, CG = 4; };
 template <> struct QrCfg<double> { static constexpr int NB = 8, CG = 2; };
 
+// 16 x 16 x 4 MFMA per precision.  Lane l supplies A[l%16][k] and B[k][l%16]
+// for the K index k it holds; accumulator register r of lane l holds row
+// drow(l, r) of column l%16.
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+  using V = f32x4;
+  static __device__ __forceinline__ V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <> struct Mfma<double> {
+  using V = f64x4;
+  static __device__ __forceinline__ V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int drow(int l, int r) { return 4 * r + (l >> 4); }
+};
+
 template <typename T>
 struct BLds {
   static constexpr int NB = QrCfg<T>::NB, CG = QrCfg<T>::CG, PS = NB + 1;
@@ -153,6 +174,45 @@ __device__ __forceinline__ void wg_sum6(double v[6], double* red) {
   }
 }
 
+// Pairwise swaps across half-waves and rows (gfx950 permlane swaps): for X,
+// Y in every lane, afterwards X + Y is the lane's own value plus its partner's
+// (lane ^ 32, resp. lane ^ 16), taken from X in the lower and from Y in the
+// upper lane of each pair.
+__device__ __forceinline__ void lane_swap32(unsigned& x, unsigned& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+__device__ __forceinline__ void lane_swap16(unsigned& x, unsigned& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+template <int MASK>
+__device__ __forceinline__ float pair_sum(float lo, float hi) {
+  unsigned x = __float_as_uint(lo), y = __float_as_uint(hi);
+  if constexpr (MASK == 32) lane_swap32(x, y); else lane_swap16(x, y);
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+template <int MASK>
+__device__ __forceinline__ double pair_sum(double lo, double hi) {
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  unsigned xl = (unsigned)a, xh = (unsigned)(a >> 32), yl = (unsigned)b, yh = (unsigned)(b >> 32);
+  if constexpr (MASK == 32) { lane_swap32(xl, yl); lane_swap32(xh, yh); }
+  else { lane_swap16(xl, yl); lane_swap16(xh, yh); }
+  const double x = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
+  const double y = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
+  return x + y;
+}
+// DPP exchange pairing each lane with one whose bit MASK differs (within a
+// row of 16): xor 8, mirror within 8, mirror within 4, xor 1.
+template <int MASK> struct PairDpp;
+template <> struct PairDpp<8> { static constexpr int ctrl = 0x128; };   // row_ror:8
+template <> struct PairDpp<4> { static constexpr int ctrl = 0x141; };   // row_half_mirror
+template <> struct PairDpp<2> { static constexpr int ctrl = 0x1B; };    // quad_perm [3,2,1,0]
+template <> struct PairDpp<1> { static constexpr int ctrl = 0xB1; };    // quad_perm [1,0,3,2]
+
 // Reduce-scatter of NV (a power of two <= 64) per-lane values over the wave:
 // every lane returns the wave total of value index lane >> (6 - log2 NV).
 // Each halving step keeps the half of the values selected by one lane bit and
@@ -160,24 +220,35 @@ __device__ __forceinline__ void wg_sum6(double v[6], double* red) {
 template <typename T, int NV, int HALF, int MASK>
 __device__ __forceinline__ void rs_step(T (&v)[NV], int lane) {
   if constexpr (HALF >= 1) {
-    const bool up = (lane & MASK) != 0;
+    if constexpr (MASK >= 16) {
 #pragma unroll
-    for (int k = 0; k < HALF; ++k) {
-      const T keep = up ? v[k + HALF] : v[k];
-      const T send = up ? v[k] : v[k + HALF];
-      v[k] = keep + __shfl_xor(send, MASK, 64);
+      for (int k = 0; k < HALF; ++k) v[k] = pair_sum<MASK>(v[k], v[k + HALF]);
+    } else {
+      const bool up = (lane & MASK) != 0;
+#pragma unroll
+      for (int k = 0; k < HALF; ++k) {
+        const T keep = up ? v[k + HALF] : v[k];
+        const T send = up ? v[k] : v[k + HALF];
+        v[k] = keep + dpp<PairDpp<MASK>::ctrl>(send);
+      }
     }
     rs_step<T, NV, HALF / 2, MASK / 2>(v, lane);
   }
+}
+template <typename T, int MASK>
+__device__ __forceinline__ T rs_tail(T r) {
+  if constexpr (MASK >= 1) {
+    if constexpr (MASK >= 16) r += __shfl_xor(r, MASK, 64);
+    else r += dpp<PairDpp<MASK>::ctrl>(r);
+    return rs_tail<T, MASK / 2>(r);
+  }
+  return r;
 }
 template <typename T, int NV>
 __device__ __forceinline__ T wave_reduce_scatter(T (&v)[NV]) {
   const int lane = threadIdx.x & 63;
   rs_step<T, NV, NV / 2, 32>(v, lane);
-  T r = v[0];
-#pragma unroll
-  for (int mask = 32 / NV; mask > 0; mask >>= 1) r += __shfl_xor(r, mask, 64);
-  return r;
+  return rs_tail<T, 32 / NV>(v[0]);
 }
 
 // ------------------------------------------------------------ Householder --
@@ -194,14 +265,26 @@ __device__ __forceinline__ T wave_reduce_scatter(T (&v)[NV]) {
 template <typename T>
 __device__ __forceinline__ void stage_panel(const T* M, int ld, int j0, int nbj, int Lr, T* Ys,
                                             bool unit) {
-  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
-  for (int a = 0; a < NB; ++a) {
-    const int ac = a < nbj ? a : 0;
-    for (int i = threadIdx.x; i < Lr; i += kBT) {
-      const T x = M[(size_t)(j0 + i) + (size_t)(j0 + ac) * ld];
-      T v = (!unit || i > a) ? x : (i == a ? (T)1 : (T)0);
-      Ys[i * PS + a] = a < nbj ? v : (T)0;
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, RS = kBatchMaxDim / kBT;
+  const T* base = M + j0 + (size_t)j0 * ld;
+  const auto rs = rsrc(base, ((size_t)(NB - 1) * ld + Lr) * sizeof(T));
+  T v[RS][NB];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int i = threadIdx.x + kBT * s;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const bool in = i < Lr && a < nbj && (!unit || i > a);
+      v[s][a] = bload<T>(rs, in ? (uint32_t)((i + (size_t)a * ld) * sizeof(T)) : kOob);
+      if (unit && i == a && a < nbj) v[s][a] += (T)1;
     }
+  }
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int i = threadIdx.x + kBT * s;
+    if (i < Lr)
+#pragma unroll
+      for (int a = 0; a < NB; ++a) Ys[i * PS + a] = v[s][a];
   }
   __syncthreads();
 }
@@ -259,28 +342,35 @@ __device__ __forceinline__ void panel_factor(BLds<T>& L, T* M, int ld, int j0, i
 }
 
 // Ts (upper, row-major NB x NB) of the panel in Ys with scalars tau[0:nbj):
-// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (Y(:, 0:j)^T y_j).
+// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (Y(:, 0:j)^T y_j), the
+// Gram Y^T Y from MFMA over 16-row chunks.  One wave.
 template <typename T>
 __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* tau) {
   constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  using MF = Mfma<T>;
   const T* Ys = L.u.f.Ys;
   T* Ts = L.u.f.Ts;
   T* Gs = L.u.f.Gs;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  constexpr int NP = NB * (NB - 1) / 2;
-  for (int pidx = w; pidx < NP; pidx += kBW) {
-    // pair (a, b), a < b, enumerated column by column
-    int b = 1, base = 0;
-    while (base + b <= pidx) { base += b; ++b; }
-    const int a = pidx - base;
-    T d = 0;
-    if (b < nbj)
-      for (int i = b + lane; i < Lr; i += 64) d += Ys[i * PS + a] * Ys[i * PS + b];
-    d = wsum(d);
-    if (lane == 0) Gs[a * NB + b] = d;
-  }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
+  const int lc = lane & 15, lg = lane >> 4;
   if (w == 0) {
+    typename MF::V g = {0, 0, 0, 0};
+    const int nk = (Lr + 15) >> 4;
+    for (int kc = 0; kc < nk; ++kc) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int row = 16 * kc + 4 * lg + t;
+        const bool ok = row < Lr && lc < NB;
+        const T y = Ys[(ok ? row : 0) * PS + (lc < NB ? lc : 0)];
+        const T yv = ok ? y : (T)0;
+        g = MF::mma(yv, yv, g);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int a = MF::drow(lane, r);
+      if (a < NB && lc < NB) Gs[a * NB + lc] = g[r];
+    }
     for (int e = lane; e < NB * NB; e += 64) Ts[e] = 0;
     for (int j = 0; j < nbj; ++j) {
       const T tj = tau[j];
@@ -295,70 +385,85 @@ __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* ta
   __syncthreads();
 }
 
-// C (Lr x nc, ldc) <- C - Y (T^T (Y^T C)) with Y = Ys (Lr x NB), T = Ts.
+// C (Lr x nc, ldc) <- C - Y (T^T (Y^T C)) with Y = Ys (Lr x NB), T = Ts, on
+// MFMA: each wave takes 16 columns at a time.  W = Y^T C accumulates over
+// 16-row chunks (lane l supplies four consecutive rows of its column), W' =
+// T^T W and C - Y W' take their B operand from the accumulator registers
+// themselves: every product is a sum over an index whose order the lanes
+// agree on, so the K order may follow the accumulator layout.  Panels
+// narrower than 16 (FP64) are padded with zero columns.
 template <typename T>
 __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc, int nc) {
-  constexpr int NB = QrCfg<T>::NB, CG = QrCfg<T>::CG, PS = NB + 1, NV = NB * CG;
-  constexpr int SH = NV == 64 ? 0 : (NV == 32 ? 1 : (NV == 16 ? 2 : 3));   // 6 - log2 NV
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  using MF = Mfma<T>;
+  using V = typename MF::V;
   const T* Ys = L.u.f.Ys;
   const T* Ts = L.u.f.Ts;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  T* Wb = L.u.f.Wb[w];
-  T* Wp = L.u.f.Wp[w];
-  const int nq = (Lr + 63) >> 6;
+  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
+  const int lc = lane & 15, lg = lane >> 4;
   if (nc <= 0) return;
   const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lr) * sizeof(T));
-  for (int c0 = CG * w; c0 < nc; c0 += CG * kBW) {
-    // W = Y^T C for CG columns: per-lane partial sums, then a reduce-scatter
-    T acc[NV];
+  const bool acol = lc < NB;
+  const int lcc = acol ? lc : 0;
+  const int nk = (Lr + 15) >> 4;
+  constexpr int KB = sizeof(T) == 4 ? 16 : 8;    // 16-row chunks per batch of loads
+  for (int c0 = 16 * w; c0 < nc; c0 += 16 * kBW) {
+    const int col = c0 + lc;
+    const bool cok = col < nc;
+    // W = Y^T C, KB chunks of loads in flight at a time
+    V acc = {0, 0, 0, 0};
+    for (int kb = 0; kb < nk; kb += KB) {
+      T cv[KB][4], yv[KB][4];
 #pragma unroll
-    for (int e = 0; e < NV; ++e) acc[e] = 0;
-#pragma unroll 4
-    for (int q = 0; q < nq; ++q) {
-      const int i = lane + 64 * q;
-      const bool ok = i < Lr;
-      const int ic = ok ? i : 0;
-      T cq[CG];
+      for (int u = 0; u < KB; ++u) {
 #pragma unroll
-      for (int cc = 0; cc < CG; ++cc)
-        cq[cc] = bload<T>(rs, (ok && c0 + cc < nc) ? (uint32_t)((i + (size_t)(c0 + cc) * ldc) * sizeof(T)) : kOob);
-#pragma unroll
-      for (int a = 0; a < NB; ++a) {
-        const T y = Ys[ic * PS + a];
-#pragma unroll
-        for (int cc = 0; cc < CG; ++cc) acc[a * CG + cc] += y * cq[cc];
+        for (int t = 0; t < 4; ++t) {
+          const int row = 16 * (kb + u) + 4 * lg + t;
+          const bool ok = row < Lr;
+          cv[u][t] = bload<T>(rs, (ok && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+          const T y = Ys[(ok ? row : 0) * PS + lcc];
+          yv[u][t] = (ok && acol) ? y : (T)0;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < KB; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc = MF::mma(yv[u][t], cv[u][t], acc);
     }
-    const T wsum = wave_reduce_scatter<T, NV>(acc);
-    if ((lane & ((1 << SH) - 1)) == 0) Wb[lane >> SH] = wsum;
-    // W' = T^T W (same wave: LDS order is program order)
-    if (lane < NV) {
-      const int a = lane / CG, cc = lane % CG;
-      T sacc = 0;
-      for (int b = 0; b <= a; ++b) sacc += Ts[b * NB + a] * Wb[b * CG + cc];
-      Wp[lane] = sacc;
+    // W' = T^T W
+    V wp = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int b = MF::drow(lane, t);
+      const T tv = Ts[(b < NB ? b : 0) * NB + lcc];
+      wp = MF::mma((b < NB && acol) ? tv : (T)0, acc[t], wp);
     }
-    T wp[NV];
+    // C <- C - Y W'
+    for (int kb = 0; kb < nk; kb += KB) {
+      V d[KB];
 #pragma unroll
-    for (int e = 0; e < NV; ++e) wp[e] = Wp[e];
-    // C -= Y W'
-#pragma unroll 2
-    for (int q = 0; q < nq; ++q) {
-      const int i = lane + 64 * q;
-      const bool ok = i < Lr;
-      const int ic = ok ? i : 0;
-      T u[CG];
+      for (int u = 0; u < KB; ++u) {
 #pragma unroll
-      for (int cc = 0; cc < CG; ++cc)
-        u[cc] = bload<T>(rs, (ok && c0 + cc < nc) ? (uint32_t)((i + (size_t)(c0 + cc) * ldc) * sizeof(T)) : kOob);
-      T y[NB];
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (kb + u) + MF::drow(lane, r);
+          d[u][r] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+        }
+      }
 #pragma unroll
-      for (int a = 0; a < NB; ++a) y[a] = Ys[ic * PS + a];
+      for (int u = 0; u < KB; ++u) {
+        const int arow = 16 * (kb + u) + lc;
+        const bool aok = arow < Lr;
 #pragma unroll
-      for (int cc = 0; cc < CG; ++cc) {
+        for (int t = 0; t < 4; ++t) {
+          const int a = MF::drow(lane, t);
+          const T y = Ys[(aok ? arow : 0) * PS + (a < NB ? a : 0)];
+          d[u] = MF::mma((aok && a < NB) ? -y : (T)0, wp[t], d[u]);
+        }
 #pragma unroll
-        for (int a = 0; a < NB; ++a) u[cc] -= y[a] * wp[a * CG + cc];
-        if (ok && c0 + cc < nc) C[(size_t)i + (size_t)(c0 + cc) * ldc] = u[cc];
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * (kb + u) + MF::drow(lane, r);
+          if (row < Lr && cok) C[(size_t)row + (size_t)col * ldc] = d[u][r];
+        }
       }
     }
   }
@@ -684,8 +789,8 @@ __device__ __forceinline__ StopOut stop_test(const double s[6], const double mat
 // an iterate is not finite or the backward error has not halved over the last
 // three steps.
 template <typename Correct, typename Residual>
-__device__ __forceinline__ void refine(Correct correct, Residual residual, const double mat[4], int gls, double tol,
-                       int maxit, BatchOut* out) {
+__device__ __forceinline__ void refine(Correct correct, Residual residual, const double mat[4], int gls,
+                                      double tol, int maxit, bool fast_exit, BatchOut* out) {
   correct(true);
   double hist[4] = {0, 0, 0, 0};
   int it = 0;
@@ -696,7 +801,14 @@ __device__ __forceinline__ void refine(Correct correct, Residual residual, const
     so = stop_test(s, mat, gls, tol);
     hist[0] = hist[1]; hist[1] = hist[2]; hist[2] = hist[3]; hist[3] = so.bmax;
     if (so.conv) break;
-    const bool stalled = it >= 3 && !(hist[3] <= 0.5 * hist[0]);
+    bool stalled = it >= 3 && !(hist[3] <= 0.5 * hist[0]);
+    if (fast_exit && it >= 1) {
+      // a higher-precision rung follows: leave once the observed contraction
+      // of the last step predicts more than kMaxPredictedSteps further steps
+      const double rho = hist[3] / hist[2];
+      stalled = stalled || !(rho < 1.0) ||
+                log(hist[3] / tol) > kMaxPredictedSteps * log(1.0 / rho);
+    }
     if (so.bad || it >= maxit || stalled) break;
     correct(false);
   }
@@ -713,7 +825,8 @@ __device__ __forceinline__ void refine(Correct correct, Residual residual, const
 // Abar = A J Qt J = Za [T; 0] (Fa), k = n - p, T11 = T[0:k, 0:k],
 // T12 = T[0:k, k:n], T22 = T[k:m, k:n] (upper part).
 template <typename T>
-__device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit, BatchOut* out,
+__device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit,
+                                             bool fast_exit, BatchOut* out,
                              BLds<T>& L) {
   const int m = P.m, n = P.n, p = P.p, k = n - p, kqa = m < n ? m : n;
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
@@ -822,41 +935,67 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     }
     __syncthreads();
   };
-  // f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v (FP64)
+  // f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v (FP64), one pass over
+  // A and B: wave w owns the 64-row blocks w, w + 4, ... (row sums in
+  // registers); the column sums are added up across the waves in LDS.
+  const auto rsA = rsrc((const double*)A, ((size_t)(n - 1) * P.lda + m) * sizeof(double));
+  const auto rsB = rsrc((const double*)B, ((size_t)(n - 1) * P.ldb + p) * sizeof(double));
   auto residual = [&](double s[6]) {
-    for (int q = 0; q < 6; ++q) s[q] = 0.0;
-    for (int i = t; i < m; i += kBT) {
-      double a = 0.0;
-      for (int j = 0; j < n; ++j) a += A[(size_t)i + (size_t)j * P.lda] * x[j];
-      const double val = bvec[i] - W.r[i] - a;
-      W.f1[i] = val;
-      s[0] += val * val;
-      s[4] += W.r[i] * W.r[i];
+    double* colacc = (double*)L.u.vec[0];
+    for (int j = t; j < n; j += kBT) colacc[j] = 0.0;
+    double ax[kRQ], bx[kRQ], rr[kRQ], vv[kRQ];
+#pragma unroll
+    for (int q = 0; q < kRQ; ++q) {
+      const int i = lane + 64 * (w + kBW * q);
+      ax[q] = 0.0;
+      bx[q] = 0.0;
+      rr[q] = i < m ? W.r[i] : 0.0;
+      vv[q] = i < p ? W.v[i] : 0.0;
     }
-    for (int i = t; i < p; i += kBT) {
-      double a = 0.0;
-      for (int j = 0; j < n; ++j) a += B[(size_t)i + (size_t)j * P.ldb] * x[j];
-      const double val = dvec[i] - a;
-      W.f2[i] = val;
-      s[1] += val * val;
-      s[5] += W.v[i] * W.v[i];
-    }
-    for (int j = w; j < n; j += kBW) {
-      double a = 0.0, b = 0.0;
-      for (int i = lane; i < m; i += 64) a += A[(size_t)i + (size_t)j * P.lda] * W.r[i];
-      for (int i = lane; i < p; i += 64) b += B[(size_t)i + (size_t)j * P.ldb] * W.v[i];
-      a = wsum(a);
-      b = wsum(b);
-      if (lane == 0) {
-        const double val = -a + b;
-        W.f3[j] = val;
-        s[2] += val * val;
-        s[3] += x[j] * x[j];
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) {
+      const double xj = x[j];
+      double cs = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRQ; ++q) {
+        const int i = lane + 64 * (w + kBW * q);
+        const double a = bload<double>(rsA, i < m ? (uint32_t)((i + (size_t)j * P.lda) * 8) : kOob);
+        const double b = bload<double>(rsB, i < p ? (uint32_t)((i + (size_t)j * P.ldb) * 8) : kOob);
+        ax[q] += a * xj;
+        bx[q] += b * xj;
+        cs += b * vv[q] - a * rr[q];
       }
+      cs = wsum(cs);
+      if (lane == 0) atomicAdd(&colacc[j], cs);
+    }
+    for (int q = 0; q < 6; ++q) s[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRQ; ++q) {
+      const int i = lane + 64 * (w + kBW * q);
+      if (i < m) {
+        const double val = bvec[i] - rr[q] - ax[q];
+        W.f1[i] = val;
+        s[0] += val * val;
+        s[4] += rr[q] * rr[q];
+      }
+      if (i < p) {
+        const double val = dvec[i] - bx[q];
+        W.f2[i] = val;
+        s[1] += val * val;
+        s[5] += vv[q] * vv[q];
+      }
+    }
+    __syncthreads();
+    for (int j = t; j < n; j += kBT) {
+      const double val = colacc[j];
+      W.f3[j] = val;
+      s[2] += val * val;
+      s[3] += x[j] * x[j];
     }
     wg_sum6(s, L.dred);
   };
-  refine(correct, residual, mat, 0, tol, maxit, out);
+  refine(correct, residual, mat, 0, tol, maxit, fast_exit, out);
 }
 
 // ------------------------------------------------------------------ GLS --
@@ -864,7 +1003,8 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
 // Vt = J_p (Qw^T V)^T J_n = Qv Tv (Fv, p x n), k = n - m,
 // A11 = Tv[0:k, 0:k], A12 = Tv[0:k, k:n], A22 = Tv[k:p, k:n] (upper part).
 template <typename T>
-__device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit, BatchOut* out,
+__device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit,
+                                             bool fast_exit, BatchOut* out,
                              BLds<T>& L) {
   const int n = P.n, m = P.m, p = P.p, k = n - m, kqv = p < n ? p : n;
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
@@ -971,40 +1111,65 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     }
     __syncthreads();
   };
-  // f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z (FP64)
+  // f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z (FP64), one pass over W
+  // and V: wave w owns the 64-row blocks w, w + 4, ... (row sums in
+  // registers); the column sums are added up across the waves in LDS.
+  const auto rsA = rsrc((const double*)A, ((size_t)(m - 1) * P.lda + n) * sizeof(double));
+  const auto rsB = rsrc((const double*)B, ((size_t)(p - 1) * P.ldb + n) * sizeof(double));
   auto residual = [&](double s[6]) {
-    for (int q = 0; q < 6; ++q) s[q] = 0.0;
-    for (int i = t; i < n; i += kBT) {
-      double a = 0.0;
-      for (int j = 0; j < m; ++j) a += A[(size_t)i + (size_t)j * P.lda] * x[j];
-      for (int j = 0; j < p; ++j) a += B[(size_t)i + (size_t)j * P.ldb] * y[j];
-      const double val = dvec[i] - a;
-      W.f2[i] = val;
-      s[1] += val * val;
-      s[5] += W.z[i] * W.z[i];
+    double* colacc = (double*)L.u.vec[0];               // [0:m) W^T z, [m:m+p) V^T z
+    for (int j = t; j < m + p; j += kBT) colacc[j] = 0.0;
+    double rs_[kRQ], zz[kRQ];
+#pragma unroll
+    for (int q = 0; q < kRQ; ++q) {
+      const int i = lane + 64 * (w + kBW * q);
+      rs_[q] = 0.0;
+      zz[q] = i < n ? W.z[i] : 0.0;
     }
-    for (int j = w; j < p + m; j += kBW) {
-      const bool isv = j < p;
-      const LSQ_GLB double* col = isv ? B + (size_t)j * P.ldb : A + (size_t)(j - p) * P.lda;
-      double a = 0.0;
-      for (int i = lane; i < n; i += 64) a += col[i] * W.z[i];
-      a = wsum(a);
-      if (lane == 0) {
-        if (isv) {
-          const double val = -y[j] + a;
-          W.f1[j] = val;
-          s[0] += val * val;
-          s[4] += y[j] * y[j];
-        } else {
-          W.f3[j - p] = a;
-          s[2] += a * a;
-          s[3] += x[j - p] * x[j - p];
-        }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < m + p; ++j) {
+      const bool isw = j < m;
+      const double cj = isw ? x[j] : y[j - m];
+      double cs = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRQ; ++q) {
+        const int i = lane + 64 * (w + kBW * q);
+        const double a = isw ? bload<double>(rsA, i < n ? (uint32_t)((i + (size_t)j * P.lda) * 8) : kOob)
+                             : bload<double>(rsB, i < n ? (uint32_t)((i + (size_t)(j - m) * P.ldb) * 8) : kOob);
+        rs_[q] += a * cj;
+        cs += a * zz[q];
       }
+      cs = wsum(cs);
+      if (lane == 0) atomicAdd(&colacc[j], cs);
+    }
+    for (int q = 0; q < 6; ++q) s[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRQ; ++q) {
+      const int i = lane + 64 * (w + kBW * q);
+      if (i < n) {
+        const double val = dvec[i] - rs_[q];
+        W.f2[i] = val;
+        s[1] += val * val;
+        s[5] += zz[q] * zz[q];
+      }
+    }
+    __syncthreads();
+    for (int j = t; j < m; j += kBT) {
+      const double val = colacc[j];
+      W.f3[j] = val;
+      s[2] += val * val;
+      s[3] += x[j] * x[j];
+    }
+    for (int j = t; j < p; j += kBT) {
+      const double val = -y[j] + colacc[m + j];
+      W.f1[j] = val;
+      s[0] += val * val;
+      s[4] += y[j] * y[j];
     }
     wg_sum6(s, L.dred);
   };
-  refine(correct, residual, mat, 1, tol, maxit, out);
+  refine(correct, residual, mat, 1, tol, maxit, fast_exit, out);
 }
 
 template <typename T>
@@ -1012,7 +1177,7 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchProb* __restrict__ 
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
                                                   size_t ws_stride, double tol, int maxit,
-                                                  BatchOut* __restrict__ out) {
+                                                  int fast_exit, BatchOut* __restrict__ out) {
   __shared__ BLds<T> L;
   char* mine = ws + (size_t)blockIdx.x * ws_stride;
   for (;;) {
@@ -1023,8 +1188,8 @@ __global__ __launch_bounds__(kBT, 2) void k_batch(const BatchProb* __restrict__ 
     if (q >= count) break;
     const int idx = order[q];
     const BatchProb P = probs[idx];
-    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, out + idx, L);
-    else gls_instance<T>(P, mine, tol, maxit, out + idx, L);
+    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, fast_exit != 0, out + idx, L);
+    else gls_instance<T>(P, mine, tol, maxit, fast_exit != 0, out + idx, L);
     __syncthreads();
   }
 }
@@ -1071,17 +1236,17 @@ double batch_factor_flops(const BatchProb& P) {
 
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
-                  BatchOut* out, double flops) {
+                  bool fast_exit, BatchOut* out, double flops) {
   if (count <= 0 || grid <= 0) return;
   LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
   const int kind = tw == 8 ? kKBatch64 : kKBatch32;
   ktimer_begin(ctx, kind, flops, 0.0);
   if (tw == 8)
     hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, out);
+                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out);
   else
     hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, out);
+                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kind);
 }

@@ -239,9 +239,10 @@ double batch_factor_flops(const BatchProb& P);
 // One persistent launch over order[0:count) (indices into probs, device
 // arrays); tw = 4 (FP32 factors and corrections) or 8 (FP64).  counter: one
 // device int; ws: grid * ws_stride bytes; flops: algorithmic work of the
-// launch, for the kernel timer.
+// launch, for the kernel timer.  fast_exit: a higher-precision rung follows,
+// so an instance whose refinement contracts too slowly stops early.
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
-                  BatchOut* out, double flops);
+                  bool fast_exit, BatchOut* out, double flops);
 
 }  // namespace lsq

@@ -98,12 +98,14 @@ __device__ __forceinline__ T wsum(T v) {
   return (lane_val(v, 0) + lane_val(v, 16)) + (lane_val(v, 32) + lane_val(v, 48));
 }
 
-// Panel width and trailing-update column group of the blocked QR: the LDS
-// panel (kBatchMaxDim x (NB + 1)) fills about 70 KB in both precisions, so
-// two work-groups share a compute unit.
+// Panel width of the blocked QR (a multiple of the 16-row MFMA tile): the LDS
+// panel (kBatchMaxDim x (NB + 1)) fills about 140 KB in both precisions, one
+// work-group per compute unit.  A single work-group is bound by the memory
+// requests one compute unit keeps in flight, so the wider panel (fewer passes
+// over the trailing matrix) matters more than a second resident work-group.
 template <typename T> struct QrCfg;
-template <> struct QrCfg<float> { static constexpr int NB = 16, CG = 4; };
-template <> struct QrCfg<double> { static constexpr int NB = 8, CG = 2; };
+template <> struct QrCfg<float> { static constexpr int NB = 32; };
+template <> struct QrCfg<double> { static constexpr int NB = 16; };
 
 // 16 x 16 x 4 MFMA per precision.  Lane l supplies A[l%16][k] and B[k][l%16]
 // for the K index k it holds; accumulator register r of lane l holds row
@@ -126,14 +128,12 @@ template <> struct Mfma<double> {
 
 template <typename T>
 struct BLds {
-  static constexpr int NB = QrCfg<T>::NB, CG = QrCfg<T>::CG, PS = NB + 1;
+  static constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
   union {
     struct {
       T Ys[kBatchMaxDim * PS];       // panel, row-major with row stride PS
       T Ts[NB * NB];                 // compact-WY triangle (row-major, upper)
       T Gs[NB * NB];                 // Gram of the panel's reflectors
-      T Wb[kBW][NB * CG];            // per-wave Y^T C block
-      T Wp[kBW][NB * CG];            // per-wave T^T Y^T C block
       T beta[NB], tau[NB];
     } f;
     T vec[kVecs][kBatchMaxDim];      // vectors of the correction solves
@@ -172,83 +172,6 @@ __device__ __forceinline__ void wg_sum6(double v[6], double* red) {
     for (int i = 0; i < kBW; ++i) s += red[i * 6 + k];
     v[k] = s;
   }
-}
-
-// Pairwise swaps across half-waves and rows (gfx950 permlane swaps): for X,
-// Y in every lane, afterwards X + Y is the lane's own value plus its partner's
-// (lane ^ 32, resp. lane ^ 16), taken from X in the lower and from Y in the
-// upper lane of each pair.
-__device__ __forceinline__ void lane_swap32(unsigned& x, unsigned& y) {
-  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
-  x = r[0];
-  y = r[1];
-}
-__device__ __forceinline__ void lane_swap16(unsigned& x, unsigned& y) {
-  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
-  x = r[0];
-  y = r[1];
-}
-template <int MASK>
-__device__ __forceinline__ float pair_sum(float lo, float hi) {
-  unsigned x = __float_as_uint(lo), y = __float_as_uint(hi);
-  if constexpr (MASK == 32) lane_swap32(x, y); else lane_swap16(x, y);
-  return __uint_as_float(x) + __uint_as_float(y);
-}
-template <int MASK>
-__device__ __forceinline__ double pair_sum(double lo, double hi) {
-  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
-  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
-  unsigned xl = (unsigned)a, xh = (unsigned)(a >> 32), yl = (unsigned)b, yh = (unsigned)(b >> 32);
-  if constexpr (MASK == 32) { lane_swap32(xl, yl); lane_swap32(xh, yh); }
-  else { lane_swap16(xl, yl); lane_swap16(xh, yh); }
-  const double x = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
-  const double y = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
-  return x + y;
-}
-// DPP exchange pairing each lane with one whose bit MASK differs (within a
-// row of 16): xor 8, mirror within 8, mirror within 4, xor 1.
-template <int MASK> struct PairDpp;
-template <> struct PairDpp<8> { static constexpr int ctrl = 0x128; };   // row_ror:8
-template <> struct PairDpp<4> { static constexpr int ctrl = 0x141; };   // row_half_mirror
-template <> struct PairDpp<2> { static constexpr int ctrl = 0x1B; };    // quad_perm [3,2,1,0]
-template <> struct PairDpp<1> { static constexpr int ctrl = 0xB1; };    // quad_perm [1,0,3,2]
-
-// Reduce-scatter of NV (a power of two <= 64) per-lane values over the wave:
-// every lane returns the wave total of value index lane >> (6 - log2 NV).
-// Each halving step keeps the half of the values selected by one lane bit and
-// adds the partner lane's copy of it.
-template <typename T, int NV, int HALF, int MASK>
-__device__ __forceinline__ void rs_step(T (&v)[NV], int lane) {
-  if constexpr (HALF >= 1) {
-    if constexpr (MASK >= 16) {
-#pragma unroll
-      for (int k = 0; k < HALF; ++k) v[k] = pair_sum<MASK>(v[k], v[k + HALF]);
-    } else {
-      const bool up = (lane & MASK) != 0;
-#pragma unroll
-      for (int k = 0; k < HALF; ++k) {
-        const T keep = up ? v[k + HALF] : v[k];
-        const T send = up ? v[k] : v[k + HALF];
-        v[k] = keep + dpp<PairDpp<MASK>::ctrl>(send);
-      }
-    }
-    rs_step<T, NV, HALF / 2, MASK / 2>(v, lane);
-  }
-}
-template <typename T, int MASK>
-__device__ __forceinline__ T rs_tail(T r) {
-  if constexpr (MASK >= 1) {
-    if constexpr (MASK >= 16) r += __shfl_xor(r, MASK, 64);
-    else r += dpp<PairDpp<MASK>::ctrl>(r);
-    return rs_tail<T, MASK / 2>(r);
-  }
-  return r;
-}
-template <typename T, int NV>
-__device__ __forceinline__ T wave_reduce_scatter(T (&v)[NV]) {
-  const int lane = threadIdx.x & 63;
-  rs_step<T, NV, NV / 2, 32>(v, lane);
-  return rs_tail<T, 32 / NV>(v[0]);
 }
 
 // ------------------------------------------------------------ Householder --
@@ -319,13 +242,34 @@ __device__ __forceinline__ void panel_factor(BLds<T>& L, T* M, int ld, int j0, i
       if (a < Lr) Ys[a * PS + a] = 1;
     }
     __syncthreads();
-    // H_a applied to the panel's columns a+1 .. nbj-1, one column per wave
-    if (tau != (T)0) {
+    // H_a applied to the panel's columns a+1 .. nbj-1, one column per wave;
+    // v and each column are read into registers in one batch of LDS loads
+    if (tau != (T)0 && a + 1 + w < nbj) {
+      const int nq = (Lr + 63) >> 6;
+      T vr[kBS];
+#pragma unroll
+      for (int q = 0; q < kBS; ++q) {
+        const int i = lane + 64 * q;
+        const bool in = q < nq && i >= a && i < Lr;
+        const T x = Ys[(in ? i : a) * PS + a];
+        vr[q] = in ? x : (T)0;
+      }
       for (int b = a + 1 + w; b < nbj; b += kBW) {
+        T cb[kBS];
+#pragma unroll
+        for (int q = 0; q < kBS; ++q) {
+          const int i = lane + 64 * q;
+          cb[q] = Ys[((q < nq && i < Lr) ? i : 0) * PS + b];
+        }
         T d = 0;
-        for (int i = a + lane; i < Lr; i += 64) d += Ys[i * PS + a] * Ys[i * PS + b];
+#pragma unroll
+        for (int q = 0; q < kBS; ++q) d += vr[q] * cb[q];
         d = wsum(d) * tau;
-        for (int i = a + lane; i < Lr; i += 64) Ys[i * PS + b] -= d * Ys[i * PS + a];
+#pragma unroll
+        for (int q = 0; q < kBS; ++q) {
+          const int i = lane + 64 * q;
+          if (q < nq && i >= a && i < Lr) Ys[i * PS + b] = cb[q] - d * vr[q];
+        }
       }
     }
     __syncthreads();
@@ -343,10 +287,10 @@ __device__ __forceinline__ void panel_factor(BLds<T>& L, T* M, int ld, int j0, i
 
 // Ts (upper, row-major NB x NB) of the panel in Ys with scalars tau[0:nbj):
 // T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (Y(:, 0:j)^T y_j), the
-// Gram Y^T Y from MFMA over 16-row chunks.  One wave.
+// Gram Y^T Y from MFMA over 16-row chunks (16 x 16 blocks).  One wave.
 template <typename T>
 __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* tau) {
-  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
   using MF = Mfma<T>;
   const T* Ys = L.u.f.Ys;
   T* Ts = L.u.f.Ts;
@@ -354,33 +298,55 @@ __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* ta
   const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
   const int lc = lane & 15, lg = lane >> 4;
   if (w == 0) {
-    typename MF::V g = {0, 0, 0, 0};
+    typename MF::V g[NBB][NBB];
+#pragma unroll
+    for (int bi = 0; bi < NBB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBB; ++bj) g[bi][bj] = typename MF::V{0, 0, 0, 0};
     const int nk = (Lr + 15) >> 4;
     for (int kc = 0; kc < nk; ++kc) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int row = 16 * kc + 4 * lg + t;
-        const bool ok = row < Lr && lc < NB;
-        const T y = Ys[(ok ? row : 0) * PS + (lc < NB ? lc : 0)];
-        const T yv = ok ? y : (T)0;
-        g = MF::mma(yv, yv, g);
+        const bool ok = row < Lr;
+        T yv[NBB];
+#pragma unroll
+        for (int b = 0; b < NBB; ++b) {
+          const T y = Ys[(ok ? row : 0) * PS + 16 * b + lc];
+          yv[b] = ok ? y : (T)0;
+        }
+#pragma unroll
+        for (int bi = 0; bi < NBB; ++bi)
+#pragma unroll
+          for (int bj = bi; bj < NBB; ++bj) g[bi][bj] = MF::mma(yv[bi], yv[bj], g[bi][bj]);
       }
     }
+    // upper blocks from the products; the lower ones are written as zeros (the
+    // recurrence multiplies them by zeros, and LDS may hold any bit pattern)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int a = MF::drow(lane, r);
-      if (a < NB && lc < NB) Gs[a * NB + lc] = g[r];
-    }
-    for (int e = lane; e < NB * NB; e += 64) Ts[e] = 0;
+    for (int bi = 0; bi < NBB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBB; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Gs[(16 * bi + MF::drow(lane, r)) * NB + 16 * bj + lc] = bj >= bi ? g[bi][bj][r] : (T)0;
+    // lane i keeps row i of T in registers; column j of G is read in one
+    // batch of (broadcast) LDS loads per step
+    T trow[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) trow[l] = 0;
     for (int j = 0; j < nbj; ++j) {
       const T tj = tau[j];
-      if (lane < j) {
-        T sacc = 0;
-        for (int l = lane; l < j; ++l) sacc += Ts[lane * NB + l] * Gs[l * NB + j];
-        Ts[lane * NB + j] = -tj * sacc;
-      }
-      if (lane == j) Ts[j * NB + j] = tj;
+      T sacc = 0;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) sacc += trow[l] * Gs[l * NB + j];
+      const T val = lane < j ? -tj * sacc : (lane == j ? tj : (T)0);
+#pragma unroll
+      for (int l = 0; l < NB; ++l) trow[l] = (l == j) ? val : trow[l];
     }
+    if (lane < NB)
+#pragma unroll
+      for (int l = 0; l < NB; ++l) Ts[lane * NB + l] = trow[l];
   }
   __syncthreads();
 }
@@ -390,11 +356,12 @@ __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* ta
 // 16-row chunks (lane l supplies four consecutive rows of its column), W' =
 // T^T W and C - Y W' take their B operand from the accumulator registers
 // themselves: every product is a sum over an index whose order the lanes
-// agree on, so the K order may follow the accumulator layout.  Panels
-// narrower than 16 (FP64) are padded with zero columns.
+// agree on, so the K order may follow the accumulator layout.  The panel's
+// NB columns form NB / 16 blocks of the 16 x 16 tiles.
 template <typename T>
 __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc, int nc) {
-  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
+  constexpr int KB = sizeof(T) == 4 ? 8 : 4;    // 16-row chunks per batch of loads
   using MF = Mfma<T>;
   using V = typename MF::V;
   const T* Ys = L.u.f.Ys;
@@ -403,62 +370,70 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc
   const int lc = lane & 15, lg = lane >> 4;
   if (nc <= 0) return;
   const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lr) * sizeof(T));
-  const bool acol = lc < NB;
-  const int lcc = acol ? lc : 0;
   const int nk = (Lr + 15) >> 4;
-  constexpr int KB = sizeof(T) == 4 ? 16 : 8;    // 16-row chunks per batch of loads
   for (int c0 = 16 * w; c0 < nc; c0 += 16 * kBW) {
     const int col = c0 + lc;
     const bool cok = col < nc;
-    // W = Y^T C, KB chunks of loads in flight at a time
-    V acc = {0, 0, 0, 0};
-    for (int kb = 0; kb < nk; kb += KB) {
-      T cv[KB][4], yv[KB][4];
+    // W = Y^T C (block b holds rows 16 b .. 16 b + 15 of W)
+    V acc[NBB];
 #pragma unroll
-      for (int u = 0; u < KB; ++u) {
+    for (int b = 0; b < NBB; ++b) acc[b] = V{0, 0, 0, 0};
+    for (int kb = 0; kb < nk; kb += KB) {
+      T cv[KB][4];
+#pragma unroll
+      for (int u = 0; u < KB; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int row = 16 * (kb + u) + 4 * lg + t;
+          cv[u][t] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+        }
+#pragma unroll
+      for (int u = 0; u < KB; ++u)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const int row = 16 * (kb + u) + 4 * lg + t;
           const bool ok = row < Lr;
-          cv[u][t] = bload<T>(rs, (ok && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
-          const T y = Ys[(ok ? row : 0) * PS + lcc];
-          yv[u][t] = (ok && acol) ? y : (T)0;
+#pragma unroll
+          for (int b = 0; b < NBB; ++b) {
+            const T y = Ys[(ok ? row : 0) * PS + 16 * b + lc];
+            acc[b] = MF::mma(ok ? y : (T)0, cv[u][t], acc[b]);
+          }
         }
-      }
-#pragma unroll
-      for (int u = 0; u < KB; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc = MF::mma(yv[u][t], cv[u][t], acc);
     }
-    // W' = T^T W
-    V wp = {0, 0, 0, 0};
+    // W' = T^T W; T is upper triangular, so block o takes blocks i <= o
+    V wp[NBB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int b = MF::drow(lane, t);
-      const T tv = Ts[(b < NB ? b : 0) * NB + lcc];
-      wp = MF::mma((b < NB && acol) ? tv : (T)0, acc[t], wp);
+    for (int o = 0; o < NBB; ++o) {
+      wp[o] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i <= o; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int b = 16 * i + MF::drow(lane, t);
+          wp[o] = MF::mma(Ts[b * NB + 16 * o + lc], acc[i][t], wp[o]);
+        }
     }
     // C <- C - Y W'
     for (int kb = 0; kb < nk; kb += KB) {
       V d[KB];
 #pragma unroll
-      for (int u = 0; u < KB; ++u) {
+      for (int u = 0; u < KB; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (kb + u) + MF::drow(lane, r);
           d[u][r] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
         }
-      }
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         const int arow = 16 * (kb + u) + lc;
         const bool aok = arow < Lr;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int a = MF::drow(lane, t);
-          const T y = Ys[(aok ? arow : 0) * PS + (a < NB ? a : 0)];
-          d[u] = MF::mma((aok && a < NB) ? -y : (T)0, wp[t], d[u]);
-        }
+        for (int b = 0; b < NBB; ++b)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const T y = Ys[(aok ? arow : 0) * PS + 16 * b + MF::drow(lane, t)];
+            d[u] = MF::mma(aok ? -y : (T)0, wp[b][t], d[u]);
+          }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * (kb + u) + MF::drow(lane, r);
@@ -1173,7 +1148,7 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBT, 2) void k_batch(const BatchProb* __restrict__ probs,
+__global__ __launch_bounds__(kBT, 1) void k_batch(const BatchProb* __restrict__ probs,
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
                                                   size_t ws_stride, double tol, int maxit,

@@ -217,7 +217,7 @@ void mlp_select(Ctx& ctx, const float* weights, const float* feats, float* logit
 // (m, n, p, A = A, B = B, b, d, x); type 1 = GLS with (n, m, p, A = W, B = V,
 // d, x, y)).  Pointers are device pointers to FP64 column-major data.
 constexpr int kBatchMaxDim = 1024;       // largest m, n, p of an instance
-constexpr int kBatchBlocksPerCu = 2;
+constexpr int kBatchBlocksPerCu = 1;
 struct BatchProb {
   int type, m, n, p;
   const double *A, *B, *b, *d;

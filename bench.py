@@ -65,19 +65,25 @@ def parse():
                          "LSE/GLS workload")
     ap.add_argument("--count", type=int, default=2000, help="instances of the batched workload")
     ap.add_argument("--workers", type=int, default=8, help="batch workers (streams)")
+    ap.add_argument("--no-workers", action="store_true",
+                    help="batched workload: skip the per-instance worker runs (context lines)")
     return ap.parse_args()
 
 
-def source_hash():
+BATCH_SOURCES = ["paper_2406_16499_amd/csrc/batch.hip", "paper_2406_16499_amd/csrc/common.hpp",
+                 "paper_2406_16499_amd/csrc/engine.hpp"]
+
+
+def source_hash(files=None):
     import hashlib
     hsh = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (files or KERNEL_SOURCES):
         with open(os.path.join(ROOT, f), "rb") as fh:
             hsh.update(fh.read())
     return hsh.hexdigest()[:16]
 
 
-def traffic_per_launch(kernel):
+def traffic_per_launch(kernel, files=None):
     """HBM bytes per launch from the committed hardware-counter summary, if it
     was taken on the current kernel sources (else None)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.txt")
@@ -88,7 +94,7 @@ def traffic_per_launch(kernel):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != source_hash():
+    if kv.get("source_hash") != source_hash(files):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -237,8 +243,15 @@ def batched(args):
     # per-instance solves on the batch workers (context): the learned selector
     # picks each instance's starting rung
     auto = lsq.default_opts(prec="auto", solver="auto", escalate=1)
-    dts, oks, rungss, _ = run(auto, 1, 0, mode="workers")
-    dtw, okw, _, _ = run(lsq.default_opts(prec="fp64", solver="direct"), 1, 0, mode="workers")
+    if not args.no_workers:
+        dts, oks, rungss, _ = run(auto, 1, 0, mode="workers")
+        dtw, okw, _, _ = run(lsq.default_opts(prec="fp64", solver="direct"), 1, 0, mode="workers")
+    # calibration copy of known size, outside the timed regions (scales the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run)
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    h.dbg_copy(dst, src, COPY_BYTES)
+    del src, dst
     value = ok / dt
     value64 = ok64 / dt64
     ms, launches, flops, _ = tim
@@ -246,10 +259,12 @@ def batched(args):
     if launches > 0 and ms > 0:
         achieved = (flops / launches) / (ms / launches * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR, "traffic": None, "kernel": "k_batch<float>",
+                "frac": achieved / PEAK_FP32_VECTOR,
+                "traffic": traffic_per_launch("batch_fp32", BATCH_SOURCES), "kernel": "k_batch<float>",
                 "launches_per_step": launches / args.steps, "avg_launch_us": 1000.0 * ms / launches,
                 "alg_flops_per_launch": flops / launches,
-                "flops_counted": "Householder flops of the factorizations of the instances in the launch"}
+                "flops_counted": "Householder flops of the factorizations of the instances in the launch",
+                "source_hash": source_hash(BATCH_SOURCES)}
     line = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
@@ -265,10 +280,12 @@ def batched(args):
         "speedup_vs_fp64": value / value64 if value64 > 0 else None,
         "certified_fraction": ok / (args.count * args.steps),
         "rungs_used": rungs,
-        "workers_selector": {"value": oks / dts, "unit": "solves/s", "ms_per_step": 1000.0 * dts,
-                             "selector": "learned" if have_sel else "none (AUTO = FP32 + IR)",
-                             "workers": args.workers, "rungs_used": rungss},
-        "workers_fp64_direct": {"value": okw / dtw, "unit": "solves/s", "ms_per_step": 1000.0 * dtw},
+        "workers_selector": None if args.no_workers else
+        {"value": oks / dts, "unit": "solves/s", "ms_per_step": 1000.0 * dts,
+         "selector": "learned" if have_sel else "none (AUTO = FP32 + IR)",
+         "workers": args.workers, "rungs_used": rungss},
+        "workers_fp64_direct": None if args.no_workers else
+        {"value": okw / dtw, "unit": "solves/s", "ms_per_step": 1000.0 * dtw},
         "roofline": roof,
         "generation_s": gen_s,
     }

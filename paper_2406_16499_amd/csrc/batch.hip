@@ -666,48 +666,69 @@ struct GlsWs {
   double *z, *f1, *f2, *f3;
 };
 
-// T blocks of the panels of a QR with k reflectors
-__host__ __device__ constexpr size_t tblocks(int k, int nb) { return (size_t)((k + nb - 1) / nb) * nb * nb; }
+// Byte offsets of an instance's workspace regions for element size esz and
+// panel width nb, computed by one function on the host (sizing) and on the
+// device (use).  LSE: Fb, taub, Tb, X, Fa, taua, Ta, r, v, f1, f2, f3;
+// GLS: Fw, taw, Tw, X, Fv, tav, Tv, z, f1, f2, f3.  Returns the total.
+__host__ __device__ inline size_t ws_layout(int type, int m, int n, int p, int esz, int nb,
+                                            size_t* off) {
+  size_t o = 0;
+  int k = 0;
+  auto take = [&](size_t bytes) {
+    off[k++] = o;
+    o += (bytes + 255) & ~(size_t)255;
+  };
+  auto tblk = [&](int refl) { return (size_t)((refl + nb - 1) / nb) * nb * nb * esz; };
+  const size_t e = (size_t)esz, M = m, N = n, Pp = p;
+  if (type == 0) {
+    const int ka = m < n ? m : n;
+    take(e * N * Pp); take(e * Pp); take(tblk(p)); take(e * N * M); take(e * M * N);
+    take(e * ka); take(tblk(ka));
+    take(8 * M); take(8 * Pp); take(8 * M); take(8 * Pp); take(8 * N);
+  } else {
+    const int kv = p < n ? p : n;
+    take(e * N * M); take(e * M); take(tblk(m)); take(e * N * Pp); take(e * Pp * N);
+    take(e * kv); take(tblk(kv));
+    take(8 * N); take(8 * Pp); take(8 * N); take(8 * M);
+  }
+  return o;
+}
 
 template <typename T>
 __device__ __forceinline__ LseWs<T> lse_ws(char* base, int m, int n, int p) {
-  constexpr int NB = QrCfg<T>::NB;
+  size_t off[12];
+  ws_layout(0, m, n, p, (int)sizeof(T), QrCfg<T>::NB, off);
   LseWs<T> w;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { char* q = base + o; o += align256(bytes); return q; };
-  const int ka = m < n ? m : n;
-  w.Fb = (T*)take(sizeof(T) * (size_t)n * p);
-  w.taub = (T*)take(sizeof(T) * p);
-  w.Tb = (T*)take(sizeof(T) * tblocks(p, NB));
-  w.X = (T*)take(sizeof(T) * (size_t)n * m);
-  w.Fa = (T*)take(sizeof(T) * (size_t)m * n);
-  w.taua = (T*)take(sizeof(T) * ka);
-  w.Ta = (T*)take(sizeof(T) * tblocks(ka, NB));
-  w.r = (double*)take(8 * (size_t)m);
-  w.v = (double*)take(8 * (size_t)p);
-  w.f1 = (double*)take(8 * (size_t)m);
-  w.f2 = (double*)take(8 * (size_t)p);
-  w.f3 = (double*)take(8 * (size_t)n);
+  w.Fb = (T*)(base + off[0]);
+  w.taub = (T*)(base + off[1]);
+  w.Tb = (T*)(base + off[2]);
+  w.X = (T*)(base + off[3]);
+  w.Fa = (T*)(base + off[4]);
+  w.taua = (T*)(base + off[5]);
+  w.Ta = (T*)(base + off[6]);
+  w.r = (double*)(base + off[7]);
+  w.v = (double*)(base + off[8]);
+  w.f1 = (double*)(base + off[9]);
+  w.f2 = (double*)(base + off[10]);
+  w.f3 = (double*)(base + off[11]);
   return w;
 }
 template <typename T>
 __device__ __forceinline__ GlsWs<T> gls_ws(char* base, int n, int m, int p) {
-  constexpr int NB = QrCfg<T>::NB;
+  size_t off[12];
+  ws_layout(1, m, n, p, (int)sizeof(T), QrCfg<T>::NB, off);
   GlsWs<T> w;
-  size_t o = 0;
-  auto take = [&](size_t bytes) { char* q = base + o; o += align256(bytes); return q; };
-  const int kv = p < n ? p : n;
-  w.Fw = (T*)take(sizeof(T) * (size_t)n * m);
-  w.taw = (T*)take(sizeof(T) * m);
-  w.Tw = (T*)take(sizeof(T) * tblocks(m, NB));
-  w.X = (T*)take(sizeof(T) * (size_t)n * p);
-  w.Fv = (T*)take(sizeof(T) * (size_t)p * n);
-  w.tav = (T*)take(sizeof(T) * kv);
-  w.Tv = (T*)take(sizeof(T) * tblocks(kv, NB));
-  w.z = (double*)take(8 * (size_t)n);
-  w.f1 = (double*)take(8 * (size_t)p);
-  w.f2 = (double*)take(8 * (size_t)n);
-  w.f3 = (double*)take(8 * (size_t)m);
+  w.Fw = (T*)(base + off[0]);
+  w.taw = (T*)(base + off[1]);
+  w.Tw = (T*)(base + off[2]);
+  w.X = (T*)(base + off[3]);
+  w.Fv = (T*)(base + off[4]);
+  w.tav = (T*)(base + off[5]);
+  w.Tv = (T*)(base + off[6]);
+  w.z = (double*)(base + off[7]);
+  w.f1 = (double*)(base + off[8]);
+  w.f2 = (double*)(base + off[9]);
+  w.f3 = (double*)(base + off[10]);
   return w;
 }
 
@@ -1172,19 +1193,10 @@ __global__ __launch_bounds__(kBT, 1) void k_batch(const BatchProb* __restrict__ 
 }  // namespace
 
 size_t batch_ws_bytes(const BatchProb& P) {
-  auto a = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t m = P.m, n = P.n, p = P.p, d = 8;
-  // T blocks: 16 x 16 floats per 16 reflectors or 8 x 8 doubles per 8, at most
-  // 64 bytes per reflector either way (+ one block)
-  auto tb = [&](size_t k) { return a(64 * k + 2048); };
-  if (P.type == 0) {
-    const size_t ka = m < n ? m : n;
-    return a(d * n * p) + a(d * p) + tb(p) + a(d * n * m) + a(d * m * n) + a(d * ka) + tb(ka) +
-           a(d * m) + a(d * p) + a(d * m) + a(d * p) + a(d * n);
-  }
-  const size_t kv = p < n ? p : n;
-  return a(d * n * m) + a(d * m) + tb(m) + a(d * n * p) + a(d * p * n) + a(d * kv) + tb(kv) +
-         a(d * n) + a(d * p) + a(d * n) + a(d * m);
+  size_t off[12];
+  const size_t a = ws_layout(P.type, P.m, P.n, P.p, 4, QrCfg<float>::NB, off);
+  const size_t b = ws_layout(P.type, P.m, P.n, P.p, 8, QrCfg<double>::NB, off);
+  return a > b ? a : b;
 }
 
 bool batch_eligible(const BatchProb& P) {

@@ -78,7 +78,7 @@ def _mean_for(per: dict, match: str):
 
 
 def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, match: str, cmd_fetch: str,
-                    cmd_write: str, out: str) -> str:
+                    cmd_write: str, out: str, sources: str = "qr") -> str:
     sys.path.insert(0, ROOT)
     import bench   # noqa: E402  (source hash and calibration size)
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
@@ -96,7 +96,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, match: str, cmd
         f"# write command: {cmd_write}",
         f"kernel: {kernel}",
         f"match: {match}",
-        f"source_hash: {bench.source_hash()}",
+        f"source_hash: {bench.source_hash(bench.BATCH_SOURCES if sources == 'batch' else None)}",
         f"dispatches_fetch: {nkf}",
         f"dispatches_write: {nkw}",
         f"fetch_kib_per_launch_raw: {kf:.1f}",
@@ -130,11 +130,14 @@ def main(argv=None):
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--sources", default="qr", choices=["qr", "batch"],
+                   help="source set whose hash the summary records")
     a = ap.parse_args(argv)
     if a.action == "stats":
         print(stats_summary(a.csv, a.cmd, a.out, a.top), end="")
     else:
-        print(traffic_summary(a.fetch, a.write, a.kernel, a.match, a.cmd_fetch, a.cmd_write, a.out),
+        print(traffic_summary(a.fetch, a.write, a.kernel, a.match, a.cmd_fetch, a.cmd_write, a.out,
+                              a.sources),
               end="")
 
 

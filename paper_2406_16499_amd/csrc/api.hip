@@ -911,7 +911,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     }
   }
   if (cur.empty()) return rest;
-  const int max_grid = kBatchBlocksPerCu * h->num_cu;
+  const int max_grid = std::max(batch_blocks_per_cu(4), batch_blocks_per_cu(8)) * h->num_cu;
   const int grid = std::min((int)cur.size(), max_grid);
   w->arena.reset();
   BatchProb* dprobs = ctx.ws->get<BatchProb>(count);
@@ -928,8 +928,10 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     double flops = 0.0;
     for (int q : cur) flops += batch_factor_flops(hp[q]);
     const bool last = prec == LSQ_PREC_FP64 || !o.escalate;
-    batch_launch(ctx, prec == LSQ_PREC_FP64 ? 8 : 4, dprobs, dorder, (int)cur.size(), dcounter, dws,
-                 stride, std::min(grid, (int)cur.size()), o.tol, o.maxit, !last, dout, flops);
+    const int tw = prec == LSQ_PREC_FP64 ? 8 : 4;
+    const int g = std::min(batch_blocks_per_cu(tw) * h->num_cu, (int)cur.size());
+    batch_launch(ctx, tw, dprobs, dorder, (int)cur.size(), dcounter, dws, stride, g, o.tol, o.maxit,
+                 !last, dout, flops);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> failed;

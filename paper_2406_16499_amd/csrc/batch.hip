@@ -1,7 +1,7 @@
 // Persistent batched solver: one work-group per instance.
 //
-// A batch of small LSE / GLS instances is solved by one launch of
-// kBatchBlocksPerCu work-groups per compute unit.  Each work-group takes the
+// A batch of small LSE / GLS instances is solved by one launch of one or two
+// work-groups per compute unit (batch_blocks_per_cu).  Each work-group takes the
 // next instance from a device counter (the host orders the instances longest
 // first) and carries out the whole method for it: the generalized RQ (LSE) or
 // generalized QR (GLS) factorization of Section 3 in precision T, then
@@ -51,6 +51,15 @@ template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4v bload4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(f32x4v, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore4(f32x4v v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b128(
+      __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)), v), r, off, 0, 0);
+}
+
 // Wave-uniform copies of values the compiler cannot prove uniform (the
 // arguments of out-of-line functions arrive in vector registers).
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -98,14 +107,16 @@ __device__ __forceinline__ T wsum(T v) {
   return (lane_val(v, 0) + lane_val(v, 16)) + (lane_val(v, 32) + lane_val(v, 48));
 }
 
-// Panel width of the blocked QR (a multiple of the 16-row MFMA tile): the LDS
-// panel (kBatchMaxDim x (NB + 1)) fills about 140 KB in both precisions, one
-// work-group per compute unit.  A single work-group is bound by the memory
-// requests one compute unit keeps in flight, so the wider panel (fewer passes
-// over the trailing matrix) matters more than a second resident work-group.
+// Panel width of the blocked QR (a multiple of the 16-row MFMA tile) and
+// resident work-groups per compute unit: the LDS panel (kBatchMaxDim x
+// (NB + 1)) takes about 70 KB in FP32 (two work-groups per compute unit) and
+// 140 KB in FP64 (one).  A work-group is bound by the memory requests its
+// compute unit keeps in flight and by the latency of the sequential panel
+// steps; wider panels cut the passes over the trailing matrix but lengthen
+// every panel step.
 template <typename T> struct QrCfg;
-template <> struct QrCfg<float> { static constexpr int NB = 32; };
-template <> struct QrCfg<double> { static constexpr int NB = 16; };
+template <> struct QrCfg<float> { static constexpr int NB = 16, BLOCKS = 2; };
+template <> struct QrCfg<double> { static constexpr int NB = 16, BLOCKS = 1; };
 
 // 16 x 16 x 4 MFMA per precision.  Lane l supplies A[l%16][k] and B[k][l%16]
 // for the K index k it holds; accumulator register r of lane l holds row
@@ -358,8 +369,11 @@ __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* ta
 // themselves: every product is a sum over an index whose order the lanes
 // agree on, so the K order may follow the accumulator layout.  The panel's
 // NB columns form NB / 16 blocks of the 16 x 16 tiles.
+// Lp >= Lr rows of each column are addressable (zero padding beyond Lr), and
+// groups of 4 rows starting at a multiple of 4 never cross Lp; FP32 moves
+// such groups with one 16-byte access per lane.
 template <typename T>
-__device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc, int nc) {
+__device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C, int ldc, int nc) {
   constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
   constexpr int KB = sizeof(T) == 4 ? 8 : 4;    // 16-row chunks per batch of loads
   using MF = Mfma<T>;
@@ -369,7 +383,7 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc
   const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
   const int lc = lane & 15, lg = lane >> 4;
   if (nc <= 0) return;
-  const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lr) * sizeof(T));
+  const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lp) * sizeof(T));
   const int nk = (Lr + 15) >> 4;
   for (int c0 = 16 * w; c0 < nc; c0 += 16 * kBW) {
     const int col = c0 + lc;
@@ -381,12 +395,20 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc
     for (int kb = 0; kb < nk; kb += KB) {
       T cv[KB][4];
 #pragma unroll
-      for (int u = 0; u < KB; ++u)
+      for (int u = 0; u < KB; ++u) {
+        const int g = 16 * (kb + u) + 4 * lg;           // rows g .. g + 3 of column col
+        if constexpr (sizeof(T) == 4) {
+          const f32x4v v = bload4(rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int row = 16 * (kb + u) + 4 * lg + t;
-          cv[u][t] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+          for (int t = 0; t < 4; ++t) cv[u][t] = v[t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int row = g + t;
+            cv[u][t] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+          }
         }
+      }
 #pragma unroll
       for (int u = 0; u < KB; ++u)
 #pragma unroll
@@ -417,12 +439,18 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc
     for (int kb = 0; kb < nk; kb += KB) {
       V d[KB];
 #pragma unroll
-      for (int u = 0; u < KB; ++u)
+      for (int u = 0; u < KB; ++u) {
+        if constexpr (sizeof(T) == 4) {
+          const int g = 16 * (kb + u) + 4 * lg;         // accumulator rows g .. g + 3
+          d[u] = bload4(rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * (kb + u) + MF::drow(lane, r);
-          d[u][r] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (kb + u) + MF::drow(lane, r);
+            d[u][r] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
+          }
         }
+      }
 #pragma unroll
       for (int u = 0; u < KB; ++u) {
         const int arow = 16 * (kb + u) + lc;
@@ -434,10 +462,15 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, T* C, int ldc
             const T y = Ys[(aok ? arow : 0) * PS + 16 * b + MF::drow(lane, t)];
             d[u] = MF::mma(aok ? -y : (T)0, wp[b][t], d[u]);
           }
+        if constexpr (sizeof(T) == 4) {
+          const int g = 16 * (kb + u) + 4 * lg;
+          bstore4(d[u], rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
+        } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * (kb + u) + MF::drow(lane, r);
-          if (row < Lr && cok) C[(size_t)row + (size_t)col * ldc] = d[u][r];
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (kb + u) + MF::drow(lane, r);
+            if (row < Lr && cok) C[(size_t)row + (size_t)col * ldc] = d[u][r];
+          }
         }
       }
     }
@@ -471,7 +504,7 @@ __device__ __noinline__ void wg_geqrf_impl(LSQ_GLB T* Mg, int ld, int r, int c, 
     }
     for (int e = threadIdx.x; e < NB * NB; e += kBT) Tst[(size_t)pan * NB * NB + e] = L.u.f.Ts[e];
     if (threadIdx.x < nbj) tau[j0 + threadIdx.x] = L.u.f.tau[threadIdx.x];
-    apply_block_qt(L, Lr, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
+    apply_block_qt(L, Lr, ld - j0, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
     __syncthreads();
   }
 }
@@ -497,7 +530,7 @@ __device__ __noinline__ void wg_apply_qt_impl(const LSQ_GLB T* Mg, int ld, int r
     const int nbj = k - j0 < NB ? k - j0 : NB, Lr = r - j0;
     for (int e = threadIdx.x; e < NB * NB; e += kBT) L.u.f.Ts[e] = Tst[(size_t)pan * NB * NB + e];
     stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, true);
-    apply_block_qt(L, Lr, X + j0, ldx, ncols);
+    apply_block_qt(L, Lr, ldx - j0, X + j0, ldx, ncols);
     __syncthreads();
   }
 }
@@ -666,6 +699,10 @@ struct GlsWs {
   double *z, *f1, *f2, *f3;
 };
 
+// Leading dimension of the workspace matrices: rows padded to a multiple of 4
+// (zero-filled), so that every aligned group of 4 rows lies in its column.
+__host__ __device__ constexpr int ldpad(int r) { return (r + 3) & ~3; }
+
 // Byte offsets of an instance's workspace regions for element size esz and
 // panel width nb, computed by one function on the host (sizing) and on the
 // device (use).  LSE: Fb, taub, Tb, X, Fa, taua, Ta, r, v, f1, f2, f3;
@@ -680,14 +717,15 @@ __host__ __device__ inline size_t ws_layout(int type, int m, int n, int p, int e
   };
   auto tblk = [&](int refl) { return (size_t)((refl + nb - 1) / nb) * nb * nb * esz; };
   const size_t e = (size_t)esz, M = m, N = n, Pp = p;
+  const size_t LM = ldpad(m), LN = ldpad(n), LP = ldpad(p);
   if (type == 0) {
     const int ka = m < n ? m : n;
-    take(e * N * Pp); take(e * Pp); take(tblk(p)); take(e * N * M); take(e * M * N);
+    take(e * LN * Pp); take(e * Pp); take(tblk(p)); take(e * LN * M); take(e * LM * N);
     take(e * ka); take(tblk(ka));
     take(8 * M); take(8 * Pp); take(8 * M); take(8 * Pp); take(8 * N);
   } else {
     const int kv = p < n ? p : n;
-    take(e * N * M); take(e * M); take(tblk(m)); take(e * N * Pp); take(e * Pp * N);
+    take(e * LN * M); take(e * M); take(tblk(m)); take(e * LN * Pp); take(e * LP * N);
     take(e * kv); take(tblk(kv));
     take(8 * N); take(8 * Pp); take(8 * N); take(8 * M);
   }
@@ -840,19 +878,21 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
   mat[3] = wg_fro(dvec, p, p, 1, L.dred);
   // factorization in T: Bt = J_n B^T J_p = Qt [Rt; 0]; X = Qt^T (J_n A^T);
   // Abar = A J Qt J = (J_n X)^T = Za [T; 0]
-  for (int i = 0; i < n; ++i) {
-    const LSQ_GLB double* bc = B + (size_t)(n - 1 - i) * P.ldb;   // column n-1-i of B
-    for (int j = t; j < p; j += kBT) W.Fb[i + (size_t)j * n] = (T)bc[p - 1 - j];
-    const LSQ_GLB double* ac = A + (size_t)(n - 1 - i) * P.lda;   // column n-1-i of A
-    for (int j = t; j < m; j += kBT) W.X[i + (size_t)j * n] = (T)ac[j];
+  const int ldn = ldpad(n), ldm = ldpad(m);
+  for (int i = 0; i < ldn; ++i) {                     // rows n .. ldn-1 are zero padding
+    const LSQ_GLB double* bc = B + (size_t)(n - 1 - (i < n ? i : 0)) * P.ldb;   // column n-1-i of B
+    for (int j = t; j < p; j += kBT) W.Fb[i + (size_t)j * ldn] = i < n ? (T)bc[p - 1 - j] : (T)0;
+    const LSQ_GLB double* ac = A + (size_t)(n - 1 - (i < n ? i : 0)) * P.lda;   // column n-1-i of A
+    for (int j = t; j < m; j += kBT) W.X[i + (size_t)j * ldn] = i < n ? (T)ac[j] : (T)0;
   }
   __syncthreads();
-  wg_geqrf(W.Fb, n, n, p, W.taub, W.Tb, L);
-  wg_apply_qt(W.Fb, n, n, p, W.Tb, W.X, n, m, L);
-  for (int j = 0; j < m; ++j)                          // X[i][j] -> Fa[j][n-1-i]
-    for (int i = t; i < n; i += kBT) W.Fa[j + (size_t)(n - 1 - i) * m] = W.X[i + (size_t)j * n];
+  wg_geqrf(W.Fb, ldn, n, p, W.taub, W.Tb, L);
+  wg_apply_qt(W.Fb, ldn, n, p, W.Tb, W.X, ldn, m, L);
+  for (int j = 0; j < ldm; ++j)                        // X[i][j] -> Fa[j][n-1-i]
+    for (int i = t; i < n; i += kBT)
+      W.Fa[j + (size_t)(n - 1 - i) * ldm] = j < m ? W.X[i + (size_t)j * ldn] : (T)0;
   __syncthreads();
-  wg_geqrf(W.Fa, m, m, n, W.taua, W.Ta, L);
+  wg_geqrf(W.Fa, ldm, m, n, W.taua, W.Ta, L);
   for (int i = t; i < n; i += kBT) x[i] = 0.0;
   for (int i = t; i < m; i += kBT) W.r[i] = 0.0;
   for (int i = t; i < p; i += kBT) W.v[i] = 0.0;
@@ -878,23 +918,23 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < p; i += kBT) Y2[i] = (T)f2[p - 1 - i];
     __syncthreads();
     // u~ = Qt^T (J f3); w = Z^T f1; Rt^T (J y2) = J f2
-    if (w == 0) wave_apply_q(W.Fb, n, n, p, W.taub, U, true);
-    else if (w == 1) wave_apply_q(W.Fa, m, m, kqa, W.taua, Wv, true);
-    else if (w == 2) wave_trsv(W.Fb, n, p, Y2, true);
+    if (w == 0) wave_apply_q(W.Fb, ldn, n, p, W.taub, U, true);
+    else if (w == 1) wave_apply_q(W.Fa, ldm, m, kqa, W.taua, Wv, true);
+    else if (w == 2) wave_trsv(W.Fb, ldn, p, Y2, true);
     __syncthreads();
     for (int i = t; i < p; i += kBT) Y2n[i] = Y2[p - 1 - i];
     for (int i = t; i < k; i += kBT) Qv[i] = U[p + k - 1 - i];
     __syncthreads();
     if (w == 0) {
-      wave_trsv(Fa, m, k, Qv, true);                      // T11^T q1 = u1
+      wave_trsv(Fa, ldm, k, Qv, true);                    // T11^T q1 = u1
     } else {
       // w1 - T12 y2 (rows < k) and q2 = w2 - T22 y2 (rows >= k)
-      const auto rs = rsrc(Fa, (size_t)m * n * sizeof(T));
+      const auto rs = rsrc(Fa, (size_t)ldm * n * sizeof(T));
       for (int i = t - 64; i < m; i += kBT - 64) {
         T acc = 0;
         for (int jj = 0; jj < p; ++jj) {
           const int col = k + jj;
-          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * m) * sizeof(T)) : kOob) * Y2n[jj];
+          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * ldm) * sizeof(T)) : kOob) * Y2n[jj];
         }
         if (i < k) Y1[i] = Wv[i] - acc;
         else Qv[i] = Wv[i] - acc;
@@ -903,13 +943,13 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     __syncthreads();
     if (w == 0) {
       for (int i = lane; i < k; i += 64) Y1[i] -= Qv[i];
-      wave_trsv(Fa, m, k, Y1, false);                     // T11 y1 = w1 - q1 - T12 y2
+      wave_trsv(Fa, ldm, k, Y1, false);                   // T11 y1 = w1 - q1 - T12 y2
     } else {
       // s = [T12; T22]^T q - u2, one column per wave
       for (int jj = w - 1; jj < p; jj += kBW - 1) {
         const int col = k + jj, lim = m < col + 1 ? m : col + 1;
         T s = 0;
-        for (int i = lane; i < lim; i += 64) s += Fa[i + (size_t)col * m] * Qv[i];
+        for (int i = lane; i < lim; i += 64) s += Fa[i + (size_t)col * ldm] * Qv[i];
         s = wsum(s);
         if (lane == 0) S[jj] = s - U[p - 1 - jj];
       }
@@ -920,13 +960,13 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < k; i += kBT) Yt[p + i] = Y1[k - 1 - i];
     __syncthreads();
     if (w == 0) {                                         // R^T dv = s
-      wave_trsv(W.Fb, n, p, X2, false);
+      wave_trsv(W.Fb, ldn, p, X2, false);
       for (int i = lane; i < p; i += 64) W.v[i] += (double)X2[p - 1 - i];
     } else if (w == 1) {                                  // dr = Z q
-      wave_apply_q(W.Fa, m, m, kqa, W.taua, Qv, false);
+      wave_apply_q(W.Fa, ldm, m, kqa, W.taua, Qv, false);
       for (int i = lane; i < m; i += 64) W.r[i] += (double)Qv[i];
     } else if (w == 2) {                                  // dx = J Qt (J y)
-      wave_apply_q(W.Fb, n, n, p, W.taub, Yt, false);
+      wave_apply_q(W.Fb, ldn, n, p, W.taub, Yt, false);
       for (int i = lane; i < n; i += 64) x[i] += (double)Yt[n - 1 - i];
     }
     __syncthreads();
@@ -1018,18 +1058,22 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
   mat[3] = 0.0;
   // factorization in T: W = Qw [Rw; 0]; X = Qw^T V;
   // Vt = J_p X^T J_n = Qv Tv
+  const int ldn = ldpad(n), ldp = ldpad(p);            // rows beyond n (p) are zero padding
   for (int j = 0; j < m; ++j)
-    for (int i = t; i < n; i += kBT) W.Fw[i + (size_t)j * n] = (T)A[(size_t)i + (size_t)j * P.lda];
+    for (int i = t; i < ldn; i += kBT)
+      W.Fw[i + (size_t)j * ldn] = i < n ? (T)A[(size_t)i + (size_t)j * P.lda] : (T)0;
   for (int j = 0; j < p; ++j)
-    for (int i = t; i < n; i += kBT) W.X[i + (size_t)j * n] = (T)B[(size_t)i + (size_t)j * P.ldb];
+    for (int i = t; i < ldn; i += kBT)
+      W.X[i + (size_t)j * ldn] = i < n ? (T)B[(size_t)i + (size_t)j * P.ldb] : (T)0;
   __syncthreads();
-  wg_geqrf(W.Fw, n, n, m, W.taw, W.Tw, L);
-  wg_apply_qt(W.Fw, n, n, m, W.Tw, W.X, n, p, L);
-  for (int j = 0; j < p; ++j)                          // X[i][j] -> Fv[p-1-j][n-1-i]
+  wg_geqrf(W.Fw, ldn, n, m, W.taw, W.Tw, L);
+  wg_apply_qt(W.Fw, ldn, n, m, W.Tw, W.X, ldn, p, L);
+  for (int j = 0; j < ldp; ++j)                        // X[i][j] -> Fv[p-1-j][n-1-i]
     for (int i = t; i < n; i += kBT)
-      W.Fv[(size_t)(p - 1 - j) + (size_t)(n - 1 - i) * p] = W.X[i + (size_t)j * n];
+      W.Fv[(size_t)(j < p ? p - 1 - j : j) + (size_t)(n - 1 - i) * ldp] =
+          j < p ? W.X[i + (size_t)j * ldn] : (T)0;
   __syncthreads();
-  wg_geqrf(W.Fv, p, p, n, W.tav, W.Tv, L);
+  wg_geqrf(W.Fv, ldp, p, n, W.tav, W.Tv, L);
   for (int i = t; i < m; i += kBT) x[i] = 0.0;
   for (int i = t; i < p; i += kBT) y[i] = 0.0;
   for (int i = t; i < n; i += kBT) W.z[i] = 0.0;
@@ -1054,23 +1098,23 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < m; i += kBT) H1[i] = first ? (T)0 : (T)W.f3[i];
     __syncthreads();
     // u = Q^T f2; J w = Zt^T (J f1); R^T h1 = f3
-    if (w == 0) wave_apply_q(W.Fw, n, n, m, W.taw, U, true);
-    else if (w == 1) wave_apply_q(W.Fv, p, p, kqv, W.tav, Wt, true);
-    else if (w == 2) wave_trsv(W.Fw, n, m, H1, true);
+    if (w == 0) wave_apply_q(W.Fw, ldn, n, m, W.taw, U, true);
+    else if (w == 1) wave_apply_q(W.Fv, ldp, p, kqv, W.tav, Wt, true);
+    else if (w == 2) wave_trsv(W.Fw, ldn, m, H1, true);
     __syncthreads();
     for (int i = t; i < m; i += kBT) H1t[i] = H1[m - 1 - i];
     for (int i = t; i < k; i += kBT) G[i] = U[m + k - 1 - i];
     __syncthreads();
     if (w == 0) {
-      wave_trsv(Fv, p, k, G, true);                       // A11^T (J g2) = J u2
+      wave_trsv(Fv, ldp, k, G, true);                     // A11^T (J g2) = J u2
     } else {
       // J w2 - A12 J h1 (rows < k) and J g1 = J w1 - A22 J h1 (rows >= k)
-      const auto rs = rsrc(Fv, (size_t)p * n * sizeof(T));
+      const auto rs = rsrc(Fv, (size_t)ldp * n * sizeof(T));
       for (int i = t - 64; i < p; i += kBT - 64) {
         T acc = 0;
         for (int jj = 0; jj < m; ++jj) {
           const int col = k + jj;
-          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * p) * sizeof(T)) : kOob) * H1t[jj];
+          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * ldp) * sizeof(T)) : kOob) * H1t[jj];
         }
         if (i < k) H2t[i] = Wt[i] - acc;
         else G[i] = Wt[i] - acc;
@@ -1079,13 +1123,13 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     __syncthreads();
     if (w == 0) {
       for (int i = lane; i < k; i += 64) H2t[i] -= G[i];
-      wave_trsv(Fv, p, k, H2t, false);                    // A11 (J h2) = J w2 - J g2 - A12 J h1
+      wave_trsv(Fv, ldp, k, H2t, false);                  // A11 (J h2) = J w2 - J g2 - A12 J h1
     } else {
       // s = Tv[:, k:n]^T (J g), one column per wave
       for (int jj = w - 1; jj < m; jj += kBW - 1) {
         const int col = k + jj, lim = p < col + 1 ? p : col + 1;
         T s = 0;
-        for (int i = lane; i < lim; i += 64) s += Fv[i + (size_t)col * p] * G[i];
+        for (int i = lane; i < lim; i += 64) s += Fv[i + (size_t)col * ldp] * G[i];
         s = wsum(s);
         if (lane == 0) S[jj] = s;
       }
@@ -1096,13 +1140,13 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < k; i += kBT) Hv[m + i] = H2t[k - 1 - i];
     __syncthreads();
     if (w == 0) {                                         // R dx = u1 - J s
-      wave_trsv(W.Fw, n, m, X, false);
+      wave_trsv(W.Fw, ldn, m, X, false);
       for (int i = lane; i < m; i += 64) x[i] += (double)X[i];
     } else if (w == 1) {                                  // dz = -Q h
-      wave_apply_q(W.Fw, n, n, m, W.taw, Hv, false);
+      wave_apply_q(W.Fw, ldn, n, m, W.taw, Hv, false);
       for (int i = lane; i < n; i += 64) W.z[i] -= (double)Hv[i];
     } else if (w == 2) {                                  // dy = J Zt (J g)
-      wave_apply_q(W.Fv, p, p, kqv, W.tav, G, false);
+      wave_apply_q(W.Fv, ldp, p, kqv, W.tav, G, false);
       for (int i = lane; i < p; i += 64) y[i] += (double)G[p - 1 - i];
     }
     __syncthreads();
@@ -1169,7 +1213,7 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBT, 1) void k_batch(const BatchProb* __restrict__ probs,
+__global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb* __restrict__ probs,
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
                                                   size_t ws_stride, double tol, int maxit,
@@ -1198,6 +1242,8 @@ size_t batch_ws_bytes(const BatchProb& P) {
   const size_t b = ws_layout(P.type, P.m, P.n, P.p, 8, QrCfg<double>::NB, off);
   return a > b ? a : b;
 }
+
+int batch_blocks_per_cu(int tw) { return tw == 8 ? QrCfg<double>::BLOCKS : QrCfg<float>::BLOCKS; }
 
 bool batch_eligible(const BatchProb& P) {
   const int lim = kBatchMaxDim;

@@ -217,7 +217,6 @@ void mlp_select(Ctx& ctx, const float* weights, const float* feats, float* logit
 // (m, n, p, A = A, B = B, b, d, x); type 1 = GLS with (n, m, p, A = W, B = V,
 // d, x, y)).  Pointers are device pointers to FP64 column-major data.
 constexpr int kBatchMaxDim = 1024;       // largest m, n, p of an instance
-constexpr int kBatchBlocksPerCu = 1;
 struct BatchProb {
   int type, m, n, p;
   const double *A, *B, *b, *d;
@@ -233,6 +232,8 @@ struct BatchOut {
 // Device workspace bytes of one work-group for instance P (either precision).
 size_t batch_ws_bytes(const BatchProb& P);
 bool batch_eligible(const BatchProb& P);
+// Resident work-groups per compute unit of the launch with element size tw.
+int batch_blocks_per_cu(int tw);
 // Householder flops of the factorization of instance P (the algorithmic work
 // the kernel timer reports for a batch launch).
 double batch_factor_flops(const BatchProb& P);

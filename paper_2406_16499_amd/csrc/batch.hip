@@ -150,6 +150,7 @@ struct BLds {
     T vec[kVecs][kBatchMaxDim];      // vectors of the correction solves
   } u;
   T red[kBW];
+  T vred[kBW * NB + 2 * NB];         // reductions of the work-group vector kernels
   double dred[kBW * 6];
   int next;
 };
@@ -542,149 +543,285 @@ __device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, co
                       ncols, (LSQ_LDS BLds<T>*)&L);
 }
 
-// ------------------------------------------------ one-wave vector kernels --
-// y (LDS, length r) <- Q^T y (trans) or Q y, Q = H_0 ... H_{k-1} with the
-// reflectors of M (ld).  The lane's entries of y stay in registers; the next
-// reflector is loaded while the current one is applied.
-// Loads are issued unconditionally from clamped (always valid) addresses and
-// masked afterwards: a conditional load whose register is written on the
-// other path makes the compiler wait for every load in flight.
-template <typename T>
-__device__ __forceinline__ T load_reflector(const T* M, int ld, int r, int j, const T* tau, int nq,
-                                            T (&dst)[kBS]) {
-  const int lane = threadIdx.x & 63;
-  const auto rs = rsrc(M + (size_t)j * ld, (size_t)r * sizeof(T));
+// ------------------------------------------- work-group vector kernels --
+// The correction solves on all waves.  A vector of length <= kBatchMaxDim
+// lives in LDS; for the matrix work thread t owns rows 4t .. 4t + 3, which a
+// padded column delivers in one (FP32) or two (FP64) 16-byte loads.
+
+// Pairwise exchanges for the reduce-scatter: the gfx950 permlane swaps pair
+// lane l with l ^ 32 (l ^ 16); for X, Y in every lane, afterwards X + Y is the
+// lane's own value plus its partner's, taken from X in the lower and from Y
+// in the upper lane of each pair.
+__device__ __forceinline__ void lane_swap32(unsigned& x, unsigned& y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+__device__ __forceinline__ void lane_swap16(unsigned& x, unsigned& y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+  x = r[0];
+  y = r[1];
+}
+template <int MASK>
+__device__ __forceinline__ float pair_sum(float lo, float hi) {
+  unsigned x = __float_as_uint(lo), y = __float_as_uint(hi);
+  if constexpr (MASK == 32) lane_swap32(x, y); else lane_swap16(x, y);
+  return __uint_as_float(x) + __uint_as_float(y);
+}
+template <int MASK>
+__device__ __forceinline__ double pair_sum(double lo, double hi) {
+  const unsigned long long a = (unsigned long long)__double_as_longlong(lo);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(hi);
+  unsigned xl = (unsigned)a, xh = (unsigned)(a >> 32), yl = (unsigned)b, yh = (unsigned)(b >> 32);
+  if constexpr (MASK == 32) { lane_swap32(xl, yl); lane_swap32(xh, yh); }
+  else { lane_swap16(xl, yl); lane_swap16(xh, yh); }
+  const double x = __longlong_as_double((long long)(((unsigned long long)xh << 32) | xl));
+  const double y = __longlong_as_double((long long)(((unsigned long long)yh << 32) | yl));
+  return x + y;
+}
+// DPP exchanges pairing each lane with one whose bit MASK differs and whose
+// higher bits agree (within a row of 16): xor 8, mirror within 8, mirror
+// within 4, xor 1.
+template <int MASK> struct PairDpp;
+template <> struct PairDpp<8> { static constexpr int ctrl = 0x128; };   // row_ror:8
+template <> struct PairDpp<4> { static constexpr int ctrl = 0x141; };   // row_half_mirror
+template <> struct PairDpp<2> { static constexpr int ctrl = 0x1B; };    // quad_perm [3,2,1,0]
+template <> struct PairDpp<1> { static constexpr int ctrl = 0xB1; };    // quad_perm [1,0,3,2]
+
+// Reduce-scatter of NV (a power of two <= 64) per-lane values over the wave:
+// every lane returns the wave total of value index lane >> (6 - log2 NV).
+// Each halving step keeps the half of the values selected by one lane bit and
+// adds the partner lane's copy of it.
+template <typename T, int NV, int HALF, int MASK>
+__device__ __forceinline__ void rs_step(T (&v)[NV], int lane) {
+  if constexpr (HALF >= 1) {
+    if constexpr (MASK >= 16) {
 #pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const int i = lane + 64 * q;
-    const T x = bload<T>(rs, (q < nq && i > j && i < r) ? (uint32_t)(i * sizeof(T)) : kOob);
-    dst[q] = x + (i == j ? (T)1 : (T)0);
+      for (int k = 0; k < HALF; ++k) v[k] = pair_sum<MASK>(v[k], v[k + HALF]);
+    } else {
+      const bool up = (lane & MASK) != 0;
+#pragma unroll
+      for (int k = 0; k < HALF; ++k) {
+        const T keep = up ? v[k + HALF] : v[k];
+        const T send = up ? v[k] : v[k + HALF];
+        v[k] = keep + dpp<PairDpp<MASK>::ctrl>(send);
+      }
+    }
+    rs_step<T, NV, HALF / 2, MASK / 2>(v, lane);
   }
-  return tau[j];
+}
+template <typename T, int MASK>
+__device__ __forceinline__ T rs_tail(T r) {
+  if constexpr (MASK >= 1) {
+    r += dpp<PairDpp<MASK>::ctrl>(r);
+    return rs_tail<T, MASK / 2>(r);
+  }
+  return r;
+}
+template <typename T, int NV>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[NV]) {
+  static_assert(NV >= 4 && NV <= 64, "the tail exchanges stay inside a row of 16");
+  const int lane = threadIdx.x & 63;
+  rs_step<T, NV, NV / 2, 32>(v, lane);
+  return rs_tail<T, 32 / NV>(v[0]);
 }
 
+typedef double f64x2v __attribute__((ext_vector_type(2)));
+
+// Rows g .. g + 3 of a padded column at byte offset off (zeros when !ok).
 template <typename T>
-__device__ __forceinline__ void apply_reflector(const T (&v)[kBS], T tau, T (&yr)[kBS]) {
-  T d = 0;
+__device__ __forceinline__ void load_rows4(__amdgpu_buffer_rsrc_t rs, bool ok, uint32_t off, T (&v)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x4v x = bload4(rs, ok ? off : kOob);
 #pragma unroll
-  for (int q = 0; q < kBS; ++q) d += v[q] * yr[q];
-  d = wsum(d) * tau;
-#pragma unroll
-  for (int q = 0; q < kBS; ++q) yr[q] -= d * v[q];
+    for (int e = 0; e < 4; ++e) v[e] = x[e];
+  } else {
+    const f64x2v a = __builtin_bit_cast(f64x2v, __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? off : kOob, 0, 0));
+    const f64x2v b = __builtin_bit_cast(f64x2v, __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? off + 16 : kOob, 0, 0));
+    v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
+  }
 }
 
-// Two register sets alternate, so the loads of the next reflector are in
-// flight while the current one is applied.
+// y (LDS, length r) <- Q^T y (trans) or Q y, Q = H_0 ... H_{k-1} from the
+// reflectors of M (ld) and the panels' T (NB x NB, row-major, at Tst; the
+// panel's product is I - Y T Y^T), one panel at a time: z = Y^T y by a wave
+// reduce-scatter and LDS, w = T^T z (T z) by NB threads, y -= Y w.  In FP32
+// the next panel's columns load while the current one is reduced.
 template <typename T>
-__device__ __noinline__ void wave_apply_q_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
-                                               const LSQ_GLB T* taug, LSQ_LDS T* yl, bool trans) {
+__device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
+                                                 const LSQ_GLB T* Tstg, LSQ_LDS T* yl,
+                                                 LSQ_LDS T* redl, bool trans) {
+  constexpr int NB = QrCfg<T>::NB;
+  static_assert(NB == 16 && kBT * 4 == kBatchMaxDim, "thread t owns rows 4t .. 4t + 3");
+  constexpr bool PF = sizeof(T) == 4;
   const T* M = (const T*)uni(Mg);
-  const T* tau = (const T*)uni(taug);
-  T* y = (T*)uni(yl);
+  const LSQ_GLB T* Tst = uni(Tstg);
+  LSQ_LDS T* y = uni(yl);
+  LSQ_LDS T* red = uni(redl);
   ld = uni(ld); r = uni(r); k = uni(k);
   trans = uni((int)trans) != 0;
-  const int lane = threadIdx.x & 63, nq = (r + 63) >> 6;
-  T yr[kBS], va[kBS], vb[kBS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g0 = 4 * t;
+  const int np = (k + NB - 1) / NB;
+  T yv[4];
 #pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const int i = lane + 64 * q;
-    const T x = y[(q < nq && i < r) ? i : 0];
-    yr[q] = (q < nq && i < r) ? x : (T)0;
-  }
-  auto jof = [&](int s) { return trans ? s : k - 1 - s; };
-  T ta = k > 0 ? load_reflector(M, ld, r, jof(0), tau, nq, va) : (T)0, tb = 0;
-  for (int s = 0; s < k; s += 2) {
-    if (s + 1 < k) tb = load_reflector(M, ld, r, jof(s + 1), tau, nq, vb);
-    apply_reflector(va, ta, yr);
-    if (s + 1 >= k) break;
-    if (s + 2 < k) ta = load_reflector(M, ld, r, jof(s + 2), tau, nq, va);
-    apply_reflector(vb, tb, yr);
+  for (int e = 0; e < 4; ++e) yv[e] = g0 + e < r ? y[g0 + e] : (T)0;
+  auto panel = [&](int b) { return trans ? b : np - 1 - b; };
+  auto load = [&](int b, T (&Yv)[NB][4], T (&Tv)[NB]) {
+    const int j0 = panel(b) * NB, nbj = k - j0 < NB ? k - j0 : NB;
+    const auto rs = rsrc(M + (size_t)j0 * ld, (size_t)nbj * ld * sizeof(T));
+    const bool act = g0 + 3 >= j0 && g0 < r;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) load_rows4(rs, act, (uint32_t)((g0 + (size_t)c * ld) * sizeof(T)), Yv[c]);
+    // thread t < NB: column t of T (w = T^T z) or row t (w = T z)
+    const LSQ_GLB T* Tp = Tst + (size_t)panel(b) * NB * NB;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Tv[i] = (t < NB && i < nbj) ? (trans ? Tp[i * NB + t] : Tp[t * NB + i]) : (T)0;
+  };
+  auto step = [&](int b, T (&Yv)[NB][4], T (&Tv)[NB], T (&Yn)[NB][4], T (&Tn)[NB]) {
+    const int j0 = panel(b) * NB, nbj = k - j0 < NB ? k - j0 : NB;
+    if (g0 + 3 >= j0 && g0 < j0 + NB) {            // the diagonal block: 1 on it, 0 above
+#pragma unroll
+      for (int c = 0; c < NB; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = g0 + e;
+          Yv[c][e] = row < j0 + c ? (T)0 : (row == j0 + c ? (c < nbj ? (T)1 : (T)0) : Yv[c][e]);
+        }
+    }
+    T pz[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) pz[c] = (Yv[c][0] * yv[0] + Yv[c][1] * yv[1]) + (Yv[c][2] * yv[2] + Yv[c][3] * yv[3]);
+    if constexpr (PF) {
+      if (b + 1 < np) load(b + 1, Yn, Tn);
+    }
+    const T zc = wave_reduce_scatter<T, NB>(pz);    // lanes 4c .. 4c + 3: the wave's z_c
+    if ((lane & 3) == 0) red[w * NB + (lane >> 2)] = zc;
+    __syncthreads();
+    if (t < NB) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const T zi = (red[i] + red[NB + i]) + (red[2 * NB + i] + red[3 * NB + i]);
+        acc += Tv[i] * zi;
+      }
+      red[kBW * NB + t] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const T wc = red[kBW * NB + c];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) yv[e] -= Yv[c][e] * wc;
+    }
+  };
+  if constexpr (PF) {
+    T Ya[NB][4], Yb[NB][4], Ta[NB], Tb[NB];
+    if (np > 0) load(0, Ya, Ta);
+    for (int b = 0; b < np; b += 2) {
+      step(b, Ya, Ta, Yb, Tb);
+      if (b + 1 < np) step(b + 1, Yb, Tb, Ya, Ta);
+    }
+  } else {
+    T Ya[NB][4], Ta[NB];
+    for (int b = 0; b < np; ++b) {
+      load(b, Ya, Ta);
+      step(b, Ya, Ta, Ya, Ta);
+    }
   }
 #pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const int i = lane + 64 * q;
-    if (q < nq && i < r) y[i] = yr[q];
-  }
+  for (int e = 0; e < 4; ++e)
+    if (g0 + e < r) y[g0 + e] = yv[e];
+  __syncthreads();
 }
 
 template <typename T>
-__device__ __forceinline__ void wave_apply_q(const T* M, int ld, int r, int k, const T* tau, T* y,
-                                             bool trans) {
-  wave_apply_q_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)tau, (LSQ_LDS T*)y, trans);
+__device__ __forceinline__ void wg_apply_q_vec(const T* M, int ld, int r, int k, const T* Tst, T* y,
+                                               T* red, bool trans) {
+  wg_apply_q_vec_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_LDS T*)y,
+                         (LSQ_LDS T*)red, trans);
 }
 
-// Column j of U above the diagonal (TRANS = false) or row j right of it
-// (TRANS = true) into the lane's slots; out-of-range entries read as 0.
+// y (LDS, length nn) <- U^{-1} y (TRANS = false) or U^{-T} y, U the upper
+// triangle of M[0:nn, 0:nn] (ld), in blocks of 16: lanes 0 .. 15 of wave 0
+// solve the diagonal block (lane i holds row i of it, or column i for U^T;
+// a partial last block is padded with the identity), then every thread
+// subtracts the block's contribution from its unsolved rows.  The update's
+// columns load before the diagonal solve.  A zero pivot gives a non-finite
+// result, which the stop test reports.
 template <typename T, bool TRANS>
-__device__ __forceinline__ T load_tri(const T* M, int ld, int nn, int j, T (&dst)[kBS]) {
-  const int lane = threadIdx.x & 63;
-  const auto rs = TRANS ? rsrc(M + j, ((size_t)(nn - 1) * ld + 1) * sizeof(T))
-                        : rsrc(M + (size_t)j * ld, (size_t)j * sizeof(T));
-#pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const int i = lane + 64 * q;
-    const uint32_t off = TRANS ? ((i > j && i < nn) ? (uint32_t)((size_t)i * ld * sizeof(T)) : kOob)
-                               : (uint32_t)(i * sizeof(T));
-    dst[q] = bload<T>(rs, off);
-  }
-  return M[j + (size_t)j * ld];
-}
-
-// One step of the substitution on the register-resident vector: x_j from its
-// owner lane, then y -= x_j u (u is zero outside the active part), and x_j
-// stored in its slot.
-template <typename T>
-__device__ __forceinline__ void tri_step(const T (&u)[kBS], T d, int j, T (&yr)[kBS]) {
-  const int lane = threadIdx.x & 63, slot = j >> 6, owner = j & 63;
-  T own = yr[0];
-#pragma unroll
-  for (int q = 1; q < kBS; ++q) own = (q == slot) ? yr[q] : own;
-  const T xj = lane_val(own, owner) / d;
-#pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const T v = yr[q] - u[q] * xj;
-    yr[q] = (q == slot && lane == owner) ? xj : v;
-  }
-}
-
-template <typename T, bool TRANS>
-__device__ __noinline__ void wave_trsv_impl(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
+__device__ __noinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
+  constexpr int NB = 16;
   const T* M = (const T*)uni(Mg);
-  T* y = (T*)uni(yl);
-  ld = uni(ld);
-  nn = uni(nn);
-  if (nn <= 0) return;
-  const int lane = threadIdx.x & 63, nq = (nn + 63) >> 6;
-  T yr[kBS], ua[kBS], ub[kBS];
+  LSQ_LDS T* y = uni(yl);
+  ld = uni(ld); nn = uni(nn);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g0 = 4 * t;
+  const int nbk = (nn + NB - 1) / NB;
+  for (int b = 0; b < nbk; ++b) {
+    const int j0 = (TRANS ? b : nbk - 1 - b) * NB, nbj = nn - j0 < NB ? nn - j0 : NB;
+    // the update's part of U: columns j0 .. j0 + nbj of rows g0 .. g0 + 3
+    // (U), or rows j0 .. j0 + nbj of columns g0 .. g0 + 3 (U^T)
+    T Uv[NB][4];
+    const bool act = TRANS ? (g0 >= j0 + NB && g0 < nn) : g0 < j0;
+    if constexpr (!TRANS) {
+      const auto rs = rsrc(M + (size_t)j0 * ld, (size_t)nbj * ld * sizeof(T));
 #pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const int i = lane + 64 * q;
-    const T x = y[(q < nq && i < nn) ? i : 0];
-    yr[q] = (q < nq && i < nn) ? x : (T)0;
-  }
-  auto jof = [&](int s) { return TRANS ? s : nn - 1 - s; };
-  T da = load_tri<T, TRANS>(M, ld, nn, jof(0), ua), db = 1;
-  for (int s = 0; s < nn; s += 2) {
-    if (s + 1 < nn) db = load_tri<T, TRANS>(M, ld, nn, jof(s + 1), ub);
-    tri_step(ua, da, jof(s), yr);
-    if (s + 1 >= nn) break;
-    if (s + 2 < nn) da = load_tri<T, TRANS>(M, ld, nn, jof(s + 2), ua);
-    tri_step(ub, db, jof(s + 1), yr);
-  }
+      for (int c = 0; c < NB; ++c) load_rows4(rs, act, (uint32_t)((g0 + (size_t)c * ld) * sizeof(T)), Uv[c]);
+    } else {
+      const auto rs = rsrc(M + j0, ((size_t)(nn - 1) * ld + nbj) * sizeof(T));
 #pragma unroll
-  for (int q = 0; q < kBS; ++q) {
-    const int i = lane + 64 * q;
-    if (q < nq && i < nn) y[i] = yr[q];
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = act && g0 + e < nn;
+#pragma unroll
+        for (int c4 = 0; c4 < NB; c4 += 4) {
+          T v[4];
+          load_rows4(rs, ok, (uint32_t)((c4 + (size_t)(g0 + e) * ld) * sizeof(T)), v);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Uv[c4 + q][e] = v[q];
+        }
+      }
+    }
+    if (w == 0) {
+      // lane i < nbj: row i (U) or column i (U^T) of the block; identity beyond
+      const auto rd = rsrc(M + j0 + (size_t)j0 * ld, ((size_t)(nbj - 1) * ld + nbj) * sizeof(T));
+      T ud[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const size_t e = TRANS ? (size_t)c + (size_t)lane * ld : (size_t)lane + (size_t)c * ld;
+        const T v = bload<T>(rd, (lane < nbj && c < nbj) ? (uint32_t)(e * sizeof(T)) : kOob);
+        ud[c] = (c == lane && c >= nbj) ? (T)1 : v;
+      }
+      T yi = lane < nbj ? y[j0 + (lane < nbj ? lane : 0)] : (T)0;
+#pragma unroll
+      for (int s = 0; s < NB; ++s) {
+        const int j = TRANS ? s : NB - 1 - s;
+        const T xj = lane_val(yi, j) / lane_val(ud[j], j);
+        const T upd = yi - ud[j] * xj;
+        yi = lane == j ? xj : ((TRANS ? lane > j : lane < j) ? upd : yi);
+      }
+      if (lane < nbj) y[j0 + lane] = yi;
+    }
+    __syncthreads();
+    if (act) {
+      T xb[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) xb[c] = c < nbj ? y[j0 + c] : (T)0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (g0 + e >= nn) continue;
+        T acc = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc += Uv[c][e] * xb[c];
+        y[g0 + e] -= acc;
+      }
+    }
+    __syncthreads();
   }
 }
 
-// y (LDS, length nn) <- U^{-1} y or U^{-T} y in place, U = M[0:nn, 0:nn]
-// (upper, ld), one wave.  A zero pivot gives a non-finite result, which the
-// stop test reports.
 template <typename T>
-__device__ __forceinline__ void wave_trsv(const T* M, int ld, int nn, T* y, bool trans) {
-  if (trans) wave_trsv_impl<T, true>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
-  else wave_trsv_impl<T, false>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
+__device__ __forceinline__ void wg_trsv_vec(const T* M, int ld, int nn, T* y, bool trans) {
+  if (trans) wg_trsv_vec_impl<T, true>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
+  else wg_trsv_vec_impl<T, false>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
 }
 
 // ----------------------------------------------------------- workspaces --
@@ -918,57 +1055,47 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < p; i += kBT) Y2[i] = (T)f2[p - 1 - i];
     __syncthreads();
     // u~ = Qt^T (J f3); w = Z^T f1; Rt^T (J y2) = J f2
-    if (w == 0) wave_apply_q(W.Fb, ldn, n, p, W.taub, U, true);
-    else if (w == 1) wave_apply_q(W.Fa, ldm, m, kqa, W.taua, Wv, true);
-    else if (w == 2) wave_trsv(W.Fb, ldn, p, Y2, true);
-    __syncthreads();
+    wg_apply_q_vec(W.Fb, ldn, n, p, W.Tb, U, L.vred, true);
+    wg_apply_q_vec(W.Fa, ldm, m, kqa, W.Ta, Wv, L.vred, true);
+    wg_trsv_vec(W.Fb, ldn, p, Y2, true);
     for (int i = t; i < p; i += kBT) Y2n[i] = Y2[p - 1 - i];
     for (int i = t; i < k; i += kBT) Qv[i] = U[p + k - 1 - i];
     __syncthreads();
-    if (w == 0) {
-      wave_trsv(Fa, ldm, k, Qv, true);                    // T11^T q1 = u1
-    } else {
+    wg_trsv_vec(Fa, ldm, k, Qv, true);                    // T11^T q1 = u1
+    {
       // w1 - T12 y2 (rows < k) and q2 = w2 - T22 y2 (rows >= k)
       const auto rs = rsrc(Fa, (size_t)ldm * n * sizeof(T));
-      for (int i = t - 64; i < m; i += kBT - 64) {
+      for (int i = t; i < m; i += kBT) {
         T acc = 0;
         for (int jj = 0; jj < p; ++jj) {
           const int col = k + jj;
           acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * ldm) * sizeof(T)) : kOob) * Y2n[jj];
         }
-        if (i < k) Y1[i] = Wv[i] - acc;
+        if (i < k) Y1[i] = Wv[i] - acc - Qv[i];
         else Qv[i] = Wv[i] - acc;
       }
     }
     __syncthreads();
-    if (w == 0) {
-      for (int i = lane; i < k; i += 64) Y1[i] -= Qv[i];
-      wave_trsv(Fa, ldm, k, Y1, false);                   // T11 y1 = w1 - q1 - T12 y2
-    } else {
-      // s = [T12; T22]^T q - u2, one column per wave
-      for (int jj = w - 1; jj < p; jj += kBW - 1) {
-        const int col = k + jj, lim = m < col + 1 ? m : col + 1;
-        T s = 0;
-        for (int i = lane; i < lim; i += 64) s += Fa[i + (size_t)col * ldm] * Qv[i];
-        s = wsum(s);
-        if (lane == 0) S[jj] = s - U[p - 1 - jj];
-      }
+    wg_trsv_vec(Fa, ldm, k, Y1, false);                   // T11 y1 = w1 - q1 - T12 y2
+    // s = [T12; T22]^T q - u2, one column per wave
+    for (int jj = w; jj < p; jj += kBW) {
+      const int col = k + jj, lim = m < col + 1 ? m : col + 1;
+      T s = 0;
+      for (int i = lane; i < lim; i += 64) s += Fa[i + (size_t)col * ldm] * Qv[i];
+      s = wsum(s);
+      if (lane == 0) S[jj] = s - U[p - 1 - jj];
     }
     __syncthreads();
     for (int i = t; i < p; i += kBT) X2[i] = S[p - 1 - i];
     for (int i = t; i < p; i += kBT) Yt[i] = Y2[i];
     for (int i = t; i < k; i += kBT) Yt[p + i] = Y1[k - 1 - i];
     __syncthreads();
-    if (w == 0) {                                         // R^T dv = s
-      wave_trsv(W.Fb, ldn, p, X2, false);
-      for (int i = lane; i < p; i += 64) W.v[i] += (double)X2[p - 1 - i];
-    } else if (w == 1) {                                  // dr = Z q
-      wave_apply_q(W.Fa, ldm, m, kqa, W.taua, Qv, false);
-      for (int i = lane; i < m; i += 64) W.r[i] += (double)Qv[i];
-    } else if (w == 2) {                                  // dx = J Qt (J y)
-      wave_apply_q(W.Fb, ldn, n, p, W.taub, Yt, false);
-      for (int i = lane; i < n; i += 64) x[i] += (double)Yt[n - 1 - i];
-    }
+    wg_trsv_vec(W.Fb, ldn, p, X2, false);                 // R^T dv = s
+    for (int i = t; i < p; i += kBT) W.v[i] += (double)X2[p - 1 - i];
+    wg_apply_q_vec(W.Fa, ldm, m, kqa, W.Ta, Qv, L.vred, false);   // dr = Z q
+    for (int i = t; i < m; i += kBT) W.r[i] += (double)Qv[i];
+    wg_apply_q_vec(W.Fb, ldn, n, p, W.Tb, Yt, L.vred, false);     // dx = J Qt (J y)
+    for (int i = t; i < n; i += kBT) x[i] += (double)Yt[n - 1 - i];
     __syncthreads();
   };
   // f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v (FP64), one pass over
@@ -1098,57 +1225,47 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < m; i += kBT) H1[i] = first ? (T)0 : (T)W.f3[i];
     __syncthreads();
     // u = Q^T f2; J w = Zt^T (J f1); R^T h1 = f3
-    if (w == 0) wave_apply_q(W.Fw, ldn, n, m, W.taw, U, true);
-    else if (w == 1) wave_apply_q(W.Fv, ldp, p, kqv, W.tav, Wt, true);
-    else if (w == 2) wave_trsv(W.Fw, ldn, m, H1, true);
-    __syncthreads();
+    wg_apply_q_vec(W.Fw, ldn, n, m, W.Tw, U, L.vred, true);
+    wg_apply_q_vec(W.Fv, ldp, p, kqv, W.Tv, Wt, L.vred, true);
+    wg_trsv_vec(W.Fw, ldn, m, H1, true);
     for (int i = t; i < m; i += kBT) H1t[i] = H1[m - 1 - i];
     for (int i = t; i < k; i += kBT) G[i] = U[m + k - 1 - i];
     __syncthreads();
-    if (w == 0) {
-      wave_trsv(Fv, ldp, k, G, true);                     // A11^T (J g2) = J u2
-    } else {
-      // J w2 - A12 J h1 (rows < k) and J g1 = J w1 - A22 J h1 (rows >= k)
+    wg_trsv_vec(Fv, ldp, k, G, true);                     // A11^T (J g2) = J u2
+    {
+      // J w2 - A12 J h1 - J g2 (rows < k) and J g1 = J w1 - A22 J h1 (rows >= k)
       const auto rs = rsrc(Fv, (size_t)ldp * n * sizeof(T));
-      for (int i = t - 64; i < p; i += kBT - 64) {
+      for (int i = t; i < p; i += kBT) {
         T acc = 0;
         for (int jj = 0; jj < m; ++jj) {
           const int col = k + jj;
           acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * ldp) * sizeof(T)) : kOob) * H1t[jj];
         }
-        if (i < k) H2t[i] = Wt[i] - acc;
+        if (i < k) H2t[i] = Wt[i] - acc - G[i];
         else G[i] = Wt[i] - acc;
       }
     }
     __syncthreads();
-    if (w == 0) {
-      for (int i = lane; i < k; i += 64) H2t[i] -= G[i];
-      wave_trsv(Fv, ldp, k, H2t, false);                  // A11 (J h2) = J w2 - J g2 - A12 J h1
-    } else {
-      // s = Tv[:, k:n]^T (J g), one column per wave
-      for (int jj = w - 1; jj < m; jj += kBW - 1) {
-        const int col = k + jj, lim = p < col + 1 ? p : col + 1;
-        T s = 0;
-        for (int i = lane; i < lim; i += 64) s += Fv[i + (size_t)col * ldp] * G[i];
-        s = wsum(s);
-        if (lane == 0) S[jj] = s;
-      }
+    wg_trsv_vec(Fv, ldp, k, H2t, false);                  // A11 (J h2) = J w2 - J g2 - A12 J h1
+    // s = Tv[:, k:n]^T (J g), one column per wave
+    for (int jj = w; jj < m; jj += kBW) {
+      const int col = k + jj, lim = p < col + 1 ? p : col + 1;
+      T s = 0;
+      for (int i = lane; i < lim; i += 64) s += Fv[i + (size_t)col * ldp] * G[i];
+      s = wsum(s);
+      if (lane == 0) S[jj] = s;
     }
     __syncthreads();
     for (int i = t; i < m; i += kBT) X[i] = U[i] - S[m - 1 - i];
     for (int i = t; i < m; i += kBT) Hv[i] = H1[i];
     for (int i = t; i < k; i += kBT) Hv[m + i] = H2t[k - 1 - i];
     __syncthreads();
-    if (w == 0) {                                         // R dx = u1 - J s
-      wave_trsv(W.Fw, ldn, m, X, false);
-      for (int i = lane; i < m; i += 64) x[i] += (double)X[i];
-    } else if (w == 1) {                                  // dz = -Q h
-      wave_apply_q(W.Fw, ldn, n, m, W.taw, Hv, false);
-      for (int i = lane; i < n; i += 64) W.z[i] -= (double)Hv[i];
-    } else if (w == 2) {                                  // dy = J Zt (J g)
-      wave_apply_q(W.Fv, ldp, p, kqv, W.tav, G, false);
-      for (int i = lane; i < p; i += 64) y[i] += (double)G[p - 1 - i];
-    }
+    wg_trsv_vec(W.Fw, ldn, m, X, false);                  // R dx = u1 - J s
+    for (int i = t; i < m; i += kBT) x[i] += (double)X[i];
+    wg_apply_q_vec(W.Fw, ldn, n, m, W.Tw, Hv, L.vred, false);     // dz = -Q h
+    for (int i = t; i < n; i += kBT) W.z[i] -= (double)Hv[i];
+    wg_apply_q_vec(W.Fv, ldp, p, kqv, W.Tv, G, L.vred, false);    // dy = J Zt (J g)
+    for (int i = t; i < p; i += kBT) y[i] += (double)G[p - 1 - i];
     __syncthreads();
   };
   // f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z (FP64), one pass over W

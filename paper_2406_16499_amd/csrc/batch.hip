@@ -17,6 +17,8 @@
 // a correction runs one wave per independent operation (applications of Q or
 // Q^T, triangular solves), so consecutive reflectors and triangular steps need
 // no work-group barrier; the waves meet at four barriers per correction.
+#include <type_traits>
+
 #include "engine.hpp"
 
 namespace lsq {
@@ -49,6 +51,14 @@ template <> __device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t
 }
 template <> __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <typename T> __device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ void bstore<float>(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0)), v), r, off, 0, 0);
+}
+template <> __device__ __forceinline__ void bstore<double>(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, off, 0, 0);
 }
 
 typedef float f32x4v __attribute__((ext_vector_type(4)));
@@ -150,7 +160,7 @@ struct BLds {
     T vec[kVecs][kBatchMaxDim];      // vectors of the correction solves
   } u;
   T red[kBW];
-  T vred[kBW * NB + 2 * NB];         // reductions of the work-group vector kernels
+  T vred[2 * (kBW + 1) * NB];        // reductions of the register panel and vector kernels
   double dred[kBW * 6];
   int next;
 };
@@ -186,368 +196,17 @@ __device__ __forceinline__ void wg_sum6(double v[6], double* red) {
   }
 }
 
-// ------------------------------------------------------------ Householder --
-// Blocked Householder QR (LAPACK's convention: H = I - tau v v^T, v(j) = 1;
-// Q = H_0 ... H_{k-1}; per panel H_j0 ... H_{j0+nb-1} = I - Y T Y^T with T
-// upper triangular).  A panel of NB columns is factored in LDS; its T comes
-// from the Gram Y^T Y; the trailing columns are updated with
-// C <- C - Y (T^T (Y^T C)), each wave streaming CG columns at a time through
-// registers (one read and one write of C per panel).
-
-// Panel rows j0 .. j0 + Lr of columns j0 .. j0 + nbj of M into Ys (columns
-// beyond nbj zero).  unit: load the reflector view (1 on the diagonal, 0
-// above) of a factored panel instead of the raw columns.
-template <typename T>
-__device__ __forceinline__ void stage_panel(const T* M, int ld, int j0, int nbj, int Lr, T* Ys,
-                                            bool unit) {
-  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, RS = kBatchMaxDim / kBT;
-  const T* base = M + j0 + (size_t)j0 * ld;
-  const auto rs = rsrc(base, ((size_t)(NB - 1) * ld + Lr) * sizeof(T));
-  T v[RS][NB];
-#pragma unroll
-  for (int s = 0; s < RS; ++s) {
-    const int i = threadIdx.x + kBT * s;
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      const bool in = i < Lr && a < nbj && (!unit || i > a);
-      v[s][a] = bload<T>(rs, in ? (uint32_t)((i + (size_t)a * ld) * sizeof(T)) : kOob);
-      if (unit && i == a && a < nbj) v[s][a] += (T)1;
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < RS; ++s) {
-    const int i = threadIdx.x + kBT * s;
-    if (i < Lr)
-#pragma unroll
-      for (int a = 0; a < NB; ++a) Ys[i * PS + a] = v[s][a];
-  }
-  __syncthreads();
-}
-
-// Householder QR of the LDS panel (Lr x nbj).  On return Ys holds the
-// reflectors (unit diagonal, zeros above), f.beta the diagonal of R, f.tau the
-// scalars, and the strictly upper part of R has been written to M.
-template <typename T>
-__device__ __forceinline__ void panel_factor(BLds<T>& L, T* M, int ld, int j0, int nbj, int Lr) {
-  constexpr int PS = BLds<T>::PS;
-  T* Ys = L.u.f.Ys;
-  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int a = 0; a < nbj; ++a) {
-    const T alpha = a < Lr ? Ys[a * PS + a] : (T)0;
-    T ss = 0;
-    for (int i = a + 1 + threadIdx.x; i < Lr; i += kBT) {
-      const T x = Ys[i * PS + a];
-      ss += x * x;
-    }
-    ss = wg_sum1(ss, L.red);
-    T tau = 0, scal = 1, beta = alpha;
-    if (ss > (T)0) {
-      const T nrm = sqrt(alpha * alpha + ss);
-      beta = alpha >= (T)0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scal = (T)1 / (alpha - beta);
-    }
-    for (int i = a + 1 + threadIdx.x; i < Lr; i += kBT) Ys[i * PS + a] *= scal;
-    if (threadIdx.x == 0) {
-      L.u.f.beta[a] = beta;
-      L.u.f.tau[a] = tau;
-      if (a < Lr) Ys[a * PS + a] = 1;
-    }
-    __syncthreads();
-    // H_a applied to the panel's columns a+1 .. nbj-1, one column per wave;
-    // v and each column are read into registers in one batch of LDS loads
-    if (tau != (T)0 && a + 1 + w < nbj) {
-      const int nq = (Lr + 63) >> 6;
-      T vr[kBS];
-#pragma unroll
-      for (int q = 0; q < kBS; ++q) {
-        const int i = lane + 64 * q;
-        const bool in = q < nq && i >= a && i < Lr;
-        const T x = Ys[(in ? i : a) * PS + a];
-        vr[q] = in ? x : (T)0;
-      }
-      for (int b = a + 1 + w; b < nbj; b += kBW) {
-        T cb[kBS];
-#pragma unroll
-        for (int q = 0; q < kBS; ++q) {
-          const int i = lane + 64 * q;
-          cb[q] = Ys[((q < nq && i < Lr) ? i : 0) * PS + b];
-        }
-        T d = 0;
-#pragma unroll
-        for (int q = 0; q < kBS; ++q) d += vr[q] * cb[q];
-        d = wsum(d) * tau;
-#pragma unroll
-        for (int q = 0; q < kBS; ++q) {
-          const int i = lane + 64 * q;
-          if (q < nq && i >= a && i < Lr) Ys[i * PS + b] = cb[q] - d * vr[q];
-        }
-      }
-    }
-    __syncthreads();
-  }
-  // R above the diagonal to M; Y keeps zeros there
-  for (int e = threadIdx.x; e < nbj * nbj; e += kBT) {
-    const int i = e % nbj, a = e / nbj;
-    if (i < a && i < Lr) {
-      M[(size_t)(j0 + i) + (size_t)(j0 + a) * ld] = Ys[i * PS + a];
-      Ys[i * PS + a] = 0;
-    }
-  }
-  __syncthreads();
-}
-
-// Ts (upper, row-major NB x NB) of the panel in Ys with scalars tau[0:nbj):
-// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (Y(:, 0:j)^T y_j), the
-// Gram Y^T Y from MFMA over 16-row chunks (16 x 16 blocks).  One wave.
-template <typename T>
-__device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* tau) {
-  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
-  using MF = Mfma<T>;
-  const T* Ys = L.u.f.Ys;
-  T* Ts = L.u.f.Ts;
-  T* Gs = L.u.f.Gs;
-  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
-  const int lc = lane & 15, lg = lane >> 4;
-  if (w == 0) {
-    typename MF::V g[NBB][NBB];
-#pragma unroll
-    for (int bi = 0; bi < NBB; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < NBB; ++bj) g[bi][bj] = typename MF::V{0, 0, 0, 0};
-    const int nk = (Lr + 15) >> 4;
-    for (int kc = 0; kc < nk; ++kc) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int row = 16 * kc + 4 * lg + t;
-        const bool ok = row < Lr;
-        T yv[NBB];
-#pragma unroll
-        for (int b = 0; b < NBB; ++b) {
-          const T y = Ys[(ok ? row : 0) * PS + 16 * b + lc];
-          yv[b] = ok ? y : (T)0;
-        }
-#pragma unroll
-        for (int bi = 0; bi < NBB; ++bi)
-#pragma unroll
-          for (int bj = bi; bj < NBB; ++bj) g[bi][bj] = MF::mma(yv[bi], yv[bj], g[bi][bj]);
-      }
-    }
-    // upper blocks from the products; the lower ones are written as zeros (the
-    // recurrence multiplies them by zeros, and LDS may hold any bit pattern)
-#pragma unroll
-    for (int bi = 0; bi < NBB; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < NBB; ++bj)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          Gs[(16 * bi + MF::drow(lane, r)) * NB + 16 * bj + lc] = bj >= bi ? g[bi][bj][r] : (T)0;
-    // lane i keeps row i of T in registers; column j of G is read in one
-    // batch of (broadcast) LDS loads per step
-    T trow[NB];
-#pragma unroll
-    for (int l = 0; l < NB; ++l) trow[l] = 0;
-    for (int j = 0; j < nbj; ++j) {
-      const T tj = tau[j];
-      T sacc = 0;
-#pragma unroll
-      for (int l = 0; l < NB; ++l) sacc += trow[l] * Gs[l * NB + j];
-      const T val = lane < j ? -tj * sacc : (lane == j ? tj : (T)0);
-#pragma unroll
-      for (int l = 0; l < NB; ++l) trow[l] = (l == j) ? val : trow[l];
-    }
-    if (lane < NB)
-#pragma unroll
-      for (int l = 0; l < NB; ++l) Ts[lane * NB + l] = trow[l];
-  }
-  __syncthreads();
-}
-
-// C (Lr x nc, ldc) <- C - Y (T^T (Y^T C)) with Y = Ys (Lr x NB), T = Ts, on
-// MFMA: each wave takes 16 columns at a time.  W = Y^T C accumulates over
-// 16-row chunks (lane l supplies four consecutive rows of its column), W' =
-// T^T W and C - Y W' take their B operand from the accumulator registers
-// themselves: every product is a sum over an index whose order the lanes
-// agree on, so the K order may follow the accumulator layout.  The panel's
-// NB columns form NB / 16 blocks of the 16 x 16 tiles.
-// Lp >= Lr rows of each column are addressable (zero padding beyond Lr), and
-// groups of 4 rows starting at a multiple of 4 never cross Lp; FP32 moves
-// such groups with one 16-byte access per lane.
-template <typename T>
-__device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C, int ldc, int nc) {
-  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
-  constexpr int KB = sizeof(T) == 4 ? 8 : 4;    // 16-row chunks per batch of loads
-  using MF = Mfma<T>;
-  using V = typename MF::V;
-  const T* Ys = L.u.f.Ys;
-  const T* Ts = L.u.f.Ts;
-  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
-  const int lc = lane & 15, lg = lane >> 4;
-  if (nc <= 0) return;
-  const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lp) * sizeof(T));
-  const int nk = (Lr + 15) >> 4;
-  for (int c0 = 16 * w; c0 < nc; c0 += 16 * kBW) {
-    const int col = c0 + lc;
-    const bool cok = col < nc;
-    // W = Y^T C (block b holds rows 16 b .. 16 b + 15 of W)
-    V acc[NBB];
-#pragma unroll
-    for (int b = 0; b < NBB; ++b) acc[b] = V{0, 0, 0, 0};
-    for (int kb = 0; kb < nk; kb += KB) {
-      T cv[KB][4];
-#pragma unroll
-      for (int u = 0; u < KB; ++u) {
-        const int g = 16 * (kb + u) + 4 * lg;           // rows g .. g + 3 of column col
-        if constexpr (sizeof(T) == 4) {
-          const f32x4v v = bload4(rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) cv[u][t] = v[t];
-        } else {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int row = g + t;
-            cv[u][t] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < KB; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int row = 16 * (kb + u) + 4 * lg + t;
-          const bool ok = row < Lr;
-#pragma unroll
-          for (int b = 0; b < NBB; ++b) {
-            const T y = Ys[(ok ? row : 0) * PS + 16 * b + lc];
-            acc[b] = MF::mma(ok ? y : (T)0, cv[u][t], acc[b]);
-          }
-        }
-    }
-    // W' = T^T W; T is upper triangular, so block o takes blocks i <= o
-    V wp[NBB];
-#pragma unroll
-    for (int o = 0; o < NBB; ++o) {
-      wp[o] = V{0, 0, 0, 0};
-#pragma unroll
-      for (int i = 0; i <= o; ++i)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int b = 16 * i + MF::drow(lane, t);
-          wp[o] = MF::mma(Ts[b * NB + 16 * o + lc], acc[i][t], wp[o]);
-        }
-    }
-    // C <- C - Y W'
-    for (int kb = 0; kb < nk; kb += KB) {
-      V d[KB];
-#pragma unroll
-      for (int u = 0; u < KB; ++u) {
-        if constexpr (sizeof(T) == 4) {
-          const int g = 16 * (kb + u) + 4 * lg;         // accumulator rows g .. g + 3
-          d[u] = bload4(rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * (kb + u) + MF::drow(lane, r);
-            d[u][r] = bload<T>(rs, (row < Lr && cok) ? (uint32_t)((row + (size_t)col * ldc) * sizeof(T)) : kOob);
-          }
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < KB; ++u) {
-        const int arow = 16 * (kb + u) + lc;
-        const bool aok = arow < Lr;
-#pragma unroll
-        for (int b = 0; b < NBB; ++b)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const T y = Ys[(aok ? arow : 0) * PS + 16 * b + MF::drow(lane, t)];
-            d[u] = MF::mma(aok ? -y : (T)0, wp[b][t], d[u]);
-          }
-        if constexpr (sizeof(T) == 4) {
-          const int g = 16 * (kb + u) + 4 * lg;
-          bstore4(d[u], rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * (kb + u) + MF::drow(lane, r);
-            if (row < Lr && cok) C[(size_t)row + (size_t)col * ldc] = d[u][r];
-          }
-        }
-      }
-    }
+// f(integral_constant<int, I>) for I = B .. E - 1, so that register arrays
+// are only ever indexed by constants.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
   }
 }
 
-// Householder QR of the r x c matrix M (ld) in place: R on and above the
-// diagonal, the reflectors below, tau[min(r, c)], and each panel's T
-// (NB x NB, row-major) at Tst + panel * NB * NB.
-template <typename T>
-__device__ __noinline__ void wg_geqrf_impl(LSQ_GLB T* Mg, int ld, int r, int c, LSQ_GLB T* taug,
-                                           LSQ_GLB T* Tstg, LSQ_LDS BLds<T>* Lp) {
-  T* M = (T*)uni(Mg);
-  T* tau = (T*)uni(taug);
-  T* Tst = (T*)uni(Tstg);
-  BLds<T>& L = *(BLds<T>*)uni(Lp);
-  ld = uni(ld); r = uni(r); c = uni(c);
-  constexpr int NB = QrCfg<T>::NB;
-  const int kq = r < c ? r : c;
-  for (int j0 = 0, pan = 0; j0 < kq; j0 += NB, ++pan) {
-    const int nbj = kq - j0 < NB ? kq - j0 : NB, Lr = r - j0;
-    stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, false);
-    panel_factor(L, M, ld, j0, nbj, Lr);
-    panel_t(L, nbj, Lr, L.u.f.tau);
-    // reflectors and the diagonal of R back to M; scalars and T to storage
-    constexpr int PS = NB + 1;
-    for (int e = threadIdx.x; e < Lr * nbj; e += kBT) {
-      const int i = e % Lr, a = e / Lr;
-      if (i > a) M[(size_t)(j0 + i) + (size_t)(j0 + a) * ld] = L.u.f.Ys[i * PS + a];
-      else if (i == a) M[(size_t)(j0 + i) + (size_t)(j0 + a) * ld] = L.u.f.beta[a];
-    }
-    for (int e = threadIdx.x; e < NB * NB; e += kBT) Tst[(size_t)pan * NB * NB + e] = L.u.f.Ts[e];
-    if (threadIdx.x < nbj) tau[j0 + threadIdx.x] = L.u.f.tau[threadIdx.x];
-    apply_block_qt(L, Lr, ld - j0, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
-    __syncthreads();
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void wg_geqrf(T* M, int ld, int r, int c, T* tau, T* Tst, BLds<T>& L) {
-  wg_geqrf_impl<T>((LSQ_GLB T*)M, ld, r, c, (LSQ_GLB T*)tau, (LSQ_GLB T*)Tst, (LSQ_LDS BLds<T>*)&L);
-}
-
-// X (r x ncols, ldx) <- Q^T X for the k reflectors stored in M (ld) by
-// wg_geqrf, panel by panel.
-template <typename T>
-__device__ __noinline__ void wg_apply_qt_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
-                                              const LSQ_GLB T* Tstg, LSQ_GLB T* Xg, int ldx,
-                                              int ncols, LSQ_LDS BLds<T>* Lp) {
-  const T* M = (const T*)uni(Mg);
-  const T* Tst = (const T*)uni(Tstg);
-  T* X = (T*)uni(Xg);
-  BLds<T>& L = *(BLds<T>*)uni(Lp);
-  ld = uni(ld); r = uni(r); k = uni(k); ldx = uni(ldx); ncols = uni(ncols);
-  constexpr int NB = QrCfg<T>::NB;
-  for (int j0 = 0, pan = 0; j0 < k; j0 += NB, ++pan) {
-    const int nbj = k - j0 < NB ? k - j0 : NB, Lr = r - j0;
-    for (int e = threadIdx.x; e < NB * NB; e += kBT) L.u.f.Ts[e] = Tst[(size_t)pan * NB * NB + e];
-    stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, true);
-    apply_block_qt(L, Lr, ldx - j0, X + j0, ldx, ncols);
-    __syncthreads();
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, const T* Tst, T* X,
-                                            int ldx, int ncols, BLds<T>& L) {
-  wg_apply_qt_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_GLB T*)X, ldx,
-                      ncols, (LSQ_LDS BLds<T>*)&L);
-}
-
-// ------------------------------------------- work-group vector kernels --
-// The correction solves on all waves.  A vector of length <= kBatchMaxDim
-// lives in LDS; for the matrix work thread t owns rows 4t .. 4t + 3, which a
-// padded column delivers in one (FP32) or two (FP64) 16-byte loads.
-
+// -------------------------------------------------- lane exchanges --
 // Pairwise exchanges for the reduce-scatter: the gfx950 permlane swaps pair
 // lane l with l ^ 32 (l ^ 16); for X, Y in every lane, afterwards X + Y is the
 // lane's own value plus its partner's, taken from X in the lower and from Y
@@ -641,6 +300,455 @@ __device__ __forceinline__ void load_rows4(__amdgpu_buffer_rsrc_t rs, bool ok, u
     v[0] = a[0]; v[1] = a[1]; v[2] = b[0]; v[3] = b[1];
   }
 }
+template <typename T>
+__device__ __forceinline__ void store_rows4(__amdgpu_buffer_rsrc_t rs, bool ok, uint32_t off, const T (&v)[4]) {
+  using R = decltype(__builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
+  if constexpr (sizeof(T) == 4) {
+    bstore4(f32x4v{v[0], v[1], v[2], v[3]}, rs, ok ? off : kOob);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(R, f64x2v{v[0], v[1]}), rs, ok ? off : kOob, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(R, f64x2v{v[2], v[3]}), rs, ok ? off + 16 : kOob, 0, 0);
+  }
+}
+
+// ------------------------------------------------------------ Householder --
+// Blocked Householder QR (LAPACK's convention: H = I - tau v v^T, v(j) = 1;
+// Q = H_0 ... H_{k-1}; per panel H_j0 ... H_{j0+nb-1} = I - Y T Y^T with T
+// upper triangular).  A panel of NB columns is factored in LDS; its T comes
+// from the Gram Y^T Y; the trailing columns are updated with
+// C <- C - Y (T^T (Y^T C)), each wave streaming CG columns at a time through
+// registers (one read and one write of C per panel).
+
+// Panel rows j0 .. j0 + Lr of columns j0 .. j0 + nbj of M into Ys (columns
+// beyond nbj zero).  unit: load the reflector view (1 on the diagonal, 0
+// above) of a factored panel instead of the raw columns.
+template <typename T>
+__device__ __forceinline__ void stage_panel(const T* M, int ld, int j0, int nbj, int Lr, T* Ys,
+                                            bool unit) {
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, RS = kBatchMaxDim / kBT;
+  const T* base = M + j0 + (size_t)j0 * ld;
+  const auto rs = rsrc(base, ((size_t)(NB - 1) * ld + Lr) * sizeof(T));
+  T v[RS][NB];
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int i = threadIdx.x + kBT * s;
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      const bool in = i < Lr && a < nbj && (!unit || i > a);
+      v[s][a] = bload<T>(rs, in ? (uint32_t)((i + (size_t)a * ld) * sizeof(T)) : kOob);
+      if (unit && i == a && a < nbj) v[s][a] += (T)1;
+    }
+  }
+  const int Lr16 = (Lr + 15) & ~15;          // rows Lr .. Lr16 zero (see panel_factor)
+#pragma unroll
+  for (int s = 0; s < RS; ++s) {
+    const int i = threadIdx.x + kBT * s;
+    if (i < Lr16)
+#pragma unroll
+      for (int a = 0; a < NB; ++a) Ys[i * PS + a] = v[s][a];
+  }
+  __syncthreads();
+}
+
+// Householder QR of the panel M[j0 : j0 + Lr, j0 : j0 + nbj) (nbj <= Lr) in
+// registers: thread t holds panel rows 4t .. 4t + 3 of the NB columns.  For
+// column a one work-group reduction gives both ||x(a+1:)||^2 and the products
+// x(a+1:)^T c_b with the later columns b (wave reduce-scatter, then the four
+// waves' partials and row a through LDS, one barrier); every thread then
+// derives H_a = I - tau v v^T (v = [1; x(a+1:) / (alpha - beta)]) and applies
+// it to its rows.  On return M holds R on and above the diagonal and the
+// reflectors below it, Ys the reflectors (unit diagonal, zeros above, zero
+// columns beyond nbj), f.beta the diagonal of R and f.tau the scalars.
+template <typename T>
+__device__ __forceinline__ void panel_factor(BLds<T>& L, T* M, int ld, int j0, int nbj, int Lr) {
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1;
+  static_assert(kBT * 4 == kBatchMaxDim, "thread t holds rows 4t .. 4t + 3");
+  T* Ys = L.u.f.Ys;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g0 = 4 * t;
+  const bool rok = g0 < Lr;
+  const auto rs = rsrc(M + j0 + (size_t)j0 * ld, ((size_t)(nbj - 1) * ld + ((Lr + 3) & ~3)) * sizeof(T));
+  T P[NB][4];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) load_rows4(rs, rok && c < nbj, (uint32_t)((g0 + (size_t)c * ld) * sizeof(T)), P[c]);
+  static_for<0, NB>([&](auto ac) {
+    constexpr int a = decltype(ac)::value;
+    if (a < nbj) {
+      T* buf = L.vred + (a & 1) * (kBW + 1) * NB;
+      T s[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        s[b] = 0;
+        if (b < a) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[b] += (g0 + e > a ? P[a][e] : (T)0) * P[b][e];
+      }
+      const T sv = wave_reduce_scatter<T, NB>(s);
+      if ((lane & 3) == 0) buf[w * NB + (lane >> 2)] = sv;
+      if (t == (a >> 2)) {
+#pragma unroll
+        for (int b = a; b < NB; ++b) buf[kBW * NB + b] = P[b][a & 3];
+      }
+      __syncthreads();
+      T S[NB], Ra[NB];
+#pragma unroll
+      for (int b = a; b < NB; ++b) {
+        S[b] = (buf[b] + buf[NB + b]) + (buf[2 * NB + b] + buf[3 * NB + b]);
+        Ra[b] = buf[kBW * NB + b];
+      }
+      const T alpha = Ra[a], ss = S[a];
+      T tau = 0, scal = 1, beta = alpha;
+      if (ss > (T)0) {
+        const T nrm = sqrt(alpha * alpha + ss);
+        beta = alpha >= (T)0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = (T)1 / (alpha - beta);
+      }
+      T v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = g0 + e;
+        v[e] = row > a ? P[a][e] * scal : (row == a ? (T)1 : (T)0);
+      }
+#pragma unroll
+      for (int b = a + 1; b < NB; ++b) {
+        const T d = tau * (Ra[b] + scal * S[b]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) P[b][e] -= d * v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = g0 + e;
+        P[a][e] = row > a ? v[e] : (row == a ? beta : P[a][e]);
+      }
+      if (t == 0) {
+        L.u.f.beta[a] = beta;
+        L.u.f.tau[a] = tau;
+      }
+    }
+  });
+#pragma unroll
+  for (int c = 0; c < NB; ++c) store_rows4(rs, rok && c < nbj, (uint32_t)((g0 + (size_t)c * ld) * sizeof(T)), P[c]);
+  // rows Lr .. 16 ceil(Lr / 16) are zero, so that the MFMA loops over
+  // 16-row chunks need no row masks
+  const int Lr16 = (Lr + 15) & ~15;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int row = g0 + e;
+    if (row >= Lr16) continue;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      Ys[row * PS + c] = (c < nbj && row < Lr) ? (row > c ? P[c][e] : (row == c ? (T)1 : (T)0)) : (T)0;
+  }
+  __syncthreads();
+}
+
+// Ts (upper, row-major NB x NB) of the panel in Ys with scalars tau[0:nbj):
+// T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) (Y(:, 0:j)^T y_j), the
+// Gram Y^T Y from MFMA over 16-row chunks (16 x 16 blocks).  One wave.
+template <typename T>
+__device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* tau) {
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
+  using MF = Mfma<T>;
+  const T* Ys = L.u.f.Ys;
+  T* Ts = L.u.f.Ts;
+  T* Gs = L.u.f.Gs;
+  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
+  const int lc = lane & 15, lg = lane >> 4;
+  if (w == 0) {
+    typename MF::V g[NBB][NBB];
+#pragma unroll
+    for (int bi = 0; bi < NBB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBB; ++bj) g[bi][bj] = typename MF::V{0, 0, 0, 0};
+    const int nk = (Lr + 15) >> 4;
+    for (int kc = 0; kc < nk; ++kc) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int row = 16 * kc + 4 * lg + t;
+        const bool ok = row < Lr;
+        T yv[NBB];
+#pragma unroll
+        for (int b = 0; b < NBB; ++b) {
+          const T y = Ys[(ok ? row : 0) * PS + 16 * b + lc];
+          yv[b] = ok ? y : (T)0;
+        }
+#pragma unroll
+        for (int bi = 0; bi < NBB; ++bi)
+#pragma unroll
+          for (int bj = bi; bj < NBB; ++bj) g[bi][bj] = MF::mma(yv[bi], yv[bj], g[bi][bj]);
+      }
+    }
+    // upper blocks from the products; the lower ones are written as zeros (the
+    // recurrence multiplies them by zeros, and LDS may hold any bit pattern)
+#pragma unroll
+    for (int bi = 0; bi < NBB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBB; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Gs[(16 * bi + MF::drow(lane, r)) * NB + 16 * bj + lc] = bj >= bi ? g[bi][bj][r] : (T)0;
+    // lane i keeps row i of T in registers; column j of G is read in one
+    // batch of (broadcast) LDS loads per step
+    T trow[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) trow[l] = 0;
+    for (int j = 0; j < nbj; ++j) {
+      const T tj = tau[j];
+      T sacc = 0;
+#pragma unroll
+      for (int l = 0; l < NB; ++l) sacc += trow[l] * Gs[l * NB + j];
+      const T val = lane < j ? -tj * sacc : (lane == j ? tj : (T)0);
+#pragma unroll
+      for (int l = 0; l < NB; ++l) trow[l] = (l == j) ? val : trow[l];
+    }
+    if (lane < NB)
+#pragma unroll
+      for (int l = 0; l < NB; ++l) Ts[lane * NB + l] = trow[l];
+  }
+  __syncthreads();
+}
+
+// C (Lr x nc, ldc) <- C - Y (T^T (Y^T C)) with Y = Ys (Lr x NB), T = Ts, on
+// MFMA: each wave takes 16 columns at a time.  W = Y^T C accumulates over
+// 16-row chunks (lane l supplies four consecutive rows of its column), W' =
+// T^T W and C - Y W' take their B operand from the accumulator registers
+// themselves: every product is a sum over an index whose order the lanes
+// agree on, so the K order may follow the accumulator layout.  The panel's
+// NB columns form NB / 16 blocks of the 16 x 16 tiles.
+// Lp >= Lr rows of each column are addressable (zero padding beyond Lr), and
+// groups of 4 rows starting at a multiple of 4 never cross Lp: the W pass
+// moves such a group with one (FP32) or two (FP64) 16-byte accesses per lane,
+// and so does the update in FP32.
+template <typename T>
+__device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C, int ldc, int nc) {
+  constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
+  constexpr int KB = sizeof(T) == 4 ? 8 : 4;    // 16-row chunks per batch of loads
+  using MF = Mfma<T>;
+  using V = typename MF::V;
+  const T* Ys = L.u.f.Ys;
+  const T* Ts = L.u.f.Ts;
+  const int lane = threadIdx.x & 63, w = uni(threadIdx.x >> 6);
+  const int lc = lane & 15, lg = lane >> 4;
+  if (nc <= 0) return;
+  const auto rs = rsrc(C, ((size_t)(nc - 1) * ldc + Lp) * sizeof(T));
+  const int nk = (Lr + 15) >> 4;
+  for (int c0 = 16 * w; c0 < nc; c0 += 16 * kBW) {
+    const int col = c0 + lc;
+    const bool cok = col < nc;
+    // Both passes run over batches of KB 16-row chunks with two register
+    // sets: the next batch's loads are issued before the current batch's
+    // MFMAs, and loads beyond the last chunk read zeros (out of range).
+    // W = Y^T C (block b holds rows 16 b .. 16 b + 15 of W); lane l supplies
+    // rows g .. g + 3 of its column, g = 16 chunk + 4 (l / 16).
+    // FP32: lane l supplies rows g .. g + 3 of its column, g = 16 chunk +
+    // 4 (l / 16), one 16-byte load.  FP64: rows 2 (l / 16) + {0, 1} and
+    // 8 + 2 (l / 16) + {0, 1} (krow), two 16-byte loads that each cover 64
+    // contiguous bytes of the column across the four lane groups.
+    auto krow = [&](int t) { return sizeof(T) == 4 ? 4 * lg + t : (t < 2 ? 2 * lg + t : 6 + 2 * lg + t); };
+    auto load1 = [&](int kb, T (&cv)[KB][4]) {
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        if constexpr (sizeof(T) == 4) {
+          const int g = 16 * (kb + u) + 4 * lg;
+          load_rows4(rs, g < Lr && cok, (uint32_t)((g + (size_t)col * ldc) * sizeof(T)), cv[u]);
+        } else {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int g = 16 * (kb + u) + 8 * h + 2 * lg;
+            const f64x2v v = __builtin_bit_cast(f64x2v, __builtin_amdgcn_raw_buffer_load_b128(
+                rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * sizeof(T)) : kOob, 0, 0));
+            cv[u][2 * h] = v[0];
+            cv[u][2 * h + 1] = v[1];
+          }
+        }
+      }
+    };
+    // two accumulators (even and odd chunks) halve the dependent MFMA chain
+    V acc[NBB], acc2[NBB];
+#pragma unroll
+    for (int b = 0; b < NBB; ++b) acc[b] = acc2[b] = V{0, 0, 0, 0};
+    auto comp1 = [&](int kb, const T (&cv)[KB][4]) {
+      // the batch's Y values first; chunks past the last one (whose C rows
+      // read as zeros) take the last chunk's finite Y rows, as Ys rows from
+      // 16 nk on are not zeroed
+      T yv[KB][4][NBB];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int ch = kb + u < nk ? kb + u : nk - 1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int b = 0; b < NBB; ++b) yv[u][t][b] = Ys[(16 * ch + krow(t)) * PS + 16 * b + lc];
+      }
+#pragma unroll
+      for (int u = 0; u < KB; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int b = 0; b < NBB; ++b) {
+            if (u & 1) acc2[b] = MF::mma(yv[u][t][b], cv[u][t], acc2[b]);
+            else acc[b] = MF::mma(yv[u][t][b], cv[u][t], acc[b]);
+          }
+    };
+    {
+      // (the scheduling barriers keep each batch's loads ahead of the
+      // previous batch's MFMAs)
+      T ca[KB][4], cb[KB][4];
+      load1(0, ca);
+      for (int kb = 0; kb < nk; kb += 2 * KB) {
+        load1(kb + KB, cb);
+        __builtin_amdgcn_sched_barrier(0);
+        comp1(kb, ca);
+        load1(kb + 2 * KB, ca);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + KB < nk) comp1(kb + KB, cb);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NBB; ++b) acc[b] += acc2[b];
+    // W' = T^T W; T is upper triangular, so block o takes blocks i <= o
+    V wp[NBB];
+#pragma unroll
+    for (int o = 0; o < NBB; ++o) {
+      wp[o] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i <= o; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int b = 16 * i + MF::drow(lane, t);
+          wp[o] = MF::mma(Ts[b * NB + 16 * o + lc], acc[i][t], wp[o]);
+        }
+    }
+    // C <- C - Y W' in the accumulator layout
+    auto load2 = [&](int kb, V (&d)[KB]) {
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        if constexpr (sizeof(T) == 4) {
+          const int g = 16 * (kb + u) + 4 * lg;         // accumulator rows g .. g + 3
+          d[u] = bload4(rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
+        } else {
+          // FP64 computes the transposed tile: register r of lane l holds row
+          // 16 chunk + l % 16 of column c0 + drow(l, r)
+          const int row = 16 * (kb + u) + lc;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int cc = c0 + MF::drow(lane, r);
+            d[u][r] = bload<T>(rs, (row < Lr && cc < nc) ? (uint32_t)((row + (size_t)cc * ldc) * sizeof(T)) : kOob);
+          }
+        }
+      }
+    };
+    auto comp2 = [&](int kb, V (&d)[KB]) {
+      T yv[KB][NBB][4];
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int ch = kb + u < nk ? kb + u : nk - 1;
+#pragma unroll
+        for (int b = 0; b < NBB; ++b)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) yv[u][b][t] = Ys[(16 * ch + lc) * PS + 16 * b + MF::drow(lane, t)];
+      }
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {                  // (chunks past the last one are not stored)
+#pragma unroll
+        for (int b = 0; b < NBB; ++b)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            // FP32: (-Y) W'; FP64: W'^T (-Y)^T, the same K order (wp[b][t]
+            // of lane l is W' row 16 b + drow(l, t) = 16 b + 4 t + l / 16)
+            if constexpr (sizeof(T) == 4) d[u] = MF::mma(-yv[u][b][t], wp[b][t], d[u]);
+            else d[u] = MF::mma(wp[b][t], -yv[u][b][t], d[u]);
+          }
+        if constexpr (sizeof(T) == 4) {
+          const int g = 16 * (kb + u) + 4 * lg;
+          bstore4(d[u], rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
+        } else {
+          const int row = 16 * (kb + u) + lc;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int cc = c0 + MF::drow(lane, r);
+            bstore<T>(d[u][r], rs, (row < Lr && cc < nc) ? (uint32_t)((row + (size_t)cc * ldc) * sizeof(T)) : kOob);
+          }
+        }
+      }
+    };
+    {
+      V da[KB], db[KB];
+      load2(0, da);
+      for (int kb = 0; kb < nk; kb += 2 * KB) {
+        load2(kb + KB, db);
+        __builtin_amdgcn_sched_barrier(0);
+        comp2(kb, da);
+        load2(kb + 2 * KB, da);
+        __builtin_amdgcn_sched_barrier(0);
+        if (kb + KB < nk) comp2(kb + KB, db);
+      }
+    }
+  }
+}
+
+// Householder QR of the r x c matrix M (ld) in place: R on and above the
+// diagonal, the reflectors below, tau[min(r, c)], and each panel's T
+// (NB x NB, row-major) at Tst + panel * NB * NB.
+template <typename T>
+__device__ __noinline__ void wg_geqrf_impl(LSQ_GLB T* Mg, int ld, int r, int c, LSQ_GLB T* taug,
+                                           LSQ_GLB T* Tstg, LSQ_LDS BLds<T>* Lp) {
+  T* M = (T*)uni(Mg);
+  T* tau = (T*)uni(taug);
+  T* Tst = (T*)uni(Tstg);
+  BLds<T>& L = *(BLds<T>*)uni(Lp);
+  ld = uni(ld); r = uni(r); c = uni(c);
+  constexpr int NB = QrCfg<T>::NB;
+  const int kq = r < c ? r : c;
+  for (int j0 = 0, pan = 0; j0 < kq; j0 += NB, ++pan) {
+    const int nbj = kq - j0 < NB ? kq - j0 : NB, Lr = r - j0;
+    panel_factor(L, M, ld, j0, nbj, Lr);
+    panel_t(L, nbj, Lr, L.u.f.tau);
+    // scalars and T to storage
+    for (int e = threadIdx.x; e < NB * NB; e += kBT) Tst[(size_t)pan * NB * NB + e] = L.u.f.Ts[e];
+    if (threadIdx.x < nbj) tau[j0 + threadIdx.x] = L.u.f.tau[threadIdx.x];
+    apply_block_qt(L, Lr, ld - j0, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void wg_geqrf(T* M, int ld, int r, int c, T* tau, T* Tst, BLds<T>& L) {
+  wg_geqrf_impl<T>((LSQ_GLB T*)M, ld, r, c, (LSQ_GLB T*)tau, (LSQ_GLB T*)Tst, (LSQ_LDS BLds<T>*)&L);
+}
+
+// X (r x ncols, ldx) <- Q^T X for the k reflectors stored in M (ld) by
+// wg_geqrf, panel by panel.
+template <typename T>
+__device__ __noinline__ void wg_apply_qt_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
+                                              const LSQ_GLB T* Tstg, LSQ_GLB T* Xg, int ldx,
+                                              int ncols, LSQ_LDS BLds<T>* Lp) {
+  const T* M = (const T*)uni(Mg);
+  const T* Tst = (const T*)uni(Tstg);
+  T* X = (T*)uni(Xg);
+  BLds<T>& L = *(BLds<T>*)uni(Lp);
+  ld = uni(ld); r = uni(r); k = uni(k); ldx = uni(ldx); ncols = uni(ncols);
+  constexpr int NB = QrCfg<T>::NB;
+  for (int j0 = 0, pan = 0; j0 < k; j0 += NB, ++pan) {
+    const int nbj = k - j0 < NB ? k - j0 : NB, Lr = r - j0;
+    for (int e = threadIdx.x; e < NB * NB; e += kBT) L.u.f.Ts[e] = Tst[(size_t)pan * NB * NB + e];
+    stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, true);
+    apply_block_qt(L, Lr, ldx - j0, X + j0, ldx, ncols);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, const T* Tst, T* X,
+                                            int ldx, int ncols, BLds<T>& L) {
+  wg_apply_qt_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_GLB T*)X, ldx,
+                      ncols, (LSQ_LDS BLds<T>*)&L);
+}
+
+// ------------------------------------------- work-group vector kernels --
+// The correction solves on all waves.  A vector of length <= kBatchMaxDim
+// lives in LDS; for the matrix work thread t owns rows 4t .. 4t + 3, which a
+// padded column delivers in one (FP32) or two (FP64) 16-byte loads.
 
 // y (LDS, length r) <- Q^T y (trans) or Q y, Q = H_0 ... H_{k-1} from the
 // reflectors of M (ld) and the panels' T (NB x NB, row-major, at Tst; the
@@ -822,6 +930,94 @@ template <typename T>
 __device__ __forceinline__ void wg_trsv_vec(const T* M, int ld, int nn, T* y, bool trans) {
   if (trans) wg_trsv_vec_impl<T, true>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
   else wg_trsv_vec_impl<T, false>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
+}
+
+// ------------------------------------------------------------- staging --
+// dst = src^T with optional reversals, through an LDS tile: src is sr x sc
+// (column-major, lds), dst is sc x sr (ldd) with dst(x', y') = src(y, x),
+// x' = sc - 1 - x if rx, y' = sr - 1 - y if ry; dst rows sc .. ldd - 1 are
+// zero filled.  A tile is 64 columns of src by kBT rows: the loads run down
+// the columns of src and the stores down the columns of dst.  Returns this
+// thread's part of the squared Frobenius norm of src.
+template <typename T, typename S>
+__device__ __noinline__ double wg_transpose_impl(const LSQ_GLB S* srcg, int lds, int sr, int sc,
+                                                 LSQ_GLB T* dstg, int ldd, int rx, int ry,
+                                                 LSQ_LDS T* tileg) {
+  constexpr int TX = 64, TY = kBT, TS = TY + 1, UB = 16;
+  const S* src = (const S*)uni(srcg);
+  LSQ_GLB T* dst = uni(dstg);
+  LSQ_LDS T* tile = uni(tileg);
+  lds = uni(lds); sr = uni(sr); sc = uni(sc); ldd = uni(ldd); rx = uni(rx); ry = uni(ry);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const auto rs = rsrc(src, ((size_t)(sc > 0 ? sc - 1 : 0) * lds + sr) * sizeof(S));
+  double ss = 0.0;
+  for (int x0 = 0; x0 < ldd; x0 += TX) {
+    for (int y0 = 0; y0 < sr; y0 += TY) {
+      const int y = y0 + t;
+#pragma unroll
+      for (int xb = 0; xb < TX; xb += UB) {
+        S v[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          const int x = x0 + xb + u;
+          v[u] = bload<S>(rs, (x < sc && y < sr) ? (uint32_t)((y + (size_t)x * lds) * sizeof(S)) : kOob);
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+          ss += (double)v[u] * (double)v[u];
+          tile[(xb + u) * TS + t] = (T)v[u];
+        }
+      }
+      __syncthreads();
+      const int x = x0 + lane;
+      const int xd = x < sc ? (rx ? sc - 1 - x : x) : x;
+      const int ny = sr - y0 < TY ? sr - y0 : TY;
+      if (x < ldd)
+        for (int yy = w; yy < ny; yy += kBW) {
+          const int yd = ry ? sr - 1 - (y0 + yy) : y0 + yy;
+          dst[(size_t)xd + (size_t)yd * ldd] = tile[lane * TS + yy];
+        }
+      __syncthreads();
+    }
+  }
+  return ss;
+}
+template <typename T, typename S>
+__device__ __forceinline__ double wg_transpose(const S* src, int lds, int sr, int sc, T* dst, int ldd,
+                                               bool rx, bool ry, T* tile) {
+  return wg_transpose_impl<T, S>((const LSQ_GLB S*)src, lds, sr, sc, (LSQ_GLB T*)dst, ldd, rx, ry,
+                                 (LSQ_LDS T*)tile);
+}
+
+// dst (rows x cols, ldd; rows .. ldd - 1 zero filled) = src (lds), UB columns
+// of loads in flight per thread.  Returns this thread's part of the squared
+// Frobenius norm of src.
+template <typename T>
+__device__ __noinline__ double wg_copy_impl(const LSQ_GLB double* srcg, int lds, int rows, int cols,
+                                            LSQ_GLB T* dstg, int ldd) {
+  constexpr int UB = 8;
+  const double* src = (const double*)uni(srcg);
+  LSQ_GLB T* dst = uni(dstg);
+  lds = uni(lds); rows = uni(rows); cols = uni(cols); ldd = uni(ldd);
+  const auto rs = rsrc(src, ((size_t)(cols > 0 ? cols - 1 : 0) * lds + rows) * sizeof(double));
+  double ss = 0.0;
+  for (int j0 = 0; j0 < cols; j0 += UB)
+    for (int i = threadIdx.x; i < ldd; i += kBT) {
+      double v[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        v[u] = bload<double>(rs, (i < rows && j0 + u < cols) ? (uint32_t)((i + (size_t)(j0 + u) * lds) * sizeof(double)) : kOob);
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        ss += v[u] * v[u];
+        if (j0 + u < cols) dst[(size_t)i + (size_t)(j0 + u) * ldd] = (T)v[u];
+      }
+    }
+  return ss;
+}
+template <typename T>
+__device__ __forceinline__ double wg_copy(const double* src, int lds, int rows, int cols, T* dst, int ldd) {
+  return wg_copy_impl<T>((const LSQ_GLB double*)src, lds, rows, cols, (LSQ_GLB T*)dst, ldd);
 }
 
 // ----------------------------------------------------------- workspaces --
@@ -1008,26 +1204,18 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
   const LSQ_GLB double* bvec = (const LSQ_GLB double*)P.b;
   const LSQ_GLB double* dvec = (const LSQ_GLB double*)P.d;
   LSQ_GLB double* x = (LSQ_GLB double*)P.x;
-  double mat[4];
-  mat[0] = wg_fro(A, P.lda, m, n, L.dred);
-  mat[1] = wg_fro(B, P.ldb, p, n, L.dred);
-  mat[2] = wg_fro(bvec, m, m, 1, L.dred);
-  mat[3] = wg_fro(dvec, p, p, 1, L.dred);
   // factorization in T: Bt = J_n B^T J_p = Qt [Rt; 0]; X = Qt^T (J_n A^T);
   // Abar = A J Qt J = (J_n X)^T = Za [T; 0]
   const int ldn = ldpad(n), ldm = ldpad(m);
-  for (int i = 0; i < ldn; ++i) {                     // rows n .. ldn-1 are zero padding
-    const LSQ_GLB double* bc = B + (size_t)(n - 1 - (i < n ? i : 0)) * P.ldb;   // column n-1-i of B
-    for (int j = t; j < p; j += kBT) W.Fb[i + (size_t)j * ldn] = i < n ? (T)bc[p - 1 - j] : (T)0;
-    const LSQ_GLB double* ac = A + (size_t)(n - 1 - (i < n ? i : 0)) * P.lda;   // column n-1-i of A
-    for (int j = t; j < m; j += kBT) W.X[i + (size_t)j * ldn] = i < n ? (T)ac[j] : (T)0;
-  }
+  double mat[4];
+  mat[0] = sqrt(wg_sum1(wg_transpose((const double*)A, P.lda, m, n, W.X, ldn, true, false, L.u.f.Ys), L.dred));
+  mat[1] = sqrt(wg_sum1(wg_transpose((const double*)B, P.ldb, p, n, W.Fb, ldn, true, true, L.u.f.Ys), L.dred));
+  mat[2] = wg_fro(bvec, m, m, 1, L.dred);
+  mat[3] = wg_fro(dvec, p, p, 1, L.dred);
   __syncthreads();
   wg_geqrf(W.Fb, ldn, n, p, W.taub, W.Tb, L);
   wg_apply_qt(W.Fb, ldn, n, p, W.Tb, W.X, ldn, m, L);
-  for (int j = 0; j < ldm; ++j)                        // X[i][j] -> Fa[j][n-1-i]
-    for (int i = t; i < n; i += kBT)
-      W.Fa[j + (size_t)(n - 1 - i) * ldm] = j < m ? W.X[i + (size_t)j * ldn] : (T)0;
+  wg_transpose(W.X, ldn, n, m, W.Fa, ldm, false, true, L.u.f.Ys);   // Fa[j][n-1-i] = X[i][j]
   __syncthreads();
   wg_geqrf(W.Fa, ldm, m, n, W.taua, W.Ta, L);
   for (int i = t; i < n; i += kBT) x[i] = 0.0;
@@ -1178,27 +1366,18 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
   const LSQ_GLB double* dvec = (const LSQ_GLB double*)P.d;
   LSQ_GLB double* x = (LSQ_GLB double*)P.x;
   LSQ_GLB double* y = (LSQ_GLB double*)P.y;
-  double mat[4];
-  mat[0] = wg_fro(A, P.lda, n, m, L.dred);
-  mat[1] = wg_fro(B, P.ldb, n, p, L.dred);
-  mat[2] = wg_fro(dvec, n, n, 1, L.dred);
-  mat[3] = 0.0;
   // factorization in T: W = Qw [Rw; 0]; X = Qw^T V;
   // Vt = J_p X^T J_n = Qv Tv
   const int ldn = ldpad(n), ldp = ldpad(p);            // rows beyond n (p) are zero padding
-  for (int j = 0; j < m; ++j)
-    for (int i = t; i < ldn; i += kBT)
-      W.Fw[i + (size_t)j * ldn] = i < n ? (T)A[(size_t)i + (size_t)j * P.lda] : (T)0;
-  for (int j = 0; j < p; ++j)
-    for (int i = t; i < ldn; i += kBT)
-      W.X[i + (size_t)j * ldn] = i < n ? (T)B[(size_t)i + (size_t)j * P.ldb] : (T)0;
+  double mat[4];
+  mat[0] = sqrt(wg_sum1(wg_copy((const double*)A, P.lda, n, m, W.Fw, ldn), L.dred));
+  mat[1] = sqrt(wg_sum1(wg_copy((const double*)B, P.ldb, n, p, W.X, ldn), L.dred));
+  mat[2] = wg_fro(dvec, n, n, 1, L.dred);
+  mat[3] = 0.0;
   __syncthreads();
   wg_geqrf(W.Fw, ldn, n, m, W.taw, W.Tw, L);
   wg_apply_qt(W.Fw, ldn, n, m, W.Tw, W.X, ldn, p, L);
-  for (int j = 0; j < ldp; ++j)                        // X[i][j] -> Fv[p-1-j][n-1-i]
-    for (int i = t; i < n; i += kBT)
-      W.Fv[(size_t)(j < p ? p - 1 - j : j) + (size_t)(n - 1 - i) * ldp] =
-          j < p ? W.X[i + (size_t)j * ldn] : (T)0;
+  wg_transpose(W.X, ldn, n, p, W.Fv, ldp, true, true, L.u.f.Ys);    // Fv[p-1-j][n-1-i] = X[i][j]
   __syncthreads();
   wg_geqrf(W.Fv, ldp, p, n, W.tav, W.Tv, L);
   for (int i = t; i < m; i += kBT) x[i] = 0.0;

@@ -11,12 +11,14 @@
 // every work-group leaves the loop once the counter passes the batch, so the
 // grid always drains.
 //
-// The factorizations are column-by-column Householder QR (LAPACK's xGEQR2
-// convention: H = I - tau v v^T, v(j) = 1) with the trailing updates split
-// over the four waves, several columns per wave at a time.  The vector side of
-// a correction runs one wave per independent operation (applications of Q or
-// Q^T, triangular solves), so consecutive reflectors and triangular steps need
-// no work-group barrier; the waves meet at four barriers per correction.
+// The factorizations are blocked Householder QR (LAPACK's convention: H = I -
+// tau v v^T, v(j) = 1): each 16-column panel is factored in registers (one
+// work-group reduction per column), its compact-WY T comes from an MFMA Gram,
+// and the trailing columns are updated on MFMA by all four waves, 16 columns
+// per wave at a time.  The correction solves also run on all waves: Q and Q^T
+// are applied one panel at a time through the stored T blocks, and the
+// triangular solves go in 16-row blocks (one wave solves the diagonal block,
+// every thread updates its rows).
 #include <type_traits>
 
 #include "engine.hpp"
@@ -30,7 +32,7 @@ constexpr int kBW = kBT / 64;            // waves per work-group
 constexpr int kBS = kBatchMaxDim / 64;   // register slots per lane for one vector
 constexpr int kVecs = 9;                 // LDS vectors of length kBatchMaxDim
 constexpr double kMaxPredictedSteps = 6.0;
-constexpr int kRQ = kBatchMaxDim / kBT;  // row slots per lane when a wave owns every 4th 64-row block
+constexpr int kRQ = kBatchMaxDim / kBT;  // row slots per thread (rows t + kBT q)
 
 // The out-of-line device functions below take their pointers in explicit
 // address spaces, so that their memory operations compile to global and LDS
@@ -159,6 +161,9 @@ struct BLds {
     } f;
     T vec[kVecs][kBatchMaxDim];      // vectors of the correction solves
   } u;
+  static_assert(kVecs * sizeof(float) >= 4 * sizeof(double), "four FP64 vectors fit over the correction vectors");
+  // FP64 vector k (k < 4) of the residual, over the correction vectors
+  __device__ double* dvec(int k) { return reinterpret_cast<double*>(&u.vec[0][0]) + kBatchMaxDim * k; }
   T red[kBW];
   T vred[2 * (kBW + 1) * NB];        // reductions of the register panel and vector kernels
   double dred[kBW * 6];
@@ -1020,6 +1025,72 @@ __device__ __forceinline__ double wg_copy(const double* src, int lds, int rows, 
   return wg_copy_impl<T>((const LSQ_GLB double*)src, lds, rows, cols, (LSQ_GLB T*)dst, ldd);
 }
 
+// ---------------------------------------------------------- residuals --
+// One pass of the FP64 augmented residual over M (rows x cols, ld, column-
+// major): thread t owns rows t + kBT q (q < kRQ), so that each load covers 64
+// consecutive rows, and returns its row sums sum_j M(i, j) xs(j); the column
+// sums sum_i M(i, j) ws(i) are added to cs[j] (LDS, zeroed by the caller)
+// through a wave reduce-scatter of CB columns at a time and LDS atomics.
+// xs and ws are LDS vectors; CB columns of loads are in flight per thread.
+struct RowSums {
+  double v[kRQ];
+};
+__device__ __noinline__ RowSums wg_resid_pass_impl(const LSQ_GLB double* Mg, int ld, int rows, int cols,
+                                                   const LSQ_LDS double* xsg, const LSQ_LDS double* wsg,
+                                                   LSQ_LDS double* csg) {
+  constexpr int CB = 8;
+  const double* M = (const double*)uni(Mg);
+  const LSQ_LDS double* xs = uni(xsg);
+  const LSQ_LDS double* ws = uni(wsg);
+  LSQ_LDS double* cs = uni(csg);
+  ld = uni(ld); rows = uni(rows); cols = uni(cols);
+  const int t = threadIdx.x, lane = t & 63;
+  const auto rs = rsrc(M, ((size_t)(cols > 0 ? cols - 1 : 0) * ld + rows) * sizeof(double));
+  RowSums o;
+  double w[kRQ];
+#pragma unroll
+  for (int q = 0; q < kRQ; ++q) {
+    const int i = t + kBT * q;
+    o.v[q] = 0.0;
+    w[q] = ws[i < rows ? i : 0];
+    w[q] = i < rows ? w[q] : 0.0;
+  }
+  for (int j0 = 0; j0 < cols; j0 += CB) {
+    double a[CB][kRQ];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int q = 0; q < kRQ; ++q) {
+        const int i = t + kBT * q;
+        a[c][q] = bload<double>(rs, (i < rows && j0 + c < cols) ? (uint32_t)((i + (size_t)(j0 + c) * ld) * 8) : kOob);
+      }
+    double csum[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const bool cin = j0 + c < cols;
+      const double xc0 = xs[cin ? j0 + c : 0];
+      const double xc = cin ? xc0 : 0.0;
+      double ps = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRQ; ++q) {
+        o.v[q] += a[c][q] * xc;
+        ps += a[c][q] * w[q];
+      }
+      csum[c] = ps;
+    }
+    const double tot = wave_reduce_scatter<double, CB>(csum);   // lanes 8c .. 8c + 7: column c
+    const int c = lane >> 3;
+    if ((lane & 7) == 0 && j0 + c < cols)
+      __hip_atomic_fetch_add(&cs[j0 + c], tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  return o;
+}
+__device__ __forceinline__ RowSums wg_resid_pass(const double* M, int ld, int rows, int cols,
+                                                 const double* xs, const double* ws, double* cs) {
+  return wg_resid_pass_impl((const LSQ_GLB double*)M, ld, rows, cols, (const LSQ_LDS double*)xs,
+                            (const LSQ_LDS double*)ws, (LSQ_LDS double*)cs);
+}
+
 // ----------------------------------------------------------- workspaces --
 template <typename T>
 struct LseWs {
@@ -1286,63 +1357,46 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < n; i += kBT) x[i] += (double)Yt[n - 1 - i];
     __syncthreads();
   };
-  // f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v (FP64), one pass over
-  // A and B: wave w owns the 64-row blocks w, w + 4, ... (row sums in
-  // registers); the column sums are added up across the waves in LDS.
-  const auto rsA = rsrc((const double*)A, ((size_t)(n - 1) * P.lda + m) * sizeof(double));
-  const auto rsB = rsrc((const double*)B, ((size_t)(n - 1) * P.ldb + p) * sizeof(double));
+  // f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v (FP64): one pass
+  // over A and one over B (row sums per thread, column sums through LDS)
   auto residual = [&](double s[6]) {
-    double* colacc = (double*)L.u.vec[0];
-    for (int j = t; j < n; j += kBT) colacc[j] = 0.0;
-    double ax[kRQ], bx[kRQ], rr[kRQ], vv[kRQ];
-#pragma unroll
-    for (int q = 0; q < kRQ; ++q) {
-      const int i = lane + 64 * (w + kBW * q);
-      ax[q] = 0.0;
-      bx[q] = 0.0;
-      rr[q] = i < m ? W.r[i] : 0.0;
-      vv[q] = i < p ? W.v[i] : 0.0;
+    double* cs = L.dvec(0);
+    double* xl = L.dvec(1);
+    double* rl = L.dvec(2);                             // -r
+    double* vl = L.dvec(3);
+    for (int j = t; j < n; j += kBT) {
+      cs[j] = 0.0;
+      xl[j] = x[j];
     }
+    for (int i = t; i < m; i += kBT) rl[i] = -W.r[i];
+    for (int i = t; i < p; i += kBT) vl[i] = W.v[i];
     __syncthreads();
-#pragma unroll 4
-    for (int j = 0; j < n; ++j) {
-      const double xj = x[j];
-      double cs = 0.0;
-#pragma unroll
-      for (int q = 0; q < kRQ; ++q) {
-        const int i = lane + 64 * (w + kBW * q);
-        const double a = bload<double>(rsA, i < m ? (uint32_t)((i + (size_t)j * P.lda) * 8) : kOob);
-        const double b = bload<double>(rsB, i < p ? (uint32_t)((i + (size_t)j * P.ldb) * 8) : kOob);
-        ax[q] += a * xj;
-        bx[q] += b * xj;
-        cs += b * vv[q] - a * rr[q];
-      }
-      cs = wsum(cs);
-      if (lane == 0) atomicAdd(&colacc[j], cs);
-    }
+    const RowSums ax = wg_resid_pass((const double*)A, P.lda, m, n, xl, rl, cs);
+    const RowSums bx = wg_resid_pass((const double*)B, P.ldb, p, n, xl, vl, cs);
+    __syncthreads();
     for (int q = 0; q < 6; ++q) s[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < kRQ; ++q) {
-      const int i = lane + 64 * (w + kBW * q);
+      const int i = t + kBT * q;
       if (i < m) {
-        const double val = bvec[i] - rr[q] - ax[q];
+        const double ri = -rl[i];
+        const double val = bvec[i] - ri - ax.v[q];
         W.f1[i] = val;
         s[0] += val * val;
-        s[4] += rr[q] * rr[q];
+        s[4] += ri * ri;
       }
       if (i < p) {
-        const double val = dvec[i] - bx[q];
+        const double val = dvec[i] - bx.v[q];
         W.f2[i] = val;
         s[1] += val * val;
-        s[5] += vv[q] * vv[q];
+        s[5] += vl[i] * vl[i];
       }
     }
-    __syncthreads();
     for (int j = t; j < n; j += kBT) {
-      const double val = colacc[j];
+      const double val = cs[j];
       W.f3[j] = val;
       s[2] += val * val;
-      s[3] += x[j] * x[j];
+      s[3] += xl[j] * xl[j];
     }
     wg_sum6(s, L.dred);
   };
@@ -1447,61 +1501,49 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     for (int i = t; i < p; i += kBT) y[i] += (double)G[p - 1 - i];
     __syncthreads();
   };
-  // f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z (FP64), one pass over W
-  // and V: wave w owns the 64-row blocks w, w + 4, ... (row sums in
-  // registers); the column sums are added up across the waves in LDS.
-  const auto rsA = rsrc((const double*)A, ((size_t)(m - 1) * P.lda + n) * sizeof(double));
-  const auto rsB = rsrc((const double*)B, ((size_t)(p - 1) * P.ldb + n) * sizeof(double));
+  // f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z (FP64): one pass over W
+  // and one over V (row sums per thread, column sums through LDS)
   auto residual = [&](double s[6]) {
-    double* colacc = (double*)L.u.vec[0];               // [0:m) W^T z, [m:m+p) V^T z
-    for (int j = t; j < m + p; j += kBT) colacc[j] = 0.0;
-    double rs_[kRQ], zz[kRQ];
-#pragma unroll
-    for (int q = 0; q < kRQ; ++q) {
-      const int i = lane + 64 * (w + kBW * q);
-      rs_[q] = 0.0;
-      zz[q] = i < n ? W.z[i] : 0.0;
+    double* cw = L.dvec(0);                             // W^T z
+    double* cv = L.dvec(1);                             // V^T z
+    double* zl = L.dvec(2);
+    double* xy = L.dvec(3);                             // x, then y
+    for (int j = t; j < m; j += kBT) {
+      cw[j] = 0.0;
+      xy[j] = x[j];
     }
+    for (int j = t; j < p; j += kBT) cv[j] = 0.0;
+    for (int i = t; i < n; i += kBT) zl[i] = W.z[i];
     __syncthreads();
-#pragma unroll 4
-    for (int j = 0; j < m + p; ++j) {
-      const bool isw = j < m;
-      const double cj = isw ? x[j] : y[j - m];
-      double cs = 0.0;
-#pragma unroll
-      for (int q = 0; q < kRQ; ++q) {
-        const int i = lane + 64 * (w + kBW * q);
-        const double a = isw ? bload<double>(rsA, i < n ? (uint32_t)((i + (size_t)j * P.lda) * 8) : kOob)
-                             : bload<double>(rsB, i < n ? (uint32_t)((i + (size_t)(j - m) * P.ldb) * 8) : kOob);
-        rs_[q] += a * cj;
-        cs += a * zz[q];
-      }
-      cs = wsum(cs);
-      if (lane == 0) atomicAdd(&colacc[j], cs);
-    }
+    const RowSums wx = wg_resid_pass((const double*)A, P.lda, n, m, xy, zl, cw);
+    __syncthreads();
+    for (int j = t; j < p; j += kBT) xy[j] = y[j];
+    __syncthreads();
+    const RowSums vy = wg_resid_pass((const double*)B, P.ldb, n, p, xy, zl, cv);
+    __syncthreads();
     for (int q = 0; q < 6; ++q) s[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < kRQ; ++q) {
-      const int i = lane + 64 * (w + kBW * q);
+      const int i = t + kBT * q;
       if (i < n) {
-        const double val = dvec[i] - rs_[q];
+        const double val = dvec[i] - wx.v[q] - vy.v[q];
         W.f2[i] = val;
         s[1] += val * val;
-        s[5] += zz[q] * zz[q];
+        s[5] += zl[i] * zl[i];
       }
     }
-    __syncthreads();
     for (int j = t; j < m; j += kBT) {
-      const double val = colacc[j];
+      const double val = cw[j];
       W.f3[j] = val;
       s[2] += val * val;
       s[3] += x[j] * x[j];
     }
     for (int j = t; j < p; j += kBT) {
-      const double val = -y[j] + colacc[m + j];
+      const double yj = xy[j];
+      const double val = -yj + cv[j];
       W.f1[j] = val;
       s[0] += val * val;
-      s[4] += y[j] * y[j];
+      s[4] += yj * yj;
     }
     wg_sum6(s, L.dred);
   };

@@ -758,8 +758,8 @@ __device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, co
 // y (LDS, length r) <- Q^T y (trans) or Q y, Q = H_0 ... H_{k-1} from the
 // reflectors of M (ld) and the panels' T (NB x NB, row-major, at Tst; the
 // panel's product is I - Y T Y^T), one panel at a time: z = Y^T y by a wave
-// reduce-scatter and LDS, w = T^T z (T z) by NB threads, y -= Y w.  In FP32
-// the next panel's columns load while the current one is reduced.
+// reduce-scatter and LDS, w = T^T z (T z) on NB lanes of each wave, y -= Y w.
+// In FP32 the next panel's columns load while the current one is reduced.
 template <typename T>
 __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
                                                  const LSQ_GLB T* Tstg, LSQ_LDS T* yl,
@@ -785,10 +785,11 @@ __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, in
     const bool act = g0 + 3 >= j0 && g0 < r;
 #pragma unroll
     for (int c = 0; c < NB; ++c) load_rows4(rs, act, (uint32_t)((g0 + (size_t)c * ld) * sizeof(T)), Yv[c]);
-    // thread t < NB: column t of T (w = T^T z) or row t (w = T z)
-    const LSQ_GLB T* Tp = Tst + (size_t)panel(b) * NB * NB;
+    // lane c < NB of every wave: column c of T (w = T^T z) or row c (w = T z)
+    const auto rt = rsrc((const T*)Tst + (size_t)panel(b) * NB * NB, NB * NB * sizeof(T));
 #pragma unroll
-    for (int i = 0; i < NB; ++i) Tv[i] = (t < NB && i < nbj) ? (trans ? Tp[i * NB + t] : Tp[t * NB + i]) : (T)0;
+    for (int i = 0; i < NB; ++i)
+      Tv[i] = bload<T>(rt, (lane < NB && i < nbj) ? (uint32_t)((trans ? i * NB + lane : lane * NB + i) * sizeof(T)) : kOob);
   };
   auto step = [&](int b, T (&Yv)[NB][4], T (&Tv)[NB], T (&Yn)[NB][4], T (&Tn)[NB]) {
     const int j0 = panel(b) * NB, nbj = k - j0 < NB ? k - j0 : NB;
@@ -808,21 +809,21 @@ __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, in
       if (b + 1 < np) load(b + 1, Yn, Tn);
     }
     const T zc = wave_reduce_scatter<T, NB>(pz);    // lanes 4c .. 4c + 3: the wave's z_c
-    if ((lane & 3) == 0) red[w * NB + (lane >> 2)] = zc;
+    // the four waves' partials meet in LDS (two buffers by panel parity, so
+    // one barrier per panel suffices); every wave then forms w on its lanes
+    // 0 .. NB - 1 and broadcasts it with readlanes
+    LSQ_LDS T* buf = red + (b & 1) * kBW * NB;
+    if ((lane & 3) == 0) buf[w * NB + (lane >> 2)] = zc;
     __syncthreads();
-    if (t < NB) {
-      T acc = 0;
+    T acc = 0;
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        const T zi = (red[i] + red[NB + i]) + (red[2 * NB + i] + red[3 * NB + i]);
-        acc += Tv[i] * zi;
-      }
-      red[kBW * NB + t] = acc;
+    for (int i = 0; i < NB; ++i) {
+      const T zi = (buf[i] + buf[NB + i]) + (buf[2 * NB + i] + buf[3 * NB + i]);
+      acc += Tv[i] * zi;
     }
-    __syncthreads();
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
-      const T wc = red[kBW * NB + c];
+      const T wc = lane_val(acc, c);
 #pragma unroll
       for (int e = 0; e < 4; ++e) yv[e] -= Yv[c][e] * wc;
     }
@@ -855,19 +856,20 @@ __device__ __forceinline__ void wg_apply_q_vec(const T* M, int ld, int r, int k,
 }
 
 // y (LDS, length nn) <- U^{-1} y (TRANS = false) or U^{-T} y, U the upper
-// triangle of M[0:nn, 0:nn] (ld), in blocks of 16: lanes 0 .. 15 of wave 0
-// solve the diagonal block (lane i holds row i of it, or column i for U^T;
-// a partial last block is padded with the identity), then every thread
-// subtracts the block's contribution from its unsolved rows.  The update's
-// columns load before the diagonal solve.  A zero pivot gives a non-finite
-// result, which the stop test reports.
+// triangle of M[0:nn, 0:nn] (ld), in blocks of 16 rows.  The wave that owns
+// a block's rows (thread t holds rows 4t .. 4t + 3) solves its diagonal block
+// on lanes 0 .. 15 (lane i holds row i of it, or column i for U^T; a partial
+// last block is padded with the identity) right after its own update, then
+// every thread subtracts the block's contribution from its unsolved rows: one
+// barrier per block.  The update's columns load before the diagonal solve.  A
+// zero pivot gives a non-finite result, which the stop test reports.
 template <typename T, bool TRANS>
 __device__ __noinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
   constexpr int NB = 16;
   const T* M = (const T*)uni(Mg);
   LSQ_LDS T* y = uni(yl);
   ld = uni(ld); nn = uni(nn);
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g0 = 4 * t;
+  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), g0 = 4 * t;
   const int nbk = (nn + NB - 1) / NB;
   for (int b = 0; b < nbk; ++b) {
     const int j0 = (TRANS ? b : nbk - 1 - b) * NB, nbj = nn - j0 < NB ? nn - j0 : NB;
@@ -893,8 +895,7 @@ __device__ __noinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int n
         }
       }
     }
-    if (w == 0) {
-      // lane i < nbj: row i (U) or column i (U^T) of the block; identity beyond
+    if (w == j0 / (4 * 64)) {                     // the block's rows are this wave's
       const auto rd = rsrc(M + j0 + (size_t)j0 * ld, ((size_t)(nbj - 1) * ld + nbj) * sizeof(T));
       T ud[NB];
 #pragma unroll
@@ -927,8 +928,8 @@ __device__ __noinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int n
         y[g0 + e] -= acc;
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 template <typename T>

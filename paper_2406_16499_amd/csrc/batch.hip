@@ -760,10 +760,11 @@ __device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, co
 // panel's product is I - Y T Y^T), one panel at a time: z = Y^T y by a wave
 // reduce-scatter and LDS, w = T^T z (T z) on NB lanes of each wave, y -= Y w.
 // In FP32 the next panel's columns load while the current one is reduced.
-template <typename T>
+template <typename T, bool TRANS>
 __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
                                                  const LSQ_GLB T* Tstg, LSQ_LDS T* yl,
-                                                 LSQ_LDS T* redl, bool trans) {
+                                                 LSQ_LDS T* redl) {
+  constexpr bool trans = TRANS;
   constexpr int NB = QrCfg<T>::NB;
   static_assert(NB == 16 && kBT * 4 == kBatchMaxDim, "thread t owns rows 4t .. 4t + 3");
   constexpr bool PF = sizeof(T) == 4;
@@ -772,24 +773,26 @@ __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, in
   LSQ_LDS T* y = uni(yl);
   LSQ_LDS T* red = uni(redl);
   ld = uni(ld); r = uni(r); k = uni(k);
-  trans = uni((int)trans) != 0;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, g0 = 4 * t;
   const int np = (k + NB - 1) / NB;
   T yv[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) yv[e] = g0 + e < r ? y[g0 + e] : (T)0;
   auto panel = [&](int b) { return trans ? b : np - 1 - b; };
+  // (b >= np loads nothing: every offset is out of range; it keeps the
+  // prefetch unconditional, so the compiler waits only for the panel in use)
   auto load = [&](int b, T (&Yv)[NB][4], T (&Tv)[NB]) {
-    const int j0 = panel(b) * NB, nbj = k - j0 < NB ? k - j0 : NB;
+    const bool valid = b < np;
+    const int j0 = valid ? panel(b) * NB : 0, nbj = valid ? (k - j0 < NB ? k - j0 : NB) : 1;
     const auto rs = rsrc(M + (size_t)j0 * ld, (size_t)nbj * ld * sizeof(T));
-    const bool act = g0 + 3 >= j0 && g0 < r;
+    const bool act = valid & (g0 + 3 >= j0) & (g0 < r);   // (no short-circuit branches)
 #pragma unroll
     for (int c = 0; c < NB; ++c) load_rows4(rs, act, (uint32_t)((g0 + (size_t)c * ld) * sizeof(T)), Yv[c]);
     // lane c < NB of every wave: column c of T (w = T^T z) or row c (w = T z)
-    const auto rt = rsrc((const T*)Tst + (size_t)panel(b) * NB * NB, NB * NB * sizeof(T));
+    const auto rt = rsrc((const T*)Tst + (size_t)(j0 / NB) * NB * NB, NB * NB * sizeof(T));
 #pragma unroll
     for (int i = 0; i < NB; ++i)
-      Tv[i] = bload<T>(rt, (lane < NB && i < nbj) ? (uint32_t)((trans ? i * NB + lane : lane * NB + i) * sizeof(T)) : kOob);
+      Tv[i] = bload<T>(rt, (valid & (lane < NB) & (i < nbj)) ? (uint32_t)((trans ? i * NB + lane : lane * NB + i) * sizeof(T)) : kOob);
   };
   auto step = [&](int b, T (&Yv)[NB][4], T (&Tv)[NB], T (&Yn)[NB][4], T (&Tn)[NB]) {
     const int j0 = panel(b) * NB, nbj = k - j0 < NB ? k - j0 : NB;
@@ -806,7 +809,8 @@ __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, in
 #pragma unroll
     for (int c = 0; c < NB; ++c) pz[c] = (Yv[c][0] * yv[0] + Yv[c][1] * yv[1]) + (Yv[c][2] * yv[2] + Yv[c][3] * yv[3]);
     if constexpr (PF) {
-      if (b + 1 < np) load(b + 1, Yn, Tn);
+      load(b + 1, Yn, Tn);
+      __builtin_amdgcn_sched_barrier(0);
     }
     const T zc = wave_reduce_scatter<T, NB>(pz);    // lanes 4c .. 4c + 3: the wave's z_c
     // the four waves' partials meet in LDS (two buffers by panel parity, so
@@ -851,8 +855,12 @@ __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, in
 template <typename T>
 __device__ __forceinline__ void wg_apply_q_vec(const T* M, int ld, int r, int k, const T* Tst, T* y,
                                                T* red, bool trans) {
-  wg_apply_q_vec_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_LDS T*)y,
-                         (LSQ_LDS T*)red, trans);
+  if (trans)
+    wg_apply_q_vec_impl<T, true>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_LDS T*)y,
+                                 (LSQ_LDS T*)red);
+  else
+    wg_apply_q_vec_impl<T, false>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_LDS T*)y,
+                                  (LSQ_LDS T*)red);
 }
 
 // y (LDS, length nn) <- U^{-1} y (TRANS = false) or U^{-T} y, U the upper

@@ -923,6 +923,61 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
   std::vector<BatchOut> hout(count);
   std::vector<int> attempts(count, 0);
   int prec = first_prec;
+  auto certified = [&](int q, int rung, const BatchOut& bo) {
+    if (!res) return;
+    lsq_result& r = res[todo[q]];
+    r = lsq_result{};
+    r.info = 0;
+    r.prec_used = rung;
+    r.solver_used = rung == LSQ_PREC_FP64 ? LSQ_SOLVER_DIRECT : LSQ_SOLVER_IR;
+    r.attempts = attempts[q];
+    r.ir_steps = bo.steps;
+    for (int k = 0; k < 3; ++k) r.berr[k] = bo.berr[k];
+    r.berr_max = bo.berr_max;
+  };
+  if (prec == LSQ_PREC_FP32 && o.escalate && ctx.side) {
+    // FP32 launch with the FP64 rung running beside it: each failure is
+    // queued on the device and solved in FP64 while the FP32 launch goes on;
+    // what no consumer took (see batch_launch_escalating) falls through to
+    // the FP64 launch below
+    const int n = (int)cur.size();
+    EscQueue* q = static_cast<EscQueue*>(ctx.ws->alloc(esc_queue_bytes(count)));
+    BatchOut* dout64 = ctx.ws->get<BatchOut>(count);
+    // a quarter of the compute units run the FP64 rung from the start (about
+    // the share of the FP64 work in the mixed batch); the rest join when
+    // the FP32 launch is over
+    const int cu64 = std::max(1, h->num_cu / 4);
+    const int g32 = std::min(batch_blocks_per_cu(4) * (h->num_cu - cu64), n);
+    const int g64a = std::min(batch_blocks_per_cu(8) * cu64, n);
+    const int g64b = std::min(batch_blocks_per_cu(8) * (h->num_cu - cu64), n);
+    char* dws64 = static_cast<char*>(ctx.ws->alloc(stride * (size_t)(g64a + g64b)));
+    LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx.stream));
+    double flops = 0.0;
+    for (int qq : cur) flops += batch_factor_flops(hp[qq]);
+    int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
+    batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
+                            o.tol, o.maxit, dout, dout64, flops, 50.0, started, n / 4);
+    std::vector<BatchOut> hout64(count);
+    LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
+    LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
+    LSQ_HIP(hipStreamSynchronize(ctx.stream));
+    std::vector<int> pending;
+    for (int qq : cur) {
+      ++attempts[qq];
+      if (hout[qq].info == 0) {
+        certified(qq, LSQ_PREC_FP32, hout[qq]);
+      } else if (hout64[qq].info == -1) {
+        pending.push_back(qq);
+      } else {
+        ++attempts[qq];
+        if (hout64[qq].info == 0) certified(qq, LSQ_PREC_FP64, hout64[qq]);
+        else rest.push_back(todo[qq]);
+      }
+    }
+    if (pending.empty()) return rest;
+    cur = pending;
+    prec = LSQ_PREC_FP64;
+  }
   for (;;) {
     LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * cur.size(), hipMemcpyHostToDevice, ctx.stream));
     double flops = 0.0;
@@ -942,17 +997,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
         failed.push_back(q);
         continue;
       }
-      if (res) {
-        lsq_result& r = res[todo[q]];
-        r = lsq_result{};
-        r.info = 0;
-        r.prec_used = prec;
-        r.solver_used = prec == LSQ_PREC_FP64 ? LSQ_SOLVER_DIRECT : LSQ_SOLVER_IR;
-        r.attempts = attempts[q];
-        r.ir_steps = bo.steps;
-        for (int k = 0; k < 3; ++k) r.berr[k] = bo.berr[k];
-        r.berr_max = bo.berr_max;
-      }
+      certified(q, prec, bo);
     }
     if (failed.empty() || prec == LSQ_PREC_FP64 || !o.escalate) {
       for (int q : failed) rest.push_back(todo[q]);

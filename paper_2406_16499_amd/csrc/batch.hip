@@ -19,6 +19,9 @@
 // are applied one panel at a time through the stored T blocks, and the
 // triangular solves go in 16-row blocks (one wave solves the diagonal block,
 // every thread updates its rows).
+#include <chrono>
+#include <stdexcept>
+#include <thread>
 #include <type_traits>
 
 #include "engine.hpp"
@@ -1564,7 +1567,8 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
                                                   size_t ws_stride, double tol, int maxit,
-                                                  int fast_exit, BatchOut* __restrict__ out) {
+                                                  int fast_exit, BatchOut* __restrict__ out,
+                                                  EscQueue* __restrict__ esc, int esc_big) {
   __shared__ BLds<T> L;
   char* mine = ws + (size_t)blockIdx.x * ws_stride;
   for (;;) {
@@ -1577,6 +1581,91 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
     const BatchProb P = probs[idx];
     if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, fast_exit != 0, out + idx, L);
     else gls_instance<T>(P, mine, tol, maxit, fast_exit != 0, out + idx, L);
+    __syncthreads();
+    if (esc && threadIdx.x == 0) {
+      // a failure goes to the FP64 launch beside this one: claim a slot,
+      // write the instance, then publish it; the first esc_big instances of
+      // the order (the longest) use their own queue, which the consumers
+      // drain first.  Every instance counts as done.
+      if (out[idx].info != 0) {
+        const int qi = q < esc_big ? 1 : 0;
+        int* slot = reinterpret_cast<int*>(esc + 1) + 2 * count * qi;
+        int* ready = slot + count;
+        const int pos = __hip_atomic_fetch_add(&esc->tail[qi], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        slot[pos] = idx;
+        __hip_atomic_store(&ready[pos], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __hip_atomic_fetch_add(&esc->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// FP64 consumer of the escalation queue.  Thread 0 claims the next published
+// slot; with the queue empty it sleeps until the FP32 launch has finished
+// every instance (then leaves once the queue is drained) or until spin_ticks
+// of the wall clock pass without a slot, when it leaves as well: the host
+// solves whatever was not taken.  No work-group ever waits on another
+// without that bound.
+__global__ __launch_bounds__(kBT, QrCfg<double>::BLOCKS) void k_batch_esc(
+    const BatchProb* __restrict__ probs, int count, EscQueue* __restrict__ esc,
+    char* __restrict__ ws, size_t ws_stride, double tol, int maxit, BatchOut* __restrict__ out,
+    unsigned long long spin_ticks, int* started) {
+  __shared__ BLds<double> L;
+  char* mine = ws + (size_t)blockIdx.x * ws_stride;
+  // residency count for the host (pinned memory), which holds the FP32
+  // launch back until the consumers own their compute units
+  if (started && threadIdx.x == 0) __hip_atomic_fetch_add(started, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  // claims the next published slot of queue qi: 1 claimed (item set, -1 if
+  // its producer never published within the bound), 0 empty, -1 lost a race
+  auto claim = [&](int qi, unsigned long long t0, int& item) {
+    int* slot = reinterpret_cast<int*>(esc + 1) + 2 * count * qi;
+    int* ready = slot + count;
+    const int h = __hip_atomic_load(&esc->head[qi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int t = __hip_atomic_load(&esc->tail[qi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (h >= t) return 0;
+    int expect = h;
+    if (!__hip_atomic_compare_exchange_strong(&esc->head[qi], &expect, h + 1, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return -1;
+    // the producer publishes right after claiming the slot
+    while (!__hip_atomic_load(&ready[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) &&
+           wall_clock64() - t0 < spin_ticks)
+      __builtin_amdgcn_s_sleep(8);
+    item = __hip_atomic_load(&ready[h], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ? slot[h] : -1;
+    return 1;
+  };
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int item = -1;
+      const unsigned long long t0 = wall_clock64();
+      for (;;) {
+        const int cb = claim(1, t0, item);
+        if (cb > 0) break;
+        if (cb < 0) continue;
+        const int cs = claim(0, t0, item);
+        if (cs > 0) break;
+        if (cs < 0) continue;
+        if (__hip_atomic_load(&esc->done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= count) {
+          // every FP32 instance is finished: leave once both queues are drained
+          bool empty = true;
+          for (int qi = 0; qi < 2; ++qi)
+            empty = empty && __hip_atomic_load(&esc->tail[qi], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <=
+                                 __hip_atomic_load(&esc->head[qi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (empty) break;
+          continue;
+        }
+        if (wall_clock64() - t0 >= spin_ticks) break;
+        __builtin_amdgcn_s_sleep(32);
+      }
+      L.next = item;
+    }
+    __syncthreads();
+    const int idx = uni(L.next);
+    __syncthreads();
+    if (idx < 0) break;
+    const BatchProb P = probs[idx];
+    if (P.type == 0) lse_instance<double>(P, mine, tol, maxit, false, out + idx, L);
+    else gls_instance<double>(P, mine, tol, maxit, false, out + idx, L);
     __syncthreads();
   }
 }
@@ -1623,12 +1712,58 @@ void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, in
   ktimer_begin(ctx, kind, flops, 0.0);
   if (tw == 8)
     hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out);
+                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out, nullptr, 0);
   else
     hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out);
+                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out, nullptr, 0);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kind);
+}
+
+size_t esc_queue_bytes(int count) { return sizeof(EscQueue) + 4 * sizeof(int) * (size_t)(count > 0 ? count : 0); }
+
+void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
+                             int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
+                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit,
+                             BatchOut* out, BatchOut* out64, double flops, double spin_ms,
+                             int* started, int big_count) {
+  if (count <= 0 || grid <= 0) return;
+  if (!ctx.side || grid64a <= 0) throw std::runtime_error("batch_launch_escalating: no side stream");
+  LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
+  LSQ_HIP(hipMemsetAsync(q, 0, esc_queue_bytes(count), ctx.stream));
+  LSQ_HIP(hipMemsetAsync(out64, 0xff, sizeof(BatchOut) * (size_t)count, ctx.stream));   // info = -1
+  hipEvent_t ready = ctx_event(ctx, 0), joined = ctx_event(ctx, 1);
+  LSQ_HIP(hipEventRecord(ready, ctx.stream));
+  const unsigned long long ticks = (unsigned long long)(spin_ms * 1e5);   // 100 MHz wall clock
+  // consumers on the compute units the FP32 grid leaves free, from the start
+  LSQ_HIP(hipStreamWaitEvent(ctx.side, ready, 0));
+  if (started) __atomic_store_n(started, 0, __ATOMIC_RELEASE);
+  hipLaunchKernelGGL(k_batch_esc, dim3(grid64a), dim3(kBT), 0, ctx.side, probs, count, q, ws64,
+                     ws_stride, tol, maxit, out64, ticks, started);
+  LSQ_LAUNCH_CHECK();
+  LSQ_HIP(hipEventRecord(joined, ctx.side));
+  if (started) {
+    // the work-groups of two launches are placed in no fixed order: the FP32
+    // grid would spread over every compute unit and leave none whole for a
+    // consumer, so it waits (at most 20 ms) until the consumers are resident
+    const auto t0 = std::chrono::steady_clock::now();
+    while (__atomic_load_n(started, __ATOMIC_ACQUIRE) < grid64a &&
+           std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(20))
+      std::this_thread::yield();
+  }
+  ktimer_begin(ctx, kKBatch32, flops, 0.0);
+  hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                     counter, ws, ws_stride, tol, maxit, 1, out, q, big_count);
+  LSQ_LAUNCH_CHECK();
+  ktimer_end(ctx, kKBatch32);
+  // more consumers once the FP32 launch is over, for what is still queued
+  if (grid64b > 0) {
+    hipLaunchKernelGGL(k_batch_esc, dim3(grid64b), dim3(kBT), 0, ctx.stream, probs, count, q,
+                       ws64 + (size_t)grid64a * ws_stride, ws_stride, tol, maxit, out64, ticks,
+                       nullptr);
+    LSQ_LAUNCH_CHECK();
+  }
+  LSQ_HIP(hipStreamWaitEvent(ctx.stream, joined, 0));
 }
 
 }  // namespace lsq

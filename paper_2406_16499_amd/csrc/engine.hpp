@@ -246,4 +246,31 @@ void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, in
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
                   bool fast_exit, BatchOut* out, double flops);
 
+// Escalation queues of the concurrent FP32 -> FP64 batch: the FP32 launch
+// appends each instance that fails to queue 1 if it is among the first
+// big_count of the order (the longest), else to queue 0, and counts every
+// finished instance in done; an FP64 launch on the side stream takes slots
+// from the heads, queue 1 first.  Device layout: this header, then per queue
+// int slot[count], int ready[count] (all zero before the launches).
+struct EscQueue {
+  int tail[2], head[2], done, pad[3];
+};
+size_t esc_queue_bytes(int count);
+// FP32 launch of `grid` work-groups over order[0:count) (as batch_launch,
+// tw = 4, fast exit on) that pushes its failures to q; beside it on ctx.side
+// an FP64 launch of grid64a work-groups, on the compute units the FP32 grid
+// leaves free, solves the queued instances into out64 as they arrive, and
+// grid64b more join after the FP32 launch (workspace ws64: grid64a +
+// grid64b slots).  out64.info = -1 where an instance was not taken: a
+// consumer that finds the queue empty for spin_ms while the FP32 launch is
+// still running leaves, and the host runs what is left.  started (pinned
+// host int, nullable): the consumers count themselves there and the FP32
+// launch waits up to 20 ms for all grid64a of them.  big_count: see
+// EscQueue.  ctx.stream waits for all three launches.
+void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
+                             int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
+                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit,
+                             BatchOut* out, BatchOut* out64, double flops, double spin_ms,
+                             int* started, int big_count);
+
 }  // namespace lsq

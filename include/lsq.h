@@ -154,8 +154,13 @@ typedef struct {
      factors the pair (Section 3) and runs classical refinement (Algorithms 2
      and 4) entirely on the device: FP32 factors and corrections first, the
      instances that do not meet tol again with FP64 factors (reported as
-     FP64 direct) when opts.escalate is set.  Instances that are not eligible
-     or still fail continue on the batch workers below, with the full ladder.
+     FP64 direct) when opts.escalate is set.  The FP64 rung runs beside the
+     FP32 launch: each instance that fails is queued on the device (the
+     longest first) and solved in FP64 by work-groups on a quarter of the
+     compute units while the FP32 launch goes on (the rest join when it ends).
+     LSQ_BATCH_SEQUENTIAL runs the FP64 rung as a second launch after the
+     FP32 one instead.  Instances that are not eligible or still fail
+     continue on the batch workers below, with the full ladder.
    - batch workers (LSQ_BATCH_WORKERS, and every other option): the instances
      run concurrently on the handle's batch workers (streams of their own, one
      host thread each; see lsq_set_batch_workers), longest estimated
@@ -188,7 +193,7 @@ int lsq_selector_features(lsq_handle handle, const lsq_problem* problem, float* 
 int lsq_set_batch_workers(lsq_handle handle, int workers);
 /* Execution of the batched entry points (see lsq_solve_batched).  Returns -2
    for an unknown mode. */
-enum { LSQ_BATCH_AUTO = 0, LSQ_BATCH_WORKERS = 1 };
+enum { LSQ_BATCH_AUTO = 0, LSQ_BATCH_WORKERS = 1, LSQ_BATCH_SEQUENTIAL = 2 };
 int lsq_set_batch_mode(lsq_handle handle, int mode);
 
 /* Same-type conveniences: every descriptor must carry the matching type. */

@@ -102,6 +102,14 @@ int lsq_dbg_timer_read(lsq_handle h, double* total_ms, int* launches, double* fl
  * pointer with bytes > 0. */
 int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes);
 
+/* Bound (ms, default 50) on how long an FP64 work-group of the concurrent
+   persistent batch waits for the FP32 launch to queue an instance; past it
+   the work-group leaves, and the FP64 work-groups launched after the FP32
+   launch (then the host, for anything still queued) solve the rest.  0 makes
+   the early work-groups leave as soon as the queue is empty.  Returns -2
+   outside [0, 1000]. */
+int lsq_dbg_batch_wait(lsq_handle h, double ms);
+
 /* Text of the last error recorded on the handle ("" if none). */
 const char* lsq_last_error(lsq_handle h);
 

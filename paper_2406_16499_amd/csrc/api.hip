@@ -167,6 +167,7 @@ struct lsq_handle_st {
   std::vector<std::unique_ptr<Worker>> pool;    // batched workers
   int batch_workers = 8;
   int batch_mode = LSQ_BATCH_AUTO;
+  double esc_wait_ms = 50.0;                    // bound on an FP64 consumer's wait (concurrent batch)
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
   std::string last_error;
@@ -935,7 +936,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     for (int k = 0; k < 3; ++k) r.berr[k] = bo.berr[k];
     r.berr_max = bo.berr_max;
   };
-  if (prec == LSQ_PREC_FP32 && o.escalate && ctx.side) {
+  if (prec == LSQ_PREC_FP32 && o.escalate && ctx.side && h->batch_mode == LSQ_BATCH_AUTO) {
     // FP32 launch with the FP64 rung running beside it: each failure is
     // queued on the device and solved in FP64 while the FP32 launch goes on;
     // what no consumer took (see batch_launch_escalating) falls through to
@@ -956,7 +957,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     for (int qq : cur) flops += batch_factor_flops(hp[qq]);
     int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
     batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
-                            o.tol, o.maxit, dout, dout64, flops, 50.0, started, n / 4);
+                            o.tol, o.maxit, dout, dout64, flops, h->esc_wait_ms, started, n / 4);
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
@@ -1078,8 +1079,16 @@ int lsq_set_batch_workers(lsq_handle h, int workers) {
 
 int lsq_set_batch_mode(lsq_handle h, int mode) {
   if (!h) return -1;
-  if (mode != LSQ_BATCH_AUTO && mode != LSQ_BATCH_WORKERS) return fail(h, -2, "unknown batch mode");
+  if (mode != LSQ_BATCH_AUTO && mode != LSQ_BATCH_WORKERS && mode != LSQ_BATCH_SEQUENTIAL)
+    return fail(h, -2, "unknown batch mode");
   h->batch_mode = mode;
+  return 0;
+}
+
+int lsq_dbg_batch_wait(lsq_handle h, double ms) {
+  if (!h) return -1;
+  if (!(ms >= 0.0 && ms <= 1000.0)) return fail(h, -2, "wait bound outside [0, 1000] ms");
+  h->esc_wait_ms = ms;
   return 0;
 }
 
@@ -1283,7 +1292,7 @@ int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const l
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
   const bool persistent =
-      h->batch_mode == LSQ_BATCH_AUTO &&
+      (h->batch_mode == LSQ_BATCH_AUTO || h->batch_mode == LSQ_BATCH_SEQUENTIAL) &&
       (o.solver == LSQ_SOLVER_AUTO || o.solver == LSQ_SOLVER_IR || o.solver == LSQ_SOLVER_DIRECT) &&
       (o.prec == LSQ_PREC_FP32 || o.prec == LSQ_PREC_FP64 || (o.prec == LSQ_PREC_AUTO && !h->sel_w));
   if (persistent) {

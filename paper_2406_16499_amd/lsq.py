@@ -95,6 +95,7 @@ _SIGS = {
     "lsq_dbg_timer_read": (c_int, [_P, ctypes.POINTER(c_double), ctypes.POINTER(c_int),
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     "lsq_dbg_copy": (c_int, [_P, _P, _P, ctypes.c_longlong]),
+    "lsq_dbg_batch_wait": (c_int, [_P, ctypes.c_double]),
     "lsq_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -271,11 +272,19 @@ class Handle:
         return rc, list(res)
 
     def set_batch_mode(self, mode: str) -> None:
-        """"persistent" (default: one work-group per eligible instance) or
-        "workers" (concurrent per-instance solves)."""
-        rc = self.lib.lsq_set_batch_mode(self.h, {"persistent": 0, "workers": 1}[mode])
+        """"persistent" (default: one work-group per eligible instance, the
+        FP64 rung beside the FP32 launch), "sequential" (persistent, the FP64
+        rung as a second launch) or "workers" (concurrent per-instance
+        solves)."""
+        rc = self.lib.lsq_set_batch_mode(self.h, {"persistent": 0, "workers": 1, "sequential": 2}[mode])
         if rc != 0:
             raise RuntimeError(f"lsq_set_batch_mode = {rc}")
+
+    def dbg_batch_wait(self, ms: float) -> None:
+        """Bound on an FP64 consumer's wait in the concurrent persistent batch."""
+        rc = self.lib.lsq_dbg_batch_wait(self.h, float(ms))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_batch_wait = {rc}: {self.last_error()}")
 
     # ---------------------------------------------------------- debug --
     def dbg_bd_apply(self, kind, prec, A, B, alpha, beta, u):

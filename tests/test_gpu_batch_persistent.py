@@ -196,3 +196,46 @@ def test_persistent_workspace_reuse_smaller_second_batch(h):
         assert rc == 0, (rc, h.last_error())
         for P, (x, y), r in zip(probs, out, res):
             _check(P, x, y, r)
+
+
+def test_persistent_concurrent_fp64_rung_matches_sequential(h):
+    # the FP64 rung beside the FP32 launch solves the same instances as a
+    # second launch would, with the same kernels: the same rungs, and both
+    # results certified (the residual's column sums are LDS atomics, so two
+    # runs agree to rounding, not bit for bit)
+    note("persistent concurrent vs sequential escalation")
+    probs = list(wl.batch_instances(seed=79, count=30, kappa_max=1e12, m_range=(64, 400)))
+    rc1, res1, out1 = _run(h, probs, prec="fp32", escalate=1)
+    h.set_batch_mode("sequential")
+    try:
+        rc2, res2, out2 = _run(h, probs, prec="fp32", escalate=1)
+    finally:
+        h.set_batch_mode("persistent")
+    assert rc1 == 0 and rc2 == 0
+    assert "fp64" in [r.as_dict()["prec_used"] for r in res1]
+    for P, a, b, r1, r2 in zip(probs, out1, out2, res1, res2):
+        d1, d2 = r1.as_dict(), r2.as_dict()
+        assert (d1["prec_used"], d1["attempts"]) == (d2["prec_used"], d2["attempts"])
+        _check(P, a[0], a[1], r1)
+        _check(P, b[0], b[1], r2)
+
+
+def test_persistent_fp64_rung_after_the_fp32_launch(h):
+    # FP64 work-groups that may not wait leave at once; the work-groups that
+    # follow the FP32 launch solve the queued instances and every instance
+    # certifies
+    note("persistent escalation, early consumers leave at once")
+    probs = list(wl.batch_instances(seed=80, count=20, kappa_max=1e12, m_range=(64, 300)))
+    h.dbg_batch_wait(0.0)
+    try:
+        rc, res, out = _run(h, probs, prec="fp32", escalate=1)
+    finally:
+        h.dbg_batch_wait(50.0)
+    assert rc == 0, (rc, h.last_error())
+    precs = [r.as_dict()["prec_used"] for r in res]
+    assert "fp64" in precs
+    for P, (x, y), r in zip(probs, out, res):
+        _check(P, x, y, r)
+        d = r.as_dict()
+        if d["prec_used"] == "fp64":
+            assert d["solver_used"] == "direct" and d["attempts"] == 2

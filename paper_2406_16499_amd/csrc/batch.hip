@@ -764,7 +764,7 @@ __device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, co
 // reduce-scatter and LDS, w = T^T z (T z) on NB lanes of each wave, y -= Y w.
 // In FP32 the next panel's columns load while the current one is reduced.
 template <typename T, bool TRANS>
-__device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
+__device__ __forceinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
                                                  const LSQ_GLB T* Tstg, LSQ_LDS T* yl,
                                                  LSQ_LDS T* redl) {
   constexpr bool trans = TRANS;
@@ -855,15 +855,30 @@ __device__ __noinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld, in
   __syncthreads();
 }
 
+// Out-of-line copy: the FP32 kernel keeps these steps as calls (its 256
+// registers per lane cannot hold them inline); the FP64 kernel, with twice
+// the register file per wave, inlines them and saves the callee-saved
+// register spills of every call.
+template <typename T, bool TRANS>
+__device__ __noinline__ void wg_apply_q_vec_call(const LSQ_GLB T* Mg, int ld, int r, int k,
+                                                 const LSQ_GLB T* Tstg, LSQ_LDS T* yl,
+                                                 LSQ_LDS T* redl) {
+  wg_apply_q_vec_impl<T, TRANS>(Mg, ld, r, k, Tstg, yl, redl);
+}
 template <typename T>
 __device__ __forceinline__ void wg_apply_q_vec(const T* M, int ld, int r, int k, const T* Tst, T* y,
                                                T* red, bool trans) {
-  if (trans)
-    wg_apply_q_vec_impl<T, true>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_LDS T*)y,
-                                 (LSQ_LDS T*)red);
-  else
-    wg_apply_q_vec_impl<T, false>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_LDS T*)y,
-                                  (LSQ_LDS T*)red);
+  const auto Mg = (const LSQ_GLB T*)M;
+  const auto Tg = (const LSQ_GLB T*)Tst;
+  const auto yl = (LSQ_LDS T*)y;
+  const auto rl = (LSQ_LDS T*)red;
+  if constexpr (sizeof(T) == 4) {
+    if (trans) wg_apply_q_vec_call<T, true>(Mg, ld, r, k, Tg, yl, rl);
+    else wg_apply_q_vec_call<T, false>(Mg, ld, r, k, Tg, yl, rl);
+  } else {
+    if (trans) wg_apply_q_vec_impl<T, true>(Mg, ld, r, k, Tg, yl, rl);
+    else wg_apply_q_vec_impl<T, false>(Mg, ld, r, k, Tg, yl, rl);
+  }
 }
 
 // y (LDS, length nn) <- U^{-1} y (TRANS = false) or U^{-T} y, U the upper
@@ -875,7 +890,7 @@ __device__ __forceinline__ void wg_apply_q_vec(const T* M, int ld, int r, int k,
 // barrier per block.  The update's columns load before the diagonal solve.  A
 // zero pivot gives a non-finite result, which the stop test reports.
 template <typename T, bool TRANS>
-__device__ __noinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
+__device__ __forceinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
   constexpr int NB = 16;
   const T* M = (const T*)uni(Mg);
   LSQ_LDS T* y = uni(yl);
@@ -943,10 +958,21 @@ __device__ __noinline__ void wg_trsv_vec_impl(const LSQ_GLB T* Mg, int ld, int n
   __syncthreads();
 }
 
+template <typename T, bool TRANS>
+__device__ __noinline__ void wg_trsv_vec_call(const LSQ_GLB T* Mg, int ld, int nn, LSQ_LDS T* yl) {
+  wg_trsv_vec_impl<T, TRANS>(Mg, ld, nn, yl);
+}
 template <typename T>
 __device__ __forceinline__ void wg_trsv_vec(const T* M, int ld, int nn, T* y, bool trans) {
-  if (trans) wg_trsv_vec_impl<T, true>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
-  else wg_trsv_vec_impl<T, false>((const LSQ_GLB T*)M, ld, nn, (LSQ_LDS T*)y);
+  const auto Mg = (const LSQ_GLB T*)M;
+  const auto yl = (LSQ_LDS T*)y;
+  if constexpr (sizeof(T) == 4) {
+    if (trans) wg_trsv_vec_call<T, true>(Mg, ld, nn, yl);
+    else wg_trsv_vec_call<T, false>(Mg, ld, nn, yl);
+  } else {
+    if (trans) wg_trsv_vec_impl<T, true>(Mg, ld, nn, yl);
+    else wg_trsv_vec_impl<T, false>(Mg, ld, nn, yl);
+  }
 }
 
 // ------------------------------------------------------------- staging --

@@ -32,7 +32,6 @@ namespace {
 
 constexpr int kBT = 256;                 // threads per work-group
 constexpr int kBW = kBT / 64;            // waves per work-group
-constexpr int kBS = kBatchMaxDim / 64;   // register slots per lane for one vector
 constexpr int kVecs = 9;                 // LDS vectors of length kBatchMaxDim
 constexpr double kMaxPredictedSteps = 6.0;
 constexpr int kRQ = kBatchMaxDim / kBT;  // row slots per thread (rows t + kBT q)
@@ -776,7 +775,7 @@ __device__ __forceinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld,
   LSQ_LDS T* y = uni(yl);
   LSQ_LDS T* red = uni(redl);
   ld = uni(ld); r = uni(r); k = uni(k);
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, g0 = 4 * t;
+  const int t = threadIdx.x, lane = t & 63, w = uni(t >> 6), g0 = 4 * t;
   const int np = (k + NB - 1) / NB;
   T yv[4];
 #pragma unroll
@@ -799,7 +798,9 @@ __device__ __forceinline__ void wg_apply_q_vec_impl(const LSQ_GLB T* Mg, int ld,
   };
   auto step = [&](int b, T (&Yv)[NB][4], T (&Tv)[NB], T (&Yn)[NB][4], T (&Tn)[NB]) {
     const int j0 = panel(b) * NB, nbj = k - j0 < NB ? k - j0 : NB;
-    if (g0 + 3 >= j0 && g0 < j0 + NB) {            // the diagonal block: 1 on it, 0 above
+    // the diagonal block (1 on it, 0 above) lies in the rows of one wave,
+    // which alone takes the (uniform) branch
+    if (w == j0 / (4 * 64)) {
 #pragma unroll
       for (int c = 0; c < NB; ++c)
 #pragma unroll

@@ -22,17 +22,29 @@ template <> struct MmaOf<double> {
   __device__ static int row(int l, int r) { return 4 * r + (l >> 4); }
 };
 
-// Element (i, j) of a masked operand stored column-major.  mask: 0 dense,
-// 1 upper (zero when i + off > j), 2 unit lower (value when i + off > j,
-// 1 on the diagonal, zero above).
+// Buffer loads: an offset past the resource's extent (kOobB) reads zero, so
+// every load can be issued without a branch.
+constexpr uint32_t kOobB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t brsrc(const void* base, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename S> __device__ __forceinline__ S bld(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ float bld<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double bld<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// Element (i, j) of a masked operand, v as loaded from storage.  mask: 0
+// dense, 1 upper (zero when i + off > j), 2 unit lower (value when i + off >
+// j, 1 on the diagonal, zero above).
 template <typename S>
-__device__ __forceinline__ double mload(const S* p, int ld, int i, int j, int mask, int off) {
-  if (mask == 1 && i + off > j) return 0.0;
-  if (mask == 2) {
-    if (i + off < j) return 0.0;
-    if (i + off == j) return 1.0;
-  }
-  return (double)p[(size_t)i + (size_t)j * ld];
+__device__ __forceinline__ double mval(S v, int i, int j, int mask, int off) {
+  double x = (double)v;
+  if (mask == 1) x = (i + off > j) ? 0.0 : x;
+  else if (mask == 2) x = (i + off < j) ? 0.0 : ((i + off == j) ? 1.0 : x);
+  return x;
 }
 
 // C = alpha * op(A) op(B) + beta * C, op(X) = X or X^T; batched over
@@ -74,24 +86,42 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   // The next 32-deep chunk of op(A) and op(B) is fetched into registers while
   // the MFMAs of the current one run.  op(A)(row, kk): storage (row, kk) or
   // (kk, row); the fast index of each thread's elements follows storage rows.
-  double av[8], bv[8];
+  // Buffer loads over each operand's extent: out-of-range elements read as
+  // zero, and the masks are applied to the loaded values.
+  const int ta = g.ta, tb = g.tb, ma = g.ma, mb = g.mb, oa = g.oa, ob = g.ob;
+  const size_t extA = g.k > 0 ? (ta ? (size_t)(g.m - 1) * g.lda + g.k : (size_t)(g.k - 1) * g.lda + g.m) : 1;
+  const size_t extB = g.k > 0 ? (tb ? (size_t)(g.k - 1) * g.ldb + g.n : (size_t)(g.n - 1) * g.ldb + g.k) : 1;
+  const auto rsA = brsrc(A, extA * sizeof(SA));
+  const auto rsB = brsrc(B, extB * sizeof(SB));
+  TC av[8], bv[8];
   auto fetch = [&](int k0) {
+    SA ra[8];
+    SB rb[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = t + 256 * q;
       int row, kk;
-      if (!g.ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
-      int gi = r0 + row, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < g.m && gk < kend) v = g.ta ? mload(A, g.lda, gk, gi, g.ma, g.oa) : mload(A, g.lda, gi, gk, g.ma, g.oa);
-      av[q] = v;
-      int col;
-      if (!g.tb) { kk = e % BK; col = e / BK; } else { col = e & 63; kk = e >> 6; }
-      const int gj = c0 + col;
-      gk = k0 + kk;
-      v = 0.0;
-      if (gj < g.n && gk < kend) v = g.tb ? mload(B, g.ldb, gj, gk, g.mb, g.ob) : mload(B, g.ldb, gk, gj, g.mb, g.ob);
-      bv[q] = v;
+      if (!ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
+      const int gi = r0 + row, gka = k0 + kk;
+      const size_t oa_ = ta ? (size_t)gka + (size_t)gi * g.lda : (size_t)gi + (size_t)gka * g.lda;
+      ra[q] = bld<SA>(rsA, ((gi < g.m) & (gka < kend)) ? (uint32_t)(oa_ * sizeof(SA)) : kOobB);
+      int col, kb;
+      if (!tb) { kb = e % BK; col = e / BK; } else { col = e & 63; kb = e >> 6; }
+      const int gj = c0 + col, gkb = k0 + kb;
+      const size_t ob_ = tb ? (size_t)gj + (size_t)gkb * g.ldb : (size_t)gkb + (size_t)gj * g.ldb;
+      rb[q] = bld<SB>(rsB, ((gj < g.n) & (gkb < kend)) ? (uint32_t)(ob_ * sizeof(SB)) : kOobB);
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = t + 256 * q;
+      int row, kk;
+      if (!ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
+      const int gi = r0 + row, gka = k0 + kk;
+      av[q] = (TC)(ta ? mval(ra[q], gka, gi, ma, oa) : mval(ra[q], gi, gka, ma, oa));
+      int col, kb;
+      if (!tb) { kb = e % BK; col = e / BK; } else { col = e & 63; kb = e >> 6; }
+      const int gj = c0 + col, gkb = k0 + kb;
+      bv[q] = (TC)(tb ? mval(rb[q], gj, gkb, mb, ob) : mval(rb[q], gkb, gj, mb, ob));
     }
   };
   if (kbeg < kend) fetch(kbeg);
@@ -103,8 +133,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       int row, kk, col, kb;
       if (!g.ta) { row = e & 63; kk = e >> 6; } else { kk = e % BK; row = e / BK; }
       if (!g.tb) { kb = e % BK; col = e / BK; } else { col = e & 63; kb = e >> 6; }
-      As[row * LD + kk] = (TC)av[q];
-      Bs[col * LD + kb] = (TC)bv[q];
+      As[row * LD + kk] = av[q];
+      Bs[col * LD + kb] = bv[q];
     }
     __syncthreads();
     if (k0 + BK < kend) fetch(k0 + BK);
@@ -195,7 +225,7 @@ __global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int l
   for (int e = t; e < 4096; e += 512) {
     const int i = e & 63, j = e >> 6;
     double v = 0.0;
-    if (i < ib && j < ib && i <= j) v = mload(U, ldu, i0 + i, i0 + j, mask, 0);
+    if (i < ib && j < ib && i <= j) v = mval(U[(size_t)(i0 + i) + (size_t)(i0 + j) * ldu], i0 + i, i0 + j, mask, 0);
     if (i == j && i >= ib) v = 1.0;
     R[i * kLdt + j] = v;
   }

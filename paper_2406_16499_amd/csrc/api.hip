@@ -727,10 +727,9 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
   const bool reuse = pre && pre->prec_id == prec;
   GlsSolver& sv = reuse ? *pre : local;
   const bool ok_factor = reuse ? pre_ok : gls_prefactor(h, a, prec, o, sv);
-  const int stat_w = ok_factor ? 0 : 1, stat_v = 0;
   const float ms_factor = sv.ms_factor;
   RungOut out;
-  if (stat_w || stat_v) {
+  if (!ok_factor) {
     out.breakdown = true;
     ++attempts;
     solver_used = solvers.empty() ? LSQ_SOLVER_IR : solvers[0];

@@ -59,10 +59,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel", default="panel_final_y", choices=sorted(KERNELS))
-    ap.add_argument("--workload", default="lse-large", choices=["lse-large", "gls-large", "batched"],
+    ap.add_argument("--workload", default="lse-large",
+                    choices=["lse-large", "gls-large", "lse-wide", "gls-tall", "batched"],
                     help="lse-large: the single 4096x2048x256 LSE (default); gls-large: the "
-                         "4096x1024x4096 GLS with GMRES-IR; batched: the 2000-instance mixed "
-                         "LSE/GLS workload")
+                         "4096x1024x4096 GLS with GMRES-IR; lse-wide: LSE 2048x4096x2560 (n > m) "
+                         "with GMRES-IR; gls-tall: GLS 4096x2560x2048 (n > p) with GMRES-IR; "
+                         "batched: the 2000-instance mixed LSE/GLS workload")
     ap.add_argument("--count", type=int, default=2000, help="instances of the batched workload")
     ap.add_argument("--workers", type=int, default=8, help="batch workers (streams)")
     ap.add_argument("--no-workers", action="store_true",
@@ -296,29 +298,52 @@ def batched(args):
 
 GLS_WORKLOAD = ("single GLS d = Wx + Vy: W 4096x1024 N(0,1), V 4096x4096 = U diag(s) V^T "
                 "(s log-spaced 1..1e-6), d N(0,1), seed 3")
+LSE_WIDE_WORKLOAD = ("single LSE with n > m: A 2048x4096 = U diag(s) V^T (s log-spaced 1..1e-4), "
+                     "B 2560x4096 N(0,1), b,d N(0,1), seed 7")
+GLS_TALL_WORKLOAD = ("single GLS with n > p: W 4096x2560 N(0,1), V 4096x2048 = U diag(s) V^T "
+                     "(s log-spaced 1..1e-4), d N(0,1), seed 8")
 
 
-def gls_large(args):
-    """The large GLS: low-precision GQR + GMRES-IR (BD preconditioner) against
-    the FP64 direct path; a solve counts only if it certifies berr <= 1e-14."""
+def single_gmres(args):
+    """One large instance solved by low-precision factorization + GMRES-IR
+    (block-diagonal split preconditioner) against the FP64 direct path; a
+    solve counts only if it certifies berr <= 1e-14.  gls-large: the GLS with
+    n <= p (eq. gls-bdpre-plarge); lse-wide: LSE with n > m
+    (eq. lse-bdpre-nlarge); gls-tall: GLS with n > p (eq. gls-bdpre-nlarge)."""
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl
-    prob = wl.config3()
-    n, m, p = prob.shape
-    W, V, d = (lsq.colmajor(a) for a in (prob.W, prob.V, prob.d))
-    x, y, z = lsq.empty(m), lsq.empty(p), lsq.empty(n)
-    torch.cuda.synchronize()
+    kind = args.workload
     h = lsq.Handle(load_selector=False)
+    if kind == "lse-wide":
+        prob = wl.lse_conditioned(np.random.default_rng(7), 2048, 4096, 2560, 1e4)
+        m, n, p = prob.shape
+        A, B, b, d = (lsq.colmajor(a) for a in (prob.A, prob.B, prob.b, prob.d))
+        x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+        solve = lambda opts: h.lse_solve(A, B, b, d, x, r, v, opts)
+        workload, shape = LSE_WIDE_WORKLOAD, {"m": m, "n": n, "p": p}
+    else:
+        if kind == "gls-tall":
+            prob = wl.gls_conditioned(np.random.default_rng(8), 4096, 2560, 2048, 1e4)
+            workload = GLS_TALL_WORKLOAD
+        else:
+            prob = wl.config3()
+            workload = GLS_WORKLOAD
+        n, m, p = prob.shape
+        W, V, d = (lsq.colmajor(a) for a in (prob.W, prob.V, prob.d))
+        x, y, z = lsq.empty(m), lsq.empty(p), lsq.empty(n)
+        solve = lambda opts: h.gls_solve(W, V, d, x, y, z, opts)
+        shape = {"n": n, "m": m, "p": p}
+    torch.cuda.synchronize()
 
     def run(opts):
         for _ in range(args.warmup):
-            h.gls_solve(W, V, d, x, y, z, opts)
+            solve(opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ok, last = 0, None
         for _ in range(args.steps):
-            rc, res = h.gls_solve(W, V, d, x, y, z, opts)
+            rc, res = solve(opts)
             last = res.as_dict()
             ok += int(rc == 0 and res.berr_max <= 1e-14)
         torch.cuda.synchronize()
@@ -333,7 +358,7 @@ def gls_large(args):
         "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": f"f64 (residuals, GMRES) / {prec} (factorization)", "data": "synthetic",
-        "config": {"workload": GLS_WORKLOAD, "n": n, "m": m, "p": p, "factorization": prec,
+        "config": {"workload": workload, **shape, "factorization": prec,
                    "solver": "GMRES-IR, block-diagonal split preconditioner, restart 30",
                    "tol": 1e-14},
         "fp64_direct": {"value": value64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / args.steps,
@@ -351,8 +376,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         return batched(args)
-    if args.workload == "gls-large":
-        return gls_large(args)
+    if args.workload in ("gls-large", "lse-wide", "gls-tall"):
+        return single_gmres(args)
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl

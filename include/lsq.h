@@ -10,7 +10,9 @@
  * refined on the 3-block augmented system with residuals in FP64 (Section 3),
  * either by classical refinement (Algorithms 2 and 4, correction solvers
  * Algorithms 1 and 3) or by GMRES with the block-diagonal split
- * preconditioner (Section 5).
+ * preconditioners (Section 5: eq. lse-bdpre-mlarge / eq. lse-bdpre-nlarge
+ * for LSE, eq. gls-bdpre-plarge / eq. gls-bdpre-nlarge for GLS, which
+ * together cover every admissible shape).
  *
  * Conventions shared by every entry point
  * ---------------------------------------

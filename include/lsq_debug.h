@@ -62,12 +62,13 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
 
 /* The block-diagonal split-preconditioned operator of GMRES-IR applied to one
  * vector: y = M_l F~ M_r u (FP64 arithmetic) with the factors computed at
- * precision prec.  LSE (type LSQ_LSE, A m x n, B p x n, needs m >= n):
- * eq. lse-bdpre-mlarge, u and y of length m + p + n ordered [r-block;
- * v-block; x-block].  GLS (type LSQ_GLS, A = W n x m, B = V n x p, needs
- * n <= p): eq. gls-bdpre-plarge, length p + n + m ordered [y; z; x].  alpha,
- * beta > 0 are the scalings of the augmented system (Section 5.1).  Returns
- * -4 when the shape condition fails. */
+ * precision prec.  LSE (type LSQ_LSE, A m x n, B p x n): eq. lse-bdpre-mlarge
+ * for m >= n, eq. lse-bdpre-nlarge for n > m; u and y of length m + p + n
+ * ordered [r-block; v-block; x-block].  GLS (type LSQ_GLS, A = W n x m,
+ * B = V n x p): eq. gls-bdpre-plarge for n <= p, eq. gls-bdpre-nlarge for
+ * n > p; length p + n + m ordered [y; z; x].  alpha, beta > 0 are the
+ * scalings of the augmented system (Section 5.1).  Returns -4 when the
+ * problem's shape rule fails (LSE p <= n <= m + p, GLS m <= n <= m + p). */
 int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, const double* A, int lda,
                      const double* B, int ldb, double alpha, double beta, const double* u,
                      double* y);

@@ -10,8 +10,9 @@ This module follows the paper's steps in its order and notation:
   u_f, initial guess, then classical refinement with residuals in FP64 until
   the stopping tests eq. lse-stop / eq. gls-stop hold;
 * GMRES-based refinement (Section 5) with the block-diagonal split
-  preconditioners eq. lse-bdpre-mlarge (LSE, m >= n) and eq. gls-bdpre-plarge
-  (GLS, n <= p) on the scaled systems of eq. lse-limit-notation and
+  preconditioners eq. lse-bdpre-mlarge (LSE, m >= n), eq. lse-bdpre-nlarge
+  (LSE, n > m), eq. gls-bdpre-plarge (GLS, n <= p) and eq. gls-bdpre-nlarge
+  (GLS, n > p) on the scaled systems of eq. lse-limit-notation and
   eq. gls-limit-notation.  GMRES runs in FP64 (Section 6.1).
 
 The low-precision factorization uses LAPACK in the precision of `uf`
@@ -26,6 +27,10 @@ Readings of the paper used in this module:
   Algorithm 3 holds for x2 = -Q h.
 * z0 = Q [0; v] (Algorithm 4, line 3, read with Q instead of Q^H).
 * The default tolerance is 1e-14 and residuals are always formed in FP64.
+* When the initial r (LSE) or y (GLS) is zero, alpha falls back to
+  2^(-1/2) min |diag| of the triangle of the second factorization (T1 for
+  LSE, T2 for GLS), an estimate of the smallest singular value that keeps
+  the scaled system well defined.
 """
 from __future__ import annotations
 
@@ -39,6 +44,7 @@ from . import direct
 
 __all__ = [
     "grq_factors", "gqr_factors", "correction_lse", "correction_gls",
+    "lse_bd_triangles", "gls_bd_triangles",
     "mplse", "mpgls", "bd_operators_lse", "bd_operators_gls", "gmres",
     "mplse_gmres_bd", "mpgls_gmres_bd", "IRResult",
 ]
@@ -311,29 +317,64 @@ def gmres(apply: Callable[[np.ndarray], np.ndarray], rhs: np.ndarray,
 # Block-diagonal split preconditioners (Sections 5.2 and 5.3)
 # --------------------------------------------------------------------------
 
-def bd_operators_lse(A, B, R, T, Q, alpha, beta):
-    """M_l, F~, M_r of eq. lse-bdpre-mlarge (m >= n) as functions on R^(m+p+n).
+def lse_bd_triangles(T, n, p):
+    """U (n x n) and Y (p x p) of the LSE preconditioners, from T (m x n).
 
-    S = T1(n-p+1:n, n-p+1:n) where T = [T1; 0].  Factors are promoted to FP64.
+    m >= n (eq. lse-bdpre-mlarge): U = T1 = T(1:n, 1:n) and Y = S =
+    T1(n-p+1:n, n-p+1:n).  n > m (eq. lse-bdpre-nlarge): T = [T1, T2] and
+    U = [T1, T2; 0, I_(n-m)], Y = [T1(n-p+1:m, n-p+1:m), T2(n-p+1:m, :); 0, I_(n-m)],
+    which is again the trailing p x p block of U.
+    """
+    T = np.asarray(T, np.float64)
+    m = T.shape[0]
+    U = np.zeros((n, n))
+    t = min(m, n)
+    U[:t, :] = T[:t, :n]
+    for i in range(t, n):
+        U[i, i] = 1.0
+    return U, U[n - p:, n - p:]
+
+
+def gls_bd_triangles(T, n, m):
+    """U (n x n) and Y (m x m) of the GLS preconditioners, from T (n x p).
+
+    n <= p (eq. gls-bdpre-plarge): T = [0, T2], U = T2 and Y = S = T2(1:m, 1:m).
+    n > p (eq. gls-bdpre-nlarge): T = [T1; T2] and U = [I_(n-p), T1; 0, T2],
+    Y = [I_(n-p), T1(:, 1:m-n+p); 0, T2(1:m-n+p, 1:m-n+p)], which is again the
+    leading m x m block of U.
+    """
+    T = np.asarray(T, np.float64)
+    p = T.shape[1]
+    U = np.zeros((n, n))
+    if n <= p:
+        U[:, :] = T[:, p - n:]
+    else:
+        U[:, n - p:] = T
+        for i in range(n - p):
+            U[i, i] = 1.0
+    return U, U[:m, :m]
+
+
+def bd_operators_lse(A, B, R, T, Q, alpha, beta):
+    """M_l, F~, M_r of eq. lse-bdpre-mlarge (m >= n) or eq. lse-bdpre-nlarge
+    (n > m) as functions on R^(m+p+n).  Factors are promoted to FP64.
     """
     m, n = A.shape
     p = B.shape[0]
-    assert m >= n, "eq. lse-bdpre-mlarge needs m >= n"
     R = np.asarray(R, np.float64)
-    T1 = np.asarray(T, np.float64)[:n, :n]
+    U, Y = lse_bd_triangles(T, n, p)
     Q = np.asarray(Q, np.float64)
-    S = T1[n - p:, n - p:]
     sa = np.sqrt(alpha)
 
     def Ml(u):
         a, b_, c = u[:m], u[m:m + p], u[m + p:]
-        return np.concatenate([a / sa, S @ _ut(R, b_) / (sa * beta),
-                               sa * _ut(T1, Q @ c, trans=True)])
+        return np.concatenate([a / sa, Y @ _ut(R, b_) / (sa * beta),
+                               sa * _ut(U, Q @ c, trans=True)])
 
     def Mr(u):
         a, b_, c = u[:m], u[m:m + p], u[m + p:]
-        return np.concatenate([a / sa, _ut(R, S.T @ b_, trans=True) / (sa * beta),
-                               sa * (Q.T @ _ut(T1, c))])
+        return np.concatenate([a / sa, _ut(R, Y.T @ b_, trans=True) / (sa * beta),
+                               sa * (Q.T @ _ut(U, c))])
 
     def F(u):
         a, b_, c = u[:m], u[m:m + p], u[m + p:]
@@ -343,28 +384,25 @@ def bd_operators_lse(A, B, R, T, Q, alpha, beta):
 
 
 def bd_operators_gls(W, V, R, T, Q, alpha, beta):
-    """M_l, F~, M_r of eq. gls-bdpre-plarge (n <= p) as functions on R^(p+n+m).
-
-    T = [0, T2] with T2 n x n upper triangular and S = T2(1:m, 1:m).
+    """M_l, F~, M_r of eq. gls-bdpre-plarge (n <= p) or eq. gls-bdpre-nlarge
+    (n > p) as functions on R^(p+n+m).  Factors are promoted to FP64.
     """
     n, m = W.shape
     p = V.shape[1]
-    assert n <= p, "eq. gls-bdpre-plarge needs n <= p"
     R = np.asarray(R, np.float64)
-    T2 = np.asarray(T, np.float64)[:, p - n:]
+    U, Y = gls_bd_triangles(T, n, m)
     Q = np.asarray(Q, np.float64)
-    S = T2[:m, :m]
     sa = np.sqrt(alpha)
 
     def Ml(u):
         a, b_, c = u[:p], u[p:p + n], u[p + n:]
-        return np.concatenate([a / sa, sa * _ut(T2, Q.T @ b_),
-                               S.T @ _ut(R, c, trans=True) / (sa * beta)])
+        return np.concatenate([a / sa, sa * _ut(U, Q.T @ b_),
+                               Y.T @ _ut(R, c, trans=True) / (sa * beta)])
 
     def Mr(u):
         a, b_, c = u[:p], u[p:p + n], u[p + n:]
-        return np.concatenate([a / sa, sa * (Q @ _ut(T2, b_, trans=True)),
-                               _ut(R, S @ c) / (sa * beta)])
+        return np.concatenate([a / sa, sa * (Q @ _ut(U, b_, trans=True)),
+                               _ut(R, Y @ c) / (sa * beta)])
 
     def F(u):
         a, b_, c = u[:p], u[p:p + n], u[p + n:]
@@ -384,7 +422,8 @@ def mplse_gmres_bd(A, B, b, d, uf=np.float32, tol=1e-14, maxit=40, restart=30,
     if alpha is None:
         alpha = float(np.linalg.norm(r))
         if not alpha > 0:
-            alpha = 2 ** -0.5 * float(np.min(np.abs(np.diag(np.asarray(T, np.float64)[:n, :n]))))
+            t = min(m, n)
+            alpha = 2 ** -0.5 * float(np.min(np.abs(np.diag(np.asarray(T, np.float64)[:t, :t]))))
     Ml, F, Mr = bd_operators_lse(A, B, R, T, Q, alpha, beta)
     sa = np.sqrt(alpha)
     hist, inner = [], 0
@@ -418,7 +457,9 @@ def mpgls_gmres_bd(W, V, d, uf=np.float32, tol=1e-14, maxit=40, restart=30,
     if alpha is None:
         alpha = float(np.linalg.norm(y))
         if not alpha > 0:
-            alpha = 2 ** -0.5 * float(np.min(np.abs(np.diag(np.asarray(T, np.float64)[:, p - n:]))))
+            T2 = np.asarray(T, np.float64)
+            T2 = T2[:, p - n:] if n <= p else T2[n - p:, :]
+            alpha = 2 ** -0.5 * float(np.min(np.abs(np.diag(T2))))
     Ml, F, Mr = bd_operators_gls(W, V, R, T, Q, alpha, beta)
     sa = np.sqrt(alpha)
     hist, inner = [], 0

@@ -289,20 +289,26 @@ struct LseSolver {
     vec_axpy(ctx, x, 8, 1.0, Yt, tc, n, true);
   }
 
-  // ---- GMRES-IR: block-diagonal split preconditioner for m >= n (Section
-  // 5.2, eq. lse-bdpre-mlarge), FP64 arithmetic on the stored factors.  With
-  // u = [a; b; c] (lengths m, p, n), S = T1(n-p:n, n-p:n) and sa = sqrt(alpha):
-  //   M_l u = [a / sa; S R^{-1} b / (sa beta); sa T1^{-T} Q c]
-  //   M_r u = [a / sa; R^{-T} S^T b / (sa beta); sa Q^T T1^{-1} c]
+  // ---- GMRES-IR: block-diagonal split preconditioners of Section 5.2, FP64
+  // arithmetic on the stored factors.  With u = [a; b; c] (lengths m, p, n)
+  // and sa = sqrt(alpha):
+  //   M_l u = [a / sa; Y R^{-1} b / (sa beta); sa U^{-T} Q c]
+  //   M_r u = [a / sa; R^{-T} Y^T b / (sa beta); sa Q^T U^{-1} c]
   //   F u   = [alpha a + A c; beta B c; A^T a + beta B^T b].
+  // U is n x n: T1 for m >= n (eq. lse-bdpre-mlarge); [T1 T2; 0 I] for n > m
+  // (eq. lse-bdpre-nlarge), where [T1 T2] is the m x n trapezoid of the QR
+  // of Abar.  Y is the trailing p x p block of U in both cases: the rows
+  // k .. t-1 (t = min(m, n), k = n - p) of the trapezoid followed by n - t
+  // identity rows.
   TriBlock tT1;
   double alpha = 1.0, beta = 1.0, sa = 1.0;
   double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *t1 = nullptr, *t2 = nullptr;
   DualParts dpa, dpb;
 
+  int tmn() const { return std::min(m, n); }
   void prepare_gmres(Ctx& ctx) {
     prepare(ctx, 8);
-    trsv_prepare(ctx, tT1, fa, 0, n, 8);
+    trsv_prepare(ctx, tT1, fa, 0, tmn(), 8);
     const int L = std::max(std::max(m, n), 1), N = std::max(m + p + n, 1);
     g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
     t1 = ctx.ws->get<double>(N); t2 = ctx.ws->get<double>(N);
@@ -321,14 +327,32 @@ struct LseSolver {
     agg_apply(ctx, fb, !trans, g3, 8);
     vec_convert(ctx, xv, 8, g3, 8, n, true);
   }
+  // x (n) <- U^{-1} x: x2 stays, T1 x1 = x1 - T2 x2
+  void u_solve(Ctx& ctx, double* xv) {
+    const int t = tmn();
+    if (n > t) gemv_upper(ctx, fa, 0, t, t, n - t, false, -1.0, xv + t, xv, 8);
+    trsv(ctx, tT1, false, xv);
+  }
+  // x (n) <- U^{-T} x: T1^T x1 = x1, x2 -= T2^T x1
+  void u_solve_t(Ctx& ctx, double* xv) {
+    const int t = tmn();
+    trsv(ctx, tT1, true, xv);
+    if (n > t) gemv_upper(ctx, fa, 0, t, t, n - t, true, -1.0, xv, xv + t, 8);
+  }
+  // y (p) += s op(Y) x
+  void y_apply(Ctx& ctx, bool trans, double s, const double* xv, double* yv) {
+    const int t = tmn(), rows = t - k;
+    gemv_upper(ctx, fa, k, k, rows, p, trans, s, xv, yv, 8);
+    if (p > rows) vec_axpy(ctx, yv + rows, 8, s, xv + rows, 8, p - rows, false);
+  }
   void m_right(Ctx& ctx, const double* u, double* out) {
     vec_convert(ctx, out, 8, u, 8, m, false, 1.0 / sa);
     vec_zero(ctx, g1, 8, p);
-    gemv_upper(ctx, fa, k, k, p, p, true, 1.0, u + m, g1, 8);
+    y_apply(ctx, true, 1.0, u + m, g1);
     r_solve(ctx, g1, true);
     vec_convert(ctx, out + m, 8, g1, 8, p, false, 1.0 / (sa * beta));
     vec_convert(ctx, g2, 8, u + m + p, 8, n, false);
-    trsv(ctx, tT1, false, g2);
+    u_solve(ctx, g2);
     q_apply(ctx, g2, true);
     vec_convert(ctx, out + m + p, 8, g2, 8, n, false, sa);
   }
@@ -337,10 +361,10 @@ struct LseSolver {
     vec_convert(ctx, g1, 8, u + m, 8, p, false);
     r_solve(ctx, g1, false);
     vec_zero(ctx, out + m, 8, p);
-    gemv_upper(ctx, fa, k, k, p, p, false, 1.0 / (sa * beta), g1, out + m, 8);
+    y_apply(ctx, false, 1.0 / (sa * beta), g1, out + m);
     vec_convert(ctx, g2, 8, u + m + p, 8, n, false);
     q_apply(ctx, g2, false);
-    trsv(ctx, tT1, true, g2);
+    u_solve_t(ctx, g2);
     vec_convert(ctx, out + m + p, 8, g2, 8, n, false, sa);
   }
   void f_apply(Ctx& ctx, const LseArgs& a, const double* u, double* out);
@@ -425,21 +449,26 @@ struct GlsSolver {
     vec_axpy(ctx, y, 8, 1.0, G, tc, p, true);
   }
 
-  // ---- GMRES-IR: block-diagonal split preconditioner for n <= p (Section
-  // 5.3, eq. gls-bdpre-plarge), FP64 arithmetic on the stored factors.  With
-  // u = [a; b; c] (lengths p, n, m), T = [0, T2], S = T2(0:m, 0:m), sa = sqrt(alpha):
-  //   M_l u = [a / sa; sa T2^{-1} Q^T b; S^T R^{-T} c / (sa beta)]
-  //   M_r u = [a / sa; sa Q T2^{-T} b; R^{-1} S c / (sa beta)]
+  // ---- GMRES-IR: block-diagonal split preconditioners of Section 5.3, FP64
+  // arithmetic on the stored factors.  With u = [a; b; c] (lengths p, n, m)
+  // and sa = sqrt(alpha):
+  //   M_l u = [a / sa; sa U^{-1} Q^T b; Y^T R^{-T} c / (sa beta)]
+  //   M_r u = [a / sa; sa Q U^{-T} b; R^{-1} Y c / (sa beta)]
   //   F u   = [alpha a + V^T b; V a + beta W c; beta W^T b].
-  // T2 = J Rv^T J for the n x n triangle Rv of the QR of Vt, and S = J A22^T J.
+  // U is n x n: T2 for n <= p (eq. gls-bdpre-plarge, T = [0, T2]); [I T1; 0 T2]
+  // for n > p (eq. gls-bdpre-nlarge, T = [T1; T2]).  Y is the leading m x m
+  // block of U in both cases.  The QR of Vt stores Rv (t x n, t = min(n, p))
+  // with T = J Rv^T J, so U = J Ut^T J for Ut = [Rv; 0 I_(n-t)], and
+  // Y = J Ut[k:n, k:n]^T J (k = n - m).
   TriBlock tRv;
   double alpha = 1.0, beta = 1.0, sa = 1.0;
   double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *g4 = nullptr, *t1 = nullptr, *t2 = nullptr;
   DualParts dpv, dpw;
 
+  int tnp() const { return std::min(n, p); }
   void prepare_gmres(Ctx& ctx) {
     prepare(ctx, 8);
-    trsv_prepare(ctx, tRv, fv, 0, n, 8);
+    trsv_prepare(ctx, tRv, fv, 0, tnp(), 8);
     const int L = std::max(std::max(n, p), 1), N = std::max(p + n + m, 1);
     g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
     g4 = ctx.ws->get<double>(L);
@@ -447,26 +476,36 @@ struct GlsSolver {
     dual_parts_alloc(ctx, n, p, dpv);
     dual_parts_alloc(ctx, n, m, dpw);
   }
-  // x (n) <- T2^{-1} x or T2^{-T} x
-  void t2_solve(Ctx& ctx, double* xv, bool trans) {
+  // x (n) <- U^{-1} x or U^{-T} x: U^{-1} = J Ut^{-T} J, U^{-T} = J Ut^{-1} J
+  void u_solve(Ctx& ctx, double* xv, bool trans) {
+    const int t = tnp();
     vec_convert(ctx, g3, 8, xv, 8, n, true);
-    trsv(ctx, tRv, !trans, g3);
+    if (!trans) {                          // Ut^T y = g: Rv1^T y1 = g1, y2 = g2 - Rv2^T y1
+      trsv(ctx, tRv, true, g3);
+      if (n > t) gemv_upper(ctx, fv, 0, t, t, n - t, true, -1.0, g3, g3 + t, 8);
+    } else {                               // Ut y = g: y2 = g2, Rv1 y1 = g1 - Rv2 y2
+      if (n > t) gemv_upper(ctx, fv, 0, t, t, n - t, false, -1.0, g3 + t, g3, 8);
+      trsv(ctx, tRv, false, g3);
+    }
     vec_convert(ctx, xv, 8, g3, 8, n, true);
   }
-  // out (m) = S x or S^T x
-  void s_apply(Ctx& ctx, const double* xv, double* out, bool trans) {
+  // out (m) = Y x or Y^T x, Y = J Ub^T J with Ub = Ut[k:n, k:n]: its first
+  // t - k rows come from Rv, the rest are identity rows
+  void y_apply(Ctx& ctx, const double* xv, double* out, bool trans) {
+    const int rows = tnp() - k;
     vec_convert(ctx, g3, 8, xv, 8, m, true);
     vec_zero(ctx, g4, 8, m);
-    gemv_upper(ctx, fv, k, k, m, m, !trans, 1.0, g3, g4, 8);
+    gemv_upper(ctx, fv, k, k, rows, m, !trans, 1.0, g3, g4, 8);
+    if (m > rows) vec_axpy(ctx, g4 + rows, 8, 1.0, g3 + rows, 8, m - rows, false);
     vec_convert(ctx, out, 8, g4, 8, m, true);
   }
   void m_right(Ctx& ctx, const double* u, double* out) {
     vec_convert(ctx, out, 8, u, 8, p, false, 1.0 / sa);
     vec_convert(ctx, g1, 8, u + p, 8, n, false);
-    t2_solve(ctx, g1, true);
+    u_solve(ctx, g1, true);
     agg_apply(ctx, fw, false, g1, 8);
     vec_convert(ctx, out + p, 8, g1, 8, n, false, sa);
-    s_apply(ctx, u + p + n, g2, false);
+    y_apply(ctx, u + p + n, g2, false);
     trsv(ctx, tR, false, g2);
     vec_convert(ctx, out + p + n, 8, g2, 8, m, false, 1.0 / (sa * beta));
   }
@@ -474,11 +513,11 @@ struct GlsSolver {
     vec_convert(ctx, out, 8, u, 8, p, false, 1.0 / sa);
     vec_convert(ctx, g1, 8, u + p, 8, n, false);
     agg_apply(ctx, fw, true, g1, 8);
-    t2_solve(ctx, g1, false);
+    u_solve(ctx, g1, false);
     vec_convert(ctx, out + p, 8, g1, 8, n, false, sa);
     vec_convert(ctx, g1, 8, u + p + n, 8, m, false);
     trsv(ctx, tR, true, g1);
-    s_apply(ctx, g1, g2, true);
+    y_apply(ctx, g1, g2, true);
     vec_convert(ctx, out + p + n, 8, g2, 8, m, false, 1.0 / (sa * beta));
   }
   void f_apply(Ctx& ctx, const GlsArgs& a, const double* u, double* out);
@@ -620,11 +659,6 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
   return out;
 }
 
-// GMRES-IR needs the block-diagonal preconditioner's shape condition
-// (eq. lse-bdpre-mlarge: m >= n; eq. gls-bdpre-plarge: n <= p).
-bool lse_gmres_ok(int m, int n) { return m >= n; }
-bool gls_gmres_ok(int n, int p) { return n <= p; }
-
 // One precision of the ladder for LSE: the factorization at prec, then the
 // refinement solvers in order on the same factors (IR: Algorithm 2; GMRES:
 // GMRES-IR; DIRECT: the FP64 factors with the classical loop).
@@ -666,10 +700,9 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
   const bool reuse = pre && pre->prec_id == prec;
   LseSolver& sv = reuse ? *pre : local;
   const bool ok_factor = reuse ? pre_ok : lse_prefactor(h, a, prec, o, sv);
-  const int stat_a = ok_factor ? 0 : 1, stat_b = 0;
   const float ms_factor = sv.ms_factor;
   RungOut out;
-  if (stat_b || stat_a) {
+  if (!ok_factor) {
     out.breakdown = true;
     ++attempts;
     solver_used = solvers.empty() ? LSQ_SOLVER_IR : solvers[0];
@@ -694,7 +727,7 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
           h, sv, a, m + p + n, zero, init, residual,
           [&]() {
             double al = dev_norm2(ctx, r, m);
-            if (!(al > 0.0)) al = std::sqrt(0.5) * min_abs_diag(ctx, sv.fa, 0, n);
+            if (!(al > 0.0)) al = std::sqrt(0.5) * min_abs_diag(ctx, sv.fa, 0, sv.tmn());
             return al > 0.0 ? al : 1.0;
           },
           [&](double* st) {
@@ -754,7 +787,7 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
           h, sv, a, p + n + m, zero, init, residual,
           [&]() {
             double al = dev_norm2(ctx, y, p);
-            if (!(al > 0.0)) al = std::sqrt(0.5) * min_abs_diag(ctx, sv.fv, 0, n);
+            if (!(al > 0.0)) al = std::sqrt(0.5) * min_abs_diag(ctx, sv.fv, 0, sv.tnp());
             return al > 0.0 ? al : 1.0;
           },
           [&](double* st) {
@@ -831,9 +864,10 @@ int class_solver(int c) { return c == 1 ? LSQ_SOLVER_GMRES_IR : LSQ_SOLVER_IR; }
 // factors).  Starting at the requested rung: with IR requested, each
 // precision tries classical IR and then GMRES-IR on the same factors; with
 // GMRES requested, GMRES-IR only; precisions rise FP8 -> BF16 -> FP16 -> FP32 and the
-// ladder ends with the FP64 direct path.  GMRES-IR is left out when the
-// preconditioner's shape condition fails.
-std::vector<std::pair<int, std::vector<int>>> ladder(const lsq_opts& o, bool gmres_ok) {
+// ladder ends with the FP64 direct path.  The block-diagonal preconditioners
+// cover every admissible shape (Sections 5.2 and 5.3), so GMRES-IR is always
+// available.
+std::vector<std::pair<int, std::vector<int>>> ladder(const lsq_opts& o) {
   std::vector<std::pair<int, std::vector<int>>> r;
   int prec = o.prec == LSQ_PREC_AUTO ? LSQ_PREC_FP32 : o.prec;
   int solver = o.solver == LSQ_SOLVER_AUTO ? LSQ_SOLVER_IR : o.solver;
@@ -841,14 +875,13 @@ std::vector<std::pair<int, std::vector<int>>> ladder(const lsq_opts& o, bool gmr
     r.push_back({LSQ_PREC_FP64, {LSQ_SOLVER_DIRECT}});
     return r;
   }
-  if (solver == LSQ_SOLVER_GMRES_IR && !gmres_ok) solver = LSQ_SOLVER_IR;
   if (!o.escalate) {
     r.push_back({prec, {solver}});
     return r;
   }
   std::vector<int> solvers;
   if (solver == LSQ_SOLVER_IR) solvers.push_back(LSQ_SOLVER_IR);
-  if (gmres_ok) solvers.push_back(LSQ_SOLVER_GMRES_IR);
+  solvers.push_back(LSQ_SOLVER_GMRES_IR);
   const int order[] = {LSQ_PREC_FP8E4M3, LSQ_PREC_BF16, LSQ_PREC_FP16, LSQ_PREC_FP32};
   bool on = false;
   for (int q : order) {
@@ -1132,7 +1165,7 @@ int lse_solve_core(Worker* w, int m, int n, int p, const double* A, int lda, con
     if (o.prec == LSQ_PREC_AUTO) o.prec = pre_ok ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
     if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
   }
-  const auto rungs = ladder(o, lse_gmres_ok(m, n));
+  const auto rungs = ladder(o);
   RungOut ro;
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
   for (const auto& [prec, solvers] : rungs) {
@@ -1171,7 +1204,7 @@ int gls_solve_core(Worker* w, int n, int m, int p, const double* W, int ldw, con
     if (o.prec == LSQ_PREC_AUTO) o.prec = pre_ok ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
     if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
   }
-  const auto rungs = ladder(o, gls_gmres_ok(n, p));
+  const auto rungs = ladder(o);
   RungOut ro;
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
   for (const auto& [prec, solvers] : rungs) {
@@ -1658,8 +1691,8 @@ int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p
   if (type != LSQ_LSE && type != LSQ_GLS) return -2;
   PrecSpec ps;
   if (!prec_spec(prec, ps)) return -3;
-  if (type == LSQ_LSE && !(p <= n && n <= m + p && lse_gmres_ok(m, n))) return -4;
-  if (type == LSQ_GLS && !(m <= n && n <= m + p && gls_gmres_ok(n, p))) return -4;
+  if (type == LSQ_LSE && !(p <= n && n <= m + p)) return -4;
+  if (type == LSQ_GLS && !(m <= n && n <= m + p)) return -4;
   if (!(alpha > 0) || !(beta > 0)) return -11;
   if (k < 0) return -15;
   return guard(h, "lsq_dbg_bd_apply_graph", [&]() -> int {
@@ -1705,8 +1738,8 @@ int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, cons
   if (type != LSQ_LSE && type != LSQ_GLS) return -2;
   PrecSpec ps;
   if (!prec_spec(prec, ps)) return -3;
-  if (type == LSQ_LSE && !(p <= n && n <= m + p && lse_gmres_ok(m, n))) return -4;
-  if (type == LSQ_GLS && !(m <= n && n <= m + p && gls_gmres_ok(n, p))) return -4;
+  if (type == LSQ_LSE && !(p <= n && n <= m + p)) return -4;
+  if (type == LSQ_GLS && !(m <= n && n <= m + p)) return -4;
   if (!(alpha > 0) || !(beta > 0)) return -11;
   return guard(h, "lsq_dbg_bd_apply", [&]() -> int {
     Ctx& ctx = h->w.ctx;

@@ -382,7 +382,7 @@ def _spectrum_counts(X, tol=1e-8):
     ev = np.sort(np.linalg.eigvalsh((X + X.T) / 2))
     phi = (1 + math.sqrt(5)) / 2
     cub = np.roots([1.0, -1.0, -2.0, 1.0]).real
-    targets = {"one": [1.0], "golden": [phi, 1 - phi], "cubic": list(cub)}
+    targets = {"one": [1.0], "minus_one": [-1.0], "golden": [phi, 1 - phi], "cubic": list(cub)}
     counts = {k: 0 for k in targets}
     for e in ev:
         hit = [k for k, vals in targets.items() if min(abs(e - t) for t in vals) < tol]
@@ -400,7 +400,7 @@ def test_lemma_c1_lse_spectrum_and_gmres_steps():
     X = _dense(lambda u: Ml(F(Mr(u))), N)
     assert np.max(np.abs(X - X.T)) < 1e-10
     c = _spectrum_counts(X)
-    assert c == {"one": m - n, "golden": 2 * (n - p), "cubic": 3 * p}
+    assert c == {"one": m - n, "minus_one": 0, "golden": 2 * (n - p), "cubic": 3 * p}
     rhs = _rng(61).standard_normal(N)
     _, its, ok = mpir.gmres(lambda u: X @ u, rhs, restart=30, tol=1e-12)
     assert ok and its <= 6
@@ -415,9 +415,96 @@ def test_lemma_c1_gls_spectrum_and_gmres_steps():
     X = _dense(lambda u: Ml(F(Mr(u))), N)
     assert np.max(np.abs(X - X.T)) < 1e-10
     c = _spectrum_counts(X)
-    assert c == {"one": p - n, "golden": 2 * (n - m), "cubic": 3 * m}
+    assert c == {"one": p - n, "minus_one": 0, "golden": 2 * (n - m), "cubic": 3 * m}
     _, its, ok = mpir.gmres(lambda u: X @ u, _rng(63).standard_normal(N), restart=30, tol=1e-12)
     assert ok and its <= 6
+
+
+# With n > m (LSE) the preconditioned matrix of eq. lse-bdpre-nlarge is, in
+# exact arithmetic, [I_m 0 Zbar; 0 0 Ibar_p; Zbar^T Ibar_p^T 0] with
+# Zbar = [Z, 0].  Rotating the first block by Z^T decouples it by index of c:
+# indices below n - p pair a with c (the 2 x 2 block [1 1; 1 0], golden
+# pair), indices n - p .. m - 1 join a, c and b (the 3 x 3 block whose
+# characteristic polynomial is t^3 - t^2 - 2t + 1) and indices m .. n - 1 pair
+# c with b only ([0 1; 1 0]: eigenvalues +1 and -1).  The GLS case n > p of
+# eq. gls-bdpre-nlarge mirrors it: n - p pairs (b, c) with eigenvalues +-1,
+# m - n + p triples and n - m golden pairs.
+@pytest.mark.parametrize("m,n,p", [(8, 12, 6), (10, 14, 9), (5, 9, 4), (7, 15, 8)])
+def test_lse_nlarge_spectrum_and_gmres_steps(m, n, p):
+    P = wl.lse_gaussian(_rng(65 + m), m, n, p)
+    R, T, Z, Q = mpir.grq_factors(P.B, P.A, np.float64)
+    Ml, F, Mr = mpir.bd_operators_lse(P.A, P.B, R, T, Q, alpha=0.8, beta=1.7)
+    N = m + n + p
+    X = _dense(lambda u: Ml(F(Mr(u))), N)
+    assert np.max(np.abs(X - X.T)) < 1e-10
+    c = _spectrum_counts(X)
+    assert c == {"one": n - m, "minus_one": n - m, "golden": 2 * (n - p), "cubic": 3 * (m - n + p)}
+    _, its, ok = mpir.gmres(lambda u: X @ u, _rng(66).standard_normal(N), restart=30, tol=1e-12)
+    assert ok and its <= 7
+
+
+@pytest.mark.parametrize("n,m,p", [(12, 8, 6), (14, 9, 10), (9, 5, 4), (15, 7, 8)])
+def test_gls_nlarge_spectrum_and_gmres_steps(n, m, p):
+    G = wl.gls_gaussian(_rng(67 + n), n, m, p)
+    R, T, Q, Z = mpir.gqr_factors(G.W, G.V, np.float64)
+    Ml, F, Mr = mpir.bd_operators_gls(G.W, G.V, R, T, Q, alpha=1.4, beta=0.5)
+    N = m + n + p
+    X = _dense(lambda u: Ml(F(Mr(u))), N)
+    assert np.max(np.abs(X - X.T)) < 1e-10
+    c = _spectrum_counts(X)
+    assert c == {"one": n - p, "minus_one": n - p, "golden": 2 * (n - m), "cubic": 3 * (m - n + p)}
+    _, its, ok = mpir.gmres(lambda u: X @ u, _rng(68).standard_normal(N), restart=30, tol=1e-12)
+    assert ok and its <= 7
+
+
+def test_bd_triangles_reduce_to_the_square_case():
+    # eq. lse-bdpre-nlarge at n = m and eq. gls-bdpre-nlarge at n = p are
+    # eq. lse-bdpre-mlarge and eq. gls-bdpre-plarge: no identity block
+    rng = _rng(69)
+    T = np.triu(rng.standard_normal((9, 9)))
+    U, Y = mpir.lse_bd_triangles(T, 9, 4)
+    assert np.array_equal(U, T) and np.array_equal(Y, T[5:, 5:])
+    U, Y = mpir.gls_bd_triangles(T, 9, 4)
+    assert np.array_equal(U, T) and np.array_equal(Y, T[:4, :4])
+    # LSE n > m: Y is the printed block matrix
+    m, n, p = 5, 8, 6
+    T = np.triu(rng.standard_normal((m, n)))
+    U, Y = mpir.lse_bd_triangles(T, n, p)
+    k = n - p
+    Yp = np.block([[T[k:m, k:m], T[k:m, m:]], [np.zeros((n - m, m - k)), np.eye(n - m)]])
+    assert np.array_equal(Y, Yp)
+    # GLS n > p: T = [T1; T2] (n x p), Y the printed block matrix
+    n, m, p = 8, 6, 5
+    T = np.vstack([rng.standard_normal((n - p, p)), np.triu(rng.standard_normal((p, p)))])
+    U, Y = mpir.gls_bd_triangles(T, n, m)
+    j = m - n + p
+    Yp = np.block([[np.eye(n - p), T[:n - p, :j]], [np.zeros((j, n - p)), T[n - p:, :j][:j]]])
+    assert np.array_equal(Y, Yp)
+
+
+def test_gmres_ir_nlarge_shapes_converge():
+    L = wl.lse_conditioned(_rng(70), 96, 128, 48, 1e5)
+    g = mpir.mplse_gmres_bd(L.A, L.B, L.b, L.d, tol=1e-14)
+    assert g.converged and g.inner > 0
+    x, _, _ = direct.lse_solve(L.A, L.B, L.b, L.d)
+    assert _rel(g.x, x) < 1e-8
+    G = wl.gls_conditioned(_rng(71), 128, 96, 48, 1e5)
+    h = mpir.mpgls_gmres_bd(G.W, G.V, G.d, tol=1e-14)
+    assert h.converged and h.inner > 0
+    xg, yg, _ = direct.gls_solve(G.W, G.V, G.d)
+    assert _rel(h.x, xg) < 1e-8 and _rel(h.aux1, yg) < 1e-8
+
+
+def test_lse_square_stack_has_zero_residual_and_multiplier():
+    # n = m + p: [A; B] is square and nonsingular, so x = [A; B]^{-1} [b; d]
+    # and the optimal r = b - A x and multiplier v vanish
+    m, n, p = 24, 40, 16
+    P = wl.lse_gaussian(_rng(72), m, n, p)
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    xs = np.linalg.solve(np.vstack([P.A, P.B]), np.concatenate([P.b, P.d]))
+    assert _rel(x, xs) < 1e-12
+    assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(P.b)
+    assert np.linalg.norm(v) < 1e-10
 
 
 def test_gmres_minimal_polynomial_degree():

@@ -58,6 +58,10 @@ struct GemmArgs {
   int ksplit;            // > 1: partial products over k-chunks go to Cpart[z % ksplit] (m x n, ld m)
   int kchunk;
   void* Cpart;
+  // two-level batch: with bper > 0, batch entry z is item z % bper of group
+  // z / bper, at offset (z % bper) s + (z / bper) s2 for each operand
+  int bper;
+  long long sa2, sb2, sc2;
 };
 
 template <typename SA, typename SB, typename TC>
@@ -71,9 +75,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int ks = g.ksplit > 1 ? g.ksplit : 1;
   const int bz = blockIdx.z / ks, kz = blockIdx.z % ks;
-  const SA* A = static_cast<const SA*>(g.A) + (long long)bz * g.sa;
-  const SB* B = static_cast<const SB*>(g.B) + (long long)bz * g.sb;
-  TC* C = static_cast<TC*>(g.C) + (long long)bz * g.sc;
+  const int bi = g.bper > 0 ? bz % g.bper : bz, bg = g.bper > 0 ? bz / g.bper : 0;
+  const SA* A = static_cast<const SA*>(g.A) + (long long)bi * g.sa + (long long)bg * g.sa2;
+  const SB* B = static_cast<const SB*>(g.B) + (long long)bi * g.sb + (long long)bg * g.sb2;
+  TC* C = static_cast<TC*>(g.C) + (long long)bi * g.sc + (long long)bg * g.sc2;
   const int kbeg = ks > 1 ? kz * g.kchunk : 0;
   const int kend = ks > 1 ? min(g.k, kbeg + g.kchunk) : g.k;
   typename Mt::V acc[2][2];
@@ -215,11 +220,14 @@ static void gemm(Ctx& ctx, GemmArgs g, int batch) {
 // ----------------------------------------------------- triangular inverse --
 // Inverse of each 64 x 64 diagonal block; one work-group per block, FP64,
 // right-looking back substitution on U X = I with all columns in parallel.
+// blockIdx.y selects the matrix of a batch (strides su, sx).
 template <typename S, typename TC>
-__global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int ldu, int mask, int nn,
-                                                  TC* __restrict__ X, int ldx) {
+__global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int ldu, long long su, int mask,
+                                                  int nn, TC* __restrict__ X, int ldx, long long sx) {
   __shared__ double R[64 * kLdt];
   __shared__ double buf[192];
+  U += (long long)blockIdx.y * su;
+  X += (long long)blockIdx.y * sx;
   const int I = blockIdx.x, i0 = I * 64, ib = min(64, nn - i0);
   const int t = threadIdx.x;
   for (int e = t; e < 4096; e += 512) {
@@ -241,25 +249,33 @@ __global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int l
 }
 
 template <typename TC>
-__global__ void k_zero_lower(TC* X, int ldx, int nn) {
+__global__ void k_zero_lower(TC* X, int ldx, long long sx, int nn, int nmat) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)nn * nn) return;
-  const int i = (int)(e % nn), j = (int)(e / nn);
-  if (i > j) X[(size_t)i + (size_t)j * ldx] = (TC)0;
+  const long long per = (long long)nn * nn;
+  if (e >= per * nmat) return;
+  const long long q = e / per, r = e % per;
+  const int i = (int)(r % nn), j = (int)(r / nn);
+  if (i > j) X[q * sx + (size_t)i + (size_t)j * ldx] = (TC)0;
 }
 
-// X (nn x nn, ld ldx, type TC) = U^{-1} for the upper triangle of U (type S,
-// masked upper).  Off-diagonal blocks by recursive doubling: for a diagonal
-// pair [A B; 0 C] of size 2b, X12 = -A^{-1} B C^{-1} (two batched GEMMs).
+// X_q (nn x nn, ld ldx, type TC) = U_q^{-1} for the upper triangles of nmat
+// matrices U_q = U + q su, X_q = X + q sx (type S, masked upper).  Off-diagonal
+// blocks by recursive doubling: for a diagonal pair [A B; 0 C] of size 2b,
+// X12 = -A^{-1} B C^{-1}; the pairs of every matrix at one level share two
+// batched GEMMs.
 template <typename S, typename TC>
-void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
-  if (nn <= 0) return;
+void tri_inverse_batched(Ctx& ctx, const S* U, int ldu, long long su, int nn, TC* X, int ldx,
+                         long long sx, int nmat) {
+  if (nn <= 0 || nmat <= 0) return;
   const int nblk = ceil_div(nn, 64);
-  const long long tot = (long long)nn * nn;
-  hipLaunchKernelGGL((k_zero_lower<TC>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, X, ldx, nn);
-  hipLaunchKernelGGL((k_diag_inv<S, TC>), dim3(nblk), dim3(512), 0, ctx.stream, U, ldu, 1, nn, X, ldx);
+  const long long tot = (long long)nn * nn * nmat;
+  hipLaunchKernelGGL((k_zero_lower<TC>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream,
+                     X, ldx, sx, nn, nmat);
+  hipLaunchKernelGGL((k_diag_inv<S, TC>), dim3(nblk, nmat), dim3(512), 0, ctx.stream, U, ldu, su, 1, nn,
+                     X, ldx, sx);
   LSQ_LAUNCH_CHECK();
-  TC* tmp = ctx.ws->get<TC>((size_t)nn * 64 + (size_t)nn * nn / 2 + 64);
+  const long long tper = (long long)nn * 64 + (long long)nn * nn / 2 + 64;   // tmp per matrix
+  TC* tmp = ctx.ws->get<TC>((size_t)tper * nmat);
   for (int b = 64; b < nn; b *= 2) {
     const int npairs = ceil_div(nn, 2 * b);
     // full pairs share one batched launch; a ragged last pair is launched alone
@@ -277,16 +293,23 @@ void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
       g1.B = X + (size_t)c0 + (size_t)c0 * ldx; g1.ldb = ldx; g1.sb = (long long)2 * b * (ldx + 1); g1.tb = 0; g1.mb = 0; g1.ob = 0;
       g1.C = tmp; g1.ldc = b; g1.sc = (long long)b * b;
       g1.m = b; g1.n = bw; g1.k = bw; g1.alpha = 1.0; g1.beta = 0.0;
-      gemm<S, TC, TC>(ctx, g1, cnt);
+      g1.bper = cnt; g1.sa2 = su; g1.sb2 = sx; g1.sc2 = tper;
+      gemm<S, TC, TC>(ctx, g1, cnt * nmat);
       // X12 = -A^{-1} tmp   (b x bw)
       GemmArgs g2{};
       g2.A = X + (size_t)a0 + (size_t)a0 * ldx; g2.lda = ldx; g2.sa = (long long)2 * b * (ldx + 1); g2.ta = 0; g2.ma = 0; g2.oa = 0;
       g2.B = tmp; g2.ldb = b; g2.sb = (long long)b * b; g2.tb = 0; g2.mb = 0; g2.ob = 0;
       g2.C = X + (size_t)a0 + (size_t)c0 * ldx; g2.ldc = ldx; g2.sc = (long long)2 * b * (ldx + 1);
       g2.m = b; g2.n = bw; g2.k = b; g2.alpha = -1.0; g2.beta = 0.0;
-      gemm<TC, TC, TC>(ctx, g2, cnt);
+      g2.bper = cnt; g2.sa2 = sx; g2.sb2 = tper; g2.sc2 = sx;
+      gemm<TC, TC, TC>(ctx, g2, cnt * nmat);
     }
   }
+}
+
+template <typename S, typename TC>
+void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
+  tri_inverse_batched<S, TC>(ctx, U, ldu, 0, nn, X, ldx, 0, 1);
 }
 
 // ------------------------------------------------- inverse-based solves --
@@ -304,13 +327,16 @@ void trmv_dense(Ctx& ctx, const TC* X, int ldx, int nn, bool trans, const TC* x,
   LSQ_LAUNCH_CHECK();
 }
 // ---------------------------------------- aggregated reflector application --
-// G = striu(Y^T Y) + diag(Y^T Y) / 2 for a unit-lower Y (rows x cols), dense output.
+// G = striu(Y^T Y) + diag(Y^T Y) / 2 for a unit-lower Y (rows x cols), dense
+// output; nmat matrices n x n stored one after another (ld n).
 template <typename TC>
-__global__ void k_ut_fix(TC* G, int ldg, int n) {
+__global__ void k_ut_fix(TC* G, int n, int nmat) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (long long)n * n) return;
-  const int i = (int)(e % n), j = (int)(e / n);
-  TC* p = G + (size_t)i + (size_t)j * ldg;
+  const long long per = (long long)n * n;
+  if (e >= per * nmat) return;
+  const long long r = e % per;
+  const int i = (int)(r % n), j = (int)(r / n);
+  TC* p = G + e;
   if (i > j) *p = (TC)0;
   else if (i == j) *p = (TC)((double)*p * 0.5);
 }
@@ -326,40 +352,60 @@ void agg_prepare(Ctx& ctx, QRFactor& f, int tc, int panels_per_block) {
   f.agg.clear();
   f.agg_tc = tc;
   const int width = 64 * (panels_per_block > 0 ? panels_per_block : 1);
+  std::vector<AggBlock> blocks;
   for (int J0 = 0; J0 < f.k; J0 += width) {
     AggBlock b;
     b.J0 = J0;
     b.w = min(width, f.k - J0);
-    const int rows = f.r - J0;
-    const long long tot = (long long)b.w * b.w;
-    b.T = ctx.ws->alloc((size_t)tc * tot);
-    GemmArgs g{};
-    g.A = f.tw == 8 ? (const void*)(static_cast<const double*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld)
-                    : (const void*)(static_cast<const float*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld);
-    g.lda = f.ld; g.ta = 1; g.ma = 2; g.oa = 0;
-    g.B = g.A; g.ldb = f.ld; g.tb = 0; g.mb = 2; g.ob = 0;
-    g.ldc = b.w; g.m = b.w; g.n = b.w; g.k = rows; g.alpha = 1.0; g.beta = 0.0;
-    if (tc == 8 || f.tw == 8) {
-      // FP64 Gram and inverse (the GMRES preconditioner and the FP64 path)
-      double* G = ctx.ws->get<double>(tot);
-      double* T64 = tc == 8 ? static_cast<double*>(b.T) : ctx.ws->get<double>(tot);
-      g.C = G;
-      if (f.tw == 8) gemm<double, double, double>(ctx, g, 1); else gemm<float, float, double>(ctx, g, 1);
-      hipLaunchKernelGGL((k_ut_fix<double>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, G, b.w, b.w);
-      tri_inverse<double, double>(ctx, G, b.w, b.w, T64, b.w);
+    blocks.push_back(b);
+  }
+  // Consecutive blocks of one width form a group: their Grams are formed one
+  // by one (the row counts differ) into consecutive w x w slots, and the
+  // triangular inverses of the group run as one batch.
+  const bool f64 = tc == 8 || f.tw == 8;   // FP64 Gram and inverse (GMRES, FP64 path)
+  size_t i = 0;
+  while (i < blocks.size()) {
+    size_t j = i;
+    while (j < blocks.size() && blocks[j].w == blocks[i].w) ++j;
+    const int w = blocks[i].w, nm = (int)(j - i);
+    const long long tot = (long long)w * w;
+    void* G = ctx.ws->alloc((f64 ? 8 : 4) * (size_t)(tot * nm));
+    for (size_t q = i; q < j; ++q) {
+      const int J0 = blocks[q].J0, rows = f.r - J0;
+      GemmArgs g{};
+      g.A = f.tw == 8 ? (const void*)(static_cast<const double*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld)
+                      : (const void*)(static_cast<const float*>(f.M) + (size_t)J0 + (size_t)J0 * f.ld);
+      g.lda = f.ld; g.ta = 1; g.ma = 2; g.oa = 0;
+      g.B = g.A; g.ldb = f.ld; g.tb = 0; g.mb = 2; g.ob = 0;
+      g.ldc = w; g.m = w; g.n = w; g.k = rows; g.alpha = 1.0; g.beta = 0.0;
+      if (f64) {
+        g.C = static_cast<double*>(G) + (size_t)(q - i) * tot;
+        if (f.tw == 8) gemm<double, double, double>(ctx, g, 1); else gemm<float, float, double>(ctx, g, 1);
+      } else {
+        g.C = static_cast<float*>(G) + (size_t)(q - i) * tot;
+        gemm<float, float, float>(ctx, g, 1);
+      }
+    }
+    const unsigned nbk = (unsigned)((tot * nm + 255) / 256);
+    void* T = ctx.ws->alloc((size_t)tc * (size_t)(tot * nm));
+    if (f64) {
+      double* G64 = static_cast<double*>(G);
+      hipLaunchKernelGGL((k_ut_fix<double>), dim3(nbk), dim3(256), 0, ctx.stream, G64, w, nm);
+      double* T64 = tc == 8 ? static_cast<double*>(T) : ctx.ws->get<double>((size_t)(tot * nm));
+      tri_inverse_batched<double, double>(ctx, G64, w, tot, w, T64, w, tot, nm);
       if (tc != 8)
-        hipLaunchKernelGGL((k_cast<float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, T64, static_cast<float*>(b.T), tot);
+        hipLaunchKernelGGL((k_cast<float>), dim3(nbk), dim3(256), 0, ctx.stream, T64, static_cast<float*>(T),
+                           tot * nm);
     } else {
-      // FP32 corrections on FP32-stored reflectors: Gram and inverse in FP32
-      float* G = ctx.ws->get<float>(tot);
-      g.C = G;
-      gemm<float, float, float>(ctx, g, 1);
-      hipLaunchKernelGGL((k_ut_fix<float>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream, G, b.w, b.w);
-      tri_inverse<float, float>(ctx, G, b.w, b.w, static_cast<float*>(b.T), b.w);
+      float* G32 = static_cast<float*>(G);
+      hipLaunchKernelGGL((k_ut_fix<float>), dim3(nbk), dim3(256), 0, ctx.stream, G32, w, nm);
+      tri_inverse_batched<float, float>(ctx, G32, w, tot, w, static_cast<float*>(T), w, tot, nm);
     }
     LSQ_LAUNCH_CHECK();
-    f.agg.push_back(b);
+    for (size_t q = i; q < j; ++q) blocks[q].T = static_cast<char*>(T) + (size_t)tc * (size_t)(q - i) * tot;
+    i = j;
   }
+  f.agg = blocks;
 }
 
 template <typename S, typename TC>

@@ -313,13 +313,12 @@ void tri_inverse(Ctx& ctx, const S* U, int ldu, int nn, TC* X, int ldx) {
 }
 
 // ------------------------------------------------- inverse-based solves --
-// x <- op(X) x for a dense upper triangular X (nn x nn): y = X x or X^T x.
-// 64 rows x 256 columns per work-group; partial row sums added atomically
-// into y, which the caller zeroes.
+// y += op(X) x for a dense upper triangular X (nn x nn): X x or X^T x.
+// Partial row sums are added atomically into y, which holds the values to
+// accumulate onto.
 template <typename TC>
 void trmv_dense(Ctx& ctx, const TC* X, int ldx, int nn, bool trans, const TC* x, TC* y) {
   if (nn <= 0) return;
-  vec_zero(ctx, y, (int)sizeof(TC), nn);          // a fill kernel: this path may be graph-captured
   if (!trans)
     gemv_n<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y);
   else
@@ -405,23 +404,29 @@ void agg_prepare(Ctx& ctx, QRFactor& f, int tc, int panels_per_block) {
     for (size_t q = i; q < j; ++q) blocks[q].T = static_cast<char*>(T) + (size_t)tc * (size_t)(q - i) * tot;
     i = j;
   }
+  size_t acc = 0;
+  for (auto& b : blocks) {
+    b.acc = acc;
+    acc += 2 * (size_t)b.w;
+  }
+  f.agg_acc_len = acc;
+  f.agg_acc = ctx.ws->alloc((size_t)tc * (acc > 0 ? acc : 1));
+  vec_zero(ctx, f.agg_acc, tc, (int)acc);
   f.agg = blocks;
 }
 
 template <typename S, typename TC>
 static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
   const int nb = (int)f.agg.size();
-  int maxw = 0;
-  for (auto& b : f.agg) maxw = max(maxw, b.w);
-  TC* s = ctx.ws->get<TC>(maxw > 0 ? maxw : 1);
-  TC* tv = ctx.ws->get<TC>(maxw > 0 ? maxw : 1);
+  TC* acc = static_cast<TC*>(f.agg_acc);
   for (int q = 0; q < nb; ++q) {
     const AggBlock& b = f.agg[trans ? q : nb - 1 - q];
     const int rows = f.r - b.J0;
     const S* Y = static_cast<const S*>(f.M) + (size_t)b.J0 + (size_t)b.J0 * f.ld;
     TC* yy = y + b.J0;
+    TC* s = acc + b.acc;                 // zero on entry
+    TC* tv = s + b.w;                    // zero on entry
     // s = Y^T y (unit-lower Y)
-    vec_zero(ctx, s, (int)sizeof(TC), b.w);
     gemv_t<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)1, yy, s);
     // Q^T = I - Y T^T Y^T  -> t = T^T s ;  Q = I - Y T Y^T -> t = T s
     trmv_dense<TC>(ctx, static_cast<const TC*>(b.T), b.w, b.w, trans, s, tv);
@@ -429,6 +434,9 @@ static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
     gemv_n<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)-1, tv, yy);
     LSQ_LAUNCH_CHECK();
   }
+  // every block's accumulators back to zero for the next application (a fill
+  // kernel: this path may be graph-captured)
+  vec_zero(ctx, acc, (int)sizeof(TC), (int)f.agg_acc_len);
 }
 
 void agg_apply(Ctx& ctx, const QRFactor& f, bool trans, void* y, int tc) {
@@ -457,7 +465,7 @@ void tri_inverse_factor(Ctx& ctx, const QRFactor& f, int o, int nn, void* X, int
   }
 }
 
-void trmv(Ctx& ctx, const void* X, int nn, bool trans, const void* x, void* y, int tc) {
+void trmv_acc(Ctx& ctx, const void* X, int nn, bool trans, const void* x, void* y, int tc) {
   if (tc == 8) trmv_dense<double>(ctx, static_cast<const double*>(X), nn, nn, trans, static_cast<const double*>(x), static_cast<double*>(y));
   else trmv_dense<float>(ctx, static_cast<const float*>(X), nn, nn, trans, static_cast<const float*>(x), static_cast<float*>(y));
 }

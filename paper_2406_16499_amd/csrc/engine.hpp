@@ -68,6 +68,7 @@ void ktimer_end(Ctx& ctx, int kind);
 struct AggBlock {
   int J0 = 0, w = 0;
   void* T = nullptr;            // w x w, column-major, compute precision
+  size_t acc = 0;               // offset (elements) of the block's accumulators in agg_acc
 };
 
 // Blocked Householder QR of an r x c column-major matrix stored in Tw
@@ -88,6 +89,10 @@ struct QRFactor {
   int* status = nullptr;        // device: bit0 = a panel Cholesky broke down
   std::vector<AggBlock> agg;    // aggregated blocks for vector application
   int agg_tc = 0;
+  // accumulators of the aggregated application, s = Y^T y (w) and t = op(T) s
+  // (w) per block in compute precision; zero between applications
+  void* agg_acc = nullptr;
+  size_t agg_acc_len = 0;
 };
 
 void qr_alloc(Ctx& ctx, QRFactor& f, int r, int c, int tw, Mma mt, int nb);
@@ -97,13 +102,15 @@ void qr_apply_left_T(Ctx& ctx, const QRFactor& f, void* C, int ldc, int ncols);
 
 // Aggregated application: prepare blocks of `panels_per_block` panels (the
 // Gram Y^T Y in FP64, T by triangular inversion) in compute precision tc, then
-// y <- Q^T y (trans) or Q y with three parallel kernels per block.
+// y <- Q^T y (trans) or Q y with three parallel kernels per block and one
+// fill that clears the accumulators after the last block.
 void agg_prepare(Ctx& ctx, QRFactor& f, int tc, int panels_per_block);
 void agg_apply(Ctx& ctx, const QRFactor& f, bool trans, void* y, int tc);
 // Dense inverse X (nn x nn, ld nn, precision tc) of the upper triangular
 // block f.M[o:o+nn, o:o+nn]; y = X x or X^T x.
 void tri_inverse_factor(Ctx& ctx, const QRFactor& f, int o, int nn, void* X, int tc);
-void trmv(Ctx& ctx, const void* X, int nn, bool trans, const void* x, void* y, int tc);
+// y += op(X) x for a dense upper triangular X (nn x nn); y is not cleared.
+void trmv_acc(Ctx& ctx, const void* X, int nn, bool trans, const void* x, void* y, int tc);
 
 // ----------------------------------------------------- vector kernels ----
 // Triangular solve with the upper triangular block U = f.M[o:o+nn, o:o+nn]:
@@ -113,7 +120,7 @@ struct TriBlock {
   const QRFactor* f = nullptr;
   int o = 0, nn = 0;
   void* inv = nullptr;          // nn x nn dense inverse (Tc)
-  void* tmp = nullptr;          // nn (Tc)
+  void* tmp = nullptr;          // nn (Tc), zero between solves
   int tc = 4;
 };
 void trsv_prepare(Ctx& ctx, TriBlock& tb, const QRFactor& f, int o, int nn, int tc);
@@ -130,6 +137,8 @@ void vec_convert(Ctx& ctx, void* dst, int td, const void* src, int ts, int n, bo
                  double scale = 1.0);
 void vec_axpy(Ctx& ctx, void* y, int ty, double a, const void* x, int tx, int n, bool reverse_x);
 void vec_zero(Ctx& ctx, void* y, int ty, int n);
+// dst = src, then src = 0 (same type t, n elements, no overlap).
+void vec_move(Ctx& ctx, void* dst, void* src, int t, int n);
 
 // Dense FP64 matrix -> Tw copy with optional transpose and index reversal:
 // dst (dr x dc, ld ldd) [i][j] = src[ri][ci] where (ri, ci) = trans ? (j, i) : (i, j),

@@ -11,13 +11,16 @@ void trsv_prepare(Ctx& ctx, TriBlock& tb, const QRFactor& f, int o, int nn, int 
   tb.f = &f; tb.o = o; tb.nn = nn; tb.tc = tc;
   tb.inv = ctx.ws->alloc((size_t)tc * (nn > 0 ? (size_t)nn * nn : 1));
   tb.tmp = ctx.ws->alloc((size_t)tc * (nn > 0 ? nn : 1));
+  vec_zero(ctx, tb.tmp, tc, nn);
   tri_inverse_factor(ctx, f, o, nn, tb.inv, tc);
 }
 
+// tmp (zero between solves) accumulates op(U^{-1}) x, then moves into x and
+// is cleared in the same pass.
 void trsv(Ctx& ctx, const TriBlock& tb, bool trans, void* x) {
   if (tb.nn <= 0) return;
-  trmv(ctx, tb.inv, tb.nn, trans, x, tb.tmp, tb.tc);
-  vec_convert(ctx, x, tb.tc, tb.tmp, tb.tc, tb.nn, false);
+  trmv_acc(ctx, tb.inv, tb.nn, trans, x, tb.tmp, tb.tc);
+  vec_move(ctx, x, tb.tmp, tb.tc, tb.nn);
 }
 
 // ------------------------------------------------------------ masked GEMV --
@@ -91,6 +94,25 @@ void vec_axpy(Ctx& ctx, void* y, int ty, double a, const void* x, int tx, int n,
                      static_cast<TY*>(y), a, static_cast<const TX*>(x), n, reverse_x ? 1 : 0);
   LSQ_DISPATCH2(ty, tx, F)
 #undef F
+  LSQ_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ void k_vec_move(T* __restrict__ dst, T* __restrict__ src, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  dst[i] = src[i];
+  src[i] = (T)0;
+}
+
+void vec_move(Ctx& ctx, void* dst, void* src, int t, int n) {
+  if (n <= 0) return;
+  if (t == 8)
+    hipLaunchKernelGGL((k_vec_move<double>), dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream,
+                       static_cast<double*>(dst), static_cast<double*>(src), n);
+  else
+    hipLaunchKernelGGL((k_vec_move<float>), dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream,
+                       static_cast<float*>(dst), static_cast<float*>(src), n);
   LSQ_LAUNCH_CHECK();
 }
 

@@ -20,12 +20,12 @@ The low-precision factorization uses LAPACK in the precision of `uf`
 formed explicitly.  Only float32 and float64 are supported as u_f here.
 
 Readings of the paper used in this module:
-* Algorithm 3, line 4 solves T22 g2 = u2 (as eq. gls-solver derives), not the
+* Algorithm 3 solves T22 g2 = u2 for g2 (as eq. gls-solver derives), not the
   transposed system printed in the algorithm.
 * The correction of z is dz = -Q h: with h defined as in the text the three
   equations of eq. gls-solver hold for h = -Q^T dz, and the ENSURE clause of
   Algorithm 3 holds for x2 = -Q h.
-* z0 = Q [0; v] (Algorithm 4, line 3, read with Q instead of Q^H).
+* z0 = Q [0; v] (Algorithm 4's initial z, read with Q instead of Q^H).
 * The default tolerance is 1e-14 and residuals are always formed in FP64.
 * When the initial r (LSE) or y (GLS) is zero, alpha falls back to
   2^(-1/2) min |diag| of the triangle of the second factorization (T1 for
@@ -111,17 +111,17 @@ def correction_lse(R, T, Z, Q, f1, f2, f3, us=np.float32):
     R, T, Z, Q = (np.asarray(M, dtype=us) for M in (R, T, Z, Q))
     f1, f2, f3 = (np.asarray(f, dtype=us) for f in (f1, f2, f3))
     T11, T12, T22 = T[:k, :k], T[:k, k:], T[k:, k:]
-    u = Q @ f3                                   # line 1
-    w = Z.T @ f1                                 # line 2
+    u = Q @ f3
+    w = Z.T @ f1
     u1, u2 = u[:k], u[k:]
     w1, w2 = w[:k], w[k:]
-    y2 = _ut(R, f2)                              # line 3
-    q1 = _ut(T11, u1, trans=True)                # line 4
-    y1 = _ut(T11, w1 - q1 - T12 @ y2)            # line 5
-    q2 = w2 - T22 @ y2                           # line 6
-    x1 = Z @ np.concatenate([q1, q2])            # line 7
+    y2 = _ut(R, f2)
+    q1 = _ut(T11, u1, trans=True)
+    y1 = _ut(T11, w1 - q1 - T12 @ y2)
+    q2 = w2 - T22 @ y2
+    x1 = Z @ np.concatenate([q1, q2])
     x3 = Q.T @ np.concatenate([y1, y2])
-    x2 = _ut(R, T12.T @ q1 + T22.T @ q2 - u2, trans=True)   # line 8
+    x2 = _ut(R, T12.T @ q1 + T22.T @ q2 - u2, trans=True)
     return (x1.astype(np.float64), x2.astype(np.float64), x3.astype(np.float64))
 
 
@@ -139,22 +139,22 @@ def correction_gls(R, T, Q, Z, f1, f2, f3, us=np.float32):
     R, T, Q, Z = (np.asarray(M, dtype=us) for M in (R, T, Q, Z))
     f1, f2, f3 = (np.asarray(f, dtype=us) for f in (f1, f2, f3))
     T11, T12, T22 = T[:m, :j], T[:m, j:], T[m:, j:]
-    u = Q.T @ f2                                 # line 1
-    w = Z @ f1                                   # line 2
+    u = Q.T @ f2
+    w = Z @ f1
     u1, u2 = u[:m], u[m:]
     w1, w2 = w[:j], w[j:]
-    h1 = _ut(R, f3, trans=True)                  # line 3
-    g2 = _ut(T22, u2)                            # line 4 (T22 g2 = u2)
-    h2 = _ut(T22, w2 - g2 - T12.T @ h1, trans=True)   # line 5
-    g1 = w1 - T11.T @ h1                         # line 6
-    dy = Z.T @ np.concatenate([g1, g2])          # line 7
+    h1 = _ut(R, f3, trans=True)
+    g2 = _ut(T22, u2)                            # T22 g2 = u2
+    h2 = _ut(T22, w2 - g2 - T12.T @ h1, trans=True)
+    g1 = w1 - T11.T @ h1
+    dy = Z.T @ np.concatenate([g1, g2])
     dz = -(Q @ np.concatenate([h1, h2]))         #   (dz = -Q h)
-    dx = _ut(R, u1 - T11 @ g1 - T12 @ g2)        # line 8
+    dx = _ut(R, u1 - T11 @ g1 - T12 @ g2)
     return (dy.astype(np.float64), dz.astype(np.float64), dx.astype(np.float64))
 
 
 # --------------------------------------------------------------------------
-# Initial guesses at u_f (Algorithms 2 and 4, lines 2-4 / 2-3)
+# Initial guesses at u_f (Algorithms 2 and 4)
 # --------------------------------------------------------------------------
 
 def _lse_initial(A, B, b, d, R, T, Z, Q, uf):
@@ -166,7 +166,7 @@ def _lse_initial(A, B, b, d, R, T, Z, Q, uf):
     c = Z.T @ bf
     y1 = _ut(T[:k, :k], c[:k] - T[:k, k:] @ y2)
     x0 = (Q.T @ np.concatenate([y1, y2])).astype(np.float64)
-    r0 = (bf - A.astype(uf) @ x0.astype(uf)).astype(np.float64)   # line 3, at u_f
+    r0 = (bf - A.astype(uf) @ x0.astype(uf)).astype(np.float64)   # at u_f
     Atr = A.T @ r0                                                  # A^T r at u_r
     v0 = _ut(R, (Q @ Atr.astype(uf))[k:], trans=True).astype(np.float64)
     return x0, r0, v0
@@ -207,21 +207,21 @@ def mplse(A, B, b, d, uf=np.float32, us=None, tol=1e-14, maxit=40):
     """Algorithm 2: mixed-precision classical refinement for LSE."""
     us = uf if us is None else us
     A, B, b, d = (np.asarray(a, dtype=np.float64) for a in (A, B, b, d))
-    R, T, Z, Q = grq_factors(B, A, uf)                              # line 1
-    x, r, v = _lse_initial(A, B, b, d, R, T, Z, Q, uf)              # lines 2-4
+    R, T, Z, Q = grq_factors(B, A, uf)
+    x, r, v = _lse_initial(A, B, b, d, R, T, Z, Q, uf)
     hist = []
     for i in range(maxit + 1):
-        f = direct.lse_residual(A, B, b, d, x, r, v)                # line 6 (FP64)
+        f = direct.lse_residual(A, B, b, d, x, r, v)                # FP64 residual
         s = direct.lse_scales(A, B, b, d, x, r, v)
         hist.append(_berr(f, s))
         if not np.all([np.all(np.isfinite(fi)) for fi in f]):
             return IRResult(x, r, v, False, i, 0, hist)
-        if _stop(f, s, tol):                                        # line 7
+        if _stop(f, s, tol):
             return IRResult(x, r, v, True, i, 0, hist)
         if i == maxit:
             break
-        dr, dv, dx = correction_lse(R, T, Z, Q, *f, us=us)          # line 10
-        r, v, x = r + dr, v + dv, x + dx                            # line 11
+        dr, dv, dx = correction_lse(R, T, Z, Q, *f, us=us)
+        r, v, x = r + dr, v + dv, x + dx
     return IRResult(x, r, v, False, maxit, 0, hist)
 
 
@@ -229,11 +229,11 @@ def mpgls(W, V, d, uf=np.float32, us=None, tol=1e-14, maxit=40):
     """Algorithm 4: mixed-precision classical refinement for GLS."""
     us = uf if us is None else us
     W, V, d = (np.asarray(a, dtype=np.float64) for a in (W, V, d))
-    R, T, Q, Z = gqr_factors(W, V, uf)                              # line 1
-    x, y, z = _gls_initial(W, V, d, R, T, Q, Z, uf)                 # lines 2-3
+    R, T, Q, Z = gqr_factors(W, V, uf)
+    x, y, z = _gls_initial(W, V, d, R, T, Q, Z, uf)
     hist = []
     for i in range(maxit + 1):
-        f = direct.gls_residual(W, V, d, x, y, z)                   # line 5 (FP64)
+        f = direct.gls_residual(W, V, d, x, y, z)                   # FP64 residual
         s = direct.gls_scales(W, V, d, x, y, z)
         hist.append(_berr(f, s))
         if not np.all([np.all(np.isfinite(fi)) for fi in f]):

@@ -252,35 +252,35 @@ struct LseSolver {
   void correct(Ctx& ctx, const double* f1, const double* f2, const double* f3, double* x,
                double* r, double* v) {
     const size_t e = (size_t)tc;
-    // line 1: u~ = Qt^T (J f3)
+    // u~ = Qt^T (J f3)
     if (f3) vec_convert(ctx, U, tc, f3, 8, n, true); else vec_zero(ctx, U, tc, n);
     agg_apply(ctx, fb, true, U, tc);
-    // line 2: w = Z^T f1
+    // w = Z^T f1
     vec_convert(ctx, Wv, tc, f1, 8, m, false);
     agg_apply(ctx, fa, true, Wv, tc);
-    // line 3: R y2 = f2  <=>  Rt^T (J y2) = J f2
+    // R y2 = f2  <=>  Rt^T (J y2) = J f2
     vec_convert(ctx, Y2, tc, f2, 8, p, true);
     trsv(ctx, tR, true, Y2);
     vec_convert(ctx, Y2n, tc, Y2, tc, p, true);
-    // line 4: T11^T q1 = u1, u1 = J u~[p:n]
+    // T11^T q1 = u1, u1 = J u~[p:n]
     vec_convert(ctx, Qv, tc, off(U, e * p), tc, k, true);
     trsv(ctx, tT11, true, Qv);
-    // line 5: T11 y1 = w1 - q1 - T12 y2
+    // T11 y1 = w1 - q1 - T12 y2
     vec_convert(ctx, Y1, tc, Wv, tc, k, false);
     vec_axpy(ctx, Y1, tc, -1.0, Qv, tc, k, false);
     gemv_upper(ctx, fa, 0, k, k, p, false, -1.0, Y2n, Y1, tc);
     trsv(ctx, tT11, false, Y1);
-    // line 6: q2 = w2 - T22 y2
+    // q2 = w2 - T22 y2
     vec_convert(ctx, off(Qv, e * k), tc, off(Wv, e * k), tc, m - k, false);
     gemv_upper(ctx, fa, k, k, m - k, p, false, -1.0, Y2n, off(Qv, e * k), tc);
-    // line 8: R^T dv = T12^T q1 + T22^T q2 - u2  <=>  Rt (J dv) = J(...)
+    // R^T dv = T12^T q1 + T22^T q2 - u2  <=>  Rt (J dv) = J(...)
     vec_zero(ctx, S, tc, p);
     gemv_upper(ctx, fa, 0, k, m, p, true, 1.0, Qv, S, tc);
     vec_axpy(ctx, S, tc, -1.0, U, tc, p, true);
     vec_convert(ctx, X2, tc, S, tc, p, true);
     trsv(ctx, tR, false, X2);
     vec_axpy(ctx, v, 8, 1.0, X2, tc, p, true);
-    // line 7: dr = Z q ; dx = Q^T y = J Qt (J y),  J y = [y2~; J y1]
+    // dr = Z q ; dx = Q^T y = J Qt (J y),  J y = [y2~; J y1]
     agg_apply(ctx, fa, false, Qv, tc);
     vec_axpy(ctx, r, 8, 1.0, Qv, tc, m, false);
     vec_convert(ctx, Yt, tc, Y2, tc, p, false);
@@ -412,35 +412,35 @@ struct GlsSolver {
   void correct(Ctx& ctx, const double* f1, const double* f2, const double* f3, double* x,
                double* y, double* z) {
     const size_t e = (size_t)tc;
-    // line 1: u = Q^T f2
+    // u = Q^T f2
     vec_convert(ctx, U, tc, f2, 8, n, false);
     agg_apply(ctx, fw, true, U, tc);
-    // line 2: w~ = J w = Zt^T (J f1)
+    // w~ = J w = Zt^T (J f1)
     if (f1) vec_convert(ctx, Wt, tc, f1, 8, p, true); else vec_zero(ctx, Wt, tc, p);
     agg_apply(ctx, fv, true, Wt, tc);
-    // line 3: R^T h1 = f3
+    // R^T h1 = f3
     if (f3) vec_convert(ctx, H1, tc, f3, 8, m, false); else vec_zero(ctx, H1, tc, m);
     trsv(ctx, tR, true, H1);
     vec_convert(ctx, H1t, tc, H1, tc, m, true);
-    // line 4: T22 g2 = u2  <=>  A11^T (J g2) = J u2
+    // T22 g2 = u2  <=>  A11^T (J g2) = J u2
     vec_convert(ctx, G, tc, off(U, e * m), tc, k, true);
     trsv(ctx, tA11, true, G);
-    // line 5: T22^T h2 = w2 - g2 - T12^T h1  <=>  A11 (J h2) = J w2 - J g2 - A12 J h1
+    // T22^T h2 = w2 - g2 - T12^T h1  <=>  A11 (J h2) = J w2 - J g2 - A12 J h1
     vec_convert(ctx, H2t, tc, Wt, tc, k, false);
     vec_axpy(ctx, H2t, tc, -1.0, G, tc, k, false);
     gemv_upper(ctx, fv, 0, k, k, m, false, -1.0, H1t, H2t, tc);
     trsv(ctx, tA11, false, H2t);
-    // line 6: g1 = w1 - T11^T h1  <=>  J g1 = J w1 - A22 J h1
+    // g1 = w1 - T11^T h1  <=>  J g1 = J w1 - A22 J h1
     vec_convert(ctx, off(G, e * k), tc, off(Wt, e * k), tc, p - k, false);
     gemv_upper(ctx, fv, k, k, p - k, m, false, -1.0, H1t, off(G, e * k), tc);
-    // line 8: R dx = u1 - T11 g1 - T12 g2 = u1 - J (Rv[:, k:n]^T (J g))
+    // R dx = u1 - T11 g1 - T12 g2 = u1 - J (Rv[:, k:n]^T (J g))
     vec_zero(ctx, S, tc, m);
     gemv_upper(ctx, fv, 0, k, p, m, true, 1.0, G, S, tc);
     vec_convert(ctx, X, tc, U, tc, m, false);
     vec_axpy(ctx, X, tc, -1.0, S, tc, m, true);
     trsv(ctx, tR, false, X);
     vec_axpy(ctx, x, 8, 1.0, X, tc, m, false);
-    // line 7: dz = -Q h, h = [h1; J h2~] ; dy = Z^T g = J Zt (J g)
+    // dz = -Q h, h = [h1; J h2~] ; dy = Z^T g = J Zt (J g)
     vec_convert(ctx, Hv, tc, H1, tc, m, false);
     vec_convert(ctx, off(Hv, e * m), tc, H2t, tc, k, true);
     agg_apply(ctx, fw, false, Hv, tc);

@@ -265,8 +265,8 @@ def test_algorithm3_ensure_identity_fp64(n, m, p):
 
 
 def test_algorithm3_as_printed_fails_ensure(monkeypatch):
-    """Planted mistakes: the printed T22^H in line 4 and the printed sign of
-    x2 each break the ENSURE identity, so the pins above would catch them."""
+    """Planted mistakes: the printed T22^H in Algorithm 3's solve for g2 and the
+    printed sign of x2 each break the ENSURE identity, so the pins above would catch them."""
     G = wl.gls_gaussian(_rng(42), 12, 4, 30)
     R, T, Q, Z = mpir.gqr_factors(G.W, G.V, np.float64)
     rng = _rng(43)
@@ -278,7 +278,7 @@ def test_algorithm3_as_printed_fails_ensure(monkeypatch):
 
     def wrong(Tm, rhs, trans=False):
         calls["n"] += 1
-        if calls["n"] == 2:                                       # line 4 as printed
+        if calls["n"] == 2:                                       # the solve for g2 as printed
             return orig(Tm, rhs, trans=True)
         return orig(Tm, rhs, trans)
     monkeypatch.setattr(mpir, "_ut", wrong)

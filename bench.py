@@ -11,7 +11,7 @@ RQ factorization at u_f, initial guess, and refinement until the stopping
 test (eq. lse-stop, tol = 1e-14) holds; a solve that does not certify
 berr <= 1e-14 is not counted.
 
-Prints one JSON line (rank 0 only; this build uses one GPU).
+Prints one JSON line (rank 0 only; the solver runs on one GPU).
 """
 from __future__ import annotations
 
@@ -370,8 +370,8 @@ def single_gmres(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the batched path would shard instances across GPUs, see the design notes)",
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU run would shard the batched instances across GPUs)",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":

@@ -3,8 +3,9 @@
     python -m paper_2406_16499_amd.build        # or build() from Python
 
 Every call compiles from source: one hipcc invocation per translation unit
-(in parallel) and one link step.  Packed FP32 instructions are disabled for
-the device code (see the note in the repository's design notes on v_pk_*_f32).
+(in parallel) and one link step.  Packed FP32 instructions (v_pk_*_f32) are
+disabled for the device code: some of their forms have given wrong results on
+this hardware without any error, so the compiler must not form them.
 """
 from __future__ import annotations
 

@@ -15,7 +15,7 @@
 // The initial guess of Algorithms 2 and 4 (null-space / Paige solution at
 // u_f, then r0, v0 resp. z0) equals, in exact arithmetic, one correction
 // solve started from the zero iterate with residual (b, d, 0) resp. (0, d, 0);
-// the drivers compute it that way.  Residuals and updates are FP64.
+// the solvers here compute it that way.  Residuals and updates are FP64.
 #include <algorithm>
 #include <atomic>
 #include <functional>

@@ -60,10 +60,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel", default="panel_final_y", choices=sorted(KERNELS))
     ap.add_argument("--workload", default="lse-large",
-                    choices=["lse-large", "gls-large", "lse-wide", "gls-tall", "batched"],
+                    choices=["lse-large", "gls-large", "lse-wide", "gls-tall", "paper-grid", "batched"],
                     help="lse-large: the single 4096x2048x256 LSE (default); gls-large: the "
                          "4096x1024x4096 GLS with GMRES-IR; lse-wide: LSE 2048x4096x2560 (n > m) "
                          "with GMRES-IR; gls-tall: GLS 4096x2560x2048 (n > p) with GMRES-IR; "
+                         "paper-grid: the paper's experiment shapes against the GPU FP64 path; "
                          "batched: the 2000-instance mixed LSE/GLS workload")
     ap.add_argument("--count", type=int, default=2000, help="instances of the batched workload")
     ap.add_argument("--workers", type=int, default=8, help="batch workers (streams)")
@@ -367,6 +368,102 @@ def single_gmres(args):
         "certified_solves": ok, "last_result": last}))
 
 
+PAPER_GRID_WORKLOAD = ("the paper's experiment shapes (Section 6): LSE m > n >> p (n 1024, (m, p) = "
+                       "(8n, n/32), (12n, n/64)) and m >> n > p (n 128, (m, p) = (128n, n/8)); GLS "
+                       "(n 1024, (p, m) = (8n, n/32), (12n, n/64)); [A^T, B^T] resp. [W, V] = "
+                       "U diag(s) V^T with log-spaced s, kappa 1e3..1e9; RHS N(0,1); seed 11")
+
+
+def paper_grid(args):
+    """The paper's experiment shapes on the GPU: for every case, the FP32
+    factorization with classical IR and with GMRES-IR (escalation on), and the
+    FP64 direct path; times, refinement steps, backward errors and the
+    distance of the mixed solution from the FP64 one (the relative-time and
+    error columns of Tables 4 and 5, against the GPU FP64 path)."""
+    import torch
+    from paper_2406_16499_amd import lsq
+    from paper_2406_16499_amd import workloads as wl
+    h = lsq.Handle(load_selector=False)
+    rng = np.random.default_rng(11)
+    cases = []
+    for kappa in (1e3, 1e5, 1e7, 1e9):
+        for (fm, fp) in ((8, 32), (12, 64)):
+            cases.append(("E1", "lse", 1024, fm, fp, kappa))
+    cases.append(("E2", "lse", 128, 128, 8, 1e5))
+    for kappa in (1e3, 1e5, 1e7, 1e9):
+        for (fm, fp) in ((8, 32), (12, 64)):
+            cases.append(("E3", "gls", 1024, fm, fp, kappa))
+    rows = []
+    t_mixed = t_fp64 = 0.0
+    ok_mixed = ok_fp64 = 0
+    for (exp, kind, n, fm, fp, kappa) in cases:
+        if kind == "lse":
+            m, p = fm * n, n // fp
+            P = wl.lse_paper_pair(rng, m, n, p, kappa)
+            A, B, b, d = (lsq.colmajor(a) for a in (P.A, P.B, P.b, P.d))
+            x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+            solve = lambda o: h.lse_solve(A, B, b, d, x, r, v, o)
+            sol = lambda: x.detach().cpu().numpy().copy()
+            shape = {"m": m, "n": n, "p": p}
+        else:
+            p_, m_ = fm * n, n // fp
+            G = wl.gls_paper_pair(rng, n, m_, p_, kappa)
+            W, V, d = (lsq.colmajor(a) for a in (G.W, G.V, G.d))
+            x, y, z = lsq.empty(m_), lsq.empty(p_), lsq.empty(n)
+            solve = lambda o: h.gls_solve(W, V, d, x, y, z, o)
+            sol = lambda: np.concatenate([x.detach().cpu().numpy(), y.detach().cpu().numpy()])
+            shape = {"n": n, "m": m_, "p": p_}
+        out = {"exp": exp, "kind": kind, **shape, "kappa": kappa}
+        ref = None
+        for name, opts in (("fp64", lsq.default_opts(prec="fp64", solver="direct")),
+                           ("ir", lsq.default_opts(prec="fp32", solver="ir", escalate=1)),
+                           ("gmres", lsq.default_opts(prec="fp32", solver="gmres", escalate=1))):
+            for _ in range(args.warmup):
+                solve(opts)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ok = 0
+            for _ in range(args.steps):
+                rc, res = solve(opts)
+                ok += int(rc == 0 and res.berr_max <= 1e-14)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            dd = res.as_dict()
+            xs = sol()
+            if name == "fp64":
+                ref = xs
+            den = float(np.max(np.abs(ref))) if ref is not None and ref.size else 0.0
+            dist = float(np.max(np.abs(xs - ref)) / den) if den > 0 else 0.0
+            out[name] = {"ms": 1000.0 * dt, "certified": ok, "steps": args.steps,
+                         "rung": f"{dd['prec_used']}/{dd['solver_used']}", "attempts": dd["attempts"],
+                         "ir_steps": dd["ir_steps"], "gmres_iters": dd["gmres_iters"],
+                         "berr": dd["berr_max"], "dist_to_fp64": dist}
+        t_fp64 += out["fp64"]["ms"]
+        ok_fp64 += out["fp64"]["certified"]
+        best = min((out["ir"], out["gmres"]), key=lambda e: e["ms"])
+        t_mixed += best["ms"]
+        ok_mixed += best["certified"]
+        out["time_ratio_best_mixed_vs_fp64"] = best["ms"] / out["fp64"]["ms"]
+        rows.append(out)
+        print(f"[grid] {exp} {kind} {shape} kappa={kappa:g} fp64 {out['fp64']['ms']:.1f} ms, "
+              f"ir {out['ir']['ms']:.1f} ms ({out['ir']['rung']}), gmres {out['gmres']['ms']:.1f} ms "
+              f"({out['gmres']['rung']})", file=sys.stderr, flush=True)
+    ncase = len(rows)
+    value = 1000.0 * ncase / t_mixed if t_mixed > 0 else 0.0
+    print(json.dumps({
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_mixed, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (residuals, updates) / fp32 (factorization)",
+        "data": "synthetic",
+        "config": {"workload": PAPER_GRID_WORKLOAD, "cases": ncase,
+                   "solver": "per case the faster of classical IR and GMRES-IR (FP32 factors, escalation on)",
+                   "tol": 1e-14},
+        "fp64_direct": {"value": 1000.0 * ncase / t_fp64 if t_fp64 > 0 else 0.0, "unit": "solves/s",
+                        "ms_per_step": t_fp64},
+        "speedup_vs_fp64": t_fp64 / t_mixed if t_mixed > 0 else None,
+        "certified_mixed": ok_mixed, "certified_fp64": ok_fp64, "cases": rows}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -378,6 +475,8 @@ def main():
         return batched(args)
     if args.workload in ("gls-large", "lse-wide", "gls-tall"):
         return single_gmres(args)
+    if args.workload == "paper-grid":
+        return paper_grid(args)
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl

@@ -140,7 +140,7 @@ def gls_paper_pair(rng, n, m, p, kappa) -> GLSProblem:
 
 
 # --------------------------------------------------------------------------
-# The named workloads.  Sizes follow the workload list of the build; smaller
+# The named workloads (the benchmark configurations); smaller
 # "scaled" variants keep the same structure for fast tests.
 # --------------------------------------------------------------------------
 

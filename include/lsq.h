@@ -126,6 +126,46 @@ int gls_solve(lsq_handle handle, int n, int m, int p,
               const double* d, double* x, double* y, double* z,
               const lsq_opts* opts, lsq_result* res);
 
+/*
+ * Factor once, solve many right-hand sides.  lse_factor / gls_factor compute
+ * the generalized RQ / QR factorization of the pair (Sections 3.1, 3.2) at
+ * precision `prec` (an lsq_prec other than AUTO) into a new factors object,
+ * which owns its own device memory.  The object keeps the pointers A and B:
+ * the FP64 residual of every later solve reads them, so both must stay
+ * allocated and unchanged until lsq_factors_destroy.  Returns 0 and sets
+ * *factors, 1 if a panel factorization broke down at this precision (no
+ * object is made), 4 on a HIP error, or -k for argument k (the numbers of
+ * lse_solve / gls_solve for the shared arguments; 9 prec, 10 factors).
+ */
+typedef struct lsq_factors_st* lsq_factors;
+int lse_factor(lsq_handle handle, int m, int n, int p,
+               const double* A, int lda, const double* B, int ldb,
+               int prec, lsq_factors* factors);
+int gls_factor(lsq_handle handle, int n, int m, int p,
+               const double* A, int lda, const double* B, int ldb,
+               int prec, lsq_factors* factors);
+/*
+ * Refinement on stored factors (the correction solves of Algorithms 1 / 3,
+ * or GMRES-IR of Section 5), with the right-hand sides b, d (LSE) or d (GLS)
+ * of this call: opts->solver IR (or AUTO) or GMRES_IR; with FP64 factors the
+ * FP64 direct solve.  The first solve of a kind also prepares the factors'
+ * triangular inverses and aggregated blocks for it; later solves reuse them.
+ * There is no escalation: a solve that does not certify returns 3 with its
+ * last iterate.  res->ms_factor is 0.  Only the handle that made the factors
+ * may use them (-2 otherwise).  Argument numbers for -k: 2 factors, 3 b,
+ * 4 d, 5 x, 8 opts (LSE); 2 factors, 3 d, 4 x, 5 y, 7 opts (GLS).
+ */
+int lse_solve_factored(lsq_handle handle, lsq_factors factors,
+                       const double* b, const double* d,
+                       double* x, double* r, double* v,
+                       const lsq_opts* opts, lsq_result* res);
+int gls_solve_factored(lsq_handle handle, lsq_factors factors,
+                       const double* d, double* x, double* y, double* z,
+                       const lsq_opts* opts, lsq_result* res);
+/* Frees the factors' device memory (NULL is a no-op).  Call it before
+ * lsq_destroy of the handle that made them, with no solve in flight. */
+int lsq_factors_destroy(lsq_factors factors);
+
 /* One instance of a batch.  type: LSQ_LSE or LSQ_GLS; sizes and pointers as in
    lse_solve (m, n, p, A, B, b, d, x) or gls_solve (n, m, p with A = W, B = V,
    d, x, y).  Pointers are device pointers; b is ignored for GLS and y for LSE. */

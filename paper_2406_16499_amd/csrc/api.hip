@@ -216,6 +216,11 @@ struct LseSolver {
   int m, n, p, k;
   int prec_id = 0;        // lsq_prec of the factors
   float ms_factor = 0.0f;
+  // Factors kept across calls (lse_factor): prepare() goes to this context's
+  // arena once per compute precision instead of once per call.
+  Ctx* pctx = nullptr;
+  int prepared_tc = 0;
+  bool prepared_gmres = false;
   PrecSpec ps;
   int tc;                 // compute precision of the correction solve
   QRFactor fb, fa;        // QR of Bt (n x p) and of Abar (m x n)
@@ -375,6 +380,9 @@ struct GlsSolver {
   int n, m, p, k;         // k = n - m
   int prec_id = 0;        // lsq_prec of the factors
   float ms_factor = 0.0f;
+  Ctx* pctx = nullptr;    // as for LseSolver
+  int prepared_tc = 0;
+  bool prepared_gmres = false;
   PrecSpec ps;
   int tc;
   QRFactor fw, fv;        // QR of W (n x m) and of Vt (p x n)
@@ -659,6 +667,19 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
   return out;
 }
 
+// Prepares the solver's triangular inverses, aggregated blocks and vectors for
+// corrections in precision tc (with the GMRES operator's extras if gmres).
+// A solver whose factors outlive the call (pctx set) keeps what it prepared
+// in pctx's arena and prepares again only when tc or the solver kind changes.
+template <typename Solver>
+void ensure_prepared(Solver& sv, Ctx& ctx, int tc, bool gmres) {
+  if (sv.pctx && sv.prepared_tc == tc && (sv.prepared_gmres || !gmres)) return;
+  Ctx& pc = sv.pctx ? *sv.pctx : ctx;
+  if (gmres) sv.prepare_gmres(pc); else sv.prepare(pc, tc);
+  sv.prepared_tc = tc;
+  sv.prepared_gmres = gmres;
+}
+
 // One precision of the ladder for LSE: the factorization at prec, then the
 // refinement solvers in order on the same factors (IR: Algorithm 2; GMRES:
 // GMRES-IR; DIRECT: the FP64 factors with the classical loop).
@@ -721,7 +742,7 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
     ++attempts;
     solver_used = solver;
     if (solver == LSQ_SOLVER_GMRES_IR) {
-      sv.prepare_gmres(ctx);
+      ensure_prepared(sv, ctx, 8, true);
       const int m = a.m, p = a.p, n = a.n;
       out = run_gmres(
           h, sv, a, m + p + n, zero, init, residual,
@@ -742,7 +763,7 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
           },
           o);
     } else {
-      sv.prepare(ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc);
+      ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
                           [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o);
     }
@@ -781,7 +802,7 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
     ++attempts;
     solver_used = solver;
     if (solver == LSQ_SOLVER_GMRES_IR) {
-      sv.prepare_gmres(ctx);
+      ensure_prepared(sv, ctx, 8, true);
       const int m = a.m, p = a.p, n = a.n;
       out = run_gmres(
           h, sv, a, p + n + m, zero, init, residual,
@@ -802,7 +823,7 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
           },
           o);
     } else {
-      sv.prepare(ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc);
+      ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
                           [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o);
     }
@@ -1257,6 +1278,44 @@ int gls_check(int n, int m, int p, const double* W, int ldw, const double* V, in
 }
 }  // namespace
 
+// Factors kept across calls: the solver object and the arena that holds its
+// factors and prepared structures; ctx is the handle's context with this
+// arena (its stream is refreshed from the handle at every call).
+struct lsq_factors_st {
+  lsq_handle owner = nullptr;
+  int device = 0;
+  int type = 0;
+  int prec = 0;
+  int m = 0, n = 0, p = 0, lda = 1, ldb = 1;
+  const double* A = nullptr;
+  const double* B = nullptr;
+  Arena arena;
+  Ctx ctx;
+  LseSolver lse;
+  GlsSolver gls;
+};
+
+namespace {
+
+// The refinement solvers a factored solve runs: FP64 factors give the FP64
+// direct solve; otherwise classical IR (IR or AUTO) or GMRES-IR.
+bool factored_solvers(int prec, int solver, std::vector<int>& out) {
+  out.clear();
+  if (prec == LSQ_PREC_FP64) { out.push_back(LSQ_SOLVER_DIRECT); return true; }
+  if (solver == LSQ_SOLVER_AUTO || solver == LSQ_SOLVER_IR) { out.push_back(LSQ_SOLVER_IR); return true; }
+  if (solver == LSQ_SOLVER_GMRES_IR) { out.push_back(LSQ_SOLVER_GMRES_IR); return true; }
+  return false;   // DIRECT needs FP64 factors
+}
+
+void factors_free(lsq_factors f) {
+  if (!f) return;
+  (void)hipSetDevice(f->device);
+  f->arena.release();
+  delete f;
+}
+
+}  // namespace
+
 extern "C" {
 
 int lse_solve(lsq_handle h, int m, int n, int p, const double* A, int lda, const double* B,
@@ -1447,6 +1506,157 @@ int lsq_selector_features(lsq_handle h, const lsq_problem* q, float* feats, floa
     if (cls) { cls[0] = sl.cls[0]; cls[1] = sl.cls[1]; }
     return 0;
   });
+}
+
+int lse_factor(lsq_handle h, int m, int n, int p, const double* A, int lda, const double* B,
+               int ldb, int prec, lsq_factors* factors) {
+  if (!h) return -1;
+  std::string why;
+  static const double one = 0.0;
+  const int bad = lse_check(m, n, p, A, lda, B, ldb, &one, &one, &one, &why);
+  if (bad) return fail(h, bad, why);
+  PrecSpec ps;
+  if (prec == LSQ_PREC_AUTO || !prec_spec(prec, ps)) return fail(h, -9, "invalid precision");
+  if (!factors) return fail(h, -10, "factors is null");
+  *factors = nullptr;
+  lsq_factors f = new lsq_factors_st();
+  f->owner = h; f->device = h->w.device; f->type = LSQ_LSE; f->prec = prec;
+  f->m = m; f->n = n; f->p = p; f->A = A; f->lda = lda; f->B = B; f->ldb = ldb;
+  const int rc = guard(h, "lse_factor", [&]() -> int {
+    f->ctx = h->w.ctx;
+    f->ctx.ws = &f->arena;
+    LseSolver& sv = f->lse;
+    sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.prec_id = prec; sv.ps = ps;
+    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb);
+    const int sb = read_int(&h->w, sv.fb.status);
+    const int sa = read_int(&h->w, sv.fa.status);
+    return (sb || sa) ? 1 : 0;
+  });
+  if (rc != 0) {
+    factors_free(f);
+    if (rc == 1) h->last_error = "lse_factor: a panel factorization broke down at this precision";
+    return rc;
+  }
+  *factors = f;
+  return 0;
+}
+
+int gls_factor(lsq_handle h, int n, int m, int p, const double* W, int ldw, const double* V,
+               int ldv, int prec, lsq_factors* factors) {
+  if (!h) return -1;
+  std::string why;
+  static const double one = 0.0;
+  const int bad = gls_check(n, m, p, W, ldw, V, ldv, &one, &one, &one, &why);
+  if (bad) return fail(h, bad, why);
+  PrecSpec ps;
+  if (prec == LSQ_PREC_AUTO || !prec_spec(prec, ps)) return fail(h, -9, "invalid precision");
+  if (!factors) return fail(h, -10, "factors is null");
+  *factors = nullptr;
+  lsq_factors f = new lsq_factors_st();
+  f->owner = h; f->device = h->w.device; f->type = LSQ_GLS; f->prec = prec;
+  f->m = m; f->n = n; f->p = p; f->A = W; f->lda = ldw; f->B = V; f->ldb = ldv;
+  const int rc = guard(h, "gls_factor", [&]() -> int {
+    f->ctx = h->w.ctx;
+    f->ctx.ws = &f->arena;
+    GlsSolver& sv = f->gls;
+    sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.prec_id = prec; sv.ps = ps;
+    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb);
+    const int sw = read_int(&h->w, sv.fw.status);
+    const int sv_ = read_int(&h->w, sv.fv.status);
+    return (sw || sv_) ? 1 : 0;
+  });
+  if (rc != 0) {
+    factors_free(f);
+    if (rc == 1) h->last_error = "gls_factor: a panel factorization broke down at this precision";
+    return rc;
+  }
+  *factors = f;
+  return 0;
+}
+
+int lse_solve_factored(lsq_handle h, lsq_factors f, const double* b, const double* d, double* x,
+                       double* r, double* v, const lsq_opts* opts, lsq_result* res) {
+  if (!h) return -1;
+  if (!f || f->type != LSQ_LSE) return fail(h, -2, "factors are not LSE factors");
+  if (f->owner != h) return fail(h, -2, "factors belong to another handle");
+  const int m = f->m, n = f->n, p = f->p;
+  if (!b && m > 0) return fail(h, -3, "b is null");
+  if (!d && p > 0) return fail(h, -4, "d is null");
+  if (!x && n > 0) return fail(h, -5, "x is null");
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  std::vector<int> solvers;
+  if (!(o.tol >= 0) || o.maxit < 0 || !factored_solvers(f->prec, o.solver, solvers))
+    return fail(h, -8, "invalid options");
+  return guard(h, "lse_solve_factored", [&]() -> int {
+    Worker* w = &h->w;
+    Ctx& ctx = w->ctx;
+    Arena* keep = f->ctx.ws;
+    f->ctx = w->ctx;                     // the handle's current stream and events
+    f->ctx.ws = keep;
+    f->lse.pctx = &f->ctx;
+    LseArgs a{m, n, p, f->A, f->B, b, d, f->lda, f->ldb};
+    frob_norms(ctx, f->A, f->lda, m, n, f->B, f->ldb, p, n, b, m, d, p, w->matnorms);
+    double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
+    double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
+    double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
+    int attempts = 0, used_s = 0;
+    RungOut ro = lse_rung(w, a, f->prec, solvers, o, xi, ri, vi, attempts, used_s, &f->lse, true);
+    ro.ms_factor = 0.0f;
+    const int info = ro.ok ? 0 : 3;
+    if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+    if (r && m > 0) LSQ_HIP(hipMemcpyAsync(r, ri, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
+    if (v && p > 0) LSQ_HIP(hipMemcpyAsync(v, vi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
+    LSQ_HIP(hipStreamSynchronize(w->stream));
+    fill_result(res, info, f->prec, used_s, attempts, ro);
+    return info;
+  });
+}
+
+int gls_solve_factored(lsq_handle h, lsq_factors f, const double* d, double* x, double* y,
+                       double* z, const lsq_opts* opts, lsq_result* res) {
+  if (!h) return -1;
+  if (!f || f->type != LSQ_GLS) return fail(h, -2, "factors are not GLS factors");
+  if (f->owner != h) return fail(h, -2, "factors belong to another handle");
+  const int n = f->n, m = f->m, p = f->p;
+  if (!d && n > 0) return fail(h, -3, "d is null");
+  if (!x && m > 0) return fail(h, -4, "x is null");
+  if (!y && p > 0) return fail(h, -5, "y is null");
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  std::vector<int> solvers;
+  if (!(o.tol >= 0) || o.maxit < 0 || !factored_solvers(f->prec, o.solver, solvers))
+    return fail(h, -7, "invalid options");
+  return guard(h, "gls_solve_factored", [&]() -> int {
+    Worker* w = &h->w;
+    Ctx& ctx = w->ctx;
+    Arena* keep = f->ctx.ws;
+    f->ctx = w->ctx;
+    f->ctx.ws = keep;
+    f->gls.pctx = &f->ctx;
+    GlsArgs a{n, m, p, f->A, f->B, d, f->lda, f->ldb};
+    frob_norms(ctx, f->A, f->lda, n, m, f->B, f->ldb, n, p, d, n, nullptr, 0, w->matnorms);
+    double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
+    double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
+    double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
+    int attempts = 0, used_s = 0;
+    RungOut ro = gls_rung(w, a, f->prec, solvers, o, xi, yi, zi, attempts, used_s, &f->gls, true);
+    ro.ms_factor = 0.0f;
+    const int info = ro.ok ? 0 : 3;
+    if (m > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
+    if (p > 0) LSQ_HIP(hipMemcpyAsync(y, yi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
+    if (z && n > 0) LSQ_HIP(hipMemcpyAsync(z, zi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+    LSQ_HIP(hipStreamSynchronize(w->stream));
+    fill_result(res, info, f->prec, used_s, attempts, ro);
+    return info;
+  });
+}
+
+int lsq_factors_destroy(lsq_factors f) {
+  factors_free(f);
+  return 0;
 }
 
 int lse_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
@@ -1703,7 +1913,7 @@ int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p
       sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
       LseArgs a{m, n, p, A, B, nullptr, nullptr, lda, ldb};
       sv.factor(ctx, A, lda, B, ldb, kMaxNb);
-      sv.prepare_gmres(ctx);
+      ensure_prepared(sv, ctx, 8, true);
       sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
       std::function<void(const double*, double*)> op = [&](const double* u, double* y) {
         sv.m_right(ctx, u, sv.t1);
@@ -1716,7 +1926,7 @@ int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p
       sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.ps = ps;
       GlsArgs a{n, m, p, A, B, nullptr, lda, ldb};
       sv.factor(ctx, A, lda, B, ldb, kMaxNb);
-      sv.prepare_gmres(ctx);
+      ensure_prepared(sv, ctx, 8, true);
       sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
       std::function<void(const double*, double*)> op = [&](const double* u, double* y) {
         sv.m_right(ctx, u, sv.t1);
@@ -1748,7 +1958,7 @@ int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, cons
       sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.ps = ps;
       LseArgs a{m, n, p, A, B, nullptr, nullptr, lda, ldb};
       sv.factor(ctx, A, lda, B, ldb, kMaxNb);
-      sv.prepare_gmres(ctx);
+      ensure_prepared(sv, ctx, 8, true);
       sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
       sv.m_right(ctx, u, sv.t1);
       sv.f_apply(ctx, a, sv.t1, sv.t2);
@@ -1758,7 +1968,7 @@ int lsq_dbg_bd_apply(lsq_handle h, int type, int prec, int m, int n, int p, cons
       sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.ps = ps;
       GlsArgs a{n, m, p, A, B, nullptr, lda, ldb};
       sv.factor(ctx, A, lda, B, ldb, kMaxNb);
-      sv.prepare_gmres(ctx);
+      ensure_prepared(sv, ctx, 8, true);
       sv.alpha = alpha; sv.beta = beta; sv.sa = std::sqrt(alpha);
       sv.m_right(ctx, u, sv.t1);
       sv.f_apply(ctx, a, sv.t1, sv.t2);

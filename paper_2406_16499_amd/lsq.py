@@ -66,6 +66,15 @@ _SIGS = {
                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
     "gls_solve": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P, _P,
                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
+    "lse_factor": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, c_int,
+                           ctypes.POINTER(c_void_p)]),
+    "gls_factor": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, c_int,
+                           ctypes.POINTER(c_void_p)]),
+    "lse_solve_factored": (c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts),
+                                   ctypes.POINTER(Result)]),
+    "gls_solve_factored": (c_int, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts),
+                                   ctypes.POINTER(Result)]),
+    "lsq_factors_destroy": (c_int, [_P]),
     "lsq_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                   ctypes.POINTER(Result)]),
     "lsq_set_batch_workers": (c_int, [_P, c_int]),
@@ -186,6 +195,41 @@ def _ld(t):
     return max(int(t.stride(1)) if c > 1 else r, 1)
 
 
+class Factors:
+    """Stored factors of one pair (lse_factor / gls_factor); keeps the pair's
+    tensors alive, since every solve's FP64 residual reads them."""
+
+    def __init__(self, handle, ptr, kind, shape, keep):
+        self.handle, self.f, self.kind, self.shape, self._keep = handle, ptr, kind, shape, keep
+
+    def solve(self, *vecs, opts: Optional[Opts] = None):
+        """LSE: solve(b, d, x, r=None, v=None); GLS: solve(d, x, y, z=None)."""
+        lib, res = self.handle.lib, Result()
+        o = ctypes.byref(opts) if opts is not None else None
+        if self.kind == "lse":
+            b, d, x, *rest = vecs
+            r, v = (rest + [None, None])[:2]
+            rc = lib.lse_solve_factored(self.handle.h, self.f, _ptr(b), _ptr(d), _ptr(x), _ptr(r),
+                                        _ptr(v), o, ctypes.byref(res))
+        else:
+            d, x, y, *rest = vecs
+            z = (rest + [None])[0]
+            rc = lib.gls_solve_factored(self.handle.h, self.f, _ptr(d), _ptr(x), _ptr(y), _ptr(z),
+                                        o, ctypes.byref(res))
+        return rc, res
+
+    def close(self):
+        if self.f:
+            self.handle.lib.lsq_factors_destroy(self.f)
+            self.f = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Handle:
     """Owns an lsq_handle bound to the current torch device and stream."""
 
@@ -262,6 +306,28 @@ class Handle:
                                 _ptr(x), _ptr(y), _ptr(z),
                                 ctypes.byref(opts) if opts is not None else None, ctypes.byref(res))
         return rc, res
+
+    def lse_factor(self, A, B, prec: str = "fp32") -> "Factors":
+        """Factor (A, B) once at `prec`; A and B must outlive the returned object."""
+        m, n = A.shape
+        p = B.shape[0]
+        f = c_void_p()
+        rc = self.lib.lse_factor(self.h, m, n, p, _ptr(A), _ld(A), _ptr(B), _ld(B) if p else 1,
+                                 PREC[prec], ctypes.byref(f))
+        if rc != 0:
+            raise RuntimeError(f"lse_factor = {rc}: {self.last_error()}")
+        return Factors(self, f, "lse", (m, n, p), (A, B))
+
+    def gls_factor(self, W, V, prec: str = "fp32") -> "Factors":
+        """Factor (W, V) once at `prec`; W and V must outlive the returned object."""
+        n, m = W.shape
+        p = V.shape[1]
+        f = c_void_p()
+        rc = self.lib.gls_factor(self.h, n, m, p, _ptr(W), _ld(W), _ptr(V), _ld(V),
+                                 PREC[prec], ctypes.byref(f))
+        if rc != 0:
+            raise RuntimeError(f"gls_factor = {rc}: {self.last_error()}")
+        return Factors(self, f, "gls", (n, m, p), (W, V))
 
     def lsq_solve_batched(self, problems, opts: Optional[Opts] = None, which: str = "lsq"):
         arr = (Problem * len(problems))(*problems)

@@ -211,6 +211,21 @@ struct GlsArgs {
   int ldw, ldv;
 };
 
+// One timing-free event owned by a solver (created on first use).
+struct SolverEvent {
+  hipEvent_t e = nullptr;
+  SolverEvent() = default;
+  SolverEvent(const SolverEvent&) = delete;
+  SolverEvent& operator=(const SolverEvent&) = delete;
+  ~SolverEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  hipEvent_t get() {
+    if (!e) LSQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return e;
+  }
+};
+
 // ----------------------------------------------------------------- LSE ----
 struct LseSolver {
   int m, n, p, k;
@@ -221,6 +236,12 @@ struct LseSolver {
   Ctx* pctx = nullptr;
   int prepared_tc = 0;
   bool prepared_gmres = false;
+  // The B-side structures (R's inverse, B's aggregated blocks) depend on fb
+  // only: factor() prepares them on the side stream while the main stream
+  // works on Abar; b_tc is the precision they are prepared for.
+  SolverEvent ev_b;
+  bool b_pending = false;
+  int b_tc = 0;
   PrecSpec ps;
   int tc;                 // compute precision of the correction solve
   QRFactor fb, fa;        // QR of Bt (n x p) and of Abar (m x n)
@@ -232,10 +253,28 @@ struct LseSolver {
     U = v(n); Wv = v(m); Y2 = v(p); Y2n = v(p); Qv = v(m); Y1 = v(k); S = v(p); X2 = v(p); Yt = v(n);
   }
 
-  void factor(Ctx& ctx, const double* A, int lda, const double* B, int ldb, int nb) {
+  void prepare_b(Ctx& ctx, int tc_) {
+    trsv_prepare(ctx, tR, fb, 0, p, tc_);
+    agg_prepare(ctx, fb, tc_, kAggPanels);
+    b_tc = tc_;
+  }
+
+  // early_tc > 0: prepare the B-side structures for that precision on the
+  // side stream, overlapping the rest of the factorization.
+  void factor(Ctx& ctx, const double* A, int lda, const double* B, int ldb, int nb, int early_tc = 0) {
     qr_alloc(ctx, fb, n, p, ps.tw, ps.mt, nb);
     mat_convert(ctx, fb.M, ps.tw, fb.ld, B, 8, ldb, n, p, true, true, true);
     qr_factor(ctx, fb);
+    if (early_tc > 0 && ctx.side) {
+      hipEvent_t e = ev_b.get();
+      LSQ_HIP(hipEventRecord(e, ctx.stream));
+      LSQ_HIP(hipStreamWaitEvent(ctx.side, e, 0));
+      Ctx sctx = ctx;
+      sctx.stream = ctx.side;
+      prepare_b(sctx, early_tc);
+      LSQ_HIP(hipEventRecord(e, ctx.side));
+      b_pending = true;
+    }
     void* X0 = ctx.ws->alloc((size_t)ps.tw * (size_t)(n > 0 ? n : 1) * (m > 0 ? m : 1));
     mat_convert(ctx, X0, ps.tw, n > 0 ? n : 1, A, 8, lda, n, m, true, false, true);
     qr_apply_left_T(ctx, fb, X0, n > 0 ? n : 1, m);
@@ -246,9 +285,12 @@ struct LseSolver {
 
   void prepare(Ctx& ctx, int tc_) {
     tc = tc_;
-    trsv_prepare(ctx, tR, fb, 0, p, tc);
+    if (b_pending) {
+      LSQ_HIP(hipStreamWaitEvent(ctx.stream, ev_b.get(), 0));
+      b_pending = false;
+    }
+    if (b_tc != tc) prepare_b(ctx, tc);
     trsv_prepare(ctx, tT11, fa, 0, k, tc);
-    agg_prepare(ctx, fb, tc, kAggPanels);
     agg_prepare(ctx, fa, tc, kAggPanels);
     alloc_vectors(ctx);
   }
@@ -383,6 +425,9 @@ struct GlsSolver {
   Ctx* pctx = nullptr;    // as for LseSolver
   int prepared_tc = 0;
   bool prepared_gmres = false;
+  SolverEvent ev_w;       // W-side structures prepared early (as LseSolver's B side)
+  bool w_pending = false;
+  int w_tc = 0;
   PrecSpec ps;
   int tc;
   QRFactor fw, fv;        // QR of W (n x m) and of Vt (p x n)
@@ -394,10 +439,26 @@ struct GlsSolver {
     U = v(n); Wt = v(p); H1 = v(m); H1t = v(m); G = v(p); H2t = v(k); S = v(m); X = v(m); Hv = v(n);
   }
 
-  void factor(Ctx& ctx, const double* W, int ldw, const double* V, int ldv, int nb) {
+  void prepare_w(Ctx& ctx, int tc_) {
+    trsv_prepare(ctx, tR, fw, 0, m, tc_);
+    agg_prepare(ctx, fw, tc_, kAggPanels);
+    w_tc = tc_;
+  }
+
+  void factor(Ctx& ctx, const double* W, int ldw, const double* V, int ldv, int nb, int early_tc = 0) {
     qr_alloc(ctx, fw, n, m, ps.tw, ps.mt, nb);
     mat_convert(ctx, fw.M, ps.tw, fw.ld, W, 8, ldw, n, m, false, false, false);
     qr_factor(ctx, fw);
+    if (early_tc > 0 && ctx.side) {
+      hipEvent_t e = ev_w.get();
+      LSQ_HIP(hipEventRecord(e, ctx.stream));
+      LSQ_HIP(hipStreamWaitEvent(ctx.side, e, 0));
+      Ctx sctx = ctx;
+      sctx.stream = ctx.side;
+      prepare_w(sctx, early_tc);
+      LSQ_HIP(hipEventRecord(e, ctx.side));
+      w_pending = true;
+    }
     const int ldn = n > 0 ? n : 1;
     void* Vw = ctx.ws->alloc((size_t)ps.tw * ldn * (p > 0 ? p : 1));
     mat_convert(ctx, Vw, ps.tw, ldn, V, 8, ldv, n, p, false, false, false);
@@ -409,9 +470,12 @@ struct GlsSolver {
 
   void prepare(Ctx& ctx, int tc_) {
     tc = tc_;
-    trsv_prepare(ctx, tR, fw, 0, m, tc);
+    if (w_pending) {
+      LSQ_HIP(hipStreamWaitEvent(ctx.stream, ev_w.get(), 0));
+      w_pending = false;
+    }
+    if (w_tc != tc) prepare_w(ctx, tc);
     trsv_prepare(ctx, tA11, fv, 0, k, tc);
-    agg_prepare(ctx, fw, tc, kAggPanels);
     agg_prepare(ctx, fv, tc, kAggPanels);
     alloc_vectors(ctx);
   }
@@ -691,7 +755,7 @@ bool lse_prefactor(Worker* h, const LseArgs& a, int prec, const lsq_opts& o, Lse
   sv.prec_id = prec;
   prec_spec(prec, sv.ps);
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
-  sv.factor(ctx, a.A, a.lda, a.B, a.ldb, default_nb(o));
+  sv.factor(ctx, a.A, a.lda, a.B, a.ldb, default_nb(o), prec == LSQ_PREC_FP64 ? 8 : sv.ps.tc);
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
   const int stat_b = read_int(h, sv.fb.status);
   const int stat_a = read_int(h, sv.fa.status);
@@ -705,7 +769,7 @@ bool gls_prefactor(Worker* h, const GlsArgs& a, int prec, const lsq_opts& o, Gls
   sv.prec_id = prec;
   prec_spec(prec, sv.ps);
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
-  sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o));
+  sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o), prec == LSQ_PREC_FP64 ? 8 : sv.ps.tc);
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
   const int stat_w = read_int(h, sv.fw.status);
   const int stat_v = read_int(h, sv.fv.status);
@@ -919,21 +983,26 @@ int fail(lsq_handle h, int code, const std::string& msg) {
 }
 
 // Runs body on worker w: selects the device, rewinds w's arena and turns HIP
-// errors into return code 4 with a message in *err.
+// errors into return code 4 with a message in *err.  Work left on the side
+// stream (a solver's early preparation that was never consumed) finishes
+// before the call returns: the next call rewinds the arena it writes into.
 int guard_w(Worker* w, std::string* err, const char* fn, const std::function<int()>& body) {
+  int rc = 4;
   try {
     LSQ_HIP(hipSetDevice(w->device));
     w->arena.reset();
-    return body();
+    rc = body();
   } catch (const HipError& e) {
     char buf[256];
     snprintf(buf, sizeof buf, "%s: %s failed: %s", fn, e.where, hipGetErrorString(e.code));
     if (err) *err = buf;
-    return 4;
+    rc = 4;
   } catch (const std::exception& e) {
     if (err) *err = std::string(fn) + ": " + e.what();
-    return 4;
+    rc = 4;
   }
+  if (w->ctx.side) (void)hipStreamSynchronize(w->ctx.side);
+  return rc;
 }
 
 int guard(lsq_handle h, const char* fn, const std::function<int()>& body) {
@@ -1527,7 +1596,7 @@ int lse_factor(lsq_handle h, int m, int n, int p, const double* A, int lda, cons
     f->ctx.ws = &f->arena;
     LseSolver& sv = f->lse;
     sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.prec_id = prec; sv.ps = ps;
-    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb);
+    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc);
     const int sb = read_int(&h->w, sv.fb.status);
     const int sa = read_int(&h->w, sv.fa.status);
     return (sb || sa) ? 1 : 0;
@@ -1560,7 +1629,7 @@ int gls_factor(lsq_handle h, int n, int m, int p, const double* W, int ldw, cons
     f->ctx.ws = &f->arena;
     GlsSolver& sv = f->gls;
     sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.prec_id = prec; sv.ps = ps;
-    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb);
+    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc);
     const int sw = read_int(&h->w, sv.fw.status);
     const int sv_ = read_int(&h->w, sv.fv.status);
     return (sw || sv_) ? 1 : 0;

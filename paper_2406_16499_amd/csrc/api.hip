@@ -1581,8 +1581,8 @@ int lse_factor(lsq_handle h, int m, int n, int p, const double* A, int lda, cons
                int ldb, int prec, lsq_factors* factors) {
   if (!h) return -1;
   std::string why;
-  static const double one = 0.0;
-  const int bad = lse_check(m, n, p, A, lda, B, ldb, &one, &one, &one, &why);
+  static const double nonnull = 0.0;   // stands in for the vectors the shared check requires
+  const int bad = lse_check(m, n, p, A, lda, B, ldb, &nonnull, &nonnull, &nonnull, &why);
   if (bad) return fail(h, bad, why);
   PrecSpec ps;
   if (prec == LSQ_PREC_AUTO || !prec_spec(prec, ps)) return fail(h, -9, "invalid precision");
@@ -1614,8 +1614,8 @@ int gls_factor(lsq_handle h, int n, int m, int p, const double* W, int ldw, cons
                int ldv, int prec, lsq_factors* factors) {
   if (!h) return -1;
   std::string why;
-  static const double one = 0.0;
-  const int bad = gls_check(n, m, p, W, ldw, V, ldv, &one, &one, &one, &why);
+  static const double nonnull = 0.0;   // stands in for the vectors the shared check requires
+  const int bad = gls_check(n, m, p, W, ldw, V, ldv, &nonnull, &nonnull, &nonnull, &why);
   if (bad) return fail(h, bad, why);
   PrecSpec ps;
   if (prec == LSQ_PREC_AUTO || !prec_spec(prec, ps)) return fail(h, -9, "invalid precision");

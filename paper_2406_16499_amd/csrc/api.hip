@@ -192,8 +192,12 @@ bool prec_spec(int prec, PrecSpec& ps) {
   }
 }
 
-// panels per aggregated block for the vector application of Q and Z
+// Panels per aggregated block for the vector application of Q and Z.  Wider
+// blocks mean fewer launches per application but larger T inverses to
+// prepare: classical IR applies Q and Z a few times per solve, GMRES-IR once
+// per inner iteration.
 constexpr int kAggPanels = 8;
+constexpr int kAggPanelsGmres = 16;
 
 int default_nb(const lsq_opts& o) { return (o.nb > 0 && o.nb <= kMaxNb) ? o.nb : kMaxNb; }
 
@@ -241,7 +245,7 @@ struct LseSolver {
   // works on Abar; b_tc is the precision they are prepared for.
   SolverEvent ev_b;
   bool b_pending = false;
-  int b_tc = 0;
+  int b_tc = 0, b_panels = 0;
   PrecSpec ps;
   int tc;                 // compute precision of the correction solve
   QRFactor fb, fa;        // QR of Bt (n x p) and of Abar (m x n)
@@ -253,10 +257,11 @@ struct LseSolver {
     U = v(n); Wv = v(m); Y2 = v(p); Y2n = v(p); Qv = v(m); Y1 = v(k); S = v(p); X2 = v(p); Yt = v(n);
   }
 
-  void prepare_b(Ctx& ctx, int tc_) {
+  void prepare_b(Ctx& ctx, int tc_, int panels) {
     trsv_prepare(ctx, tR, fb, 0, p, tc_);
-    agg_prepare(ctx, fb, tc_, kAggPanels);
+    agg_prepare(ctx, fb, tc_, panels);
     b_tc = tc_;
+    b_panels = panels;
   }
 
   // early_tc > 0: prepare the B-side structures for that precision on the
@@ -271,7 +276,7 @@ struct LseSolver {
       LSQ_HIP(hipStreamWaitEvent(ctx.side, e, 0));
       Ctx sctx = ctx;
       sctx.stream = ctx.side;
-      prepare_b(sctx, early_tc);
+      prepare_b(sctx, early_tc, kAggPanels);
       LSQ_HIP(hipEventRecord(e, ctx.side));
       b_pending = true;
     }
@@ -283,15 +288,15 @@ struct LseSolver {
     qr_factor(ctx, fa);
   }
 
-  void prepare(Ctx& ctx, int tc_) {
+  void prepare(Ctx& ctx, int tc_, int panels = kAggPanels) {
     tc = tc_;
     if (b_pending) {
       LSQ_HIP(hipStreamWaitEvent(ctx.stream, ev_b.get(), 0));
       b_pending = false;
     }
-    if (b_tc != tc) prepare_b(ctx, tc);
+    if (b_tc != tc || b_panels != panels) prepare_b(ctx, tc, panels);
     trsv_prepare(ctx, tT11, fa, 0, k, tc);
-    agg_prepare(ctx, fa, tc, kAggPanels);
+    agg_prepare(ctx, fa, tc, panels);
     alloc_vectors(ctx);
   }
 
@@ -354,7 +359,7 @@ struct LseSolver {
 
   int tmn() const { return std::min(m, n); }
   void prepare_gmres(Ctx& ctx) {
-    prepare(ctx, 8);
+    prepare(ctx, 8, kAggPanelsGmres);
     trsv_prepare(ctx, tT1, fa, 0, tmn(), 8);
     const int L = std::max(std::max(m, n), 1), N = std::max(m + p + n, 1);
     g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
@@ -427,7 +432,7 @@ struct GlsSolver {
   bool prepared_gmres = false;
   SolverEvent ev_w;       // W-side structures prepared early (as LseSolver's B side)
   bool w_pending = false;
-  int w_tc = 0;
+  int w_tc = 0, w_panels = 0;
   PrecSpec ps;
   int tc;
   QRFactor fw, fv;        // QR of W (n x m) and of Vt (p x n)
@@ -439,10 +444,11 @@ struct GlsSolver {
     U = v(n); Wt = v(p); H1 = v(m); H1t = v(m); G = v(p); H2t = v(k); S = v(m); X = v(m); Hv = v(n);
   }
 
-  void prepare_w(Ctx& ctx, int tc_) {
+  void prepare_w(Ctx& ctx, int tc_, int panels) {
     trsv_prepare(ctx, tR, fw, 0, m, tc_);
-    agg_prepare(ctx, fw, tc_, kAggPanels);
+    agg_prepare(ctx, fw, tc_, panels);
     w_tc = tc_;
+    w_panels = panels;
   }
 
   void factor(Ctx& ctx, const double* W, int ldw, const double* V, int ldv, int nb, int early_tc = 0) {
@@ -455,7 +461,7 @@ struct GlsSolver {
       LSQ_HIP(hipStreamWaitEvent(ctx.side, e, 0));
       Ctx sctx = ctx;
       sctx.stream = ctx.side;
-      prepare_w(sctx, early_tc);
+      prepare_w(sctx, early_tc, kAggPanels);
       LSQ_HIP(hipEventRecord(e, ctx.side));
       w_pending = true;
     }
@@ -468,15 +474,15 @@ struct GlsSolver {
     qr_factor(ctx, fv);
   }
 
-  void prepare(Ctx& ctx, int tc_) {
+  void prepare(Ctx& ctx, int tc_, int panels = kAggPanels) {
     tc = tc_;
     if (w_pending) {
       LSQ_HIP(hipStreamWaitEvent(ctx.stream, ev_w.get(), 0));
       w_pending = false;
     }
-    if (w_tc != tc) prepare_w(ctx, tc);
+    if (w_tc != tc || w_panels != panels) prepare_w(ctx, tc, panels);
     trsv_prepare(ctx, tA11, fv, 0, k, tc);
-    agg_prepare(ctx, fv, tc, kAggPanels);
+    agg_prepare(ctx, fv, tc, panels);
     alloc_vectors(ctx);
   }
 
@@ -539,7 +545,7 @@ struct GlsSolver {
 
   int tnp() const { return std::min(n, p); }
   void prepare_gmres(Ctx& ctx) {
-    prepare(ctx, 8);
+    prepare(ctx, 8, kAggPanelsGmres);
     trsv_prepare(ctx, tRv, fv, 0, tnp(), 8);
     const int L = std::max(std::max(n, p), 1), N = std::max(p + n + m, 1);
     g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);

@@ -526,3 +526,39 @@ def test_gmres_ir_converges_where_classical_ir_struggles():
     assert g.converged and g.steps < a.steps
     x, _, _ = direct.lse_solve(L.A, L.B, L.b, L.d)
     assert _rel(g.x, x) < 1e-6
+
+
+# With b = 0, d = 0 (LSE) or d = 0 (GLS) the initial r0 or y0 is exactly
+# zero, so GMRES-IR takes the fallback alpha of the reading of Section 5.1
+# (2^-1/2 min |diag| of the triangle).  It must be finite and positive on
+# either side of the n = m (LSE) and n = p (GLS) split of the
+# preconditioners, and the solve returns the zero solution at once.
+@pytest.mark.parametrize("m,n,p", [(60, 30, 8), (30, 44, 20)])
+def test_lse_gmres_ir_fallback_alpha(m, n, p):
+    P = wl.lse_gaussian(_rng(73 + n), m, n, p)
+    g = mpir.mplse_gmres_bd(P.A, P.B, np.zeros(m), np.zeros(p), tol=1e-14)
+    assert g.converged and g.steps == 0
+    assert np.all(g.x == 0.0) and np.all(g.aux1 == 0.0) and np.all(g.aux2 == 0.0)
+    R, T, Z, Q = mpir.grq_factors(P.B, P.A, np.float32)
+    t = min(m, n)
+    alpha = 2 ** -0.5 * float(np.min(np.abs(np.diag(np.asarray(T, np.float64)[:t, :t]))))
+    assert np.isfinite(alpha) and alpha > 0
+    Ml, F, Mr = mpir.bd_operators_lse(P.A, P.B, R, T, Q, alpha, 1.0)
+    u = _rng(74).standard_normal(m + p + n)
+    assert np.all(np.isfinite(Ml(F(Mr(u)))))
+
+
+@pytest.mark.parametrize("n,m,p", [(30, 10, 40), (44, 30, 20)])
+def test_gls_gmres_ir_fallback_alpha(n, m, p):
+    G = wl.gls_gaussian(_rng(75 + n), n, m, p)
+    g = mpir.mpgls_gmres_bd(G.W, G.V, np.zeros(n), tol=1e-14)
+    assert g.converged and g.steps == 0
+    assert np.all(g.x == 0.0) and np.all(g.aux1 == 0.0) and np.all(g.aux2 == 0.0)
+    R, T, Q, Z = mpir.gqr_factors(G.W, G.V, np.float32)
+    T2 = np.asarray(T, np.float64)
+    T2 = T2[:, p - n:] if n <= p else T2[n - p:, :]
+    alpha = 2 ** -0.5 * float(np.min(np.abs(np.diag(T2))))
+    assert np.isfinite(alpha) and alpha > 0
+    Ml, F, Mr = mpir.bd_operators_gls(G.W, G.V, R, T, Q, alpha, 1.0)
+    u = _rng(76).standard_normal(m + p + n)
+    assert np.all(np.isfinite(Ml(F(Mr(u)))))

@@ -51,3 +51,9 @@ def test_ctypes_layouts_match_the_c_header(tmp_path):
                                           check=True).stdout.split()]
     assert got == [ctypes.sizeof(lsq.Opts), ctypes.sizeof(lsq.Problem), ctypes.sizeof(lsq.Result),
                    lsq.Result.berr.offset, lsq.Problem.x.offset]
+
+
+def test_binding_declares_every_entry_point():
+    # the ctypes binding sets a signature for exactly the functions the headers declare
+    names = set(lsq.header_symbols())
+    assert names == set(lsq._SIGS), (sorted(names - set(lsq._SIGS)), sorted(set(lsq._SIGS) - names))

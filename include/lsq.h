@@ -27,15 +27,32 @@
  * - Return codes (LAPACK-style INFO):
  *      0   success: the returned iterate passes the stopping test with tol;
  *     -k   argument k is invalid (shape rule, leading dimension, null pointer);
- *      1   rank(B) < p (LSE) or rank(W) < m (GLS) detected by the FP64
- *          factorization (assumptions eq. assump:lse / eq. assump:gls);
- *      2   T11 (LSE) or T22 (GLS) is singular: the uniqueness condition fails;
- *      3   no rung of the escalation ladder met tol; the best iterate found
- *          is returned and its backward error reported;
+ *      1   rank(B) < p (LSE) or rank(W) < m (GLS) (assumptions eq. assump:lse /
+ *          eq. assump:gls): the FP64 factorization of B (LSE) or W (GLS) broke
+ *          down, or the FP64 rung did not meet tol and that triangle R has a
+ *          pivot ratio min|r_ii| / max|r_ii| <= 16 * 2^-53;
+ *      2   T11 (LSE) or T22 (GLS) is singular, i.e. rank([A; B]) < n (LSE) or
+ *          rank([W, V]) < n (GLS), the uniqueness condition of Section 1: the
+ *          same two tests on the second FP64 factorization;
+ *      3   no rung of the escalation ladder met tol; the iterate with the
+ *          smallest backward error over all rungs is returned and its
+ *          backward error reported (x = 0 and the backward error of x = 0 if
+ *          no rung produced a finite iterate);
  *      4   HIP error or device allocation failure;
- *      5   a non-finite value in the inputs.
- *   A low-precision factorization never returns 1 or 2: near-singularity at
- *   u_f escalates to the next rung instead.
+ *      5   a non-finite value (NaN or infinity) in A, B, b or d; nothing is
+ *          factored and the outputs are not written.
+ *   Outputs are written for codes 0 and 3 only.  A low-precision
+ *   factorization never returns 1 or 2: near-singularity at u_f escalates to
+ *   the next rung instead.
+ * - Input scaling: every factorization works on its two matrices each
+ *   scaled by the power of two that brings its largest magnitude into
+ *   [1/2, 1), and scales the triangular factors back (exact in binary
+ *   floating point).  The FP16 and BF16 MFMA inputs rounded from them stay
+ *   inside the 16-bit range (Section 6.1 asks for scaling on the conversion
+ *   to a lower precision), and the panels' Gram matrices cannot overflow.
+ *   FP8 MFMA inputs are in addition scaled per tile.  The stop test's norms
+ *   of A, B, b, d are exact to rounding over the whole FP64 range; those of
+ *   the iterates are plain sums of squares (magnitudes up to about 1e150).
  * - Thread safety: a handle is used by one host thread at a time.
  */
 #ifndef LSQ_H
@@ -88,7 +105,10 @@ typedef struct {
   int gmres_iters;     /* total GMRES iterations on the final rung                  */
   double berr[3];      /* ||f_i|| / (right-hand side of the stop test without tol)  */
   double berr_max;
-  float ms_convert, ms_factor, ms_refine;   /* stream time per phase (final rung)  */
+  /* stream time per phase: ms_convert the FP64 norm / magnitude / finiteness
+     scan of the inputs (the down-conversions run inside the factorization and
+     count in ms_factor); ms_factor and ms_refine those of the final rung     */
+  float ms_convert, ms_factor, ms_refine;
 } lsq_result;
 
 /* Create a handle bound to GPU `device`; it owns a device workspace that grows
@@ -134,8 +154,10 @@ int gls_solve(lsq_handle handle, int n, int m, int p,
  * the FP64 residual of every later solve reads them, so both must stay
  * allocated and unchanged until lsq_factors_destroy.  Returns 0 and sets
  * *factors, 1 if a panel factorization broke down at this precision (no
- * object is made), 4 on a HIP error, or -k for argument k (the numbers of
- * lse_solve / gls_solve for the shared arguments; 9 prec, 10 factors).
+ * object is made), 5 for a non-finite value in A or B, 4 on a HIP error, or
+ * -k for argument k (the numbers of lse_solve / gls_solve for the shared
+ * arguments; 9 prec, 10 factors).  The factors are computed from
+ * power-of-two scaled inputs as in lse_solve.
  */
 typedef struct lsq_factors_st* lsq_factors;
 int lse_factor(lsq_handle handle, int m, int n, int p,
@@ -150,10 +172,13 @@ int gls_factor(lsq_handle handle, int n, int m, int p,
  * of this call: opts->solver IR (or AUTO) or GMRES_IR; with FP64 factors the
  * FP64 direct solve.  The first solve of a kind also prepares the factors'
  * triangular inverses and aggregated blocks for it; later solves reuse them.
- * There is no escalation: a solve that does not certify returns 3 with its
- * last iterate.  res->ms_factor is 0.  Only the handle that made the factors
- * may use them (-2 otherwise).  Argument numbers for -k: 2 factors, 3 b,
- * 4 d, 5 x, 8 opts (LSE); 2 factors, 3 d, 4 x, 5 y, 7 opts (GLS).
+ * There is no escalation: a solve that does not certify returns 3 with the
+ * iterate of smallest backward error; a non-finite value in b or d returns 5.
+ * The prepared structures of one kind replace those of the other in the
+ * factors' memory, which stays the same size over any number of switches.
+ * res->ms_factor is 0.  Only the handle that made the factors may use them
+ * (-2 otherwise).  Argument numbers for -k: 2 factors, 3 b, 4 d, 5 x, 8 opts
+ * (LSE); 2 factors, 3 d, 4 x, 5 y, 7 opts (GLS).
  */
 int lse_solve_factored(lsq_handle handle, lsq_factors factors,
                        const double* b, const double* d,

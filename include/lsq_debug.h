@@ -111,6 +111,10 @@ int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes);
    outside [0, 1000]. */
 int lsq_dbg_batch_wait(lsq_handle h, double ms);
 
+/* Device memory of a factors object (lse_factor / gls_factor): bytes in use
+   and bytes held.  Returns -1 for NULL. */
+int lsq_dbg_factors_bytes(lsq_factors factors, long long* in_use, long long* capacity);
+
 /* Text of the last error recorded on the handle ("" if none). */
 const char* lsq_last_error(lsq_handle h);
 

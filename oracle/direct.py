@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+from scipy.sparse.linalg import LinearOperator, onenormest
 
 __all__ = [
     "grq", "lse_solve", "gqr", "gls_solve",
@@ -23,6 +24,7 @@ __all__ = [
     "lse_berr", "gls_berr",
     "lse_err1", "lse_err2", "gls_err1", "gls_err2",
     "skeel_cond_block", "lse_cond_x", "gls_cond_xy",
+    "skeel_cond_block_est", "lse_cond_x_est", "gls_cond_xy_est",
     "check_lse_assumptions", "check_gls_assumptions",
 ]
 
@@ -310,3 +312,50 @@ def gls_cond_xy(W, V, x, y, z):
     u = np.concatenate([y, -z, x])
     return (skeel_cond_block(F, u, slice(p + n, p + n + m)),
             skeel_cond_block(F, u, slice(0, p)))
+
+
+def skeel_cond_block_est(F, u, sl):
+    """Estimate of skeel_cond_block(F, u, sl) for large N, without F^-1.
+
+    With g = |F| |u| (nonnegative), the block's entries of |F^-1| g are the
+    column sums of |S| for S = diag(g) F^-T P, where P keeps the block's
+    coordinates and zeroes the rest; so || (|F^-1| g)[sl] ||_inf = ||S||_1.
+    The block 1-norm estimator of Higham and Tisseur
+    (scipy.sparse.linalg.onenormest) estimates ||S||_1 from products with S
+    and S^T, each one solve with an LU factorization of F.  The estimate is a
+    lower bound of the exact value and equals it in most cases.
+    """
+    N = F.shape[0]
+    lu = sla.lu_factor(F)
+    g = np.abs(F) @ np.abs(u)
+    keep = np.zeros(N)
+    keep[sl] = 1.0
+
+    def matvec(y):
+        return g * sla.lu_solve(lu, keep * np.ravel(y), trans=1)
+
+    def rmatvec(w):
+        return keep * sla.lu_solve(lu, g * np.ravel(w))
+
+    op = LinearOperator((N, N), matvec=matvec, rmatvec=rmatvec, dtype=np.float64)
+    est = float(onenormest(op, t=2, itmax=6))
+    den = np.max(np.abs(u[sl]))
+    return est / den if den > 0 else float("inf")
+
+
+def lse_cond_x_est(A, B, x, r, v):
+    """lse_cond_x through skeel_cond_block_est (large systems)."""
+    m, n = A.shape
+    p = B.shape[0]
+    u = np.concatenate([r, -v, x])
+    return skeel_cond_block_est(lse_augmented(A, B), u, slice(m + p, m + p + n))
+
+
+def gls_cond_xy_est(W, V, x, y, z):
+    """gls_cond_xy through skeel_cond_block_est (large systems)."""
+    n, m = W.shape
+    p = V.shape[1]
+    F = gls_augmented(W, V)
+    u = np.concatenate([y, -z, x])
+    return (skeel_cond_block_est(F, u, slice(p + n, p + n + m)),
+            skeel_cond_block_est(F, u, slice(0, p)))

@@ -62,6 +62,27 @@ void Arena::reset() {
   for (auto& c : chunks_) c.used = 0;
   cur_ = 0;
 }
+Arena::Mark Arena::mark() const {
+  Mark m;
+  m.chunk = cur_;
+  m.used = cur_ < chunks_.size() ? chunks_[cur_].used : 0;
+  return m;
+}
+void Arena::rewind(const Mark& m) {
+  for (size_t q = m.chunk + 1; q < chunks_.size(); ++q) chunks_[q].used = 0;
+  if (m.chunk < chunks_.size()) chunks_[m.chunk].used = m.used;
+  cur_ = m.chunk;
+}
+size_t Arena::capacity() const {
+  size_t t = 0;
+  for (const auto& c : chunks_) t += c.size;
+  return t;
+}
+size_t Arena::in_use() const {
+  size_t t = 0;
+  for (const auto& c : chunks_) t += c.used;
+  return t;
+}
 void Arena::release() {
   for (auto& c : chunks_) (void)hipFree(c.base);
   chunks_.clear();
@@ -240,6 +261,8 @@ struct LseSolver {
   Ctx* pctx = nullptr;
   int prepared_tc = 0;
   bool prepared_gmres = false;
+  Arena::Mark pmark;      // pctx's arena right after the factorization
+  bool has_pmark = false;
   // The B-side structures (R's inverse, B's aggregated blocks) depend on fb
   // only: factor() prepares them on the side stream while the main stream
   // works on Abar; b_tc is the precision they are prepared for.
@@ -264,12 +287,23 @@ struct LseSolver {
     b_panels = panels;
   }
 
+  // Power-of-two scales of A and B for the factorization (1 unless set
+  // before factor()).
+  double sA = 1.0, sB = 1.0;
+
   // early_tc > 0: prepare the B-side structures for that precision on the
-  // side stream, overlapping the rest of the factorization.
-  void factor(Ctx& ctx, const double* A, int lda, const double* B, int ldb, int nb, int early_tc = 0) {
+  // side stream, overlapping the rest of the factorization.  The factors and
+  // prepared structures go to ctx.ws; the factorization's temporaries to
+  // scratch (ctx.ws when null).  A and B are factored scaled by sA and sB; the
+  // triangular factors R and T are scaled back afterwards (exact: powers of two).
+  void factor(Ctx& ctx, const double* A, int lda, const double* B, int ldb, int nb, int early_tc = 0,
+              Arena* scratch = nullptr) {
+    Ctx tctx = ctx;
+    if (scratch) tctx.ws = scratch;
     qr_alloc(ctx, fb, n, p, ps.tw, ps.mt, nb);
-    mat_convert(ctx, fb.M, ps.tw, fb.ld, B, 8, ldb, n, p, true, true, true);
-    qr_factor(ctx, fb);
+    mat_convert(ctx, fb.M, ps.tw, fb.ld, B, 8, ldb, n, p, true, true, true, sB);
+    qr_factor(tctx, fb);
+    scale_upper(ctx, fb, 1.0 / sB);
     if (early_tc > 0 && ctx.side) {
       hipEvent_t e = ev_b.get();
       LSQ_HIP(hipEventRecord(e, ctx.stream));
@@ -280,12 +314,13 @@ struct LseSolver {
       LSQ_HIP(hipEventRecord(e, ctx.side));
       b_pending = true;
     }
-    void* X0 = ctx.ws->alloc((size_t)ps.tw * (size_t)(n > 0 ? n : 1) * (m > 0 ? m : 1));
-    mat_convert(ctx, X0, ps.tw, n > 0 ? n : 1, A, 8, lda, n, m, true, false, true);
-    qr_apply_left_T(ctx, fb, X0, n > 0 ? n : 1, m);
+    void* X0 = tctx.ws->alloc((size_t)ps.tw * (size_t)(n > 0 ? n : 1) * (m > 0 ? m : 1));
+    mat_convert(ctx, X0, ps.tw, n > 0 ? n : 1, A, 8, lda, n, m, true, false, true, sA);
+    qr_apply_left_T(tctx, fb, X0, n > 0 ? n : 1, m);
     qr_alloc(ctx, fa, m, n, ps.tw, ps.mt, nb);
     mat_convert(ctx, fa.M, ps.tw, fa.ld, X0, ps.tw, n > 0 ? n : 1, m, n, true, true, false);
-    qr_factor(ctx, fa);
+    qr_factor(tctx, fa);
+    scale_upper(ctx, fa, 1.0 / sA);
   }
 
   void prepare(Ctx& ctx, int tc_, int panels = kAggPanels) {
@@ -430,6 +465,8 @@ struct GlsSolver {
   Ctx* pctx = nullptr;    // as for LseSolver
   int prepared_tc = 0;
   bool prepared_gmres = false;
+  Arena::Mark pmark;
+  bool has_pmark = false;
   SolverEvent ev_w;       // W-side structures prepared early (as LseSolver's B side)
   bool w_pending = false;
   int w_tc = 0, w_panels = 0;
@@ -451,10 +488,16 @@ struct GlsSolver {
     w_panels = panels;
   }
 
-  void factor(Ctx& ctx, const double* W, int ldw, const double* V, int ldv, int nb, int early_tc = 0) {
+  double sW = 1.0, sV = 1.0;   // power-of-two scales of W and V (as LseSolver's sA, sB)
+
+  void factor(Ctx& ctx, const double* W, int ldw, const double* V, int ldv, int nb, int early_tc = 0,
+              Arena* scratch = nullptr) {
+    Ctx tctx = ctx;
+    if (scratch) tctx.ws = scratch;
     qr_alloc(ctx, fw, n, m, ps.tw, ps.mt, nb);
-    mat_convert(ctx, fw.M, ps.tw, fw.ld, W, 8, ldw, n, m, false, false, false);
-    qr_factor(ctx, fw);
+    mat_convert(ctx, fw.M, ps.tw, fw.ld, W, 8, ldw, n, m, false, false, false, sW);
+    qr_factor(tctx, fw);
+    scale_upper(ctx, fw, 1.0 / sW);
     if (early_tc > 0 && ctx.side) {
       hipEvent_t e = ev_w.get();
       LSQ_HIP(hipEventRecord(e, ctx.stream));
@@ -466,12 +509,13 @@ struct GlsSolver {
       w_pending = true;
     }
     const int ldn = n > 0 ? n : 1;
-    void* Vw = ctx.ws->alloc((size_t)ps.tw * ldn * (p > 0 ? p : 1));
-    mat_convert(ctx, Vw, ps.tw, ldn, V, 8, ldv, n, p, false, false, false);
-    qr_apply_left_T(ctx, fw, Vw, ldn, p);
+    void* Vw = tctx.ws->alloc((size_t)ps.tw * ldn * (p > 0 ? p : 1));
+    mat_convert(ctx, Vw, ps.tw, ldn, V, 8, ldv, n, p, false, false, false, sV);
+    qr_apply_left_T(tctx, fw, Vw, ldn, p);
     qr_alloc(ctx, fv, p, n, ps.tw, ps.mt, nb);
     mat_convert(ctx, fv.M, ps.tw, fv.ld, Vw, ps.tw, ldn, p, n, true, true, true);
-    qr_factor(ctx, fv);
+    qr_factor(tctx, fv);
+    scale_upper(ctx, fv, 1.0 / sV);
   }
 
   void prepare(Ctx& ctx, int tc_, int panels = kAggPanels) {
@@ -620,11 +664,41 @@ void GlsSolver::f_apply(Ctx& ctx, const GlsArgs& a, const double* u, double* out
 // ------------------------------------------------------- rung execution --
 struct RungOut {
   bool ok = false;
-  bool breakdown = false;  // the factorization failed (rank deficiency at u_f)
+  // the factorization failed at this precision: 1 in the first factorization
+  // (R from B, LSE; R from W, GLS), 2 in the second (T), 0 none
+  int breakdown = 0;
+  // FP64 rung that did not certify: 1 or 2 when the triangle R (resp. T11 /
+  // T22) is numerically singular, 0 otherwise
+  int singular = 0;
   int steps = 0, inner = 0;
   double berr[3] = {0, 0, 0}, berr_max = INFINITY;
   float ms_convert = 0, ms_factor = 0, ms_refine = 0;
 };
+
+// The best iterate seen by the rungs of one solve (smallest blockwise
+// backward error), kept for a solve that ends without meeting tol; save()
+// copies the current iterate to the caller's buffers.
+struct BestIter {
+  bool have = false;
+  double berr[3] = {0, 0, 0}, berr_max = INFINITY;
+  int steps = 0, inner = 0, prec = 0, solver = 0;
+  std::function<void()> save;
+  void observe(const StopStatus& st, int steps_, int inner_, int prec_, int solver_) {
+    if (!save || st.converged || st.nonfinite || !(st.berr_max < berr_max)) return;
+    save();
+    have = true;
+    for (int q = 0; q < 3; ++q) berr[q] = st.berr[q];
+    berr_max = st.berr_max;
+    steps = steps_;
+    inner = inner_;
+    prec = prec_;
+    solver = solver_;
+  }
+};
+
+// Pivot ratio min |t_ii| / max |t_ii| at or below which an FP64 triangle
+// that did not certify is reported singular (a few units of roundoff).
+constexpr double kSingularRatio = 16.0 * 1.1102230246251565e-16;
 
 void read_status(Worker* h) {
   LSQ_HIP(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(StopStatus), hipMemcpyDeviceToHost, h->stream));
@@ -659,7 +733,8 @@ bool stalled(const std::vector<double>& hist) {
 // test on the device, correct() adds one correction.
 RungOut run_classical(Worker* h, const std::function<void()>& zero,
                       const std::function<void()>& init, const std::function<void()>& residual,
-                      const std::function<void()>& correct, const lsq_opts& o) {
+                      const std::function<void()>& correct, const lsq_opts& o,
+                      const std::function<void(const StopStatus&, int, int)>& observe) {
   RungOut out;
   zero();
   LSQ_HIP(hipEventRecord(h->ev[2], h->stream));
@@ -669,6 +744,7 @@ RungOut run_classical(Worker* h, const std::function<void()>& zero,
     residual();
     read_status(h);
     const StopStatus& st = *h->st_host;
+    if (observe) observe(st, it, 0);
     hist.push_back(st.berr_max);
     for (int q = 0; q < 3; ++q) out.berr[q] = st.berr[q];
     out.berr_max = st.berr_max;
@@ -694,7 +770,8 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
                   const std::function<void()>& residual,
                   const std::function<double()>& alpha0,
                   const std::function<void(double*)>& scaled_residual,
-                  const std::function<void(const double*)>& update, const lsq_opts& o) {
+                  const std::function<void(const double*)>& update, const lsq_opts& o,
+                  const std::function<void(const StopStatus&, int, int)>& observe) {
   Ctx& ctx = h->ctx;
   RungOut out;
   zero();
@@ -717,6 +794,7 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
     residual();
     read_status(h);
     const StopStatus& stt = *h->st_host;
+    if (observe) observe(stt, it, out.inner);
     hist.push_back(stt.berr_max);
     for (int q = 0; q < 3; ++q) out.berr[q] = stt.berr[q];
     out.berr_max = stt.berr_max;
@@ -741,10 +819,16 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
 // corrections in precision tc (with the GMRES operator's extras if gmres).
 // A solver whose factors outlive the call (pctx set) keeps what it prepared
 // in pctx's arena and prepares again only when tc or the solver kind changes.
+// The factors' arena is rewound to the mark taken after the factorization
+// before each new preparation, so alternating kinds keeps its size flat.
 template <typename Solver>
 void ensure_prepared(Solver& sv, Ctx& ctx, int tc, bool gmres) {
   if (sv.pctx && sv.prepared_tc == tc && (sv.prepared_gmres || !gmres)) return;
   Ctx& pc = sv.pctx ? *sv.pctx : ctx;
+  if (sv.pctx && sv.has_pmark) {
+    LSQ_HIP(hipStreamSynchronize(pc.stream));   // nothing in flight reads what the rewind frees
+    pc.ws->rewind(sv.pmark);
+  }
   if (gmres) sv.prepare_gmres(pc); else sv.prepare(pc, tc);
   sv.prepared_tc = tc;
   sv.prepared_gmres = gmres;
@@ -755,46 +839,81 @@ void ensure_prepared(Solver& sv, Ctx& ctx, int tc, bool gmres) {
 // GMRES-IR; DIRECT: the FP64 factors with the classical loop).
 // Factors an LSE at prec (the generalized RQ of Section 3.1); true if no
 // panel Cholesky broke down.
-bool lse_prefactor(Worker* h, const LseArgs& a, int prec, const lsq_opts& o, LseSolver& sv) {
+// Power-of-two scale that maps a largest magnitude mx into [1/2, 1) (1 when
+// mx is 0).  Every factorization works on its matrices scaled this way and
+// scales the triangular factors back (exact in binary floating point): the
+// FP16 and BF16 MFMA inputs rounded from them stay inside the 16-bit range
+// (Section 6.1 asks for scaling on the conversion to a lower precision), and
+// the Gram matrices of the Cholesky-QR panels cannot overflow or underflow.
+double pow2_scale(double mx) {
+  if (!(mx > 0.0) || !std::isfinite(mx)) return 1.0;
+  int e = 0;
+  std::frexp(mx, &e);
+  return std::ldexp(1.0, -e);
+}
+
+// Factors an LSE at prec (the generalized RQ of Section 3.1); returns 0, or
+// 1 / 2 when a panel Cholesky of the first / second factorization broke down.
+// mx: largest magnitudes of A and B (for the scales; null: no scaling).
+int lse_prefactor(Worker* h, const LseArgs& a, int prec, const lsq_opts& o, LseSolver& sv,
+                  const double* mx) {
   Ctx& ctx = h->ctx;
   sv.m = a.m; sv.n = a.n; sv.p = a.p; sv.k = a.n - a.p;
   sv.prec_id = prec;
   prec_spec(prec, sv.ps);
+  sv.sA = mx ? pow2_scale(mx[0]) : 1.0;
+  sv.sB = mx ? pow2_scale(mx[1]) : 1.0;
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
   sv.factor(ctx, a.A, a.lda, a.B, a.ldb, default_nb(o), prec == LSQ_PREC_FP64 ? 8 : sv.ps.tc);
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
   const int stat_b = read_int(h, sv.fb.status);
   const int stat_a = read_int(h, sv.fa.status);
   sv.ms_factor = elapsed(h->ev[0], h->ev[1]);
-  return !(stat_b || stat_a);
+  return stat_b ? 1 : (stat_a ? 2 : 0);
 }
 
-bool gls_prefactor(Worker* h, const GlsArgs& a, int prec, const lsq_opts& o, GlsSolver& sv) {
+int gls_prefactor(Worker* h, const GlsArgs& a, int prec, const lsq_opts& o, GlsSolver& sv,
+                  const double* mx) {
   Ctx& ctx = h->ctx;
   sv.n = a.n; sv.m = a.m; sv.p = a.p; sv.k = a.n - a.m;
   sv.prec_id = prec;
   prec_spec(prec, sv.ps);
+  sv.sW = mx ? pow2_scale(mx[0]) : 1.0;
+  sv.sV = mx ? pow2_scale(mx[1]) : 1.0;
   LSQ_HIP(hipEventRecord(h->ev[0], h->stream));
   sv.factor(ctx, a.W, a.ldw, a.V, a.ldv, default_nb(o), prec == LSQ_PREC_FP64 ? 8 : sv.ps.tc);
   LSQ_HIP(hipEventRecord(h->ev[1], h->stream));
   const int stat_w = read_int(h, sv.fw.status);
   const int stat_v = read_int(h, sv.fv.status);
   sv.ms_factor = elapsed(h->ev[0], h->ev[1]);
-  return !(stat_w || stat_v);
+  return stat_w ? 1 : (stat_v ? 2 : 0);
+}
+
+// Singularity of an FP64 rung's triangles after it failed to certify: 1 when
+// R (from B, LSE; from W, GLS) has a negligible pivot, 2 when T11 (LSE) /
+// T22 (GLS) has one, else 0.
+int fp64_singular(Ctx& ctx, const QRFactor& f1, int n1, const QRFactor& f2, int n2) {
+  double d[2];
+  diag_minmax(ctx, f1, 0, n1, d);
+  if (n1 > 0 && !(d[0] > kSingularRatio * d[1])) return 1;
+  diag_minmax(ctx, f2, 0, n2, d);
+  if (n2 > 0 && !(d[0] > kSingularRatio * d[1])) return 2;
+  return 0;
 }
 
 RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& solvers,
                  const lsq_opts& o, double* x, double* r, double* v, int& attempts,
-                 int& solver_used, LseSolver* pre = nullptr, bool pre_ok = true) {
+                 int& solver_used, const double* mx, BestIter* best, LseSolver* pre = nullptr,
+                 int pre_code = 0) {
   Ctx& ctx = h->ctx;
   LseSolver local;
   const bool reuse = pre && pre->prec_id == prec;
   LseSolver& sv = reuse ? *pre : local;
-  const bool ok_factor = reuse ? pre_ok : lse_prefactor(h, a, prec, o, sv);
+  const int code = reuse ? pre_code : lse_prefactor(h, a, prec, o, sv, mx);
   const float ms_factor = sv.ms_factor;
   RungOut out;
-  if (!ok_factor) {
-    out.breakdown = true;
+  if (code != 0) {
+    out.breakdown = code;
     ++attempts;
     solver_used = solvers.empty() ? LSQ_SOLVER_IR : solvers[0];
     return out;
@@ -811,6 +930,9 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
   for (int solver : solvers) {
     ++attempts;
     solver_used = solver;
+    auto observe = [&](const StopStatus& st, int it, int inner) {
+      if (best) best->observe(st, it, inner, prec, solver);
+    };
     if (solver == LSQ_SOLVER_GMRES_IR) {
       ensure_prepared(sv, ctx, 8, true);
       const int m = a.m, p = a.p, n = a.n;
@@ -831,30 +953,32 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
             vec_axpy(ctx, v, 8, -sv.sa * sv.beta, du + m, 8, p, false);
             vec_axpy(ctx, x, 8, 1.0 / sv.sa, du + m + p, 8, n, false);
           },
-          o);
+          o, observe);
     } else {
       ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
-                          [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o);
+                          [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o, observe);
     }
     out.ms_factor = ms_factor;
     if (out.ok) break;
   }
+  if (prec == LSQ_PREC_FP64 && !out.ok) out.singular = fp64_singular(ctx, sv.fb, a.p, sv.fa, sv.k);
   return out;
 }
 
 RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& solvers,
                  const lsq_opts& o, double* x, double* y, double* z, int& attempts,
-                 int& solver_used, GlsSolver* pre = nullptr, bool pre_ok = true) {
+                 int& solver_used, const double* mx, BestIter* best, GlsSolver* pre = nullptr,
+                 int pre_code = 0) {
   Ctx& ctx = h->ctx;
   GlsSolver local;
   const bool reuse = pre && pre->prec_id == prec;
   GlsSolver& sv = reuse ? *pre : local;
-  const bool ok_factor = reuse ? pre_ok : gls_prefactor(h, a, prec, o, sv);
+  const int code = reuse ? pre_code : gls_prefactor(h, a, prec, o, sv, mx);
   const float ms_factor = sv.ms_factor;
   RungOut out;
-  if (!ok_factor) {
-    out.breakdown = true;
+  if (code != 0) {
+    out.breakdown = code;
     ++attempts;
     solver_used = solvers.empty() ? LSQ_SOLVER_IR : solvers[0];
     return out;
@@ -871,6 +995,9 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
   for (int solver : solvers) {
     ++attempts;
     solver_used = solver;
+    auto observe = [&](const StopStatus& st, int it, int inner) {
+      if (best) best->observe(st, it, inner, prec, solver);
+    };
     if (solver == LSQ_SOLVER_GMRES_IR) {
       ensure_prepared(sv, ctx, 8, true);
       const int m = a.m, p = a.p, n = a.n;
@@ -891,15 +1018,16 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
             vec_axpy(ctx, z, 8, -1.0 / sv.sa, du + p, 8, n, false);
             vec_axpy(ctx, x, 8, sv.sa * sv.beta, du + p + n, 8, m, false);
           },
-          o);
+          o, observe);
     } else {
       ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
-                          [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o);
+                          [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o, observe);
     }
     out.ms_factor = ms_factor;
     if (out.ok) break;
   }
+  if (prec == LSQ_PREC_FP64 && !out.ok) out.singular = fp64_singular(ctx, sv.fw, a.m, sv.fv, sv.k);
   return out;
 }
 
@@ -1241,43 +1369,116 @@ static void fill_result(lsq_result* res, int info, int prec, int solver, int att
 }  // extern "C"
 
 namespace {
+// Ingest of one solve: FP64 norms for the stop test, the largest magnitudes
+// (for the FP16 / BF16 scales) and a finiteness check, in one read of each
+// input.  Returns false when an input holds a non-finite value; mx receives
+// the largest magnitudes of the four inputs, ms the stream time of the scan.
+bool ingest(Worker* w, const double* M1, int ld1, int r1, int c1, const double* M2, int ld2, int r2,
+            int c2, const double* v1, int n1, const double* v2, int n2, double* mx, float* ms) {
+  Ctx& ctx = w->ctx;
+  LSQ_HIP(hipEventRecord(w->ev[0], w->stream));
+  frob_norms(ctx, M1, ld1, r1, c1, M2, ld2, r2, c2, v1, n1, v2, n2, w->matnorms);
+  LSQ_HIP(hipEventRecord(w->ev[1], w->stream));
+  LSQ_HIP(hipMemcpyAsync(w->pin, w->matnorms, 8 * sizeof(double), hipMemcpyDeviceToHost, w->stream));
+  LSQ_HIP(hipStreamSynchronize(w->stream));
+  bool finite = true;
+  for (int k = 0; k < 4; ++k) {
+    mx[k] = w->pin[4 + k];
+    if (std::isnan(mx[k])) finite = false;
+  }
+  *ms = elapsed(w->ev[0], w->ev[1]);
+  return finite;
+}
+
+void fill_best(lsq_result* res, int attempts, const BestIter& b, const RungOut& last) {
+  if (!res) return;
+  res->info = 3;
+  res->prec_used = b.prec;
+  res->solver_used = b.solver;
+  res->attempts = attempts;
+  res->ir_steps = b.steps;
+  res->gmres_iters = b.inner;
+  for (int q = 0; q < 3; ++q) res->berr[q] = b.berr[q];
+  res->berr_max = b.berr_max;
+  res->ms_convert = last.ms_convert;
+  res->ms_factor = last.ms_factor;
+  res->ms_refine = last.ms_refine;
+}
+
+void d2d(Worker* w, double* dst, const double* src, int n) {
+  if (dst && n > 0)
+    LSQ_HIP(hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+}
+
 // The ladder for one LSE instance on worker w (arguments already checked).
 int lse_solve_core(Worker* w, int m, int n, int p, const double* A, int lda, const double* B,
                    int ldb, const double* b, const double* d, double* x, double* r, double* v,
                    const lsq_opts& o_in, lsq_result* res, const float* sel_w) {
   Ctx& ctx = w->ctx;
   LseArgs a{m, n, p, A, B, b, d, lda, ldb};
-  frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, w->matnorms);
+  double mx[4];
+  float ms_convert = 0.0f;
+  RungOut ro;
+  if (!ingest(w, A, lda, m, n, B, ldb, p, n, b, m, d, p, mx, &ms_convert)) {
+    ro.ms_convert = ms_convert;
+    fill_result(res, 5, 0, 0, 0, ro);
+    return 5;
+  }
   double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
   double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
   double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
+  double* xb = ctx.ws->get<double>(n > 0 ? n : 1);
+  double* rb = ctx.ws->get<double>(m > 0 ? m : 1);
+  double* vb = ctx.ws->get<double>(p > 0 ? p : 1);
+  BestIter best;
+  best.save = [&]() { d2d(w, xb, xi, n); d2d(w, rb, ri, m); d2d(w, vb, vi, p); };
   lsq_opts o = o_in;
   LseSolver pre;
-  bool have_pre = false, pre_ok = true;
+  bool have_pre = false;
+  int pre_code = 0;
   if (sel_w && (o.prec == LSQ_PREC_AUTO || o.solver == LSQ_SOLVER_AUTO)) {
-    pre_ok = lse_prefactor(w, a, kSelFactorPrec, o, pre);
+    pre_code = lse_prefactor(w, a, kSelFactorPrec, o, pre, mx);
     have_pre = true;
     const Selection sl = select_run(w, LSQ_LSE, m, n, p, pre.fb, p, pre.fa, n - p, n, sel_w);
-    if (o.prec == LSQ_PREC_AUTO) o.prec = pre_ok ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
+    if (o.prec == LSQ_PREC_AUTO) o.prec = pre_code == 0 ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
     if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
   }
   const auto rungs = ladder(o);
-  RungOut ro;
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
   for (const auto& [prec, solvers] : rungs) {
-    ro = lse_rung(w, a, prec, solvers, o, xi, ri, vi, attempts, used_s, have_pre ? &pre : nullptr,
-                  pre_ok);
+    ro = lse_rung(w, a, prec, solvers, o, xi, ri, vi, attempts, used_s, mx, &best,
+                  have_pre ? &pre : nullptr, pre_code);
     used_p = prec;
-    if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
+    if (ro.breakdown && prec == LSQ_PREC_FP64) { info = ro.breakdown; break; }
     if (ro.ok) { info = 0; break; }
+    if (ro.singular) { info = ro.singular; break; }
   }
-  if (info != 1) {
-    if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
-    if (r && m > 0) LSQ_HIP(hipMemcpyAsync(r, ri, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
-    if (v && p > 0) LSQ_HIP(hipMemcpyAsync(v, vi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
+  ro.ms_convert = ms_convert;
+  if (info == 0) {
+    d2d(w, x, xi, n); d2d(w, r, ri, m); d2d(w, v, vi, p);
+    fill_result(res, info, used_p, used_s, attempts, ro);
+  } else if (info == 3) {
+    if (!best.have) {
+      // no rung produced a finite iterate: return x = 0 (r = v = 0) with its
+      // backward error
+      vec_zero(ctx, xb, 8, n); vec_zero(ctx, rb, 8, m); vec_zero(ctx, vb, 8, p);
+      double* f1 = ctx.ws->get<double>(m > 0 ? m : 1);
+      double* f2 = ctx.ws->get<double>(p > 0 ? p : 1);
+      double* f3 = ctx.ws->get<double>(n > 0 ? n : 1);
+      lse_residual(ctx, m, n, p, A, lda, B, ldb, b, d, xb, rb, vb, f1, f2, f3, w->matnorms, o.tol,
+                   w->st_dev);
+      read_status(w);
+      for (int q = 0; q < 3; ++q) best.berr[q] = w->st_host->berr[q];
+      best.berr_max = w->st_host->berr_max;
+      best.prec = used_p;
+      best.solver = used_s;
+    }
+    d2d(w, x, xb, n); d2d(w, r, rb, m); d2d(w, v, vb, p);
+    fill_best(res, attempts, best, ro);
+  } else {
+    fill_result(res, info, used_p, used_s, attempts, ro);
   }
   LSQ_HIP(hipStreamSynchronize(w->stream));
-  fill_result(res, info, used_p, used_s, attempts, ro);
   return info;
 }
 
@@ -1286,37 +1487,67 @@ int gls_solve_core(Worker* w, int n, int m, int p, const double* W, int ldw, con
                    lsq_result* res, const float* sel_w) {
   Ctx& ctx = w->ctx;
   GlsArgs a{n, m, p, W, V, d, ldw, ldv};
-  frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, w->matnorms);
+  double mx[4];
+  float ms_convert = 0.0f;
+  RungOut ro;
+  if (!ingest(w, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, mx, &ms_convert)) {
+    ro.ms_convert = ms_convert;
+    fill_result(res, 5, 0, 0, 0, ro);
+    return 5;
+  }
   double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
   double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
   double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
+  double* xb = ctx.ws->get<double>(m > 0 ? m : 1);
+  double* yb = ctx.ws->get<double>(p > 0 ? p : 1);
+  double* zb = ctx.ws->get<double>(n > 0 ? n : 1);
+  BestIter best;
+  best.save = [&]() { d2d(w, xb, xi, m); d2d(w, yb, yi, p); d2d(w, zb, zi, n); };
   lsq_opts o = o_in;
   GlsSolver pre;
-  bool have_pre = false, pre_ok = true;
+  bool have_pre = false;
+  int pre_code = 0;
   if (sel_w && (o.prec == LSQ_PREC_AUTO || o.solver == LSQ_SOLVER_AUTO)) {
-    pre_ok = gls_prefactor(w, a, kSelFactorPrec, o, pre);
+    pre_code = gls_prefactor(w, a, kSelFactorPrec, o, pre, mx);
     have_pre = true;
     const Selection sl = select_run(w, LSQ_GLS, m, n, p, pre.fw, m, pre.fv, n - m, n, sel_w);
-    if (o.prec == LSQ_PREC_AUTO) o.prec = pre_ok ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
+    if (o.prec == LSQ_PREC_AUTO) o.prec = pre_code == 0 ? class_prec(sl.cls[0]) : LSQ_PREC_FP64;
     if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
   }
   const auto rungs = ladder(o);
-  RungOut ro;
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
   for (const auto& [prec, solvers] : rungs) {
-    ro = gls_rung(w, a, prec, solvers, o, xi, yi, zi, attempts, used_s, have_pre ? &pre : nullptr,
-                  pre_ok);
+    ro = gls_rung(w, a, prec, solvers, o, xi, yi, zi, attempts, used_s, mx, &best,
+                  have_pre ? &pre : nullptr, pre_code);
     used_p = prec;
-    if (ro.breakdown && prec == LSQ_PREC_FP64) { info = 1; break; }
+    if (ro.breakdown && prec == LSQ_PREC_FP64) { info = ro.breakdown; break; }
     if (ro.ok) { info = 0; break; }
+    if (ro.singular) { info = ro.singular; break; }
   }
-  if (info != 1) {
-    if (m > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
-    if (p > 0) LSQ_HIP(hipMemcpyAsync(y, yi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
-    if (z && n > 0) LSQ_HIP(hipMemcpyAsync(z, zi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+  ro.ms_convert = ms_convert;
+  if (info == 0) {
+    d2d(w, x, xi, m); d2d(w, y, yi, p); d2d(w, z, zi, n);
+    fill_result(res, info, used_p, used_s, attempts, ro);
+  } else if (info == 3) {
+    if (!best.have) {
+      vec_zero(ctx, xb, 8, m); vec_zero(ctx, yb, 8, p); vec_zero(ctx, zb, 8, n);
+      double* f1 = ctx.ws->get<double>(p > 0 ? p : 1);
+      double* f2 = ctx.ws->get<double>(n > 0 ? n : 1);
+      double* f3 = ctx.ws->get<double>(m > 0 ? m : 1);
+      gls_residual(ctx, n, m, p, W, ldw, V, ldv, d, xb, yb, zb, f1, f2, f3, w->matnorms, o.tol,
+                   w->st_dev);
+      read_status(w);
+      for (int q = 0; q < 3; ++q) best.berr[q] = w->st_host->berr[q];
+      best.berr_max = w->st_host->berr_max;
+      best.prec = used_p;
+      best.solver = used_s;
+    }
+    d2d(w, x, xb, m); d2d(w, y, yb, p); d2d(w, z, zb, n);
+    fill_best(res, attempts, best, ro);
+  } else {
+    fill_result(res, info, used_p, used_s, attempts, ro);
   }
   LSQ_HIP(hipStreamSynchronize(w->stream));
-  fill_result(res, info, used_p, used_s, attempts, ro);
   return info;
 }
 
@@ -1565,14 +1796,14 @@ int lsq_selector_features(lsq_handle h, const lsq_problem* q, float* feats, floa
       frob_norms(w->ctx, q->A, q->lda, q->m, q->n, q->B, q->ldb, q->p, q->n, q->b, q->m, q->d, q->p,
                  w->matnorms);
       LseSolver sv;
-      lse_prefactor(w, a, kSelFactorPrec, o, sv);
+      lse_prefactor(w, a, kSelFactorPrec, o, sv, nullptr);
       sl = select_run(w, LSQ_LSE, q->m, q->n, q->p, sv.fb, q->p, sv.fa, q->n - q->p, q->n, h->sel_w);
     } else {
       GlsArgs a{q->n, q->m, q->p, q->A, q->B, q->d, q->lda, q->ldb};
       frob_norms(w->ctx, q->A, q->lda, q->n, q->m, q->B, q->ldb, q->n, q->p, q->d, q->n, nullptr, 0,
                  w->matnorms);
       GlsSolver sv;
-      gls_prefactor(w, a, kSelFactorPrec, o, sv);
+      gls_prefactor(w, a, kSelFactorPrec, o, sv, nullptr);
       sl = select_run(w, LSQ_GLS, q->m, q->n, q->p, sv.fw, q->m, sv.fv, q->n - q->m, q->n, h->sel_w);
     }
     for (int i = 0; i < kSelFeatures; ++i) feats[i] = sl.feats[i];
@@ -1598,18 +1829,27 @@ int lse_factor(lsq_handle h, int m, int n, int p, const double* A, int lda, cons
   f->owner = h; f->device = h->w.device; f->type = LSQ_LSE; f->prec = prec;
   f->m = m; f->n = n; f->p = p; f->A = A; f->lda = lda; f->B = B; f->ldb = ldb;
   const int rc = guard(h, "lse_factor", [&]() -> int {
+    double mx[4];
+    float ms = 0.0f;
+    if (!ingest(&h->w, A, lda, m, n, B, ldb, p, n, nullptr, 0, nullptr, 0, mx, &ms)) return 5;
     f->ctx = h->w.ctx;
     f->ctx.ws = &f->arena;
     LseSolver& sv = f->lse;
     sv.m = m; sv.n = n; sv.p = p; sv.k = n - p; sv.prec_id = prec; sv.ps = ps;
-    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc);
+    sv.sA = pow2_scale(mx[0]);
+    sv.sB = pow2_scale(mx[1]);
+    // the factorization's temporaries go to the handle's arena
+    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc, &h->w.arena);
     const int sb = read_int(&h->w, sv.fb.status);
     const int sa = read_int(&h->w, sv.fa.status);
+    sv.pmark = f->arena.mark();
+    sv.has_pmark = true;
     return (sb || sa) ? 1 : 0;
   });
   if (rc != 0) {
     factors_free(f);
     if (rc == 1) h->last_error = "lse_factor: a panel factorization broke down at this precision";
+    if (rc == 5) h->last_error = "lse_factor: a non-finite value in A or B";
     return rc;
   }
   *factors = f;
@@ -1631,18 +1871,26 @@ int gls_factor(lsq_handle h, int n, int m, int p, const double* W, int ldw, cons
   f->owner = h; f->device = h->w.device; f->type = LSQ_GLS; f->prec = prec;
   f->m = m; f->n = n; f->p = p; f->A = W; f->lda = ldw; f->B = V; f->ldb = ldv;
   const int rc = guard(h, "gls_factor", [&]() -> int {
+    double mx[4];
+    float ms = 0.0f;
+    if (!ingest(&h->w, W, ldw, n, m, V, ldv, n, p, nullptr, 0, nullptr, 0, mx, &ms)) return 5;
     f->ctx = h->w.ctx;
     f->ctx.ws = &f->arena;
     GlsSolver& sv = f->gls;
     sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.prec_id = prec; sv.ps = ps;
-    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc);
+    sv.sW = pow2_scale(mx[0]);
+    sv.sV = pow2_scale(mx[1]);
+    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc, &h->w.arena);
     const int sw = read_int(&h->w, sv.fw.status);
     const int sv_ = read_int(&h->w, sv.fv.status);
+    sv.pmark = f->arena.mark();
+    sv.has_pmark = true;
     return (sw || sv_) ? 1 : 0;
   });
   if (rc != 0) {
     factors_free(f);
     if (rc == 1) h->last_error = "gls_factor: a panel factorization broke down at this precision";
+    if (rc == 5) h->last_error = "gls_factor: a non-finite value in W or V";
     return rc;
   }
   *factors = f;
@@ -1672,19 +1920,35 @@ int lse_solve_factored(lsq_handle h, lsq_factors f, const double* b, const doubl
     f->ctx.ws = keep;
     f->lse.pctx = &f->ctx;
     LseArgs a{m, n, p, f->A, f->B, b, d, f->lda, f->ldb};
-    frob_norms(ctx, f->A, f->lda, m, n, f->B, f->ldb, p, n, b, m, d, p, w->matnorms);
+    double mx[4];
+    float ms_convert = 0.0f;
+    RungOut ro;
+    if (!ingest(w, f->A, f->lda, m, n, f->B, f->ldb, p, n, b, m, d, p, mx, &ms_convert)) {
+      ro.ms_convert = ms_convert;
+      fill_result(res, 5, f->prec, 0, 0, ro);
+      return 5;
+    }
     double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
     double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
     double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
+    double* xb = ctx.ws->get<double>(n > 0 ? n : 1);
+    double* rb = ctx.ws->get<double>(m > 0 ? m : 1);
+    double* vb = ctx.ws->get<double>(p > 0 ? p : 1);
+    BestIter best;
+    best.save = [&]() { d2d(w, xb, xi, n); d2d(w, rb, ri, m); d2d(w, vb, vi, p); };
     int attempts = 0, used_s = 0;
-    RungOut ro = lse_rung(w, a, f->prec, solvers, o, xi, ri, vi, attempts, used_s, &f->lse, true);
+    ro = lse_rung(w, a, f->prec, solvers, o, xi, ri, vi, attempts, used_s, nullptr, &best, &f->lse, 0);
     ro.ms_factor = 0.0f;
+    ro.ms_convert = ms_convert;
     const int info = ro.ok ? 0 : 3;
-    if (n > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
-    if (r && m > 0) LSQ_HIP(hipMemcpyAsync(r, ri, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
-    if (v && p > 0) LSQ_HIP(hipMemcpyAsync(v, vi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
+    if (info == 0 || !best.have) {
+      d2d(w, x, xi, n); d2d(w, r, ri, m); d2d(w, v, vi, p);
+      fill_result(res, info, f->prec, used_s, attempts, ro);
+    } else {
+      d2d(w, x, xb, n); d2d(w, r, rb, m); d2d(w, v, vb, p);
+      fill_best(res, attempts, best, ro);
+    }
     LSQ_HIP(hipStreamSynchronize(w->stream));
-    fill_result(res, info, f->prec, used_s, attempts, ro);
     return info;
   });
 }
@@ -1712,21 +1976,44 @@ int gls_solve_factored(lsq_handle h, lsq_factors f, const double* d, double* x, 
     f->ctx.ws = keep;
     f->gls.pctx = &f->ctx;
     GlsArgs a{n, m, p, f->A, f->B, d, f->lda, f->ldb};
-    frob_norms(ctx, f->A, f->lda, n, m, f->B, f->ldb, n, p, d, n, nullptr, 0, w->matnorms);
+    double mx[4];
+    float ms_convert = 0.0f;
+    RungOut ro;
+    if (!ingest(w, f->A, f->lda, n, m, f->B, f->ldb, n, p, d, n, nullptr, 0, mx, &ms_convert)) {
+      ro.ms_convert = ms_convert;
+      fill_result(res, 5, f->prec, 0, 0, ro);
+      return 5;
+    }
     double* xi = ctx.ws->get<double>(m > 0 ? m : 1);
     double* yi = ctx.ws->get<double>(p > 0 ? p : 1);
     double* zi = ctx.ws->get<double>(n > 0 ? n : 1);
+    double* xb = ctx.ws->get<double>(m > 0 ? m : 1);
+    double* yb = ctx.ws->get<double>(p > 0 ? p : 1);
+    double* zb = ctx.ws->get<double>(n > 0 ? n : 1);
+    BestIter best;
+    best.save = [&]() { d2d(w, xb, xi, m); d2d(w, yb, yi, p); d2d(w, zb, zi, n); };
     int attempts = 0, used_s = 0;
-    RungOut ro = gls_rung(w, a, f->prec, solvers, o, xi, yi, zi, attempts, used_s, &f->gls, true);
+    ro = gls_rung(w, a, f->prec, solvers, o, xi, yi, zi, attempts, used_s, nullptr, &best, &f->gls, 0);
     ro.ms_factor = 0.0f;
+    ro.ms_convert = ms_convert;
     const int info = ro.ok ? 0 : 3;
-    if (m > 0) LSQ_HIP(hipMemcpyAsync(x, xi, sizeof(double) * m, hipMemcpyDeviceToDevice, w->stream));
-    if (p > 0) LSQ_HIP(hipMemcpyAsync(y, yi, sizeof(double) * p, hipMemcpyDeviceToDevice, w->stream));
-    if (z && n > 0) LSQ_HIP(hipMemcpyAsync(z, zi, sizeof(double) * n, hipMemcpyDeviceToDevice, w->stream));
+    if (info == 0 || !best.have) {
+      d2d(w, x, xi, m); d2d(w, y, yi, p); d2d(w, z, zi, n);
+      fill_result(res, info, f->prec, used_s, attempts, ro);
+    } else {
+      d2d(w, x, xb, m); d2d(w, y, yb, p); d2d(w, z, zb, n);
+      fill_best(res, attempts, best, ro);
+    }
     LSQ_HIP(hipStreamSynchronize(w->stream));
-    fill_result(res, info, f->prec, used_s, attempts, ro);
     return info;
   });
+}
+
+int lsq_dbg_factors_bytes(lsq_factors f, long long* in_use, long long* capacity) {
+  if (!f) return -1;
+  if (in_use) *in_use = (long long)f->arena.in_use();
+  if (capacity) *capacity = (long long)f->arena.capacity();
+  return 0;
 }
 
 int lsq_factors_destroy(lsq_factors f) {

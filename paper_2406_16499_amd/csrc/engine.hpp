@@ -20,6 +20,13 @@ class Arena {
   template <typename T> T* get(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
   void reset();
   void release();
+  // Position of the next allocation; rewind(mark) frees everything allocated
+  // after it (the memory stays with the arena for reuse).
+  struct Mark { size_t chunk = 0, used = 0; };
+  Mark mark() const;
+  void rewind(const Mark& m);
+  size_t capacity() const;   // bytes held in chunks
+  size_t in_use() const;     // bytes handed out since the last reset / rewind
  private:
   struct Chunk { char* base; size_t size; size_t used; };
   std::vector<Chunk> chunks_;
@@ -141,10 +148,17 @@ void vec_zero(Ctx& ctx, void* y, int ty, int n);
 void vec_move(Ctx& ctx, void* dst, void* src, int t, int n);
 
 // Dense FP64 matrix -> Tw copy with optional transpose and index reversal:
-// dst (dr x dc, ld ldd) [i][j] = src[ri][ci] where (ri, ci) = trans ? (j, i) : (i, j),
+// dst (dr x dc, ld ldd) [i][j] = scale * src[ri][ci] where (ri, ci) = trans ? (j, i) : (i, j),
 // then ri, ci reversed when rev_r / rev_c (relative to src's own extents).
 void mat_convert(Ctx& ctx, void* dst, int td, int ldd, const void* src, int ts, int lds,
-                 int dr, int dc, bool trans, bool rev_rows_src, bool rev_cols_src);
+                 int dr, int dc, bool trans, bool rev_rows_src, bool rev_cols_src,
+                 double scale = 1.0);
+// Multiplies the triangular factor of f (the entries on and above the
+// diagonal of its first k rows) by s: undoes the power-of-two scale a matrix
+// was factored with (exact in binary floating point).
+void scale_upper(Ctx& ctx, QRFactor& f, double s);
+// out[0] = min |diag|, out[1] = max |diag| of f.M[o:o+nn, o:o+nn] (synchronizes).
+void diag_minmax(Ctx& ctx, const QRFactor& f, int o, int nn, double* out);
 
 // ------------------------------------------------- FP64 residual sweep ----
 // One pass over a column-major FP64 matrix M (rows x cols) yielding partial
@@ -179,7 +193,10 @@ void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const
                   int ldv, const double* d, const double* x, const double* y, const double* z,
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
                   StopStatus* st);
-// matnorms[0..1] = ||A||_F, ||B||_F; matnorms[2..3] = ||b||, ||d|| (LSE) or ||d||, 0 (GLS).
+// matnorms[0..1] = ||A||_F, ||B||_F; matnorms[2..3] = ||b||, ||d|| (LSE) or ||d||, 0 (GLS);
+// matnorms[4..7] = the largest magnitudes of the same four inputs, NaN for an
+// input that holds a non-finite value.  Norms are exact to rounding over the
+// whole FP64 range (no overflow or underflow of the squares).
 // Plain copy of `bytes` bytes (16-byte vector loads/stores; calibration kernel).
 void dev_copy(Ctx& ctx, void* dst, const void* src, size_t bytes);
 

@@ -125,6 +125,35 @@ __global__ __launch_bounds__(256) void k_min_abs_diag(const Tw* __restrict__ M, 
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+template <typename Tw>
+__global__ __launch_bounds__(256) void k_diag_minmax(const Tw* __restrict__ M, int ld, int nn,
+                                                     double* __restrict__ out) {
+  __shared__ double rmin[256];
+  __shared__ double rmax[256];
+  double lo = INFINITY, hi = 0.0;
+  for (int i = threadIdx.x; i < nn; i += 256) {
+    const double a = fabs((double)M[(size_t)i + (size_t)i * ld]);
+    lo = isnan(a) ? a : fmin(lo, a);
+    hi = isnan(a) ? a : fmax(hi, a);
+  }
+  rmin[threadIdx.x] = lo;
+  rmax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double a = rmin[threadIdx.x], b = rmin[threadIdx.x + s];
+      const double c = rmax[threadIdx.x], d = rmax[threadIdx.x + s];
+      rmin[threadIdx.x] = (isnan(a) || isnan(b)) ? NAN : fmin(a, b);
+      rmax[threadIdx.x] = (isnan(c) || isnan(d)) ? NAN : fmax(c, d);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = rmin[0];
+    out[1] = rmax[0];
+  }
+}
+
 // ------------------------------------------------------------------ host --
 void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c1, const double* p1,
              int np1, double c2, const double* p2, int np2) {
@@ -161,6 +190,23 @@ double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn) {
   LSQ_HIP(hipMemcpyAsync(ctx.pin, out, sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
   LSQ_HIP(hipStreamSynchronize(ctx.stream));
   return ctx.pin[0];
+}
+
+void diag_minmax(Ctx& ctx, const QRFactor& f, int o, int nn, double* out) {
+  out[0] = out[1] = 0.0;
+  if (nn <= 0) return;
+  double* d = ctx.ws->get<double>(2);
+  if (f.tw == 8)
+    hipLaunchKernelGGL((k_diag_minmax<double>), dim3(1), dim3(256), 0, ctx.stream,
+                       static_cast<const double*>(f.M) + (size_t)o * (f.ld + 1), f.ld, nn, d);
+  else
+    hipLaunchKernelGGL((k_diag_minmax<float>), dim3(1), dim3(256), 0, ctx.stream,
+                       static_cast<const float*>(f.M) + (size_t)o * (f.ld + 1), f.ld, nn, d);
+  LSQ_LAUNCH_CHECK();
+  LSQ_HIP(hipMemcpyAsync(ctx.pin, d, 2 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+  LSQ_HIP(hipStreamSynchronize(ctx.stream));
+  out[0] = ctx.pin[0];
+  out[1] = ctx.pin[1];
 }
 
 // The operator as a replayable HIP graph: apply() is captured once from a

@@ -133,7 +133,7 @@ template <typename Td, typename Ts>
 __global__ __launch_bounds__(256) void k_mat_convert(Td* __restrict__ dst, int ldd,
                                                      const Ts* __restrict__ src, int lds, int dr,
                                                      int dc, int trans, int rev_r, int rev_c,
-                                                     int sr, int sc) {
+                                                     int sr, int sc, double scale) {
   __shared__ double tile[64 * 65];
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int t = threadIdx.x;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_mat_convert(Td* __restrict__ dst, int l
       int a = trans ? j : i, b = trans ? i : j;
       if (rev_r) a = sr - 1 - a;
       if (rev_c) b = sc - 1 - b;
-      v = (double)src[(size_t)a + (size_t)b * lds];
+      v = (double)src[(size_t)a + (size_t)b * lds] * scale;
     }
     tile[(i - i0) * 65 + (j - j0)] = v;
   }
@@ -158,16 +158,36 @@ __global__ __launch_bounds__(256) void k_mat_convert(Td* __restrict__ dst, int l
 }
 
 void mat_convert(Ctx& ctx, void* dst, int td, int ldd, const void* src, int ts, int lds,
-                 int dr, int dc, bool trans, bool rev_r, bool rev_c) {
+                 int dr, int dc, bool trans, bool rev_r, bool rev_c, double scale) {
   if (dr <= 0 || dc <= 0) return;
   const int sr = trans ? dc : dr, sc = trans ? dr : dc;
   dim3 grid(ceil_div(dr, 64), ceil_div(dc, 64));
 #define F(TD, TS)                                                                       \
   hipLaunchKernelGGL((k_mat_convert<TD, TS>), grid, dim3(256), 0, ctx.stream,           \
                      static_cast<TD*>(dst), ldd, static_cast<const TS*>(src), lds, dr, dc, \
-                     trans ? 1 : 0, rev_r ? 1 : 0, rev_c ? 1 : 0, sr, sc);
+                     trans ? 1 : 0, rev_r ? 1 : 0, rev_c ? 1 : 0, sr, sc, scale);
   LSQ_DISPATCH2(td, ts, F)
 #undef F
+  LSQ_LAUNCH_CHECK();
+}
+
+// Entries on and above the diagonal of the first k rows, times s.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale_upper(T* __restrict__ M, int ld, int k, int c, double s) {
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (j < c && i < k && i <= j) M[(size_t)i + (size_t)j * ld] = (T)((double)M[(size_t)i + (size_t)j * ld] * s);
+}
+
+void scale_upper(Ctx& ctx, QRFactor& f, double s) {
+  if (f.k <= 0 || f.c <= 0 || s == 1.0) return;
+  const dim3 grid(ceil_div(f.k, 256), f.c);
+  if (f.tw == 8)
+    hipLaunchKernelGGL((k_scale_upper<double>), grid, dim3(256), 0, ctx.stream, static_cast<double*>(f.M),
+                       f.ld, f.k, f.c, s);
+  else
+    hipLaunchKernelGGL((k_scale_upper<float>), grid, dim3(256), 0, ctx.stream, static_cast<float*>(f.M),
+                       f.ld, f.k, f.c, s);
   LSQ_LAUNCH_CHECK();
 }
 
@@ -419,27 +439,84 @@ void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const
 }
 
 // --------------------------------------------------------------- norms ----
+// One read of each input yields its Frobenius norm, its largest magnitude and
+// whether it holds a non-finite value.  The sum of squares is kept three times
+// (entries scaled by 2^-600, unscaled, scaled by 2^600) so that the norm is
+// right over the whole FP64 range: the unscaled sum when it neither overflows
+// nor underflows, else the scaled one that does not.
+// Work items are 1024-row segments of one column (contiguous reads); each
+// work-group writes per slot k: lo, mid, hi sums and the max (NaN when a
+// non-finite entry was seen) at part[(4 k + s) * per + block].
+constexpr double kTwo600 = 4.149515568880993e180;    // 2^600
+constexpr double kTwoM600 = 2.409919865102884e-181;  // 2^-600
+
 __global__ __launch_bounds__(256) void k_sumsq_mat(const double* __restrict__ M, int ld, int rows,
-                                                   int cols, double* __restrict__ part) {
+                                                   int cols, double* __restrict__ part, int per) {
   __shared__ double red[4];
-  double s = 0.0;
-  const size_t total = (size_t)rows * cols;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-    const size_t i = e % rows, j = e / rows;
-    const double v = M[i + j * (size_t)ld];
-    s += v * v;
+  double lo = 0.0, mid = 0.0, hi = 0.0, mx = 0.0, bad = 0.0;
+  const int nseg = (rows + 1023) / 1024;
+  const long long items = (long long)nseg * cols;
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int j = (int)(it / nseg), i0 = (int)(it % nseg) * 1024;
+    const double* col = M + (size_t)j * ld;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = i0 + q * 256 + threadIdx.x;
+      if (i < rows) {
+        const double v = col[i];
+        if (!isfinite(v)) {
+          bad = 1.0;
+        } else {
+          const double a = fabs(v);
+          mx = fmax(mx, a);
+          const double vl = v * kTwoM600, vh = v * kTwo600;
+          lo = fma(vl, vl, lo);
+          mid = fma(v, v, mid);
+          hi = fma(vh, vh, hi);
+        }
+      }
+    }
   }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
+  lo = block_sum(lo, red);
+  mid = block_sum(mid, red);
+  hi = block_sum(hi, red);
+  bad = block_sum(bad, red);
+  mx = block_max(mx, red);
+  if (threadIdx.x == 0) {
+    part[(size_t)0 * per + blockIdx.x] = lo;
+    part[(size_t)1 * per + blockIdx.x] = mid;
+    part[(size_t)2 * per + blockIdx.x] = hi;
+    part[(size_t)3 * per + blockIdx.x] = bad > 0.0 ? NAN : mx;
+  }
 }
 
+// out[k] = ||input k|| (k < 4), out[4 + k] = its largest magnitude, NaN when
+// it holds a non-finite value.
 __global__ void k_norms_final(const double* __restrict__ part, int per, double* __restrict__ out) {
   __shared__ double red[4];
   for (int k = 0; k < 4; ++k) {
-    double s = 0.0;
-    for (int q = threadIdx.x; q < per; q += blockDim.x) s += part[(size_t)k * per + q];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[k] = sqrt(s);
+    const double* pk = part + (size_t)4 * k * per;
+    double lo = 0.0, mid = 0.0, hi = 0.0, mx = 0.0, bad = 0.0;
+    for (int q = threadIdx.x; q < per; q += blockDim.x) {
+      lo += pk[q];
+      mid += pk[per + q];
+      hi += pk[2 * per + q];
+      const double m = pk[3 * per + q];
+      if (isnan(m)) bad = 1.0; else mx = fmax(mx, m);
+    }
+    lo = block_sum(lo, red);
+    mid = block_sum(mid, red);
+    hi = block_sum(hi, red);
+    bad = block_sum(bad, red);
+    mx = block_max(mx, red);
+    if (threadIdx.x == 0) {
+      double nrm;
+      if (!isfinite(mid)) nrm = sqrt(lo) * kTwo600;              // squares overflow
+      else if (mid < 0x1p-960 && hi > 0.0) nrm = sqrt(hi) * kTwoM600;   // squares underflow
+      else nrm = sqrt(mid);
+      out[k] = nrm;
+      out[4 + k] = bad > 0.0 ? NAN : mx;
+    }
   }
 }
 
@@ -447,17 +524,16 @@ void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double
                 int br, int bc, const double* v1, int n1, const double* v2, int n2,
                 double* matnorms) {
   const int per = 512;
-  double* part = ctx.ws->get<double>(4 * per);
-  vec_zero(ctx, part, 8, 4 * per);
+  double* part = ctx.ws->get<double>(16 * per);
+  vec_zero(ctx, part, 8, 16 * per);
   const double* mats[4] = {A, B, v1, v2};
   const int rr[4] = {ar, br, n1, n2}, cc[4] = {ac, bc, 1, 1}, ll[4] = {lda, ldb, n1 > 0 ? n1 : 1, n2 > 0 ? n2 : 1};
   for (int k = 0; k < 4; ++k) {
     if (!mats[k] || rr[k] <= 0 || cc[k] <= 0) continue;
-    const size_t total = (size_t)rr[k] * cc[k];
-    int g = (int)((total + 255) / 256);
-    if (g > per) g = per;
+    const long long items = (long long)ceil_div(rr[k], 1024) * cc[k];
+    const int g = (int)(items < per ? items : per);
     hipLaunchKernelGGL(k_sumsq_mat, dim3(g), dim3(256), 0, ctx.stream, mats[k], ll[k], rr[k], cc[k],
-                       part + (size_t)k * per);
+                       part + (size_t)4 * k * per, per);
   }
   hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, ctx.stream, part, per, matnorms);
   LSQ_LAUNCH_CHECK();

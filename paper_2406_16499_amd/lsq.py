@@ -105,6 +105,8 @@ _SIGS = {
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     "lsq_dbg_copy": (c_int, [_P, _P, _P, ctypes.c_longlong]),
     "lsq_dbg_batch_wait": (c_int, [_P, ctypes.c_double]),
+    "lsq_dbg_factors_bytes": (c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong)]),
     "lsq_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -217,6 +219,14 @@ class Factors:
             rc = lib.gls_solve_factored(self.handle.h, self.f, _ptr(d), _ptr(x), _ptr(y), _ptr(z),
                                         o, ctypes.byref(res))
         return rc, res
+
+    def bytes(self):
+        """(bytes in use, bytes held) of the factors' device memory."""
+        u, c = ctypes.c_longlong(), ctypes.c_longlong()
+        rc = self.handle.lib.lsq_dbg_factors_bytes(self.f, ctypes.byref(u), ctypes.byref(c))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_factors_bytes = {rc}")
+        return u.value, c.value
 
     def close(self):
         if self.f:

@@ -59,13 +59,13 @@ def _check(P, x, y, res):
         xo, ro, vo = direct.lse_solve(P.A, P.B, P.b, P.d)
         assert direct.lse_err1(P.B, P.d, x) <= 1e-13
         cond = direct.lse_cond_x(P.A, P.B, xo, ro, vo)
-        assert _fwd(x, xo) <= 10 * cond * max(U64, res.berr_max)
+        assert _fwd(x, xo) <= 10 * cond * U64
     else:
         xo, yo, zo = direct.gls_solve(P.W, P.V, P.d)
         assert direct.gls_err1(P.W, P.V, P.d, x, y) <= 1e-13
         cx, cy = direct.gls_cond_xy(P.W, P.V, xo, yo, zo)
-        assert _fwd(x, xo) <= 10 * cx * max(U64, res.berr_max)
-        assert _fwd(y, yo) <= 10 * cy * max(U64, res.berr_max)
+        assert _fwd(x, xo) <= 10 * cx * U64
+        assert _fwd(y, yo) <= 10 * cy * U64
 
 
 @pytest.mark.parametrize("mode,workers", [("workers", 1), ("workers", 4), ("workers", 8),

@@ -1,0 +1,322 @@
+"""Return codes of the solve entry points (1, 2, 3, 5), the best iterate of
+a solve that does not certify, the ingest timing, the power-of-two input
+scaling of the FP16 / BF16 factorizations, and the memory of a factors
+object over switches between solver kinds.  Every call goes through the
+C-ABI (liblsq.so)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import direct
+from paper_2406_16499_amd import lsq
+from paper_2406_16499_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+U64 = 2.0 ** -53
+SENTINEL = 12345.0
+
+
+def note(msg):
+    sys.stdout.write(f"\n[case] {msg}\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def h():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = lsq.Handle(load_selector=False)
+    yield hd
+    hd.close()
+
+
+def D(a):
+    return lsq.colmajor(a)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def filled(n, val=SENTINEL):
+    t = lsq.empty(n)
+    t.fill_(val)
+    return t
+
+
+def _fwd(a, ref):
+    s = np.max(np.abs(ref)) if ref.size else 0.0
+    d = np.max(np.abs(a - ref)) if ref.size else 0.0
+    return d / s if s > 0 else d
+
+
+# ------------------------------------------------------------ info 5 ----
+
+@pytest.mark.parametrize("where,bad", [("b", np.nan), ("d", np.inf), ("A", np.nan), ("B", -np.inf)])
+def test_lse_nonfinite_input_returns_5(h, where, bad):
+    note(f"lse info 5: {where} = {bad}")
+    P = wl.lse_gaussian(np.random.default_rng(201), 60, 30, 6)
+    arrs = {"A": P.A.copy(), "B": P.B.copy(), "b": P.b.copy(), "d": P.d.copy()}
+    a = arrs[where]
+    if a.ndim == 2:
+        a[3, 2] = bad
+    else:
+        a[1] = bad
+    m, n, p = P.shape
+    x, r, v = filled(n), filled(m), filled(p)
+    rc, res = h.lse_solve(D(arrs["A"]), D(arrs["B"]), D(arrs["b"]), D(arrs["d"]), x, r, v,
+                          lsq.default_opts(prec="fp32"))
+    assert rc == 5 and res.info == 5, (rc, h.last_error())
+    # nothing is written
+    assert np.all(H(x) == SENTINEL) and np.all(H(r) == SENTINEL) and np.all(H(v) == SENTINEL)
+
+
+@pytest.mark.parametrize("where", ["W", "V", "d"])
+def test_gls_nonfinite_input_returns_5(h, where):
+    note(f"gls info 5: {where}")
+    G = wl.gls_gaussian(np.random.default_rng(202), 50, 10, 60)
+    arrs = {"W": G.W.copy(), "V": G.V.copy(), "d": G.d.copy()}
+    a = arrs[where]
+    if a.ndim == 2:
+        a[-1, -1] = np.nan
+    else:
+        a[0] = np.inf
+    n, m, p = G.shape
+    x, y = filled(m), filled(p)
+    rc, res = h.gls_solve(D(arrs["W"]), D(arrs["V"]), D(arrs["d"]), x, y, None,
+                          lsq.default_opts(prec="fp32"))
+    assert rc == 5, (rc, h.last_error())
+    assert np.all(H(x) == SENTINEL) and np.all(H(y) == SENTINEL)
+
+
+def test_factored_nonfinite_inputs_return_5(h):
+    note("factored info 5")
+    P = wl.lse_gaussian(np.random.default_rng(203), 50, 20, 5)
+    A = P.A.copy()
+    A[0, 0] = np.nan
+    with pytest.raises(RuntimeError, match="= 5"):
+        h.lse_factor(D(A), D(P.B), "fp32")
+    F = h.lse_factor(D(P.A), D(P.B), "fp32")
+    try:
+        b = P.b.copy()
+        b[4] = np.inf
+        x = filled(20)
+        rc, res = F.solve(D(b), D(P.d), x)
+        assert rc == 5 and np.all(H(x) == SENTINEL)
+    finally:
+        F.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_and_tiny_magnitudes(h, prec):
+    # matrices with entries near 2^+-300 (b, d and the solution of order one):
+    # the power-of-two scaling keeps the panels' Gram matrices (entries of
+    # order 2^+-600 unscaled) in range, and the solution is that of the
+    # unscaled problem
+    note(f"lse magnitudes 2^300 / 2^-300 {prec}")
+    P = wl.lse_gaussian(np.random.default_rng(204), 80, 40, 8)
+    m, n, p = P.shape
+    xo, _, _ = direct.lse_solve(P.A, P.B, P.b, P.d)
+    for s in (2.0 ** 300, 2.0 ** -300):
+        x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+        rc, res = h.lse_solve(D(P.A * s), D(P.B * s), D(P.b * s), D(P.d * s), x, r, v,
+                              lsq.default_opts(prec=prec))
+        assert rc == 0, (s, rc, h.last_error(), res.as_dict())
+        assert res.as_dict()["prec_used"] == prec and res.berr_max <= 1e-14
+        assert _fwd(H(x), xo) <= 1e-12
+
+
+# ---------------------------------------------------------- info 1, 2 ----
+
+def test_lse_rank_deficient_B_returns_1(h):
+    # a zero row of B: rank(B) < p (eq. assump:lse); the panel Cholesky of
+    # the FP64 factorization of B meets an exactly zero pivot
+    note("lse info 1: zero row in B")
+    P = wl.lse_gaussian(np.random.default_rng(205), 60, 30, 6)
+    B = P.B.copy()
+    B[2, :] = 0.0
+    m, n, p = P.shape
+    x = filled(n)
+    rc, res = h.lse_solve(D(P.A), D(B), D(P.b), D(P.d), x, None, None, lsq.default_opts(prec="fp32"))
+    assert rc == 1 and res.info == 1, (rc, h.last_error(), res.as_dict())
+    assert res.as_dict()["prec_used"] == "fp64"        # low precisions escalate instead
+    assert np.all(H(x) == SENTINEL)
+
+
+def test_lse_rank_deficient_stack_returns_2(h):
+    # p = 0 and a zero column of A: rank([A; B]) < n, so T11 (here all of T)
+    # is singular: the uniqueness condition fails
+    note("lse info 2: zero column, p = 0")
+    g = np.random.default_rng(206)
+    A = g.standard_normal((50, 20))
+    A[:, 7] = 0.0
+    b = g.standard_normal(50)
+    x = filled(20)
+    rc, res = h.lse_solve(D(A), lsq.colmajor(np.zeros((0, 20))), D(b), lsq.empty(0), x, None, None,
+                          lsq.default_opts(prec="fp32"))
+    assert rc == 2 and res.info == 2, (rc, h.last_error(), res.as_dict())
+    assert np.all(H(x) == SENTINEL)
+
+
+def test_gls_rank_deficient_W_returns_1(h):
+    note("gls info 1: zero column in W")
+    G = wl.gls_gaussian(np.random.default_rng(207), 50, 10, 60)
+    W = G.W.copy()
+    W[:, 3] = 0.0
+    n, m, p = G.shape
+    x, y = filled(m), filled(p)
+    rc, res = h.gls_solve(D(W), D(G.V), D(G.d), x, y, None, lsq.default_opts(prec="fp32"))
+    assert rc == 1, (rc, h.last_error(), res.as_dict())
+    assert np.all(H(x) == SENTINEL)
+
+
+def test_gls_rank_deficient_stack_returns_2(h):
+    # m = 0 and a zero row of V: rank([W, V]) < n, T22 (all of T) singular
+    note("gls info 2: zero row in V, m = 0")
+    g = np.random.default_rng(208)
+    V = g.standard_normal((30, 45))
+    V[11, :] = 0.0
+    d = g.standard_normal(30)
+    y = filled(45)
+    rc, res = h.gls_solve(lsq.colmajor(np.zeros((30, 0))), D(V), D(d), lsq.empty(0), y, None,
+                          lsq.default_opts(prec="fp32"))
+    assert rc == 2, (rc, h.last_error(), res.as_dict())
+    assert np.all(H(y) == SENTINEL)
+
+
+# ------------------------------------------------------------- info 3 ----
+
+def test_lse_tol_zero_returns_3_with_the_best_iterate(h):
+    note("lse info 3: tol = 0")
+    P = wl.lse_gaussian(np.random.default_rng(209), 120, 60, 10)
+    m, n, p = P.shape
+    x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+    rc, res = h.lse_solve(D(P.A), D(P.B), D(P.b), D(P.d), x, r, v,
+                          lsq.default_opts(prec="fp32", tol=0.0))
+    assert rc == 3 and res.info == 3, (rc, h.last_error())
+    # the iterate returned is a converged one, with its backward error reported
+    assert 0.0 < res.berr_max <= 1e-14
+    be = direct.lse_berr(P.A, P.B, P.b, P.d, H(x), H(r), H(v))
+    assert be[3] <= 1e-14
+    xo, ro, vo = direct.lse_solve(P.A, P.B, P.b, P.d)
+    cond = direct.lse_cond_x(P.A, P.B, xo, ro, vo)
+    assert _fwd(H(x), xo) <= 10 * cond * U64
+
+
+def test_gls_tol_zero_returns_3_with_the_best_iterate(h):
+    note("gls info 3: tol = 0")
+    G = wl.gls_gaussian(np.random.default_rng(210), 80, 20, 90)
+    n, m, p = G.shape
+    x, y, z = lsq.empty(m), lsq.empty(p), lsq.empty(n)
+    rc, res = h.gls_solve(D(G.W), D(G.V), D(G.d), x, y, z, lsq.default_opts(prec="fp32", tol=0.0))
+    assert rc == 3, (rc, h.last_error())
+    assert 0.0 < res.berr_max <= 1e-14
+    assert direct.gls_berr(G.W, G.V, G.d, H(x), H(y), H(z))[3] <= 1e-14
+
+
+def test_breakdown_without_escalation_returns_3_and_zero(h):
+    # a low-precision rung that breaks down, with no ladder after it: no
+    # iterate exists, so x = 0 is returned with its backward error (1 in the
+    # first and second blocks: f = (b, d, 0))
+    note("lse info 3 after breakdown, escalate = 0")
+    P = wl.lse_gaussian(np.random.default_rng(211), 60, 30, 6)
+    B = P.B.copy()
+    B[0, :] = 0.0
+    m, n, p = P.shape
+    x, r, v = filled(n), filled(m), filled(p)
+    rc, res = h.lse_solve(D(P.A), D(B), D(P.b), D(P.d), x, r, v,
+                          lsq.default_opts(prec="fp32", escalate=0))
+    assert rc == 3, (rc, h.last_error(), res.as_dict())
+    assert np.all(H(x) == 0.0) and np.all(H(r) == 0.0) and np.all(H(v) == 0.0)
+    assert res.berr_max == pytest.approx(1.0, rel=1e-12)
+
+
+def test_ms_convert_is_timed(h):
+    note("ms_convert")
+    P = wl.config1()
+    m, n, p = P.shape
+    x = lsq.empty(n)
+    rc, res = h.lse_solve(D(P.A), D(P.B), D(P.b), D(P.d), x, None, None, lsq.default_opts(prec="fp32"))
+    assert rc == 0
+    assert res.ms_convert > 0.0 and res.ms_factor > 0.0 and res.ms_refine > 0.0
+
+
+# ------------------------------------------- FP16 / BF16 input scaling ----
+
+@pytest.mark.parametrize("prec,scale", [("fp16", 2.0 ** 20), ("fp16", 2.0 ** -30), ("bf16", 2.0 ** 20)])
+def test_lse_scaled_inputs_certify_at_low_precision(h, prec, scale):
+    # entries of 2^20 N(0,1) exceed the FP16 range (65504) and entries of
+    # 2^-30 N(0,1) fall below its subnormals; the per-matrix power-of-two scale
+    # keeps the factorization at u_f, so the rung certifies without escalating
+    note(f"lse {prec} inputs x {scale:g}")
+    P = wl.config1()
+    m, n, p = P.shape
+    A, B, b, d = P.A * scale, P.B * scale, P.b * scale, P.d * scale
+    x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+    rc, res = h.lse_solve(D(A), D(B), D(b), D(d), x, r, v,
+                          lsq.default_opts(prec=prec, solver="ir", escalate=0))
+    assert rc == 0, (rc, h.last_error(), res.as_dict())
+    assert res.as_dict()["prec_used"] == prec and res.attempts == 1
+    be = direct.lse_berr(A, B, b, d, H(x), H(r), H(v))
+    assert be[3] <= 1.01e-14
+    xo, ro, vo = direct.lse_solve(A, B, b, d)
+    cond = direct.lse_cond_x(A, B, xo, ro, vo)
+    assert _fwd(H(x), xo) <= 10 * cond * U64
+
+
+def test_gls_fp16_scaled_inputs_certify(h):
+    note("gls fp16 inputs x 2^20")
+    G = wl.gls_gaussian(np.random.default_rng(212), 120, 30, 150)
+    s = 2.0 ** 20
+    W, V, d = G.W * s, G.V * s, G.d * s
+    n, m, p = G.shape
+    x, y, z = lsq.empty(m), lsq.empty(p), lsq.empty(n)
+    rc, res = h.gls_solve(D(W), D(V), D(d), x, y, z, lsq.default_opts(prec="fp16", solver="ir", escalate=0))
+    assert rc == 0, (rc, h.last_error(), res.as_dict())
+    assert direct.gls_berr(W, V, d, H(x), H(y), H(z))[3] <= 1.01e-14
+
+
+def test_factored_fp16_scaled_inputs(h):
+    note("factored fp16 inputs x 2^20")
+    P = wl.config1()
+    m, n, p = P.shape
+    s = 2.0 ** 20
+    A, B = D(P.A * s), D(P.B * s)
+    F = h.lse_factor(A, B, "fp16")
+    try:
+        x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+        rc, res = F.solve(D(P.b * s), D(P.d * s), x, r, v,
+                          opts=lsq.default_opts(prec="fp16", solver="ir", escalate=0))
+        assert rc == 0, (rc, res.as_dict())
+        be = direct.lse_berr(P.A * s, P.B * s, P.b * s, P.d * s, H(x), H(r), H(v))
+        assert be[3] <= 1.01e-14
+    finally:
+        F.close()
+
+
+# ------------------------------------------------- factors' memory ----
+
+def test_factors_memory_stays_flat_over_solver_switches(h):
+    note("factored: IR <-> GMRES-IR switches, memory")
+    P = wl.lse_gaussian(np.random.default_rng(213), 700, 300, 40)
+    m, n, p = P.shape
+    A, B, b, d = D(P.A), D(P.B), D(P.b), D(P.d)
+    F = h.lse_factor(A, B, "fp32")
+    try:
+        xo, _, _ = direct.lse_solve(P.A, P.B, P.b, P.d)
+        seen = []
+        for it in range(6):
+            solver = "ir" if it % 2 == 0 else "gmres"
+            x = lsq.empty(n)
+            rc, res = F.solve(b, d, x, opts=lsq.default_opts(prec="fp32", solver=solver, escalate=0))
+            assert rc == 0, (it, solver, res.as_dict())
+            assert _fwd(H(x), xo) <= 1e-10
+            seen.append(F.bytes())
+        # after the first switch in each direction the usage repeats exactly
+        assert seen[2] == seen[0] and seen[4] == seen[0]
+        assert seen[3] == seen[1] and seen[5] == seen[1]
+        assert len({c for _, c in seen[1:]}) == 1      # no memory added after the first switch
+    finally:
+        F.close()

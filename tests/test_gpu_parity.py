@@ -186,8 +186,10 @@ def _check_lse(P, x, r, v, res, tol=1e-14):
     m, n, p = P.shape
     if m + n + p <= 2500:
         cond = direct.lse_cond_x(P.A, P.B, xo, ro, vo)
-        fwd = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
-        assert fwd <= 10 * cond * max(U64, be[3])
+    else:
+        cond = direct.lse_cond_x_est(P.A, P.B, xo, ro, vo)
+    fwd = np.max(np.abs(x - xo)) / np.max(np.abs(xo))
+    assert fwd <= 10 * cond * U64
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16", "fp16"])
@@ -227,11 +229,13 @@ def _check_gls(G, x, y, z, res, tol=1e-14):
     n, m, p = G.shape
     if m + n + p <= 2500:
         cx, cy = direct.gls_cond_xy(G.W, G.V, xo, yo, zo)
-        assert _fwd(x, xo) <= 10 * cx * max(U64, be[3])
-        if np.max(np.abs(yo)) > 0:
-            assert _fwd(y, yo) <= 10 * cy * max(U64, be[3])
-        else:
-            assert np.max(np.abs(y)) <= 1e-14 * (np.linalg.norm(G.d) + 1)
+    else:
+        cx, cy = direct.gls_cond_xy_est(G.W, G.V, xo, yo, zo)
+    assert _fwd(x, xo) <= 10 * cx * U64
+    if np.max(np.abs(yo)) > 0:
+        assert _fwd(y, yo) <= 10 * cy * U64
+    else:
+        assert np.max(np.abs(y)) <= 1e-14 * (np.linalg.norm(G.d) + 1)
 
 
 @pytest.mark.parametrize("n,m,p", [(60, 20, 80), (12, 4, 30), (9, 9, 3), (8, 3, 5), (300, 70, 513), (65, 64, 1)])

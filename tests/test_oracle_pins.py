@@ -264,3 +264,36 @@ def test_gls_cond_xy_take_the_x_and_y_blocks():
     assert cy == pytest.approx(ex[0], rel=1e-12)
     assert abs(ex[0] - ex[2]) > 1e-3 * ex[2] and abs(ex[1] - ex[2]) > 1e-3 * ex[2]
     assert abs(ex[1] - ex[0]) > 1e-3 * ex[0]
+
+
+# ------------------------------------------------ condition-number estimate --
+
+@pytest.mark.parametrize("m,n,p", [(200, 100, 20), (60, 30, 8), (30, 12, 4), (40, 40, 10)])
+def test_lse_cond_estimate_brackets_the_dense_value(m, n, p):
+    # the block 1-norm estimator gives a lower bound that is close to the
+    # exact value computed with the dense inverse
+    from paper_2406_16499_amd import workloads as wl
+    P = wl.lse_gaussian(np.random.default_rng(m + n + p), m, n, p)
+    x, r, v = direct.lse_solve(P.A, P.B, P.b, P.d)
+    exact = direct.lse_cond_x(P.A, P.B, x, r, v)
+    est = direct.lse_cond_x_est(P.A, P.B, x, r, v)
+    assert 0.5 * exact <= est <= exact * (1 + 1e-10)
+
+
+def test_gls_cond_estimate_brackets_the_dense_value():
+    from paper_2406_16499_amd import workloads as wl
+    G = wl.gls_gaussian(np.random.default_rng(3), 60, 20, 80)
+    x, y, z = direct.gls_solve(G.W, G.V, G.d)
+    ex = direct.gls_cond_xy(G.W, G.V, x, y, z)
+    es = direct.gls_cond_xy_est(G.W, G.V, x, y, z)
+    for e, c in zip(es, ex):
+        assert 0.5 * c <= e <= c * (1 + 1e-10)
+
+
+def test_cond_estimate_on_the_hand_worked_lse():
+    # exact rational value of the x-block (see test_lse_cond_x_takes_the_x_block)
+    m, n, p = 3, 2, 1
+    x, r, v = np.array([0.0, 1.0]), np.array([1.0, 1.0, 2.0]), np.array([3.0])
+    u = np.concatenate([r, -v, x])
+    ex = _exact_skeel_blocks(direct.lse_augmented(A, B), u, [(m + p, m + p + n)])[0]
+    assert direct.lse_cond_x_est(A, B, x, r, v) == pytest.approx(ex, rel=1e-12)

@@ -94,6 +94,10 @@ typedef struct {
   double alpha, beta;  /* GMRES scaling (Section 5); <= 0 selects alpha = ||r0||    */
                        /* (LSE) or ||y0|| (GLS) and beta = 1                        */
   int nb;              /* panel width of the blocked factorization; 0 = default     */
+  double polish;       /* after the stop test passes, one more correction while the */
+                       /* backward error is above polish, toward the limiting       */
+                       /* accuracy (forward error ~ cond u); default 8 * 2^-53;     */
+                       /* <= 0 stops at once, as Algorithms 2 and 4 do              */
 } lsq_opts;
 
 typedef struct {
@@ -145,6 +149,29 @@ int gls_solve(lsq_handle handle, int n, int m, int p,
               const double* A, int lda, const double* B, int ldb,
               const double* d, double* x, double* y, double* z,
               const lsq_opts* opts, lsq_result* res);
+
+/*
+ * Complex LSE and GLS (Section 1 states both problems over C, with
+ * Hermitian transposes): the same arguments as lse_solve / gls_solve, with
+ * every matrix and vector complex, stored as interleaved (real, imaginary)
+ * FP64 pairs (C99 double complex / LAPACK complex*16 layout), column-major
+ * with lda, ldb counted in complex elements.  The solve runs on the real
+ * embedding [Re M, -Im M; Im M, Re M] of each matrix (vectors [Re; Im]),
+ * an LSE (GLS) of twice the sizes whose augmented system is the embedding
+ * of the complex one, so its solution is the complex solution; the stop test
+ * uses the complex Frobenius norms, so res->berr is the backward error of
+ * the complex problem.  The solve holds the embedded copies (4 m n + 4 n p
+ * doubles) in the handle's workspace.  Return codes and argument numbers as
+ * lse_solve / gls_solve.
+ */
+int zlse_solve(lsq_handle handle, int m, int n, int p,
+               const double* A, int lda, const double* B, int ldb,
+               const double* b, const double* d, double* x, double* r, double* v,
+               const lsq_opts* opts, lsq_result* res);
+int zgls_solve(lsq_handle handle, int n, int m, int p,
+               const double* A, int lda, const double* B, int ldb,
+               const double* d, double* x, double* y, double* z,
+               const lsq_opts* opts, lsq_result* res);
 
 /*
  * Factor once, solve many right-hand sides.  lse_factor / gls_factor compute

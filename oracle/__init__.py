@@ -17,5 +17,9 @@ mpir     The paper's method itself on the CPU: Algorithms 1-4 (classical
          refinement with the block-diagonal split preconditioners of
          Section 5, using LAPACK single precision for the low-precision
          factorization.
+complex_lsq
+         The complex problems of Section 1 (Hermitian transposes): null-space
+         and Paige solutions over C, augmented residuals, stop-test scales,
+         backward errors and condition numbers, with no real embedding.
 """
-from . import direct, mpir  # noqa: F401
+from . import complex_lsq, direct, mpir  # noqa: F401

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -139,6 +140,10 @@ struct Worker {
   hipStream_t side = nullptr;      // look-ahead stream (default priority)
   std::vector<hipEvent_t> events;
   std::string last_error;
+  // factor applied to the Frobenius norms of the two matrices after the
+  // ingest scan: 1, or 1/sqrt(2) while a complex problem runs through its
+  // real embedding (whose Frobenius norms are sqrt(2) times the complex ones)
+  double norm_scale = 1.0;
 
   void init(int dev, int num_cu, bool new_stream) {
     device = dev;
@@ -728,6 +733,18 @@ bool stalled(const std::vector<double>& hist) {
   return false;
 }
 
+// After an iterate passed the stop test: true to stop now; false (once) to
+// take one more correction first, while its backward error is above
+// o.polish.  The stop test certifies berr <= tol; first-order perturbation
+// theory bounds the forward error by about cond * berr, so an iterate
+// certified at berr near tol = 1e-14 may sit well above the limiting
+// accuracy cond * u that one more contraction reaches.
+bool polish_done(const lsq_opts& o, const StopStatus& st, int it, bool& polished) {
+  if (polished || !(o.polish > 0.0) || st.berr_max <= o.polish || it >= o.maxit) return true;
+  polished = true;
+  return false;
+}
+
 // Classical refinement (Algorithms 2 and 4): init() adds the initial guess to
 // the zeroed iterate, residual() evaluates the FP64 residual and the stop
 // test on the device, correct() adds one correction.
@@ -740,6 +757,7 @@ RungOut run_classical(Worker* h, const std::function<void()>& zero,
   LSQ_HIP(hipEventRecord(h->ev[2], h->stream));
   init();
   std::vector<double> hist;
+  bool polished = false;
   for (int it = 0;; ++it) {
     residual();
     read_status(h);
@@ -749,8 +767,13 @@ RungOut run_classical(Worker* h, const std::function<void()>& zero,
     for (int q = 0; q < 3; ++q) out.berr[q] = st.berr[q];
     out.berr_max = st.berr_max;
     out.steps = it;
-    if (st.converged) { out.ok = true; break; }
-    if (st.nonfinite || it >= o.maxit || stalled(hist)) break;
+    if (st.converged) {
+      out.ok = true;
+      if (polish_done(o, st, it, polished)) break;
+    } else if (st.nonfinite || it >= o.maxit || stalled(hist)) {
+      out.ok = false;
+      break;
+    }
     correct();
   }
   LSQ_HIP(hipEventRecord(h->ev[3], h->stream));
@@ -790,6 +813,7 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
     sv.m_left(ctx, sv.t2, y);
   };
   std::vector<double> hist;
+  bool polished = false;
   for (int it = 0;; ++it) {
     residual();
     read_status(h);
@@ -799,8 +823,13 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
     for (int q = 0; q < 3; ++q) out.berr[q] = stt.berr[q];
     out.berr_max = stt.berr_max;
     out.steps = it;
-    if (stt.converged) { out.ok = true; break; }
-    if (stt.nonfinite || it >= o.maxit || out.inner >= o.gmres_maxit || stalled(hist)) break;
+    if (stt.converged) {
+      out.ok = true;
+      if (polish_done(o, stt, it, polished) || out.inner >= o.gmres_maxit) break;
+    } else if (stt.nonfinite || it >= o.maxit || out.inner >= o.gmres_maxit || stalled(hist)) {
+      out.ok = false;
+      break;
+    }
     scaled_residual(st);
     sv.m_left(ctx, st, rhs);
     const GmresOut g = gmres(ctx, N, apply, rhs, w, o.gmres_restart, o.gmres_tol,
@@ -1213,7 +1242,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     for (int qq : cur) flops += batch_factor_flops(hp[qq]);
     int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
     batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
-                            o.tol, o.maxit, dout, dout64, flops, h->esc_wait_ms, started, n / 4);
+                            o.tol, o.maxit, o.polish, dout, dout64, flops, h->esc_wait_ms, started, n / 4);
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
@@ -1242,7 +1271,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     const bool last = prec == LSQ_PREC_FP64 || !o.escalate;
     const int tw = prec == LSQ_PREC_FP64 ? 8 : 4;
     const int g = std::min(batch_blocks_per_cu(tw) * h->num_cu, (int)cur.size());
-    batch_launch(ctx, tw, dprobs, dorder, (int)cur.size(), dcounter, dws, stride, g, o.tol, o.maxit,
+    batch_launch(ctx, tw, dprobs, dorder, (int)cur.size(), dcounter, dws, stride, g, o.tol, o.maxit, o.polish,
                  !last, dout, flops);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
@@ -1283,6 +1312,7 @@ void lsq_opts_default(lsq_opts* o) {
   o->alpha = 0.0;
   o->beta = 0.0;
   o->nb = 0;
+  o->polish = 8.0 * 1.1102230246251565e-16;
 }
 
 int lsq_create(lsq_handle* out, int device) {
@@ -1378,6 +1408,7 @@ bool ingest(Worker* w, const double* M1, int ld1, int r1, int c1, const double* 
   Ctx& ctx = w->ctx;
   LSQ_HIP(hipEventRecord(w->ev[0], w->stream));
   frob_norms(ctx, M1, ld1, r1, c1, M2, ld2, r2, c2, v1, n1, v2, n2, w->matnorms);
+  if (w->norm_scale != 1.0) scale_first(ctx, w->matnorms, 2, w->norm_scale);
   LSQ_HIP(hipEventRecord(w->ev[1], w->stream));
   LSQ_HIP(hipMemcpyAsync(w->pin, w->matnorms, 8 * sizeof(double), hipMemcpyDeviceToHost, w->stream));
   LSQ_HIP(hipStreamSynchronize(w->stream));
@@ -1656,6 +1687,99 @@ int gls_solve(lsq_handle h, int n, int m, int p, const double* W, int ldw, const
   });
 }
 
+// Complex problems through their real embedding: the complex LSE with A
+// (m x n), B (p x n) is the real LSE with [Re A, -Im A; Im A, Re A] (2m x 2n),
+// the same embedding of B (2p x 2n) and b, d, x, r, v as [Re; Im] (the
+// embedding of A^H is the transpose of A's, so the augmented system, its
+// residual blocks and the solution carry over exactly); GLS likewise.  The
+// stop test uses the complex Frobenius norms (the embedding's divided by
+// sqrt(2)) and the vector norms, which the embedding keeps, so berr is that
+// of the complex problem.
+namespace {
+struct ComplexNorms {
+  Worker* w;
+  explicit ComplexNorms(Worker* w_) : w(w_) { w->norm_scale = std::sqrt(0.5); }
+  ~ComplexNorms() { w->norm_scale = 1.0; }
+};
+}  // namespace
+
+int zlse_solve(lsq_handle h, int m, int n, int p, const double* A, int lda, const double* B,
+               int ldb, const double* b, const double* d, double* x, double* r, double* v,
+               const lsq_opts* opts, lsq_result* res) {
+  if (!h) return -1;
+  std::string why;
+  const int bad = lse_check(m, n, p, A, lda, B, ldb, b, d, x, &why);
+  if (bad) return fail(h, bad, why);
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0) return fail(h, -14, "invalid options");
+  return guard(h, "zlse_solve", [&]() -> int {
+    Worker* w = &h->w;
+    Ctx& ctx = w->ctx;
+    const int M = 2 * m, N = 2 * n, P = 2 * p;
+    auto buf = [&](size_t len) { return ctx.ws->get<double>(len > 0 ? len : 1); };
+    double* Ae = buf((size_t)M * N);
+    double* Be = buf((size_t)P * N);
+    double *be = buf(M), *de = buf(P), *xe = buf(N), *re = buf(M), *ve = buf(P);
+    embed_mat(ctx, A, lda, m, n, Ae);
+    embed_mat(ctx, B, ldb, p, n, Be);
+    embed_vec(ctx, b, m, be);
+    embed_vec(ctx, d, p, de);
+    int info;
+    {
+      ComplexNorms cn(w);
+      info = lse_solve_core(w, M, N, P, Ae, M > 1 ? M : 1, Be, P > 1 ? P : 1, be, de, xe, re, ve, o,
+                            res, h->sel_w);
+    }
+    if (info == 0 || info == 3) {
+      unembed_vec(ctx, xe, n, x);
+      unembed_vec(ctx, re, m, r);
+      unembed_vec(ctx, ve, p, v);
+      LSQ_HIP(hipStreamSynchronize(w->stream));
+    }
+    return info;
+  });
+}
+
+int zgls_solve(lsq_handle h, int n, int m, int p, const double* W, int ldw, const double* V,
+               int ldv, const double* d, double* x, double* y, double* z, const lsq_opts* opts,
+               lsq_result* res) {
+  if (!h) return -1;
+  std::string why;
+  const int bad = gls_check(n, m, p, W, ldw, V, ldv, d, x, y, &why);
+  if (bad) return fail(h, bad, why);
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0) return fail(h, -13, "invalid options");
+  return guard(h, "zgls_solve", [&]() -> int {
+    Worker* w = &h->w;
+    Ctx& ctx = w->ctx;
+    const int Nn = 2 * n, Mm = 2 * m, P = 2 * p;
+    auto buf = [&](size_t len) { return ctx.ws->get<double>(len > 0 ? len : 1); };
+    double* We = buf((size_t)Nn * Mm);
+    double* Ve = buf((size_t)Nn * P);
+    double *de = buf(Nn), *xe = buf(Mm), *ye = buf(P), *ze = buf(Nn);
+    embed_mat(ctx, W, ldw, n, m, We);
+    embed_mat(ctx, V, ldv, n, p, Ve);
+    embed_vec(ctx, d, n, de);
+    int info;
+    {
+      ComplexNorms cn(w);
+      info = gls_solve_core(w, Nn, Mm, P, We, Nn > 1 ? Nn : 1, Ve, Nn > 1 ? Nn : 1, de, xe, ye, ze,
+                            o, res, h->sel_w);
+    }
+    if (info == 0 || info == 3) {
+      unembed_vec(ctx, xe, m, x);
+      unembed_vec(ctx, ye, p, y);
+      unembed_vec(ctx, ze, n, z);
+      LSQ_HIP(hipStreamSynchronize(w->stream));
+    }
+    return info;
+  });
+}
+
 int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
                       lsq_result* res) {
   if (!h) return -1;
@@ -1839,7 +1963,9 @@ int lse_factor(lsq_handle h, int m, int n, int p, const double* A, int lda, cons
     sv.sA = pow2_scale(mx[0]);
     sv.sB = pow2_scale(mx[1]);
     // the factorization's temporaries go to the handle's arena
-    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc, &h->w.arena);
+    // no early preparation: every prepared structure then sits above the mark
+    // taken below, so a switch of solver kind rewinds all of it
+    sv.factor(f->ctx, A, lda, B, ldb, kMaxNb, 0, &h->w.arena);
     const int sb = read_int(&h->w, sv.fb.status);
     const int sa = read_int(&h->w, sv.fa.status);
     sv.pmark = f->arena.mark();
@@ -1880,7 +2006,9 @@ int gls_factor(lsq_handle h, int n, int m, int p, const double* W, int ldw, cons
     sv.n = n; sv.m = m; sv.p = p; sv.k = n - m; sv.prec_id = prec; sv.ps = ps;
     sv.sW = pow2_scale(mx[0]);
     sv.sV = pow2_scale(mx[1]);
-    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb, prec == LSQ_PREC_FP64 ? 8 : ps.tc, &h->w.arena);
+    // no early preparation: every prepared structure then sits above the mark
+    // taken below, so a switch of solver kind rewinds all of it
+    sv.factor(f->ctx, W, ldw, V, ldv, kMaxNb, 0, &h->w.arena);
     const int sw = read_int(&h->w, sv.fw.status);
     const int sv_ = read_int(&h->w, sv.fv.status);
     sv.pmark = f->arena.mark();
@@ -1897,59 +2025,78 @@ int gls_factor(lsq_handle h, int n, int m, int p, const double* W, int ldw, cons
   return 0;
 }
 
+}  // extern "C"
+
+// Argument checks shared by the two factored LSE entry points (0 or -k).
+static int lse_factored_check(lsq_handle h, lsq_factors f, const double* b, const double* d,
+                              const double* x, const lsq_opts* opts, lsq_opts& o,
+                              std::vector<int>& solvers) {
+  if (!f || f->type != LSQ_LSE) return fail(h, -2, "factors are not LSE factors");
+  if (f->owner != h) return fail(h, -2, "factors belong to another handle");
+  if (!b && f->m > 0) return fail(h, -3, "b is null");
+  if (!d && f->p > 0) return fail(h, -4, "d is null");
+  if (!x && f->n > 0) return fail(h, -5, "x is null");
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0 || !factored_solvers(f->prec, o.solver, solvers))
+    return fail(h, -8, "invalid options");
+  return 0;
+}
+
+// Refinement of one right-hand side on stored LSE factors, on the handle's
+// worker; its per-call temporaries come from the worker context's workspace.
+static int lse_factored_run(Worker* w, lsq_factors f, const double* b, const double* d, double* x,
+                            double* r, double* v, const lsq_opts& o, const std::vector<int>& solvers,
+                            lsq_result* res) {
+  const int m = f->m, n = f->n, p = f->p;
+  Ctx& ctx = w->ctx;
+  Arena* keep = f->ctx.ws;
+  f->ctx = w->ctx;                     // the handle's current stream and events
+  f->ctx.ws = keep;
+  f->lse.pctx = &f->ctx;
+  LseArgs a{m, n, p, f->A, f->B, b, d, f->lda, f->ldb};
+  double mx[4];
+  float ms_convert = 0.0f;
+  RungOut ro;
+  if (!ingest(w, f->A, f->lda, m, n, f->B, f->ldb, p, n, b, m, d, p, mx, &ms_convert)) {
+    ro.ms_convert = ms_convert;
+    fill_result(res, 5, f->prec, 0, 0, ro);
+    return 5;
+  }
+  double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
+  double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
+  double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
+  double* xb = ctx.ws->get<double>(n > 0 ? n : 1);
+  double* rb = ctx.ws->get<double>(m > 0 ? m : 1);
+  double* vb = ctx.ws->get<double>(p > 0 ? p : 1);
+  BestIter best;
+  best.save = [&]() { d2d(w, xb, xi, n); d2d(w, rb, ri, m); d2d(w, vb, vi, p); };
+  int attempts = 0, used_s = 0;
+  ro = lse_rung(w, a, f->prec, solvers, o, xi, ri, vi, attempts, used_s, nullptr, &best, &f->lse, 0);
+  ro.ms_factor = 0.0f;
+  ro.ms_convert = ms_convert;
+  const int info = ro.ok ? 0 : 3;
+  if (info == 0 || !best.have) {
+    d2d(w, x, xi, n); d2d(w, r, ri, m); d2d(w, v, vi, p);
+    fill_result(res, info, f->prec, used_s, attempts, ro);
+  } else {
+    d2d(w, x, xb, n); d2d(w, r, rb, m); d2d(w, v, vb, p);
+    fill_best(res, attempts, best, ro);
+  }
+  LSQ_HIP(hipStreamSynchronize(w->stream));
+  return info;
+}
+
+extern "C" {
+
 int lse_solve_factored(lsq_handle h, lsq_factors f, const double* b, const double* d, double* x,
                        double* r, double* v, const lsq_opts* opts, lsq_result* res) {
   if (!h) return -1;
-  if (!f || f->type != LSQ_LSE) return fail(h, -2, "factors are not LSE factors");
-  if (f->owner != h) return fail(h, -2, "factors belong to another handle");
-  const int m = f->m, n = f->n, p = f->p;
-  if (!b && m > 0) return fail(h, -3, "b is null");
-  if (!d && p > 0) return fail(h, -4, "d is null");
-  if (!x && n > 0) return fail(h, -5, "x is null");
   lsq_opts o;
-  lsq_opts_default(&o);
-  if (opts) o = *opts;
   std::vector<int> solvers;
-  if (!(o.tol >= 0) || o.maxit < 0 || !factored_solvers(f->prec, o.solver, solvers))
-    return fail(h, -8, "invalid options");
+  if (const int bad = lse_factored_check(h, f, b, d, x, opts, o, solvers)) return bad;
   return guard(h, "lse_solve_factored", [&]() -> int {
-    Worker* w = &h->w;
-    Ctx& ctx = w->ctx;
-    Arena* keep = f->ctx.ws;
-    f->ctx = w->ctx;                     // the handle's current stream and events
-    f->ctx.ws = keep;
-    f->lse.pctx = &f->ctx;
-    LseArgs a{m, n, p, f->A, f->B, b, d, f->lda, f->ldb};
-    double mx[4];
-    float ms_convert = 0.0f;
-    RungOut ro;
-    if (!ingest(w, f->A, f->lda, m, n, f->B, f->ldb, p, n, b, m, d, p, mx, &ms_convert)) {
-      ro.ms_convert = ms_convert;
-      fill_result(res, 5, f->prec, 0, 0, ro);
-      return 5;
-    }
-    double* xi = ctx.ws->get<double>(n > 0 ? n : 1);
-    double* ri = ctx.ws->get<double>(m > 0 ? m : 1);
-    double* vi = ctx.ws->get<double>(p > 0 ? p : 1);
-    double* xb = ctx.ws->get<double>(n > 0 ? n : 1);
-    double* rb = ctx.ws->get<double>(m > 0 ? m : 1);
-    double* vb = ctx.ws->get<double>(p > 0 ? p : 1);
-    BestIter best;
-    best.save = [&]() { d2d(w, xb, xi, n); d2d(w, rb, ri, m); d2d(w, vb, vi, p); };
-    int attempts = 0, used_s = 0;
-    ro = lse_rung(w, a, f->prec, solvers, o, xi, ri, vi, attempts, used_s, nullptr, &best, &f->lse, 0);
-    ro.ms_factor = 0.0f;
-    ro.ms_convert = ms_convert;
-    const int info = ro.ok ? 0 : 3;
-    if (info == 0 || !best.have) {
-      d2d(w, x, xi, n); d2d(w, r, ri, m); d2d(w, v, vi, p);
-      fill_result(res, info, f->prec, used_s, attempts, ro);
-    } else {
-      d2d(w, x, xb, n); d2d(w, r, rb, m); d2d(w, v, vb, p);
-      fill_best(res, attempts, best, ro);
-    }
-    LSQ_HIP(hipStreamSynchronize(w->stream));
-    return info;
+    return lse_factored_run(&h->w, f, b, d, x, r, v, o, solvers, res);
   });
 }
 

@@ -1267,17 +1267,25 @@ __device__ __forceinline__ StopOut stop_test(const double s[6], const double mat
 // three steps.
 template <typename Correct, typename Residual>
 __device__ __forceinline__ void refine(Correct correct, Residual residual, const double mat[4], int gls,
-                                      double tol, int maxit, bool fast_exit, BatchOut* out) {
+                                      double tol, int maxit, double polish, bool fast_exit, BatchOut* out) {
   correct(true);
   double hist[4] = {0, 0, 0, 0};
   int it = 0;
   StopOut so;
+  bool polished = false;
   for (;; ++it) {
     double s[6];
     residual(s);
     so = stop_test(s, mat, gls, tol);
     hist[0] = hist[1]; hist[1] = hist[2]; hist[2] = hist[3]; hist[3] = so.bmax;
-    if (so.conv) break;
+    if (so.conv) {
+      // one more correction toward the limiting accuracy while the backward
+      // error is still above `polish` (polish <= 0: stop at once)
+      if (polished || !(polish > 0.0) || so.bmax <= polish || it >= maxit) break;
+      polished = true;
+      correct(false);
+      continue;
+    }
     bool stalled = it >= 3 && !(hist[3] <= 0.5 * hist[0]);
     if (fast_exit && it >= 1) {
       // a higher-precision rung follows: leave once the observed contraction
@@ -1302,7 +1310,7 @@ __device__ __forceinline__ void refine(Correct correct, Residual residual, const
 // Abar = A J Qt J = Za [T; 0] (Fa), k = n - p, T11 = T[0:k, 0:k],
 // T12 = T[0:k, k:n], T22 = T[k:m, k:n] (upper part).
 template <typename T>
-__device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit,
+__device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit, double polish,
                                              bool fast_exit, BatchOut* out,
                              BLds<T>& L) {
   const int m = P.m, n = P.n, p = P.p, k = n - p, kqa = m < n ? m : n;
@@ -1439,7 +1447,7 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     }
     wg_sum6(s, L.dred);
   };
-  refine(correct, residual, mat, 0, tol, maxit, fast_exit, out);
+  refine(correct, residual, mat, 0, tol, maxit, polish, fast_exit, out);
 }
 
 // ------------------------------------------------------------------ GLS --
@@ -1447,7 +1455,7 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
 // Vt = J_p (Qw^T V)^T J_n = Qv Tv (Fv, p x n), k = n - m,
 // A11 = Tv[0:k, 0:k], A12 = Tv[0:k, k:n], A22 = Tv[k:p, k:n] (upper part).
 template <typename T>
-__device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit,
+__device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit, double polish,
                                              bool fast_exit, BatchOut* out,
                              BLds<T>& L) {
   const int n = P.n, m = P.m, p = P.p, k = n - m, kqv = p < n ? p : n;
@@ -1586,14 +1594,14 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     }
     wg_sum6(s, L.dred);
   };
-  refine(correct, residual, mat, 1, tol, maxit, fast_exit, out);
+  refine(correct, residual, mat, 1, tol, maxit, polish, fast_exit, out);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb* __restrict__ probs,
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
-                                                  size_t ws_stride, double tol, int maxit,
+                                                  size_t ws_stride, double tol, int maxit, double polish,
                                                   int fast_exit, BatchOut* __restrict__ out,
                                                   EscQueue* __restrict__ esc, int esc_big) {
   __shared__ BLds<T> L;
@@ -1606,8 +1614,8 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
     if (q >= count) break;
     const int idx = order[q];
     const BatchProb P = probs[idx];
-    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, fast_exit != 0, out + idx, L);
-    else gls_instance<T>(P, mine, tol, maxit, fast_exit != 0, out + idx, L);
+    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, out + idx, L);
+    else gls_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, out + idx, L);
     __syncthreads();
     if (esc && threadIdx.x == 0) {
       // a failure goes to the FP64 launch beside this one: claim a slot,
@@ -1635,7 +1643,7 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
 // without that bound.
 __global__ __launch_bounds__(kBT, QrCfg<double>::BLOCKS) void k_batch_esc(
     const BatchProb* __restrict__ probs, int count, EscQueue* __restrict__ esc,
-    char* __restrict__ ws, size_t ws_stride, double tol, int maxit, BatchOut* __restrict__ out,
+    char* __restrict__ ws, size_t ws_stride, double tol, int maxit, double polish, BatchOut* __restrict__ out,
     unsigned long long spin_ticks, int* started) {
   __shared__ BLds<double> L;
   char* mine = ws + (size_t)blockIdx.x * ws_stride;
@@ -1691,8 +1699,8 @@ __global__ __launch_bounds__(kBT, QrCfg<double>::BLOCKS) void k_batch_esc(
     __syncthreads();
     if (idx < 0) break;
     const BatchProb P = probs[idx];
-    if (P.type == 0) lse_instance<double>(P, mine, tol, maxit, false, out + idx, L);
-    else gls_instance<double>(P, mine, tol, maxit, false, out + idx, L);
+    if (P.type == 0) lse_instance<double>(P, mine, tol, maxit, polish, false, out + idx, L);
+    else gls_instance<double>(P, mine, tol, maxit, polish, false, out + idx, L);
     __syncthreads();
   }
 }
@@ -1731,7 +1739,7 @@ double batch_factor_flops(const BatchProb& P) {
 }
 
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
-                  int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
+                  int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit, double polish,
                   bool fast_exit, BatchOut* out, double flops) {
   if (count <= 0 || grid <= 0) return;
   LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
@@ -1739,10 +1747,10 @@ void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, in
   ktimer_begin(ctx, kind, flops, 0.0);
   if (tw == 8)
     hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out, nullptr, 0);
+                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, out, nullptr, 0);
   else
     hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, fast_exit ? 1 : 0, out, nullptr, 0);
+                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, out, nullptr, 0);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kind);
 }
@@ -1751,7 +1759,7 @@ size_t esc_queue_bytes(int count) { return sizeof(EscQueue) + 4 * sizeof(int) * 
 
 void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
-                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit,
+                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish,
                              BatchOut* out, BatchOut* out64, double flops, double spin_ms,
                              int* started, int big_count) {
   if (count <= 0 || grid <= 0) return;
@@ -1766,7 +1774,7 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
   LSQ_HIP(hipStreamWaitEvent(ctx.side, ready, 0));
   if (started) __atomic_store_n(started, 0, __ATOMIC_RELEASE);
   hipLaunchKernelGGL(k_batch_esc, dim3(grid64a), dim3(kBT), 0, ctx.side, probs, count, q, ws64,
-                     ws_stride, tol, maxit, out64, ticks, started);
+                     ws_stride, tol, maxit, polish, out64, ticks, started);
   LSQ_LAUNCH_CHECK();
   LSQ_HIP(hipEventRecord(joined, ctx.side));
   if (started) {
@@ -1780,13 +1788,13 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
   }
   ktimer_begin(ctx, kKBatch32, flops, 0.0);
   hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                     counter, ws, ws_stride, tol, maxit, 1, out, q, big_count);
+                     counter, ws, ws_stride, tol, maxit, polish, 1, out, q, big_count);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kKBatch32);
   // more consumers once the FP32 launch is over, for what is still queued
   if (grid64b > 0) {
     hipLaunchKernelGGL(k_batch_esc, dim3(grid64b), dim3(kBT), 0, ctx.stream, probs, count, q,
-                       ws64 + (size_t)grid64a * ws_stride, ws_stride, tol, maxit, out64, ticks,
+                       ws64 + (size_t)grid64a * ws_stride, ws_stride, tol, maxit, polish, out64, ticks,
                        nullptr);
     LSQ_LAUNCH_CHECK();
   }

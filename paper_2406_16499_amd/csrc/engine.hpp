@@ -183,7 +183,7 @@ struct StopStatus {
   int nonfinite;
 };
 // Norm accumulation slots used by the residual kernels.
-constexpr int kNormSlots = 8;
+constexpr int kNormSlots = 12;
 
 void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
                   int ldb, const double* b, const double* d, const double* x, const double* r,
@@ -203,6 +203,17 @@ void dev_copy(Ctx& ctx, void* dst, const void* src, size_t bytes);
 void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double* B, int ldb,
                 int br, int bc, const double* v1, int n1, const double* v2, int n2,
                 double* matnorms);
+
+// ------------------------------------------------------- complex data ----
+// Real embedding of complex data (interleaved (re, im) pairs, column-major,
+// ld in complex elements): E (2 rows x 2 cols, ld 2 rows) = [Re M, -Im M;
+// Im M, Re M]; vectors as [Re u; Im u].  unembed_vec writes the interleaved
+// vector back (nothing for a null u).
+void embed_mat(Ctx& ctx, const double* M, int ld, int rows, int cols, double* E);
+void embed_vec(Ctx& ctx, const double* u, int n, double* e);
+void unembed_vec(Ctx& ctx, const double* e, int n, double* u);
+// v[0:n] *= s (n <= 64)
+void scale_first(Ctx& ctx, double* v, int n, double s);
 
 // ------------------------------------------------------- FP64 Krylov ----
 // out[i] = c0 x0[i] + c1 sum_q p1[q][i] + c2 sum_q p2[q][i] (null terms skipped),
@@ -269,7 +280,7 @@ double batch_factor_flops(const BatchProb& P);
 // launch, for the kernel timer.  fast_exit: a higher-precision rung follows,
 // so an instance whose refinement contracts too slowly stops early.
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
-                  int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit,
+                  int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit, double polish,
                   bool fast_exit, BatchOut* out, double flops);
 
 // Escalation queues of the concurrent FP32 -> FP64 batch: the FP32 launch
@@ -295,7 +306,7 @@ size_t esc_queue_bytes(int count);
 // EscQueue.  ctx.stream waits for all three launches.
 void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
-                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit,
+                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish,
                              BatchOut* out, BatchOut* out64, double flops, double spin_ms,
                              int* started, int big_count);
 

@@ -276,8 +276,51 @@ struct PartsView {
   }
 };
 
-// LSE: f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v, plus partial sums of
-// squares of f1, f2, f3, x, r, v into normp[block][6].
+// Scaled sums of squares of six per-thread values over a work-group of 256:
+// for each slot k, the work-group's largest magnitude 2^e (frexp exponent e)
+// and the sum of (value 2^-e)^2 go to out[k] and out[6 + k].  The squares of
+// the scaled values lie in [0, 1), so no sum overflows or underflows for any
+// finite input; the stop test combines the blocks' (sum, e) pairs.
+__device__ __forceinline__ void scaled_sumsq6(const double val[6], double* __restrict__ out) {
+  __shared__ double red[4][6];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    a[k] = fabs(val[k]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a[k] = fmax(a[k], __shfl_xor(a[k], o, 64));
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[w][k] = a[k];
+  __syncthreads();
+  int e[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double mx = fmax(fmax(red[0][k], red[1][k]), fmax(red[2][k], red[3][k]));
+    e[k] = 0;
+    if (mx > 0.0 && isfinite(mx)) frexp(mx, &e[k]);   // inf / NaN stay inf / NaN below
+    const double t = ldexp(val[k], -e[k]);
+    a[k] = t * t;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) a[k] += __shfl_xor(a[k], o, 64);
+  }
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[w][k] = a[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      out[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+      out[6 + k] = (double)e[k];
+    }
+}
+
+// LSE: f1 = b - r - A x, f2 = d - B x, f3 = -A^T r + B^T v, plus the scaled
+// sums of squares of f1, f2, f3, x, r, v into normp[block][12].
 __global__ __launch_bounds__(256) void k_lse_finish(int m, int n, int p, const double* __restrict__ b,
                                                     const double* __restrict__ d,
                                                     const double* __restrict__ x,
@@ -287,35 +330,31 @@ __global__ __launch_bounds__(256) void k_lse_finish(int m, int n, int p, const d
                                                     double* __restrict__ f1, double* __restrict__ f2,
                                                     double* __restrict__ f3,
                                                     double* __restrict__ normp) {
-  __shared__ double red[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double s[6] = {0, 0, 0, 0, 0, 0};
   if (i < m) {
     const double val = b[i] - r[i] - Ax.sum(i);
     f1[i] = val;
-    s[0] = val * val;
-    s[4] = r[i] * r[i];
+    s[0] = val;
+    s[4] = r[i];
   }
   if (i < p) {
     const double val = d[i] - Bx.sum(i);
     f2[i] = val;
-    s[1] = val * val;
-    s[5] = v[i] * v[i];
+    s[1] = val;
+    s[5] = v[i];
   }
   if (i < n) {
     const double val = -Atr.sum(i) + Btv.sum(i);
     f3[i] = val;
-    s[2] = val * val;
-    s[3] = x[i] * x[i];
+    s[2] = val;
+    s[3] = x[i];
   }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const double tot = block_sum(s[k], red);
-    if (threadIdx.x == 0) normp[(size_t)blockIdx.x * kNormSlots + k] = tot;
-  }
+  scaled_sumsq6(s, normp + (size_t)blockIdx.x * kNormSlots);
 }
 
-// GLS: f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z; squares of f1, f2, f3, x, y, z.
+// GLS: f1 = -y + V^T z, f2 = d - W x - V y, f3 = W^T z; scaled sums of squares
+// of f1, f2, f3, x, y, z.
 __global__ __launch_bounds__(256) void k_gls_finish(int n, int m, int p, const double* __restrict__ d,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ y,
@@ -324,35 +363,31 @@ __global__ __launch_bounds__(256) void k_gls_finish(int n, int m, int p, const d
                                                     double* __restrict__ f1, double* __restrict__ f2,
                                                     double* __restrict__ f3,
                                                     double* __restrict__ normp) {
-  __shared__ double red[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double s[6] = {0, 0, 0, 0, 0, 0};
   if (i < p) {
     const double val = -y[i] + Vtz.sum(i);
     f1[i] = val;
-    s[0] = val * val;
-    s[4] = y[i] * y[i];
+    s[0] = val;
+    s[4] = y[i];
   }
   if (i < n) {
     const double val = d[i] - Wx.sum(i) - Vy.sum(i);
     f2[i] = val;
-    s[1] = val * val;
-    s[5] = z[i] * z[i];
+    s[1] = val;
+    s[5] = z[i];
   }
   if (i < m) {
     const double val = Wtz.sum(i);
     f3[i] = val;
-    s[2] = val * val;
-    s[3] = x[i] * x[i];
+    s[2] = val;
+    s[3] = x[i];
   }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const double tot = block_sum(s[k], red);
-    if (threadIdx.x == 0) normp[(size_t)blockIdx.x * kNormSlots + k] = tot;
-  }
+  scaled_sumsq6(s, normp + (size_t)blockIdx.x * kNormSlots);
 }
 
-// Stop test.  norms: [||f1||^2, ||f2||^2, ||f3||^2, ||x||^2, ||a1||^2, ||a2||^2]
+// Stop test.  normp: per block the scaled sums of squares and exponents of
+// [f1, f2, f3, x, a1, a2] (k_lse_finish / k_gls_finish).
 // matnorms: [||A||_F, ||B||_F, ||rhs1||, ||rhs2||].
 // LSE (gls = 0): scale1 = ||b|| + ||r|| + ||A|| ||x||, scale2 = ||d|| + ||B|| ||x||,
 //                scale3 = ||A|| ||r|| + ||B|| ||v||              (a1 = r, a2 = v)
@@ -363,15 +398,28 @@ __global__ void k_stop(const double* __restrict__ normp, int nblk, const double*
   __shared__ double red[4];
   __shared__ double nrm[6];
   for (int k = 0; k < 6; ++k) {
+    // common exponent E = the largest block exponent among nonzero blocks,
+    // then the sum of the blocks' scaled sums brought to 2^E
+    // (exponents offset by 4096 so that they are positive; 0 = no nonzero block)
+    double ev = 0.0;
+    for (int q = threadIdx.x; q < nblk; q += blockDim.x)
+      if (normp[(size_t)q * kNormSlots + k] > 0.0)
+        ev = fmax(ev, normp[(size_t)q * kNormSlots + 6 + k] + 4096.0);
+    ev = block_max(ev, red);
+    const int E = ev > 0.0 ? (int)ev - 4096 : 0;
     double s = 0.0;
-    for (int q = threadIdx.x; q < nblk; q += blockDim.x) s += normp[(size_t)q * kNormSlots + k];
+    for (int q = threadIdx.x; q < nblk; q += blockDim.x) {
+      const double part = normp[(size_t)q * kNormSlots + k];
+      if (part > 0.0) s += ldexp(part, 2 * ((int)normp[(size_t)q * kNormSlots + 6 + k] - E));
+      else if (part != 0.0) s += part;   // NaN: the norm becomes NaN
+    }
     s = block_sum(s, red);
-    if (threadIdx.x == 0) nrm[k] = s;
+    if (threadIdx.x == 0) nrm[k] = ldexp(sqrt(s), E);
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double nf1 = sqrt(nrm[0]), nf2 = sqrt(nrm[1]), nf3 = sqrt(nrm[2]);
-  const double nx = sqrt(nrm[3]), na1 = sqrt(nrm[4]), na2 = sqrt(nrm[5]);
+  const double nf1 = nrm[0], nf2 = nrm[1], nf3 = nrm[2];
+  const double nx = nrm[3], na1 = nrm[4], na2 = nrm[5];
   const double nA = matnorms[0], nB = matnorms[1], nr1 = matnorms[2], nr2 = matnorms[3];
   double sc[3];
   if (!gls) {
@@ -406,6 +454,9 @@ void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const
                   int ldb, const double* b, const double* d, const double* x, const double* r,
                   const double* v, double* f1, double* f2, double* f3, const double* matnorms,
                   double tol, StopStatus* st) {
+  // the partial sums live only until the finish kernel below has read them:
+  // the memory goes back to the workspace (stream order keeps it safe)
+  const Arena::Mark mk = ctx.ws->mark();
   DualParts pa, pb;
   dual_gemv(ctx, A, lda, m, n, x, r, pa);
   dual_gemv(ctx, B, ldb, p, n, x, v, pb);
@@ -418,12 +469,16 @@ void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const
                      Atr, Bx, Btv, f1, f2, f3, normp);
   hipLaunchKernelGGL(k_stop, dim3(1), dim3(256), 0, ctx.stream, normp, nblk, matnorms, 0, tol, st);
   LSQ_LAUNCH_CHECK();
+  ctx.ws->rewind(mk);
 }
 
 void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
                   int ldv, const double* d, const double* x, const double* y, const double* z,
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
                   StopStatus* st) {
+  // the partial sums live only until the finish kernel below has read them:
+  // the memory goes back to the workspace (stream order keeps it safe)
+  const Arena::Mark mk = ctx.ws->mark();
   DualParts pw, pv;
   dual_gemv(ctx, W, ldw, n, m, x, z, pw);
   dual_gemv(ctx, V, ldv, n, p, y, z, pv);
@@ -436,6 +491,7 @@ void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const
                      Wtz, Vy, Vtz, f1, f2, f3, normp);
   hipLaunchKernelGGL(k_stop, dim3(1), dim3(256), 0, ctx.stream, normp, nblk, matnorms, 1, tol, st);
   LSQ_LAUNCH_CHECK();
+  ctx.ws->rewind(mk);
 }
 
 // --------------------------------------------------------------- norms ----
@@ -536,6 +592,66 @@ void frob_norms(Ctx& ctx, const double* A, int lda, int ar, int ac, const double
                        part + (size_t)4 * k * per, per);
   }
   hipLaunchKernelGGL(k_norms_final, dim3(1), dim3(256), 0, ctx.stream, part, per, matnorms);
+  LSQ_LAUNCH_CHECK();
+}
+
+// --------------------------------------------------------- complex data --
+// Real embedding of a complex column-major matrix M (rows x cols, interleaved
+// (re, im) pairs, ld in complex elements): E = [Re M, -Im M; Im M, Re M]
+// (2 rows x 2 cols, ld 2 rows).  M u = w over C is E [Re u; Im u] = [Re w; Im w],
+// and E^T is the embedding of M^H.  One thread per complex element, rows fastest.
+__global__ __launch_bounds__(256) void k_embed_mat(const double2* __restrict__ M, int ld, int rows,
+                                                   int cols, double* __restrict__ E) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)rows * cols) return;
+  const int i = (int)(e % rows), j = (int)(e / rows);
+  const double2 z = M[(size_t)i + (size_t)j * ld];
+  const size_t le = 2 * (size_t)rows;
+  E[(size_t)i + (size_t)j * le] = z.x;
+  E[(size_t)i + (size_t)(cols + j) * le] = -z.y;
+  E[(size_t)(rows + i) + (size_t)j * le] = z.y;
+  E[(size_t)(rows + i) + (size_t)(cols + j) * le] = z.x;
+}
+// [Re u; Im u] (2n) from an interleaved complex vector u (n), and back.
+__global__ void k_embed_vec(const double2* __restrict__ u, int n, double* __restrict__ e) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double2 z = u[i];
+  e[i] = z.x;
+  e[n + i] = z.y;
+}
+__global__ void k_unembed_vec(const double* __restrict__ e, int n, double2* __restrict__ u) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  u[i] = make_double2(e[i], e[n + i]);
+}
+__global__ void k_scale_first(double* __restrict__ v, int n, double s) {
+  const int i = threadIdx.x;
+  if (i < n) v[i] *= s;
+}
+
+void embed_mat(Ctx& ctx, const double* M, int ld, int rows, int cols, double* E) {
+  const long long tot = (long long)rows * cols;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_embed_mat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, ctx.stream,
+                     reinterpret_cast<const double2*>(M), ld, rows, cols, E);
+  LSQ_LAUNCH_CHECK();
+}
+void embed_vec(Ctx& ctx, const double* u, int n, double* e) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_embed_vec, dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream,
+                     reinterpret_cast<const double2*>(u), n, e);
+  LSQ_LAUNCH_CHECK();
+}
+void unembed_vec(Ctx& ctx, const double* e, int n, double* u) {
+  if (n <= 0 || !u) return;
+  hipLaunchKernelGGL(k_unembed_vec, dim3(ceil_div(n, 256)), dim3(256), 0, ctx.stream, e, n,
+                     reinterpret_cast<double2*>(u));
+  LSQ_LAUNCH_CHECK();
+}
+void scale_first(Ctx& ctx, double* v, int n, double s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale_first, dim3(1), dim3(64), 0, ctx.stream, v, n, s);
   LSQ_LAUNCH_CHECK();
 }
 

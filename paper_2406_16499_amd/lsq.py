@@ -32,7 +32,8 @@ c_int, c_double, c_void_p, c_float = ctypes.c_int, ctypes.c_double, ctypes.c_voi
 class Opts(ctypes.Structure):
     _fields_ = [("prec", c_int), ("solver", c_int), ("tol", c_double), ("maxit", c_int),
                 ("gmres_restart", c_int), ("gmres_tol", c_double), ("gmres_maxit", c_int),
-                ("escalate", c_int), ("alpha", c_double), ("beta", c_double), ("nb", c_int)]
+                ("escalate", c_int), ("alpha", c_double), ("beta", c_double), ("nb", c_int),
+                ("polish", c_double)]
 
 
 class Result(ctypes.Structure):
@@ -66,6 +67,10 @@ _SIGS = {
                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
     "gls_solve": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P, _P,
                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
+    "zlse_solve": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P, _P, _P,
+                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
+    "zgls_solve": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P, _P,
+                           ctypes.POINTER(Opts), ctypes.POINTER(Result)]),
     "lse_factor": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, c_int,
                            ctypes.POINTER(c_void_p)]),
     "gls_factor": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, c_int,
@@ -175,6 +180,26 @@ def colmajor(a, device="cuda"):
     return t
 
 
+def colmajor_c(a, device="cuda"):
+    """complex128 device tensor with column-major storage holding `a` (the
+    interleaved (re, im) layout the complex entry points take)."""
+    torch = _torch()
+    a = np.asarray(a, dtype=np.complex128)
+    if a.ndim == 1:
+        t = torch.empty(a.shape[0], dtype=torch.complex128, device=device)
+        t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+        return t
+    r, c = a.shape
+    t = torch.empty_strided((r, c), (1, max(r, 1)), dtype=torch.complex128, device=device)
+    t.copy_(torch.from_numpy(np.asfortranarray(a)))
+    return t
+
+
+def empty_c(n, device="cuda"):
+    torch = _torch()
+    return torch.zeros(max(int(n), 0), dtype=torch.complex128, device=device)
+
+
 def empty(n, device="cuda"):
     torch = _torch()
     return torch.zeros(max(int(n), 0), dtype=torch.float64, device=device)
@@ -186,6 +211,14 @@ def _ptr(t):
     torch = _torch()
     assert t.dtype == torch.float64, "liblsq takes float64 tensors"
     return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else ctypes.c_void_p(t.data_ptr() or 8)
+
+
+def _cptr(t):
+    if t is None:
+        return None
+    torch = _torch()
+    assert t.dtype == torch.complex128, "the complex entry points take complex128 tensors"
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() > 0 else ctypes.c_void_p(t.data_ptr() or 16)
 
 
 def _ld(t):
@@ -315,6 +348,26 @@ class Handle:
         rc = self.lib.gls_solve(self.h, n, m, p, _ptr(W), _ld(W), _ptr(V), _ld(V), _ptr(d),
                                 _ptr(x), _ptr(y), _ptr(z),
                                 ctypes.byref(opts) if opts is not None else None, ctypes.byref(res))
+        return rc, res
+
+    def zlse_solve(self, A, B, b, d, x, r=None, v=None, opts: Optional[Opts] = None):
+        """Complex LSE (complex128 column-major tensors)."""
+        m, n = A.shape
+        p = B.shape[0]
+        res = Result()
+        rc = self.lib.zlse_solve(self.h, m, n, p, _cptr(A), _ld(A), _cptr(B), _ld(B) if p else 1,
+                                 _cptr(b), _cptr(d), _cptr(x), _cptr(r), _cptr(v),
+                                 ctypes.byref(opts) if opts is not None else None, ctypes.byref(res))
+        return rc, res
+
+    def zgls_solve(self, W, V, d, x, y, z=None, opts: Optional[Opts] = None):
+        """Complex GLS (complex128 column-major tensors)."""
+        n, m = W.shape
+        p = V.shape[1]
+        res = Result()
+        rc = self.lib.zgls_solve(self.h, n, m, p, _cptr(W), _ld(W), _cptr(V), _ld(V), _cptr(d),
+                                 _cptr(x), _cptr(y), _cptr(z),
+                                 ctypes.byref(opts) if opts is not None else None, ctypes.byref(res))
         return rc, res
 
     def lse_factor(self, A, B, prec: str = "fp32") -> "Factors":

@@ -214,6 +214,29 @@ int lse_solve_factored(lsq_handle handle, lsq_factors factors,
 int gls_solve_factored(lsq_handle handle, lsq_factors factors,
                        const double* d, double* x, double* y, double* z,
                        const lsq_opts* opts, lsq_result* res);
+/*
+ * Allocation-free variant of lse_solve_factored, for callers that cannot
+ * allocate device memory during the call (tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, return codes and results as
+ * lse_solve_factored with classical refinement (or, on FP64 factors, the
+ * FP64 direct solve); the call itself allocates nothing: its per-call
+ * workspace (ingest partial sums, iterates, residual blocks and the
+ * residual's partial sums) lives in a static device array of 64 MiB, one per
+ * GPU, held until the process ends.  Limits and errors:
+ *   - -8 for opts->solver GMRES_IR (or invalid options);
+ *   - -2 when the factors have not been prepared for classical refinement
+ *     (solve once with lse_solve_factored and solver IR or AUTO first), and
+ *     when the per-call workspace, about 8 (m n / 64 + m n / 256 + 3 (m + n
+ *     + p)) bytes, exceeds the 64 MiB;
+ *   - 4 if the handle's device has no scratch address (lsq_create sets it up).
+ * Every call on one GPU uses that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (two handles, two host threads, or
+ * two streams) race and must be serialized by the caller.
+ */
+int lse_solve_factored_noalloc(lsq_handle handle, lsq_factors factors,
+                               const double* b, const double* d,
+                               double* x, double* r, double* v,
+                               const lsq_opts* opts, lsq_result* res);
 /* Frees the factors' device memory (NULL is a no-op).  Call it before
  * lsq_destroy of the handle that made them, with no solve in flight. */
 int lsq_factors_destroy(lsq_factors factors);

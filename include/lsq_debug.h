@@ -115,6 +115,14 @@ int lsq_dbg_batch_wait(lsq_handle h, double ms);
    and bytes held.  Returns -1 for NULL. */
 int lsq_dbg_factors_bytes(lsq_factors factors, long long* in_use, long long* capacity);
 
+/* Workspace of lse_solve_factored_noalloc: *need (nullable) receives the
+   bytes one call on these factors takes from the static scratch array, *cap
+   (nullable) the bytes the entry point accepts.  lsq_dbg_noalloc_cap lowers
+   that cap to `bytes` (0 < bytes <= 64 MiB; 0 restores 64 MiB) so that the
+   size check can be exercised on small problems; -1 outside that range. */
+int lsq_dbg_noalloc_bytes(lsq_factors factors, long long* need, long long* cap);
+int lsq_dbg_noalloc_cap(long long bytes);
+
 /* Text of the last error recorded on the handle ("" if none). */
 const char* lsq_last_error(lsq_handle h);
 

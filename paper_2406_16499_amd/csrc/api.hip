@@ -20,6 +20,7 @@
 #include <atomic>
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstdio>
@@ -41,6 +42,7 @@ static_assert(kSelFeatures == LSQ_SELECTOR_FEATURES, "selector feature count");
 namespace lsq {
 Arena::~Arena() { release(); }
 void* Arena::alloc(size_t bytes) {
+  if (frozen_) throw std::runtime_error("an allocation was requested where none is allowed");
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
   while (cur_ < chunks_.size()) {
@@ -48,16 +50,29 @@ void* Arena::alloc(size_t bytes) {
     if (c.used + bytes <= c.size) {
       void* p = c.base + c.used;
       c.used += bytes;
+      high_ = std::max(high_, in_use());
       return p;
     }
+    if (fixed_) break;
     ++cur_;
   }
+  if (fixed_)
+    throw std::runtime_error("the workspace needs more than the " +
+                             std::to_string(chunks_.empty() ? 0 : chunks_[0].size) +
+                             " bytes of the fixed scratch buffer");
   size_t sz = bytes > (size_t(256) << 20) ? bytes : (size_t(256) << 20);
   void* base = nullptr;
   LSQ_HIP(hipMalloc(&base, sz));
-  chunks_.push_back(Chunk{static_cast<char*>(base), sz, bytes});
+  chunks_.push_back(Chunk{static_cast<char*>(base), sz, bytes, true});
   cur_ = chunks_.size() - 1;
+  high_ = std::max(high_, in_use());
   return base;
+}
+void Arena::adopt_fixed(void* base, size_t bytes) {
+  release();
+  chunks_.push_back(Chunk{static_cast<char*>(base), bytes, 0, false});
+  cur_ = 0;
+  fixed_ = true;
 }
 void Arena::reset() {
   for (auto& c : chunks_) c.used = 0;
@@ -85,9 +100,12 @@ size_t Arena::in_use() const {
   return t;
 }
 void Arena::release() {
-  for (auto& c : chunks_) (void)hipFree(c.base);
+  for (auto& c : chunks_)
+    if (c.owned) (void)hipFree(c.base);
   chunks_.clear();
   cur_ = 0;
+  fixed_ = false;
+  high_ = 0;
 }
 
 hipEvent_t ctx_event(Ctx& ctx, int i) {
@@ -121,6 +139,35 @@ void ktimer_end(Ctx& ctx, int kind) {
   ++t->used;
 }
 }  // namespace lsq
+
+// Workspace of the allocation-free factored solve: one array per GPU (each
+// device that loads the library holds its own copy until the process ends).
+// Host code never passes the array's name to a kernel; it uses the device
+// address looked up once per device by scratch_setup().
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: looks up the device address of that device's
+// scratch array (once per device) and keeps it.
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) throw std::runtime_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  LSQ_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) throw std::runtime_error("no device address for the scratch array");
+  g_scratch_ptr[device] = ptr;
+}
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
 
 // Everything one solve in flight needs: a stream, a workspace arena, the
 // device stop-test status with its pinned host mirror, and events.  The
@@ -1327,8 +1374,12 @@ int lsq_create(lsq_handle* out, int device) {
     LSQ_HIP(hipGetDeviceProperties(&prop, device));
     h->num_cu = prop.multiProcessorCount;
     h->w.init(device, h->num_cu, false);
+    scratch_setup(device);
     LSQ_HIP(hipDeviceSynchronize());
   } catch (const HipError&) {
+    lsq_destroy(h);
+    return 4;
+  } catch (const std::exception&) {
     lsq_destroy(h);
     return 4;
   }
@@ -2087,6 +2138,30 @@ static int lse_factored_run(Worker* w, lsq_factors f, const double* b, const dou
   return info;
 }
 
+// Bytes of the per-call workspace of a classical-IR solve on stored LSE
+// factors: the ingest scan's partial sums, the iterates and best iterate, the
+// residual blocks, one residual evaluation's partial sums (returned to the
+// workspace after each evaluation) and the pivot check of an FP64 solve that
+// did not certify.  Each piece is rounded up to the
+// workspace's 256-byte granularity.
+static size_t lse_factored_ws_bytes(int m, int n, int p) {
+  auto piece = [](size_t elems) { const size_t b = 8 * (elems > 0 ? elems : 1); return (b + 255) & ~size_t(255); };
+  auto cd = [](long long a, long long q) { return (a + q - 1) / q; };
+  size_t t = piece(16 * 512);                                  // ingest
+  t += 2 * (piece(n) + piece(m) + piece(p));                   // iterate, best iterate
+  t += piece(m) + piece(p) + piece(n);                         // f1, f2, f3
+  t += piece((size_t)cd(n, 64) * m) + piece((size_t)cd(m, 256) * n);   // A's partial sums
+  t += piece((size_t)cd(n, 64) * p) + piece((size_t)cd(p, 256) * n);   // B's partial sums
+  const int len = std::max(std::max(m, n), p);
+  t += piece((size_t)cd(len, 256) * kNormSlots);               // norm partials
+  t += 2 * piece(2);                                           // pivot check of FP64 triangles
+  return t;
+}
+
+// Cap of the allocation-free workspace in bytes (<= kScratchBytes; lowered
+// only by the inspection entry point that tests the size check).
+static size_t g_noalloc_cap = kScratchBytes;
+
 extern "C" {
 
 int lse_solve_factored(lsq_handle h, lsq_factors f, const double* b, const double* d, double* x,
@@ -2098,6 +2173,42 @@ int lse_solve_factored(lsq_handle h, lsq_factors f, const double* b, const doubl
   return guard(h, "lse_solve_factored", [&]() -> int {
     return lse_factored_run(&h->w, f, b, d, x, r, v, o, solvers, res);
   });
+}
+
+int lse_solve_factored_noalloc(lsq_handle h, lsq_factors f, const double* b, const double* d,
+                               double* x, double* r, double* v, const lsq_opts* opts,
+                               lsq_result* res) {
+  if (!h) return -1;
+  lsq_opts o;
+  std::vector<int> solvers;
+  if (const int bad = lse_factored_check(h, f, b, d, x, opts, o, solvers)) return bad;
+  if (solvers.size() != 1 || solvers[0] == LSQ_SOLVER_GMRES_IR)
+    return fail(h, -8, "the allocation-free solve runs classical IR (or the FP64 direct solve) only");
+  const int tc = f->prec == LSQ_PREC_FP64 ? 8 : f->lse.ps.tc;
+  if (f->lse.prepared_tc != tc)
+    return fail(h, -2, "the factors are not prepared for classical refinement: "
+                       "solve once with lse_solve_factored (solver IR) first");
+  const size_t need = lse_factored_ws_bytes(f->m, f->n, f->p);
+  if (need > g_noalloc_cap)
+    return fail(h, -2, "the factors need " + std::to_string(need) +
+                           " bytes of workspace per solve, more than the " +
+                           std::to_string(g_noalloc_cap) + " bytes of the static scratch buffer");
+  void* ptr = scratch_ptr(h->w.device);
+  if (!ptr) return fail(h, 4, "no scratch buffer was set up on this device");
+  Worker* w = &h->w;
+  Arena fixed;
+  fixed.adopt_fixed(ptr, g_noalloc_cap);
+  Arena* prev = w->ctx.ws;
+  w->ctx.ws = &fixed;
+  w->arena.set_frozen(true);
+  f->arena.set_frozen(true);
+  const int rc = guard(h, "lse_solve_factored_noalloc", [&]() -> int {
+    return lse_factored_run(w, f, b, d, x, r, v, o, solvers, res);
+  });
+  w->ctx.ws = prev;
+  w->arena.set_frozen(false);
+  f->arena.set_frozen(false);
+  return rc;
 }
 
 int gls_solve_factored(lsq_handle h, lsq_factors f, const double* d, double* x, double* y,
@@ -2160,6 +2271,19 @@ int lsq_dbg_factors_bytes(lsq_factors f, long long* in_use, long long* capacity)
   if (!f) return -1;
   if (in_use) *in_use = (long long)f->arena.in_use();
   if (capacity) *capacity = (long long)f->arena.capacity();
+  return 0;
+}
+
+int lsq_dbg_noalloc_bytes(lsq_factors f, long long* need, long long* cap) {
+  if (!f || f->type != LSQ_LSE) return -1;
+  if (need) *need = (long long)lse_factored_ws_bytes(f->m, f->n, f->p);
+  if (cap) *cap = (long long)g_noalloc_cap;
+  return 0;
+}
+
+int lsq_dbg_noalloc_cap(long long bytes) {
+  if (bytes < 0 || bytes > (long long)kScratchBytes) return -1;
+  g_noalloc_cap = bytes == 0 ? kScratchBytes : (size_t)bytes;
   return 0;
 }
 

@@ -27,10 +27,20 @@ class Arena {
   void rewind(const Mark& m);
   size_t capacity() const;   // bytes held in chunks
   size_t in_use() const;     // bytes handed out since the last reset / rewind
+  // Fixed mode: the arena hands out memory from [base, base + bytes) only,
+  // which it does not own (release() leaves it alone), and an allocation that
+  // does not fit throws instead of allocating a new chunk.
+  void adopt_fixed(void* base, size_t bytes);
+  // Frozen: every allocation throws (a caller that must not allocate).
+  void set_frozen(bool f) { frozen_ = f; }
+  bool frozen() const { return frozen_; }
+  size_t high_water() const { return high_; }   // largest in_use() seen
  private:
-  struct Chunk { char* base; size_t size; size_t used; };
+  struct Chunk { char* base; size_t size; size_t used; bool owned; };
   std::vector<Chunk> chunks_;
   size_t cur_ = 0;
+  bool fixed_ = false, frozen_ = false;
+  size_t high_ = 0;
 };
 
 // Optional timing of one kernel kind: HIP events on the context stream around

@@ -79,6 +79,8 @@ _SIGS = {
                                    ctypes.POINTER(Result)]),
     "gls_solve_factored": (c_int, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts),
                                    ctypes.POINTER(Result)]),
+    "lse_solve_factored_noalloc": (c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Opts),
+                                           ctypes.POINTER(Result)]),
     "lsq_factors_destroy": (c_int, [_P]),
     "lsq_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                   ctypes.POINTER(Result)]),
@@ -112,6 +114,9 @@ _SIGS = {
     "lsq_dbg_batch_wait": (c_int, [_P, ctypes.c_double]),
     "lsq_dbg_factors_bytes": (c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong)]),
+    "lsq_dbg_noalloc_bytes": (c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
+                                      ctypes.POINTER(ctypes.c_longlong)]),
+    "lsq_dbg_noalloc_cap": (c_int, [ctypes.c_longlong]),
     "lsq_last_error": (ctypes.c_char_p, [_P]),
 }
 
@@ -252,6 +257,24 @@ class Factors:
             rc = lib.gls_solve_factored(self.handle.h, self.f, _ptr(d), _ptr(x), _ptr(y), _ptr(z),
                                         o, ctypes.byref(res))
         return rc, res
+
+    def solve_noalloc(self, b, d, x, r=None, v=None, opts: Optional[Opts] = None):
+        """lse_solve_factored_noalloc (LSE factors only)."""
+        if self.kind != "lse":
+            raise ValueError("the allocation-free solve takes LSE factors")
+        lib, res = self.handle.lib, Result()
+        o = ctypes.byref(opts) if opts is not None else None
+        rc = lib.lse_solve_factored_noalloc(self.handle.h, self.f, _ptr(b), _ptr(d), _ptr(x),
+                                            _ptr(r), _ptr(v), o, ctypes.byref(res))
+        return rc, res
+
+    def noalloc_bytes(self):
+        """(bytes one allocation-free solve needs, bytes it accepts)."""
+        need, cap = ctypes.c_longlong(), ctypes.c_longlong()
+        rc = self.handle.lib.lsq_dbg_noalloc_bytes(self.f, ctypes.byref(need), ctypes.byref(cap))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_noalloc_bytes = {rc}")
+        return need.value, cap.value
 
     def bytes(self):
         """(bytes in use, bytes held) of the factors' device memory."""

@@ -1,17 +1,21 @@
-"""Benchmark: LSE solves/s at FP64 backward error <= 1e-14, mixed-precision
+"""Benchmark: LSE/GLS solves/s at FP64 backward error <= 1e-14, mixed-precision
 refinement vs the all-FP64 GPU path, on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp32] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload NAME]
 
-Workload: single large LSE, A 4096 x 2048 = U diag(s) V^T (Haar U, V; s
-log-spaced 1 .. 1e-4, kappa(A) = 1e4), B 256 x 2048 i.i.d. N(0,1), b, d
-i.i.d. N(0,1) (seed 2), synthetic and resident in HBM before timing starts.
-A step is one complete solve through the C-ABI: down-conversion, generalized
-RQ factorization at u_f, initial guess, and refinement until the stopping
-test (eq. lse-stop, tol = 1e-14) holds; a solve that does not certify
-berr <= 1e-14 is not counted.
+Default line (--workload headline): the batched workload, 2000 LSE/GLS
+instances of uneven size (seed 4), solved per step by the persistent batched
+path with FP32 factors and classical refinement (instances that do not
+certify continue in FP64), against the all-FP64 persistent path on the same
+instances; a solve counts only if it certifies berr <= 1e-14.  The line
+carries two sub-records, each mixed precision against the FP64 direct path:
+the single large LSE (A 4096 x 2048, kappa 1e4, B 256 x 2048; FP32 and BF16
+factorizations with classical IR) and the single large GLS (W 4096 x 1024,
+V 4096 x 4096 with kappa 1e6; FP16 factorization with GMRES-IR and the
+escalation ladder).  Inputs are synthetic and resident in HBM before timing
+starts.  The other workloads (--workload) print a line of their own.
 
-Prints one JSON line (rank 0 only; the solver runs on one GPU).
+Prints one JSON line (the solver runs on one GPU).
 """
 from __future__ import annotations
 
@@ -33,17 +37,21 @@ PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0}   # dense M
 HBM_PEAK = 8000.0                                                     # GB/s
 PEAK_FP32_VECTOR = 157.3                                              # TFLOP/s
 COPY_BYTES = 256 << 20            # calibration copy for the hardware byte counters
-# Kernel whose roofline is reported, with its bound: the Householder panel
-# reconstruction dominates the mixed-precision solve (FP64 arithmetic).
+# Kernels whose roofline can be reported, with their bound.  The panel kernel
+# counts the Householder flops of its panel (2 mr jb^2 - 2 jb^3 / 3) against
+# the FP64 peak (its arithmetic is FP64 whatever the storage precision); the
+# GEMV kernels count one read of their matrix against the HBM peak.
 KERNELS = {
     "panel_final_y": ("k_panel_final_y", "mfma", 78.6, "TFLOP/s"),
     "panel_cholpass": ("k_panel_cholpass", "mfma", 78.6, "TFLOP/s"),
     "wy_u": ("k_wy_u", "mfma", None, "TFLOP/s"),
     "wy_t": ("k_wy_t", "mfma", None, "TFLOP/s"),
     "dual_gemv": ("k_dual_gemv", "hbm", HBM_PEAK, "GB/s"),
+    "agg_gemv": ("k_gemv_t / k_gemv_n (aggregated reflector blocks)", "hbm", HBM_PEAK, "GB/s"),
 }
 KERNEL_SOURCES = ["paper_2406_16499_amd/csrc/qr.hip", "paper_2406_16499_amd/csrc/wg64.hpp",
-                  "paper_2406_16499_amd/csrc/vec.hip", "paper_2406_16499_amd/csrc/common.hpp",
+                  "paper_2406_16499_amd/csrc/vec.hip", "paper_2406_16499_amd/csrc/blas.hip",
+                  "paper_2406_16499_amd/csrc/gemv.hpp", "paper_2406_16499_amd/csrc/common.hpp",
                   "paper_2406_16499_amd/csrc/engine.hpp"]
 
 
@@ -59,15 +67,18 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel", default="panel_final_y", choices=sorted(KERNELS))
-    ap.add_argument("--workload", default="lse-large",
-                    choices=["lse-large", "gls-large", "lse-wide", "gls-tall", "paper-grid", "lse-factored",
-                             "batched"],
-                    help="lse-large: the single 4096x2048x256 LSE (default); gls-large: the "
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "lse-large", "gls-large", "lse-wide", "gls-tall", "paper-grid",
+                             "lse-factored", "batched"],
+                    help="headline (default): the batched workload with the large LSE and GLS as "
+                         "sub-records; lse-large: the single 4096x2048x256 LSE; gls-large: the "
                          "4096x1024x4096 GLS with GMRES-IR; lse-wide: LSE 2048x4096x2560 (n > m) "
                          "with GMRES-IR; gls-tall: GLS 4096x2560x2048 (n > p) with GMRES-IR; "
                          "paper-grid: the paper's experiment shapes against the GPU FP64 path; "
                          "lse-factored: the default LSE factored once, solves with new right-hand sides; "
                          "batched: the 2000-instance mixed LSE/GLS workload")
+    ap.add_argument("--grid", default="E1,E2,E3", help="paper-grid: experiments to run")
+    ap.add_argument("--grid-n", default="", help="paper-grid: only these n (comma-separated)")
     ap.add_argument("--count", type=int, default=2000, help="instances of the batched workload")
     ap.add_argument("--workers", type=int, default=8, help="batch workers (streams)")
     ap.add_argument("--no-workers", action="store_true",
@@ -296,7 +307,7 @@ def batched(args):
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_batch(probs, args.cpu_seconds)
-    print(json.dumps(line))
+    return line
 
 
 GLS_WORKLOAD = ("single GLS d = Wx + Vy: W 4096x1024 N(0,1), V 4096x4096 = U diag(s) V^T "
@@ -356,7 +367,8 @@ def single_gmres(args):
     dt, ok, last = run(lsq.default_opts(prec=prec, solver="gmres", escalate=1))
     dt64, ok64, last64 = run(lsq.default_opts(prec="fp64", solver="direct"))
     value, value64 = ok / dt, ok64 / dt64
-    print(json.dumps({
+    h.close()
+    return ({
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1000.0 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
@@ -367,89 +379,123 @@ def single_gmres(args):
         "fp64_direct": {"value": value64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / args.steps,
                         "last_result": last64},
         "speedup_vs_fp64": value / value64 if value64 > 0 else None,
-        "certified_solves": ok, "last_result": last}))
+        "certified_solves": ok, "last_result": last})
 
 
-PAPER_GRID_WORKLOAD = ("the paper's experiment shapes (Section 6): LSE m > n >> p (n 1024, (m, p) = "
-                       "(8n, n/32), (12n, n/64)) and m >> n > p (n 128, (m, p) = (128n, n/8)); GLS "
-                       "(n 1024, (p, m) = (8n, n/32), (12n, n/64)); [A^T, B^T] resp. [W, V] = "
-                       "U diag(s) V^T with log-spaced s, kappa 1e3..1e9; RHS N(0,1); seed 11")
+PAPER_GRID_WORKLOAD = ("the paper's experiment grid (Section 6): E1 LSE m > n >> p, n in {1024, 2048, 3072}, "
+                       "(m, p) in {8n, 10n, 12n} x {n/32, n/64}, kappa([A^T, B^T]) in {1e3, 1e5, 1e7, 1e9}; "
+                       "E2 LSE m >> n > p, n in {128, 192, 256}, (m, p) in {128n, 256n} x {n/8, n/4, n/2}, "
+                       "kappa 1e5; E3 GLS, n in {1024, 2048, 3072}, (p, m) in {8n, 10n, 12n} x "
+                       "{n/32, n/64}, kappa([W, V]) in {1e3, 1e5, 1e7, 1e9}; [A^T, B^T] resp. [W, V] = "
+                       "U diag(s) V^T with Haar U, V and log-spaced s; RHS N(0,1); seed 11")
+
+
+def grid_cases(exps, ns):
+    """Groups (n, big, small, [(exp, kind, kappas), ...]) of the paper's grid:
+    E1's (m, p) = (big, small) and E3's (p, m) = (big, small) share the shape
+    of the stacked matrix, so one pair of orthogonal bases serves both and
+    every kappa."""
+    groups = []
+    if "E1" in exps or "E3" in exps:
+        for n in [x for x in (1024, 2048, 3072) if not ns or x in ns]:
+            for fm in (8, 10, 12):
+                for fp in (32, 64):
+                    runs = [(e, "lse" if e == "E1" else "gls", (1e3, 1e5, 1e7, 1e9))
+                            for e in ("E1", "E3") if e in exps]
+                    groups.append((n, fm * n, n // fp, runs))
+    if "E2" in exps:
+        for n in [x for x in (128, 192, 256) if not ns or x in ns]:
+            for fm in (128, 256):
+                for fp in (8, 4, 2):
+                    groups.append((n, fm * n, n // fp, [("E2", "lse", (1e5,))]))
+    return groups
 
 
 def paper_grid(args):
-    """The paper's experiment shapes on the GPU: for every case, the FP32
-    factorization with classical IR and with GMRES-IR (escalation on), and the
-    FP64 direct path; times, refinement steps, backward errors and the
-    distance of the mixed solution from the FP64 one (the relative-time and
-    error columns of Tables 4 and 5, against the GPU FP64 path)."""
+    """The paper's experiment grid on the GPU: for every case, the FP32
+    factorization with classical IR and with GMRES-IR (escalation on) against
+    the FP64 direct path, with the time, refinement steps, backward error and
+    the err-1 / err-2 measures of Tables 4 (LSE) and 5 (GLS), err-2 taken
+    against the FP64 direct solution."""
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl
     h = lsq.Handle(load_selector=False)
+    exps = [e for e in args.grid.split(",") if e]
+    ns = [int(x) for x in args.grid_n.split(",") if x] if args.grid_n else []
     rng = np.random.default_rng(11)
-    cases = []
-    for kappa in (1e3, 1e5, 1e7, 1e9):
-        for (fm, fp) in ((8, 32), (12, 64)):
-            cases.append(("E1", "lse", 1024, fm, fp, kappa))
-    cases.append(("E2", "lse", 128, 128, 8, 1e5))
-    for kappa in (1e3, 1e5, 1e7, 1e9):
-        for (fm, fp) in ((8, 32), (12, 64)):
-            cases.append(("E3", "gls", 1024, fm, fp, kappa))
+    nrm = np.linalg.norm
     rows = []
     t_mixed = t_fp64 = 0.0
     ok_mixed = ok_fp64 = 0
-    for (exp, kind, n, fm, fp, kappa) in cases:
-        if kind == "lse":
-            m, p = fm * n, n // fp
-            P = wl.lse_paper_pair(rng, m, n, p, kappa)
-            A, B, b, d = (lsq.colmajor(a) for a in (P.A, P.B, P.b, P.d))
-            x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
-            solve = lambda o: h.lse_solve(A, B, b, d, x, r, v, o)
-            sol = lambda: x.detach().cpu().numpy().copy()
-            shape = {"m": m, "n": n, "p": p}
-        else:
-            p_, m_ = fm * n, n // fp
-            G = wl.gls_paper_pair(rng, n, m_, p_, kappa)
-            W, V, d = (lsq.colmajor(a) for a in (G.W, G.V, G.d))
-            x, y, z = lsq.empty(m_), lsq.empty(p_), lsq.empty(n)
-            solve = lambda o: h.gls_solve(W, V, d, x, y, z, o)
-            sol = lambda: np.concatenate([x.detach().cpu().numpy(), y.detach().cpu().numpy()])
-            shape = {"n": n, "m": m_, "p": p_}
-        out = {"exp": exp, "kind": kind, **shape, "kappa": kappa}
-        ref = None
-        for name, opts in (("fp64", lsq.default_opts(prec="fp64", solver="direct")),
-                           ("ir", lsq.default_opts(prec="fp32", solver="ir", escalate=1)),
-                           ("gmres", lsq.default_opts(prec="fp32", solver="gmres", escalate=1))):
-            for _ in range(args.warmup):
-                solve(opts)
+    for (n, big, small, runs) in grid_cases(exps, ns):
+        N = big + small
+        U, Vb = wl.paper_bases(rng, n, N)
+        for (exp, kind, kappa) in [(e, k, kp) for (e, k, kps) in runs for kp in kps]:
+            if kind == "lse":
+                m, p = big, small
+                P = wl.lse_paper_from_bases(rng, U, Vb, m, p, kappa)
+                A, B, b, d = (lsq.colmajor(a) for a in (P.A, P.B, P.b, P.d))
+                x, r, v = lsq.empty(n), lsq.empty(m), lsq.empty(p)
+                solve = lambda o: h.lse_solve(A, B, b, d, x, r, v, o)
+                sol = lambda: x.detach().cpu().numpy().copy()
+                fro_b = nrm(P.B)
+                err1 = lambda xs: float(nrm(P.B @ xs - P.d) / (fro_b * nrm(xs) + nrm(P.d)))
+                res_ref = {}
+                def err2(xs, xr):
+                    if "r" not in res_ref:
+                        res_ref["r"] = nrm(P.A @ xr - P.b)
+                    return float(abs(nrm(P.A @ xs - P.b) / res_ref["r"] - 1.0))
+                shape = {"m": m, "n": n, "p": p}
+            else:
+                p, m = big, small
+                G = wl.gls_paper_from_bases(rng, U, Vb, m, p, kappa)
+                W, V, d = (lsq.colmajor(a) for a in (G.W, G.V, G.d))
+                x, y, z = lsq.empty(m), lsq.empty(p), lsq.empty(n)
+                solve = lambda o: h.gls_solve(W, V, d, x, y, z, o)
+                sol = lambda: (x.detach().cpu().numpy().copy(), y.detach().cpu().numpy().copy())
+                fw, fv = nrm(G.W), nrm(G.V)
+                err1 = lambda s_: float(nrm(G.W @ s_[0] + G.V @ s_[1] - G.d)
+                                        / (fw * nrm(s_[0]) + fv * nrm(s_[1]) + nrm(G.d)))
+                err2 = lambda s_, sr: float(abs(nrm(s_[1]) / nrm(sr[1]) - 1.0))
+                shape = {"n": n, "m": m, "p": p}
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ok = 0
-            for _ in range(args.steps):
-                rc, res = solve(opts)
-                ok += int(rc == 0 and res.berr_max <= 1e-14)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / args.steps
-            dd = res.as_dict()
-            xs = sol()
-            if name == "fp64":
-                ref = xs
-            den = float(np.max(np.abs(ref))) if ref is not None and ref.size else 0.0
-            dist = float(np.max(np.abs(xs - ref)) / den) if den > 0 else 0.0
-            out[name] = {"ms": 1000.0 * dt, "certified": ok, "steps": args.steps,
-                         "rung": f"{dd['prec_used']}/{dd['solver_used']}", "attempts": dd["attempts"],
-                         "ir_steps": dd["ir_steps"], "gmres_iters": dd["gmres_iters"],
-                         "berr": dd["berr_max"], "dist_to_fp64": dist}
-        t_fp64 += out["fp64"]["ms"]
-        ok_fp64 += out["fp64"]["certified"]
-        best = min((out["ir"], out["gmres"]), key=lambda e: e["ms"])
-        t_mixed += best["ms"]
-        ok_mixed += best["certified"]
-        out["time_ratio_best_mixed_vs_fp64"] = best["ms"] / out["fp64"]["ms"]
-        rows.append(out)
-        print(f"[grid] {exp} {kind} {shape} kappa={kappa:g} fp64 {out['fp64']['ms']:.1f} ms, "
-              f"ir {out['ir']['ms']:.1f} ms ({out['ir']['rung']}), gmres {out['gmres']['ms']:.1f} ms "
-              f"({out['gmres']['rung']})", file=sys.stderr, flush=True)
+            out = {"exp": exp, "kind": kind, **shape, "kappa": kappa}
+            ref = None
+            for name, opts in (("fp64", lsq.default_opts(prec="fp64", solver="direct")),
+                               ("ir", lsq.default_opts(prec="fp32", solver="ir", escalate=1)),
+                               ("gmres", lsq.default_opts(prec="fp32", solver="gmres", escalate=1))):
+                for _ in range(args.warmup):
+                    solve(opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ok = 0
+                for _ in range(args.steps):
+                    rc, res = solve(opts)
+                    ok += int(rc == 0 and res.berr_max <= 1e-14)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / args.steps
+                dd = res.as_dict()
+                xs = sol()
+                if name == "fp64":
+                    ref = xs
+                out[name] = {"ms": 1000.0 * dt, "certified": ok, "steps": args.steps,
+                             "rung": f"{dd['prec_used']}/{dd['solver_used']}", "attempts": dd["attempts"],
+                             "ir_steps": dd["ir_steps"], "gmres_iters": dd["gmres_iters"],
+                             "berr": dd["berr_max"], "err1": err1(xs), "err2": err2(xs, ref)}
+            t_fp64 += out["fp64"]["ms"]
+            ok_fp64 += out["fp64"]["certified"]
+            best = min((out["ir"], out["gmres"]), key=lambda e: e["ms"])
+            t_mixed += best["ms"]
+            ok_mixed += best["certified"]
+            out["time_ratio_best_mixed_vs_fp64"] = best["ms"] / out["fp64"]["ms"]
+            rows.append(out)
+            print(f"[grid] {exp} {kind} {shape} kappa={kappa:g} fp64 {out['fp64']['ms']:.1f} ms, "
+                  f"ir {out['ir']['ms']:.1f} ms ({out['ir']['rung']}, {out['ir']['ir_steps']} steps, "
+                  f"err1 {out['ir']['err1']:.1e} err2 {out['ir']['err2']:.1e}), gmres {out['gmres']['ms']:.1f} ms "
+                  f"({out['gmres']['rung']}, {out['gmres']['gmres_iters']} it)", file=sys.stderr, flush=True)
+            del solve, sol
+        del U, Vb
     ncase = len(rows)
     value = 1000.0 * ncase / t_mixed if t_mixed > 0 else 0.0
     print(json.dumps({
@@ -457,7 +503,8 @@ def paper_grid(args):
         "warmup": args.warmup, "ms_per_step": t_mixed, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 (residuals, updates) / fp32 (factorization)",
         "data": "synthetic",
-        "config": {"workload": PAPER_GRID_WORKLOAD, "cases": ncase,
+        "config": {"workload": PAPER_GRID_WORKLOAD, "experiments": exps, "n": ns or "all",
+                   "cases": ncase,
                    "solver": "per case the faster of classical IR and GMRES-IR (FP32 factors, escalation on)",
                    "tol": 1e-14},
         "fp64_direct": {"value": 1000.0 * ncase / t_fp64 if t_fp64 > 0 else 0.0, "unit": "solves/s",
@@ -516,21 +563,25 @@ def lse_factored(args):
         "certified_solves": ok, "last_result": last}))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
-              "(a multi-GPU run would shard the batched instances across GPUs)",
-              file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "batched":
-        return batched(args)
-    if args.workload in ("gls-large", "lse-wide", "gls-tall"):
-        return single_gmres(args)
-    if args.workload == "paper-grid":
-        return paper_grid(args)
-    if args.workload == "lse-factored":
-        return lse_factored(args)
+def roofline_of(timing, kernel, steps, files=None):
+    """Roofline object of one timed kernel kind: achieved = algorithmic work per
+    launch / average event-timed launch duration."""
+    if timing is None or timing[1] <= 0:
+        return None
+    total_ms, launches, flops, nbytes = timing
+    name, bound, peak, unit = KERNELS[kernel]
+    avg_s = total_ms * 1e-3 / launches
+    achieved = (nbytes / launches / avg_s / 1e9) if bound == "hbm" else (flops / launches / avg_s / 1e12)
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": traffic_per_launch(kernel, files), "kernel": name,
+            "launches_per_step": launches / steps, "avg_launch_us": avg_s * 1e6,
+            "alg_flops_per_launch": flops / launches, "alg_bytes_per_launch": nbytes / launches,
+            "source_hash": source_hash(files)}
+
+
+def lse_large(args, cpu=True):
+    """The single large LSE: FP32 (and BF16) factorization with classical IR and
+    the escalation ladder against the FP64 direct path."""
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl
@@ -539,58 +590,41 @@ def main():
     tensors = tuple(lsq.colmajor(a) for a in (prob.A, prob.B, prob.b, prob.d))
     torch.cuda.synchronize()
     h = lsq.Handle()
-
-    mixed_opts = lsq.default_opts(prec=args.prec, solver="ir", escalate=1)
+    precs = [args.prec] + (["bf16"] if args.prec == "fp32" else [])
+    mixed = {}
+    for prec in precs:
+        o = lsq.default_opts(prec=prec, solver="ir", escalate=1)
+        mixed[prec] = time_solves(h, lsq, torch, tensors, o, args.steps, args.warmup,
+                                  kernel=args.kernel if prec == args.prec else None)
     fp64_opts = lsq.default_opts(prec="fp64", solver="direct")
-    dt_mix, ok_mix, res_mix, timing = time_solves(h, lsq, torch, tensors, mixed_opts, args.steps,
-                                                  args.warmup, kernel=args.kernel)
     dt_64, ok_64, res_64, _ = time_solves(h, lsq, torch, tensors, fp64_opts, args.steps, args.warmup)
+    # the HBM-bound refinement kernels, timed on extra mixed solves (outside
+    # the solves/s figures): the FP64 residual sweep and the reflector GEMVs
+    o32 = lsq.default_opts(prec=args.prec, solver="ir", escalate=1)
+    hbm = {}
+    for k in ("dual_gemv", "agg_gemv"):
+        _, _, _, tk = time_solves(h, lsq, torch, tensors, o32, 2, 0, kernel=k)
+        hbm[k] = roofline_of(tk, k, 2)
     # calibration copy of known size, outside the timed regions (scales the
     # FETCH_SIZE / WRITE_SIZE counters of a profiled run)
     src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     h.dbg_copy(dst, src, COPY_BYTES)
     del src, dst
+    h.close()
 
+    dt_mix, ok_mix, res_mix, timing = mixed[args.prec]
     value = ok_mix / dt_mix
     value64 = ok_64 / dt_64
     m, n, p = args.m, args.n, args.p
     # algorithmic work of one generalized RQ (Section 3.1 flop model, leading terms):
     # RQ of B 2np^2 - 2p^3/3, A Q^T 4mnp - 2mp^2, QR of A Q^T 2mn^2 - 2n^3/3
     tf = (2 * n * p * p - 2 * p ** 3 / 3) + (4 * m * n * p - 2 * m * p * p) + (2 * m * n * n - 2 * n ** 3 / 3)
-
-    roof = None
-    if timing is not None and timing[1] > 0:
-        total_ms, launches, flops, nbytes = timing
-        name, bound, peak, unit = KERNELS[args.kernel]
-        if peak is None:
-            peak = PEAK.get(args.prec, PEAK["fp32"])
-        avg_s = total_ms * 1e-3 / launches
-        if bound == "hbm":
-            achieved = nbytes / launches / avg_s / 1e9
-        else:
-            achieved = flops / launches / avg_s / 1e12
-        traffic = traffic_per_launch(args.kernel)
-        roof = {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": traffic,
-                "kernel": name, "launches_per_step": launches / args.steps,
-                "avg_launch_us": avg_s * 1e6,
-                "alg_flops_per_launch": flops / launches, "alg_bytes_per_launch": nbytes / launches,
-                "source_hash": source_hash()}
-
     line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1000.0 * dt_mix / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64 (residuals, updates) / " + args.prec + " (factorization)",
-        "data": "synthetic",
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * dt_mix / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (residuals, updates) / " + args.prec + " (factorization)", "data": "synthetic",
         "config": {"workload": WORKLOAD, "m": m, "n": n, "p": p, "factorization": args.prec,
                    "solver": "classical IR with escalation ladder", "tol": 1e-14},
         "fp64_direct": {"value": value64, "unit": "solves/s", "ms_per_step": 1000.0 * dt_64 / args.steps,
@@ -600,10 +634,58 @@ def main():
         "last_result": res_mix[-1] if res_mix else None,
         "last_result_fp64": res_64[-1] if res_64 else None,
         "factor_flops": tf,
-        "roofline": roof,
+        "factor_tflops": {"mixed": tf / (res_mix[-1]["ms_factor"] * 1e-3) / 1e12 if res_mix else None,
+                          "fp64": tf / (res_64[-1]["ms_factor"] * 1e-3) / 1e12 if res_64 else None},
+        "roofline": roofline_of(timing, args.kernel, args.steps),
+        "hbm_kernels": hbm,
     }
-    if not args.no_cpu:
+    for prec in precs[1:]:
+        dt, ok, res, _ = mixed[prec]
+        line[f"mixed_{prec}"] = {"value": ok / dt, "unit": "solves/s", "ms_per_step": 1000.0 * dt / args.steps,
+                                 "speedup_vs_fp64": (ok / dt) / value64 if value64 > 0 else None,
+                                 "certified": ok, "last_result": res[-1] if res else None}
+    if cpu and not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU run would shard the batched instances across GPUs)",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "batched":
+        print(json.dumps(batched(args)))
+        return
+    if args.workload in ("gls-large", "lse-wide", "gls-tall"):
+        print(json.dumps(single_gmres(args)))
+        return
+    if args.workload == "paper-grid":
+        return paper_grid(args)
+    if args.workload == "lse-factored":
+        return lse_factored(args)
+    if args.workload == "lse-large":
+        print(json.dumps(lse_large(args)))
+        return
+    # headline: the batched workload, with the large LSE and GLS as sub-records
+    line = batched(args)
+    print("[bench] batched done", file=sys.stderr, flush=True)
+    sub_lse = lse_large(args, cpu=False)
+    print("[bench] large LSE done", file=sys.stderr, flush=True)
+    gls_args = argparse.Namespace(**vars(args))
+    gls_args.workload, gls_args.prec = "gls-large", "fp16"
+    gls_args.steps, gls_args.warmup = min(args.steps, 3), min(args.warmup, 1)
+    sub_gls = single_gmres(gls_args)
+    print("[bench] large GLS done", file=sys.stderr, flush=True)
+    keep = ("value", "unit", "ms_per_step", "steps", "config", "fp64_direct", "speedup_vs_fp64",
+            "certified_solves", "last_result", "last_result_fp64", "factor_flops", "factor_tflops",
+            "roofline", "hbm_kernels", "mixed_bf16")
+    line["sub_records"] = {
+        "lse_large": {k: sub_lse[k] for k in keep if k in sub_lse},
+        "gls_large": {k: sub_gls[k] for k in keep if k in sub_gls},
+    }
     print(json.dumps(line))
 
 

@@ -98,6 +98,12 @@ typedef struct {
                        /* backward error is above polish, toward the limiting       */
                        /* accuracy (forward error ~ cond u); default 8 * 2^-53;     */
                        /* <= 0 stops at once, as Algorithms 2 and 4 do              */
+  int residual;        /* 0: FP64 residual (u_r = u, default); 1: double-double     */
+                       /* residual (u_r = u^2, Table 2's extra-precise rows): the   */
+                       /* refinement then goes on after the stop test passes while  */
+                       /* the corrections change x (GLS: x and y) by more than 2u   */
+                       /* relative and keep at least halving, so the forward error  */
+                       /* reaches O(u) independently of the condition number        */
 } lsq_opts;
 
 typedef struct {
@@ -226,8 +232,8 @@ int gls_solve_factored(lsq_handle handle, lsq_factors factors,
  *   - -8 for opts->solver GMRES_IR (or invalid options);
  *   - -2 when the factors have not been prepared for classical refinement
  *     (solve once with lse_solve_factored and solver IR or AUTO first), and
- *     when the per-call workspace, about 8 (m n / 64 + m n / 256 + 3 (m + n
- *     + p)) bytes, exceeds the 64 MiB;
+ *     when the per-call workspace, about 16 (m n / 64 + m n / 256) + 32 (m +
+ *     n + p) bytes, exceeds the 64 MiB;
  *   - 4 if the handle's device has no scratch address (lsq_create sets it up).
  * Every call on one GPU uses that GPU's array, which keeps the last call's
  * contents: calls that overlap on one GPU (two handles, two host threads, or

@@ -46,6 +46,10 @@ int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* A, int
                          const double* y, const double* z, double* f1, double* f2, double* f3,
                          double* out);
 
+/* on != 0: the two residual inspection entry points above evaluate the
+ * residual in double-double (the opts->residual = 1 path), else in FP64. */
+int lsq_dbg_residual_dd(lsq_handle h, int on);
+
 /* Generalized RQ factorization of (B, A) at precision prec, then one call of
  * the LSE correction solver (Algorithm 1) on (f1, f2, f3): outputs dr (m),
  * dv (p), dx (n) with [[I,0,A],[0,0,B],[A^T,B^T,0]] [dr; -dv; dx] = f. */
@@ -85,7 +89,8 @@ int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p
 /* Kernel timing.  While enabled, HIP events are recorded on the handle's
  * stream around every launch of the named kernel kind ("panel_final_y",
  * "panel_cholpass", "wy_t", "wy_u", "dual_gemv", and "batch_fp32" /
- * "batch_fp64" for the persistent batched solver), and the launch's
+ * "batch_fp64" for the persistent batched solver, "agg_gemv" for the two
+ * reflector-block GEMVs of each block of an aggregated application of Q), and the launch's
  * algorithmic flops and bytes are added up (the step each kernel carries out
  * is the one cited at its launch site: Householder QR panels and updates of
  * Section 4.1, the residual of eq. aug-LSE / eq. aug-GLS; for a batch launch
@@ -122,6 +127,11 @@ int lsq_dbg_factors_bytes(lsq_factors factors, long long* in_use, long long* cap
    size check can be exercised on small problems; -1 outside that range. */
 int lsq_dbg_noalloc_bytes(lsq_factors factors, long long* need, long long* cap);
 int lsq_dbg_noalloc_cap(long long bytes);
+
+/* Look-ahead of the blocked QR on the handle's factorizations: 0 off (the
+   default), 1 the trailing updates after the next panel's columns on the
+   side stream, overlapping the next panel.  -2 outside 0..1. */
+int lsq_dbg_lookahead(lsq_handle h, int mode);
 
 /* Text of the last error recorded on the handle ("" if none). */
 const char* lsq_last_error(lsq_handle h);

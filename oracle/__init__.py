@@ -21,5 +21,8 @@ complex_lsq
          The complex problems of Section 1 (Hermitian transposes): null-space
          and Paige solutions over C, augmented residuals, stop-test scales,
          backward errors and condition numbers, with no real embedding.
+extended The residual blocks computed exactly (rational arithmetic) and rounded
+         once, and solutions of the augmented systems in mpmath: references
+         for the extra-precise (double-double) residual.
 """
-from . import complex_lsq, direct, mpir  # noqa: F401
+from . import complex_lsq, direct, extended, mpir  # noqa: F401

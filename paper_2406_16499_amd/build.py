@@ -65,5 +65,45 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+SANITIZERS = {"address": "asan", "thread": "tsan"}
+
+
+def build_sanitized(kind: str = "address", verbose: bool = False) -> str:
+    """The library's sources and the host driver csrc/sanitize_driver.cpp built
+    into one executable with a host-code sanitizer (AddressSanitizer or
+    ThreadSanitizer): every -fsanitize flag applies to the host compilation
+    only (-Xarch_host); the device code is built as for liblsq.so.  Returns the
+    executable's path (lsq_<asan|tsan>_driver beside liblsq.so)."""
+    tag = SANITIZERS[kind]
+    out_dir = os.path.join(BUILD_DIR, tag)
+    os.makedirs(out_dir, exist_ok=True)
+    host = ["-Xarch_host", f"-fsanitize={kind}", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+    flags = [f if f != "-O3" else "-O1" for f in COMMON] + host
+
+    def comp(src):
+        obj = os.path.join(out_dir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        extra = ["-x", "hip"] if src.endswith(".cpp") else []
+        r = subprocess.run([hipcc(), *flags, *extra, "-c", src, "-o", obj], stdout=subprocess.PIPE,
+                           stderr=subprocess.STDOUT, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compiling {src} ({kind}) failed:\n{r.stdout}")
+        return obj
+
+    srcs = [os.path.join(CSRC, f) for f in SOURCES] + [os.path.join(CSRC, "sanitize_driver.cpp")]
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = list(ex.map(comp, srcs))
+    exe = os.path.join(HERE, f"lsq_{tag}_driver")
+    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", *host, "-o", exe, *objs],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"linking the {kind} driver failed:\n" + r.stdout)
+    if verbose:
+        print("built", exe)
+    return exe
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if len(sys.argv) > 2 and sys.argv[1] == "sanitize":
+        build_sanitized(sys.argv[2], verbose=True)
+    else:
+        build(verbose=True)

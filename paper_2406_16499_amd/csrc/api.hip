@@ -244,6 +244,7 @@ struct lsq_handle_st {
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
   std::string last_error;
+  bool dbg_dd = false;                          // residual inspection in double-double
 };
 
 namespace {
@@ -780,17 +781,33 @@ bool stalled(const std::vector<double>& hist) {
   return false;
 }
 
-// After an iterate passed the stop test: true to stop now; false (once) to
-// take one more correction first, while its backward error is above
-// o.polish.  The stop test certifies berr <= tol; first-order perturbation
-// theory bounds the forward error by about cond * berr, so an iterate
-// certified at berr near tol = 1e-14 may sit well above the limiting
-// accuracy cond * u that one more contraction reaches.
-bool polish_done(const lsq_opts& o, const StopStatus& st, int it, bool& polished) {
-  if (polished || !(o.polish > 0.0) || st.berr_max <= o.polish || it >= o.maxit) return true;
-  polished = true;
-  return false;
-}
+// After an iterate passed the stop test: whether to take one more
+// correction first.  The stop test certifies berr <= tol; first-order
+// perturbation theory bounds the forward error by about cond * berr, so an
+// iterate certified at berr near tol = 1e-14 may sit well above the limiting
+// accuracy.  With the FP64 residual one more correction (once, while berr >
+// o.polish) reaches the limiting accuracy cond * u.  With the double-double
+// residual the limiting accuracy no longer depends on cond, and refinement
+// goes on while the corrections still change the solution blocks by more
+// than 2u relative and keep at least halving (the classical stop rule on the
+// size of the correction; the FP64 iterate itself bounds the accuracy at u).
+void d2d(Worker* w, double* dst, const double* src, int n);
+
+struct Continuation {
+  const lsq_opts& o;
+  bool dd = false;
+  bool polished = false;
+  double last_dx = INFINITY, prev_dx = INFINITY;   // ||dx||_inf / ||x||_inf of the last two corrections
+  explicit Continuation(const lsq_opts& o_) : o(o_), dd(o_.residual == 1) {}
+  void observe_dx(double r) { prev_dx = last_dx; last_dx = r; }
+  bool more(const StopStatus& st, int it) {
+    if (it >= o.maxit) return false;
+    if (dd) return last_dx > 2.0 * 1.1102230246251565e-16 && (prev_dx == INFINITY || last_dx <= 0.5 * prev_dx);
+    if (polished || !(o.polish > 0.0) || st.berr_max <= o.polish) return false;
+    polished = true;
+    return true;
+  }
+};
 
 // Classical refinement (Algorithms 2 and 4): init() adds the initial guess to
 // the zeroed iterate, residual() evaluates the FP64 residual and the stop
@@ -798,13 +815,13 @@ bool polish_done(const lsq_opts& o, const StopStatus& st, int it, bool& polished
 RungOut run_classical(Worker* h, const std::function<void()>& zero,
                       const std::function<void()>& init, const std::function<void()>& residual,
                       const std::function<void()>& correct, const lsq_opts& o,
-                      const std::function<void(const StopStatus&, int, int)>& observe) {
+                      const std::function<void(const StopStatus&, int, int)>& observe,
+                      Continuation& cont) {
   RungOut out;
   zero();
   LSQ_HIP(hipEventRecord(h->ev[2], h->stream));
   init();
   std::vector<double> hist;
-  bool polished = false;
   for (int it = 0;; ++it) {
     residual();
     read_status(h);
@@ -816,7 +833,7 @@ RungOut run_classical(Worker* h, const std::function<void()>& zero,
     out.steps = it;
     if (st.converged) {
       out.ok = true;
-      if (polish_done(o, st, it, polished)) break;
+      if (!cont.more(st, it)) break;
     } else if (st.nonfinite || it >= o.maxit || stalled(hist)) {
       out.ok = false;
       break;
@@ -841,7 +858,8 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
                   const std::function<double()>& alpha0,
                   const std::function<void(double*)>& scaled_residual,
                   const std::function<void(const double*)>& update, const lsq_opts& o,
-                  const std::function<void(const StopStatus&, int, int)>& observe) {
+                  const std::function<void(const StopStatus&, int, int)>& observe,
+                  Continuation& cont) {
   Ctx& ctx = h->ctx;
   RungOut out;
   zero();
@@ -860,7 +878,6 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
     sv.m_left(ctx, sv.t2, y);
   };
   std::vector<double> hist;
-  bool polished = false;
   for (int it = 0;; ++it) {
     residual();
     read_status(h);
@@ -872,7 +889,7 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
     out.steps = it;
     if (stt.converged) {
       out.ok = true;
-      if (polish_done(o, stt, it, polished) || out.inner >= o.gmres_maxit) break;
+      if (!cont.more(stt, it) || out.inner >= o.gmres_maxit) break;
     } else if (stt.nonfinite || it >= o.maxit || out.inner >= o.gmres_maxit || stalled(hist)) {
       out.ok = false;
       break;
@@ -997,17 +1014,26 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
   double* f1 = ctx.ws->get<double>(a.m > 0 ? a.m : 1);
   double* f2 = ctx.ws->get<double>(a.p > 0 ? a.p : 1);
   double* f3 = ctx.ws->get<double>(a.n > 0 ? a.n : 1);
+  const bool dd = o.residual == 1;
   auto residual = [&]() {
     lse_residual(ctx, a.m, a.n, a.p, a.A, a.lda, a.B, a.ldb, a.b, a.d, x, r, v, f1, f2, f3,
-                 h->matnorms, o.tol, h->st_dev);
+                 h->matnorms, o.tol, h->st_dev, dd);
   };
   auto zero = [&]() { vec_zero(ctx, x, 8, a.n); vec_zero(ctx, r, 8, a.m); vec_zero(ctx, v, 8, a.p); };
   auto init = [&]() { sv.correct(ctx, a.b, a.d, nullptr, x, r, v); };
+  // double-double residual: the relative size of each correction of x
+  double* xold = dd ? ctx.ws->get<double>(a.n > 0 ? a.n : 1) : nullptr;
   for (int solver : solvers) {
     ++attempts;
     solver_used = solver;
+    Continuation cont(o);
     auto observe = [&](const StopStatus& st, int it, int inner) {
       if (best) best->observe(st, it, inner, prec, solver);
+    };
+    auto tracked = [&](const std::function<void()>& step) {
+      if (dd) d2d(h, xold, x, a.n);
+      step();
+      if (dd) cont.observe_dx(rel_change(ctx, xold, x, a.n));
     };
     if (solver == LSQ_SOLVER_GMRES_IR) {
       ensure_prepared(sv, ctx, 8, true);
@@ -1025,15 +1051,18 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
             vec_convert(ctx, st + m + p, 8, f3, 8, n, false, 1.0 / sv.sa);
           },
           [&](const double* du) {
-            vec_axpy(ctx, r, 8, sv.sa, du, 8, m, false);
-            vec_axpy(ctx, v, 8, -sv.sa * sv.beta, du + m, 8, p, false);
-            vec_axpy(ctx, x, 8, 1.0 / sv.sa, du + m + p, 8, n, false);
+            tracked([&]() {
+              vec_axpy(ctx, r, 8, sv.sa, du, 8, m, false);
+              vec_axpy(ctx, v, 8, -sv.sa * sv.beta, du + m, 8, p, false);
+              vec_axpy(ctx, x, 8, 1.0 / sv.sa, du + m + p, 8, n, false);
+            });
           },
-          o, observe);
+          o, observe, cont);
     } else {
       ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
-                          [&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }, o, observe);
+                          [&]() { tracked([&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }); }, o,
+                          observe, cont);
     }
     out.ms_factor = ms_factor;
     if (out.ok) break;
@@ -1062,17 +1091,27 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
   double* f1 = ctx.ws->get<double>(a.p > 0 ? a.p : 1);
   double* f2 = ctx.ws->get<double>(a.n > 0 ? a.n : 1);
   double* f3 = ctx.ws->get<double>(a.m > 0 ? a.m : 1);
+  const bool dd = o.residual == 1;
   auto residual = [&]() {
     gls_residual(ctx, a.n, a.m, a.p, a.W, a.ldw, a.V, a.ldv, a.d, x, y, z, f1, f2, f3,
-                 h->matnorms, o.tol, h->st_dev);
+                 h->matnorms, o.tol, h->st_dev, dd);
   };
   auto zero = [&]() { vec_zero(ctx, x, 8, a.m); vec_zero(ctx, y, 8, a.p); vec_zero(ctx, z, 8, a.n); };
   auto init = [&]() { sv.correct(ctx, nullptr, a.d, nullptr, x, y, z); };
+  // double-double residual: the relative size of each correction of x and y
+  double* xold = dd ? ctx.ws->get<double>(a.m > 0 ? a.m : 1) : nullptr;
+  double* yold = dd ? ctx.ws->get<double>(a.p > 0 ? a.p : 1) : nullptr;
   for (int solver : solvers) {
     ++attempts;
     solver_used = solver;
+    Continuation cont(o);
     auto observe = [&](const StopStatus& st, int it, int inner) {
       if (best) best->observe(st, it, inner, prec, solver);
+    };
+    auto tracked = [&](const std::function<void()>& step) {
+      if (dd) { d2d(h, xold, x, a.m); d2d(h, yold, y, a.p); }
+      step();
+      if (dd) cont.observe_dx(std::max(rel_change(ctx, xold, x, a.m), rel_change(ctx, yold, y, a.p)));
     };
     if (solver == LSQ_SOLVER_GMRES_IR) {
       ensure_prepared(sv, ctx, 8, true);
@@ -1090,15 +1129,18 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
             vec_convert(ctx, st + p + n, 8, f3, 8, m, false, sv.sa * sv.beta);
           },
           [&](const double* du) {
-            vec_axpy(ctx, y, 8, sv.sa, du, 8, p, false);
-            vec_axpy(ctx, z, 8, -1.0 / sv.sa, du + p, 8, n, false);
-            vec_axpy(ctx, x, 8, sv.sa * sv.beta, du + p + n, 8, m, false);
+            tracked([&]() {
+              vec_axpy(ctx, y, 8, sv.sa, du, 8, p, false);
+              vec_axpy(ctx, z, 8, -1.0 / sv.sa, du + p, 8, n, false);
+              vec_axpy(ctx, x, 8, sv.sa * sv.beta, du + p + n, 8, m, false);
+            });
           },
-          o, observe);
+          o, observe, cont);
     } else {
       ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
-                          [&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }, o, observe);
+                          [&]() { tracked([&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }); }, o,
+                          observe, cont);
     }
     out.ms_factor = ms_factor;
     if (out.ok) break;
@@ -1360,6 +1402,7 @@ void lsq_opts_default(lsq_opts* o) {
   o->beta = 0.0;
   o->nb = 0;
   o->polish = 8.0 * 1.1102230246251565e-16;
+  o->residual = 0;
 }
 
 int lsq_create(lsq_handle* out, int device) {
@@ -1419,6 +1462,13 @@ int lsq_set_batch_mode(lsq_handle h, int mode) {
   if (mode != LSQ_BATCH_AUTO && mode != LSQ_BATCH_WORKERS && mode != LSQ_BATCH_SEQUENTIAL)
     return fail(h, -2, "unknown batch mode");
   h->batch_mode = mode;
+  return 0;
+}
+
+int lsq_dbg_lookahead(lsq_handle h, int mode) {
+  if (!h) return -1;
+  if (mode < 0 || mode > 1) return fail(h, -2, "look-ahead mode outside 0..1");
+  h->w.ctx.lookahead = mode != 0;
   return 0;
 }
 
@@ -2141,8 +2191,9 @@ static int lse_factored_run(Worker* w, lsq_factors f, const double* b, const dou
 // Bytes of the per-call workspace of a classical-IR solve on stored LSE
 // factors: the ingest scan's partial sums, the iterates and best iterate, the
 // residual blocks, one residual evaluation's partial sums (returned to the
-// workspace after each evaluation) and the pivot check of an FP64 solve that
-// did not certify.  Each piece is rounded up to the
+// workspace after each evaluation; hi and lo parts with the double-double
+// residual), the previous x of the double-double mode and the pivot check of
+// an FP64 solve that did not certify.  Each piece is rounded up to the
 // workspace's 256-byte granularity.
 static size_t lse_factored_ws_bytes(int m, int n, int p) {
   auto piece = [](size_t elems) { const size_t b = 8 * (elems > 0 ? elems : 1); return (b + 255) & ~size_t(255); };
@@ -2150,8 +2201,10 @@ static size_t lse_factored_ws_bytes(int m, int n, int p) {
   size_t t = piece(16 * 512);                                  // ingest
   t += 2 * (piece(n) + piece(m) + piece(p));                   // iterate, best iterate
   t += piece(m) + piece(p) + piece(n);                         // f1, f2, f3
-  t += piece((size_t)cd(n, 64) * m) + piece((size_t)cd(m, 256) * n);   // A's partial sums
-  t += piece((size_t)cd(n, 64) * p) + piece((size_t)cd(p, 256) * n);   // B's partial sums
+  // A's and B's partial sums, twice over (hi and lo) for the double-double residual
+  t += 2 * (piece((size_t)cd(n, 64) * m) + piece((size_t)cd(m, 256) * n));
+  t += 2 * (piece((size_t)cd(n, 64) * p) + piece((size_t)cd(p, 256) * n));
+  t += piece(n);                                               // previous x (double-double mode)
   const int len = std::max(std::max(m, n), p);
   t += piece((size_t)cd(len, 256) * kNormSlots);               // norm partials
   t += 2 * piece(2);                                           // pivot check of FP64 triangles
@@ -2407,7 +2460,7 @@ int lsq_dbg_lse_residual(lsq_handle h, int m, int n, int p, const double* A, int
     Ctx& ctx = h->w.ctx;
     frob_norms(ctx, A, lda, m, n, B, ldb, p, n, b, m, d, p, h->w.matnorms);
     lse_residual(ctx, m, n, p, A, lda, B, ldb, b, d, x, r, v, f1, f2, f3, h->w.matnorms, 1e-14,
-                 h->w.st_dev);
+                 h->w.st_dev, h->dbg_dd);
     if (out) status_out(h, out);
     LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
@@ -2423,11 +2476,17 @@ int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* W, int
     Ctx& ctx = h->w.ctx;
     frob_norms(ctx, W, ldw, n, m, V, ldv, n, p, d, n, nullptr, 0, h->w.matnorms);
     gls_residual(ctx, n, m, p, W, ldw, V, ldv, d, x, y, z, f1, f2, f3, h->w.matnorms, 1e-14,
-                 h->w.st_dev);
+                 h->w.st_dev, h->dbg_dd);
     if (out) status_out(h, out);
     LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
+}
+
+int lsq_dbg_residual_dd(lsq_handle h, int on) {
+  if (!h) return -1;
+  h->dbg_dd = on != 0;
+  return 0;
 }
 
 int lsq_dbg_lse_correction(lsq_handle h, int prec, int m, int n, int p, const double* A, int lda,
@@ -2476,7 +2535,7 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
 
 // ------------------------------------------------------------- timing --
 static const char* const kKernelNames[kKCount] = {"panel_final_y", "panel_cholpass", "wy_t", "wy_u",
-                                                  "dual_gemv", "batch_fp32", "batch_fp64"};
+                                                  "dual_gemv", "batch_fp32", "batch_fp64", "agg_gemv"};
 
 int lsq_dbg_timer_enable(lsq_handle h, const char* kernel) {
   if (!h) return -1;

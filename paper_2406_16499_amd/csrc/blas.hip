@@ -426,12 +426,18 @@ static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
     TC* yy = y + b.J0;
     TC* s = acc + b.acc;                 // zero on entry
     TC* tv = s + b.w;                    // zero on entry
+    // one read of the block's reflectors (rows x w in S) per product
+    const double fl = 2.0 * rows * b.w, by = (double)rows * b.w * sizeof(S);
     // s = Y^T y (unit-lower Y)
+    ktimer_begin(ctx, kKAggGemv, fl, by);
     gemv_t<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)1, yy, s);
+    ktimer_end(ctx, kKAggGemv);
     // Q^T = I - Y T^T Y^T  -> t = T^T s ;  Q = I - Y T Y^T -> t = T s
     trmv_dense<TC>(ctx, static_cast<const TC*>(b.T), b.w, b.w, trans, s, tv);
     // y -= Y t
+    ktimer_begin(ctx, kKAggGemv, fl, by);
     gemv_n<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)-1, tv, yy);
+    ktimer_end(ctx, kKAggGemv);
     LSQ_LAUNCH_CHECK();
   }
   // every block's accumulators back to zero for the next application (a fill

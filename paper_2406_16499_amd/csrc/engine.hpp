@@ -47,7 +47,7 @@ class Arena {
 // each launch of that kind, with the launch's algorithmic flops and bytes.
 enum KernelKind : int {
   kKPanelFinal = 0, kKPanelCholPass = 1, kKWyT = 2, kKWyU = 3, kKDualGemv = 4, kKBatch32 = 5,
-  kKBatch64 = 6, kKCount = 7
+  kKBatch64 = 6, kKAggGemv = 7, kKCount = 8
 };
 struct KernelTimer {
   int target = -1;
@@ -67,9 +67,9 @@ struct Ctx {
   double* pin = nullptr;             // pinned host scratch (kPinDoubles)
   std::vector<hipEvent_t>* events = nullptr;   // pool of timing-free events
   // Look-ahead in the blocked QR (next panel's columns first, the rest on the
-  // side stream).  Off: on the 4096 x 2048 factorization the concurrent
-  // trailing updates slowed the latency-bound panel kernels more than the
-  // overlap saved (12.7 vs 12.4 ms per FP32 solve).
+  // side stream).  Off by default: the concurrent trailing updates take the
+  // compute units the latency-bound panel kernels need, and the overlap
+  // gains about 2% (6.27 vs 6.39 ms for the 4096 x 2048 FP32 factorization).
   bool lookahead = false;
 };
 // The i-th event of the context's pool (created on first use).
@@ -198,11 +198,12 @@ constexpr int kNormSlots = 12;
 void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
                   int ldb, const double* b, const double* d, const double* x, const double* r,
                   const double* v, double* f1, double* f2, double* f3, const double* matnorms,
-                  double tol, StopStatus* st);
+                  double tol, StopStatus* st, bool dd = false);
 void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
                   int ldv, const double* d, const double* x, const double* y, const double* z,
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
-                  StopStatus* st);
+                  StopStatus* st, bool dd = false);
+// dd: the residual in double-double (u_r = u^2) instead of FP64.
 // matnorms[0..1] = ||A||_F, ||B||_F; matnorms[2..3] = ||b||, ||d|| (LSE) or ||d||, 0 (GLS);
 // matnorms[4..7] = the largest magnitudes of the same four inputs, NaN for an
 // input that holds a non-finite value.  Norms are exact to rounding over the
@@ -232,6 +233,8 @@ void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c
              int np1, double c2, const double* p2, int np2);
 double dev_norm2(Ctx& ctx, const double* x, int n);                 // synchronizes
 double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn);   // synchronizes
+// max |cur - old| / max |cur| over n elements (synchronizes; inf for NaN)
+double rel_change(Ctx& ctx, const double* old, const double* cur, int n);
 
 struct GmresOut {
   int iters = 0;

@@ -154,6 +154,26 @@ __global__ __launch_bounds__(256) void k_diag_minmax(const Tw* __restrict__ M, i
   }
 }
 
+// out[2 b] = max |cur - old|, out[2 b + 1] = max |cur| over block b's stride.
+__global__ __launch_bounds__(256) void k_change_max(const double* __restrict__ old,
+                                                    const double* __restrict__ cur, int n,
+                                                    double* __restrict__ out) {
+  __shared__ double red[4];
+  double dm = 0.0, xm = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const double c = cur[i];
+    dm = fmax(dm, fabs(c - old[i]));
+    xm = fmax(xm, fabs(c));
+    if (c != c) dm = c;                      // NaN propagates
+  }
+  dm = block_max(dm, red);
+  xm = block_max(xm, red);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = dm;
+    out[2 * blockIdx.x + 1] = xm;
+  }
+}
+
 // ------------------------------------------------------------------ host --
 void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c1, const double* p1,
              int np1, double c2, const double* p2, int np2) {
@@ -175,6 +195,24 @@ double dev_norm2(Ctx& ctx, const double* x, int n) {
   double s = 0.0;
   for (int q = 0; q < g; ++q) s += ctx.pin[q];
   return std::sqrt(s);
+}
+
+double rel_change(Ctx& ctx, const double* old, const double* cur, int n) {
+  if (n <= 0) return 0.0;
+  int g = ceil_div(n, 256);
+  if (g > 64) g = 64;
+  double* part = ctx.ws->get<double>(128);
+  hipLaunchKernelGGL(k_change_max, dim3(g), dim3(256), 0, ctx.stream, old, cur, n, part);
+  LSQ_LAUNCH_CHECK();
+  LSQ_HIP(hipMemcpyAsync(ctx.pin, part, sizeof(double) * 2 * g, hipMemcpyDeviceToHost, ctx.stream));
+  LSQ_HIP(hipStreamSynchronize(ctx.stream));
+  double dm = 0.0, xm = 0.0;
+  for (int q = 0; q < g; ++q) {
+    if (!(ctx.pin[2 * q] <= dm)) dm = ctx.pin[2 * q];
+    xm = std::max(xm, ctx.pin[2 * q + 1]);
+  }
+  if (!(dm == dm)) return INFINITY;
+  return xm > 0.0 ? dm / xm : (dm > 0.0 ? INFINITY : 0.0);
 }
 
 double min_abs_diag(Ctx& ctx, const QRFactor& f, int o, int nn) {

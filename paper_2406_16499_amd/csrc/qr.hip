@@ -748,10 +748,11 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
       LSQ_HIP(hipStreamWaitEvent(ctx.stream, ctx_event(ctx, 2 * side_pending + 1), 0));
       side_pending = -1;
     }
-    // algorithmic work of the reconstruction: Cholesky, LU and the four
-    // triangular inverses / products of the 64 x 64 part (11 jb^3 / 3), Y = Q1 Mmat
-    // and Yhat = Y T^T (2 mr jb^2 each); bytes: Q1 in, Y and Yhat out
-    ktimer_begin(ctx, kKPanelFinal, 4.0 * mr * jb * jb + 11.0 * jb * jb * jb / 3.0,
+    // algorithmic work: the Householder factorization of the mr x jb panel
+    // (2 mr jb^2 - 2 jb^3 / 3 flops, Section 4.1's xGEQRF), which this kernel
+    // completes; the Cholesky-QR passes and the reconstruction are how it is
+    // computed, not extra work of the method.  Bytes: Q1 in, Y and Yhat out.
+    ktimer_begin(ctx, kKPanelFinal, 2.0 * mr * jb * jb - 2.0 * jb * jb * jb / 3.0,
                  (double)mr * jb * (8 + 2 * sizeof(Tw)));
     hipLaunchKernelGGL((k_panel_final_y<Tw, Acc>), dim3(tiles), dim3(kPT), 0, ctx.stream,
                        Glast, jb, mr, Qlast, mr, Racc, M, ld, j0, Tb + (size_t)j * 4096,

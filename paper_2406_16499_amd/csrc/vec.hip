@@ -266,6 +266,102 @@ void dual_gemv(Ctx& ctx, const double* M, int ld, int rows, int cols, const doub
   LSQ_LAUNCH_CHECK();
 }
 
+// ------------------------------------------ double-double residual sweep --
+// Extra-precise residual (u_r = u^2, Table 2's "quad" rows): every product
+// and sum of the residual is carried as an unevaluated pair hi + lo with
+// error-free transformations (Knuth's TwoSum, an FMA-based TwoProduct), and
+// the residual blocks are rounded to FP64 only at the end.  Two passes over
+// the matrix (M u, then M^T w); an optional mode, so plainness beats fusion.
+// The transformations are exact only if every product and sum is rounded on
+// its own: FP contraction (an FMA formed from a product and a later sum) is
+// off inside them.
+struct DD { double hi, lo; };
+__device__ __forceinline__ DD dd_two_sum(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ DD dd_quick(double a, double b) {
+#pragma clang fp contract(off)
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+#pragma clang fp contract(off)
+  const DD s = dd_two_sum(a.hi, b.hi);
+  return dd_quick(s.hi, s.lo + (a.lo + b.lo));
+}
+__device__ __forceinline__ DD dd_prod(double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+__device__ __forceinline__ DD dd_shfl_xor(DD a, int m) {
+  return {__shfl_xor(a.hi, m, 64), __shfl_xor(a.lo, m, 64)};
+}
+
+// rowp[cb][i] = sum over the 64 columns of block cb of M[i][j] u[j] (hi / lo arrays)
+__global__ __launch_bounds__(256) void k_gemv_n_dd(const double* __restrict__ M, int ld, int rows,
+                                                   int cols, const double* __restrict__ u,
+                                                   double* __restrict__ hi, double* __restrict__ lo) {
+  __shared__ double us[64];
+  const int t = threadIdx.x, r = blockIdx.x * 256 + t, c0 = blockIdx.y * 64;
+  if (t < 64) us[t] = (c0 + t < cols) ? u[c0 + t] : 0.0;
+  __syncthreads();
+  if (r >= rows) return;
+  DD acc = {0.0, 0.0};
+  const int ce = min(cols, c0 + 64);
+  for (int j = c0; j < ce; ++j) acc = dd_add(acc, dd_prod(M[(size_t)r + (size_t)j * ld], us[j - c0]));
+  hi[(size_t)blockIdx.y * rows + r] = acc.hi;
+  lo[(size_t)blockIdx.y * rows + r] = acc.lo;
+}
+
+// colp[rb][j] = sum over the 256 rows of block rb of M[i][j] w[i]: each wave
+// takes 16 columns, each lane four rows of a column, then a pairwise reduction.
+__global__ __launch_bounds__(256) void k_gemv_t_dd(const double* __restrict__ M, int ld, int rows,
+                                                   int cols, const double* __restrict__ w,
+                                                   double* __restrict__ hi, double* __restrict__ lo) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * 256, c0 = blockIdx.x * 64 + 16 * wv;
+  double wr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int i = r0 + lane + 64 * k;
+    wr[k] = i < rows ? w[i] : 0.0;
+  }
+  for (int c = 0; c < 16; ++c) {
+    const int j = c0 + c;
+    if (j >= cols) break;
+    DD acc = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int i = r0 + lane + 64 * k;
+      if (i < rows) acc = dd_add(acc, dd_prod(M[(size_t)i + (size_t)j * ld], wr[k]));
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) acc = dd_add(acc, dd_shfl_xor(acc, m));
+    if (lane == 0) {
+      hi[(size_t)blockIdx.y * cols + j] = acc.hi;
+      lo[(size_t)blockIdx.y * cols + j] = acc.lo;
+    }
+  }
+}
+
+// Partial sums of one product in double-double: part q of element i is
+// hi[q len + i] + lo[q len + i].
+struct PartsDD {
+  const double* hi; const double* lo; int nparts; int len;
+  __device__ DD sum(int i) const {
+    DD s = {0.0, 0.0};
+    for (int q = 0; q < nparts; ++q)
+      s = dd_add(s, DD{hi[(size_t)q * len + i], lo[(size_t)q * len + i]});
+    return s;
+  }
+};
+__device__ __forceinline__ DD dd_neg(DD a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ DD dd_from(double a) { return {a, 0.0}; }
+__device__ __forceinline__ double dd_round(DD a) { return a.hi + a.lo; }
+
 // ------------------------------------------------------- residual finish --
 struct PartsView {
   const double* p; int nparts; int len;
@@ -386,6 +482,72 @@ __global__ __launch_bounds__(256) void k_gls_finish(int n, int m, int p, const d
   scaled_sumsq6(s, normp + (size_t)blockIdx.x * kNormSlots);
 }
 
+// Double-double versions of the two finish kernels: the residual blocks
+// are formed from the FP64 inputs and iterate and the double-double partial
+// products, and rounded once.
+__global__ __launch_bounds__(256) void k_lse_finish_dd(int m, int n, int p, const double* __restrict__ b,
+                                                       const double* __restrict__ d,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ r,
+                                                       const double* __restrict__ v, PartsDD Ax,
+                                                       PartsDD Atr, PartsDD Bx, PartsDD Btv,
+                                                       double* __restrict__ f1, double* __restrict__ f2,
+                                                       double* __restrict__ f3,
+                                                       double* __restrict__ normp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (i < m) {
+    const double val = dd_round(dd_add(dd_two_sum(b[i], -r[i]), dd_neg(Ax.sum(i))));
+    f1[i] = val;
+    s[0] = val;
+    s[4] = r[i];
+  }
+  if (i < p) {
+    const double val = dd_round(dd_add(dd_from(d[i]), dd_neg(Bx.sum(i))));
+    f2[i] = val;
+    s[1] = val;
+    s[5] = v[i];
+  }
+  if (i < n) {
+    const double val = dd_round(dd_add(dd_neg(Atr.sum(i)), Btv.sum(i)));
+    f3[i] = val;
+    s[2] = val;
+    s[3] = x[i];
+  }
+  scaled_sumsq6(s, normp + (size_t)blockIdx.x * kNormSlots);
+}
+
+__global__ __launch_bounds__(256) void k_gls_finish_dd(int n, int m, int p, const double* __restrict__ d,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ z, PartsDD Wx,
+                                                       PartsDD Wtz, PartsDD Vy, PartsDD Vtz,
+                                                       double* __restrict__ f1, double* __restrict__ f2,
+                                                       double* __restrict__ f3,
+                                                       double* __restrict__ normp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (i < p) {
+    const double val = dd_round(dd_add(dd_from(-y[i]), Vtz.sum(i)));
+    f1[i] = val;
+    s[0] = val;
+    s[4] = y[i];
+  }
+  if (i < n) {
+    const double val = dd_round(dd_add(dd_add(dd_from(d[i]), dd_neg(Wx.sum(i))), dd_neg(Vy.sum(i))));
+    f2[i] = val;
+    s[1] = val;
+    s[5] = z[i];
+  }
+  if (i < m) {
+    const double val = dd_round(Wtz.sum(i));
+    f3[i] = val;
+    s[2] = val;
+    s[3] = x[i];
+  }
+  scaled_sumsq6(s, normp + (size_t)blockIdx.x * kNormSlots);
+}
+
 // Stop test.  normp: per block the scaled sums of squares and exponents of
 // [f1, f2, f3, x, a1, a2] (k_lse_finish / k_gls_finish).
 // matnorms: [||A||_F, ||B||_F, ||rhs1||, ||rhs2||].
@@ -450,23 +612,54 @@ __global__ void k_stop(const double* __restrict__ normp, int nblk, const double*
   st->nonfinite = bad;
 }
 
+// Double-double partial products of M (rows x cols): Mu parts (one per
+// 64-column block, length rows) and M^T w parts (one per 256-row block,
+// length cols), from the workspace.
+struct DualDD { PartsDD mu, mtw; };
+static DualDD dual_dd(Ctx& ctx, const double* M, int ld, int rows, int cols, const double* u,
+                      const double* w) {
+  DualDD o;
+  const int ncb = ceil_div(cols, 64), nrb = ceil_div(rows, 256);
+  if (rows <= 0 || cols <= 0) {
+    o.mu = {nullptr, nullptr, 0, rows};
+    o.mtw = {nullptr, nullptr, 0, cols};
+    return o;
+  }
+  double* rh = ctx.ws->get<double>((size_t)ncb * rows);
+  double* rl = ctx.ws->get<double>((size_t)ncb * rows);
+  double* ch = ctx.ws->get<double>((size_t)nrb * cols);
+  double* cl = ctx.ws->get<double>((size_t)nrb * cols);
+  hipLaunchKernelGGL(k_gemv_n_dd, dim3(nrb, ncb), dim3(256), 0, ctx.stream, M, ld, rows, cols, u, rh, rl);
+  hipLaunchKernelGGL(k_gemv_t_dd, dim3(ncb, nrb), dim3(256), 0, ctx.stream, M, ld, rows, cols, w, ch, cl);
+  LSQ_LAUNCH_CHECK();
+  o.mu = {rh, rl, ncb, rows};
+  o.mtw = {ch, cl, nrb, cols};
+  return o;
+}
+
 void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
                   int ldb, const double* b, const double* d, const double* x, const double* r,
                   const double* v, double* f1, double* f2, double* f3, const double* matnorms,
-                  double tol, StopStatus* st) {
+                  double tol, StopStatus* st, bool dd) {
   // the partial sums live only until the finish kernel below has read them:
   // the memory goes back to the workspace (stream order keeps it safe)
   const Arena::Mark mk = ctx.ws->mark();
-  DualParts pa, pb;
-  dual_gemv(ctx, A, lda, m, n, x, r, pa);
-  dual_gemv(ctx, B, ldb, p, n, x, v, pb);
   const int len = m > n ? (m > p ? m : p) : (n > p ? n : p);
   const int nblk = ceil_div(len, 256);
   double* normp = ctx.ws->get<double>((size_t)nblk * kNormSlots);
-  PartsView Ax{pa.rowp, pa.ncb, m}, Atr{pa.colp, pa.nrb, n}, Bx{pb.rowp, pb.ncb, p},
-      Btv{pb.colp, pb.nrb, n};
-  hipLaunchKernelGGL(k_lse_finish, dim3(nblk), dim3(256), 0, ctx.stream, m, n, p, b, d, x, r, v, Ax,
-                     Atr, Bx, Btv, f1, f2, f3, normp);
+  if (dd) {
+    const DualDD pa = dual_dd(ctx, A, lda, m, n, x, r), pb = dual_dd(ctx, B, ldb, p, n, x, v);
+    hipLaunchKernelGGL(k_lse_finish_dd, dim3(nblk), dim3(256), 0, ctx.stream, m, n, p, b, d, x, r, v,
+                       pa.mu, pa.mtw, pb.mu, pb.mtw, f1, f2, f3, normp);
+  } else {
+    DualParts pa, pb;
+    dual_gemv(ctx, A, lda, m, n, x, r, pa);
+    dual_gemv(ctx, B, ldb, p, n, x, v, pb);
+    PartsView Ax{pa.rowp, pa.ncb, m}, Atr{pa.colp, pa.nrb, n}, Bx{pb.rowp, pb.ncb, p},
+        Btv{pb.colp, pb.nrb, n};
+    hipLaunchKernelGGL(k_lse_finish, dim3(nblk), dim3(256), 0, ctx.stream, m, n, p, b, d, x, r, v, Ax,
+                       Atr, Bx, Btv, f1, f2, f3, normp);
+  }
   hipLaunchKernelGGL(k_stop, dim3(1), dim3(256), 0, ctx.stream, normp, nblk, matnorms, 0, tol, st);
   LSQ_LAUNCH_CHECK();
   ctx.ws->rewind(mk);
@@ -475,20 +668,26 @@ void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const
 void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
                   int ldv, const double* d, const double* x, const double* y, const double* z,
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
-                  StopStatus* st) {
+                  StopStatus* st, bool dd) {
   // the partial sums live only until the finish kernel below has read them:
   // the memory goes back to the workspace (stream order keeps it safe)
   const Arena::Mark mk = ctx.ws->mark();
-  DualParts pw, pv;
-  dual_gemv(ctx, W, ldw, n, m, x, z, pw);
-  dual_gemv(ctx, V, ldv, n, p, y, z, pv);
   const int len = m > n ? (m > p ? m : p) : (n > p ? n : p);
   const int nblk = ceil_div(len, 256);
   double* normp = ctx.ws->get<double>((size_t)nblk * kNormSlots);
-  PartsView Wx{pw.rowp, pw.ncb, n}, Wtz{pw.colp, pw.nrb, m}, Vy{pv.rowp, pv.ncb, n},
-      Vtz{pv.colp, pv.nrb, p};
-  hipLaunchKernelGGL(k_gls_finish, dim3(nblk), dim3(256), 0, ctx.stream, n, m, p, d, x, y, z, Wx,
-                     Wtz, Vy, Vtz, f1, f2, f3, normp);
+  if (dd) {
+    const DualDD pw = dual_dd(ctx, W, ldw, n, m, x, z), pv = dual_dd(ctx, V, ldv, n, p, y, z);
+    hipLaunchKernelGGL(k_gls_finish_dd, dim3(nblk), dim3(256), 0, ctx.stream, n, m, p, d, x, y, z,
+                       pw.mu, pw.mtw, pv.mu, pv.mtw, f1, f2, f3, normp);
+  } else {
+    DualParts pw, pv;
+    dual_gemv(ctx, W, ldw, n, m, x, z, pw);
+    dual_gemv(ctx, V, ldv, n, p, y, z, pv);
+    PartsView Wx{pw.rowp, pw.ncb, n}, Wtz{pw.colp, pw.nrb, m}, Vy{pv.rowp, pv.ncb, n},
+        Vtz{pv.colp, pv.nrb, p};
+    hipLaunchKernelGGL(k_gls_finish, dim3(nblk), dim3(256), 0, ctx.stream, n, m, p, d, x, y, z, Wx,
+                       Wtz, Vy, Vtz, f1, f2, f3, normp);
+  }
   hipLaunchKernelGGL(k_stop, dim3(1), dim3(256), 0, ctx.stream, normp, nblk, matnorms, 1, tol, st);
   LSQ_LAUNCH_CHECK();
   ctx.ws->rewind(mk);

@@ -9,9 +9,11 @@ If liblsq.so has not been built, `load()` raises; there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 from typing import Optional
 
 import numpy as np
@@ -33,7 +35,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("prec", c_int), ("solver", c_int), ("tol", c_double), ("maxit", c_int),
                 ("gmres_restart", c_int), ("gmres_tol", c_double), ("gmres_maxit", c_int),
                 ("escalate", c_int), ("alpha", c_double), ("beta", c_double), ("nb", c_int),
-                ("polish", c_double)]
+                ("polish", c_double), ("residual", c_int)]
 
 
 class Result(ctypes.Structure):
@@ -99,6 +101,7 @@ _SIGS = {
                                      _P, _P, _P, _P, _P, ctypes.POINTER(c_double)]),
     "lsq_dbg_gls_residual": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P,
                                      _P, _P, _P, _P, ctypes.POINTER(c_double)]),
+    "lsq_dbg_residual_dd": (c_int, [_P, c_int]),
     "lsq_dbg_lse_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
                                        _P, _P, _P, _P, _P]),
     "lsq_dbg_gls_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
@@ -112,6 +115,7 @@ _SIGS = {
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     "lsq_dbg_copy": (c_int, [_P, _P, _P, ctypes.c_longlong]),
     "lsq_dbg_batch_wait": (c_int, [_P, ctypes.c_double]),
+    "lsq_dbg_lookahead": (c_int, [_P, c_int]),
     "lsq_dbg_factors_bytes": (c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong)]),
     "lsq_dbg_noalloc_bytes": (c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
@@ -235,12 +239,35 @@ def _ld(t):
     return max(int(t.stride(1)) if c > 1 else r, 1)
 
 
+# Every live handle and factors object, closed (factors first) by an exit
+# hook that runs before the interpreter tears its modules down: a destructor
+# left to the final garbage collection could otherwise call into the HIP
+# runtime after a profiler or torch has finalized it.
+_LIVE_HANDLES: "weakref.WeakSet" = weakref.WeakSet()
+_LIVE_FACTORS: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for f in list(_LIVE_FACTORS):
+        try:
+            f.close()
+        except Exception:
+            pass
+    for h in list(_LIVE_HANDLES):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
 class Factors:
     """Stored factors of one pair (lse_factor / gls_factor); keeps the pair's
     tensors alive, since every solve's FP64 residual reads them."""
 
     def __init__(self, handle, ptr, kind, shape, keep):
         self.handle, self.f, self.kind, self.shape, self._keep = handle, ptr, kind, shape, keep
+        _LIVE_FACTORS.add(self)
 
     def solve(self, *vecs, opts: Optional[Opts] = None):
         """LSE: solve(b, d, x, r=None, v=None); GLS: solve(d, x, y, z=None)."""
@@ -308,6 +335,7 @@ class Handle:
         if rc != 0:
             raise RuntimeError(f"lsq_create failed ({rc})")
         self.h = h
+        _LIVE_HANDLES.add(self)
         self.sync_stream()
         if load_selector:
             from . import selector

@@ -71,7 +71,10 @@ def _per_dispatch(path: str, counter: str):
 
 
 def _mean_for(per: dict, match: str):
-    vals = [v for name, vs in per.items() if match in name for v in vs]
+    """Mean over the dispatches of every kernel whose name contains one of the
+    '|'-separated alternatives of match."""
+    alts = [m for m in match.split("|") if m]
+    vals = [v for name, vs in per.items() if any(m in name for m in alts) for v in vs]
     if not vals:
         raise SystemExit(f"no dispatch of a kernel matching {match!r}")
     return sum(vals) / len(vals), len(vals)

@@ -133,6 +133,30 @@ def lse_paper_pair(rng, m, n, p, kappa) -> LSEProblem:
                       rng.standard_normal(p), kappa_A=kappa)
 
 
+def paper_bases(rng, n, N):
+    """Orthogonal factors of the paper's generator (Section 6.2): U (n x n)
+    and V (N x n, orthonormal columns), both Haar.  One pair serves every
+    condition number of a shape: lse_paper_from_bases / gls_paper_from_bases
+    put the spectrum between them."""
+    return haar(rng, n, n), haar(rng, N, n)
+
+
+def lse_paper_from_bases(rng, U, V, m, p, kappa) -> LSEProblem:
+    """LSE with [A^T, B^T] = U diag(s) V^T (n x (m+p)), s log-spaced 1 .. 1/kappa;
+    b, d ~ N(0, 1) drawn from rng."""
+    n = U.shape[0]
+    C = (U * log_spaced(n, kappa)) @ V.T
+    return LSEProblem(_f(C[:, :m].T), _f(C[:, m:m + p].T), rng.standard_normal(m),
+                      rng.standard_normal(p), kappa_A=kappa)
+
+
+def gls_paper_from_bases(rng, U, V, m, p, kappa) -> GLSProblem:
+    """GLS with [W, V] = U diag(s) V^T (n x (m+p)); d ~ N(0, 1) drawn from rng."""
+    n = U.shape[0]
+    C = (U * log_spaced(n, kappa)) @ V.T
+    return GLSProblem(_f(C[:, :m]), _f(C[:, m:m + p]), rng.standard_normal(n), kappa_V=kappa)
+
+
 def gls_paper_pair(rng, n, m, p, kappa) -> GLSProblem:
     """GLS whose [W, V] (n x (m+p)) has condition number kappa (Section 6.3)."""
     C = conditioned(rng, n, m + p, kappa)

@@ -232,7 +232,7 @@ int gls_solve_factored(lsq_handle handle, lsq_factors factors,
  *   - -8 for opts->solver GMRES_IR (or invalid options);
  *   - -2 when the factors have not been prepared for classical refinement
  *     (solve once with lse_solve_factored and solver IR or AUTO first), and
- *     when the per-call workspace, about 16 (m n / 64 + m n / 256) + 32 (m +
+ *     when the per-call workspace, about 24 (m n / 64 + m n / 256) + 32 (m +
  *     n + p) bytes, exceeds the 64 MiB;
  *   - 4 if the handle's device has no scratch address (lsq_create sets it up).
  * Every call on one GPU uses that GPU's array, which keeps the last call's

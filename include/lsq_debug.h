@@ -46,6 +46,11 @@ int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* A, int
                          const double* y, const double* z, double* f1, double* f2, double* f3,
                          double* out);
 
+/* on = 0: classical refinement on the handle's stream runs each step kernel
+ * by kernel instead of replaying it as a captured HIP graph (the default,
+ * on != 0).  For comparing the two executions. */
+int lsq_dbg_step_graph(lsq_handle h, int on);
+
 /* on != 0: the two residual inspection entry points above evaluate the
  * residual in double-double (the opts->residual = 1 path), else in FP64. */
 int lsq_dbg_residual_dd(lsq_handle h, int on);

@@ -191,6 +191,13 @@ struct Worker {
   // ingest scan: 1, or 1/sqrt(2) while a complex problem runs through its
   // real embedding (whose Frobenius norms are sqrt(2) times the complex ones)
   double norm_scale = 1.0;
+  // a higher rung of the escalation ladder follows the one running (set by
+  // the ladder; false for solves on stored factors): a GMRES-IR rung may then
+  // give up on an inner solve that cannot converge within its budget
+  bool more_rungs = false;
+  // classical refinement replays each step (correction, residual, stop
+  // status) as one captured HIP graph; off only for inspection
+  bool step_graphs = true;
 
   void init(int dev, int num_cu, bool new_stream) {
     device = dev;
@@ -809,6 +816,52 @@ struct Continuation {
   }
 };
 
+// One step of classical refinement (the correction, the FP64 residual and
+// the copy of the stop status to the pinned host mirror) captured once as a
+// HIP graph on the worker's side stream and replayed on its stream: the
+// host then issues one launch per step instead of some sixty kernels.  The
+// captured work must neither allocate nor synchronize; if capture fails the
+// steps run kernel by kernel.
+struct StepGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~StepGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  bool capture(Worker* h, const std::function<void()>& body) {
+    Ctx& ctx = h->ctx;
+    if (!h->side) return false;
+    KernelTimer* saved_timer = ctx.timer;          // no event records inside the graph
+    hipStream_t saved = ctx.stream;
+    ctx.timer = nullptr;
+    ctx.stream = h->side;
+    bool ok = hipStreamBeginCapture(h->side, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      try {
+        body();
+      } catch (const HipError&) {
+        ok = false;
+      }
+      hipGraph_t g = nullptr;
+      const bool ended = hipStreamEndCapture(h->side, &g) == hipSuccess;
+      graph = g;
+      ok = ok && ended && graph != nullptr;
+    }
+    ctx.timer = saved_timer;
+    ctx.stream = saved;
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+      (void)hipGetLastError();
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      exec = nullptr;
+      graph = nullptr;
+    }
+    return ok;
+  }
+};
+
 // Classical refinement (Algorithms 2 and 4): init() adds the initial guess to
 // the zeroed iterate, residual() evaluates the FP64 residual and the stop
 // test on the device, correct() adds one correction.
@@ -816,15 +869,23 @@ RungOut run_classical(Worker* h, const std::function<void()>& zero,
                       const std::function<void()>& init, const std::function<void()>& residual,
                       const std::function<void()>& correct, const lsq_opts& o,
                       const std::function<void(const StopStatus&, int, int)>& observe,
-                      Continuation& cont) {
+                      Continuation& cont, bool capturable) {
   RungOut out;
   zero();
   LSQ_HIP(hipEventRecord(h->ev[2], h->stream));
   init();
   std::vector<double> hist;
+  StepGraph sg;
+  bool tried = false;
   for (int it = 0;; ++it) {
-    residual();
-    read_status(h);
+    if (it > 0 && sg.exec) {
+      LSQ_HIP(hipGraphLaunch(sg.exec, h->stream));
+      LSQ_HIP(hipStreamSynchronize(h->stream));
+    } else {
+      if (it > 0) correct();
+      residual();
+      read_status(h);
+    }
     const StopStatus& st = *h->st_host;
     if (observe) observe(st, it, 0);
     hist.push_back(st.berr_max);
@@ -838,7 +899,15 @@ RungOut run_classical(Worker* h, const std::function<void()>& zero,
       out.ok = false;
       break;
     }
-    correct();
+    if (capturable && h->step_graphs && !tried) {
+      tried = true;
+      sg.capture(h, [&]() {
+        correct();
+        residual();
+        LSQ_HIP(hipMemcpyAsync(h->st_host, h->st_dev, sizeof(StopStatus), hipMemcpyDeviceToHost,
+                               h->ctx.stream));
+      });
+    }
   }
   LSQ_HIP(hipEventRecord(h->ev[3], h->stream));
   LSQ_HIP(hipEventSynchronize(h->ev[3]));
@@ -896,9 +965,12 @@ RungOut run_gmres(Worker* h, Solver& sv, const Args& a, int N,
     }
     scaled_residual(st);
     sv.m_left(ctx, st, rhs);
+    // with a higher rung after this one, give up on an inner solve whose
+    // rate cannot reach the inner tolerance within the rung's budget
     const GmresOut g = gmres(ctx, N, apply, rhs, w, o.gmres_restart, o.gmres_tol,
-                             o.gmres_maxit - out.inner);
+                             o.gmres_maxit - out.inner, true, h->more_rungs);
     out.inner += g.iters;
+    if (g.hopeless) break;
     sv.m_right(ctx, w, du);
     update(du);
   }
@@ -1015,9 +1087,11 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
   double* f2 = ctx.ws->get<double>(a.p > 0 ? a.p : 1);
   double* f3 = ctx.ws->get<double>(a.n > 0 ? a.n : 1);
   const bool dd = o.residual == 1;
+  ResidualScratch rs;
+  residual_scratch_alloc(ctx, a.m, a.n, a.p, a.n, std::max(std::max(a.m, a.n), a.p), rs);
   auto residual = [&]() {
     lse_residual(ctx, a.m, a.n, a.p, a.A, a.lda, a.B, a.ldb, a.b, a.d, x, r, v, f1, f2, f3,
-                 h->matnorms, o.tol, h->st_dev, dd);
+                 h->matnorms, o.tol, h->st_dev, dd, &rs);
   };
   auto zero = [&]() { vec_zero(ctx, x, 8, a.n); vec_zero(ctx, r, 8, a.m); vec_zero(ctx, v, 8, a.p); };
   auto init = [&]() { sv.correct(ctx, a.b, a.d, nullptr, x, r, v); };
@@ -1062,7 +1136,7 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
       ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
                           [&]() { tracked([&]() { sv.correct(ctx, f1, f2, f3, x, r, v); }); }, o,
-                          observe, cont);
+                          observe, cont, !dd);
     }
     out.ms_factor = ms_factor;
     if (out.ok) break;
@@ -1092,9 +1166,11 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
   double* f2 = ctx.ws->get<double>(a.n > 0 ? a.n : 1);
   double* f3 = ctx.ws->get<double>(a.m > 0 ? a.m : 1);
   const bool dd = o.residual == 1;
+  ResidualScratch rs;
+  residual_scratch_alloc(ctx, a.n, a.m, a.n, a.p, std::max(std::max(a.m, a.n), a.p), rs);
   auto residual = [&]() {
     gls_residual(ctx, a.n, a.m, a.p, a.W, a.ldw, a.V, a.ldv, a.d, x, y, z, f1, f2, f3,
-                 h->matnorms, o.tol, h->st_dev, dd);
+                 h->matnorms, o.tol, h->st_dev, dd, &rs);
   };
   auto zero = [&]() { vec_zero(ctx, x, 8, a.m); vec_zero(ctx, y, 8, a.p); vec_zero(ctx, z, 8, a.n); };
   auto init = [&]() { sv.correct(ctx, nullptr, a.d, nullptr, x, y, z); };
@@ -1140,7 +1216,7 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
       ensure_prepared(sv, ctx, solver == LSQ_SOLVER_DIRECT ? 8 : sv.ps.tc, false);
       out = run_classical(h, zero, init, residual,
                           [&]() { tracked([&]() { sv.correct(ctx, f1, f2, f3, x, y, z); }); }, o,
-                          observe, cont);
+                          observe, cont, !dd);
     }
     out.ms_factor = ms_factor;
     if (out.ok) break;
@@ -1243,6 +1319,7 @@ int guard_w(Worker* w, std::string* err, const char* fn, const std::function<int
   try {
     LSQ_HIP(hipSetDevice(w->device));
     w->arena.reset();
+    w->more_rungs = false;
     rc = body();
   } catch (const HipError& e) {
     char buf[256];
@@ -1577,7 +1654,10 @@ int lse_solve_core(Worker* w, int m, int n, int p, const double* A, int lda, con
   }
   const auto rungs = ladder(o);
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
-  for (const auto& [prec, solvers] : rungs) {
+  for (size_t ri_ = 0; ri_ < rungs.size(); ++ri_) {
+    const int prec = rungs[ri_].first;
+    const std::vector<int>& solvers = rungs[ri_].second;
+    w->more_rungs = ri_ + 1 < rungs.size();
     ro = lse_rung(w, a, prec, solvers, o, xi, ri, vi, attempts, used_s, mx, &best,
                   have_pre ? &pre : nullptr, pre_code);
     used_p = prec;
@@ -1585,6 +1665,7 @@ int lse_solve_core(Worker* w, int m, int n, int p, const double* A, int lda, con
     if (ro.ok) { info = 0; break; }
     if (ro.singular) { info = ro.singular; break; }
   }
+  w->more_rungs = false;
   ro.ms_convert = ms_convert;
   if (info == 0) {
     d2d(w, x, xi, n); d2d(w, r, ri, m); d2d(w, v, vi, p);
@@ -1648,7 +1729,10 @@ int gls_solve_core(Worker* w, int n, int m, int p, const double* W, int ldw, con
   }
   const auto rungs = ladder(o);
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
-  for (const auto& [prec, solvers] : rungs) {
+  for (size_t ri_ = 0; ri_ < rungs.size(); ++ri_) {
+    const int prec = rungs[ri_].first;
+    const std::vector<int>& solvers = rungs[ri_].second;
+    w->more_rungs = ri_ + 1 < rungs.size();
     ro = gls_rung(w, a, prec, solvers, o, xi, yi, zi, attempts, used_s, mx, &best,
                   have_pre ? &pre : nullptr, pre_code);
     used_p = prec;
@@ -1656,6 +1740,7 @@ int gls_solve_core(Worker* w, int n, int m, int p, const double* W, int ldw, con
     if (ro.ok) { info = 0; break; }
     if (ro.singular) { info = ro.singular; break; }
   }
+  w->more_rungs = false;
   ro.ms_convert = ms_convert;
   if (info == 0) {
     d2d(w, x, xi, m); d2d(w, y, yi, p); d2d(w, z, zi, n);
@@ -2201,12 +2286,13 @@ static size_t lse_factored_ws_bytes(int m, int n, int p) {
   size_t t = piece(16 * 512);                                  // ingest
   t += 2 * (piece(n) + piece(m) + piece(p));                   // iterate, best iterate
   t += piece(m) + piece(p) + piece(n);                         // f1, f2, f3
-  // A's and B's partial sums, twice over (hi and lo) for the double-double residual
-  t += 2 * (piece((size_t)cd(n, 64) * m) + piece((size_t)cd(m, 256) * n));
-  t += 2 * (piece((size_t)cd(n, 64) * p) + piece((size_t)cd(p, 256) * n));
+  // A's and B's partial sums: the rung's FP64 residual workspace, and hi and
+  // lo parts besides it when the residual is double-double
+  t += 3 * (piece((size_t)cd(n, 64) * m) + piece((size_t)cd(m, 256) * n));
+  t += 3 * (piece((size_t)cd(n, 64) * p) + piece((size_t)cd(p, 256) * n));
   t += piece(n);                                               // previous x (double-double mode)
   const int len = std::max(std::max(m, n), p);
-  t += piece((size_t)cd(len, 256) * kNormSlots);               // norm partials
+  t += 2 * piece((size_t)cd(len, 256) * kNormSlots);           // norm partials
   t += 2 * piece(2);                                           // pivot check of FP64 triangles
   return t;
 }
@@ -2255,9 +2341,12 @@ int lse_solve_factored_noalloc(lsq_handle h, lsq_factors f, const double* b, con
   w->ctx.ws = &fixed;
   w->arena.set_frozen(true);
   f->arena.set_frozen(true);
+  const bool graphs = w->step_graphs;
+  w->step_graphs = false;              // instantiating a graph allocates
   const int rc = guard(h, "lse_solve_factored_noalloc", [&]() -> int {
     return lse_factored_run(w, f, b, d, x, r, v, o, solvers, res);
   });
+  w->step_graphs = graphs;
   w->ctx.ws = prev;
   w->arena.set_frozen(false);
   f->arena.set_frozen(false);
@@ -2481,6 +2570,12 @@ int lsq_dbg_gls_residual(lsq_handle h, int n, int m, int p, const double* W, int
     LSQ_HIP(hipStreamSynchronize(h->w.stream));
     return 0;
   });
+}
+
+int lsq_dbg_step_graph(lsq_handle h, int on) {
+  if (!h) return -1;
+  h->w.step_graphs = on != 0;
+  return 0;
 }
 
 int lsq_dbg_residual_dd(lsq_handle h, int on) {

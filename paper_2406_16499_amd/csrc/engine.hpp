@@ -195,15 +195,27 @@ struct StopStatus {
 // Norm accumulation slots used by the residual kernels.
 constexpr int kNormSlots = 12;
 
+// Workspace of one FP64 residual evaluation, allocated once by the caller
+// (for evaluations captured into a graph, whose addresses must stay fixed):
+// the partial products of both matrices and the norm partials.
+struct ResidualScratch {
+  DualParts p1, p2;
+  double* normp = nullptr;
+};
+// rows x cols of the two matrices of an LSE (A m x n, B p x n) or GLS
+// (W n x m, V n x p) residual.
+void residual_scratch_alloc(Ctx& ctx, int r1, int c1, int r2, int c2, int len, ResidualScratch& rs);
+
 void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
                   int ldb, const double* b, const double* d, const double* x, const double* r,
                   const double* v, double* f1, double* f2, double* f3, const double* matnorms,
-                  double tol, StopStatus* st, bool dd = false);
+                  double tol, StopStatus* st, bool dd = false, ResidualScratch* rs = nullptr);
 void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
                   int ldv, const double* d, const double* x, const double* y, const double* z,
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
-                  StopStatus* st, bool dd = false);
-// dd: the residual in double-double (u_r = u^2) instead of FP64.
+                  StopStatus* st, bool dd = false, ResidualScratch* rs = nullptr);
+// dd: the residual in double-double (u_r = u^2) instead of FP64.  rs
+// (FP64 only): preallocated workspace instead of the context's arena.
 // matnorms[0..1] = ||A||_F, ||B||_F; matnorms[2..3] = ||b||, ||d|| (LSE) or ||d||, 0 (GLS);
 // matnorms[4..7] = the largest magnitudes of the same four inputs, NaN for an
 // input that holds a non-finite value.  Norms are exact to rounding over the
@@ -240,13 +252,18 @@ struct GmresOut {
   int iters = 0;
   bool converged = false;
   bool graph = false;          // the operator ran as a replayed HIP graph
+  // the rate of the last restart cycle predicts more iterations than the
+  // budget has left (only when give_up was set): GMRES stopped early
+  bool hopeless = false;
 };
 // Restarted GMRES from x = 0 for apply(u) = M u (FP64, CGS2, Givens on the
 // host).  With use_graph, apply (which must not synchronize the host) is
-// captured once and replayed per iteration.
+// captured once and replayed per iteration.  give_up: stop after a restart
+// cycle whose residual reduction, extrapolated at the same rate, would not
+// reach tol within maxit iterations.
 GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
                const double* rhs, double* x, int restart, double tol, int maxit,
-               bool use_graph = true);
+               bool use_graph = true, bool give_up = false);
 // Y[:, j] = M U[:, j], j < k, by replays of the captured operator graph.
 void graph_apply_columns(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply,
                          const double* U, double* Y, int k, bool* graph_used);

@@ -5,9 +5,13 @@
 // Arnoldi with classical Gram-Schmidt applied twice (CGS2): per pass one
 // kernel forms the partial dot products V_k^T w per 256-row block, the next
 // sums them and subtracts V_k h from w (the second pass also accumulates
-// ||w||^2 per block).  The (k+1)-vector h and the norm go to the host, which
-// applies the Givens rotations to the small Hessenberg matrix and decides
-// convergence.  The basis is column-major N x (restart + 1) in FP64.
+// ||w||^2 per block).  A one-wave kernel then applies the Givens rotations
+// to the new Hessenberg column on the device and records the residual
+// estimate and a done flag; the host enqueues the next iteration before it
+// reads the previous one's flag (one iteration in flight beyond the test),
+// so no iteration waits for a host round trip.  After convergence the
+// kernels of an iteration already queued return at once.  The basis is
+// column-major N x (restart + 1) in FP64.
 #include "engine.hpp"
 
 namespace lsq {
@@ -23,8 +27,10 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 
 // part[b * kCgsMax + j] = sum over the rows of block b of V[i, j] w[i], j < kc.
 __global__ __launch_bounds__(256) void k_cgs_dot(const double* __restrict__ V, int ldv, int N, int kc,
-                                                 const double* __restrict__ w, double* __restrict__ part) {
+                                                 const double* __restrict__ w, double* __restrict__ part,
+                                                 const double* __restrict__ stat) {
   __shared__ double red[4][kCgsMax];
+  if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int i = blockIdx.x * kCgsRows + t;
   const double wi = i < N ? w[i] : 0.0;
@@ -44,9 +50,11 @@ __global__ __launch_bounds__(256) void k_cgs_dot(const double* __restrict__ V, i
 __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V, int ldv, int N, int kc,
                                                     const double* __restrict__ part, int nblk,
                                                     double* __restrict__ w, double* __restrict__ hacc,
-                                                    int accumulate, double* __restrict__ nrm) {
+                                                    int accumulate, double* __restrict__ nrm,
+                                                    const double* __restrict__ stat) {
   __shared__ double h[kCgsMax];
   __shared__ double red[4];
+  if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
   const int t = threadIdx.x;
   if (t < kc) {
     double s = 0.0;
@@ -67,6 +75,64 @@ __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V
     sq = block_sum(sq, red);
     if (t == 0) nrm[blockIdx.x] = sq;
   }
+}
+
+// Device state of one restart cycle: the rotated Hessenberg matrix H
+// ((restart + 1) x restart, column-major), the rotations cs, sn and the
+// right-hand side g of the small least-squares problem, and
+// stat = [|g_{k+1}|, h_{k+1,k}, done, iterations].
+struct GivensState {
+  double* H; int ldh;
+  double* cs; double* sn; double* g;
+  double* stat;
+};
+
+// Iteration k: the new column h (k + 1 entries from CGS2) and h_{k+1,k} =
+// ||w|| (block partial sums of squares) are rotated by the k earlier
+// rotations, the new rotation zeroes h_{k+1,k}, and g is updated.  done is
+// set once |g_{k+1}| <= tol_abs or h_{k+1,k} = 0 (breakdown: the Krylov space
+// holds the solution).  One wave; the work is O(k).
+__global__ void k_givens(int k, const double* __restrict__ hcol, const double* __restrict__ nrm,
+                         int nblk, GivensState st, double tol_abs) {
+  if (st.stat[2] != 0.0) return;
+  double sq = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += 64) sq += nrm[b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(sq);
+  double* col = st.H + (size_t)k * st.ldh;
+  for (int i = 0; i <= k; ++i) col[i] = hcol[i];
+  col[k + 1] = hn;
+  for (int i = 0; i < k; ++i) {
+    const double t0 = st.cs[i] * col[i] + st.sn[i] * col[i + 1];
+    col[i + 1] = -st.sn[i] * col[i] + st.cs[i] * col[i + 1];
+    col[i] = t0;
+  }
+  const double rho = hypot(col[k], col[k + 1]);
+  const double c = rho > 0.0 ? col[k] / rho : 1.0, sn = rho > 0.0 ? col[k + 1] / rho : 0.0;
+  st.cs[k] = c;
+  st.sn[k] = sn;
+  col[k] = rho;
+  col[k + 1] = 0.0;
+  const double gk = st.g[k];
+  st.g[k + 1] = -sn * gk;
+  st.g[k] = c * gk;
+  st.stat[0] = fabs(st.g[k + 1]);
+  st.stat[1] = hn;
+  st.stat[3] = (double)(k + 1);
+  if (fabs(st.g[k + 1]) <= tol_abs || hn == 0.0) st.stat[2] = 1.0;
+}
+
+// w <- w / h_{k+1,k} (the next basis vector), unless that is 0 or an earlier
+// iteration converged.
+__global__ __launch_bounds__(256) void k_scale_basis(double* __restrict__ w, int N,
+                                                     const double* __restrict__ stat, int k) {
+  if (stat[2] != 0.0 && stat[3] < (double)(k + 1)) return;
+  const double hn = stat[1];
+  if (!(hn > 0.0)) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < N) w[i] *= 1.0 / hn;
 }
 
 // x += V[:, 0:kc] y
@@ -311,7 +377,8 @@ struct GraphOp {
 // Arnoldi residual estimate reaches tol ||rhs|| or after maxit iterations in
 // total; after every cycle the residual is recomputed from x.
 GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)>& apply_eager,
-               const double* rhs, double* x, int restart, double tol, int maxit, bool use_graph) {
+               const double* rhs, double* x, int restart, double tol, int maxit, bool use_graph,
+               bool give_up) {
   GmresOut out;
   GraphOp op(ctx, apply_eager, N, use_graph);
   auto apply = [&](const double* u, double* y) { op.run(u, y); };
@@ -321,16 +388,28 @@ GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)
   if (restart > kCgsMax - 1) restart = kCgsMax - 1;
   if (restart < 1) restart = 1;
   const int nblk = ceil_div(N, kCgsRows);
+  const int ldh = restart + 1;
   double* Vb = ctx.ws->get<double>((size_t)N * (restart + 1));
   double* r = ctx.ws->get<double>(N);
   double* part = ctx.ws->get<double>((size_t)nblk * kCgsMax);
   double* hdev = ctx.ws->get<double>(kCgsMax);
   double* nrm = ctx.ws->get<double>(nblk);
   double* ydev = ctx.ws->get<double>(kCgsMax);
-  double* pin = ctx.pin;                     // pinned: kCgsMax + nblk doubles needed
-  if (kCgsMax + nblk > kPinDoubles) throw HipError{hipErrorInvalidValue, "GMRES: vector too long"};
-  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1);
-  auto Hc = [&](int i, int k) -> double& { return H[(size_t)i + (size_t)k * (restart + 1)]; };
+  // device Givens state: H, cs, sn, g, stat (one allocation)
+  double* gs = ctx.ws->get<double>((size_t)ldh * restart + 3 * kCgsMax + 4);
+  GivensState st{gs, ldh, gs + (size_t)ldh * restart, gs + (size_t)ldh * restart + kCgsMax,
+                 gs + (size_t)ldh * restart + 2 * kCgsMax, gs + (size_t)ldh * restart + 3 * kCgsMax};
+  // pinned host staging: g and stat for the cycle start, two stat slots for
+  // the per-iteration reads, H, g and stat at the cycle end
+  double* pin = ctx.pin;
+  const size_t hstage = (size_t)ldh * restart + 3 * kCgsMax + 4;
+  if (hstage + kCgsMax + 4 + 8 > (size_t)kPinDoubles - 16)
+    throw HipError{hipErrorInvalidValue, "GMRES: restart too long for the pinned staging"};
+  double* pin_start = pin;                              // g (kCgsMax) then stat (4)
+  double* pin_stat = pin + kCgsMax + 4;                 // 2 slots of 4
+  double* pin_end = pin_stat + 8;                       // H, cs, sn, g, stat
+  hipEvent_t evs[2] = {ctx_event(ctx, 200), ctx_event(ctx, 201)};
+  std::vector<double> y(restart);
 
   vec_convert(ctx, r, 8, rhs, 8, N, false);
   const double beta0 = dev_norm2(ctx, r, N);
@@ -338,54 +417,55 @@ GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)
   double beta = beta0;
   while (out.iters < maxit) {
     if (beta <= tol * beta0) { out.converged = true; break; }
+    const double beta_start = beta;
     const int kmax = std::min(restart, maxit - out.iters);
-    std::fill(H.begin(), H.end(), 0.0);
-    std::fill(g.begin(), g.end(), 0.0);
-    g[0] = beta;
+    for (int q = 0; q < kCgsMax + 4; ++q) pin_start[q] = 0.0;
+    pin_start[0] = beta;                                // g = beta e1; stat = 0
+    LSQ_HIP(hipMemcpyAsync(st.g, pin_start, sizeof(double) * kCgsMax, hipMemcpyHostToDevice, ctx.stream));
+    LSQ_HIP(hipMemcpyAsync(st.stat, pin_start + kCgsMax, sizeof(double) * 4, hipMemcpyHostToDevice,
+                           ctx.stream));
     vec_convert(ctx, Vb, 8, r, 8, N, false, 1.0 / beta);
-    int kdone = 0;
-    bool done = false;
+    // iteration k is enqueued before the flag of iteration k - 1 is read
+    int launched = 0;
     for (int k = 0; k < kmax; ++k) {
       double* w = Vb + (size_t)(k + 1) * N;
       apply(Vb + (size_t)k * N, w);
       const int kc = k + 1;
       for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_cgs_dot, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, w, part);
+        hipLaunchKernelGGL(k_cgs_dot, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, w, part,
+                           st.stat);
         hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, part, nblk,
-                           w, hdev, pass, pass == 1 ? nrm : nullptr);
+                           w, hdev, pass, pass == 1 ? nrm : nullptr, st.stat);
       }
+      hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, ctx.stream, k, hdev, nrm, nblk, st,
+                         tol * beta0);
+      hipLaunchKernelGGL(k_scale_basis, dim3(ceil_div(N, 256)), dim3(256), 0, ctx.stream, w, N,
+                         st.stat, k);
       LSQ_LAUNCH_CHECK();
-      LSQ_HIP(hipMemcpyAsync(pin, hdev, sizeof(double) * kc, hipMemcpyDeviceToHost, ctx.stream));
-      LSQ_HIP(hipMemcpyAsync(pin + kCgsMax, nrm, sizeof(double) * nblk, hipMemcpyDeviceToHost, ctx.stream));
-      LSQ_HIP(hipStreamSynchronize(ctx.stream));
-      double hn2 = 0.0;
-      for (int b = 0; b < nblk; ++b) hn2 += pin[kCgsMax + b];
-      const double hn = std::sqrt(hn2);
-      for (int i = 0; i < kc; ++i) Hc(i, k) = pin[i];
-      Hc(k + 1, k) = hn;
-      if (hn > 0.0) vec_convert(ctx, w, 8, w, 8, N, false, 1.0 / hn);
-      for (int i = 0; i < k; ++i) {        // earlier rotations
-        const double t0 = cs[i] * Hc(i, k) + sn[i] * Hc(i + 1, k);
-        Hc(i + 1, k) = -sn[i] * Hc(i, k) + cs[i] * Hc(i + 1, k);
-        Hc(i, k) = t0;
+      LSQ_HIP(hipMemcpyAsync(pin_stat + 4 * (k & 1), st.stat, sizeof(double) * 4, hipMemcpyDeviceToHost,
+                             ctx.stream));
+      LSQ_HIP(hipEventRecord(evs[k & 1], ctx.stream));
+      launched = k + 1;
+      if (k >= 1) {
+        LSQ_HIP(hipEventSynchronize(evs[(k - 1) & 1]));
+        if (pin_stat[4 * ((k - 1) & 1) + 2] != 0.0) break;    // converged at iteration k - 1
       }
-      const double rho = std::hypot(Hc(k, k), Hc(k + 1, k));
-      cs[k] = rho > 0.0 ? Hc(k, k) / rho : 1.0;
-      sn[k] = rho > 0.0 ? Hc(k + 1, k) / rho : 0.0;
-      Hc(k, k) = rho;
-      Hc(k + 1, k) = 0.0;
-      g[k + 1] = -sn[k] * g[k];
-      g[k] = cs[k] * g[k];
-      ++out.iters;
-      kdone = k + 1;
-      if (std::fabs(g[k + 1]) <= tol * beta0 || hn == 0.0) { done = true; break; }
     }
+    // the cycle's state: H, g and stat after the last queued iteration
+    LSQ_HIP(hipMemcpyAsync(pin_end, gs, sizeof(double) * hstage, hipMemcpyDeviceToHost, ctx.stream));
+    LSQ_HIP(hipStreamSynchronize(ctx.stream));
+    const double* Hh = pin_end;
+    const double* g = pin_end + (size_t)ldh * restart + 2 * kCgsMax;
+    const double* sth = pin_end + (size_t)ldh * restart + 3 * kCgsMax;
+    const int kdone = std::min((int)sth[3], launched);
+    const bool done = sth[2] != 0.0;
+    out.iters += kdone;
     // y = H(0:kdone, 0:kdone)^{-1} g, x += V y, r = rhs - M x
-    std::vector<double> y(kdone);
     for (int i = kdone - 1; i >= 0; --i) {
-      double s = g[i];
-      for (int j = i + 1; j < kdone; ++j) s -= Hc(i, j) * y[j];
-      y[i] = Hc(i, i) != 0.0 ? s / Hc(i, i) : 0.0;
+      double sacc = g[i];
+      for (int jj = i + 1; jj < kdone; ++jj) sacc -= Hh[(size_t)i + (size_t)jj * ldh] * y[jj];
+      const double hii = Hh[(size_t)i + (size_t)i * ldh];
+      y[i] = hii != 0.0 ? sacc / hii : 0.0;
     }
     for (int i = 0; i < kdone; ++i) pin[i] = y[i];
     LSQ_HIP(hipMemcpyAsync(ydev, pin, sizeof(double) * kdone, hipMemcpyHostToDevice, ctx.stream));
@@ -396,7 +476,18 @@ GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)
     vec_axpy(ctx, r, 8, -1.0, rhs, 8, N, false);          // r = M x - rhs
     beta = dev_norm2(ctx, r, N);
     vec_convert(ctx, r, 8, r, 8, N, false, -1.0);           // r = rhs - M x
-    if (done && std::fabs(g[kdone]) <= tol * beta0) { out.converged = true; break; }
+    if (done && kdone > 0 && std::fabs(g[kdone]) <= tol * beta0) { out.converged = true; break; }
+    if (give_up && !(beta <= tol * beta0) && out.iters < maxit) {
+      // the cycle reduced the residual by beta / beta_start over kdone
+      // iterations; at that rate the rest of the way to tol takes
+      // log(tol beta0 / beta) / log(rate) more
+      const double ratio = beta / beta_start;
+      const double need = ratio > 0.0 && ratio < 1.0 && kdone > 0
+                              ? std::log(tol * beta0 / beta) / (std::log(ratio) / kdone)
+                              : INFINITY;
+      if (!(need <= (double)(maxit - out.iters))) { out.hopeless = true; break; }
+    }
+    if (kdone == 0) break;
   }
   if (!out.converged) out.converged = beta <= tol * beta0;
   return out;

@@ -637,22 +637,30 @@ static DualDD dual_dd(Ctx& ctx, const double* M, int ld, int rows, int cols, con
   return o;
 }
 
+void residual_scratch_alloc(Ctx& ctx, int r1, int c1, int r2, int c2, int len, ResidualScratch& rs) {
+  dual_parts_alloc(ctx, r1, c1, rs.p1);
+  dual_parts_alloc(ctx, r2, c2, rs.p2);
+  rs.normp = ctx.ws->get<double>((size_t)ceil_div(len > 0 ? len : 1, 256) * kNormSlots);
+}
+
 void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const double* B,
                   int ldb, const double* b, const double* d, const double* x, const double* r,
                   const double* v, double* f1, double* f2, double* f3, const double* matnorms,
-                  double tol, StopStatus* st, bool dd) {
+                  double tol, StopStatus* st, bool dd, ResidualScratch* rs) {
   // the partial sums live only until the finish kernel below has read them:
   // the memory goes back to the workspace (stream order keeps it safe)
   const Arena::Mark mk = ctx.ws->mark();
   const int len = m > n ? (m > p ? m : p) : (n > p ? n : p);
   const int nblk = ceil_div(len, 256);
-  double* normp = ctx.ws->get<double>((size_t)nblk * kNormSlots);
+  if (dd) rs = nullptr;
+  double* normp = rs ? rs->normp : ctx.ws->get<double>((size_t)nblk * kNormSlots);
   if (dd) {
     const DualDD pa = dual_dd(ctx, A, lda, m, n, x, r), pb = dual_dd(ctx, B, ldb, p, n, x, v);
     hipLaunchKernelGGL(k_lse_finish_dd, dim3(nblk), dim3(256), 0, ctx.stream, m, n, p, b, d, x, r, v,
                        pa.mu, pa.mtw, pb.mu, pb.mtw, f1, f2, f3, normp);
   } else {
     DualParts pa, pb;
+    if (rs) { pa = rs->p1; pb = rs->p2; }
     dual_gemv(ctx, A, lda, m, n, x, r, pa);
     dual_gemv(ctx, B, ldb, p, n, x, v, pb);
     PartsView Ax{pa.rowp, pa.ncb, m}, Atr{pa.colp, pa.nrb, n}, Bx{pb.rowp, pb.ncb, p},
@@ -668,19 +676,21 @@ void lse_residual(Ctx& ctx, int m, int n, int p, const double* A, int lda, const
 void gls_residual(Ctx& ctx, int n, int m, int p, const double* W, int ldw, const double* V,
                   int ldv, const double* d, const double* x, const double* y, const double* z,
                   double* f1, double* f2, double* f3, const double* matnorms, double tol,
-                  StopStatus* st, bool dd) {
+                  StopStatus* st, bool dd, ResidualScratch* rs) {
   // the partial sums live only until the finish kernel below has read them:
   // the memory goes back to the workspace (stream order keeps it safe)
   const Arena::Mark mk = ctx.ws->mark();
   const int len = m > n ? (m > p ? m : p) : (n > p ? n : p);
   const int nblk = ceil_div(len, 256);
-  double* normp = ctx.ws->get<double>((size_t)nblk * kNormSlots);
+  if (dd) rs = nullptr;
+  double* normp = rs ? rs->normp : ctx.ws->get<double>((size_t)nblk * kNormSlots);
   if (dd) {
     const DualDD pw = dual_dd(ctx, W, ldw, n, m, x, z), pv = dual_dd(ctx, V, ldv, n, p, y, z);
     hipLaunchKernelGGL(k_gls_finish_dd, dim3(nblk), dim3(256), 0, ctx.stream, n, m, p, d, x, y, z,
                        pw.mu, pw.mtw, pv.mu, pv.mtw, f1, f2, f3, normp);
   } else {
     DualParts pw, pv;
+    if (rs) { pw = rs->p1; pv = rs->p2; }
     dual_gemv(ctx, W, ldw, n, m, x, z, pw);
     dual_gemv(ctx, V, ldv, n, p, y, z, pv);
     PartsView Wx{pw.rowp, pw.ncb, n}, Wtz{pw.colp, pw.nrb, m}, Vy{pv.rowp, pv.ncb, n},

@@ -102,6 +102,7 @@ _SIGS = {
     "lsq_dbg_gls_residual": (c_int, [_P, c_int, c_int, c_int, _P, c_int, _P, c_int, _P, _P, _P,
                                      _P, _P, _P, _P, ctypes.POINTER(c_double)]),
     "lsq_dbg_residual_dd": (c_int, [_P, c_int]),
+    "lsq_dbg_step_graph": (c_int, [_P, c_int]),
     "lsq_dbg_lse_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,
                                        _P, _P, _P, _P, _P]),
     "lsq_dbg_gls_correction": (c_int, [_P, c_int, c_int, c_int, c_int, _P, c_int, _P, c_int, _P,

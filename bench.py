@@ -197,6 +197,32 @@ BATCH_WORKLOAD = ("2000 instances, 50/50 LSE/GLS; LSE m~U[64,1024], n~U[32,m/2],
                   "GLS mirrored; A,B (W,V) = U diag(s) V^T, kappa log-U[1e1,1e8]; RHS N(0,1); seed 4")
 
 
+def schedule_summary(tl):
+    """Work-group time of the last persistent call, from the per-instance
+    device clocks (ms): the FP32 attempts (split into factorization and
+    refinement, and the part spent on instances that then escalated), the
+    FP64 attempts, and when the last attempt of each kind ended."""
+    import numpy as np
+    f32, f64 = tl[:, 0, :], tl[:, 1, :]
+    has32, has64 = ~np.isnan(f32[:, 0]), ~np.isnan(f64[:, 0])
+    esc = has32 & has64
+
+    def busy(a, m):
+        return float(np.sum(a[m, 2] - a[m, 0])) if m.any() else 0.0
+    return {
+        "fp32_attempts": int(has32.sum()), "fp64_attempts": int(has64.sum()),
+        "fp32_factor_ms": float(np.sum(f32[has32, 1] - f32[has32, 0])) if has32.any() else 0.0,
+        "fp32_refine_ms": float(np.sum(f32[has32, 2] - f32[has32, 1])) if has32.any() else 0.0,
+        "fp32_on_escalated_ms": busy(f32, esc),
+        "fp64_factor_ms": float(np.sum(f64[has64, 1] - f64[has64, 0])) if has64.any() else 0.0,
+        "fp64_refine_ms": float(np.sum(f64[has64, 2] - f64[has64, 1])) if has64.any() else 0.0,
+        "fp32_last_end_ms": float(np.nanmax(f32[:, 2])) if has32.any() else None,
+        "fp64_first_start_ms": float(np.nanmin(f64[:, 0])) if has64.any() else None,
+        "fp64_last_end_ms": float(np.nanmax(f64[:, 2])) if has64.any() else None,
+        "unit": "work-group ms (sums) / ms from the first start (ends)",
+    }
+
+
 def batched(args):
     """The batched workload: every instance solved per step, a solve counting
     only if it certifies berr <= 1e-14."""
@@ -254,13 +280,16 @@ def batched(args):
     # not certify factored again in FP64 inside a second persistent launch
     mixed = lsq.default_opts(prec="fp32", solver="ir", escalate=1)
     dt, ok, rungs, tim = run(mixed, args.steps, args.warmup, kernel="batch_fp32")
+    sched = schedule_summary(h.dbg_batch_timeline(len(descs)))
     dt64, ok64, _, tim64 = run(lsq.default_opts(prec="fp64", solver="direct"), args.steps,
                                args.warmup, kernel="batch_fp64")
+    sched64 = schedule_summary(h.dbg_batch_timeline(len(descs)))
     # per-instance solves on the batch workers (context): the learned selector
     # picks each instance's starting rung
     auto = lsq.default_opts(prec="auto", solver="auto", escalate=1)
     if not args.no_workers:
         dts, oks, rungss, _ = run(auto, 1, 0, mode="workers")
+        dtl, okl, rungsl, _ = run(mixed, 1, 0, mode="workers")
         dtw, okw, _, _ = run(lsq.default_opts(prec="fp64", solver="direct"), 1, 0, mode="workers")
     # calibration copy of known size, outside the timed regions (scales the
     # FETCH_SIZE / WRITE_SIZE counters of a profiled run)
@@ -294,12 +323,16 @@ def batched(args):
                         "ms_per_step": 1000.0 * dt64 / args.steps,
                         "avg_launch_us": 1000.0 * tim64[0] / max(tim64[1], 1)},
         "speedup_vs_fp64": value / value64 if value64 > 0 else None,
+        "schedule": {"mixed": sched, "fp64": sched64},
         "certified_fraction": ok / (args.count * args.steps),
         "rungs_used": rungs,
         "workers_selector": None if args.no_workers else
         {"value": oks / dts, "unit": "solves/s", "ms_per_step": 1000.0 * dts,
          "selector": "learned" if have_sel else "none (AUTO = FP32 + IR)",
          "workers": args.workers, "rungs_used": rungss},
+        "workers_ladder": None if args.no_workers else
+        {"value": okl / dtl, "unit": "solves/s", "ms_per_step": 1000.0 * dtl,
+         "ladder": "fp32 classical IR, then GMRES-IR, then fp64", "rungs_used": rungsl},
         "workers_fp64_direct": None if args.no_workers else
         {"value": okw / dtw, "unit": "solves/s", "ms_per_step": 1000.0 * dtw},
         "roofline": roof,

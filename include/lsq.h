@@ -127,6 +127,13 @@ int lsq_create(lsq_handle* handle, int device);
 int lsq_destroy(lsq_handle handle);
 /* Queue all later work on `stream` (a hipStream_t; NULL = the default stream). */
 int lsq_set_stream(lsq_handle handle, void* stream);
+/* The defaults above (FP32 factorization, classical IR, tol 1e-14, the
+   escalation ladder), each overridable from the environment for runs that
+   cannot change the caller: LSQ_PREC (auto, fp8, bf16, fp16, fp32, fp64),
+   LSQ_SOLVER (auto, ir, gmres, direct), LSQ_TOL (>= 0), LSQ_MAXIT (integer
+   >= 0), LSQ_GMRES_MAXIT (integer >= 1), LSQ_ESCALATE (0 or 1), LSQ_RESIDUAL
+   (0 or 1).  A value that does not parse or lies outside its range is
+   ignored.  Needs no GPU. */
 void lsq_opts_default(lsq_opts* opts);
 
 /*

@@ -121,6 +121,46 @@ int lsq_dbg_copy(lsq_handle h, void* dst, const void* src, long long bytes);
    outside [0, 1000]. */
 int lsq_dbg_batch_wait(lsq_handle h, double ms);
 
+/* Deterministic mode (1) or the default (0).  By default the panel Grams
+   and the skinny GEMVs of the corrections add partial sums with FP64 atomics,
+   so the last bits of a result depend on the order in which work-groups
+   finish.  In the deterministic mode every such sum is formed in a fixed
+   order (one Gram copy per row tile, summed in order; GEMV column blocks
+   launched one after another), and the same input on the same device gives
+   bitwise identical output from lse_solve, gls_solve, the complex and
+   factored variants and the batched workers.  The persistent batched kernel
+   is not covered.  Returns -2 outside 0..1. */
+int lsq_dbg_deterministic(lsq_handle h, int on);
+
+/* Per-step record of the last solve on the handle's own stream (lse_solve,
+   gls_solve, the complex and factored variants; not the batched entry
+   points): for step i < min(returned count, max_steps), berr[3 i .. 3 i + 2]
+   = the three block backward errors of eq. lse-stop / gls-stop after that
+   step, and (if rung is not NULL) rung[3 i .. 3 i + 2] = the precision and
+   solver (lsq_prec, lsq_solver) of the rung and, for GMRES-IR, the inner
+   iterations so far.  Steps of every rung the ladder ran are listed in
+   order.  Returns the number of steps recorded, -2 for max_steps < 0 or a
+   NULL berr with max_steps > 0. */
+int lsq_dbg_history(lsq_handle h, int max_steps, double* berr, int* rung);
+
+/* Route of the persistent batch's FP32 rung: when the FP64 rung follows, an
+   instance whose FP32 triangles (R of B and T11 for the LSE, R of W and the
+   leading (n - m) block of the second triangle for the GLS) show a largest to
+   smallest diagonal magnitude ratio above `ratio` goes to the FP64 rung
+   without refining.  0 turns the route off.  Returns -2 for a negative or
+   NaN ratio. */
+int lsq_dbg_batch_route(lsq_handle h, double ratio);
+
+/* Schedule of the last persistent batched call (lsq_solve_batched and the
+   typed variants, persistent modes), from the device wall clock: for each of
+   the first `count` problems of that call, out[6 i .. 6 i + 5] = start,
+   factored and end (ms from the earliest start) of its FP32 attempt, then of
+   its FP64 attempt; NaN where an attempt did not run on the persistent path
+   (or for i beyond that call).  Factored is the end of the conversions and
+   the factorization; the refinement, initial solve included, runs from there
+   to the end.  Returns -2 for count < 0 or a NULL out with count > 0. */
+int lsq_dbg_batch_timeline(lsq_handle h, int count, double* out);
+
 /* Device memory of a factors object (lse_factor / gls_factor): bytes in use
    and bytes held.  Returns -1 for NULL. */
 int lsq_dbg_factors_bytes(lsq_factors factors, long long* in_use, long long* capacity);

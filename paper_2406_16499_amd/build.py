@@ -38,9 +38,14 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Wno-unused-result", "-munsafe-fp-atomics"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+POISON_LIB = os.path.join(HERE, "liblsq_poison.so")
+
+
+def _compile(src: str, variant: str = "") -> str:
+    out_dir = os.path.join(BUILD_DIR, variant) if variant else BUILD_DIR
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    extra = ["-DLSQ_POISON_LDS"] if variant == "poison" else []
+    cmd = [hipcc(), *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -50,19 +55,22 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, variant: str = "") -> str:
+    """liblsq.so, or with variant "poison" the debug library liblsq_poison.so
+    whose kernels fill their LDS with NaN patterns before first use."""
+    lib = POISON_LIB if variant == "poison" else LIB
+    os.makedirs(os.path.join(BUILD_DIR, variant) if variant else BUILD_DIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, variant), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
-        raise RuntimeError("linking liblsq.so failed:\n" + r.stdout)
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"linking {os.path.basename(lib)} failed:\n" + r.stdout)
+    os.replace(tmp, lib)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", lib)
+    return lib
 
 
 SANITIZERS = {"address": "asan", "thread": "tsan"}
@@ -105,5 +113,7 @@ def build_sanitized(kind: str = "address", verbose: bool = False) -> str:
 if __name__ == "__main__":
     if len(sys.argv) > 2 and sys.argv[1] == "sanitize":
         build_sanitized(sys.argv[2], verbose=True)
+    elif len(sys.argv) > 1 and sys.argv[1] == "poison":
+        build(verbose=True, variant="poison")
     else:
         build(verbose=True)

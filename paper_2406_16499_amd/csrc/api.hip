@@ -24,6 +24,7 @@
 #include <thread>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -198,6 +199,10 @@ struct Worker {
   // classical refinement replays each step (correction, residual, stop
   // status) as one captured HIP graph; off only for inspection
   bool step_graphs = true;
+  // per refinement step of the last solve on this worker: the three block
+  // backward errors, and the rung (precision, solver) and inner iterations
+  struct Step { double berr[3]; int prec, solver, inner; };
+  std::vector<Step> history;
 
   void init(int dev, int num_cu, bool new_stream) {
     device = dev;
@@ -240,6 +245,14 @@ struct Worker {
   }
 };
 
+// Diagonal ratio of an FP32 triangle in the persistent batch above which an
+// instance goes to the FP64 rung without refining (see batch.hip).  The
+// ratio bounds the triangle's condition number from below; on matrices
+// U diag(s) V^T it runs 10 to 30 times below kappa, and FP32 classical
+// refinement stops contracting fast enough near kappa = 1e6 to 1e7.  Chosen by
+// a sweep of the threshold over the 2000-instance batch (1e4 .. 1e7).
+constexpr double kBatchRoute = 3e5;
+
 struct lsq_handle_st {
   int device = 0;
   int num_cu = 256;
@@ -248,10 +261,16 @@ struct lsq_handle_st {
   int batch_workers = 8;
   int batch_mode = LSQ_BATCH_AUTO;
   double esc_wait_ms = 50.0;                    // bound on an FP64 consumer's wait (concurrent batch)
+  double batch_route = kBatchRoute;             // diagonal-ratio route of the persistent FP32 rung
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
   std::string last_error;
   bool dbg_dd = false;                          // residual inspection in double-double
+  double wclk_khz = 100000.0;                   // device wall clock rate (wall_clock64)
+  // last persistent batched call, per instance of its problem array: the
+  // FP32 attempt's and the FP64 attempt's (start, factored, end) in ms from
+  // the earliest start (NaN where an attempt did not run)
+  std::vector<double> timeline;
 };
 
 namespace {
@@ -1102,6 +1121,8 @@ RungOut lse_rung(Worker* h, const LseArgs& a, int prec, const std::vector<int>& 
     solver_used = solver;
     Continuation cont(o);
     auto observe = [&](const StopStatus& st, int it, int inner) {
+      (void)it;
+      h->history.push_back({{st.berr[0], st.berr[1], st.berr[2]}, prec, solver, inner});
       if (best) best->observe(st, it, inner, prec, solver);
     };
     auto tracked = [&](const std::function<void()>& step) {
@@ -1182,6 +1203,8 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
     solver_used = solver;
     Continuation cont(o);
     auto observe = [&](const StopStatus& st, int it, int inner) {
+      (void)it;
+      h->history.push_back({{st.berr[0], st.berr[1], st.berr[2]}, prec, solver, inner});
       if (best) best->observe(st, it, inner, prec, solver);
     };
     auto tracked = [&](const std::function<void()>& step) {
@@ -1225,9 +1248,10 @@ RungOut gls_rung(Worker* h, const GlsArgs& a, int prec, const std::vector<int>& 
   return out;
 }
 
-// Selector input and output for one instance from its BF16 factors: the
-// triangles' diagonal statistics, the features and, with weights, the MLP
-// classes.  host: 16 features, 6 logits (float) then 2 classes (int).
+// Selector input and output for one instance from the factors of its first
+// ladder rung (FP32, kSelFactorPrec): the triangles' diagonal statistics, the
+// features and, with weights, the MLP classes.  host: 16 features, 7 logits
+// (float) then 2 classes (int).
 struct Selection {
   float feats[kSelFeatures];
   float logits[kSelOut];
@@ -1266,11 +1290,13 @@ int class_prec(int c) {
                                     LSQ_PREC_FP64};
   return map[c < 0 ? 0 : (c >= kSelPrec ? kSelPrec - 1 : c)];
 }
-// Precision of the factorization the features are taken from; its factors
-// are kept when the selector picks it.  FP64: on the batched workload the
-// trained selector picks the FP64 direct rung for nearly every instance (the
-// small factorizations are latency-bound, so lower precisions save no time).
-constexpr int kSelFactorPrec = LSQ_PREC_FP64;
+// Precision of the factorization the features are taken from: the first
+// rung of the plain ladder, so that its factors are kept (no second
+// factorization) whenever the selector picks an FP32 rung, and an instance it
+// sends to FP64 pays the FP32 factorization but none of the failing
+// refinement the ladder would run before escalating.  The diagonals of the
+// FP32 triangles estimate condition numbers up to about 1/u_FP32.
+constexpr int kSelFactorPrec = LSQ_PREC_FP32;
 int class_solver(int c) { return c == 1 ? LSQ_SOLVER_GMRES_IR : LSQ_SOLVER_IR; }
 
 // Escalation ladder: (precision, refinement solvers on that precision's
@@ -1375,6 +1401,14 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
   std::vector<BatchOut> hout(count);
   std::vector<int> attempts(count, 0);
   int prec = first_prec;
+  // per-instance clocks of both attempts (ticks; 0 where no attempt ran)
+  std::vector<BatchOut> clk32(count), clk64(count);
+  for (auto* v : {&clk32, &clk64})
+    for (auto& b : *v) b.t0 = b.t1 = b.t2 = 0;
+  const double tick_ms = 1.0 / h->wclk_khz;
+  auto span = [&](unsigned long long a, unsigned long long b) {
+    return b > a ? (float)((double)(b - a) * tick_ms) : 0.0f;
+  };
   auto certified = [&](int q, int rung, const BatchOut& bo) {
     if (!res) return;
     lsq_result& r = res[todo[q]];
@@ -1386,6 +1420,36 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     r.ir_steps = bo.steps;
     for (int k = 0; k < 3; ++k) r.berr[k] = bo.berr[k];
     r.berr_max = bo.berr_max;
+    // in-kernel wall clock, summed over the attempts (factorization includes
+    // the instance's conversions; refinement starts with the initial solve)
+    for (const BatchOut* c : {&clk32[q], &clk64[q]}) {
+      r.ms_factor += span(c->t0, c->t1);
+      r.ms_refine += span(c->t1, c->t2);
+    }
+  };
+  auto record_timeline = [&]() {
+    unsigned long long base = ~0ull;
+    for (int q = 0; q < count; ++q)
+      for (const BatchOut* c : {&clk32[q], &clk64[q]})
+        if (c->t0) base = std::min(base, c->t0);
+    int span_n = 0;
+    for (int q = 0; q < count; ++q) span_n = std::max(span_n, todo[q] + 1);
+    h->timeline.assign((size_t)6 * span_n, NAN);
+    // the timeline is indexed by the caller's problem index
+    for (int q = 0; q < count; ++q) {
+      const BatchOut* cs[2] = {&clk32[q], &clk64[q]};
+      for (int a = 0; a < 2; ++a) {
+        if (!cs[a]->t0) continue;
+        double* o = &h->timeline[(size_t)6 * todo[q] + 3 * a];
+        o[0] = (double)(cs[a]->t0 - base) * tick_ms;
+        o[1] = (double)(cs[a]->t1 - base) * tick_ms;
+        o[2] = (double)(cs[a]->t2 - base) * tick_ms;
+      }
+    }
+  };
+  auto keep_clock = [&](int q, int rung, const BatchOut& bo) {
+    BatchOut& c = rung == LSQ_PREC_FP64 ? clk64[q] : clk32[q];
+    if (bo.info >= 0) { c.t0 = bo.t0; c.t1 = bo.t1; c.t2 = bo.t2; }
   };
   if (prec == LSQ_PREC_FP32 && o.escalate && ctx.side && h->batch_mode == LSQ_BATCH_AUTO) {
     // FP32 launch with the FP64 rung running beside it: each failure is
@@ -1408,12 +1472,17 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     for (int qq : cur) flops += batch_factor_flops(hp[qq]);
     int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
     batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
-                            o.tol, o.maxit, o.polish, dout, dout64, flops, h->esc_wait_ms, started, n / 4);
+                            o.tol, o.maxit, o.polish, h->batch_route, dout, dout64, flops, h->esc_wait_ms,
+                            started, n / 4);
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> pending;
+    for (int qq : cur) {
+      keep_clock(qq, LSQ_PREC_FP32, hout[qq]);
+      if (hout64[qq].info != -1) keep_clock(qq, LSQ_PREC_FP64, hout64[qq]);
+    }
     for (int qq : cur) {
       ++attempts[qq];
       if (hout[qq].info == 0) {
@@ -1426,7 +1495,10 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
         else rest.push_back(todo[qq]);
       }
     }
-    if (pending.empty()) return rest;
+    if (pending.empty()) {
+      record_timeline();
+      return rest;
+    }
     cur = pending;
     prec = LSQ_PREC_FP64;
   }
@@ -1438,10 +1510,11 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     const int tw = prec == LSQ_PREC_FP64 ? 8 : 4;
     const int g = std::min(batch_blocks_per_cu(tw) * h->num_cu, (int)cur.size());
     batch_launch(ctx, tw, dprobs, dorder, (int)cur.size(), dcounter, dws, stride, g, o.tol, o.maxit, o.polish,
-                 !last, dout, flops);
+                 !last, h->batch_route, dout, flops);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> failed;
+    for (int q : cur) keep_clock(q, prec, hout[q]);
     for (int q : cur) {
       ++attempts[q];
       const BatchOut& bo = hout[q];
@@ -1458,9 +1531,49 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     cur = failed;
     prec = LSQ_PREC_FP64;
   }
+  record_timeline();
   return rest;
 }
 }  // namespace
+
+// Overrides of the defaults from the environment (LSQ_PREC, LSQ_SOLVER,
+// LSQ_TOL, LSQ_MAXIT, LSQ_GMRES_MAXIT, LSQ_ESCALATE, LSQ_RESIDUAL); a value
+// that does not parse, or lies outside its field's range, is ignored.
+static void apply_env_overrides(lsq_opts* o) {
+  auto str = [](const char* k) -> const char* {
+    const char* v = std::getenv(k);
+    return (v && *v) ? v : nullptr;
+  };
+  auto num = [&](const char* k, double& out) {
+    const char* v = str(k);
+    if (!v) return false;
+    char* end = nullptr;
+    const double d = std::strtod(v, &end);
+    if (end == v || *end != '\0' || !std::isfinite(d)) return false;
+    out = d;
+    return true;
+  };
+  if (const char* v = str("LSQ_PREC")) {
+    static const std::pair<const char*, int> names[] = {
+        {"auto", LSQ_PREC_AUTO}, {"fp8", LSQ_PREC_FP8E4M3}, {"bf16", LSQ_PREC_BF16},
+        {"fp16", LSQ_PREC_FP16}, {"fp32", LSQ_PREC_FP32},    {"fp64", LSQ_PREC_FP64}};
+    for (const auto& nm : names)
+      if (std::strcmp(v, nm.first) == 0) o->prec = nm.second;
+  }
+  if (const char* v = str("LSQ_SOLVER")) {
+    static const std::pair<const char*, int> names[] = {
+        {"auto", LSQ_SOLVER_AUTO}, {"ir", LSQ_SOLVER_IR}, {"gmres", LSQ_SOLVER_GMRES_IR},
+        {"direct", LSQ_SOLVER_DIRECT}};
+    for (const auto& nm : names)
+      if (std::strcmp(v, nm.first) == 0) o->solver = nm.second;
+  }
+  double d;
+  if (num("LSQ_TOL", d) && d >= 0.0) o->tol = d;
+  if (num("LSQ_MAXIT", d) && d >= 0.0 && d <= 1e6 && d == std::floor(d)) o->maxit = (int)d;
+  if (num("LSQ_GMRES_MAXIT", d) && d >= 1.0 && d <= 1e6 && d == std::floor(d)) o->gmres_maxit = (int)d;
+  if (num("LSQ_ESCALATE", d) && (d == 0.0 || d == 1.0)) o->escalate = (int)d;
+  if (num("LSQ_RESIDUAL", d) && (d == 0.0 || d == 1.0)) o->residual = (int)d;
+}
 
 // ================================================================== C ABI ==
 extern "C" {
@@ -1480,6 +1593,7 @@ void lsq_opts_default(lsq_opts* o) {
   o->nb = 0;
   o->polish = 8.0 * 1.1102230246251565e-16;
   o->residual = 0;
+  apply_env_overrides(o);
 }
 
 int lsq_create(lsq_handle* out, int device) {
@@ -1493,6 +1607,9 @@ int lsq_create(lsq_handle* out, int device) {
     hipDeviceProp_t prop;
     LSQ_HIP(hipGetDeviceProperties(&prop, device));
     h->num_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+      h->wclk_khz = (double)khz;
     h->w.init(device, h->num_cu, false);
     scratch_setup(device);
     LSQ_HIP(hipDeviceSynchronize());
@@ -1546,6 +1663,45 @@ int lsq_dbg_lookahead(lsq_handle h, int mode) {
   if (!h) return -1;
   if (mode < 0 || mode > 1) return fail(h, -2, "look-ahead mode outside 0..1");
   h->w.ctx.lookahead = mode != 0;
+  return 0;
+}
+
+int lsq_dbg_deterministic(lsq_handle h, int on) {
+  if (!h) return -1;
+  if (on < 0 || on > 1) return fail(h, -2, "deterministic mode outside 0..1");
+  h->w.ctx.deterministic = on != 0;
+  return 0;
+}
+
+int lsq_dbg_history(lsq_handle h, int max_steps, double* berr, int* rung) {
+  if (!h) return -1;
+  if (max_steps < 0 || (max_steps > 0 && !berr)) return -2;
+  const auto& hs = h->w.history;
+  const int n = (int)hs.size();
+  for (int i = 0; i < n && i < max_steps; ++i) {
+    for (int k = 0; k < 3; ++k) berr[3 * i + k] = hs[i].berr[k];
+    if (rung) {
+      rung[3 * i] = hs[i].prec;
+      rung[3 * i + 1] = hs[i].solver;
+      rung[3 * i + 2] = hs[i].inner;
+    }
+  }
+  return n;
+}
+
+int lsq_dbg_batch_route(lsq_handle h, double ratio) {
+  if (!h) return -1;
+  if (!(ratio >= 0.0)) return fail(h, -2, "lsq_dbg_batch_route: ratio must be >= 0");
+  h->batch_route = ratio;
+  return 0;
+}
+
+int lsq_dbg_batch_timeline(lsq_handle h, int count, double* out) {
+  if (!h) return -1;
+  if (count < 0 || (count > 0 && !out)) return -2;
+  const size_t have = h->timeline.size() / 6;
+  for (int i = 0; i < count; ++i)
+    for (int k = 0; k < 6; ++k) out[(size_t)6 * i + k] = (size_t)i < have ? h->timeline[(size_t)6 * i + k] : NAN;
   return 0;
 }
 
@@ -1653,6 +1809,7 @@ int lse_solve_core(Worker* w, int m, int n, int p, const double* A, int lda, con
     if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
   }
   const auto rungs = ladder(o);
+  w->history.clear();
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
   for (size_t ri_ = 0; ri_ < rungs.size(); ++ri_) {
     const int prec = rungs[ri_].first;
@@ -1728,6 +1885,7 @@ int gls_solve_core(Worker* w, int n, int m, int p, const double* W, int ldw, con
     if (o.solver == LSQ_SOLVER_AUTO) o.solver = class_solver(sl.cls[1]);
   }
   const auto rungs = ladder(o);
+  w->history.clear();
   int used_p = 0, used_s = 0, attempts = 0, info = 3;
   for (size_t ri_ = 0; ri_ < rungs.size(); ++ri_) {
     const int prec = rungs[ri_].first;
@@ -2028,6 +2186,7 @@ int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const l
   }
   std::atomic<int> next{0}, nfail{0};
   std::vector<std::string> errs(nw);
+  for (auto& wp : h->pool) wp->ctx.deterministic = h->w.ctx.deterministic;
   auto run = [&](int t) {
     Worker* w = h->pool[t].get();
     for (;;) {
@@ -2258,6 +2417,7 @@ static int lse_factored_run(Worker* w, lsq_factors f, const double* b, const dou
   BestIter best;
   best.save = [&]() { d2d(w, xb, xi, n); d2d(w, rb, ri, m); d2d(w, vb, vi, p); };
   int attempts = 0, used_s = 0;
+  w->history.clear();
   ro = lse_rung(w, a, f->prec, solvers, o, xi, ri, vi, attempts, used_s, nullptr, &best, &f->lse, 0);
   ro.ms_factor = 0.0f;
   ro.ms_convert = ms_convert;
@@ -2393,6 +2553,7 @@ int gls_solve_factored(lsq_handle h, lsq_factors f, const double* d, double* x, 
     BestIter best;
     best.save = [&]() { d2d(w, xb, xi, m); d2d(w, yb, yi, p); d2d(w, zb, zi, n); };
     int attempts = 0, used_s = 0;
+    w->history.clear();
     ro = gls_rung(w, a, f->prec, solvers, o, xi, yi, zi, attempts, used_s, nullptr, &best, &f->gls, 0);
     ro.ms_factor = 0.0f;
     ro.ms_convert = ms_convert;

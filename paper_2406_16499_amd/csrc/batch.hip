@@ -187,6 +187,38 @@ __device__ __forceinline__ T wg_sum1(T v, T* red) {
   return s;
 }
 
+// max |d_i| / min |d_i| over the diagonal d_i = F[i + i ld], i < nn, of the
+// triangle of one factorization (1 for nn = 0; a zero pivot gives infinity).
+// Every thread receives it.  red: kBW * 6 doubles.
+template <typename T>
+__device__ __forceinline__ double wg_diag_ratio(const T* F, int ld, int nn, double* red) {
+  double mx = 0.0, mn = INFINITY;
+  for (int i = threadIdx.x; i < nn; i += kBT) {
+    const double a = fabs((double)F[i + (size_t)i * ld]);
+    mx = fmax(mx, a);
+    mn = fmin(mn, a);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[(threadIdx.x >> 6) * 2] = mx;
+    red[(threadIdx.x >> 6) * 2 + 1] = mn;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kBW; ++i) {
+    mx = fmax(mx, red[2 * i]);
+    mn = fmin(mn, red[2 * i + 1]);
+  }
+  __syncthreads();
+  if (nn <= 0) return 1.0;
+  return mn > 0.0 ? mx / mn : INFINITY;
+}
+
 __device__ __forceinline__ void wg_sum6(double v[6], double* red) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) v[k] = wsum(v[k]);
@@ -1267,7 +1299,22 @@ __device__ __forceinline__ StopOut stop_test(const double s[6], const double mat
 // three steps.
 template <typename Correct, typename Residual>
 __device__ __forceinline__ void refine(Correct correct, Residual residual, const double mat[4], int gls,
-                                      double tol, int maxit, double polish, bool fast_exit, BatchOut* out) {
+                                      double tol, int maxit, double polish, bool fast_exit, BatchOut* out,
+                                      unsigned long long t0, bool skip) {
+  const unsigned long long t1 = wall_clock64();
+  if (skip) {
+    // routed to the next rung on the strength of the factors alone
+    if (threadIdx.x == 0) {
+      out->info = 3;
+      out->steps = -1;
+      for (int k = 0; k < 3; ++k) out->berr[k] = INFINITY;
+      out->berr_max = INFINITY;
+      out->t0 = t0;
+      out->t1 = t1;
+      out->t2 = t1;
+    }
+    return;
+  }
   correct(true);
   double hist[4] = {0, 0, 0, 0};
   int it = 0;
@@ -1302,6 +1349,9 @@ __device__ __forceinline__ void refine(Correct correct, Residual residual, const
     out->steps = it;
     for (int k = 0; k < 3; ++k) out->berr[k] = so.berr[k];
     out->berr_max = so.bmax;
+    out->t0 = t0;
+    out->t1 = t1;
+    out->t2 = wall_clock64();
   }
 }
 
@@ -1311,8 +1361,9 @@ __device__ __forceinline__ void refine(Correct correct, Residual residual, const
 // T12 = T[0:k, k:n], T22 = T[k:m, k:n] (upper part).
 template <typename T>
 __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit, double polish,
-                                             bool fast_exit, BatchOut* out,
+                                             bool fast_exit, double route, BatchOut* out,
                              BLds<T>& L) {
+  const unsigned long long t_start = wall_clock64();
   const int m = P.m, n = P.n, p = P.p, k = n - p, kqa = m < n ? m : n;
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   const LseWs<T> W = lse_ws<T>(base, m, n, p);
@@ -1336,6 +1387,12 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
   wg_transpose(W.X, ldn, n, m, W.Fa, ldm, false, true, L.u.f.Ys);   // Fa[j][n-1-i] = X[i][j]
   __syncthreads();
   wg_geqrf(W.Fa, ldm, m, n, W.taua, W.Ta, L);
+  __syncthreads();
+  // with a higher rung to follow, an instance whose triangles Rt or T11 show
+  // a diagonal ratio above `route` (a lower bound on their condition number)
+  // goes on to it without refining
+  const bool skip = fast_exit && route > 0.0 &&
+                    !(fmax(wg_diag_ratio(W.Fb, ldn, p, L.dred), wg_diag_ratio(W.Fa, ldm, k, L.dred)) <= route);
   for (int i = t; i < n; i += kBT) x[i] = 0.0;
   for (int i = t; i < m; i += kBT) W.r[i] = 0.0;
   for (int i = t; i < p; i += kBT) W.v[i] = 0.0;
@@ -1447,7 +1504,7 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     }
     wg_sum6(s, L.dred);
   };
-  refine(correct, residual, mat, 0, tol, maxit, polish, fast_exit, out);
+  refine(correct, residual, mat, 0, tol, maxit, polish, fast_exit, out, t_start, skip);
 }
 
 // ------------------------------------------------------------------ GLS --
@@ -1456,8 +1513,9 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
 // A11 = Tv[0:k, 0:k], A12 = Tv[0:k, k:n], A22 = Tv[k:p, k:n] (upper part).
 template <typename T>
 __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit, double polish,
-                                             bool fast_exit, BatchOut* out,
+                                             bool fast_exit, double route, BatchOut* out,
                              BLds<T>& L) {
+  const unsigned long long t_start = wall_clock64();
   const int n = P.n, m = P.m, p = P.p, k = n - m, kqv = p < n ? p : n;
   const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   const GlsWs<T> W = gls_ws<T>(base, n, m, p);
@@ -1481,6 +1539,10 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
   wg_transpose(W.X, ldn, n, p, W.Fv, ldp, true, true, L.u.f.Ys);    // Fv[p-1-j][n-1-i] = X[i][j]
   __syncthreads();
   wg_geqrf(W.Fv, ldp, p, n, W.tav, W.Tv, L);
+  __syncthreads();
+  // route as for the LSE: triangles Rw and A11 = Tv[0:k, 0:k]
+  const bool skip = fast_exit && route > 0.0 &&
+                    !(fmax(wg_diag_ratio(W.Fw, ldn, m, L.dred), wg_diag_ratio(W.Fv, ldp, k, L.dred)) <= route);
   for (int i = t; i < m; i += kBT) x[i] = 0.0;
   for (int i = t; i < p; i += kBT) y[i] = 0.0;
   for (int i = t; i < n; i += kBT) W.z[i] = 0.0;
@@ -1594,7 +1656,7 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     }
     wg_sum6(s, L.dred);
   };
-  refine(correct, residual, mat, 1, tol, maxit, polish, fast_exit, out);
+  refine(correct, residual, mat, 1, tol, maxit, polish, fast_exit, out, t_start, skip);
 }
 
 template <typename T>
@@ -1602,7 +1664,7 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
                                                   size_t ws_stride, double tol, int maxit, double polish,
-                                                  int fast_exit, BatchOut* __restrict__ out,
+                                                  int fast_exit, double route, BatchOut* __restrict__ out,
                                                   EscQueue* __restrict__ esc, int esc_big) {
   __shared__ BLds<T> L;
   char* mine = ws + (size_t)blockIdx.x * ws_stride;
@@ -1614,8 +1676,12 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
     if (q >= count) break;
     const int idx = order[q];
     const BatchProb P = probs[idx];
-    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, out + idx, L);
-    else gls_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, out + idx, L);
+    LSQ_LDS_POISON(L.u);
+    LSQ_LDS_POISON(L.red);
+    LSQ_LDS_POISON(L.vred);
+    LSQ_LDS_POISON(L.dred);
+    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, route, out + idx, L);
+    else gls_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, route, out + idx, L);
     __syncthreads();
     if (esc && threadIdx.x == 0) {
       // a failure goes to the FP64 launch beside this one: claim a slot,
@@ -1699,8 +1765,12 @@ __global__ __launch_bounds__(kBT, QrCfg<double>::BLOCKS) void k_batch_esc(
     __syncthreads();
     if (idx < 0) break;
     const BatchProb P = probs[idx];
-    if (P.type == 0) lse_instance<double>(P, mine, tol, maxit, polish, false, out + idx, L);
-    else gls_instance<double>(P, mine, tol, maxit, polish, false, out + idx, L);
+    LSQ_LDS_POISON(L.u);
+    LSQ_LDS_POISON(L.red);
+    LSQ_LDS_POISON(L.vred);
+    LSQ_LDS_POISON(L.dred);
+    if (P.type == 0) lse_instance<double>(P, mine, tol, maxit, polish, false, 0.0, out + idx, L);
+    else gls_instance<double>(P, mine, tol, maxit, polish, false, 0.0, out + idx, L);
     __syncthreads();
   }
 }
@@ -1740,17 +1810,17 @@ double batch_factor_flops(const BatchProb& P) {
 
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit, double polish,
-                  bool fast_exit, BatchOut* out, double flops) {
+                  bool fast_exit, double route, BatchOut* out, double flops) {
   if (count <= 0 || grid <= 0) return;
   LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
   const int kind = tw == 8 ? kKBatch64 : kKBatch32;
   ktimer_begin(ctx, kind, flops, 0.0);
   if (tw == 8)
     hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, out, nullptr, 0);
+                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, route, out, nullptr, 0);
   else
     hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, out, nullptr, 0);
+                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, route, out, nullptr, 0);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kind);
 }
@@ -1760,7 +1830,7 @@ size_t esc_queue_bytes(int count) { return sizeof(EscQueue) + 4 * sizeof(int) * 
 void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
                              int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish,
-                             BatchOut* out, BatchOut* out64, double flops, double spin_ms,
+                             double route, BatchOut* out, BatchOut* out64, double flops, double spin_ms,
                              int* started, int big_count) {
   if (count <= 0 || grid <= 0) return;
   if (!ctx.side || grid64a <= 0) throw std::runtime_error("batch_launch_escalating: no side stream");
@@ -1788,7 +1858,7 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
   }
   ktimer_begin(ctx, kKBatch32, flops, 0.0);
   hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                     counter, ws, ws_stride, tol, maxit, polish, 1, out, q, big_count);
+                     counter, ws, ws_stride, tol, maxit, polish, 1, route, out, q, big_count);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kKBatch32);
   // more consumers once the FP32 launch is over, for what is still queued

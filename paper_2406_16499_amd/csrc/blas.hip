@@ -71,6 +71,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   constexpr int LD = BK + Mt::PAD;
   __shared__ TC As[64 * LD];
   __shared__ TC Bs[64 * LD];
+  LSQ_LDS_POISON(As);
+  LSQ_LDS_POISON(Bs);
   const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
   const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
   const int ks = g.ksplit > 1 ? g.ksplit : 1;
@@ -219,13 +221,15 @@ static void gemm(Ctx& ctx, GemmArgs g, int batch) {
 
 // ----------------------------------------------------- triangular inverse --
 // Inverse of each 64 x 64 diagonal block; one work-group per block, FP64,
-// right-looking back substitution on U X = I with all columns in parallel.
-// blockIdx.y selects the matrix of a batch (strides su, sx).
+// blocked (16 x 16 diagonal blocks on four waves at once, MFMA products for
+// the rest).  blockIdx.y selects the matrix of a batch (strides su, sx).
 template <typename S, typename TC>
 __global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int ldu, long long su, int mask,
                                                   int nn, TC* __restrict__ X, int ldx, long long sx) {
   __shared__ double R[64 * kLdt];
-  __shared__ double buf[192];
+  __shared__ double Xs[64 * kLdt];
+  LSQ_LDS_POISON(R);
+  LSQ_LDS_POISON(Xs);
   U += (long long)blockIdx.y * su;
   X += (long long)blockIdx.y * sx;
   const int I = blockIdx.x, i0 = I * 64, ib = min(64, nn - i0);
@@ -238,13 +242,10 @@ __global__ __launch_bounds__(512) void k_diag_inv(const S* __restrict__ U, int l
     R[i * kLdt + j] = v;
   }
   __syncthreads();
-  double x[8];
-  reg_upper_inverse<8>(R, x, buf);
-  const Own<8> o;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int i = o.r0 + q;
-    if (i < ib && o.c < ib) X[(size_t)(i0 + i) + (size_t)(i0 + o.c) * ldx] = (TC)x[q];
+  blk_upper_inverse<8>(R, Xs);
+  for (int e = t; e < 4096; e += 512) {
+    const int i = e & 63, j = e >> 6;
+    if (i < ib && j < ib) X[(size_t)(i0 + i) + (size_t)(i0 + j) * ldx] = (TC)Xs[i * kLdt + j];
   }
 }
 
@@ -320,9 +321,9 @@ template <typename TC>
 void trmv_dense(Ctx& ctx, const TC* X, int ldx, int nn, bool trans, const TC* x, TC* y) {
   if (nn <= 0) return;
   if (!trans)
-    gemv_n<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y);
+    gemv_n<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y, ctx.deterministic);
   else
-    gemv_t<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y);
+    gemv_t<TC, TC, kUpper>(ctx.stream, X, ldx, nn, nn, 0, (TC)1, x, y, ctx.deterministic);
   LSQ_LAUNCH_CHECK();
 }
 // ---------------------------------------- aggregated reflector application --
@@ -430,13 +431,13 @@ static void agg_apply_t(Ctx& ctx, const QRFactor& f, bool trans, TC* y) {
     const double fl = 2.0 * rows * b.w, by = (double)rows * b.w * sizeof(S);
     // s = Y^T y (unit-lower Y)
     ktimer_begin(ctx, kKAggGemv, fl, by);
-    gemv_t<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)1, yy, s);
+    gemv_t<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)1, yy, s, ctx.deterministic);
     ktimer_end(ctx, kKAggGemv);
     // Q^T = I - Y T^T Y^T  -> t = T^T s ;  Q = I - Y T Y^T -> t = T s
     trmv_dense<TC>(ctx, static_cast<const TC*>(b.T), b.w, b.w, trans, s, tv);
     // y -= Y t
     ktimer_begin(ctx, kKAggGemv, fl, by);
-    gemv_n<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)-1, tv, yy);
+    gemv_n<S, TC, kUnitLower>(ctx.stream, Y, f.ld, rows, b.w, 0, (TC)-1, tv, yy, ctx.deterministic);
     ktimer_end(ctx, kKAggGemv);
     LSQ_LAUNCH_CHECK();
   }

@@ -22,6 +22,26 @@ struct HipError {
 
 #define LSQ_LAUNCH_CHECK() LSQ_HIP(hipGetLastError())
 
+// --------------------------------------------------- LDS poisoning (debug) --
+// In builds with LSQ_POISON_LDS every work-group fills its LDS buffers with
+// all-ones bit patterns (NaN in FP32 and FP64) before first use, so that a
+// read of an LDS element no thread has written turns into a NaN in the
+// results instead of a plausible stale value.  Every thread of the
+// work-group must reach the call (it ends with a barrier).
+#ifdef LSQ_POISON_LDS
+template <typename T>
+__device__ __forceinline__ void lds_poison(T* p, size_t bytes) {
+  unsigned* w = reinterpret_cast<unsigned*>(p);
+  const size_t nt = (size_t)blockDim.x * blockDim.y * blockDim.z;
+  const size_t t = threadIdx.x + (size_t)blockDim.x * (threadIdx.y + (size_t)blockDim.y * threadIdx.z);
+  for (size_t i = t; i < bytes / 4; i += nt) w[i] = 0xFFFFFFFFu;
+  __syncthreads();
+}
+#define LSQ_LDS_POISON(arr) ::lsq::lds_poison(&(arr), sizeof(arr))
+#else
+#define LSQ_LDS_POISON(arr) ((void)0)
+#endif
+
 // ------------------------------------------------------------- constants --
 constexpr int kWave = 64;               // CDNA wavefront width
 constexpr int kMaxNb = 64;              // widest panel of the blocked QR

@@ -71,6 +71,10 @@ struct Ctx {
   // compute units the latency-bound panel kernels need, and the overlap
   // gains about 2% (6.27 vs 6.39 ms for the 4096 x 2048 FP32 factorization).
   bool lookahead = false;
+  // Bitwise reproducible results: every sum that FP64 atomics would
+  // accumulate in arrival order (panel Grams, skinny GEMVs) is formed in a
+  // fixed order instead, at some cost in launches and traffic.
+  bool deterministic = false;
 };
 // The i-th event of the context's pool (created on first use).
 hipEvent_t ctx_event(Ctx& ctx, int i);
@@ -295,6 +299,9 @@ struct BatchOut {
   int steps;         // corrections after the initial solve
   double berr[3];
   double berr_max;
+  // device wall clock (wall_clock64 ticks) when the work-group took the
+  // instance, when its factorization was done and when its refinement ended
+  unsigned long long t0, t1, t2;
 };
 // Device workspace bytes of one work-group for instance P (either precision).
 size_t batch_ws_bytes(const BatchProb& P);
@@ -308,10 +315,11 @@ double batch_factor_flops(const BatchProb& P);
 // arrays); tw = 4 (FP32 factors and corrections) or 8 (FP64).  counter: one
 // device int; ws: grid * ws_stride bytes; flops: algorithmic work of the
 // launch, for the kernel timer.  fast_exit: a higher-precision rung follows,
-// so an instance whose refinement contracts too slowly stops early.
+// so an instance whose refinement contracts too slowly stops early, and one
+// whose triangles show a diagonal ratio above route (> 0) skips refinement.
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit, double polish,
-                  bool fast_exit, BatchOut* out, double flops);
+                  bool fast_exit, double route, BatchOut* out, double flops);
 
 // Escalation queues of the concurrent FP32 -> FP64 batch: the FP32 launch
 // appends each instance that fails to queue 1 if it is among the first
@@ -336,7 +344,7 @@ size_t esc_queue_bytes(int count);
 // EscQueue.  ctx.stream waits for all three launches.
 void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
-                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish,
+                             int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish, double route,
                              BatchOut* out, BatchOut* out64, double flops, double spin_ms,
                              int* started, int big_count);
 

@@ -32,6 +32,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(const S* __restrict__ A, int lda
                                                 TC* __restrict__ y) {
   constexpr int CB = 64;
   __shared__ TC xs[CB];
+  LSQ_LDS_POISON(xs);
   const int t = threadIdx.x;
   const int r0 = blockIdx.x * 256, c0 = blockIdx.y * CB;
   const int ce = min(cols, c0 + CB);
@@ -66,6 +67,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(const S* __restrict__ A, int lda
                                                 TC* __restrict__ s, int rows_per_block) {
   constexpr int NC = 16;
   __shared__ TC red[4][NC];
+  LSQ_LDS_POISON(red);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int c0 = blockIdx.x * NC;
   const int rb = blockIdx.y * rows_per_block, re = min(rows, rb + rows_per_block);
@@ -99,21 +101,36 @@ __global__ __launch_bounds__(256) void k_gemv_t(const S* __restrict__ A, int lda
 }
 
 // Launchers (stream-ordered; y / s must hold the values to accumulate onto).
+// det: no two work-groups of one launch add into the same element, so the
+// sums do not depend on the order the work-groups finish in (gemv_n then
+// launches its 64-column blocks one after another; gemv_t gives each
+// 16-column group one work-group for all the rows).
 template <typename S, typename TC, int MASK>
-void gemv_n(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* x, TC* y) {
+void gemv_n(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* x, TC* y,
+            bool det = false) {
   if (rows <= 0 || cols <= 0) return;
+  if (det) {
+    // block c holds columns 64 c .. : column j' of the block is j = j' + 64 c,
+    // so the mask's offset becomes d + 64 c
+    for (int c0 = 0; c0 < cols; c0 += 64)
+      hipLaunchKernelGGL((k_gemv_n<S, TC, MASK>), dim3(ceil_div(rows, 256), 1), dim3(256), 0, st,
+                         A + (size_t)c0 * lda, lda, rows, cols - c0 < 64 ? cols - c0 : 64, d + c0, alpha,
+                         x + c0, y);
+    return;
+  }
   hipLaunchKernelGGL((k_gemv_n<S, TC, MASK>), dim3(ceil_div(rows, 256), ceil_div(cols, 64)), dim3(256), 0,
                      st, A, lda, rows, cols, d, alpha, x, y);
 }
 
 template <typename S, typename TC, int MASK>
-void gemv_t(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* yv, TC* s) {
+void gemv_t(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* yv, TC* s,
+            bool det = false) {
   if (rows <= 0 || cols <= 0) return;
   const int nbx = ceil_div(cols, 16);
   int nby = ceil_div(rows, 256);
   const int want = ceil_div(2048, nbx);
   if (nby > want) nby = want;
-  if (nby < 1) nby = 1;
+  if (nby < 1 || det) nby = 1;
   const int rpb = ceil_div(ceil_div(rows, nby), 256) * 256;
   nby = ceil_div(rows, rpb);
   hipLaunchKernelGGL((k_gemv_t<S, TC, MASK>), dim3(nbx, nby), dim3(256), 0, st, A, lda, rows, cols, d,

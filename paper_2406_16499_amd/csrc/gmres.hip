@@ -30,6 +30,7 @@ __global__ __launch_bounds__(256) void k_cgs_dot(const double* __restrict__ V, i
                                                  const double* __restrict__ w, double* __restrict__ part,
                                                  const double* __restrict__ stat) {
   __shared__ double red[4][kCgsMax];
+  LSQ_LDS_POISON(red);
   if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int i = blockIdx.x * kCgsRows + t;
@@ -54,6 +55,8 @@ __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V
                                                     const double* __restrict__ stat) {
   __shared__ double h[kCgsMax];
   __shared__ double red[4];
+  LSQ_LDS_POISON(h);
+  LSQ_LDS_POISON(red);
   if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
   const int t = threadIdx.x;
   if (t < kc) {

@@ -29,18 +29,17 @@ constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
 // ---------------------------------------------------------------------------
 // Gram accumulation: G (upper triangle, column-major ld 64) += tile^T tile for
 // the 64 x 64 FP64 LDS tile (columns >= jb are zero).  FP64 MFMA, then FP64
-// atomics from the upper quadrants into one of kGramCopies copies of G
-// (chosen by the work-group), which the readers sum.  More copies divide the
-// atomic contention but multiply the readers' traffic; on the 4096-row
-// panels one copy measured fastest.
+// atomics from the upper quadrants into copy (row tile mod copies) of G; the
+// readers sum the copies in order.  One copy measured fastest on the
+// 4096-row panels (more divide the atomic contention but multiply the
+// readers' traffic).  The deterministic mode gives every row tile a copy of
+// its own: each copy then receives one sum, and the readers' fixed order makes
+// the Gram independent of the order in which the work-groups finish.
 // ---------------------------------------------------------------------------
-constexpr int kGramCopies = 1;
-constexpr int kGramStride = kGramCopies * 4096;   // doubles per Gram accumulator
-
 template <int NW>
-__device__ __forceinline__ void gram_atomic(const double* tile, int jb, double* __restrict__ Gbase) {
+__device__ __forceinline__ void gram_atomic(const double* tile, int jb, double* __restrict__ Gbase, int copies) {
   constexpr int BR = 8 / NW;
-  double* __restrict__ G = Gbase + (size_t)((blockIdx.x + blockIdx.y) % kGramCopies) * 4096;
+  double* __restrict__ G = Gbase + (size_t)(blockIdx.x % copies) * 4096;
   f64x4 acc[BR][2];
   mm64_acc<NW>(tile, true, tile, acc);
   const int w = threadIdx.x >> 6;
@@ -65,28 +64,28 @@ constexpr int kPR = 64 / kPW;   // register rows per thread
 // theirs from the trailing update that produces them (k_wy_u).
 template <typename Tin>
 __global__ __launch_bounds__(kPT) void k_panel_gram(const Tin* __restrict__ X, int ldx, int mr,
-                                                    int jb, double* __restrict__ G) {
+                                                    int jb, double* __restrict__ G, int copies) {
   __shared__ double tile[64 * kLdt];
+  LSQ_LDS_POISON(tile);
   const int rb = blockIdx.x * 64;
   for (int e = threadIdx.x; e < 64 * 64; e += kPT) {
     const int i = e & 63, j = e >> 6;
     tile[i * kLdt + j] = (rb + i < mr && j < jb) ? (double)X[(size_t)(rb + i) + (size_t)j * ldx] : 0.0;
   }
   __syncthreads();
-  gram_atomic<kPW>(tile, jb, G);
+  gram_atomic<kPW>(tile, jb, G, copies);
 }
 
 // Loads the Gram accumulated in Gin as a symmetric LDS matrix, adds the
 // shift of shifted Cholesky QR when asked and pads it with the identity
 // beyond jb.  sigma = 11 (mr jb + jb (jb + 1)) u tr(G).
-__device__ __forceinline__ void load_gram(const double* Gin, int jb, int mr, int shift, double* S,
+__device__ __forceinline__ void load_gram(const double* Gin, int copies, int jb, int mr, int shift, double* S,
                                           double* red) {
   for (int e = threadIdx.x; e < 4096; e += kPT) {
     const int i = e & 63, j = e >> 6;
     const int src = (i <= j) ? i + j * 64 : j + i * 64;
     double v = 0.0;
-#pragma unroll
-    for (int c = 0; c < kGramCopies; ++c) v += Gin[(size_t)c * 4096 + src];
+    for (int c = 0; c < copies; ++c) v += Gin[(size_t)c * 4096 + src];
     S[i * kLdt + j] = v;
   }
   __syncthreads();
@@ -109,14 +108,19 @@ template <typename Tin>
 __global__ __launch_bounds__(kPT) void k_panel_cholpass(
     const double* __restrict__ Gin, int shift, int first, double* __restrict__ Racc,
     int* __restrict__ status, const Tin* __restrict__ X, int ldx, int mr, int jb,
-    double* __restrict__ Xout, int ldo, double* __restrict__ Gout) {
+    double* __restrict__ Xout, int ldo, double* __restrict__ Gout, int copies) {
   __shared__ double S0[64 * kLdt];
   __shared__ double S1[64 * kLdt];
   __shared__ double S2[64 * kLdt];
   __shared__ double buf[512];
   __shared__ double red[kPW];
+  LSQ_LDS_POISON(S0);
+  LSQ_LDS_POISON(S1);
+  LSQ_LDS_POISON(S2);
+  LSQ_LDS_POISON(buf);
+  LSQ_LDS_POISON(red);
   const int t = threadIdx.x;
-  load_gram(Gin, jb, mr, shift, S0, red);
+  load_gram(Gin, copies, jb, mr, shift, S0, red);
   double x[kPR], z[kPR];
   regs_load<kPW>(S0, x);
   const bool ok = reg_cholesky_inv<kPW>(x, z, buf);
@@ -145,7 +149,7 @@ __global__ __launch_bounds__(kPT) void k_panel_cholpass(
     const int i = e & 63, j = e >> 6;
     if (rb + i < mr && j < jb) Xout[(size_t)(rb + i) + (size_t)j * ldo] = S0[i * kLdt + j];
   }
-  gram_atomic<kPW>(S0, jb, Gout);
+  gram_atomic<kPW>(S0, jb, Gout, copies);
 }
 
 // Last Cholesky QR pass fused with the Householder reconstruction and the
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(kPT) void k_panel_final_y(
     const double* __restrict__ Q1, int ldq,           // FP64 panel basis before the last pass
     double* __restrict__ Racc, Tw* __restrict__ Mst, int ldm, int j0,
     Tw* __restrict__ Tout, Tw* __restrict__ Yhat, int ldy, int* __restrict__ status,
-    const Tw* __restrict__ Cn, int ncn, Acc* __restrict__ Wpart) {
+    const Tw* __restrict__ Cn, int ncn, Acc* __restrict__ Wpart, int copies) {
   __shared__ double A0[64 * kLdt];     // U rows (published step by step), then -U S, then T
   __shared__ double A1[64 * kLdt];     // R2^{-1}, then W^T, then the Y tile
   __shared__ double A2[64 * kLdt];     // scratch, V^T -> Mmat, then T^T
@@ -175,11 +179,19 @@ __global__ __launch_bounds__(kPT) void k_panel_final_y(
   __shared__ double cbuf[128];
   __shared__ double sgn[64];
   __shared__ double red[kPW];
+  LSQ_LDS_POISON(A0);
+  LSQ_LDS_POISON(A1);
+  LSQ_LDS_POISON(A2);
+  LSQ_LDS_POISON(A3);
+  LSQ_LDS_POISON(buf);
+  LSQ_LDS_POISON(cbuf);
+  LSQ_LDS_POISON(sgn);
+  LSQ_LDS_POISON(red);
   const int t = threadIdx.x;
   const Own<kPW> o;
   double x[kPR], v[kPR], w[kPR];
   // R2 and R2^{-1}
-  load_gram(Gin, jb, mr, 0, A0, red);
+  load_gram(Gin, copies, jb, mr, 0, A0, red);
   regs_load<kPW>(A0, x);
   {
     double z[kPR];
@@ -442,6 +454,8 @@ __global__ __launch_bounds__(256) void k_wy_t(
   constexpr int LD = BK + T::PAD;
   __shared__ __attribute__((aligned(16))) typename T::In As[64 * LD];
   __shared__ __attribute__((aligned(16))) typename T::In Bs[64 * LD];
+  LSQ_LDS_POISON(As);
+  LSQ_LDS_POISON(Bs);
   const int t = threadIdx.x;
   const int c0 = blockIdx.x * 64;
   const int kbeg = blockIdx.y * kch;
@@ -539,13 +553,14 @@ template <typename Tw, Mma MT>
 __global__ __launch_bounds__(256) void k_wy_u(
     const Tw* __restrict__ Yhat, int ldy, int mr, int jb,
     const typename MmaT<MT>::Acc* __restrict__ W, Tw* __restrict__ C, int ldc, int nc,
-    double* __restrict__ Gnext, int jbn) {
+    double* __restrict__ Gnext, int jbn, int copies) {
   using T = MmaT<MT>;
   using In = typename T::In;
   constexpr int BK = 64;
   constexpr int LD = BK + T::PAD;
   constexpr size_t kOps = 2 * 64 * LD * sizeof(In), kTile = 64 * kLdt * sizeof(double);
   __shared__ __attribute__((aligned(16))) char smem[kOps > kTile ? kOps : kTile];
+  LSQ_LDS_POISON(smem);
   In* As = reinterpret_cast<In*>(smem);
   In* Bs = As + 64 * LD;
   double* tile = reinterpret_cast<double*>(smem);
@@ -624,7 +639,7 @@ __global__ __launch_bounds__(256) void k_wy_u(
     const int e = t + 256 * q, i = e & 63, c = e >> 6;
     if (r0 + i < mr && c0 + c < nc) C[(size_t)(r0 + i) + (size_t)(c0 + c) * ldc] = (Tw)tile[i * kLdt + c];
   }
-  if (Gnext != nullptr && blockIdx.y == 0 && blockIdx.x > 0) gram_atomic<4>(tile, jbn, Gnext);
+  if (Gnext != nullptr && blockIdx.y == 0 && blockIdx.x > 0) gram_atomic<4>(tile, jbn, Gnext, copies);
 }
 
 // ---------------------------------------------------------------- host side
@@ -650,7 +665,7 @@ void qr_alloc(Ctx& ctx, QRFactor& f, int r, int c, int tw, Mma mt, int nb) {
 
 template <typename Tw, Mma MT>
 static void wy_apply(Ctx& ctx, const Tw* Y, int ldy, int mr, int jb, const Tw* Yhat, int ldyh,
-                     Tw* C, int ldc, int nc, double* Gnext = nullptr, int jbn = 0) {
+                     Tw* C, int ldc, int nc, double* Gnext = nullptr, int jbn = 0, int gcopies = 1) {
   using Acc = typename MmaT<MT>::Acc;
   if (nc <= 0 || mr <= 0) return;
   const int nct = ceil_div(nc, 64);
@@ -673,7 +688,7 @@ static void wy_apply(Ctx& ctx, const Tw* Y, int ldy, int mr, int jb, const Tw* Y
   LSQ_LAUNCH_CHECK();
   ktimer_begin(ctx, kKWyU, 2.0 * mr * jb * nc, (double)mr * (jb + 2.0 * nc) * sizeof(Tw));
   hipLaunchKernelGGL((k_wy_u<Tw, MT>), dim3(ceil_div(mr, 64), nct), dim3(256), 0, ctx.stream,
-                     Yhat, ldyh, mr, jb, W, C, ldc, nc, Gnext, jbn);
+                     Yhat, ldyh, mr, jb, W, C, ldc, nc, Gnext, jbn, gcopies);
   ktimer_end(ctx, kKWyU);
   LSQ_LAUNCH_CHECK();
 }
@@ -687,9 +702,12 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
   const int r = f.r, ld = f.ld;
   double* Q0 = ctx.ws->get<double>((size_t)r * 64);
   double* Q1 = ctx.ws->get<double>((size_t)r * 64);
-  // three Gram accumulators (kGramCopies copies each) per panel, zeroed once
-  double* Gall = ctx.ws->get<double>((size_t)f.np * 3 * kGramStride);
-  LSQ_HIP(hipMemsetAsync(Gall, 0, sizeof(double) * (size_t)f.np * 3 * kGramStride, ctx.stream));
+  // three Gram accumulators per panel (gcopies copies each: one, or one per
+  // row tile in the deterministic mode), zeroed once
+  const int gcopies = ctx.deterministic ? ceil_div(r, 64) : 1;
+  const size_t gstride = (size_t)gcopies * 4096;
+  double* Gall = ctx.ws->get<double>((size_t)f.np * 3 * gstride);
+  LSQ_HIP(hipMemsetAsync(Gall, 0, sizeof(double) * (size_t)f.np * 3 * gstride, ctx.stream));
   double* Racc = ctx.ws->get<double>(4096);
   const bool lookahead = ctx.lookahead && ctx.side != nullptr && ctx.events != nullptr && f.np > 1;
   Ctx sctx = ctx;
@@ -698,16 +716,16 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
   {
     const int jb = f.k < f.nb ? f.k : f.nb;
     hipLaunchKernelGGL((k_panel_gram<Tw>), dim3(ceil_div(r, 64)), dim3(kPT), 0, ctx.stream,
-                       M, ld, r, jb, Gall);
+                       M, ld, r, jb, Gall, gcopies);
   }
   for (int j = 0; j < f.np; ++j) {
     const int j0 = j * f.nb;
     const int jb = (f.k - j0) < f.nb ? (f.k - j0) : f.nb;
     const int mr = r - j0;
     const int tiles = ceil_div(mr, 64);
-    double* G0 = Gall + (size_t)j * 3 * kGramStride;
-    double* G1 = G0 + kGramStride;
-    double* G2 = G1 + kGramStride;
+    double* G0 = Gall + (size_t)j * 3 * gstride;
+    double* G1 = G0 + gstride;
+    double* G2 = G1 + gstride;
     Tw* P = M + (size_t)j0 + (size_t)j0 * ld;
     // shifted pass: Q0 = P R0^{-1}, R0 = chol(P^T P + sigma I)
     // algorithmic work of a pass: X R^{-1} and the Gram (2 mr jb^2 each), the
@@ -715,14 +733,14 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
     const double pass_flops = 4.0 * mr * jb * jb + 2.0 * jb * jb * jb / 3.0;
     ktimer_begin(ctx, kKPanelCholPass, pass_flops, (double)mr * jb * (sizeof(Tw) + 8));
     hipLaunchKernelGGL((k_panel_cholpass<Tw>), dim3(tiles), dim3(kPT), 0, ctx.stream,
-                       G0, 1, 1, Racc, f.status, P, ld, mr, jb, Q0, mr, G1);
+                       G0, 1, 1, Racc, f.status, P, ld, mr, jb, Q0, mr, G1, gcopies);
     ktimer_end(ctx, kKPanelCholPass);
     const double* Qlast = Q0;
     const double* Glast = G1;
     if (f.passes >= 3) {
       ktimer_begin(ctx, kKPanelCholPass, pass_flops, (double)mr * jb * 16);
       hipLaunchKernelGGL((k_panel_cholpass<double>), dim3(tiles), dim3(kPT), 0, ctx.stream,
-                         G1, 0, 0, Racc, f.status, Q0, mr, mr, jb, Q1, mr, G2);
+                         G1, 0, 0, Racc, f.status, Q0, mr, mr, jb, Q1, mr, G2, gcopies);
       ktimer_end(ctx, kKPanelCholPass);
       Qlast = Q1;
       Glast = G2;
@@ -738,7 +756,7 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
     double* Gnext = nullptr;
     int jbn = 0;
     if (j + 1 < f.np) {
-      Gnext = Gall + (size_t)(j + 1) * 3 * kGramStride;
+      Gnext = Gall + (size_t)(j + 1) * 3 * gstride;
       jbn = (f.k - j0 - f.nb) < f.nb ? (f.k - j0 - f.nb) : f.nb;
     }
     Tw* Ctr = M + (size_t)j0 + (size_t)(j0 + jb) * ld;
@@ -756,7 +774,7 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
                  (double)mr * jb * (8 + 2 * sizeof(Tw)));
     hipLaunchKernelGGL((k_panel_final_y<Tw, Acc>), dim3(tiles), dim3(kPT), 0, ctx.stream,
                        Glast, jb, mr, Qlast, mr, Racc, M, ld, j0, Tb + (size_t)j * 4096,
-                       Yh + f.yoff[j], mr, f.status, (const Tw*)Ctr, la ? jbn : 0, Wpart);
+                       Yh + f.yoff[j], mr, f.status, (const Tw*)Ctr, la ? jbn : 0, Wpart, gcopies);
     ktimer_end(ctx, kKPanelFinal);
     LSQ_LAUNCH_CHECK();
     if (la) {
@@ -766,7 +784,7 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
       hipLaunchKernelGGL((k_wy_reduce<Acc>), dim3(ceil_div(64 * jbn, 256)), dim3(256), 0, ctx.stream,
                          Wpart, tiles, 64 * jbn, W);
       hipLaunchKernelGGL((k_wy_u<Tw, MT>), dim3(tiles, 1), dim3(256), 0, ctx.stream,
-                         Yh + f.yoff[j], mr, mr, jb, W, Ctr, ld, jbn, Gnext, jbn);
+                         Yh + f.yoff[j], mr, mr, jb, W, Ctr, ld, jbn, Gnext, jbn, gcopies);
       LSQ_LAUNCH_CHECK();
       LSQ_HIP(hipStreamWaitEvent(sctx.stream, panel_done, 0));
       wy_apply<Tw, MT>(sctx, P, ld, mr, jb, Yh + f.yoff[j], mr, Ctr + (size_t)jbn * ld, ld,
@@ -774,7 +792,7 @@ static void qr_factor_t(Ctx& ctx, QRFactor& f) {
       LSQ_HIP(hipEventRecord(ctx_event(ctx, 2 * j + 1), sctx.stream));
       side_pending = j;
     } else {
-      wy_apply<Tw, MT>(ctx, P, ld, mr, jb, Yh + f.yoff[j], mr, Ctr, ld, nc, Gnext, jbn);
+      wy_apply<Tw, MT>(ctx, P, ld, mr, jb, Yh + f.yoff[j], mr, Ctr, ld, nc, Gnext, jbn, gcopies);
     }
   }
   if (side_pending >= 0) LSQ_HIP(hipStreamWaitEvent(ctx.stream, ctx_event(ctx, 2 * side_pending + 1), 0));

@@ -1,8 +1,9 @@
 // Learned precision / solver selector.
 //
 // Features (16, FP32) of an instance come from FP64 norms of the inputs and
-// from the diagonals of the triangular factors of its FP64 generalized
-// factorization (whose factors are reused when the selector keeps FP64).  An
+// from the diagonals of the triangular factors of its FP32 generalized
+// factorization, the first rung of the plain ladder (whose factors are reused
+// when the selector picks an FP32 rung).  An
 // MLP 16 -> 64 -> 64 -> 7 (ReLU, FP32) maps the standardized features to two
 // heads: 5 logits for the factorization precision {FP8-e4m3, BF16, FP16,
 // FP32, FP64 direct} and 2 for the refinement solver {classical IR, GMRES-IR}.
@@ -76,6 +77,10 @@ __global__ void k_features(int type, int m, int n, int p, const double* __restri
 __global__ __launch_bounds__(64) void k_mlp(const float* __restrict__ W, const float* __restrict__ f,
                                             float* __restrict__ logits, int* __restrict__ cls) {
   __shared__ float x[kSelFeatures], h1[kSelHidden], h2[kSelHidden], lo[kSelOut];
+  LSQ_LDS_POISON(x);
+  LSQ_LDS_POISON(h1);
+  LSQ_LDS_POISON(h2);
+  LSQ_LDS_POISON(lo);
   const int t = threadIdx.x;
   const float* mean = W;
   const float* sd = W + kSelFeatures;

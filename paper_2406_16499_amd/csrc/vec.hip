@@ -33,10 +33,10 @@ void gemv_upper(Ctx& ctx, const QRFactor& f, int ro, int co, int nr, int nc, boo
     const TW* A = static_cast<const TW*>(f.M) + (size_t)ro + (size_t)co * f.ld;                 \
     if (!trans)                                                                                 \
       gemv_n<TW, TC, kUpper>(ctx.stream, A, f.ld, nr, nc, co - ro, (TC)alpha,                   \
-                             static_cast<const TC*>(x), static_cast<TC*>(y));                   \
+                             static_cast<const TC*>(x), static_cast<TC*>(y), ctx.deterministic); \
     else                                                                                        \
       gemv_t<TW, TC, kUpper>(ctx.stream, A, f.ld, nr, nc, co - ro, (TC)alpha,                   \
-                             static_cast<const TC*>(x), static_cast<TC*>(y));                   \
+                             static_cast<const TC*>(x), static_cast<TC*>(y), ctx.deterministic); \
   }
   if (f.tw == 8) {
     if (tc == 8) { LSQ_GEMV(double, double) } else { LSQ_GEMV(double, float) }
@@ -135,6 +135,7 @@ __global__ __launch_bounds__(256) void k_mat_convert(Td* __restrict__ dst, int l
                                                      int dc, int trans, int rev_r, int rev_c,
                                                      int sr, int sc, double scale) {
   __shared__ double tile[64 * 65];
+  LSQ_LDS_POISON(tile);
   const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   const int t = threadIdx.x;
   for (int e = t; e < 4096; e += 256) {
@@ -201,6 +202,8 @@ __global__ __launch_bounds__(256) void k_dual_gemv(const double* __restrict__ M,
                                                    double* __restrict__ colp) {
   __shared__ double us[64];
   __shared__ double red[4][64];
+  LSQ_LDS_POISON(us);
+  LSQ_LDS_POISON(red);
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int r0 = blockIdx.x * 256, c0 = blockIdx.y * 64;
   if (t < 64) us[t] = (c0 + t < cols) ? u[c0 + t] : 0.0;

@@ -11,8 +11,8 @@ constexpr int kLdt = kMaxNb + 1;   // padded LDS row stride for 64-wide FP64 til
 //
 // Thread t owns column c = t & 63 of rows r0 .. r0 + R - 1 (R = 64 / NW,
 // r0 = R (t >> 6)) and keeps those R entries in registers.  The sequential
-// algorithms (Cholesky, triangular inverse, LU, triangular solve for T) are
-// right-looking; in each step only the pivot rows or column travel through a
+// algorithms (Cholesky with its inverse factor, the modified LU of the panel
+// kernels) are right-looking; in each step only the pivot rows or column travel through a
 // double-buffered LDS line, so there is one barrier per step and no LDS
 // read-modify-write traffic.  With NW = 8 two waves share each SIMD and hide
 // each other's LDS and dependency latency.  Dense 64 x 64 products run on
@@ -200,31 +200,113 @@ __device__ __forceinline__ bool reg_cholesky_inv(double* x, double* z, double* b
   return ok;
 }
 
-// x <- R^{-1} (upper) with R read from LDS (row-major, zero below the diagonal,
-// identity-padded).  Right-looking back substitution with the diagonal
-// reciprocals computed up front; the owner of the finished row restores it
-// after the (unmasked) update.  buf: 2 x 64 + 64 doubles.
+// ---------------------------------------------------------------------------
+// Blocked inverse of a 64 x 64 upper triangle as a 4 x 4 grid of 16 x 16
+// blocks: each diagonal block is inverted by one wave in registers (16 steps
+// that need no work-group barrier, rows travelling by lane shuffles), four
+// waves at once; the off-diagonal blocks follow by distance from the diagonal
+// (one barrier per distance) as 16 x 16 x 16 FP64 MFMA products, one block
+// per wave.
+// ---------------------------------------------------------------------------
+
+// fp64 16x16x4 operand fragments of block (bi, bj) of S, for K steps s = 0..3:
+// as the A operand lane l supplies M[l%16][4s + l/16], as the B operand
+// M[4s + l/16][l%16], M the block.
+__device__ __forceinline__ void frag_a(const double* S, int bi, int bj, double a[4]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) a[s] = S[(16 * bi + (l & 15)) * kLdt + 16 * bj + 4 * s + (l >> 4)];
+}
+__device__ __forceinline__ void frag_b(const double* S, int bi, int bj, double b[4]) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) b[s] = S[(16 * bi + 4 * s + (l >> 4)) * kLdt + 16 * bj + (l & 15)];
+}
+// Accumulator register r of lane l holds row 4 r + l/16, column l%16 of the
+// block: the B-operand layout, so a product can feed the next one directly.
+__device__ __forceinline__ void blk_store(double* S, int bi, int bj, const f64x4& acc) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[(16 * bi + 4 * r + (l >> 4)) * kLdt + 16 * bj + (l & 15)] = acc[r];
+}
+__device__ __forceinline__ f64x4 blk_zero() {
+  f64x4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = 0.0;
+  return acc;
+}
+// acc += sign * A B for fragments a (A operand) and b (B operand)
+__device__ __forceinline__ f64x4 blk_mma(const double a[4], const double b[4], f64x4 acc, double sign = 1.0) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * a[s], b[s], acc, 0, 0, 0);
+  return acc;
+}
+__device__ __forceinline__ f64x4 blk_mma_acc(const double a[4], const f64x4& b, f64x4 acc, double sign = 1.0) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * a[s], b[s], acc, 0, 0, 0);
+  return acc;
+}
+// Zero the blocks strictly below (lower = true) or above the diagonal.
 template <int NW>
-__device__ __forceinline__ void reg_upper_inverse(const double* R, double* x, double* buf) {
-  constexpr int RR = Own<NW>::R;
-  const Own<NW> o;
-  double* dinv = buf + 128;
-  if (threadIdx.x < 64) dinv[threadIdx.x] = rcp64(R[threadIdx.x * kLdt + threadIdx.x]);
+__device__ __forceinline__ void zero_off_blocks(double* S, bool lower) {
+  for (int e = threadIdx.x; e < 4096; e += 64 * NW) {
+    const int i = e >> 6, j = e & 63;
+    if (lower ? (i >> 4) > (j >> 4) : (i >> 4) < (j >> 4)) S[i * kLdt + j] = 0.0;
+  }
+}
+
+// One wave: X(b, b) = R(b, b)^{-1} for an upper triangular diagonal block, by
+// back substitution on [R(b, b) | I] (the triangle itself needs no update:
+// column k of the rows above k is read as it was); rows travel by lane
+// shuffles.
+__device__ __forceinline__ void wave_uinv16(const double* R, double* X, int b) {
+  const int l = threadIdx.x & 63, i = l & 15, q = l >> 4, o = 16 * b;
+  double r[4], x[4];
 #pragma unroll
-  for (int qq = 0; qq < RR; ++qq) x[qq] = (o.r0 + qq == o.c) ? 1.0 : 0.0;
+  for (int j = 0; j < 4; ++j) {
+    r[j] = R[(o + i) * kLdt + o + 4 * q + j];
+    x[j] = (4 * q + j == i) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int k = 15; k >= 0; --k) {
+    const double rkk = __shfl(r[k & 3], ((k >> 2) << 4) + k, 64);
+    const double rik = __shfl(r[k & 3], ((k >> 2) << 4) + i, 64);    // R[i][k]
+    const double ip = rcp64(rkk);
+    double xk[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xk[j] = __shfl(x[j], (q << 4) + k, 64) * ip;   // row k of the inverse
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = (i < k) ? fma(-rik, xk[j], x[j]) : (i == k ? xk[j] : x[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) X[(o + i) * kLdt + o + 4 * q + j] = x[j];
+}
+
+// X = R^{-1} for an upper triangular R (64 x 64 LDS, zeros below the
+// diagonal, identity-padded where unused): the four diagonal blocks on four
+// waves at once, then the off-diagonal blocks by distance from the diagonal.
+template <int NW>
+__device__ __forceinline__ void blk_upper_inverse(const double* R, double* X) {
+  static_assert(NW >= 4, "one wave per diagonal block");
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  zero_off_blocks<NW>(X, true);
+  if (w < 4) wave_uinv16(R, X, w);
   __syncthreads();
-  for (int wi = NW - 1; wi >= 0; --wi) {
-#pragma unroll
-    for (int q = RR - 1; q >= 0; --q) {
-      const int i = RR * wi + q;
-      double* rb = buf + (i & 1) * 64;
-      if (o.w == wi) rb[o.c] = x[q] * dinv[i];
-      __syncthreads();
-      const double xi = rb[o.c];
-#pragma unroll
-      for (int qq = 0; qq < RR; ++qq) x[qq] = fma(-R[(o.r0 + qq) * kLdt + i], xi, x[qq]);
-      if (o.w == wi) x[q] = xi;
+  for (int dd = 1; dd < 4; ++dd) {
+    if (w < 4 - dd) {
+      const int i = w, j = w + dd;
+      f64x4 acc = blk_zero();
+      for (int k = i + 1; k <= j; ++k) {
+        double a[4], bb[4];
+        frag_a(R, i, k, a);
+        frag_b(X, k, j, bb);
+        acc = blk_mma(a, bb, acc);
+      }
+      double a[4];
+      frag_a(X, i, i, a);
+      blk_store(X, i, j, blk_mma_acc(a, acc, blk_zero(), -1.0));
     }
+    __syncthreads();
   }
 }
 

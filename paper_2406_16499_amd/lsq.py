@@ -116,6 +116,10 @@ _SIGS = {
                                    ctypes.POINTER(c_double), ctypes.POINTER(c_double)]),
     "lsq_dbg_copy": (c_int, [_P, _P, _P, ctypes.c_longlong]),
     "lsq_dbg_batch_wait": (c_int, [_P, ctypes.c_double]),
+    "lsq_dbg_batch_timeline": (c_int, [_P, c_int, _P]),
+    "lsq_dbg_batch_route": (c_int, [_P, ctypes.c_double]),
+    "lsq_dbg_history": (c_int, [_P, c_int, _P, _P]),
+    "lsq_dbg_deterministic": (c_int, [_P, c_int]),
     "lsq_dbg_lookahead": (c_int, [_P, c_int]),
     "lsq_dbg_factors_bytes": (c_int, [_P, ctypes.POINTER(ctypes.c_longlong),
                                       ctypes.POINTER(ctypes.c_longlong)]),
@@ -141,11 +145,11 @@ def header_symbols():
     return names
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load liblsq.so (raises if it has not been built)."""
-    global _lib
-    if _lib is not None:
-        return _lib
+_variants = {}
+POISON_LIB_PATH = os.path.join(_HERE, "liblsq_poison.so")
+
+
+def _bind(path: str) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2406_16499_amd.build`")
     lib = ctypes.CDLL(path)
@@ -153,8 +157,23 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
     return lib
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblsq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        _lib = _bind(path)
+    return _lib
+
+
+def load_variant(path: str) -> ctypes.CDLL:
+    """A debug build of the library (e.g. liblsq_poison.so) beside the main
+    one, for a Handle(lib=...)."""
+    if path not in _variants:
+        _variants[path] = _bind(path)
+    return _variants[path]
 
 
 def default_opts(**kw) -> Opts:
@@ -327,9 +346,9 @@ class Factors:
 class Handle:
     """Owns an lsq_handle bound to the current torch device and stream."""
 
-    def __init__(self, device: Optional[int] = None, load_selector: bool = True):
+    def __init__(self, device: Optional[int] = None, load_selector: bool = True, lib=None):
         torch = _torch()
-        self.lib = load()
+        self.lib = lib if lib is not None else load()
         dev = torch.cuda.current_device() if device is None else device
         h = ctypes.c_void_p()
         rc = self.lib.lsq_create(ctypes.byref(h), dev)
@@ -460,6 +479,32 @@ class Handle:
         rc = self.lib.lsq_set_batch_mode(self.h, {"persistent": 0, "workers": 1, "sequential": 2}[mode])
         if rc != 0:
             raise RuntimeError(f"lsq_set_batch_mode = {rc}")
+
+    def dbg_batch_timeline(self, count: int) -> np.ndarray:
+        """(count, 2, 3) ms: per problem of the last persistent batched call,
+        (start, factored, end) of its FP32 and FP64 attempts (NaN: none)."""
+        out = np.empty((count, 2, 3), np.float64)
+        rc = self.lib.lsq_dbg_batch_timeline(self.h, int(count), out.ctypes.data_as(c_void_p))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_batch_timeline = {rc}: {self.last_error()}")
+        return out
+
+    def dbg_history(self, max_steps: int = 256):
+        """(berr (k, 3), rung (k, 3): precision, solver, inner iterations) of
+        the refinement steps of the last single solve."""
+        berr = np.empty((max_steps, 3), np.float64)
+        rung = np.empty((max_steps, 3), np.int32)
+        n = self.lib.lsq_dbg_history(self.h, int(max_steps), berr.ctypes.data_as(c_void_p),
+                                     rung.ctypes.data_as(c_void_p))
+        if n < 0:
+            raise RuntimeError(f"lsq_dbg_history = {n}: {self.last_error()}")
+        k = min(n, max_steps)
+        return berr[:k], rung[:k]
+
+    def dbg_batch_route(self, ratio: float) -> None:
+        rc = self.lib.lsq_dbg_batch_route(self.h, float(ratio))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_batch_route = {rc}: {self.last_error()}")
 
     def dbg_batch_wait(self, ms: float) -> None:
         """Bound on an FP64 consumer's wait in the concurrent persistent batch."""

@@ -3,12 +3,20 @@
 The selector (liblsq: lsq_selector_set / lsq_selector_features, inference in
 a HIP kernel) maps 16 features of an instance to a factorization precision
 {FP8-e4m3, BF16, FP16, FP32, FP64 direct} and a refinement solver {classical
-IR, GMRES-IR}.  Its labels come from the method itself: every instance of a
-generated training set is solved once per rung with escalation off, and the
-label is the fastest rung that certified a backward error <= 1e-14.
+IR, GMRES-IR}.  The features are cheap: the sizes, the FP64 norms of the
+inputs, and the diagonal statistics of the triangles of the instance's FP32
+generalized factorization, the first rung of the plain ladder, whose factors
+the FP32 rungs then reuse.
 
-    python -m paper_2406_16499_amd.selector train --count 3000 --seed 5
-    python -m paper_2406_16499_amd.selector evaluate --count 1000 --seed 6
+Labels come from the method itself: every instance of a generated set is
+solved once per rung (escalation off) on the batch workers, and the label is
+the rung that certifies a backward error <= 1e-14 at the least cost to AUTO,
+which is the rung's own time for an FP32 rung and the FP32 factorization plus
+the rung's time for any other.
+
+    python -m paper_2406_16499_amd.selector collect --count 50000 --seed 5 --out data.npz
+    python -m paper_2406_16499_amd.selector fit --data data.npz
+    python -m paper_2406_16499_amd.selector evaluate --count 5000 --seed 6
 
 Weights are stored as text (one value per line, the packed order of
 LSQ_SELECTOR_WEIGHTS) in selector_weights.txt next to this file; Handle()
@@ -33,9 +41,11 @@ N_WEIGHTS = 2 * NF + NH * NF + NH + NH * NH + NH + NO * NH + NO
 PREC_CLASSES = ["fp8", "bf16", "fp16", "fp32", "fp64"]
 NP = len(PREC_CLASSES)
 SOLVER_CLASSES = ["ir", "gmres"]
-# rungs tried when labelling (FP8 has no factorization of its own yet: it runs as BF16)
-RUNGS = [("bf16", "ir"), ("bf16", "gmres"), ("fp16", "ir"), ("fp16", "gmres"),
-         ("fp32", "ir"), ("fp32", "gmres"), ("fp64", "direct")]
+# rungs tried when labelling; the features come from the FP32 factorization
+RUNGS = [("fp8", "ir"), ("fp8", "gmres"), ("bf16", "ir"), ("bf16", "gmres"), ("fp16", "ir"),
+         ("fp16", "gmres"), ("fp32", "ir"), ("fp32", "gmres"), ("fp64", "direct")]
+FEATURE_PREC = "fp32"
+REUSES_FEATURE_FACTORS = np.array([p == FEATURE_PREC for p, _ in RUNGS])
 
 
 # ----------------------------------------------------------------- model --
@@ -137,6 +147,43 @@ def load(path=WEIGHTS_PATH):
 
 
 # ----------------------------------------------------- data from the GPU --
+def _generate(args):
+    """Instances [start, stop) of the batch recipe (runs in a worker process,
+    one BLAS thread)."""
+    seed, start, stop, kappa_max = args
+    from threadpoolctl import threadpool_limits
+    from . import workloads as wl
+    with threadpool_limits(1):
+        return list(wl.batch_instances(seed=seed, count=stop, kappa_max=kappa_max, start=start))
+
+
+def instance_stream(count, seed, kappa_max, chunk, procs=12, sub=50):
+    """Chunks of `chunk` instances, generated by `procs` worker processes while
+    the caller works on the previous chunk (at most two chunks in flight)."""
+    import multiprocessing as mp
+    from collections import deque
+    from concurrent.futures import ProcessPoolExecutor
+    spans = [(s, min(s + sub, count)) for s in range(0, count, sub)]
+    per_chunk = max(1, chunk // sub)
+    with ProcessPoolExecutor(max_workers=procs, mp_context=mp.get_context("spawn")) as pool:
+        pending = deque()
+        nxt = 0
+
+        def fill():
+            nonlocal nxt
+            while nxt < len(spans) and len(pending) < 2 * per_chunk:
+                a, b = spans[nxt]
+                pending.append(pool.submit(_generate, (seed, a, b, kappa_max)))
+                nxt += 1
+        fill()
+        while pending:
+            out = []
+            for _ in range(min(per_chunk, len(pending))):
+                out.extend(pending.popleft().result())
+            fill()
+            yield out
+
+
 def _device_problem(P):
     from . import lsq
     if P.kind == "lse":
@@ -153,49 +200,134 @@ def features(h, P):
     return h.selector_features(desc)[0]
 
 
-def label(h, P, maxit=20, gmres_maxit=150):
-    """(times, ok) of every rung of RUNGS on one instance, escalation off."""
-    import torch
+def label_chunk(h, descs, maxit=20, gmres_maxit=60, log=None):
+    """(T, OK, TF) for instances already on the device: per rung of RUNGS the
+    solve time (ms: conversion + factorization + refinement, event-timed on
+    the batch worker that ran it) and whether it certified at that rung, and
+    the FP32 factorization time (conversion + factorization of the fp32/ir
+    solve)."""
     from . import lsq
-    desc, keep = _device_problem(P)
-    times, ok = [], []
-    for prec, solver in RUNGS:
+    n = len(descs)
+    T = np.full((n, len(RUNGS)), np.inf)
+    OK = np.zeros((n, len(RUNGS)), bool)
+    TF = np.full(n, np.inf)
+    h.set_batch_mode("workers")
+    for j, (prec, solver) in enumerate(RUNGS):
         opts = lsq.default_opts(prec=prec, solver=solver, escalate=0, maxit=maxit,
                                 gmres_maxit=gmres_maxit)
+        t0 = time.perf_counter()
+        rc, res = h.lsq_solve_batched(descs, opts)
+        for i, r in enumerate(res):
+            T[i, j] = r.ms_convert + r.ms_factor + r.ms_refine
+            OK[i, j] = (r.info == 0 and r.berr_max <= 1e-14 and lsq.PREC_NAME[r.prec_used] == prec
+                        and lsq.SOLVER_NAME[r.solver_used] == solver)
+            if (prec, solver) == (FEATURE_PREC, "ir"):
+                TF[i] = r.ms_convert + r.ms_factor
+        if log:
+            log(f"  rung {prec}/{solver}: {int(OK[:, j].sum())}/{n} certified, "
+                f"{time.perf_counter() - t0:.1f} s")
+    h.set_batch_mode("persistent")
+    return T, OK, TF
+
+
+TIMES = {}   # mode -> [seconds, certified] summed over the chunks of the last collect
+
+
+def time_modes(h, descs, weights, log=None):
+    """Wall-clock seconds and certified counts of one pass over descs on the
+    batch workers for AUTO (selector weights set), the plain ladder (FP32
+    classical IR, then GMRES-IR, then FP64 direct) and FP64 direct."""
+    import torch
+    from . import lsq
+    h.set_batch_mode("workers")
+    modes = {"auto": lsq.default_opts(prec="auto", solver="auto", escalate=1),
+             "ladder": lsq.default_opts(prec="fp32", solver="ir", escalate=1),
+             "fp64": lsq.default_opts(prec="fp64", solver="direct")}
+    out = {}
+    for name, opts in modes.items():
+        h.selector_set(weights if name == "auto" else None)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc, res = h.lsq_solve_batched([desc], opts)
+        rc, res = h.lsq_solve_batched(descs, opts)
+        torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        r = res[0]
-        good = rc == 0 and r.info == 0 and r.berr_max <= 1e-14 and \
-            lsq.PREC_NAME[r.prec_used] == prec and lsq.SOLVER_NAME[r.solver_used] == solver
-        times.append(dt)
-        ok.append(bool(good))
-    return np.array(times), np.array(ok)
+        ok = sum(1 for r in res if r.info == 0 and r.berr_max <= 1e-14)
+        out[name] = (dt, ok)
+        if log:
+            log(f"  {name}: {dt:.2f} s, {ok}/{len(descs)} certified")
+    h.selector_set(None)
+    h.set_batch_mode("persistent")
+    return out
 
 
-def make_dataset(h, count, seed, kappa_max=1e12, log=None):
-    from . import workloads as wl
-    X, T, OK = [], [], []
-    for i, P in enumerate(wl.batch_instances(seed=seed, count=count, kappa_max=kappa_max)):
-        X.append(features(h, P))
-        t, ok = label(h, P)
-        T.append(t)
-        OK.append(ok)
-        if log and (i + 1) % 100 == 0:
-            log(f"labelled {i + 1}/{count}")
-    return np.array(X), np.array(T), np.array(OK)
+def collect(h, count, seed, kappa_max=1e12, chunk=2000, out=None, log=None, procs=12, weights=None):
+    """Features and labels of `count` instances of the batch recipe.  h is a
+    Handle, or a callable returning one: it is then called after the generator
+    processes have started, so that they are not started from a process that
+    already holds the GPU."""
+    import torch
+    X, T, OK, TF, META = [], [], [], [], []
+    TIMES.clear()
+    done = 0
+    stream = instance_stream(count, seed, kappa_max, chunk, procs)
+    first = next(stream, None)
+    if callable(h):
+        h = h()
+
+    def chunks():
+        if first is not None:
+            yield first
+            yield from stream
+    for probs in chunks():
+        t0 = time.perf_counter()
+        up = [_device_problem(P) for P in probs]
+        descs = [d for d, _ in up]
+        torch.cuda.synchronize()
+        X.extend(h.selector_features(d)[0] for d in descs)
+        if log:
+            log(f"chunk at {done}: {len(probs)} instances on the device, features in "
+                f"{time.perf_counter() - t0:.1f} s")
+        if weights is not None:
+            for name, (dt, okc) in time_modes(h, descs, weights, log).items():
+                acc = TIMES.setdefault(name, [0.0, 0])
+                acc[0] += dt
+                acc[1] += okc
+        t, ok, tf = label_chunk(h, descs, log=log)
+        T.append(t); OK.append(ok); TF.append(tf)
+        META.extend([(0 if P.kind == "lse" else 1, *P.shape,
+                      getattr(P, "kappa_A", None) or getattr(P, "kappa_W", None) or 0.0,
+                      getattr(P, "kappa_B", None) or getattr(P, "kappa_V", None) or 0.0)
+                     for P in probs])
+        done += len(probs)
+        del up, descs
+        torch.cuda.empty_cache()
+        if out:
+            np.savez(out, X=np.array(X, np.float32), T=np.concatenate(T), OK=np.concatenate(OK),
+                     TF=np.concatenate(TF), META=np.array(META, float))
+        if log:
+            log(f"labelled {done}/{count}")
+    return (np.array(X, np.float32), np.concatenate(T), np.concatenate(OK), np.concatenate(TF),
+            np.array(META, float))
 
 
-def targets(T, OK):
-    """Fastest certified rung per instance -> (precision class, solver class);
-    FP64 direct counts as the solver class IR.  Instances that no rung
-    certified are dropped."""
+def auto_cost(T, TF):
+    """AUTO's cost of starting at each rung: the features come from the FP32
+    factorization, which the FP32 rungs keep and every other rung pays on top
+    of its own solve."""
+    return np.where(REUSES_FEATURE_FACTORS[None, :], T, T + TF[:, None])
+
+
+def targets(T, OK, TF=None):
+    """Cheapest certified rung per instance (AUTO's cost when TF is given, the
+    rung's own time otherwise) -> (precision class, solver class); FP64 direct
+    counts as the solver class IR.  Instances that no rung certified are
+    dropped."""
+    C = auto_cost(T, TF) if TF is not None else T
     keep, yp, ys = [], [], []
-    for i in range(len(T)):
+    for i in range(len(C)):
         if not OK[i].any():
             continue
-        j = int(np.argmin(np.where(OK[i], T[i], np.inf)))
+        j = int(np.argmin(np.where(OK[i], C[i], np.inf)))
         prec, solver = RUNGS[j]
         keep.append(i)
         yp.append(PREC_CLASSES.index(prec))
@@ -203,43 +335,63 @@ def targets(T, OK):
     return np.array(keep, int), np.array(yp, int), np.array(ys, int)
 
 
+def rung_of(pc, sc):
+    """Index in RUNGS of the rung the selector's classes start at."""
+    prec = PREC_CLASSES[pc]
+    return RUNGS.index((prec, "direct" if prec == "fp64" else SOLVER_CLASSES[sc]))
+
+
+def fit(data, out=WEIGHTS_PATH, epochs=600, seed=0, meta=None):
+    d = np.load(data)
+    X, T, OK, TF = d["X"], d["T"], d["OK"], d["TF"]
+    keep, yp, ys = targets(T, OK, TF)
+    P, hist = train(X[keep], yp, ys, epochs=epochs, seed=seed)
+    pp, ps = predict(P, X[keep])
+    acc = float(np.mean((pp == yp) & (ps == ys)))
+    counts = {f"{PREC_CLASSES[p]}/{SOLVER_CLASSES[s]}": int(np.sum((yp == p) & (ys == s)))
+              for p in range(NP) for s in range(2)}
+    save(P, out, dict(meta or {}, trained_on=int(len(keep)), train_joint_accuracy=acc,
+                      final_loss=hist[-1], label_counts=counts))
+    return {"trained_on": int(len(keep)), "joint_accuracy": acc, "label_counts": counts}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("action", choices=["train", "evaluate"])
+    ap.add_argument("action", choices=["collect", "fit", "evaluate"])
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--kappa-max", type=float, default=1e12)
-    ap.add_argument("--out", default=WEIGHTS_PATH)
-    ap.add_argument("--dump", default=None, help="save features/labels (.npz) here")
+    ap.add_argument("--chunk", type=int, default=2000)
+    ap.add_argument("--data", default=None, help="features/labels (.npz)")
+    ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
-    sys.path.insert(0, os.path.dirname(HERE))
-    from . import lsq
-    h = lsq.Handle(load_selector=False)
     log = lambda s: print(s, flush=True)  # noqa: E731
-    if a.action == "train":
-        X, T, OK = make_dataset(h, a.count, a.seed, a.kappa_max, log)
-        if a.dump:
-            np.savez(a.dump, X=X, T=T, OK=OK)
-        keep, yp, ys = targets(T, OK)
-        P, hist = train(X[keep], yp, ys)
-        pp, ps = predict(P, X[keep])
-        acc = float(np.mean((pp == yp) & (ps == ys)))
-        save(P, a.out, {"count": a.count, "seed": a.seed, "kappa_max": a.kappa_max,
-                        "train_joint_accuracy": acc, "final_loss": hist[-1]})
-        print(json.dumps({"trained_on": int(len(keep)), "joint_accuracy": acc,
-                          "label_counts": {f"{PREC_CLASSES[p]}/{SOLVER_CLASSES[s]}": int(np.sum((yp == p) & (ys == s)))
-                                           for p in range(NP) for s in range(2)}}))
-    else:
-        P = unpack(load(a.out))
-        X, T, OK = make_dataset(h, a.count, a.seed, a.kappa_max, log)
-        keep, yp, ys = targets(T, OK)
-        pp, ps = predict(P, X[keep])
-        def rung_of(c, sv):
-            prec = PREC_CLASSES[max(1, c)]
-            return RUNGS.index((prec, "direct" if prec == "fp64" else SOLVER_CLASSES[sv]))
-        first_ok = float(np.mean([OK[i][rung_of(pp[j], ps[j])] for j, i in enumerate(keep)]))
-        print(json.dumps({"evaluated": int(len(keep)), "first_pick_certifies": first_ok,
-                          "joint_accuracy": float(np.mean((pp == yp) & (ps == ys)))}))
+    if a.action == "fit":
+        print(json.dumps(fit(a.data, a.out or WEIGHTS_PATH,
+                             meta={"data": os.path.basename(a.data)})))
+        return
+    from . import lsq
+    h = lambda: lsq.Handle(load_selector=False)  # noqa: E731
+    if a.action == "collect":
+        collect(h, a.count, a.seed, a.kappa_max, a.chunk, a.out, log)
+        return
+    # evaluate: the selector's first pick on a fresh stream, against the
+    # labels of the same instances
+    wts = load(a.out or WEIGHTS_PATH)
+    P = unpack(wts)
+    X, T, OK, TF, _ = collect(h, a.count, a.seed, a.kappa_max, a.chunk, a.data, log, weights=wts)
+    keep, yp, ys = targets(T, OK, TF)
+    pp, ps = predict(P, X[keep])
+    C = auto_cost(T, TF)
+    picks = [rung_of(pp[j], ps[j]) for j in range(len(keep))]
+    first_ok = float(np.mean([OK[i][picks[j]] for j, i in enumerate(keep)]))
+    print(json.dumps({"instances": a.count, "wall_s": {k: round(v[0], 3) for k, v in TIMES.items()},
+                      "certified": {k: v[1] for k, v in TIMES.items()},
+                      "evaluated": int(len(keep)), "first_pick_certifies": first_ok,
+                      "joint_accuracy": float(np.mean((pp == yp) & (ps == ys))),
+                      "regret_ms_when_certified": float(np.mean(
+                          [C[i][picks[j]] - C[i][rung_of(yp[j], ys[j])]
+                           for j, i in enumerate(keep) if OK[i][picks[j]]]))}))
 
 
 if __name__ == "__main__":

@@ -186,7 +186,7 @@ def config3(seed: int = 3, n: int = 4096, m: int = 1024, p: int = 4096,
 
 
 def batch_instances(seed: int = 4, count: int = 2000, kappa_max: float = 1e8,
-                    m_range=(64, 1024)) -> Iterator[object]:
+                    m_range=(64, 1024), start: int = 0) -> Iterator[object]:
     """Mixed LSE/GLS instances of uneven size.
 
     LSE: m ~ U[m_lo, m_hi], n ~ U[32, m/2], p ~ U[4, n/4].
@@ -195,11 +195,11 @@ def batch_instances(seed: int = 4, count: int = 2000, kappa_max: float = 1e8,
     Both matrices of an instance are U diag(s) V^T with an independent
     kappa ~ log-uniform[1e1, kappa_max]; right-hand sides are N(0,1).
     Instance i draws from SeedSequence(seed).spawn(count)[i], so any
-    instance can be regenerated on its own.
+    instance can be regenerated on its own; `start` skips the first ones.
     """
     children = np.random.SeedSequence(seed).spawn(count)
     lo, hi = m_range
-    for i, ss in enumerate(children):
+    for ss in children[start:]:
         rng = np.random.default_rng(ss)
         is_lse = rng.random() < 0.5
         big = int(rng.integers(lo, hi + 1))

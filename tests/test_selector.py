@@ -50,13 +50,41 @@ def test_training_separates_a_synthetic_rule():
     assert np.mean(pp == yp) > 0.9 and np.mean(ps == ys) > 0.98
 
 
-def test_targets_pick_fastest_certified_rung():
-    T = np.array([[1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0], [1.0, 2.0, 3.0, 4.0, 0.5, 6.0, 7.0],
-                  [1, 1, 1, 1, 1, 1, 1.0], [5, 5, 5, 5, 5, 5, 0.1]])
-    OK = np.array([[False, True, True, False, True, True, True], [True] * 7, [False] * 7,
-                   [True] * 7])
+def test_targets_pick_cheapest_certified_rung_for_auto():
+    # RUNGS: fp8 ir/gmres, bf16 ir/gmres, fp16 ir/gmres, fp32 ir/gmres, fp64 direct
+    assert [r for r in sel.RUNGS if r[0] == sel.FEATURE_PREC] == [("fp32", "ir"), ("fp32", "gmres")]
+    T = np.array([[1.0, 2, 3, 4, 5, 6, 7, 8, 9],
+                  [1.0, 2, 3, 4, 5, 6, 7, 8, 0.5],
+                  [1.0] * 9,
+                  [9.0, 9, 9, 9, 9, 9, 6, 9, 2]])
+    OK = np.array([[False, False, True, False, True, True, True, True, True], [True] * 9, [False] * 9,
+                   [True] * 9])
+    TF = np.array([10.0, 0.1, 1.0, 5.0])
+    # own times: row 0 -> bf16/ir (3), row 1 -> fp64 (0.5), row 3 -> fp64 (2)
     keep, yp, ys = sel.targets(T, OK)
     assert list(keep) == [0, 1, 3]
-    assert (sel.PREC_CLASSES[yp[0]], sel.SOLVER_CLASSES[ys[0]]) == ("bf16", "gmres")
-    assert (sel.PREC_CLASSES[yp[1]], sel.SOLVER_CLASSES[ys[1]]) == ("fp32", "ir")
-    assert sel.PREC_CLASSES[yp[2]] == "fp64"
+    assert [(sel.PREC_CLASSES[p], sel.SOLVER_CLASSES[s]) for p, s in zip(yp, ys)] == \
+        [("bf16", "ir"), ("fp64", "ir"), ("fp64", "ir")]
+    # AUTO pays the FP32 factorization (TF) on top of every non-FP32 rung:
+    # row 0: bf16/ir 13 vs fp32/ir 7 -> fp32/ir; row 1: fp8/ir 1.1 vs fp64 0.6 -> fp64;
+    # row 3: fp64 7 vs fp32/ir 6 -> fp32/ir
+    C = sel.auto_cost(T, TF)
+    assert C[0, 2] == 13.0 and C[0, 6] == 7.0 and C[3, 8] == 7.0 and C[3, 6] == 6.0
+    keep, yp, ys = sel.targets(T, OK, TF)
+    assert list(keep) == [0, 1, 3]
+    assert [(sel.PREC_CLASSES[p], sel.SOLVER_CLASSES[s]) for p, s in zip(yp, ys)] == \
+        [("fp32", "ir"), ("fp64", "ir"), ("fp32", "ir")]
+    assert [sel.rung_of(p, s) for p, s in zip(yp, ys)] == [6, 8, 6]
+
+
+def test_instance_stream_matches_the_generator():
+    from paper_2406_16499_amd import workloads as wl
+    chunks = list(sel.instance_stream(7, seed=11, kappa_max=1e12, chunk=4, procs=2, sub=2))
+    assert [len(c) for c in chunks] == [4, 3]
+    ref = list(wl.batch_instances(seed=11, count=7, kappa_max=1e12))
+    got = [P for c in chunks for P in c]
+    for P, Q in zip(got, ref):
+        assert P.kind == Q.kind and P.shape == Q.shape
+        a, b = (P.A, Q.A) if P.kind == "lse" else (P.W, Q.W)
+        # the same instance up to the rounding of multi- vs single-threaded BLAS
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * np.max(np.abs(b)))

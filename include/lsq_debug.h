@@ -151,6 +151,12 @@ int lsq_dbg_history(lsq_handle h, int max_steps, double* berr, int* rung);
    NaN ratio. */
 int lsq_dbg_batch_route(lsq_handle h, double ratio);
 
+/* Share of the compute units on which the concurrent FP64 rung of the
+   persistent batch starts beside the FP32 launch (default 0.25; the FP32
+   launch takes the rest, and every unit joins the FP64 rung once the FP32
+   launch ends).  Returns -2 outside (0, 1). */
+int lsq_dbg_batch_split(lsq_handle h, double fp64_share);
+
 /* Schedule of the last persistent batched call (lsq_solve_batched and the
    typed variants, persistent modes), from the device wall clock: for each of
    the first `count` problems of that call, out[6 i .. 6 i + 5] = start,

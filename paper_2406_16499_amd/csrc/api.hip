@@ -262,6 +262,11 @@ struct lsq_handle_st {
   int batch_mode = LSQ_BATCH_AUTO;
   double esc_wait_ms = 50.0;                    // bound on an FP64 consumer's wait (concurrent batch)
   double batch_route = kBatchRoute;             // diagonal-ratio route of the persistent FP32 rung
+  double batch_fp64_share = 0.25;               // compute units the concurrent FP64 rung starts on
+  // tuned (route, FP64 share) per size bucket: the entry with the smallest
+  // bound >= the batch's largest dimension applies; none: the values above
+  struct BatchTune { int max_dim; double route, share; };
+  std::vector<BatchTune> batch_tuning;
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
   std::string last_error;
@@ -1389,6 +1394,20 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     }
   }
   if (cur.empty()) return rest;
+  double route = h->batch_route, fp64_share = h->batch_fp64_share;
+  {
+    int dim = 0;
+    for (int q : cur) dim = std::max(dim, std::max(hp[q].m, std::max(hp[q].n, hp[q].p)));
+    int best = -1;
+    for (int e = 0; e < (int)h->batch_tuning.size(); ++e)
+      if (h->batch_tuning[e].max_dim >= dim &&
+          (best < 0 || h->batch_tuning[e].max_dim < h->batch_tuning[best].max_dim))
+        best = e;
+    if (best >= 0) {
+      route = h->batch_tuning[best].route;
+      fp64_share = h->batch_tuning[best].share;
+    }
+  }
   const int max_grid = std::max(batch_blocks_per_cu(4), batch_blocks_per_cu(8)) * h->num_cu;
   const int grid = std::min((int)cur.size(), max_grid);
   w->arena.reset();
@@ -1459,10 +1478,10 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     const int n = (int)cur.size();
     EscQueue* q = static_cast<EscQueue*>(ctx.ws->alloc(esc_queue_bytes(count)));
     BatchOut* dout64 = ctx.ws->get<BatchOut>(count);
-    // a quarter of the compute units run the FP64 rung from the start (about
-    // the share of the FP64 work in the mixed batch); the rest join when
-    // the FP32 launch is over
-    const int cu64 = std::max(1, h->num_cu / 4);
+    // a share of the compute units (a quarter by default, about the share of
+    // the FP64 work in the mixed batch) runs the FP64 rung from the start;
+    // the rest join when the FP32 launch is over
+    const int cu64 = std::min(h->num_cu - 1, std::max(1, (int)std::lround(h->num_cu * fp64_share)));
     const int g32 = std::min(batch_blocks_per_cu(4) * (h->num_cu - cu64), n);
     const int g64a = std::min(batch_blocks_per_cu(8) * cu64, n);
     const int g64b = std::min(batch_blocks_per_cu(8) * (h->num_cu - cu64), n);
@@ -1472,7 +1491,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     for (int qq : cur) flops += batch_factor_flops(hp[qq]);
     int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
     batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
-                            o.tol, o.maxit, o.polish, h->batch_route, dout, dout64, flops, h->esc_wait_ms,
+                            o.tol, o.maxit, o.polish, route, dout, dout64, flops, h->esc_wait_ms,
                             started, n / 4);
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
@@ -1510,7 +1529,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     const int tw = prec == LSQ_PREC_FP64 ? 8 : 4;
     const int g = std::min(batch_blocks_per_cu(tw) * h->num_cu, (int)cur.size());
     batch_launch(ctx, tw, dprobs, dorder, (int)cur.size(), dcounter, dws, stride, g, o.tol, o.maxit, o.polish,
-                 !last, h->batch_route, dout, flops);
+                 !last, route, dout, flops);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> failed;
@@ -1687,6 +1706,27 @@ int lsq_dbg_history(lsq_handle h, int max_steps, double* berr, int* rung) {
     }
   }
   return n;
+}
+
+int lsq_batch_tuning(lsq_handle h, int n, const int* max_dim, const double* route,
+                     const double* fp64_share) {
+  if (!h) return -1;
+  if (n < 0 || (n > 0 && (!max_dim || !route || !fp64_share))) return fail(h, -2, "lsq_batch_tuning: bad table");
+  std::vector<lsq_handle_st::BatchTune> t;
+  for (int i = 0; i < n; ++i) {
+    if (max_dim[i] < 1 || !(route[i] >= 0.0) || !(fp64_share[i] > 0.0 && fp64_share[i] < 1.0))
+      return fail(h, -3, "lsq_batch_tuning: entry " + std::to_string(i) + " out of range");
+    t.push_back({max_dim[i], route[i], fp64_share[i]});
+  }
+  h->batch_tuning = std::move(t);
+  return 0;
+}
+
+int lsq_dbg_batch_split(lsq_handle h, double fp64_share) {
+  if (!h) return -1;
+  if (!(fp64_share > 0.0 && fp64_share < 1.0)) return fail(h, -2, "lsq_dbg_batch_split: share outside (0, 1)");
+  h->batch_fp64_share = fp64_share;
+  return 0;
 }
 
 int lsq_dbg_batch_route(lsq_handle h, double ratio) {

@@ -118,6 +118,8 @@ _SIGS = {
     "lsq_dbg_batch_wait": (c_int, [_P, ctypes.c_double]),
     "lsq_dbg_batch_timeline": (c_int, [_P, c_int, _P]),
     "lsq_dbg_batch_route": (c_int, [_P, ctypes.c_double]),
+    "lsq_dbg_batch_split": (c_int, [_P, ctypes.c_double]),
+    "lsq_batch_tuning": (c_int, [_P, c_int, _P, _P, _P]),
     "lsq_dbg_history": (c_int, [_P, c_int, _P, _P]),
     "lsq_dbg_deterministic": (c_int, [_P, c_int]),
     "lsq_dbg_lookahead": (c_int, [_P, c_int]),
@@ -346,7 +348,8 @@ class Factors:
 class Handle:
     """Owns an lsq_handle bound to the current torch device and stream."""
 
-    def __init__(self, device: Optional[int] = None, load_selector: bool = True, lib=None):
+    def __init__(self, device: Optional[int] = None, load_selector: bool = True, lib=None,
+                 load_tuning: bool = True):
         torch = _torch()
         self.lib = lib if lib is not None else load()
         dev = torch.cuda.current_device() if device is None else device
@@ -361,6 +364,11 @@ class Handle:
             from . import selector
             if os.path.exists(selector.WEIGHTS_PATH):
                 self.selector_set(selector.load())
+        if load_tuning:
+            from . import autotune
+            table = autotune.load()
+            if table:
+                self.batch_tuning(table)
 
     def selector_set(self, weights):
         """Install selector weights (LSQ_SELECTOR_WEIGHTS floats) or remove them (None)."""
@@ -500,6 +508,23 @@ class Handle:
             raise RuntimeError(f"lsq_dbg_history = {n}: {self.last_error()}")
         k = min(n, max_steps)
         return berr[:k], rung[:k]
+
+    def batch_tuning(self, entries) -> None:
+        """Install the persistent batch's launch-shape table: entries of
+        (max_dim, route, fp64_share); [] clears it."""
+        n = len(entries)
+        md = np.array([e[0] for e in entries], np.int32)
+        rt = np.array([e[1] for e in entries], np.float64)
+        sh = np.array([e[2] for e in entries], np.float64)
+        rc = self.lib.lsq_batch_tuning(self.h, n, md.ctypes.data_as(c_void_p), rt.ctypes.data_as(c_void_p),
+                                       sh.ctypes.data_as(c_void_p))
+        if rc != 0:
+            raise RuntimeError(f"lsq_batch_tuning = {rc}: {self.last_error()}")
+
+    def dbg_batch_split(self, fp64_share: float) -> None:
+        rc = self.lib.lsq_dbg_batch_split(self.h, float(fp64_share))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_batch_split = {rc}: {self.last_error()}")
 
     def dbg_batch_route(self, ratio: float) -> None:
         rc = self.lib.lsq_dbg_batch_route(self.h, float(ratio))

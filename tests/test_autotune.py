@@ -1,0 +1,44 @@
+"""The batch tuning table: reading it back, and the C-ABI's checks of it
+(positive bucket bounds, non-negative routes, shares inside (0, 1))."""
+import json
+
+import pytest
+
+from paper_2406_16499_amd import autotune
+
+
+def test_load_absent_is_empty(tmp_path):
+    assert autotune.load(str(tmp_path / "none.json")) == []
+
+
+def test_load_roundtrip(tmp_path):
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps({"entries": [
+        {"max_dim": 256, "route": 3e5, "fp64_share": 0.25, "solves_per_s": 1.0},
+        {"max_dim": 1024, "route": 0.0, "fp64_share": 0.1875}]}))
+    assert autotune.load(str(p)) == [(256, 3e5, 0.25), (1024, 0.0, 0.1875)]
+
+
+def test_grid_in_range():
+    assert all(0.0 < s < 1.0 for s in autotune.SHARES)
+    assert all(r >= 0.0 for r in autotune.ROUTES)
+    his = [hi for _, hi in autotune.BUCKETS]
+    assert his == sorted(his) and len(set(his)) == len(his)
+
+
+@pytest.mark.gpu
+def test_table_checks_and_apply():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_16499_amd import lsq
+    h = lsq.Handle(load_selector=False, load_tuning=False)
+    try:
+        h.batch_tuning([(256, 3e5, 0.25), (1024, 1e5, 0.125)])
+        h.batch_tuning([])
+        h.batch_tuning([(1024, 0.0, 0.25), (256, 0.0, 0.25)])     # any order: the smallest cover wins
+        for bad in ([(256, 0.0, 1.5)], [(256, -1.0, 0.25)], [(0, 0.0, 0.25)], [(256, 0.0, 0.0)]):
+            with pytest.raises(RuntimeError):
+                h.batch_tuning(bad)
+    finally:
+        h.close()

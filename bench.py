@@ -20,6 +20,7 @@ Prints one JSON line (the solver runs on one GPU).
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -245,6 +246,11 @@ def batched(args):
             keep.append((t, x, y))
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
+    # the ~8000 tensors of the instances would make every full garbage
+    # collection of the interpreter a ~45 ms pause inside a timed call:
+    # collect once and move them out of the collector's generations
+    gc.collect()
+    gc.freeze()
     h = lsq.Handle()
     h.lib.lsq_set_batch_workers(h.h, args.workers)
 

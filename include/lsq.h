@@ -332,11 +332,14 @@ int lsq_set_batch_mode(lsq_handle handle, int mode);
    with the smallest such bound winning.  route[i] (>= 0, 0 = off) is the
    diagonal-ratio route of the FP32 rung (lsq_dbg_batch_route), fp64_share[i]
    in (0, 1) the share of compute units the concurrent FP64 rung starts on
-   (lsq_dbg_batch_split).  A batch no entry covers uses those two settings.
-   n = 0 clears the table.  Returns -2 for n < 0 or NULL arrays with n > 0, -3
-   for an entry out of range (the table is then unchanged). */
+   (lsq_dbg_batch_split), pre[i] in [0, 8] the number of the longest
+   instances, per work-group of that rung, that it solves in FP64 from the
+   start instead of after an FP32 attempt (lsq_dbg_batch_pre).  A batch no
+   entry covers uses those three settings.  n = 0 clears the table.  Returns
+   -2 for n < 0 or NULL arrays with n > 0, -3 for an entry out of range (the
+   table is then unchanged). */
 int lsq_batch_tuning(lsq_handle handle, int n, const int* max_dim, const double* route,
-                     const double* fp64_share);
+                     const double* fp64_share, const double* pre);
 
 /* Same-type conveniences: every descriptor must carry the matching type. */
 int lse_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,

@@ -157,6 +157,15 @@ int lsq_dbg_batch_route(lsq_handle h, double ratio);
    launch ends).  Returns -2 outside (0, 1). */
 int lsq_dbg_batch_split(lsq_handle h, double fp64_share);
 
+/* Longest instances of the concurrent persistent batch (the head of its
+   longest-first order), per work-group of the FP64 rung, that the rung solves
+   in FP64 from the start (default 0; rounded to a count, at most the batch).
+   The largest instances take about as long in FP32 as in FP64 on one
+   work-group, so one that escalates would put both attempts on the launch's
+   critical path.  Such an instance reports one attempt.  Returns -2 outside
+   [0, 8]. */
+int lsq_dbg_batch_pre(lsq_handle h, double per_wg);
+
 /* Schedule of the last persistent batched call (lsq_solve_batched and the
    typed variants, persistent modes), from the device wall clock: for each of
    the first `count` problems of that call, out[6 i .. 6 i + 5] = start,

@@ -253,6 +253,8 @@ struct Worker {
 // a sweep of the threshold over the 2000-instance batch (1e4 .. 1e7).
 constexpr double kBatchRoute = 3e5;
 
+constexpr double kMaxBatchPre = 8.0;            // bound on the FP64-first instances per FP64 work-group
+
 struct lsq_handle_st {
   int device = 0;
   int num_cu = 256;
@@ -263,9 +265,11 @@ struct lsq_handle_st {
   double esc_wait_ms = 50.0;                    // bound on an FP64 consumer's wait (concurrent batch)
   double batch_route = kBatchRoute;             // diagonal-ratio route of the persistent FP32 rung
   double batch_fp64_share = 0.25;               // compute units the concurrent FP64 rung starts on
-  // tuned (route, FP64 share) per size bucket: the entry with the smallest
-  // bound >= the batch's largest dimension applies; none: the values above
-  struct BatchTune { int max_dim; double route, share; };
+  double batch_pre = 0.0;                       // longest instances sent to FP64 at once, per FP64 work-group
+  // tuned (route, FP64 share, pre) per size bucket: the entry with the
+  // smallest bound >= the batch's largest dimension applies; none: the
+  // values above
+  struct BatchTune { int max_dim; double route, share, pre; };
   std::vector<BatchTune> batch_tuning;
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
@@ -1394,7 +1398,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     }
   }
   if (cur.empty()) return rest;
-  double route = h->batch_route, fp64_share = h->batch_fp64_share;
+  double route = h->batch_route, fp64_share = h->batch_fp64_share, pre_share = h->batch_pre;
   {
     int dim = 0;
     for (int q : cur) dim = std::max(dim, std::max(hp[q].m, std::max(hp[q].n, hp[q].p)));
@@ -1406,6 +1410,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     if (best >= 0) {
       route = h->batch_tuning[best].route;
       fp64_share = h->batch_tuning[best].share;
+      pre_share = h->batch_tuning[best].pre;
     }
   }
   const int max_grid = std::max(batch_blocks_per_cu(4), batch_blocks_per_cu(8)) * h->num_cu;
@@ -1490,19 +1495,36 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     double flops = 0.0;
     for (int qq : cur) flops += batch_factor_flops(hp[qq]);
     int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
+    // the longest instances (the head of the order) that the FP64 rung takes
+    // at once: an FP32 attempt that escalates would put both attempts of one
+    // of them on the launch's critical path
+    const int pre = std::min(n, (int)std::lround(pre_share * g64a));
     batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
                             o.tol, o.maxit, o.polish, route, dout, dout64, flops, h->esc_wait_ms,
-                            started, n / 4);
+                            started, n / 4, pre);
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> pending;
-    for (int qq : cur) {
-      keep_clock(qq, LSQ_PREC_FP32, hout[qq]);
+    for (int i = 0; i < n; ++i) {
+      const int qq = cur[i];
+      if (i >= pre) keep_clock(qq, LSQ_PREC_FP32, hout[qq]);
       if (hout64[qq].info != -1) keep_clock(qq, LSQ_PREC_FP64, hout64[qq]);
     }
-    for (int qq : cur) {
+    for (int i = 0; i < n; ++i) {
+      const int qq = cur[i];
+      if (i < pre) {
+        // no FP32 attempt: the FP64 rung's result, or the FP64 launch below
+        if (hout64[qq].info == -1) {
+          pending.push_back(qq);
+        } else {
+          ++attempts[qq];
+          if (hout64[qq].info == 0) certified(qq, LSQ_PREC_FP64, hout64[qq]);
+          else rest.push_back(todo[qq]);
+        }
+        continue;
+      }
       ++attempts[qq];
       if (hout[qq].info == 0) {
         certified(qq, LSQ_PREC_FP32, hout[qq]);
@@ -1709,16 +1731,25 @@ int lsq_dbg_history(lsq_handle h, int max_steps, double* berr, int* rung) {
 }
 
 int lsq_batch_tuning(lsq_handle h, int n, const int* max_dim, const double* route,
-                     const double* fp64_share) {
+                     const double* fp64_share, const double* pre) {
   if (!h) return -1;
-  if (n < 0 || (n > 0 && (!max_dim || !route || !fp64_share))) return fail(h, -2, "lsq_batch_tuning: bad table");
+  if (n < 0 || (n > 0 && (!max_dim || !route || !fp64_share || !pre)))
+    return fail(h, -2, "lsq_batch_tuning: bad table");
   std::vector<lsq_handle_st::BatchTune> t;
   for (int i = 0; i < n; ++i) {
-    if (max_dim[i] < 1 || !(route[i] >= 0.0) || !(fp64_share[i] > 0.0 && fp64_share[i] < 1.0))
+    if (max_dim[i] < 1 || !(route[i] >= 0.0) || !(fp64_share[i] > 0.0 && fp64_share[i] < 1.0) ||
+        !(pre[i] >= 0.0 && pre[i] <= kMaxBatchPre))
       return fail(h, -3, "lsq_batch_tuning: entry " + std::to_string(i) + " out of range");
-    t.push_back({max_dim[i], route[i], fp64_share[i]});
+    t.push_back({max_dim[i], route[i], fp64_share[i], pre[i]});
   }
   h->batch_tuning = std::move(t);
+  return 0;
+}
+
+int lsq_dbg_batch_pre(lsq_handle h, double per_wg) {
+  if (!h) return -1;
+  if (!(per_wg >= 0.0 && per_wg <= kMaxBatchPre)) return fail(h, -2, "lsq_dbg_batch_pre: outside [0, 8]");
+  h->batch_pre = per_wg;
   return 0;
 }
 

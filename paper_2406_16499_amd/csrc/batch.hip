@@ -164,8 +164,12 @@ struct BLds {
     T vec[kVecs][kBatchMaxDim];      // vectors of the correction solves
   } u;
   static_assert(kVecs * sizeof(float) >= 4 * sizeof(double), "four FP64 vectors fit over the correction vectors");
+  static_assert(sizeof(u) >= (kVecs + kBW) * kBatchMaxDim * sizeof(T), "the block products' scratch fits");
   // FP64 vector k (k < 4) of the residual, over the correction vectors
   __device__ double* dvec(int k) { return reinterpret_cast<double*>(&u.vec[0][0]) + kBatchMaxDim * k; }
+  // kBW x kBatchMaxDim words after the correction vectors (the panel's
+  // space, unused while refining): per-wave partial sums of the block products
+  __device__ T* wscratch() { return &u.vec[0][0] + kVecs * kBatchMaxDim; }
   T red[kBW];
   T vred[2 * (kBW + 1) * NB];        // reductions of the register panel and vector kernels
   double dred[kBW * 6];
@@ -1008,6 +1012,148 @@ __device__ __forceinline__ void wg_trsv_vec(const T* M, int ld, int nn, T* y, bo
   }
 }
 
+// Products with the upper part of the column block F[:, k : k + nc) (ld; rows
+// i <= k + c of column k + c, i < r, r <= kBatchMaxDim): the off-diagonal
+// blocks of the second factorization's triangle in the correction solves.
+// Thread t owns rows 4t .. 4t + 3, which a padded column delivers in one
+// (FP32) or two (FP64) 16-byte loads; the columns go in chunks of 16 (FP32) or
+// 8 (FP64), the next chunk's loads in flight while the current one is used.
+template <typename T>
+struct Rows4 {
+  T v[4];
+};
+template <typename T>
+struct UpperBlock {
+  static constexpr int CB = sizeof(T) == 4 ? 16 : 8;   // two chunks in registers: 128 VGPRs
+  const T* F;
+  int ld, r, k, nc, g0;
+  __amdgpu_buffer_rsrc_t rs;
+  __device__ UpperBlock(const T* F_, int ld_, int r_, int k_, int nc_)
+      : F(F_), ld(ld_), r(r_), k(k_), nc(nc_), g0(4 * (int)threadIdx.x),
+        rs(rsrc(F_ + (size_t)k_ * ld_, (size_t)(nc_ > 0 ? nc_ : 1) * ld_ * sizeof(T))) {}
+  // (chunks past nc load nothing: every offset is out of range)
+  __device__ __forceinline__ void load(int c0, T (&Yv)[CB][4]) const {
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const bool ok = (g0 < r) & (c0 + c < nc) & (g0 <= k + c0 + c);
+      load_rows4(rs, ok, (uint32_t)((g0 + (size_t)(c0 + c) * ld) * sizeof(T)), Yv[c]);
+    }
+  }
+  // element (g0 + e, k + c0 + c) of the upper part, else 0
+  __device__ __forceinline__ T at(const T (&Yv)[CB][4], int c0, int c, int e) const {
+    return (g0 + e <= k + c0 + c) & (g0 + e < r) ? Yv[c][e] : (T)0;
+  }
+};
+
+// Rows 4t .. 4t + 3 of F[:, k : k + nc) h over the upper part (h: LDS,
+// length nc).  No barrier.
+template <typename T>
+__device__ __forceinline__ Rows4<T> wg_upper_gemv_n_impl(const LSQ_GLB T* Fg, int ld, int r, int k, int nc,
+                                                      const LSQ_LDS T* hg) {
+  constexpr int CB = UpperBlock<T>::CB;
+  const LSQ_LDS T* h = uni(hg);
+  const UpperBlock<T> U((const T*)uni(Fg), uni(ld), uni(r), uni(k), uni(nc));
+  Rows4<T> o;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) o.v[e] = 0;
+  auto step = [&](int c0, const T (&Yv)[CB][4]) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const T hc0 = h[c0 + c < U.nc ? c0 + c : 0];
+      const T hc = c0 + c < U.nc ? hc0 : (T)0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o.v[e] += U.at(Yv, c0, c, e) * hc;
+    }
+  };
+  T Ya[CB][4], Yb[CB][4];
+  U.load(0, Ya);
+  for (int c0 = 0; c0 < U.nc; c0 += 2 * CB) {
+    U.load(c0 + CB, Yb);
+    __builtin_amdgcn_sched_barrier(0);
+    step(c0, Ya);
+    U.load(c0 + 2 * CB, Ya);
+    __builtin_amdgcn_sched_barrier(0);
+    if (c0 + CB < U.nc) step(c0 + CB, Yb);
+  }
+  return o;
+}
+
+// out(c) = sum_i F(i, k + c) g(i) over the upper part, c < nc (g, out: LDS;
+// wbuf: LDS scratch of kBW x kBatchMaxDim words).  Each chunk's column sums
+// are reduced over the wave and the four waves' partials meet in wbuf: one
+// barrier at the end, and one after out is written.
+template <typename T>
+__device__ __forceinline__ void wg_upper_gemv_t_impl(const LSQ_GLB T* Fg, int ld, int r, int k, int nc,
+                                                   const LSQ_LDS T* gg, LSQ_LDS T* outg, LSQ_LDS T* wbufg) {
+  constexpr int CB = UpperBlock<T>::CB;
+  const LSQ_LDS T* g = uni(gg);
+  LSQ_LDS T* out = uni(outg);
+  LSQ_LDS T* wbuf = uni(wbufg);
+  const UpperBlock<T> U((const T*)uni(Fg), uni(ld), uni(r), uni(k), uni(nc));
+  const int lane = threadIdx.x & 63, w = uni((int)threadIdx.x >> 6);
+  T gv[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const T v = g[U.g0 + e < U.r ? U.g0 + e : 0];
+    gv[e] = U.g0 + e < U.r ? v : (T)0;
+  }
+  auto step = [&](int c0, const T (&Yv)[CB][4]) {
+    T pz[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+      pz[c] = (U.at(Yv, c0, c, 0) * gv[0] + U.at(Yv, c0, c, 1) * gv[1]) +
+              (U.at(Yv, c0, c, 2) * gv[2] + U.at(Yv, c0, c, 3) * gv[3]);
+    // lanes (64 / CB) c .. (64 / CB) (c + 1) - 1: the wave's sum of column c
+    const T zc = wave_reduce_scatter<T, CB>(pz);
+    constexpr int LPC = 64 / CB;
+    const int c = c0 + lane / LPC;
+    if (lane % LPC == 0 && c < U.nc) wbuf[w * kBatchMaxDim + c] = zc;
+  };
+  T Ya[CB][4], Yb[CB][4];
+  U.load(0, Ya);
+  for (int c0 = 0; c0 < U.nc; c0 += 2 * CB) {
+    U.load(c0 + CB, Yb);
+    __builtin_amdgcn_sched_barrier(0);
+    step(c0, Ya);
+    U.load(c0 + 2 * CB, Ya);
+    __builtin_amdgcn_sched_barrier(0);
+    if (c0 + CB < U.nc) step(c0 + CB, Yb);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < U.nc; c += kBT)
+    out[c] = (wbuf[c] + wbuf[kBatchMaxDim + c]) + (wbuf[2 * kBatchMaxDim + c] + wbuf[3 * kBatchMaxDim + c]);
+  __syncthreads();
+}
+
+// Out-of-line copies for the FP32 kernel (see wg_apply_q_vec_call).
+template <typename T>
+__device__ __noinline__ Rows4<T> wg_upper_gemv_n_call(const LSQ_GLB T* Fg, int ld, int r, int k, int nc,
+                                                     const LSQ_LDS T* hg) {
+  return wg_upper_gemv_n_impl<T>(Fg, ld, r, k, nc, hg);
+}
+template <typename T>
+__device__ __noinline__ void wg_upper_gemv_t_call(const LSQ_GLB T* Fg, int ld, int r, int k, int nc,
+                                                  const LSQ_LDS T* gg, LSQ_LDS T* outg, LSQ_LDS T* wbufg) {
+  wg_upper_gemv_t_impl<T>(Fg, ld, r, k, nc, gg, outg, wbufg);
+}
+template <typename T>
+__device__ __forceinline__ Rows4<T> wg_upper_gemv_n(const T* F, int ld, int r, int k, int nc, const T* h) {
+  const auto Fg = (const LSQ_GLB T*)F;
+  const auto hl = (const LSQ_LDS T*)h;
+  if constexpr (sizeof(T) == 4) return wg_upper_gemv_n_call<T>(Fg, ld, r, k, nc, hl);
+  else return wg_upper_gemv_n_impl<T>(Fg, ld, r, k, nc, hl);
+}
+template <typename T>
+__device__ __forceinline__ void wg_upper_gemv_t(const T* F, int ld, int r, int k, int nc, const T* g, T* out,
+                                                T* wbuf) {
+  const auto Fg = (const LSQ_GLB T*)F;
+  const auto gl = (const LSQ_LDS T*)g;
+  const auto ol = (LSQ_LDS T*)out;
+  const auto wl = (LSQ_LDS T*)wbuf;
+  if constexpr (sizeof(T) == 4) wg_upper_gemv_t_call<T>(Fg, ld, r, k, nc, gl, ol, wl);
+  else wg_upper_gemv_t_impl<T>(Fg, ld, r, k, nc, gl, ol, wl);
+}
+
 // ------------------------------------------------------------- staging --
 // dst = src^T with optional reversals, through an LDS tile: src is sr x sc
 // (column-major, lds), dst is sc x sr (ldd) with dst(x', y') = src(y, x),
@@ -1427,29 +1573,19 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
     wg_trsv_vec(Fa, ldm, k, Qv, true);                    // T11^T q1 = u1
     {
       // w1 - T12 y2 (rows < k) and q2 = w2 - T22 y2 (rows >= k)
-      const auto rs = rsrc(Fa, (size_t)ldm * n * sizeof(T));
-      for (int i = t; i < m; i += kBT) {
-        T acc = 0;
-        for (int jj = 0; jj < p; ++jj) {
-          const int col = k + jj;
-          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * ldm) * sizeof(T)) : kOob) * Y2n[jj];
-        }
-        if (i < k) Y1[i] = Wv[i] - acc - Qv[i];
-        else Qv[i] = Wv[i] - acc;
+      const Rows4<T> ty = wg_upper_gemv_n(Fa, ldm, m, k, p, Y2n);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * t + e;
+        if (i < k) Y1[i] = Wv[i] - ty.v[e] - Qv[i];
+        else if (i < m) Qv[i] = Wv[i] - ty.v[e];
       }
     }
     __syncthreads();
     wg_trsv_vec(Fa, ldm, k, Y1, false);                   // T11 y1 = w1 - q1 - T12 y2
-    // s = [T12; T22]^T q - u2, one column per wave
-    for (int jj = w; jj < p; jj += kBW) {
-      const int col = k + jj, lim = m < col + 1 ? m : col + 1;
-      T s = 0;
-      for (int i = lane; i < lim; i += 64) s += Fa[i + (size_t)col * ldm] * Qv[i];
-      s = wsum(s);
-      if (lane == 0) S[jj] = s - U[p - 1 - jj];
-    }
-    __syncthreads();
-    for (int i = t; i < p; i += kBT) X2[i] = S[p - 1 - i];
+    // s = [T12; T22]^T q - u2
+    wg_upper_gemv_t(Fa, ldm, m, k, p, Qv, S, L.wscratch());
+    for (int i = t; i < p; i += kBT) X2[i] = S[p - 1 - i] - U[i];
     for (int i = t; i < p; i += kBT) Yt[i] = Y2[i];
     for (int i = t; i < k; i += kBT) Yt[p + i] = Y1[k - 1 - i];
     __syncthreads();
@@ -1576,28 +1712,18 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
     wg_trsv_vec(Fv, ldp, k, G, true);                     // A11^T (J g2) = J u2
     {
       // J w2 - A12 J h1 - J g2 (rows < k) and J g1 = J w1 - A22 J h1 (rows >= k)
-      const auto rs = rsrc(Fv, (size_t)ldp * n * sizeof(T));
-      for (int i = t; i < p; i += kBT) {
-        T acc = 0;
-        for (int jj = 0; jj < m; ++jj) {
-          const int col = k + jj;
-          acc += bload<T>(rs, i <= col ? (uint32_t)((i + (size_t)col * ldp) * sizeof(T)) : kOob) * H1t[jj];
-        }
-        if (i < k) H2t[i] = Wt[i] - acc - G[i];
-        else G[i] = Wt[i] - acc;
+      const Rows4<T> ah = wg_upper_gemv_n(Fv, ldp, p, k, m, H1t);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 4 * t + e;
+        if (i < k) H2t[i] = Wt[i] - ah.v[e] - G[i];
+        else if (i < p) G[i] = Wt[i] - ah.v[e];
       }
     }
     __syncthreads();
     wg_trsv_vec(Fv, ldp, k, H2t, false);                  // A11 (J h2) = J w2 - J g2 - A12 J h1
-    // s = Tv[:, k:n]^T (J g), one column per wave
-    for (int jj = w; jj < m; jj += kBW) {
-      const int col = k + jj, lim = p < col + 1 ? p : col + 1;
-      T s = 0;
-      for (int i = lane; i < lim; i += 64) s += Fv[i + (size_t)col * ldp] * G[i];
-      s = wsum(s);
-      if (lane == 0) S[jj] = s;
-    }
-    __syncthreads();
+    // s = Tv[:, k:n]^T (J g)
+    wg_upper_gemv_t(Fv, ldp, p, k, m, G, S, L.wscratch());
     for (int i = t; i < m; i += kBT) X[i] = U[i] - S[m - 1 - i];
     for (int i = t; i < m; i += kBT) Hv[i] = H1[i];
     for (int i = t; i < k; i += kBT) Hv[m + i] = H2t[k - 1 - i];
@@ -1775,6 +1901,24 @@ __global__ __launch_bounds__(kBT, QrCfg<double>::BLOCKS) void k_batch_esc(
   }
 }
 
+// Queue 1 (drained first by the FP64 consumers) preloaded with the first
+// `pre` entries of the order, which the FP32 launch then skips: its counter
+// and the done count start at pre.
+__global__ void k_esc_preload(const int* __restrict__ order, int count, int pre, int* __restrict__ counter,
+                              EscQueue* __restrict__ esc) {
+  int* slot = reinterpret_cast<int*>(esc + 1) + 2 * count;
+  int* ready = slot + count;
+  for (int i = threadIdx.x; i < pre; i += blockDim.x) {
+    slot[i] = order[i];
+    ready[i] = 1;
+  }
+  if (threadIdx.x == 0) {
+    esc->tail[1] = pre;
+    esc->done = pre;
+    *counter = pre;
+  }
+}
+
 }  // namespace
 
 size_t batch_ws_bytes(const BatchProb& P) {
@@ -1831,12 +1975,14 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
                              int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish,
                              double route, BatchOut* out, BatchOut* out64, double flops, double spin_ms,
-                             int* started, int big_count) {
+                             int* started, int big_count, int pre) {
   if (count <= 0 || grid <= 0) return;
   if (!ctx.side || grid64a <= 0) throw std::runtime_error("batch_launch_escalating: no side stream");
-  LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
+  if (pre < 0 || pre > count) throw std::runtime_error("batch_launch_escalating: pre outside [0, count]");
   LSQ_HIP(hipMemsetAsync(q, 0, esc_queue_bytes(count), ctx.stream));
   LSQ_HIP(hipMemsetAsync(out64, 0xff, sizeof(BatchOut) * (size_t)count, ctx.stream));   // info = -1
+  hipLaunchKernelGGL(k_esc_preload, dim3(1), dim3(kBT), 0, ctx.stream, order, count, pre, counter, q);
+  LSQ_LAUNCH_CHECK();
   hipEvent_t ready = ctx_event(ctx, 0), joined = ctx_event(ctx, 1);
   LSQ_HIP(hipEventRecord(ready, ctx.stream));
   const unsigned long long ticks = (unsigned long long)(spin_ms * 1e5);   // 100 MHz wall clock

@@ -341,11 +341,13 @@ size_t esc_queue_bytes(int count);
 // still running leaves, and the host runs what is left.  started (pinned
 // host int, nullable): the consumers count themselves there and the FP32
 // launch waits up to 20 ms for all grid64a of them.  big_count: see
-// EscQueue.  ctx.stream waits for all three launches.
+// EscQueue.  pre: the first pre entries of the order go to the FP64 launch
+// directly (queue 1, before any failure), and the FP32 launch starts after
+// them.  ctx.stream waits for all three launches.
 void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
                              int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish, double route,
                              BatchOut* out, BatchOut* out64, double flops, double spin_ms,
-                             int* started, int big_count);
+                             int* started, int big_count, int pre);
 
 }  // namespace lsq

@@ -16,12 +16,13 @@ def test_load_roundtrip(tmp_path):
     p.write_text(json.dumps({"entries": [
         {"max_dim": 256, "route": 3e5, "fp64_share": 0.25, "solves_per_s": 1.0},
         {"max_dim": 1024, "route": 0.0, "fp64_share": 0.1875}]}))
-    assert autotune.load(str(p)) == [(256, 3e5, 0.25), (1024, 0.0, 0.1875)]
+    assert autotune.load(str(p)) == [(256, 3e5, 0.25, 0.0), (1024, 0.0, 0.1875, 0.0)]
 
 
 def test_grid_in_range():
     assert all(0.0 < s < 1.0 for s in autotune.SHARES)
     assert all(r >= 0.0 for r in autotune.ROUTES)
+    assert all(0.0 <= p <= 8.0 for p in autotune.PRES)
     his = [hi for _, hi in autotune.BUCKETS]
     assert his == sorted(his) and len(set(his)) == len(his)
 
@@ -37,7 +38,9 @@ def test_table_checks_and_apply():
         h.batch_tuning([(256, 3e5, 0.25), (1024, 1e5, 0.125)])
         h.batch_tuning([])
         h.batch_tuning([(1024, 0.0, 0.25), (256, 0.0, 0.25)])     # any order: the smallest cover wins
-        for bad in ([(256, 0.0, 1.5)], [(256, -1.0, 0.25)], [(0, 0.0, 0.25)], [(256, 0.0, 0.0)]):
+        h.batch_tuning([(256, 3e5, 0.25, 1.0)])
+        for bad in ([(256, 0.0, 1.5)], [(256, -1.0, 0.25)], [(0, 0.0, 0.25)], [(256, 0.0, 0.0)],
+                    [(256, 0.0, 0.25, -1.0)], [(256, 0.0, 0.25, 9.0)]):
             with pytest.raises(RuntimeError):
                 h.batch_tuning(bad)
     finally:

@@ -1,6 +1,7 @@
 """The launch shape of the persistent batch: the diagonal-ratio route that
-sends an instance from the FP32 rung straight to FP64, set directly and
-through the size-bucket table, and the FP64 share of the compute units.
+sends an instance from the FP32 rung straight to FP64, the longest instances
+that the FP64 rung takes from the start, both set directly and through the
+size-bucket table, and the FP64 share of the compute units.
 Every setting must certify every instance against the oracle; only the rung
 that solves an instance may change."""
 import sys
@@ -102,6 +103,75 @@ def test_tuning_table_overrides_the_route_for_its_bucket(h, batch):
     finally:
         h.batch_tuning([])
         h.dbg_batch_route(3e5)
+
+
+def _work(P):
+    # the longest-first order of the batched entry points (factorization flops)
+    if P.kind == "lse":
+        m, n, p = P.shape
+        return 2 * m * n * n + 4 * m * n * p + 2 * n * p * p
+    n, m, p = P.shape
+    return 2 * n * m * m + 4 * n * m * p + 2 * p * n * n
+
+
+@pytest.mark.parametrize("per_wg,count", [(0.25, 6), (8.0, 24)])
+def test_pre_sends_the_longest_instances_to_fp64(h, batch, per_wg, count):
+    # share 1/4 of 256 compute units: 64 FP64 work-groups, capped at the 24
+    # instances, so per_wg x 24 instances (rounded) go to FP64 at once
+    note(f"pre {per_wg}: {count} of 24 instances FP64 from the start")
+    probs = batch[0]
+    longest = set(sorted(range(len(probs)), key=lambda i: -_work(probs[i]))[:count])
+    h.dbg_batch_route(0.0)
+    h.dbg_batch_pre(per_wg)
+    try:
+        rungs = _solve_check(h, batch)
+    finally:
+        h.dbg_batch_pre(0.0)
+        h.dbg_batch_route(3e5)
+    for i, r in enumerate(rungs):
+        assert r == (("fp64", 1) if i in longest else ("fp32", 1)), (i, r)
+
+
+def test_tuning_table_sets_pre_for_its_bucket(h, batch):
+    note("table: bucket <= 300 with pre 0.25")
+    probs = batch[0]
+    longest = set(sorted(range(len(probs)), key=lambda i: -_work(probs[i]))[:6])
+    try:
+        h.batch_tuning([(300, 0.0, 0.25, 0.25)])
+        rungs = _solve_check(h, batch)
+    finally:
+        h.batch_tuning([])
+    for i, r in enumerate(rungs):
+        assert r == (("fp64", 1) if i in longest else ("fp32", 1)), (i, r)
+
+
+def test_pre_with_escalations(h):
+    # FP64-first instances and FP32 failures share the FP64 rung's queues
+    note("pre 0.25 with escalations, 20 instances kappa<=1e12")
+    probs = list(wl.batch_instances(seed=85, count=20, kappa_max=1e12, m_range=(64, 300)))
+    keep, descs = [], []
+    for P in probs:
+        if P.kind == "lse":
+            t = tuple(lsq.colmajor(a) for a in (P.A, P.B, P.b, P.d))
+            x, y = lsq.empty(P.shape[1]), None
+            descs.append(lsq.make_problem("lse", t, x))
+        else:
+            t = tuple(lsq.colmajor(a) for a in (P.W, P.V, P.d))
+            x, y = lsq.empty(P.shape[1]), lsq.empty(P.shape[2])
+            descs.append(lsq.make_problem("gls", t, x, y))
+        keep.append((t, x, y))
+    longest = set(sorted(range(len(probs)), key=lambda i: -_work(probs[i]))[:5])
+    h.dbg_batch_pre(0.25)
+    try:
+        rungs = _solve_check(h, (probs, keep, descs))
+    finally:
+        h.dbg_batch_pre(0.0)
+    assert any(r == ("fp64", 2) for r in rungs), rungs
+    for i, r in enumerate(rungs):
+        if i in longest:
+            assert r == ("fp64", 1), (i, r)
+        else:
+            assert r in (("fp32", 1), ("fp64", 2)), (i, r)
 
 
 @pytest.mark.parametrize("share", [0.0625, 0.5])

@@ -36,7 +36,6 @@ METRIC = "LSE/GLS solves/s at FP64 backward error <=1e-14: mixed-IR vs plain FP6
 WORKLOAD = "single LSE, A 4096x2048 kappa(A)=1e4 (U diag(s) V^T), B 256x2048 N(0,1), b,d N(0,1), seed 2"
 PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0, "fp16": 2500.0}   # dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                                                     # GB/s
-PEAK_FP32_VECTOR = 157.3                                              # TFLOP/s
 COPY_BYTES = 256 << 20            # calibration copy for the hardware byte counters
 # Kernels whose roofline can be reported, with their bound.  The panel kernel
 # counts the Householder flops of its panel (2 mr jb^2 - 2 jb^3 / 3) against
@@ -285,11 +284,26 @@ def batched(args):
     # persistent launch: FP32 factors and corrections, the instances that do
     # not certify factored again in FP64 inside a second persistent launch
     mixed = lsq.default_opts(prec="fp32", solver="ir", escalate=1)
-    dt, ok, rungs, tim = run(mixed, args.steps, args.warmup, kernel="batch_fp32")
+    # the FP64 rung beside the FP32 launch carries most of the mixed step
+    # under the tuned schedule: its launches are the ones timed
+    dt, ok, rungs, tim = run(mixed, args.steps, args.warmup, kernel="batch_esc")
     sched = schedule_summary(h.dbg_batch_timeline(len(descs)))
     dt64, ok64, _, tim64 = run(lsq.default_opts(prec="fp64", solver="direct"), args.steps,
                                args.warmup, kernel="batch_fp64")
     sched64 = schedule_summary(h.dbg_batch_timeline(len(descs)))
+    # the same mixed batch captured once as a HIP graph and replayed
+    plan = h.batch_plan(descs, mixed)
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    tg = time.perf_counter()
+    okg = 0
+    for _ in range(args.steps):
+        rcg, resg = plan.run()
+        okg += sum(1 for r in resg if r.info == 0 and r.berr_max <= 1e-14)
+    torch.cuda.synchronize()
+    dtg = time.perf_counter() - tg
+    plan.close()
     # per-instance solves on the batch workers (context): the learned selector
     # picks each instance's starting rung
     auto = lsq.default_opts(prec="auto", solver="auto", escalate=1)
@@ -309,12 +323,15 @@ def batched(args):
     roof = None
     if launches > 0 and ms > 0:
         achieved = (flops / launches) / (ms / launches * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR,
-                "traffic": traffic_per_launch("batch_fp32", BATCH_SOURCES), "kernel": "k_batch<float>",
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK["fp64"],
+                "traffic": traffic_per_launch("batch_esc", BATCH_SOURCES),
+                "kernel": "k_batch_esc (the FP64 rung beside the FP32 launch: one launch from the start, "
+                          "one more when the FP32 launch ends)",
                 "launches_per_step": launches / args.steps, "avg_launch_us": 1000.0 * ms / launches,
                 "alg_flops_per_launch": flops / launches,
-                "flops_counted": "Householder flops of the factorizations of the instances in the launch",
+                "flops_counted": "Householder flops of the factorizations of the instances the rung solved, "
+                                 "split evenly over its launches",
                 "source_hash": source_hash(BATCH_SOURCES)}
     line = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -329,6 +346,9 @@ def batched(args):
                         "ms_per_step": 1000.0 * dt64 / args.steps,
                         "avg_launch_us": 1000.0 * tim64[0] / max(tim64[1], 1)},
         "speedup_vs_fp64": value / value64 if value64 > 0 else None,
+        "graph_replay": {"value": okg / dtg, "unit": "solves/s", "ms_per_step": 1000.0 * dtg / args.steps,
+                         "api": "lsq_batch_plan_run (the mixed batch captured once as a HIP graph)",
+                         "certified_fraction": okg / (args.count * args.steps)},
         "schedule": {"mixed": sched, "fp64": sched64},
         "certified_fraction": ok / (args.count * args.steps),
         "rungs_used": rungs,

@@ -286,10 +286,11 @@ typedef struct {
      instances that do not meet tol again with FP64 factors (reported as
      FP64 direct) when opts.escalate is set.  The FP64 rung runs beside the
      FP32 launch: each instance that fails is queued on the device (the
-     longest first) and solved in FP64 by work-groups on a quarter of the
-     compute units while the FP32 launch goes on (the rest join when it ends).
-     LSQ_BATCH_SEQUENTIAL runs the FP64 rung as a second launch after the
-     FP32 one instead.  Instances that are not eligible or still fail
+     longest first) and solved in FP64 by work-groups on a share of the
+     compute units while the FP32 launch goes on (the rest join when it
+     ends); the longest instances may go to that rung from the start (see
+     lsq_batch_tuning), and report one attempt.  LSQ_BATCH_SEQUENTIAL runs the
+     FP64 rung as a second launch after the FP32 one instead.  Instances that are not eligible or still fail
      continue on the batch workers below, with the full ladder.
    - batch workers (LSQ_BATCH_WORKERS, and every other option): the instances
      run concurrently on the handle's batch workers (streams of their own, one
@@ -297,6 +298,36 @@ typedef struct {
      factorization first, each as lse_solve / gls_solve would run it. */
 int lsq_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,
                       const lsq_opts* opts, lsq_result* res);
+
+/* The persistent batch of lsq_solve_batched (opts.prec FP32, solver IR or
+   AUTO, escalate set; concurrent mode) captured once for a fixed problem
+   set, then replayed as one HIP graph.  A plan keeps the descriptors it was
+   created with (the matrices and vectors they point to may change between
+   runs, their sizes and addresses may not), their longest-first order, the
+   launch shape in force at creation (route, FP64 share and FP64-first count
+   of lsq_batch_tuning / the lsq_dbg_batch_* settings) and device buffers of
+   its own; the handle must outlive it, and a plan runs on the handle's
+   stream.  The graph holds the queue reset, the FP64 consumers on the side
+   stream, a bounded device-side wait (at most 20 ms) until they are
+   resident, the FP32 launch and the late consumers; it records no memset.
+   lsq_batch_plan_create captures without running anything: returns -2 for a
+   NULL plan pointer or an empty set, -3 for an invalid descriptor, -4 for
+   invalid options, -5 when the set or the options are not of that form
+   (another precision or solver, no escalation, another batch mode, an
+   instance with m, n or p beyond 1024), 4 on a HIP error.
+   lsq_batch_plan_run replays the graph, reads the results back and solves
+   what no FP64 consumer took with an FP64 launch as lsq_solve_batched would;
+   instances neither rung certifies continue on the batch workers.  `res`
+   (nullable, `count` records in the order of creation) as for
+   lsq_solve_batched; returns the number of instances with info != 0, -1 for
+   a NULL plan.  Runs of plans on one handle must not overlap.
+   lsq_batch_plan_destroy waits for the handle's streams and frees the plan
+   (NULL is a no-op). */
+typedef struct lsq_batch_plan_st* lsq_batch_plan;
+int lsq_batch_plan_create(lsq_handle handle, int count, const lsq_problem* probs,
+                          const lsq_opts* opts, lsq_batch_plan* plan);
+int lsq_batch_plan_run(lsq_batch_plan plan, lsq_result* res);
+int lsq_batch_plan_destroy(lsq_batch_plan plan);
 /* Learned precision / solver selector (used when opts.prec is LSQ_PREC_AUTO
    or opts.solver is LSQ_SOLVER_AUTO; without weights AUTO means FP32 with
    classical IR).  An instance's features come from FP64 norms of its inputs

@@ -91,15 +91,16 @@ int lsq_dbg_bd_apply_graph(lsq_handle h, int type, int prec, int m, int n, int p
                            int lda, const double* B, int ldb, double alpha, double beta,
                            const double* U, double* Y, int k, int* graph_used);
 
-/* Kernel timing.  While enabled, HIP events are recorded on the handle's
- * stream around every launch of the named kernel kind ("panel_final_y",
- * "panel_cholpass", "wy_t", "wy_u", "dual_gemv", and "batch_fp32" /
- * "batch_fp64" for the persistent batched solver, "agg_gemv" for the two
- * reflector-block GEMVs of each block of an aggregated application of Q), and the launch's
- * algorithmic flops and bytes are added up (the step each kernel carries out
- * is the one cited at its launch site: Householder QR panels and updates of
- * Section 4.1, the residual of eq. aug-LSE / eq. aug-GLS; for a batch launch
- * the Householder flops of the instances' factorizations).  NULL or "" disables; an unknown
+/* Kernel timing.  While enabled, HIP events are recorded on the stream of
+ * every launch of the named kernel kind ("panel_final_y", "panel_cholpass",
+ * "wy_t", "wy_u", "dual_gemv", and "batch_fp32" / "batch_fp64" for the
+ * persistent batched solver, "batch_esc" for the launches of its concurrent
+ * FP64 rung, "agg_gemv" for the two reflector-block GEMVs of each block of an
+ * aggregated application of Q) around it, and the launch's algorithmic flops
+ * and bytes are added up (the step each kernel carries out is the one cited
+ * at its launch site: Householder QR panels and updates of Section 4.1, the
+ * residual of eq. aug-LSE / eq. aug-GLS; for a batch launch the Householder
+ * flops of the factorizations of the instances it solved).  NULL or "" disables; an unknown
  * name returns -2.  lsq_dbg_timer_read synchronizes the stream, returns the
  * summed event durations (ms), the launch count and the summed flops and
  * bytes since the last enable or read, and resets those counters.  Any output

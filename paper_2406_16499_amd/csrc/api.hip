@@ -119,7 +119,7 @@ hipEvent_t ctx_event(Ctx& ctx, int i) {
   return pool[i];
 }
 
-void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes) {
+void ktimer_begin_on(Ctx& ctx, int kind, hipStream_t s, double flops, double bytes) {
   KernelTimer* t = ctx.timer;
   if (!t || t->target != kind) return;
   if ((size_t)(2 * t->used + 2) > t->ev.size()) {
@@ -129,15 +129,25 @@ void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes) {
       t->ev.push_back(e);
     }
   }
-  LSQ_HIP(hipEventRecord(t->ev[2 * t->used], ctx.stream));
+  LSQ_HIP(hipEventRecord(t->ev[2 * t->used], s));
   t->flops += flops;
   t->bytes += bytes;
 }
-void ktimer_end(Ctx& ctx, int kind) {
+void ktimer_end_on(Ctx& ctx, int kind, hipStream_t s) {
   KernelTimer* t = ctx.timer;
   if (!t || t->target != kind) return;
-  LSQ_HIP(hipEventRecord(t->ev[2 * t->used + 1], ctx.stream));
+  LSQ_HIP(hipEventRecord(t->ev[2 * t->used + 1], s));
   ++t->used;
+}
+void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes) {
+  ktimer_begin_on(ctx, kind, ctx.stream, flops, bytes);
+}
+void ktimer_end(Ctx& ctx, int kind) { ktimer_end_on(ctx, kind, ctx.stream); }
+void ktimer_add(Ctx& ctx, int kind, double flops, double bytes) {
+  KernelTimer* t = ctx.timer;
+  if (!t || t->target != kind) return;
+  t->flops += flops;
+  t->bytes += bytes;
 }
 }  // namespace lsq
 
@@ -1374,12 +1384,54 @@ int guard(lsq_handle h, const char* fn, const std::function<int()>& body) {
   return guard_w(&h->w, &h->last_error, fn, body);
 }
 
+}  // namespace
+
+// A captured persistent batch (lsq_batch_plan_create): the problem set, its
+// longest-first order, the launch shape taken at capture, device buffers of
+// its own and the instantiated graph.
+struct lsq_batch_plan_st {
+  lsq_handle h = nullptr;
+  std::vector<lsq_problem> probs;
+  std::vector<int> order;
+  lsq_opts opts{};
+  double route = 0.0, fp64_share = 0.0, pre_share = 0.0;
+  BatchProb* dprobs = nullptr;
+  int* dorder = nullptr;
+  int* dcounter = nullptr;
+  int* dstarted = nullptr;
+  BatchOut* dout = nullptr;
+  BatchOut* dout64 = nullptr;
+  EscQueue* q = nullptr;
+  char* dws = nullptr;
+  char* dws64 = nullptr;
+  hipStream_t cap = nullptr;                    // the stream the graph was recorded on
+  hipGraphExec_t exec = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+    for (void* ptr : {(void*)dprobs, (void*)dorder, (void*)dcounter, (void*)dstarted, (void*)dout, (void*)dout64,
+                      (void*)q, (void*)dws, (void*)dws64})
+      if (ptr) (void)hipFree(ptr);
+    dprobs = nullptr; dorder = dcounter = dstarted = nullptr; dout = dout64 = nullptr; q = nullptr;
+    dws = dws64 = nullptr;
+  }
+};
+
+namespace {
+
 // Persistent batched execution of the eligible instances among todo (one
 // work-group per instance): the first rung in first_prec (FP32 or FP64), the
 // failures again in FP64 when escalating.  Writes res for the instances it
 // certifies and returns those left for the worker ladder, longest first.
+// With a plan (concurrent FP32 + FP64 mode only): on its first call the
+// plan's buffers are allocated, the descriptors and the order uploaded and
+// the launch sequence captured as a graph, and nothing runs; on later calls
+// the graph is replayed in place of the launches.
 std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const std::vector<int>& todo,
-                                  const lsq_opts& o, int first_prec, lsq_result* res) {
+                                  const lsq_opts& o, int first_prec, lsq_result* res,
+                                  lsq_batch_plan_st* plan = nullptr) {
   Worker* w = &h->w;
   Ctx& ctx = w->ctx;
   const int count = (int)todo.size();
@@ -1398,8 +1450,17 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     }
   }
   if (cur.empty()) return rest;
+  const bool capture = plan && !plan->exec;
   double route = h->batch_route, fp64_share = h->batch_fp64_share, pre_share = h->batch_pre;
-  {
+  if (capture && !(first_prec == LSQ_PREC_FP32 && o.escalate && ctx.side && h->batch_mode == LSQ_BATCH_AUTO &&
+                   rest.empty()))
+    throw std::runtime_error("batch plan: only the concurrent FP32 + FP64 batch of eligible instances is captured");
+  if (plan && plan->exec) {
+    // the launch shape the graph was captured with
+    route = plan->route;
+    fp64_share = plan->fp64_share;
+    pre_share = plan->pre_share;
+  } else {
     int dim = 0;
     for (int q : cur) dim = std::max(dim, std::max(hp[q].m, std::max(hp[q].n, hp[q].p)));
     int best = -1;
@@ -1416,12 +1477,38 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
   const int max_grid = std::max(batch_blocks_per_cu(4), batch_blocks_per_cu(8)) * h->num_cu;
   const int grid = std::min((int)cur.size(), max_grid);
   w->arena.reset();
-  BatchProb* dprobs = ctx.ws->get<BatchProb>(count);
-  int* dorder = ctx.ws->get<int>(count);
-  int* dcounter = ctx.ws->get<int>(1);
-  BatchOut* dout = ctx.ws->get<BatchOut>(count);
-  char* dws = static_cast<char*>(ctx.ws->alloc(stride * (size_t)grid));
-  LSQ_HIP(hipMemcpyAsync(dprobs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, ctx.stream));
+  BatchProb* dprobs;
+  int* dorder;
+  int* dcounter;
+  BatchOut* dout;
+  char* dws;
+  if (plan) {
+    if (capture) {
+      plan->route = route;
+      plan->fp64_share = fp64_share;
+      plan->pre_share = pre_share;
+      LSQ_HIP(hipMalloc(&plan->dprobs, sizeof(BatchProb) * count));
+      LSQ_HIP(hipMalloc(&plan->dorder, sizeof(int) * count));
+      LSQ_HIP(hipMalloc(&plan->dcounter, sizeof(int)));
+      LSQ_HIP(hipMalloc(&plan->dstarted, sizeof(int)));
+      LSQ_HIP(hipMalloc(&plan->dout, sizeof(BatchOut) * count));
+      LSQ_HIP(hipMalloc(&plan->dws, stride * (size_t)grid));
+      LSQ_HIP(hipMemcpyAsync(plan->dprobs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice,
+                             ctx.stream));
+    }
+    dprobs = plan->dprobs;
+    dorder = plan->dorder;
+    dcounter = plan->dcounter;
+    dout = plan->dout;
+    dws = plan->dws;
+  } else {
+    dprobs = ctx.ws->get<BatchProb>(count);
+    dorder = ctx.ws->get<int>(count);
+    dcounter = ctx.ws->get<int>(1);
+    dout = ctx.ws->get<BatchOut>(count);
+    dws = static_cast<char*>(ctx.ws->alloc(stride * (size_t)grid));
+    LSQ_HIP(hipMemcpyAsync(dprobs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, ctx.stream));
+  }
   std::vector<BatchOut> hout(count);
   std::vector<int> attempts(count, 0);
   int prec = first_prec;
@@ -1481,8 +1568,12 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     // what no consumer took (see batch_launch_escalating) falls through to
     // the FP64 launch below
     const int n = (int)cur.size();
-    EscQueue* q = static_cast<EscQueue*>(ctx.ws->alloc(esc_queue_bytes(count)));
-    BatchOut* dout64 = ctx.ws->get<BatchOut>(count);
+    if (capture) {
+      LSQ_HIP(hipMalloc(&plan->q, esc_queue_bytes(count)));
+      LSQ_HIP(hipMalloc(&plan->dout64, sizeof(BatchOut) * count));
+    }
+    EscQueue* q = plan ? plan->q : static_cast<EscQueue*>(ctx.ws->alloc(esc_queue_bytes(count)));
+    BatchOut* dout64 = plan ? plan->dout64 : ctx.ws->get<BatchOut>(count);
     // a share of the compute units (a quarter by default, about the share of
     // the FP64 work in the mixed batch) runs the FP64 rung from the start;
     // the rest join when the FP32 launch is over
@@ -1490,22 +1581,72 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     const int g32 = std::min(batch_blocks_per_cu(4) * (h->num_cu - cu64), n);
     const int g64a = std::min(batch_blocks_per_cu(8) * cu64, n);
     const int g64b = std::min(batch_blocks_per_cu(8) * (h->num_cu - cu64), n);
-    char* dws64 = static_cast<char*>(ctx.ws->alloc(stride * (size_t)(g64a + g64b)));
-    LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx.stream));
-    double flops = 0.0;
-    for (int qq : cur) flops += batch_factor_flops(hp[qq]);
+    if (capture) LSQ_HIP(hipMalloc(&plan->dws64, stride * (size_t)(g64a + g64b)));
+    char* dws64 = plan ? plan->dws64 : static_cast<char*>(ctx.ws->alloc(stride * (size_t)(g64a + g64b)));
+    if (!plan || capture)
+      LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * n, hipMemcpyHostToDevice, ctx.stream));
     int* started = reinterpret_cast<int*>(ctx.pin + kPinDoubles - 1);   // last pinned slot
     // the longest instances (the head of the order) that the FP64 rung takes
     // at once: an FP32 attempt that escalates would put both attempts of one
     // of them on the launch's critical path
     const int pre = std::min(n, (int)std::lround(pre_share * g64a));
-    batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
-                            o.tol, o.maxit, o.polish, route, dout, dout64, flops, h->esc_wait_ms,
-                            started, n / 4, pre);
+    // the FP32 launch's work for its timer: the instances it factors
+    double flops = 0.0;
+    for (int i = pre; i < n; ++i) flops += batch_factor_flops(hp[cur[i]]);
+    if (capture) {
+      // record the launches on a stream of the plan's own (the handle's
+      // stream may be the legacy default stream, which cannot be captured),
+      // with no timer events inside the graph; replays go to the handle's
+      // stream
+      LSQ_HIP(hipStreamSynchronize(ctx.stream));
+      if (!plan->cap) LSQ_HIP(hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking));
+      const hipStream_t own = ctx.stream;
+      KernelTimer* timer = ctx.timer;
+      ctx.timer = nullptr;
+      ctx.stream = plan->cap;
+      hipGraph_t graph = nullptr;
+      try {
+        LSQ_HIP(hipStreamBeginCapture(ctx.stream, hipStreamCaptureModeThreadLocal));
+        try {
+          batch_capture_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
+                                   o.tol, o.maxit, o.polish, route, dout, dout64, h->esc_wait_ms,
+                                   plan->dstarted, n / 4, pre);
+        } catch (...) {
+          (void)hipStreamEndCapture(ctx.stream, &graph);
+          throw;
+        }
+        LSQ_HIP(hipStreamEndCapture(ctx.stream, &graph));
+      } catch (...) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();                // leave no error behind for the caller's next check
+        ctx.stream = own;
+        ctx.timer = timer;
+        throw;
+      }
+      ctx.stream = own;
+      ctx.timer = timer;
+      const hipError_t ie = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) (void)hipGetLastError();
+      LSQ_HIP(ie);
+      return {};
+    }
+    if (plan) {
+      LSQ_HIP(hipGraphLaunch(plan->exec, ctx.stream));
+    } else {
+      batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
+                              o.tol, o.maxit, o.polish, route, dout, dout64, flops, h->esc_wait_ms,
+                              started, n / 4, pre);
+    }
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
+    // the FP64 rung's work for its timer: the instances its launches solved
+    double flops64 = 0.0;
+    for (int qq : cur)
+      if (hout64[qq].info != -1) flops64 += batch_factor_flops(hp[qq]);
+    ktimer_add(ctx, kKBatchEsc, flops64, 0.0);
     std::vector<int> pending;
     for (int i = 0; i < n; ++i) {
       const int qq = cur[i];
@@ -1542,6 +1683,14 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     }
     cur = pending;
     prec = LSQ_PREC_FP64;
+  }
+  if (plan) {
+    // the plan's order and outputs stay as captured: this launch takes its
+    // own from the arena
+    dorder = ctx.ws->get<int>(count);
+    dcounter = ctx.ws->get<int>(1);
+    dout = ctx.ws->get<BatchOut>(count);
+    dws = static_cast<char*>(ctx.ws->alloc(stride * (size_t)grid));
   }
   for (;;) {
     LSQ_HIP(hipMemcpyAsync(dorder, cur.data(), sizeof(int) * cur.size(), hipMemcpyHostToDevice, ctx.stream));
@@ -2288,6 +2437,97 @@ int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const l
   return nfail.load();
 }
 
+int lsq_batch_plan_create(lsq_handle h, int count, const lsq_problem* probs, const lsq_opts* opts,
+                          lsq_batch_plan* plan_out) {
+  if (!h) return -1;
+  if (!plan_out) return fail(h, -2, "plan pointer is null");
+  *plan_out = nullptr;
+  if (count <= 0 || !probs) return fail(h, -2, "empty problem set");
+  lsq_opts o;
+  lsq_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol >= 0) || o.maxit < 0) return fail(h, -4, "invalid options");
+  if (o.prec != LSQ_PREC_FP32 || !(o.solver == LSQ_SOLVER_IR || o.solver == LSQ_SOLVER_AUTO) || !o.escalate)
+    return fail(h, -5, "a plan captures the FP32 rung with escalation to FP64 (prec FP32, solver IR, escalate 1)");
+  if (h->batch_mode != LSQ_BATCH_AUTO || !h->w.ctx.side)
+    return fail(h, -5, "a plan needs the concurrent persistent batch mode");
+  std::vector<double> work(count);
+  for (int i = 0; i < count; ++i) {
+    const lsq_problem& q = probs[i];
+    std::string why;
+    int bad;
+    if (q.type == LSQ_LSE)
+      bad = lse_check(q.m, q.n, q.p, q.A, q.lda, q.B, q.ldb, q.b, q.d, q.x, &why);
+    else if (q.type == LSQ_GLS)
+      bad = gls_check(q.n, q.m, q.p, q.A, q.lda, q.B, q.ldb, q.d, q.x, q.y, &why);
+    else
+      bad = -1, why = "unknown problem type";
+    if (bad) return fail(h, -3, "instance " + std::to_string(i) + ": " + why);
+    const BatchProb bp{q.type == LSQ_LSE ? 0 : 1, q.m, q.n, q.p, q.A, q.B, q.b, q.d, q.lda, q.ldb, q.x, q.y};
+    if (!batch_eligible(bp))
+      return fail(h, -5, "instance " + std::to_string(i) + " exceeds the persistent kernel's sizes");
+    const double m = q.m, n = q.n, p = q.p;
+    work[i] = q.type == LSQ_LSE ? 2 * m * n * n + 4 * m * n * p + 2 * n * p * p
+                                : 2 * n * m * m + 4 * n * m * p + 2 * p * n * n;
+  }
+  auto plan = std::make_unique<lsq_batch_plan_st>();
+  plan->h = h;
+  plan->probs.assign(probs, probs + count);
+  plan->opts = o;
+  plan->order.resize(count);
+  for (int i = 0; i < count; ++i) plan->order[i] = i;
+  std::stable_sort(plan->order.begin(), plan->order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  const int rc = guard(h, "lsq_batch_plan_create", [&]() -> int {
+    LSQ_HIP(hipSetDevice(h->device));
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
+    (void)batch_persistent(h, plan->probs.data(), plan->order, o, LSQ_PREC_FP32, nullptr, plan.get());
+    LSQ_HIP(hipStreamSynchronize(h->w.stream));
+    return 0;
+  });
+  if (rc != 0) {
+    plan->release();
+    return rc;
+  }
+  *plan_out = plan.release();
+  return 0;
+}
+
+int lsq_batch_plan_run(lsq_batch_plan plan, lsq_result* res) {
+  if (!plan || !plan->h || !plan->exec) return -1;
+  lsq_handle h = plan->h;
+  std::vector<int> rest;
+  const int rc = guard(h, "lsq_batch_plan_run", [&]() -> int {
+    LSQ_HIP(hipSetDevice(h->device));
+    rest = batch_persistent(h, plan->probs.data(), plan->order, plan->opts, LSQ_PREC_FP32, res, plan);
+    return 0;
+  });
+  if (rc != 0 || rest.empty()) return rc;
+  // what neither rung certified goes through the worker ladder, as in
+  // lsq_solve_batched
+  std::vector<lsq_problem> sub;
+  for (int i : rest) sub.push_back(plan->probs[i]);
+  std::vector<lsq_result> subres(sub.size());
+  const int mode = h->batch_mode;
+  h->batch_mode = LSQ_BATCH_WORKERS;
+  const int r2 = lsq_solve_batched(h, (int)sub.size(), sub.data(), &plan->opts, subres.data());
+  h->batch_mode = mode;
+  if (res)
+    for (size_t k = 0; k < rest.size(); ++k) res[rest[k]] = subres[k];
+  return r2;
+}
+
+int lsq_batch_plan_destroy(lsq_batch_plan plan) {
+  if (!plan) return 0;
+  if (plan->h) {
+    (void)hipSetDevice(plan->h->device);
+    (void)hipStreamSynchronize(plan->h->w.stream);
+    if (plan->h->w.ctx.side) (void)hipStreamSynchronize(plan->h->w.ctx.side);
+  }
+  plan->release();
+  delete plan;
+  return 0;
+}
+
 int lsq_selector_set(lsq_handle h, const float* weights, int count) {
   if (!h) return -1;
   if (!weights) {
@@ -2862,7 +3102,8 @@ int lsq_dbg_gls_correction(lsq_handle h, int prec, int n, int m, int p, const do
 
 // ------------------------------------------------------------- timing --
 static const char* const kKernelNames[kKCount] = {"panel_final_y", "panel_cholpass", "wy_t", "wy_u",
-                                                  "dual_gemv", "batch_fp32", "batch_fp64", "agg_gemv"};
+                                                  "dual_gemv", "batch_fp32", "batch_fp64", "agg_gemv",
+                                                  "batch_esc"};
 
 int lsq_dbg_timer_enable(lsq_handle h, const char* kernel) {
   if (!h) return -1;

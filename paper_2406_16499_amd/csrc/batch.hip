@@ -1919,6 +1919,31 @@ __global__ void k_esc_preload(const int* __restrict__ order, int count, int pre,
   }
 }
 
+// n words of p set to v (graph capture records kernels, not memsets).
+__global__ void k_fill_words(unsigned* __restrict__ p, size_t n, unsigned v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Holds the stream until `target` FP64 consumers have counted themselves in
+// *started, or `ticks` of the wall clock pass: the device-side form of the
+// host's wait in batch_launch_escalating, for a captured graph.
+__global__ void k_wait_resident(const int* __restrict__ started, int target, unsigned long long ticks) {
+  if (threadIdx.x != 0) return;
+  const unsigned long long t0 = wall_clock64();
+  while (__hip_atomic_load(started, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target &&
+         wall_clock64() - t0 < ticks)
+    __builtin_amdgcn_s_sleep(8);
+}
+
+void fill_words(hipStream_t s, void* p, size_t bytes, unsigned v) {
+  const size_t n = bytes / 4;
+  if (n == 0) return;
+  const int grid = (int)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_fill_words, dim3(grid), dim3(256), 0, s, static_cast<unsigned*>(p), n, v);
+  LSQ_LAUNCH_CHECK();
+}
+
 }  // namespace
 
 size_t batch_ws_bytes(const BatchProb& P) {
@@ -1989,9 +2014,11 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
   // consumers on the compute units the FP32 grid leaves free, from the start
   LSQ_HIP(hipStreamWaitEvent(ctx.side, ready, 0));
   if (started) __atomic_store_n(started, 0, __ATOMIC_RELEASE);
+  ktimer_begin_on(ctx, kKBatchEsc, ctx.side, 0.0, 0.0);
   hipLaunchKernelGGL(k_batch_esc, dim3(grid64a), dim3(kBT), 0, ctx.side, probs, count, q, ws64,
                      ws_stride, tol, maxit, polish, out64, ticks, started);
   LSQ_LAUNCH_CHECK();
+  ktimer_end_on(ctx, kKBatchEsc, ctx.side);
   LSQ_HIP(hipEventRecord(joined, ctx.side));
   if (started) {
     // the work-groups of two launches are placed in no fixed order: the FP32
@@ -2008,6 +2035,44 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kKBatch32);
   // more consumers once the FP32 launch is over, for what is still queued
+  if (grid64b > 0) {
+    ktimer_begin(ctx, kKBatchEsc, 0.0, 0.0);
+    hipLaunchKernelGGL(k_batch_esc, dim3(grid64b), dim3(kBT), 0, ctx.stream, probs, count, q,
+                       ws64 + (size_t)grid64a * ws_stride, ws_stride, tol, maxit, polish, out64, ticks,
+                       nullptr);
+    LSQ_LAUNCH_CHECK();
+    ktimer_end(ctx, kKBatchEsc);
+  }
+  LSQ_HIP(hipStreamWaitEvent(ctx.stream, joined, 0));
+}
+
+void batch_capture_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count, int* counter,
+                              char* ws, size_t ws_stride, int grid, char* ws64, int grid64a, int grid64b,
+                              EscQueue* q, double tol, int maxit, double polish, double route, BatchOut* out,
+                              BatchOut* out64, double spin_ms, int* started, int big_count, int pre) {
+  if (count <= 0 || grid <= 0) return;
+  if (!ctx.side || grid64a <= 0) throw std::runtime_error("batch_capture_escalating: no side stream");
+  if (pre < 0 || pre > count) throw std::runtime_error("batch_capture_escalating: pre outside [0, count]");
+  fill_words(ctx.stream, q, esc_queue_bytes(count), 0u);
+  fill_words(ctx.stream, out64, sizeof(BatchOut) * (size_t)count, 0xffffffffu);   // info = -1
+  fill_words(ctx.stream, started, sizeof(int), 0u);
+  hipLaunchKernelGGL(k_esc_preload, dim3(1), dim3(kBT), 0, ctx.stream, order, count, pre, counter, q);
+  LSQ_LAUNCH_CHECK();
+  hipEvent_t ready = ctx_event(ctx, 0), joined = ctx_event(ctx, 1);
+  LSQ_HIP(hipEventRecord(ready, ctx.stream));
+  const unsigned long long ticks = (unsigned long long)(spin_ms * 1e5);   // 100 MHz wall clock
+  LSQ_HIP(hipStreamWaitEvent(ctx.side, ready, 0));
+  hipLaunchKernelGGL(k_batch_esc, dim3(grid64a), dim3(kBT), 0, ctx.side, probs, count, q, ws64,
+                     ws_stride, tol, maxit, polish, out64, ticks, started);
+  LSQ_LAUNCH_CHECK();
+  LSQ_HIP(hipEventRecord(joined, ctx.side));
+  // (at most 20 ms, as the host's wait)
+  hipLaunchKernelGGL(k_wait_resident, dim3(1), dim3(64), 0, ctx.stream, started, grid64a,
+                     (unsigned long long)(20.0 * 1e5));
+  LSQ_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                     counter, ws, ws_stride, tol, maxit, polish, 1, route, out, q, big_count);
+  LSQ_LAUNCH_CHECK();
   if (grid64b > 0) {
     hipLaunchKernelGGL(k_batch_esc, dim3(grid64b), dim3(kBT), 0, ctx.stream, probs, count, q,
                        ws64 + (size_t)grid64a * ws_stride, ws_stride, tol, maxit, polish, out64, ticks,

@@ -47,7 +47,7 @@ class Arena {
 // each launch of that kind, with the launch's algorithmic flops and bytes.
 enum KernelKind : int {
   kKPanelFinal = 0, kKPanelCholPass = 1, kKWyT = 2, kKWyU = 3, kKDualGemv = 4, kKBatch32 = 5,
-  kKBatch64 = 6, kKAggGemv = 7, kKCount = 8
+  kKBatch64 = 6, kKAggGemv = 7, kKBatchEsc = 8, kKCount = 9
 };
 struct KernelTimer {
   int target = -1;
@@ -82,6 +82,11 @@ hipEvent_t ctx_event(Ctx& ctx, int i);
 // Brackets one launch of kind `kind`; does nothing unless the timer targets it.
 void ktimer_begin(Ctx& ctx, int kind, double flops, double bytes);
 void ktimer_end(Ctx& ctx, int kind);
+// The same on stream s (a launch on the side stream).
+void ktimer_begin_on(Ctx& ctx, int kind, hipStream_t s, double flops, double bytes);
+void ktimer_end_on(Ctx& ctx, int kind, hipStream_t s);
+// Work of launches of kind `kind` known only once they have run.
+void ktimer_add(Ctx& ctx, int kind, double flops, double bytes);
 
 // ---------------------------------------------- Householder QR engine ----
 // Aggregated compact-WY block over the panels starting at J0 (w columns):
@@ -349,5 +354,14 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
                              int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish, double route,
                              BatchOut* out, BatchOut* out64, double flops, double spin_ms,
                              int* started, int big_count, int pre);
+// The same sequence in a form a stream capture can record: fill kernels
+// instead of memsets, the wait for the grid64a consumers on the device
+// (started: a device int the consumers count themselves in, bounded at
+// 20 ms), no kernel timer.  The FP32 results go to out, the FP64 ones to
+// out64 (info -1: not taken).
+void batch_capture_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count, int* counter,
+                              char* ws, size_t ws_stride, int grid, char* ws64, int grid64a, int grid64b,
+                              EscQueue* q, double tol, int maxit, double polish, double route, BatchOut* out,
+                              BatchOut* out64, double spin_ms, int* started, int big_count, int pre);
 
 }  // namespace lsq

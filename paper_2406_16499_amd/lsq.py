@@ -86,6 +86,10 @@ _SIGS = {
     "lsq_factors_destroy": (c_int, [_P]),
     "lsq_solve_batched": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                   ctypes.POINTER(Result)]),
+    "lsq_batch_plan_create": (c_int, [_P, c_int, ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                                      ctypes.POINTER(c_void_p)]),
+    "lsq_batch_plan_run": (c_int, [_P, ctypes.POINTER(Result)]),
+    "lsq_batch_plan_destroy": (c_int, [_P]),
     "lsq_set_batch_workers": (c_int, [_P, c_int]),
     "lsq_set_batch_mode": (c_int, [_P, c_int]),
     "lsq_selector_set": (c_int, [_P, ctypes.POINTER(c_float), c_int]),
@@ -262,10 +266,10 @@ def _ld(t):
     return max(int(t.stride(1)) if c > 1 else r, 1)
 
 
-# Every live handle and factors object, closed (factors first) by an exit
-# hook that runs before the interpreter tears its modules down: a destructor
-# left to the final garbage collection could otherwise call into the HIP
-# runtime after a profiler or torch has finalized it.
+# Every live handle, factors object and batch plan, closed (factors and plans
+# first) by an exit hook that runs before the interpreter tears its modules
+# down: a destructor left to the final garbage collection could otherwise
+# call into the HIP runtime after a profiler or torch has finalized it.
 _LIVE_HANDLES: "weakref.WeakSet" = weakref.WeakSet()
 _LIVE_FACTORS: "weakref.WeakSet" = weakref.WeakSet()
 
@@ -338,6 +342,41 @@ class Factors:
         if self.f:
             self.handle.lib.lsq_factors_destroy(self.f)
             self.f = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """A captured persistent batch (lsq_batch_plan_create) over a fixed list
+    of descriptors; keeps them (and the caller's tensors, via `keep`) alive."""
+
+    def __init__(self, handle, problems, opts: Optional[Opts] = None, keep=None):
+        self.handle, self._keep = handle, keep
+        self._arr = (Problem * len(problems))(*problems)
+        self.count = len(problems)
+        ptr = c_void_p()
+        rc = handle.lib.lsq_batch_plan_create(handle.h, self.count, self._arr,
+                                              ctypes.byref(opts) if opts is not None else None,
+                                              ctypes.byref(ptr))
+        if rc != 0:
+            raise RuntimeError(f"lsq_batch_plan_create = {rc}: {handle.last_error()}")
+        self.p = ptr
+        _LIVE_FACTORS.add(self)
+
+    def run(self):
+        """Replay; (rc, [Result] in the order of creation)."""
+        res = (Result * self.count)()
+        rc = self.handle.lib.lsq_batch_plan_run(self.p, res)
+        return rc, list(res)
+
+    def close(self):
+        if self.p:
+            self.handle.lib.lsq_batch_plan_destroy(self.p)
+            self.p = None
 
     def __del__(self):
         try:
@@ -479,6 +518,9 @@ class Handle:
               "gls": self.lib.gls_solve_batched}[which]
         rc = fn(self.h, len(problems), arr, ctypes.byref(opts) if opts is not None else None, res)
         return rc, list(res)
+
+    def batch_plan(self, problems, opts: Optional[Opts] = None, keep=None) -> "BatchPlan":
+        return BatchPlan(self, problems, opts, keep)
 
     def set_batch_mode(self, mode: str) -> None:
         """"persistent" (default: one work-group per eligible instance, the

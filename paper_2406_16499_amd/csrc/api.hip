@@ -1562,7 +1562,11 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     BatchOut& c = rung == LSQ_PREC_FP64 ? clk64[q] : clk32[q];
     if (bo.info >= 0) { c.t0 = bo.t0; c.t1 = bo.t1; c.t2 = bo.t2; }
   };
-  if (prec == LSQ_PREC_FP32 && o.escalate && ctx.side && h->batch_mode == LSQ_BATCH_AUTO) {
+  // the diagonal-ratio route scales with the factorization's unit roundoff
+  // (the tuned values are for FP32, u = 2^-24; BF16 has u = 2^-8)
+  const double route_bf16 = route * std::ldexp(1.0, -16);
+  if ((prec == LSQ_PREC_FP32 || prec == LSQ_PREC_BF16) && o.escalate && ctx.side &&
+      h->batch_mode == LSQ_BATCH_AUTO) {
     // FP32 launch with the FP64 rung running beside it: each failure is
     // queued on the device and solved in FP64 while the FP32 launch goes on;
     // what no consumer took (see batch_launch_escalating) falls through to
@@ -1634,9 +1638,10 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     if (plan) {
       LSQ_HIP(hipGraphLaunch(plan->exec, ctx.stream));
     } else {
+      const bool lowp = prec == LSQ_PREC_BF16;
       batch_launch_escalating(ctx, dprobs, dorder, n, dcounter, dws, stride, g32, dws64, g64a, g64b, q,
-                              o.tol, o.maxit, o.polish, route, dout, dout64, flops, h->esc_wait_ms,
-                              started, n / 4, pre);
+                              o.tol, o.maxit, o.polish, lowp ? route_bf16 : route, dout, dout64, flops,
+                              h->esc_wait_ms, started, n / 4, pre, lowp);
     }
     std::vector<BatchOut> hout64(count);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
@@ -1650,7 +1655,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     std::vector<int> pending;
     for (int i = 0; i < n; ++i) {
       const int qq = cur[i];
-      if (i >= pre) keep_clock(qq, LSQ_PREC_FP32, hout[qq]);
+      if (i >= pre) keep_clock(qq, prec, hout[qq]);
       if (hout64[qq].info != -1) keep_clock(qq, LSQ_PREC_FP64, hout64[qq]);
     }
     for (int i = 0; i < n; ++i) {
@@ -1668,7 +1673,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
       }
       ++attempts[qq];
       if (hout[qq].info == 0) {
-        certified(qq, LSQ_PREC_FP32, hout[qq]);
+        certified(qq, prec, hout[qq]);
       } else if (hout64[qq].info == -1) {
         pending.push_back(qq);
       } else {
@@ -1700,7 +1705,7 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     const int tw = prec == LSQ_PREC_FP64 ? 8 : 4;
     const int g = std::min(batch_blocks_per_cu(tw) * h->num_cu, (int)cur.size());
     batch_launch(ctx, tw, dprobs, dorder, (int)cur.size(), dcounter, dws, stride, g, o.tol, o.maxit, o.polish,
-                 !last, route, dout, flops);
+                 !last, prec == LSQ_PREC_BF16 ? route_bf16 : route, dout, flops, prec == LSQ_PREC_BF16);
     LSQ_HIP(hipMemcpyAsync(hout.data(), dout, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     std::vector<int> failed;
@@ -2379,9 +2384,11 @@ int lsq_solve_batched(lsq_handle h, int count, const lsq_problem* probs, const l
   const bool persistent =
       (h->batch_mode == LSQ_BATCH_AUTO || h->batch_mode == LSQ_BATCH_SEQUENTIAL) &&
       (o.solver == LSQ_SOLVER_AUTO || o.solver == LSQ_SOLVER_IR || o.solver == LSQ_SOLVER_DIRECT) &&
-      (o.prec == LSQ_PREC_FP32 || o.prec == LSQ_PREC_FP64 || (o.prec == LSQ_PREC_AUTO && !h->sel_w));
+      (o.prec == LSQ_PREC_FP32 || o.prec == LSQ_PREC_FP64 || o.prec == LSQ_PREC_BF16 ||
+       (o.prec == LSQ_PREC_AUTO && !h->sel_w));
   if (persistent) {
     const int first = (o.prec == LSQ_PREC_FP64 || o.solver == LSQ_SOLVER_DIRECT) ? LSQ_PREC_FP64
+                      : o.prec == LSQ_PREC_BF16                                 ? LSQ_PREC_BF16
                                                                                 : LSQ_PREC_FP32;
     try {
       LSQ_HIP(hipSetDevice(h->device));

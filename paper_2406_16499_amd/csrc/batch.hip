@@ -562,8 +562,15 @@ __device__ __forceinline__ void panel_t(BLds<T>& L, int nbj, int Lr, const T* ta
 // groups of 4 rows starting at a multiple of 4 never cross Lp: the W pass
 // moves such a group with one (FP32) or two (FP64) 16-byte accesses per lane,
 // and so does the update in FP32.
-template <typename T>
+// LP (FP32 storage only): the BF16 factorization.  The two products with the
+// panel take BF16 inputs (rounded to nearest even) with FP32 accumulation: a
+// lane's four rows of two consecutive chunks are the eight K values of one
+// 16 x 16 x 32 BF16 MFMA in the W pass, and its four values of W' the four of
+// one 16 x 16 x 16 BF16 MFMA in the update (A and B take the same lane slots,
+// so the K order is again the lanes' own).  W' = T^T W stays in FP32.
+template <typename T, bool LP = false>
 __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C, int ldc, int nc) {
+  static_assert(!LP || sizeof(T) == 4, "BF16 updates of FP32 storage");
   constexpr int NB = QrCfg<T>::NB, PS = NB + 1, NBB = NB / 16;
   constexpr int KB = sizeof(T) == 4 ? 8 : 4;    // 16-row chunks per batch of loads
   using MF = Mfma<T>;
@@ -623,15 +630,34 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C,
 #pragma unroll
           for (int b = 0; b < NBB; ++b) yv[u][t][b] = Ys[(16 * ch + krow(t)) * PS + 16 * b + lc];
       }
+      if constexpr (LP) {
+        static_assert(KB % 2 == 0, "chunk pairs");
 #pragma unroll
-      for (int u = 0; u < KB; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int u = 0; u < KB; u += 2)
 #pragma unroll
           for (int b = 0; b < NBB; ++b) {
-            if (u & 1) acc2[b] = MF::mma(yv[u][t][b], cv[u][t], acc2[b]);
-            else acc[b] = MF::mma(yv[u][t][b], cv[u][t], acc[b]);
+            bf16x8 av, bv;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              av[t] = (__bf16)(float)yv[u][t][b];
+              av[4 + t] = (__bf16)(float)yv[u + 1][t][b];
+              bv[t] = (__bf16)(float)cv[u][t];
+              bv[4 + t] = (__bf16)(float)cv[u + 1][t];
+            }
+            if ((u >> 1) & 1) acc2[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc2[b], 0, 0, 0);
+            else acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
           }
+      } else {
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int b = 0; b < NBB; ++b) {
+              if (u & 1) acc2[b] = MF::mma(yv[u][t][b], cv[u][t], acc2[b]);
+              else acc[b] = MF::mma(yv[u][t][b], cv[u][t], acc[b]);
+            }
+      }
     };
     {
       // (the scheduling barriers keep each batch's loads ahead of the
@@ -694,14 +720,26 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C,
 #pragma unroll
       for (int u = 0; u < KB; ++u) {                  // (chunks past the last one are not stored)
 #pragma unroll
-        for (int b = 0; b < NBB; ++b)
+        for (int b = 0; b < NBB; ++b) {
+          if constexpr (LP) {
+            bf16x4 av, bv;
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            // FP32: (-Y) W'; FP64: W'^T (-Y)^T, the same K order (wp[b][t]
-            // of lane l is W' row 16 b + drow(l, t) = 16 b + 4 t + l / 16)
-            if constexpr (sizeof(T) == 4) d[u] = MF::mma(-yv[u][b][t], wp[b][t], d[u]);
-            else d[u] = MF::mma(wp[b][t], -yv[u][b][t], d[u]);
+            for (int t = 0; t < 4; ++t) {
+              av[t] = (__bf16)(float)-yv[u][b][t];
+              bv[t] = (__bf16)(float)wp[b][t];
+            }
+            d[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, av),
+                                                             __builtin_bit_cast(s16x4, bv), d[u], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              // FP32: (-Y) W'; FP64: W'^T (-Y)^T, the same K order (wp[b][t]
+              // of lane l is W' row 16 b + drow(l, t) = 16 b + 4 t + l / 16)
+              if constexpr (sizeof(T) == 4) d[u] = MF::mma(-yv[u][b][t], wp[b][t], d[u]);
+              else d[u] = MF::mma(wp[b][t], -yv[u][b][t], d[u]);
+            }
           }
+        }
         if constexpr (sizeof(T) == 4) {
           const int g = 16 * (kb + u) + 4 * lg;
           bstore4(d[u], rs, (g < Lr && cok) ? (uint32_t)((g + (size_t)col * ldc) * 4) : kOob);
@@ -733,7 +771,7 @@ __device__ __forceinline__ void apply_block_qt(BLds<T>& L, int Lr, int Lp, T* C,
 // Householder QR of the r x c matrix M (ld) in place: R on and above the
 // diagonal, the reflectors below, tau[min(r, c)], and each panel's T
 // (NB x NB, row-major) at Tst + panel * NB * NB.
-template <typename T>
+template <typename T, bool LP>
 __device__ __noinline__ void wg_geqrf_impl(LSQ_GLB T* Mg, int ld, int r, int c, LSQ_GLB T* taug,
                                            LSQ_GLB T* Tstg, LSQ_LDS BLds<T>* Lp) {
   T* M = (T*)uni(Mg);
@@ -750,19 +788,19 @@ __device__ __noinline__ void wg_geqrf_impl(LSQ_GLB T* Mg, int ld, int r, int c, 
     // scalars and T to storage
     for (int e = threadIdx.x; e < NB * NB; e += kBT) Tst[(size_t)pan * NB * NB + e] = L.u.f.Ts[e];
     if (threadIdx.x < nbj) tau[j0 + threadIdx.x] = L.u.f.tau[threadIdx.x];
-    apply_block_qt(L, Lr, ld - j0, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
+    apply_block_qt<T, LP>(L, Lr, ld - j0, M + j0 + (size_t)(j0 + nbj) * ld, ld, c - j0 - nbj);
     __syncthreads();
   }
 }
 
-template <typename T>
+template <typename T, bool LP = false>
 __device__ __forceinline__ void wg_geqrf(T* M, int ld, int r, int c, T* tau, T* Tst, BLds<T>& L) {
-  wg_geqrf_impl<T>((LSQ_GLB T*)M, ld, r, c, (LSQ_GLB T*)tau, (LSQ_GLB T*)Tst, (LSQ_LDS BLds<T>*)&L);
+  wg_geqrf_impl<T, LP>((LSQ_GLB T*)M, ld, r, c, (LSQ_GLB T*)tau, (LSQ_GLB T*)Tst, (LSQ_LDS BLds<T>*)&L);
 }
 
 // X (r x ncols, ldx) <- Q^T X for the k reflectors stored in M (ld) by
 // wg_geqrf, panel by panel.
-template <typename T>
+template <typename T, bool LP>
 __device__ __noinline__ void wg_apply_qt_impl(const LSQ_GLB T* Mg, int ld, int r, int k,
                                               const LSQ_GLB T* Tstg, LSQ_GLB T* Xg, int ldx,
                                               int ncols, LSQ_LDS BLds<T>* Lp) {
@@ -776,15 +814,15 @@ __device__ __noinline__ void wg_apply_qt_impl(const LSQ_GLB T* Mg, int ld, int r
     const int nbj = k - j0 < NB ? k - j0 : NB, Lr = r - j0;
     for (int e = threadIdx.x; e < NB * NB; e += kBT) L.u.f.Ts[e] = Tst[(size_t)pan * NB * NB + e];
     stage_panel(M, ld, j0, nbj, Lr, L.u.f.Ys, true);
-    apply_block_qt(L, Lr, ldx - j0, X + j0, ldx, ncols);
+    apply_block_qt<T, LP>(L, Lr, ldx - j0, X + j0, ldx, ncols);
     __syncthreads();
   }
 }
 
-template <typename T>
+template <typename T, bool LP = false>
 __device__ __forceinline__ void wg_apply_qt(const T* M, int ld, int r, int k, const T* Tst, T* X,
                                             int ldx, int ncols, BLds<T>& L) {
-  wg_apply_qt_impl<T>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_GLB T*)X, ldx,
+  wg_apply_qt_impl<T, LP>((const LSQ_GLB T*)M, ld, r, k, (const LSQ_GLB T*)Tst, (LSQ_GLB T*)X, ldx,
                       ncols, (LSQ_LDS BLds<T>*)&L);
 }
 
@@ -1505,7 +1543,7 @@ __device__ __forceinline__ void refine(Correct correct, Residual residual, const
 // Layout as the single-instance path: Bt = J_n B^T J_p = Qt [Rt; 0] (Fb),
 // Abar = A J Qt J = Za [T; 0] (Fa), k = n - p, T11 = T[0:k, 0:k],
 // T12 = T[0:k, k:n], T22 = T[k:m, k:n] (upper part).
-template <typename T>
+template <typename T, bool LP = false>
 __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, double tol, int maxit, double polish,
                                              bool fast_exit, double route, BatchOut* out,
                              BLds<T>& L) {
@@ -1528,11 +1566,11 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
   mat[2] = wg_fro(bvec, m, m, 1, L.dred);
   mat[3] = wg_fro(dvec, p, p, 1, L.dred);
   __syncthreads();
-  wg_geqrf(W.Fb, ldn, n, p, W.taub, W.Tb, L);
-  wg_apply_qt(W.Fb, ldn, n, p, W.Tb, W.X, ldn, m, L);
+  wg_geqrf<T, LP>(W.Fb, ldn, n, p, W.taub, W.Tb, L);
+  wg_apply_qt<T, LP>(W.Fb, ldn, n, p, W.Tb, W.X, ldn, m, L);
   wg_transpose(W.X, ldn, n, m, W.Fa, ldm, false, true, L.u.f.Ys);   // Fa[j][n-1-i] = X[i][j]
   __syncthreads();
-  wg_geqrf(W.Fa, ldm, m, n, W.taua, W.Ta, L);
+  wg_geqrf<T, LP>(W.Fa, ldm, m, n, W.taua, W.Ta, L);
   __syncthreads();
   // with a higher rung to follow, an instance whose triangles Rt or T11 show
   // a diagonal ratio above `route` (a lower bound on their condition number)
@@ -1647,7 +1685,7 @@ __device__ __forceinline__ void lse_instance(const BatchProb& P, char* base, dou
 // Layout as the single-instance path: W = Qw [Rw; 0] (Fw),
 // Vt = J_p (Qw^T V)^T J_n = Qv Tv (Fv, p x n), k = n - m,
 // A11 = Tv[0:k, 0:k], A12 = Tv[0:k, k:n], A22 = Tv[k:p, k:n] (upper part).
-template <typename T>
+template <typename T, bool LP = false>
 __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, double tol, int maxit, double polish,
                                              bool fast_exit, double route, BatchOut* out,
                              BLds<T>& L) {
@@ -1670,11 +1708,11 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
   mat[2] = wg_fro(dvec, n, n, 1, L.dred);
   mat[3] = 0.0;
   __syncthreads();
-  wg_geqrf(W.Fw, ldn, n, m, W.taw, W.Tw, L);
-  wg_apply_qt(W.Fw, ldn, n, m, W.Tw, W.X, ldn, p, L);
+  wg_geqrf<T, LP>(W.Fw, ldn, n, m, W.taw, W.Tw, L);
+  wg_apply_qt<T, LP>(W.Fw, ldn, n, m, W.Tw, W.X, ldn, p, L);
   wg_transpose(W.X, ldn, n, p, W.Fv, ldp, true, true, L.u.f.Ys);    // Fv[p-1-j][n-1-i] = X[i][j]
   __syncthreads();
-  wg_geqrf(W.Fv, ldp, p, n, W.tav, W.Tv, L);
+  wg_geqrf<T, LP>(W.Fv, ldp, p, n, W.tav, W.Tv, L);
   __syncthreads();
   // route as for the LSE: triangles Rw and A11 = Tv[0:k, 0:k]
   const bool skip = fast_exit && route > 0.0 &&
@@ -1785,7 +1823,7 @@ __device__ __forceinline__ void gls_instance(const BatchProb& P, char* base, dou
   refine(correct, residual, mat, 1, tol, maxit, polish, fast_exit, out, t_start, skip);
 }
 
-template <typename T>
+template <typename T, bool LP = false>
 __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb* __restrict__ probs,
                                                   const int* __restrict__ order, int count,
                                                   int* __restrict__ counter, char* __restrict__ ws,
@@ -1806,8 +1844,8 @@ __global__ __launch_bounds__(kBT, QrCfg<T>::BLOCKS) void k_batch(const BatchProb
     LSQ_LDS_POISON(L.red);
     LSQ_LDS_POISON(L.vred);
     LSQ_LDS_POISON(L.dred);
-    if (P.type == 0) lse_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, route, out + idx, L);
-    else gls_instance<T>(P, mine, tol, maxit, polish, fast_exit != 0, route, out + idx, L);
+    if (P.type == 0) lse_instance<T, LP>(P, mine, tol, maxit, polish, fast_exit != 0, route, out + idx, L);
+    else gls_instance<T, LP>(P, mine, tol, maxit, polish, fast_exit != 0, route, out + idx, L);
     __syncthreads();
     if (esc && threadIdx.x == 0) {
       // a failure goes to the FP64 launch beside this one: claim a slot,
@@ -1979,13 +2017,16 @@ double batch_factor_flops(const BatchProb& P) {
 
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit, double polish,
-                  bool fast_exit, double route, BatchOut* out, double flops) {
+                  bool fast_exit, double route, BatchOut* out, double flops, bool lowp) {
   if (count <= 0 || grid <= 0) return;
   LSQ_HIP(hipMemsetAsync(counter, 0, sizeof(int), ctx.stream));
   const int kind = tw == 8 ? kKBatch64 : kKBatch32;
   ktimer_begin(ctx, kind, flops, 0.0);
   if (tw == 8)
     hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                       counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, route, out, nullptr, 0);
+  else if (lowp)
+    hipLaunchKernelGGL((k_batch<float, true>), dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
                        counter, ws, ws_stride, tol, maxit, polish, fast_exit ? 1 : 0, route, out, nullptr, 0);
   else
     hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
@@ -2000,7 +2041,7 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
                              int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish,
                              double route, BatchOut* out, BatchOut* out64, double flops, double spin_ms,
-                             int* started, int big_count, int pre) {
+                             int* started, int big_count, int pre, bool lowp) {
   if (count <= 0 || grid <= 0) return;
   if (!ctx.side || grid64a <= 0) throw std::runtime_error("batch_launch_escalating: no side stream");
   if (pre < 0 || pre > count) throw std::runtime_error("batch_launch_escalating: pre outside [0, count]");
@@ -2030,8 +2071,12 @@ void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order,
       std::this_thread::yield();
   }
   ktimer_begin(ctx, kKBatch32, flops, 0.0);
-  hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
-                     counter, ws, ws_stride, tol, maxit, polish, 1, route, out, q, big_count);
+  if (lowp)
+    hipLaunchKernelGGL((k_batch<float, true>), dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                       counter, ws, ws_stride, tol, maxit, polish, 1, route, out, q, big_count);
+  else
+    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBT), 0, ctx.stream, probs, order, count,
+                       counter, ws, ws_stride, tol, maxit, polish, 1, route, out, q, big_count);
   LSQ_LAUNCH_CHECK();
   ktimer_end(ctx, kKBatch32);
   // more consumers once the FP32 launch is over, for what is still queued

@@ -322,9 +322,11 @@ double batch_factor_flops(const BatchProb& P);
 // launch, for the kernel timer.  fast_exit: a higher-precision rung follows,
 // so an instance whose refinement contracts too slowly stops early, and one
 // whose triangles show a diagonal ratio above route (> 0) skips refinement.
+// lowp (tw = 4): the BF16 factorization (trailing updates and the
+// application of the first factorization's Q^T with BF16 MFMA inputs).
 void batch_launch(Ctx& ctx, int tw, const BatchProb* probs, const int* order, int count,
                   int* counter, char* ws, size_t ws_stride, int grid, double tol, int maxit, double polish,
-                  bool fast_exit, double route, BatchOut* out, double flops);
+                  bool fast_exit, double route, BatchOut* out, double flops, bool lowp = false);
 
 // Escalation queues of the concurrent FP32 -> FP64 batch: the FP32 launch
 // appends each instance that fails to queue 1 if it is among the first
@@ -348,12 +350,13 @@ size_t esc_queue_bytes(int count);
 // launch waits up to 20 ms for all grid64a of them.  big_count: see
 // EscQueue.  pre: the first pre entries of the order go to the FP64 launch
 // directly (queue 1, before any failure), and the FP32 launch starts after
-// them.  ctx.stream waits for all three launches.
+// them.  lowp: the first launch factors in BF16 (as batch_launch).
+// ctx.stream waits for all three launches.
 void batch_launch_escalating(Ctx& ctx, const BatchProb* probs, const int* order, int count,
                              int* counter, char* ws, size_t ws_stride, int grid, char* ws64,
                              int grid64a, int grid64b, EscQueue* q, double tol, int maxit, double polish, double route,
                              BatchOut* out, BatchOut* out64, double flops, double spin_ms,
-                             int* started, int big_count, int pre);
+                             int* started, int big_count, int pre, bool lowp = false);
 // The same sequence in a form a stream capture can record: fill kernels
 // instead of memsets, the wait for the grid64a consumers on the device
 // (started: a device int the consumers count themselves in, bounded at

@@ -23,7 +23,8 @@ def h():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    hd = lsq.Handle()
+    # without the launch-shape table: these tests pin the FP32-first rungs
+    hd = lsq.Handle(load_tuning=False)
     yield hd
     hd.close()
 
@@ -88,12 +89,17 @@ def test_batched_mixed_fp32(h, mode, workers):
 
 def test_batched_bf16_with_ladder(h):
     # kappa up to 1e8: BF16 classical IR cannot reach every instance; the
-    # ladder (GMRES-IR on the same factors, then higher precisions) must
-    note("batched 16 instances bf16 kappa<=1e8")
+    # ladder on the batch workers (GMRES-IR on the same factors, then higher
+    # precisions) must (the persistent batch goes from BF16 straight to FP64)
+    note("batched 16 instances bf16 kappa<=1e8, workers")
     probs = list(wl.batch_instances(seed=41, count=16, kappa_max=1e8, m_range=(64, 400)))
     keep, descs = _descriptors(probs)
     assert h.lib.lsq_set_batch_workers(h.h, 8) == 0
-    rc, res = h.lsq_solve_batched(descs, lsq.default_opts(prec="bf16", solver="ir", escalate=1))
+    h.set_batch_mode("workers")
+    try:
+        rc, res = h.lsq_solve_batched(descs, lsq.default_opts(prec="bf16", solver="ir", escalate=1))
+    finally:
+        h.set_batch_mode("persistent")
     assert rc == 0, (rc, h.last_error())
     for P, (t, x, y), r in zip(probs, keep, res):
         _check(P, x.cpu().numpy(), None if y is None else y.cpu().numpy(), r)

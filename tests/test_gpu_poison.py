@@ -68,12 +68,16 @@ def test_gls_under_poisoned_lds(h, solver):
     assert np.max(np.abs(H(y) - yo)) <= 10 * cy * U64 * np.max(np.abs(yo))
 
 
-def test_persistent_batch_under_poisoned_lds(h):
-    note("poison persistent batch 40 instances")
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_persistent_batch_under_poisoned_lds(h, prec):
+    # without the launch-shape table, so that every instance starts on the
+    # FP32 (BF16) kernel and the failures reach the FP64 rung beside it
+    note(f"poison persistent batch 40 instances, {prec} first")
     probs = list(wl.batch_instances(seed=903, count=40, kappa_max=1e8, m_range=(64, 600)))
     from paper_2406_16499_amd import selector as sel
     ups = [sel._device_problem(P) for P in probs]
-    rc, res = h.lsq_solve_batched([d for d, _ in ups], lsq.default_opts(prec="fp32", solver="ir"))
+    h.batch_tuning([])
+    rc, res = h.lsq_solve_batched([d for d, _ in ups], lsq.default_opts(prec=prec, solver="ir"))
     assert rc == 0
     for P, (_, k), r in zip(probs, ups, res):
         assert r.info == 0 and r.berr_max <= 1e-14, r.as_dict()

@@ -487,7 +487,7 @@ struct LseSolver {
   // identity rows.
   TriBlock tT1;
   double alpha = 1.0, beta = 1.0, sa = 1.0;
-  double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *g4 = nullptr, *t1 = nullptr, *t2 = nullptr;
   DualParts dpa, dpb;
 
   int tmn() const { return std::min(m, n); }
@@ -496,6 +496,7 @@ struct LseSolver {
     trsv_prepare(ctx, tT1, fa, 0, tmn(), 8);
     const int L = std::max(std::max(m, n), 1), N = std::max(m + p + n, 1);
     g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
+    g4 = ctx.ws->get<double>(L);
     t1 = ctx.ws->get<double>(N); t2 = ctx.ws->get<double>(N);
     dual_parts_alloc(ctx, m, n, dpa);
     dual_parts_alloc(ctx, p, n, dpb);
@@ -530,27 +531,31 @@ struct LseSolver {
     gemv_upper(ctx, fa, k, k, rows, p, trans, s, xv, yv, 8);
     if (p > rows) vec_axpy(ctx, yv + rows, 8, s, xv + rows, 8, p - rows, false);
   }
+  // The two preconditioner applications with their vector glue merged into
+  // three segment launches each (the same arithmetic as r_solve, q_apply and
+  // y_apply with their reversal, scaling and addition steps one by one).
   void m_right(Ctx& ctx, const double* u, double* out) {
-    vec_convert(ctx, out, 8, u, 8, m, false, 1.0 / sa);
-    vec_zero(ctx, g1, 8, p);
-    y_apply(ctx, true, 1.0, u + m, g1);
-    r_solve(ctx, g1, true);
-    vec_convert(ctx, out + m, 8, g1, 8, p, false, 1.0 / (sa * beta));
-    vec_convert(ctx, g2, 8, u + m + p, 8, n, false);
+    const int t = tmn(), rows = t - k;
+    vec_segs(ctx, {seg_copy(out, u, m, false, 1.0 / sa), seg_zero(g1, p), seg_copy(g2, u + m + p, n)});
+    gemv_upper(ctx, fa, k, k, rows, p, true, 1.0, u + m, g1, 8);                 // Y^T b
     u_solve(ctx, g2);
-    q_apply(ctx, g2, true);
-    vec_convert(ctx, out + m + p, 8, g2, 8, n, false, sa);
+    vec_segs(ctx, {seg_add(g3, g1, u + m, p, true, rows), seg_copy(g4, g2, n, true)});
+    trsv(ctx, tR, false, g3);                                                      // R^{-T}
+    agg_apply(ctx, fb, false, g4, 8);                                              // Q^T
+    vec_segs(ctx, {seg_copy(out + m, g3, p, true, 1.0 / (sa * beta)), seg_copy(out + m + p, g4, n, true, sa)});
   }
   void m_left(Ctx& ctx, const double* u, double* out) {
-    vec_convert(ctx, out, 8, u, 8, m, false, 1.0 / sa);
-    vec_convert(ctx, g1, 8, u + m, 8, p, false);
-    r_solve(ctx, g1, false);
-    vec_zero(ctx, out + m, 8, p);
-    y_apply(ctx, false, 1.0 / (sa * beta), g1, out + m);
-    vec_convert(ctx, g2, 8, u + m + p, 8, n, false);
-    q_apply(ctx, g2, false);
+    const int t = tmn(), rows = t - k;
+    const double s = 1.0 / (sa * beta);
+    vec_segs(ctx, {seg_copy(out, u, m, false, 1.0 / sa), seg_copy(g3, u + m, p, true),
+                   seg_copy(g4, u + m + p, n, true), seg_zero(out + m, p)});
+    trsv(ctx, tR, true, g3);                                                       // R^{-1}
+    agg_apply(ctx, fb, true, g4, 8);                                               // Q
+    vec_segs(ctx, {seg_copy(g1, g3, p, true), seg_copy(g2, g4, n, true)});
+    gemv_upper(ctx, fa, k, k, rows, p, false, s, g1, out + m, 8);                 // Y R^{-1} b
     u_solve_t(ctx, g2);
-    vec_convert(ctx, out + m + p, 8, g2, 8, n, false, sa);
+    vec_segs(ctx, {seg_add(out + m + rows, out + m + rows, g1 + rows, p - rows, false, 0, s),
+                   seg_copy(out + m + p, g2, n, false, sa)});
   }
   void f_apply(Ctx& ctx, const LseArgs& a, const double* u, double* out);
 };
@@ -682,7 +687,8 @@ struct GlsSolver {
   // Y = J Ut[k:n, k:n]^T J (k = n - m).
   TriBlock tRv;
   double alpha = 1.0, beta = 1.0, sa = 1.0;
-  double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *g4 = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *g4 = nullptr, *g5 = nullptr, *g6 = nullptr;
+  double *t1 = nullptr, *t2 = nullptr;
   DualParts dpv, dpw;
 
   int tnp() const { return std::min(n, p); }
@@ -691,7 +697,7 @@ struct GlsSolver {
     trsv_prepare(ctx, tRv, fv, 0, tnp(), 8);
     const int L = std::max(std::max(n, p), 1), N = std::max(p + n + m, 1);
     g1 = ctx.ws->get<double>(L); g2 = ctx.ws->get<double>(L); g3 = ctx.ws->get<double>(L);
-    g4 = ctx.ws->get<double>(L);
+    g4 = ctx.ws->get<double>(L); g5 = ctx.ws->get<double>(L); g6 = ctx.ws->get<double>(L);
     t1 = ctx.ws->get<double>(N); t2 = ctx.ws->get<double>(N);
     dual_parts_alloc(ctx, n, p, dpv);
     dual_parts_alloc(ctx, n, m, dpw);
@@ -719,26 +725,35 @@ struct GlsSolver {
     if (m > rows) vec_axpy(ctx, g4 + rows, 8, 1.0, g3 + rows, 8, m - rows, false);
     vec_convert(ctx, out, 8, g4, 8, m, true);
   }
+  // The two preconditioner applications with their vector glue merged into
+  // three segment launches each (the same arithmetic as u_solve / y_apply
+  // with their reversal and scaling steps one by one; the segments' factors
+  // of 1 are exact).  Buffers: g3 the U solve, g5 / g4 the Y product's
+  // input / output, g1 / g2 / g6 the Q and R solves.
   void m_right(Ctx& ctx, const double* u, double* out) {
-    vec_convert(ctx, out, 8, u, 8, p, false, 1.0 / sa);
-    vec_convert(ctx, g1, 8, u + p, 8, n, false);
-    u_solve(ctx, g1, true);
+    const int t = tnp(), rows = t - k;
+    vec_segs(ctx, {seg_copy(out, u, p, false, 1.0 / sa), seg_copy(g3, u + p, n, true),
+                   seg_copy(g5, u + p + n, m, true), seg_zero(g4, m)});
+    if (n > t) gemv_upper(ctx, fv, 0, t, t, n - t, false, -1.0, g3 + t, g3, 8);   // Ut y = J b
+    trsv(ctx, tRv, false, g3);
+    gemv_upper(ctx, fv, k, k, rows, m, true, 1.0, g5, g4, 8);                    // Y c
+    vec_segs(ctx, {seg_copy(g1, g3, n, true), seg_add(g2, g4, g5, m, true, rows)});
     agg_apply(ctx, fw, false, g1, 8);
-    vec_convert(ctx, out + p, 8, g1, 8, n, false, sa);
-    y_apply(ctx, u + p + n, g2, false);
     trsv(ctx, tR, false, g2);
-    vec_convert(ctx, out + p + n, 8, g2, 8, m, false, 1.0 / (sa * beta));
+    vec_segs(ctx, {seg_copy(out + p, g1, n, false, sa), seg_copy(out + p + n, g2, m, false, 1.0 / (sa * beta))});
   }
   void m_left(Ctx& ctx, const double* u, double* out) {
-    vec_convert(ctx, out, 8, u, 8, p, false, 1.0 / sa);
-    vec_convert(ctx, g1, 8, u + p, 8, n, false);
+    const int t = tnp(), rows = t - k;
+    vec_segs(ctx, {seg_copy(out, u, p, false, 1.0 / sa), seg_copy(g1, u + p, n), seg_copy(g6, u + p + n, m),
+                   seg_zero(g4, m)});
     agg_apply(ctx, fw, true, g1, 8);
-    u_solve(ctx, g1, false);
-    vec_convert(ctx, out + p, 8, g1, 8, n, false, sa);
-    vec_convert(ctx, g1, 8, u + p + n, 8, m, false);
-    trsv(ctx, tR, true, g1);
-    y_apply(ctx, g1, g2, true);
-    vec_convert(ctx, out + p + n, 8, g2, 8, m, false, 1.0 / (sa * beta));
+    trsv(ctx, tR, true, g6);
+    vec_segs(ctx, {seg_copy(g3, g1, n, true), seg_copy(g5, g6, m, true)});
+    trsv(ctx, tRv, true, g3);                                                      // Ut^T y = J Q^T b
+    if (n > t) gemv_upper(ctx, fv, 0, t, t, n - t, true, -1.0, g3, g3 + t, 8);
+    gemv_upper(ctx, fv, k, k, rows, m, false, 1.0, g5, g4, 8);                   // Y^T R^{-T} c
+    vec_segs(ctx, {seg_copy(out + p, g3, n, true, sa), seg_add(out + p + n, g4, g5, m, true, rows, 1.0,
+                                                               1.0 / (sa * beta))});
   }
   void f_apply(Ctx& ctx, const GlsArgs& a, const double* u, double* out);
 };
@@ -746,17 +761,17 @@ struct GlsSolver {
 void LseSolver::f_apply(Ctx& ctx, const LseArgs& a, const double* u, double* out) {
   dual_gemv(ctx, a.A, a.lda, m, n, u + m + p, u, dpa);         // A c, A^T a
   dual_gemv(ctx, a.B, a.ldb, p, n, u + m + p, u + m, dpb);     // B c, B^T b
-  combine(ctx, out, m, alpha, u, 1.0, dpa.rowp, dpa.ncb, 0.0, nullptr, 0);
-  combine(ctx, out + m, p, 0.0, nullptr, beta, dpb.rowp, dpb.ncb, 0.0, nullptr, 0);
-  combine(ctx, out + m + p, n, 0.0, nullptr, 1.0, dpa.colp, dpa.nrb, beta, dpb.colp, dpb.nrb);
+  combine3(ctx, CombineArgs{out, m, alpha, u, 1.0, dpa.rowp, dpa.ncb, 0.0, nullptr, 0},
+           CombineArgs{out + m, p, 0.0, nullptr, beta, dpb.rowp, dpb.ncb, 0.0, nullptr, 0},
+           CombineArgs{out + m + p, n, 0.0, nullptr, 1.0, dpa.colp, dpa.nrb, beta, dpb.colp, dpb.nrb});
 }
 
 void GlsSolver::f_apply(Ctx& ctx, const GlsArgs& a, const double* u, double* out) {
   dual_gemv(ctx, a.V, a.ldv, n, p, u, u + p, dpv);             // V a, V^T b
   dual_gemv(ctx, a.W, a.ldw, n, m, u + p + n, u + p, dpw);     // W c, W^T b
-  combine(ctx, out, p, alpha, u, 1.0, dpv.colp, dpv.nrb, 0.0, nullptr, 0);
-  combine(ctx, out + p, n, 0.0, nullptr, 1.0, dpv.rowp, dpv.ncb, beta, dpw.rowp, dpw.ncb);
-  combine(ctx, out + p + n, m, 0.0, nullptr, beta, dpw.colp, dpw.nrb, 0.0, nullptr, 0);
+  combine3(ctx, CombineArgs{out, p, alpha, u, 1.0, dpv.colp, dpv.nrb, 0.0, nullptr, 0},
+           CombineArgs{out + p, n, 0.0, nullptr, 1.0, dpv.rowp, dpv.ncb, beta, dpw.rowp, dpw.ncb},
+           CombineArgs{out + p + n, m, 0.0, nullptr, beta, dpw.colp, dpw.nrb, 0.0, nullptr, 0});
 }
 
 // ------------------------------------------------------- rung execution --

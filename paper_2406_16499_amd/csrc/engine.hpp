@@ -1,5 +1,6 @@
 // Host-side interfaces between liblsq's HIP translation units.
 #pragma once
+#include <initializer_list>
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -248,6 +249,48 @@ void unembed_vec(Ctx& ctx, const double* e, int n, double* u);
 void scale_first(Ctx& ctx, double* v, int n, double s);
 
 // ------------------------------------------------------- FP64 Krylov ----
+// One FP64 vector segment of vec_segs: dst[i] = c (a src[j] + b src2[j]),
+// j = n - 1 - i if rev else i, the src2 term only for j >= lo, a null source
+// contributing 0 (both null: a zero fill).  A reversed segment may not write
+// over its sources.
+struct VecSeg {
+  double* dst;
+  const double* src;
+  const double* src2;
+  int n, rev, lo;
+  double a, b, c;
+};
+constexpr int kVecSegs = 6;
+struct VecSegs {
+  VecSeg s[kVecSegs];
+  int count;
+};
+// Up to kVecSegs independent segments in one launch (segments with n <= 0
+// are skipped).
+void vec_segs(Ctx& ctx, std::initializer_list<VecSeg> segs);
+inline VecSeg seg_copy(double* dst, const double* src, int n, bool rev = false, double c = 1.0) {
+  return VecSeg{dst, src, nullptr, n, rev ? 1 : 0, 0, 1.0, 0.0, c};
+}
+inline VecSeg seg_zero(double* dst, int n) { return VecSeg{dst, nullptr, nullptr, n, 0, 0, 0.0, 0.0, 1.0}; }
+// dst[i] = c (src[j] + b [j >= lo] src2[j])
+inline VecSeg seg_add(double* dst, const double* src, const double* src2, int n, bool rev, int lo,
+                      double b = 1.0, double c = 1.0) {
+  return VecSeg{dst, src, src2, n, rev ? 1 : 0, lo, 1.0, b, c};
+}
+// Arguments of one combine (below); combine3 runs three in one launch.
+struct CombineArgs {
+  double* out;
+  int n;
+  double c0;
+  const double* x0;
+  double c1;
+  const double* p1;
+  int np1;
+  double c2;
+  const double* p2;
+  int np2;
+};
+void combine3(Ctx& ctx, const CombineArgs& a0, const CombineArgs& a1, const CombineArgs& a2);
 // out[i] = c0 x0[i] + c1 sum_q p1[q][i] + c2 sum_q p2[q][i] (null terms skipped),
 // the parts being the partial products left by dual_gemv.
 void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c1, const double* p1,

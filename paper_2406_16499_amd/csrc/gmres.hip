@@ -243,7 +243,63 @@ __global__ __launch_bounds__(256) void k_change_max(const double* __restrict__ o
   }
 }
 
+// Independent FP64 vector segments in one launch (blockIdx.y = segment): the
+// copies, reversals, scalings and partial additions between the solves of
+// the preconditioners, which would otherwise be one small launch each.
+__global__ __launch_bounds__(256) void k_vec_segs(VecSegs v) {
+  const VecSeg g = v.s[blockIdx.y];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < g.n; i += gridDim.x * 256) {
+    const int j = g.rev ? g.n - 1 - i : i;
+    double val = g.src ? g.a * g.src[j] : 0.0;
+    if (g.src2 && j >= g.lo) val = val + g.b * g.src2[j];
+    g.dst[i] = val * g.c;
+  }
+}
+
+// The operator's three combines in one launch (blockIdx.y = block of F u).
+__global__ __launch_bounds__(256) void k_combine3(CombineArgs a0, CombineArgs a1, CombineArgs a2) {
+  const CombineArgs a = blockIdx.y == 0 ? a0 : (blockIdx.y == 1 ? a1 : a2);
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  double s = a.x0 ? a.c0 * a.x0[i] : 0.0;
+  if (a.p1) {
+    double t = 0.0;
+    for (int q = 0; q < a.np1; ++q) t += a.p1[(size_t)q * a.n + i];
+    s = fma(a.c1, t, s);
+  }
+  if (a.p2) {
+    double t = 0.0;
+    for (int q = 0; q < a.np2; ++q) t += a.p2[(size_t)q * a.n + i];
+    s = fma(a.c2, t, s);
+  }
+  a.out[i] = s;
+}
+
 // ------------------------------------------------------------------ host --
+void vec_segs(Ctx& ctx, std::initializer_list<VecSeg> segs) {
+  VecSegs v{};
+  int nmax = 0;
+  for (const VecSeg& g : segs) {
+    if (g.n <= 0) continue;
+    if (v.count == kVecSegs) throw std::runtime_error("vec_segs: too many segments");
+    if (g.rev && (g.dst == g.src || g.dst == g.src2))
+      throw std::runtime_error("vec_segs: a reversed segment cannot work in place");
+    v.s[v.count++] = g;
+    nmax = std::max(nmax, g.n);
+  }
+  if (v.count == 0) return;
+  const int gx = std::min(ceil_div(nmax, 256), 64);
+  hipLaunchKernelGGL(k_vec_segs, dim3(gx, v.count), dim3(256), 0, ctx.stream, v);
+  LSQ_LAUNCH_CHECK();
+}
+
+void combine3(Ctx& ctx, const CombineArgs& a0, const CombineArgs& a1, const CombineArgs& a2) {
+  const int nmax = std::max(a0.n, std::max(a1.n, a2.n));
+  if (nmax <= 0) return;
+  hipLaunchKernelGGL(k_combine3, dim3(ceil_div(nmax, 256), 3), dim3(256), 0, ctx.stream, a0, a1, a2);
+  LSQ_LAUNCH_CHECK();
+}
+
 void combine(Ctx& ctx, double* out, int n, double c0, const double* x0, double c1, const double* p1,
              int np1, double c2, const double* p2, int np2) {
   if (n <= 0) return;

@@ -47,16 +47,22 @@ __global__ __launch_bounds__(256) void k_cgs_dot(const double* __restrict__ V, i
 }
 
 // h = sum of the block partials; w -= V h; hacc (+)= h (written by block 0);
-// with nrm, nrm[b] = sum over block b of the updated w[i]^2.
+// with nrm, nrm[b] = sum over block b of the updated w[i]^2; with part_next,
+// the next pass's partials of V^T w from the updated rows (the sums of
+// k_cgs_dot, in its order; a buffer of their own, since other blocks may
+// still read part).
 __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V, int ldv, int N, int kc,
                                                     const double* __restrict__ part, int nblk,
                                                     double* __restrict__ w, double* __restrict__ hacc,
                                                     int accumulate, double* __restrict__ nrm,
-                                                    const double* __restrict__ stat) {
+                                                    const double* __restrict__ stat,
+                                                    double* __restrict__ part_next) {
   __shared__ double h[kCgsMax];
   __shared__ double red[4];
+  __shared__ double red2[4][kCgsMax];
   LSQ_LDS_POISON(h);
   LSQ_LDS_POISON(red);
+  LSQ_LDS_POISON(red2);
   if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
   const int t = threadIdx.x;
   if (t < kc) {
@@ -67,9 +73,9 @@ __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V
   }
   __syncthreads();
   const int i = blockIdx.x * kCgsRows + t;
-  double sq = 0.0;
+  double sq = 0.0, wi = 0.0;
   if (i < N) {
-    double wi = w[i];
+    wi = w[i];
     for (int j = 0; j < kc; ++j) wi = fma(-V[(size_t)i + (size_t)j * ldv], h[j], wi);
     w[i] = wi;
     sq = wi * wi;
@@ -77,6 +83,18 @@ __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V
   if (nrm) {
     sq = block_sum(sq, red);
     if (t == 0) nrm[blockIdx.x] = sq;
+  }
+  if (part_next) {
+    const int lane = t & 63, wv = t >> 6;
+#pragma unroll 4
+    for (int j = 0; j < kCgsMax; ++j) {
+      if (j >= kc) break;
+      double s = i < N ? V[(size_t)i + (size_t)j * ldv] * wi : 0.0;
+      s = wave_sum_d(s);
+      if (lane == 0) red2[wv][j] = s;
+    }
+    __syncthreads();
+    if (t < kc) part_next[(size_t)blockIdx.x * kCgsMax + t] = red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
   }
 }
 
@@ -127,15 +145,19 @@ __global__ void k_givens(int k, const double* __restrict__ hcol, const double* _
   if (fabs(st.g[k + 1]) <= tol_abs || hn == 0.0) st.stat[2] = 1.0;
 }
 
-// w <- w / h_{k+1,k} (the next basis vector), unless that is 0 or an earlier
-// iteration converged.
-__global__ __launch_bounds__(256) void k_scale_basis(double* __restrict__ w, int N,
-                                                     const double* __restrict__ stat, int k) {
+// v = w / h_{k+1,k} (the next basis vector) into v and, if set, v2 (the
+// operator graph's input), unless h is 0 or an earlier iteration converged.
+// v may be w itself.
+__global__ __launch_bounds__(256) void k_scale_basis(const double* w, double* v, double* __restrict__ v2,
+                                                     int N, const double* __restrict__ stat, int k) {
   if (stat[2] != 0.0 && stat[3] < (double)(k + 1)) return;
   const double hn = stat[1];
   if (!(hn > 0.0)) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < N) w[i] *= 1.0 / hn;
+  if (i >= N) return;
+  const double x = w[i] * (1.0 / hn);
+  v[i] = x;
+  if (v2) v2[i] = x;
 }
 
 // x += V[:, 0:kc] y
@@ -451,6 +473,10 @@ GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)
   double* Vb = ctx.ws->get<double>((size_t)N * (restart + 1));
   double* r = ctx.ws->get<double>(N);
   double* part = ctx.ws->get<double>((size_t)nblk * kCgsMax);
+  double* part2 = ctx.ws->get<double>((size_t)nblk * kCgsMax);
+  // with the operator captured, the Arnoldi loop feeds its fixed input and
+  // orthogonalizes its fixed output in place: no copies around the replays
+  const bool direct = op.exec != nullptr;
   double* hdev = ctx.ws->get<double>(kCgsMax);
   double* nrm = ctx.ws->get<double>(nblk);
   double* ydev = ctx.ws->get<double>(kCgsMax);
@@ -483,23 +509,26 @@ GmresOut gmres(Ctx& ctx, int N, const std::function<void(const double*, double*)
     LSQ_HIP(hipMemcpyAsync(st.g, pin_start, sizeof(double) * kCgsMax, hipMemcpyHostToDevice, ctx.stream));
     LSQ_HIP(hipMemcpyAsync(st.stat, pin_start + kCgsMax, sizeof(double) * 4, hipMemcpyHostToDevice,
                            ctx.stream));
-    vec_convert(ctx, Vb, 8, r, 8, N, false, 1.0 / beta);
+    vec_segs(ctx, {seg_copy(Vb, r, N, false, 1.0 / beta), seg_copy(direct ? op.in : nullptr, r, direct ? N : 0,
+                                                                    false, 1.0 / beta)});
     // iteration k is enqueued before the flag of iteration k - 1 is read
     int launched = 0;
     for (int k = 0; k < kmax; ++k) {
-      double* w = Vb + (size_t)(k + 1) * N;
-      apply(Vb + (size_t)k * N, w);
+      double* vnext = Vb + (size_t)(k + 1) * N;
+      double* w = direct ? op.out : vnext;
+      if (direct) LSQ_HIP(hipGraphLaunch(op.exec, ctx.stream));
+      else apply(Vb + (size_t)k * N, w);
       const int kc = k + 1;
-      for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_cgs_dot, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, w, part,
-                           st.stat);
-        hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, part, nblk,
-                           w, hdev, pass, pass == 1 ? nrm : nullptr, st.stat);
-      }
+      // CGS2: the first pass's update also forms the second pass's dots
+      hipLaunchKernelGGL(k_cgs_dot, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, w, part, st.stat);
+      hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, part, nblk, w, hdev,
+                         0, nullptr, st.stat, part2);
+      hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(256), 0, ctx.stream, Vb, N, N, kc, part2, nblk, w,
+                         hdev, 1, nrm, st.stat, nullptr);
       hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, ctx.stream, k, hdev, nrm, nblk, st,
                          tol * beta0);
-      hipLaunchKernelGGL(k_scale_basis, dim3(ceil_div(N, 256)), dim3(256), 0, ctx.stream, w, N,
-                         st.stat, k);
+      hipLaunchKernelGGL(k_scale_basis, dim3(ceil_div(N, 256)), dim3(256), 0, ctx.stream, w, vnext,
+                         direct ? op.in : nullptr, N, st.stat, k);
       LSQ_LAUNCH_CHECK();
       LSQ_HIP(hipMemcpyAsync(pin_stat + 4 * (k & 1), st.stat, sizeof(double) * 4, hipMemcpyDeviceToHost,
                              ctx.stream));

@@ -1663,10 +1663,13 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     LSQ_HIP(hipMemcpyAsync(hout64.data(), dout64, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, ctx.stream));
     LSQ_HIP(hipStreamSynchronize(ctx.stream));
     // the FP64 rung's work for its timer: the instances its launches solved
-    double flops64 = 0.0;
-    for (int qq : cur)
-      if (hout64[qq].info != -1) flops64 += batch_factor_flops(hp[qq]);
-    ktimer_add(ctx, kKBatchEsc, flops64, 0.0);
+    // (a replayed plan records no timer events, so it adds no work either)
+    if (!plan) {
+      double flops64 = 0.0;
+      for (int qq : cur)
+        if (hout64[qq].info != -1) flops64 += batch_factor_flops(hp[qq]);
+      ktimer_add(ctx, kKBatchEsc, flops64, 0.0);
+    }
     std::vector<int> pending;
     for (int i = 0; i < n; ++i) {
       const int qq = cur[i];

@@ -45,3 +45,14 @@ def test_table_checks_and_apply():
                 h.batch_tuning(bad)
     finally:
         h.close()
+
+
+def test_committed_table_is_accepted():
+    # Handle() installs this table; every entry must pass lsq_batch_tuning's checks
+    table = autotune.load()
+    assert table, "the measured table ships with the package"
+    dims = [e[0] for e in table]
+    assert len(set(dims)) == len(dims)
+    for max_dim, route, share, pre in table:
+        assert max_dim >= 1 and route >= 0.0 and 0.0 < share < 1.0 and 0.0 <= pre <= 8.0
+    assert max(dims) >= 1024          # covers every instance the persistent kernel takes

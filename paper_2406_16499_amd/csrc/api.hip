@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "segs.hpp"
 #include "lsq.h"
 #include "lsq_debug.h"
 
@@ -434,44 +435,37 @@ struct LseSolver {
   }
 
   // Algorithm 1 on (f1, f2, f3) (f3 may be null = 0); adds (dr, dv, dx) to (r, v, x).
+  // The vector steps between the solves run as six multi-segment launches
+  // (segs.hpp), each segment the same once-rounded expression as the
+  // conversion or axpy it stands for.
   void correct(Ctx& ctx, const double* f1, const double* f2, const double* f3, double* x,
                double* r, double* v) {
     const size_t e = (size_t)tc;
-    // u~ = Qt^T (J f3)
-    if (f3) vec_convert(ctx, U, tc, f3, 8, n, true); else vec_zero(ctx, U, tc, n);
-    agg_apply(ctx, fb, true, U, tc);
-    // w = Z^T f1
-    vec_convert(ctx, Wv, tc, f1, 8, m, false);
-    agg_apply(ctx, fa, true, Wv, tc);
-    // R y2 = f2  <=>  Rt^T (J y2) = J f2
-    vec_convert(ctx, Y2, tc, f2, 8, p, true);
-    trsv(ctx, tR, true, Y2);
-    vec_convert(ctx, Y2n, tc, Y2, tc, p, true);
-    // T11^T q1 = u1, u1 = J u~[p:n]
-    vec_convert(ctx, Qv, tc, off(U, e * p), tc, k, true);
-    trsv(ctx, tT11, true, Qv);
-    // T11 y1 = w1 - q1 - T12 y2
-    vec_convert(ctx, Y1, tc, Wv, tc, k, false);
-    vec_axpy(ctx, Y1, tc, -1.0, Qv, tc, k, false);
+    // u~ = J f3 (or 0), w = f1, y2 = J f2 in tc; S = 0
+    vec_segs_t(ctx, {f3 ? tcopy(U, tc, f3, 8, n, true) : tzero(U, tc, n), tcopy(Wv, tc, f1, 8, m),
+                     tcopy(Y2, tc, f2, 8, p, true), tzero(S, tc, p)});
+    agg_apply(ctx, fb, true, U, tc);                    // u~ = Qt^T (J f3)
+    agg_apply(ctx, fa, true, Wv, tc);                   // w = Z^T f1
+    trsv(ctx, tR, true, Y2);                            // R y2 = f2  <=>  Rt^T (J y2) = J f2
+    // J y2; u1 = J u~[p:n]
+    vec_segs_t(ctx, {tcopy(Y2n, tc, Y2, tc, p, true), tcopy(Qv, tc, off(U, e * p), tc, k, true)});
+    trsv(ctx, tT11, true, Qv);                          // T11^T q1 = u1
+    // w1 - q1; w2 (the start of q2)
+    vec_segs_t(ctx, {tadd(Y1, tc, Wv, tc, false, Qv, tc, false, k, -1.0),
+                     tcopy(off(Qv, e * k), tc, off(Wv, e * k), tc, m - k)});
     gemv_upper(ctx, fa, 0, k, k, p, false, -1.0, Y2n, Y1, tc);
-    trsv(ctx, tT11, false, Y1);
-    // q2 = w2 - T22 y2
-    vec_convert(ctx, off(Qv, e * k), tc, off(Wv, e * k), tc, m - k, false);
-    gemv_upper(ctx, fa, k, k, m - k, p, false, -1.0, Y2n, off(Qv, e * k), tc);
+    trsv(ctx, tT11, false, Y1);                         // T11 y1 = w1 - q1 - T12 y2
+    gemv_upper(ctx, fa, k, k, m - k, p, false, -1.0, Y2n, off(Qv, e * k), tc);   // q2 = w2 - T22 y2
     // R^T dv = T12^T q1 + T22^T q2 - u2  <=>  Rt (J dv) = J(...)
-    vec_zero(ctx, S, tc, p);
     gemv_upper(ctx, fa, 0, k, m, p, true, 1.0, Qv, S, tc);
-    vec_axpy(ctx, S, tc, -1.0, U, tc, p, true);
-    vec_convert(ctx, X2, tc, S, tc, p, true);
+    vec_segs_t(ctx, {tadd(X2, tc, S, tc, true, U, tc, false, p, -1.0)});
     trsv(ctx, tR, false, X2);
-    vec_axpy(ctx, v, 8, 1.0, X2, tc, p, true);
-    // dr = Z q ; dx = Q^T y = J Qt (J y),  J y = [y2~; J y1]
-    agg_apply(ctx, fa, false, Qv, tc);
-    vec_axpy(ctx, r, 8, 1.0, Qv, tc, m, false);
-    vec_convert(ctx, Yt, tc, Y2, tc, p, false);
-    vec_convert(ctx, off(Yt, e * p), tc, Y1, tc, k, true);
-    agg_apply(ctx, fb, false, Yt, tc);
-    vec_axpy(ctx, x, 8, 1.0, Yt, tc, n, true);
+    // v += J dv~; J y = [y2~; J y1]
+    vec_segs_t(ctx, {taxpy(v, 8, 1.0, X2, tc, p, true), tcopy(Yt, tc, Y2, tc, p),
+                     tcopy(off(Yt, e * p), tc, Y1, tc, k, true)});
+    agg_apply(ctx, fa, false, Qv, tc);                  // dr = Z q
+    agg_apply(ctx, fb, false, Yt, tc);                  // dx = J Qt (J y)
+    vec_segs_t(ctx, {taxpy(r, 8, 1.0, Qv, tc, m), taxpy(x, 8, 1.0, Yt, tc, n, true)});
   }
 
   // ---- GMRES-IR: block-diagonal split preconditioners of Section 5.2, FP64
@@ -634,44 +628,38 @@ struct GlsSolver {
   }
 
   // Algorithm 3 on (f1, f2, f3) (f1, f3 may be null = 0); adds (dy, dz, dx) to (y, z, x).
+  // The vector steps between the solves run as six multi-segment launches,
+  // as in LseSolver::correct.
   void correct(Ctx& ctx, const double* f1, const double* f2, const double* f3, double* x,
                double* y, double* z) {
     const size_t e = (size_t)tc;
-    // u = Q^T f2
-    vec_convert(ctx, U, tc, f2, 8, n, false);
-    agg_apply(ctx, fw, true, U, tc);
-    // w~ = J w = Zt^T (J f1)
-    if (f1) vec_convert(ctx, Wt, tc, f1, 8, p, true); else vec_zero(ctx, Wt, tc, p);
-    agg_apply(ctx, fv, true, Wt, tc);
-    // R^T h1 = f3
-    if (f3) vec_convert(ctx, H1, tc, f3, 8, m, false); else vec_zero(ctx, H1, tc, m);
-    trsv(ctx, tR, true, H1);
-    vec_convert(ctx, H1t, tc, H1, tc, m, true);
-    // T22 g2 = u2  <=>  A11^T (J g2) = J u2
-    vec_convert(ctx, G, tc, off(U, e * m), tc, k, true);
-    trsv(ctx, tA11, true, G);
+    // f2, J f1 (or 0), f3 (or 0) in tc; S = 0
+    vec_segs_t(ctx, {tcopy(U, tc, f2, 8, n), f1 ? tcopy(Wt, tc, f1, 8, p, true) : tzero(Wt, tc, p),
+                     f3 ? tcopy(H1, tc, f3, 8, m) : tzero(H1, tc, m), tzero(S, tc, m)});
+    agg_apply(ctx, fw, true, U, tc);                    // u = Q^T f2
+    agg_apply(ctx, fv, true, Wt, tc);                   // J w = Zt^T (J f1)
+    trsv(ctx, tR, true, H1);                            // R^T h1 = f3
+    // J h1; J u2
+    vec_segs_t(ctx, {tcopy(H1t, tc, H1, tc, m, true), tcopy(G, tc, off(U, e * m), tc, k, true)});
+    trsv(ctx, tA11, true, G);                           // T22 g2 = u2  <=>  A11^T (J g2) = J u2
+    // J w2 - J g2; J w1 (the start of J g1)
+    vec_segs_t(ctx, {tadd(H2t, tc, Wt, tc, false, G, tc, false, k, -1.0),
+                     tcopy(off(G, e * k), tc, off(Wt, e * k), tc, p - k)});
     // T22^T h2 = w2 - g2 - T12^T h1  <=>  A11 (J h2) = J w2 - J g2 - A12 J h1
-    vec_convert(ctx, H2t, tc, Wt, tc, k, false);
-    vec_axpy(ctx, H2t, tc, -1.0, G, tc, k, false);
     gemv_upper(ctx, fv, 0, k, k, m, false, -1.0, H1t, H2t, tc);
     trsv(ctx, tA11, false, H2t);
     // g1 = w1 - T11^T h1  <=>  J g1 = J w1 - A22 J h1
-    vec_convert(ctx, off(G, e * k), tc, off(Wt, e * k), tc, p - k, false);
     gemv_upper(ctx, fv, k, k, p - k, m, false, -1.0, H1t, off(G, e * k), tc);
     // R dx = u1 - T11 g1 - T12 g2 = u1 - J (Rv[:, k:n]^T (J g))
-    vec_zero(ctx, S, tc, m);
     gemv_upper(ctx, fv, 0, k, p, m, true, 1.0, G, S, tc);
-    vec_convert(ctx, X, tc, U, tc, m, false);
-    vec_axpy(ctx, X, tc, -1.0, S, tc, m, true);
+    vec_segs_t(ctx, {tadd(X, tc, U, tc, false, S, tc, true, m, -1.0)});
     trsv(ctx, tR, false, X);
-    vec_axpy(ctx, x, 8, 1.0, X, tc, m, false);
-    // dz = -Q h, h = [h1; J h2~] ; dy = Z^T g = J Zt (J g)
-    vec_convert(ctx, Hv, tc, H1, tc, m, false);
-    vec_convert(ctx, off(Hv, e * m), tc, H2t, tc, k, true);
-    agg_apply(ctx, fw, false, Hv, tc);
-    vec_axpy(ctx, z, 8, -1.0, Hv, tc, n, false);
-    agg_apply(ctx, fv, false, G, tc);
-    vec_axpy(ctx, y, 8, 1.0, G, tc, p, true);
+    // x += dx; h = [h1; J h2~]
+    vec_segs_t(ctx, {taxpy(x, 8, 1.0, X, tc, m), tcopy(Hv, tc, H1, tc, m),
+                     tcopy(off(Hv, e * m), tc, H2t, tc, k, true)});
+    agg_apply(ctx, fw, false, Hv, tc);                  // dz = -Q h
+    agg_apply(ctx, fv, false, G, tc);                   // dy = Z^T g = J Zt (J g)
+    vec_segs_t(ctx, {taxpy(z, 8, -1.0, Hv, tc, n), taxpy(y, 8, 1.0, G, tc, p, true)});
   }
 
   // ---- GMRES-IR: block-diagonal split preconditioners of Section 5.3, FP64

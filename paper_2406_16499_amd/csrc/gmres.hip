@@ -13,6 +13,7 @@
 // kernels of an iteration already queued return at once.  The basis is
 // column-major N x (restart + 1) in FP64.
 #include "engine.hpp"
+#include "segs.hpp"
 
 namespace lsq {
 
@@ -278,6 +279,22 @@ __global__ __launch_bounds__(256) void k_vec_segs(VecSegs v) {
   }
 }
 
+// Mixed-precision segments (segs.hpp), blockIdx.y = segment.
+__device__ __forceinline__ double seg_ld(const void* p, int t, int i) {
+  return t == 8 ? static_cast<const double*>(p)[i] : (double)static_cast<const float*>(p)[i];
+}
+__global__ __launch_bounds__(256) void k_vec_segs_t(VecSegsT v) {
+  const VecSegT g = v.s[blockIdx.y];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < g.n; i += gridDim.x * 256) {
+    const int j1 = g.rev ? g.n - 1 - i : i, j2 = g.rev2 ? g.n - 1 - i : i;
+    double val = g.src ? g.a * seg_ld(g.src, g.ts, j1) : 0.0;
+    if (g.src2 && j2 >= g.lo) val = val + g.b * seg_ld(g.src2, g.ts2, j2);
+    val = val * g.c;
+    if (g.td == 8) static_cast<double*>(g.dst)[i] = val;
+    else static_cast<float*>(g.dst)[i] = (float)val;
+  }
+}
+
 // The operator's three combines in one launch (blockIdx.y = block of F u).
 __global__ __launch_bounds__(256) void k_combine3(CombineArgs a0, CombineArgs a1, CombineArgs a2) {
   const CombineArgs a = blockIdx.y == 0 ? a0 : (blockIdx.y == 1 ? a1 : a2);
@@ -312,6 +329,23 @@ void vec_segs(Ctx& ctx, std::initializer_list<VecSeg> segs) {
   if (v.count == 0) return;
   const int gx = std::min(ceil_div(nmax, 256), 64);
   hipLaunchKernelGGL(k_vec_segs, dim3(gx, v.count), dim3(256), 0, ctx.stream, v);
+  LSQ_LAUNCH_CHECK();
+}
+
+void vec_segs_t(Ctx& ctx, std::initializer_list<VecSegT> segs) {
+  VecSegsT v{};
+  int nmax = 0;
+  for (const VecSegT& g : segs) {
+    if (g.n <= 0) continue;
+    if (v.count == kVecSegsT) throw std::runtime_error("vec_segs_t: too many segments");
+    if ((g.rev && g.src == g.dst) || (g.rev2 && g.src2 == g.dst))
+      throw std::runtime_error("vec_segs_t: a reversed source cannot be the destination");
+    v.s[v.count++] = g;
+    nmax = std::max(nmax, g.n);
+  }
+  if (v.count == 0) return;
+  const int gx = std::min(ceil_div(nmax, 256), 64);
+  hipLaunchKernelGGL(k_vec_segs_t, dim3(gx, v.count), dim3(256), 0, ctx.stream, v);
   LSQ_LAUNCH_CHECK();
 }
 

@@ -226,13 +226,13 @@ def schedule_summary(tl):
 # The launch shape for batches whose instances mostly certify at FP32: the
 # FP64 rung on 1/16 of the compute units, no instance FP64 first (the shipped
 # table is tuned for the headline recipe, where about 40% need FP64).
-WELL_CONDITIONED_SCHEDULE = [(1024, 3e5, 0.0625, 0.0)]
-
-
 def batched_regime(args, kappa_max):
     """The batched recipe with both condition numbers log-uniform up to
-    kappa_max, mixed (with the schedule for well-conditioned batches) against
-    all-FP64 on the same instances; a solve counts only if it certifies."""
+    kappa_max, mixed against all-FP64 on the same instances; a solve counts
+    only if it certifies.  The handle carries the shipped launch-shape table,
+    whose entry each call picks by the escalation fraction of the call before
+    (a new handle starts with the entry for any regime: the first warm-up
+    call's)."""
     import torch
     from paper_2406_16499_amd import lsq
     from paper_2406_16499_amd import workloads as wl
@@ -252,8 +252,7 @@ def batched_regime(args, kappa_max):
     del probs
     torch.cuda.synchronize()
     gc.collect()
-    h = lsq.Handle(load_selector=False, load_tuning=False)
-    h.batch_tuning(WELL_CONDITIONED_SCHEDULE)
+    h = lsq.Handle(load_selector=False)
     h.set_batch_mode("persistent")
 
     def run(opts):
@@ -272,6 +271,7 @@ def batched_regime(args, kappa_max):
         return dt, ok, rungs
 
     dt, ok, rungs = run(lsq.default_opts(prec="fp32", solver="ir", escalate=1))
+    escalation = h.dbg_batch_regime()
     dt64, ok64, _ = run(lsq.default_opts(prec="fp64", solver="direct"))
     h.close()
     del keep, descs
@@ -280,7 +280,8 @@ def batched_regime(args, kappa_max):
     return {"value": value, "unit": "solves/s", "ms_per_step": 1000.0 * dt / args.steps,
             "config": {"workload": BATCH_WORKLOAD.replace("1e8", f"{kappa_max:g}"), "count": args.count,
                        "kappa_max": kappa_max,
-                       "schedule": "FP64 rung on 1/16 of the compute units, no instance FP64 first, route 3e5"},
+                       "schedule": "shipped table, entry picked by the previous call's escalation fraction"},
+            "escalation_fraction": escalation,
             "fp64_direct": {"value": value64, "unit": "solves/s", "ms_per_step": 1000.0 * dt64 / args.steps},
             "speedup_vs_fp64": value / value64 if value64 > 0 else None,
             "certified_fraction": ok / (args.count * args.steps), "rungs_used": rungs}

@@ -357,20 +357,25 @@ int lsq_set_batch_workers(lsq_handle handle, int workers);
 enum { LSQ_BATCH_AUTO = 0, LSQ_BATCH_WORKERS = 1, LSQ_BATCH_SEQUENTIAL = 2 };
 int lsq_set_batch_mode(lsq_handle handle, int mode);
 
-/* Launch-shape table of the persistent batch, per size bucket, as written by
-   the autotuner (paper_2406_16499_amd/autotune.py): entry i applies to a
-   batch whose largest dimension max(m, n, p) is at most max_dim[i], the entry
-   with the smallest such bound winning.  route[i] (>= 0, 0 = off) is the
-   diagonal-ratio route of the FP32 rung (lsq_dbg_batch_route), fp64_share[i]
-   in (0, 1) the share of compute units the concurrent FP64 rung starts on
-   (lsq_dbg_batch_split), pre[i] in [0, 8] the number of the longest
-   instances, per work-group of that rung, that it solves in FP64 from the
-   start instead of after an FP32 attempt (lsq_dbg_batch_pre).  A batch no
-   entry covers uses those three settings.  n = 0 clears the table.  Returns
-   -2 for n < 0 or NULL arrays with n > 0, -3 for an entry out of range (the
-   table is then unchanged). */
+/* Launch-shape table of the persistent batch, per size bucket and
+   escalation regime, as written by the autotuner
+   (paper_2406_16499_amd/autotune.py).  Entry i applies to a batch whose
+   largest dimension max(m, n, p) is at most max_dim[i] while the escalation
+   fraction of the handle's last FP32-first persistent batch (the share of the
+   instances that tried the first rung and did not certify there; 1 before the
+   first such batch and after every call of this function) is at most
+   esc_max[i] in [0, 1] (NULL: all 1).  Of the entries that apply, the one
+   with the smallest max_dim, then the smallest esc_max, wins.  route[i]
+   (>= 0, 0 = off) is the diagonal-ratio route of the FP32 rung
+   (lsq_dbg_batch_route), fp64_share[i] in (0, 1) the share of compute units
+   the concurrent FP64 rung starts on (lsq_dbg_batch_split), pre[i] in [0, 8]
+   the number of the longest instances, per work-group of that rung, that it
+   solves in FP64 from the start instead of after an FP32 attempt
+   (lsq_dbg_batch_pre).  A batch no entry covers uses those three settings.
+   n = 0 clears the table.  Returns -2 for n < 0 or NULL arrays with n > 0,
+   -3 for an entry out of range (the table is then unchanged). */
 int lsq_batch_tuning(lsq_handle handle, int n, const int* max_dim, const double* route,
-                     const double* fp64_share, const double* pre);
+                     const double* fp64_share, const double* pre, const double* esc_max);
 
 /* Same-type conveniences: every descriptor must carry the matching type. */
 int lse_solve_batched(lsq_handle handle, int count, const lsq_problem* probs,

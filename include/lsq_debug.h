@@ -167,6 +167,11 @@ int lsq_dbg_batch_split(lsq_handle h, double fp64_share);
    [0, 8]. */
 int lsq_dbg_batch_pre(lsq_handle h, double per_wg);
 
+/* The escalation fraction of the handle's last FP32-first persistent batch
+   (the regime lsq_batch_tuning's esc_max compares against; 1 before any).
+   Returns -2 for a NULL pointer. */
+int lsq_dbg_batch_regime(lsq_handle h, double* last_escalation);
+
 /* Schedule of the last persistent batched call (lsq_solve_batched and the
    typed variants, persistent modes), from the device wall clock: for each of
    the first `count` problems of that call, out[6 i .. 6 i + 5] = start,

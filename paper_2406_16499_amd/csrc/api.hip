@@ -277,10 +277,13 @@ struct lsq_handle_st {
   double batch_route = kBatchRoute;             // diagonal-ratio route of the persistent FP32 rung
   double batch_fp64_share = 0.25;               // compute units the concurrent FP64 rung starts on
   double batch_pre = 0.0;                       // longest instances sent to FP64 at once, per FP64 work-group
-  // tuned (route, FP64 share, pre) per size bucket: the entry with the
-  // smallest bound >= the batch's largest dimension applies; none: the
-  // values above
-  struct BatchTune { int max_dim; double route, share, pre; };
+  // tuned (route, FP64 share, pre) per size bucket and escalation regime: of
+  // the entries whose bound is >= the batch's largest dimension and whose
+  // esc_max is >= the escalation fraction the last FP32-first persistent
+  // batch showed, the one with the smallest bound, then the smallest esc_max,
+  // applies; none: the values above
+  struct BatchTune { int max_dim; double route, share, pre, esc_max; };
+  double last_escalation = 1.0;                 // nothing seen yet: the regime with the most escalations
   std::vector<BatchTune> batch_tuning;
   float* sel_w = nullptr;                       // selector weights on the device (null: none)
   KernelTimer timer;
@@ -1467,10 +1470,13 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     int dim = 0;
     for (int q : cur) dim = std::max(dim, std::max(hp[q].m, std::max(hp[q].n, hp[q].p)));
     int best = -1;
-    for (int e = 0; e < (int)h->batch_tuning.size(); ++e)
-      if (h->batch_tuning[e].max_dim >= dim &&
-          (best < 0 || h->batch_tuning[e].max_dim < h->batch_tuning[best].max_dim))
+    for (int e = 0; e < (int)h->batch_tuning.size(); ++e) {
+      const auto& te = h->batch_tuning[e];
+      if (te.max_dim < dim || te.esc_max < h->last_escalation) continue;
+      if (best < 0 || te.max_dim < h->batch_tuning[best].max_dim ||
+          (te.max_dim == h->batch_tuning[best].max_dim && te.esc_max < h->batch_tuning[best].esc_max))
         best = e;
+    }
     if (best >= 0) {
       route = h->batch_tuning[best].route;
       fp64_share = h->batch_tuning[best].share;
@@ -1657,6 +1663,13 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
       for (int qq : cur)
         if (hout64[qq].info != -1) flops64 += batch_factor_flops(hp[qq]);
       ktimer_add(ctx, kKBatchEsc, flops64, 0.0);
+    }
+    // the regime for the next call's table entry: the share of the instances
+    // that tried the FP32 rung and did not certify there
+    if (prec == LSQ_PREC_FP32 && n > pre) {
+      int failed = 0;
+      for (int i = pre; i < n; ++i) failed += hout[cur[i]].info != 0;
+      h->last_escalation = (double)failed / (double)(n - pre);
     }
     std::vector<int> pending;
     for (int i = 0; i < n; ++i) {
@@ -1891,18 +1904,27 @@ int lsq_dbg_history(lsq_handle h, int max_steps, double* berr, int* rung) {
 }
 
 int lsq_batch_tuning(lsq_handle h, int n, const int* max_dim, const double* route,
-                     const double* fp64_share, const double* pre) {
+                     const double* fp64_share, const double* pre, const double* esc_max) {
   if (!h) return -1;
   if (n < 0 || (n > 0 && (!max_dim || !route || !fp64_share || !pre)))
     return fail(h, -2, "lsq_batch_tuning: bad table");
   std::vector<lsq_handle_st::BatchTune> t;
   for (int i = 0; i < n; ++i) {
+    const double em = esc_max ? esc_max[i] : 1.0;
     if (max_dim[i] < 1 || !(route[i] >= 0.0) || !(fp64_share[i] > 0.0 && fp64_share[i] < 1.0) ||
-        !(pre[i] >= 0.0 && pre[i] <= kMaxBatchPre))
+        !(pre[i] >= 0.0 && pre[i] <= kMaxBatchPre) || !(em >= 0.0 && em <= 1.0))
       return fail(h, -3, "lsq_batch_tuning: entry " + std::to_string(i) + " out of range");
-    t.push_back({max_dim[i], route[i], fp64_share[i], pre[i]});
+    t.push_back({max_dim[i], route[i], fp64_share[i], pre[i], em});
   }
   h->batch_tuning = std::move(t);
+  h->last_escalation = 1.0;
+  return 0;
+}
+
+int lsq_dbg_batch_regime(lsq_handle h, double* last_escalation) {
+  if (!h) return -1;
+  if (!last_escalation) return -2;
+  *last_escalation = h->last_escalation;
   return 0;
 }
 

@@ -124,7 +124,8 @@ _SIGS = {
     "lsq_dbg_batch_route": (c_int, [_P, ctypes.c_double]),
     "lsq_dbg_batch_split": (c_int, [_P, ctypes.c_double]),
     "lsq_dbg_batch_pre": (c_int, [_P, ctypes.c_double]),
-    "lsq_batch_tuning": (c_int, [_P, c_int, _P, _P, _P, _P]),
+    "lsq_batch_tuning": (c_int, [_P, c_int, _P, _P, _P, _P, _P]),
+    "lsq_dbg_batch_regime": (c_int, [_P, ctypes.POINTER(c_double)]),
     "lsq_dbg_history": (c_int, [_P, c_int, _P, _P]),
     "lsq_dbg_deterministic": (c_int, [_P, c_int]),
     "lsq_dbg_lookahead": (c_int, [_P, c_int]),
@@ -554,16 +555,27 @@ class Handle:
 
     def batch_tuning(self, entries) -> None:
         """Install the persistent batch's launch-shape table: entries of
-        (max_dim, route, fp64_share[, pre]); [] clears it."""
+        (max_dim, route, fp64_share[, pre[, esc_max]]); [] clears it and any
+        table resets the handle's escalation regime to 1."""
         n = len(entries)
         md = np.array([e[0] for e in entries], np.int32)
         rt = np.array([e[1] for e in entries], np.float64)
         sh = np.array([e[2] for e in entries], np.float64)
         pr = np.array([e[3] if len(e) > 3 else 0.0 for e in entries], np.float64)
+        em = np.array([e[4] if len(e) > 4 else 1.0 for e in entries], np.float64)
         rc = self.lib.lsq_batch_tuning(self.h, n, md.ctypes.data_as(c_void_p), rt.ctypes.data_as(c_void_p),
-                                       sh.ctypes.data_as(c_void_p), pr.ctypes.data_as(c_void_p))
+                                       sh.ctypes.data_as(c_void_p), pr.ctypes.data_as(c_void_p),
+                                       em.ctypes.data_as(c_void_p))
         if rc != 0:
             raise RuntimeError(f"lsq_batch_tuning = {rc}: {self.last_error()}")
+
+    def dbg_batch_regime(self) -> float:
+        """The escalation fraction of the last FP32-first persistent batch."""
+        v = c_double()
+        rc = self.lib.lsq_dbg_batch_regime(self.h, ctypes.byref(v))
+        if rc != 0:
+            raise RuntimeError(f"lsq_dbg_batch_regime = {rc}: {self.last_error()}")
+        return v.value
 
     def dbg_batch_pre(self, per_wg: float) -> None:
         rc = self.lib.lsq_dbg_batch_pre(self.h, float(per_wg))

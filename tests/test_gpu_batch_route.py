@@ -174,6 +174,49 @@ def test_pre_with_escalations(h):
             assert r in (("fp32", 1), ("fp64", 2)), (i, r)
 
 
+def _make(probs):
+    keep, descs = [], []
+    for P in probs:
+        if P.kind == "lse":
+            t = tuple(lsq.colmajor(a) for a in (P.A, P.B, P.b, P.d))
+            x, y = lsq.empty(P.shape[1]), None
+            descs.append(lsq.make_problem("lse", t, x))
+        else:
+            t = tuple(lsq.colmajor(a) for a in (P.W, P.V, P.d))
+            x, y = lsq.empty(P.shape[1]), lsq.empty(P.shape[2])
+            descs.append(lsq.make_problem("gls", t, x, y))
+        keep.append((t, x, y))
+    return probs, keep, descs
+
+
+def test_escalation_regime_picks_the_entry(h, batch):
+    # two entries for one bucket: one for any regime (6 of the 24 longest
+    # instances FP64 first), one while at most 2% escalated (none first)
+    note("regime: entry for any regime, then the low-escalation entry, then back")
+    probs = batch[0]
+    longest = set(sorted(range(len(probs)), key=lambda i: -_work(probs[i]))[:6])
+    ill = _make(list(wl.batch_instances(seed=85, count=20, kappa_max=1e12, m_range=(64, 300))))
+    h.dbg_batch_route(0.0)
+    try:
+        h.batch_tuning([(300, 0.0, 0.25, 0.25, 1.0), (300, 0.0, 0.25, 0.0, 0.02)])
+        assert h.dbg_batch_regime() == 1.0
+        for i, r in enumerate(_solve_check(h, batch)):
+            assert r == (("fp64", 1) if i in longest else ("fp32", 1)), (i, r)
+        assert h.dbg_batch_regime() == 0.0
+        assert all(r == ("fp32", 1) for r in _solve_check(h, batch))
+        rungs = _solve_check(h, ill)
+        assert all(r in (("fp32", 1), ("fp64", 2)) for r in rungs), rungs
+        failed = sum(r == ("fp64", 2) for r in rungs)
+        assert failed >= 1 and h.dbg_batch_regime() == failed / len(rungs)
+        for i, r in enumerate(_solve_check(h, batch)):
+            assert r == (("fp64", 1) if i in longest else ("fp32", 1)), (i, r)
+        h.batch_tuning([(300, 0.0, 0.25, 0.25, 1.0), (300, 0.0, 0.25, 0.0, 0.02)])
+        assert h.dbg_batch_regime() == 1.0      # a new table starts from the top regime
+    finally:
+        h.batch_tuning([])
+        h.dbg_batch_route(3e5)
+
+
 @pytest.mark.parametrize("share", [0.0625, 0.5])
 def test_fp64_share_keeps_results_certified(h, share):
     note(f"fp64 share {share}, 20 instances kappa<=1e12")

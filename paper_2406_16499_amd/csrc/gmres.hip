@@ -296,21 +296,31 @@ __global__ __launch_bounds__(256) void k_vec_segs_t(VecSegsT v) {
 }
 
 // The operator's three combines in one launch (blockIdx.y = block of F u).
+// A work-group covers 64 outputs; its four waves each add every fourth
+// partial product of both sums (the partials of one index are 64 contiguous
+// words per wave), and the first wave adds the four subtotals in a fixed
+// order, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void k_combine3(CombineArgs a0, CombineArgs a1, CombineArgs a2) {
+  __shared__ double red[2][4][64];
+  LSQ_LDS_POISON(red);
   const CombineArgs a = blockIdx.y == 0 ? a0 : (blockIdx.y == 1 ? a1 : a2);
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
+  if ((int)blockIdx.x * 64 >= a.n) return;      // the whole work-group: no barrier is skipped by part of it
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  double t1 = 0.0, t2 = 0.0;
+  if (i < a.n) {
+    if (a.p1)
+      for (int q = wv; q < a.np1; q += 4) t1 += a.p1[(size_t)q * a.n + i];
+    if (a.p2)
+      for (int q = wv; q < a.np2; q += 4) t2 += a.p2[(size_t)q * a.n + i];
+  }
+  red[0][wv][lane] = t1;
+  red[1][wv][lane] = t2;
+  __syncthreads();
+  if (wv != 0 || i >= a.n) return;
   double s = a.x0 ? a.c0 * a.x0[i] : 0.0;
-  if (a.p1) {
-    double t = 0.0;
-    for (int q = 0; q < a.np1; ++q) t += a.p1[(size_t)q * a.n + i];
-    s = fma(a.c1, t, s);
-  }
-  if (a.p2) {
-    double t = 0.0;
-    for (int q = 0; q < a.np2; ++q) t += a.p2[(size_t)q * a.n + i];
-    s = fma(a.c2, t, s);
-  }
+  if (a.p1) s = fma(a.c1, (red[0][0][lane] + red[0][1][lane]) + (red[0][2][lane] + red[0][3][lane]), s);
+  if (a.p2) s = fma(a.c2, (red[1][0][lane] + red[1][1][lane]) + (red[1][2][lane] + red[1][3][lane]), s);
   a.out[i] = s;
 }
 
@@ -352,7 +362,7 @@ void vec_segs_t(Ctx& ctx, std::initializer_list<VecSegT> segs) {
 void combine3(Ctx& ctx, const CombineArgs& a0, const CombineArgs& a1, const CombineArgs& a2) {
   const int nmax = std::max(a0.n, std::max(a1.n, a2.n));
   if (nmax <= 0) return;
-  hipLaunchKernelGGL(k_combine3, dim3(ceil_div(nmax, 256), 3), dim3(256), 0, ctx.stream, a0, a1, a2);
+  hipLaunchKernelGGL(k_combine3, dim3(ceil_div(nmax, 64), 3), dim3(256), 0, ctx.stream, a0, a1, a2);
   LSQ_LAUNCH_CHECK();
 }
 

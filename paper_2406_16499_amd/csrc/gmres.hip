@@ -27,24 +27,60 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 
 // part[b * kCgsMax + j] = sum over the rows of block b of V[i, j] w[i], j < kc.
+// Row i of the basis, columns j < kc, into registers (zero elsewhere).  The
+// loads are unconditional, at indexes clamped into the basis (rows past N
+// read row N - 1, columns past kc read column kc - 1, both then discarded),
+// so the compiler issues all of them before the first use: a pass waits for
+// memory once, not once per column.  Needs N >= 1 and kc >= 1.
+__device__ __forceinline__ void cgs_load_row(const double* __restrict__ V, int ldv, int N, int kc, int i,
+                                             double (&v)[kCgsMax]) {
+  const size_t ic = (size_t)(i < N ? i : N - 1);
+#pragma unroll
+  for (int j = 0; j < kCgsMax; ++j) {
+    const double x = V[ic + (size_t)(j < kc ? j : kc - 1) * ldv];
+    v[j] = (i < N && j < kc) ? x : 0.0;
+  }
+}
+
+// Block sums of v[j] * wi into part[b * kCgsMax + j] for j < kc (b = this
+// block).  Each wave reduces its 32 products with a reduce-scatter over lane
+// bits 5..1 (every step halves the values a lane holds; 32 exchanges in all
+// instead of 6 per column), after which lane l holds the wave sum of column
+// l >> 1; the four waves' sums are added in a fixed order.
+static_assert(kCgsMax == 32, "the reduce-scatter maps 32 columns onto lane pairs");
+__device__ __forceinline__ void cgs_block_dots(const double (&v)[kCgsMax], double wi, int kc,
+                                               double (*red)[kCgsMax], double* __restrict__ part) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double cp[kCgsMax];
+#pragma unroll
+  for (int j = 0; j < kCgsMax; ++j) cp[j] = v[j] * wi;
+#pragma unroll
+  for (int m = 32, c = kCgsMax; c > 1; m >>= 1, c >>= 1) {
+    const bool up = (lane & m) != 0;
+#pragma unroll
+    for (int q = 0; q < c / 2; ++q) {
+      const double send = up ? cp[q] : cp[q + c / 2];
+      const double keep = up ? cp[q + c / 2] : cp[q];
+      cp[q] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  cp[0] += __shfl_xor(cp[0], 1, 64);
+  if ((lane & 1) == 0) red[wv][lane >> 1] = cp[0];
+  __syncthreads();
+  if (t < kc) part[(size_t)blockIdx.x * kCgsMax + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+}
+
 __global__ __launch_bounds__(256) void k_cgs_dot(const double* __restrict__ V, int ldv, int N, int kc,
                                                  const double* __restrict__ w, double* __restrict__ part,
                                                  const double* __restrict__ stat) {
   __shared__ double red[4][kCgsMax];
   LSQ_LDS_POISON(red);
   if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int i = blockIdx.x * kCgsRows + t;
+  const int i = blockIdx.x * kCgsRows + threadIdx.x;
+  double v[kCgsMax];
+  cgs_load_row(V, ldv, N, kc, i, v);
   const double wi = i < N ? w[i] : 0.0;
-#pragma unroll 4
-  for (int j = 0; j < kCgsMax; ++j) {
-    if (j >= kc) break;
-    double s = i < N ? V[(size_t)i + (size_t)j * ldv] * wi : 0.0;
-    s = wave_sum_d(s);
-    if (lane == 0) red[wv][j] = s;
-  }
-  __syncthreads();
-  if (t < kc) part[(size_t)blockIdx.x * kCgsMax + t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+  cgs_block_dots(v, wi, kc, red, part);
 }
 
 // h = sum of the block partials; w -= V h; hacc (+)= h (written by block 0);
@@ -59,44 +95,47 @@ __global__ __launch_bounds__(256) void k_cgs_update(const double* __restrict__ V
                                                     const double* __restrict__ stat,
                                                     double* __restrict__ part_next) {
   __shared__ double h[kCgsMax];
+  __shared__ double hp[8][kCgsMax];
   __shared__ double red[4];
   __shared__ double red2[4][kCgsMax];
   LSQ_LDS_POISON(h);
+  LSQ_LDS_POISON(hp);
   LSQ_LDS_POISON(red);
   LSQ_LDS_POISON(red2);
   if (stat && stat[2] != 0.0) return;        // converged at an earlier iteration
   const int t = threadIdx.x;
-  if (t < kc) {
+  const int i = blockIdx.x * kCgsRows + t;
+  double v[kCgsMax];
+  cgs_load_row(V, ldv, N, kc, i, v);          // in flight while h is summed
+  {
+    // the block partials of column j = t & 31, every eighth one per group of
+    // 32 threads, then the eight group sums in a fixed order
+    const int j = t & (kCgsMax - 1), g = t / kCgsMax;
     double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kCgsMax + t];
-    h[t] = s;
-    if (blockIdx.x == 0) hacc[t] = accumulate ? hacc[t] + s : s;
+    if (j < kc)
+      for (int b = g; b < nblk; b += 8) s += part[(size_t)b * kCgsMax + j];
+    hp[g][j] = s;
   }
   __syncthreads();
-  const int i = blockIdx.x * kCgsRows + t;
-  double sq = 0.0, wi = 0.0;
-  if (i < N) {
-    wi = w[i];
-    for (int j = 0; j < kc; ++j) wi = fma(-V[(size_t)i + (size_t)j * ldv], h[j], wi);
-    w[i] = wi;
-    sq = wi * wi;
+  if (t < kCgsMax) {
+    double s = 0.0;
+    if (t < kc) {
+      s = ((hp[0][t] + hp[1][t]) + (hp[2][t] + hp[3][t])) + ((hp[4][t] + hp[5][t]) + (hp[6][t] + hp[7][t]));
+      if (blockIdx.x == 0) hacc[t] = accumulate ? hacc[t] + s : s;
+    }
+    h[t] = s;                                   // zero past kc: those fma terms leave wi unchanged
   }
+  __syncthreads();
+  double wi = i < N ? w[i] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kCgsMax; ++j) wi = fma(-v[j], h[j], wi);
+  double sq = wi * wi;
+  if (i < N) w[i] = wi;
   if (nrm) {
     sq = block_sum(sq, red);
     if (t == 0) nrm[blockIdx.x] = sq;
   }
-  if (part_next) {
-    const int lane = t & 63, wv = t >> 6;
-#pragma unroll 4
-    for (int j = 0; j < kCgsMax; ++j) {
-      if (j >= kc) break;
-      double s = i < N ? V[(size_t)i + (size_t)j * ldv] * wi : 0.0;
-      s = wave_sum_d(s);
-      if (lane == 0) red2[wv][j] = s;
-    }
-    __syncthreads();
-    if (t < kc) part_next[(size_t)blockIdx.x * kCgsMax + t] = red2[0][t] + red2[1][t] + red2[2][t] + red2[3][t];
-  }
+  if (part_next) cgs_block_dots(v, wi, kc, red2, part_next);
 }
 
 // Device state of one restart cycle: the rotated Hessenberg matrix H

@@ -13,6 +13,8 @@
 //    columns per work-group, one accumulator per column, block reduction).
 // Work-groups whose whole tile is masked out return at once.
 #pragma once
+#include <algorithm>
+#include <cstdint>
 #include "common.hpp"
 
 namespace lsq {
@@ -100,6 +102,75 @@ __global__ __launch_bounds__(256) void k_gemv_t(const S* __restrict__ A, int lda
   }
 }
 
+// T with 16-byte loads: each lane takes VN = 16 / sizeof(S) consecutive rows
+// of a column per load (a pass of the work-group covers 256 VN rows), eight
+// columns per work-group, the column loads of a pass all issued before the
+// first product.  Needs A 16-byte aligned, lda a multiple of VN and
+// rows_per_block a multiple of 256 VN; a ragged last group of rows falls back
+// to scalar loads.
+template <typename S> struct Vec16 {};
+template <> struct Vec16<float> { using T = float4; static constexpr int N = 4; };
+template <> struct Vec16<double> { using T = double2; static constexpr int N = 2; };
+
+template <typename S, typename TC, int MASK>
+__global__ __launch_bounds__(256) void k_gemv_tv(const S* __restrict__ A, int lda, int rows, int cols,
+                                                 int d, TC alpha, const TC* __restrict__ yv,
+                                                 TC* __restrict__ s, int rows_per_block) {
+  using V = typename Vec16<S>::T;
+  constexpr int VN = Vec16<S>::N;
+  constexpr int NC = 8;
+  __shared__ TC red[4][NC];
+  LSQ_LDS_POISON(red);
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int c0 = blockIdx.x * NC;
+  const int rb = blockIdx.y * rows_per_block, re = min(rows, rb + rows_per_block);
+  const int cl = min(cols, c0 + NC) - 1;
+  if (MASK == kUpper && rb - cl > d) return;
+  if (MASK == kUnitLower && (re - 1) - c0 < d) return;
+  TC acc[NC];
+#pragma unroll
+  for (int u = 0; u < NC; ++u) acc[u] = (TC)0;
+  for (int i0 = rb + VN * t; i0 < re; i0 += VN * 256) {
+    if (i0 + VN <= re) {
+      V a[NC];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        const int j = c0 + u < cols ? c0 + u : cols - 1;     // a column past the end: re-read, unused
+        a[u] = *reinterpret_cast<const V*>(A + (size_t)i0 + (size_t)j * lda);
+      }
+      TC yi[VN];
+#pragma unroll
+      for (int q = 0; q < VN; ++q) yi[q] = yv[i0 + q];
+#pragma unroll
+      for (int u = 0; u < NC; ++u) {
+        if (c0 + u >= cols) continue;
+        const S* av = reinterpret_cast<const S*>(&a[u]);
+#pragma unroll
+        for (int q = 0; q < VN; ++q)
+          acc[u] = fma(gemv_masked<MASK>((TC)av[q], i0 + q, c0 + u, d), yi[q], acc[u]);
+      }
+    } else {
+      for (int i = i0; i < re; ++i) {
+        const TC yi = yv[i];
+#pragma unroll
+        for (int u = 0; u < NC; ++u)
+          if (c0 + u < cols)
+            acc[u] = fma(gemv_masked<MASK>((TC)A[(size_t)i + (size_t)(c0 + u) * lda], i, c0 + u, d), yi, acc[u]);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < NC; ++u) {
+    const TC v = wave_sum(acc[u]);
+    if (lane == 0) red[w][u] = v;
+  }
+  __syncthreads();
+  if (t < NC && c0 + t < cols) {
+    const TC v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    if (v != (TC)0) atomicAdd(&s[c0 + t], alpha * v);
+  }
+}
+
 // Launchers (stream-ordered; y / s must hold the values to accumulate onto).
 // det: no two work-groups of one launch add into the same element, so the
 // sums do not depend on the order the work-groups finish in (gemv_n then
@@ -126,6 +197,20 @@ template <typename S, typename TC, int MASK>
 void gemv_t(hipStream_t st, const S* A, int lda, int rows, int cols, int d, TC alpha, const TC* yv, TC* s,
             bool det = false) {
   if (rows <= 0 || cols <= 0) return;
+  constexpr int VN = 16 / (int)sizeof(S);
+  if constexpr (sizeof(S) == 4 || sizeof(S) == 8) {
+    if (reinterpret_cast<uintptr_t>(A) % 16 == 0 && lda % VN == 0) {
+      // one pass of 256 VN rows per work-group, up to about 4096 work-groups
+      const int nbx = ceil_div(cols, 8), pass = 256 * VN;
+      int nby = std::min(ceil_div(rows, pass), ceil_div(4096, nbx));
+      if (nby < 1 || det) nby = 1;
+      const int rpb = ceil_div(ceil_div(rows, nby), pass) * pass;
+      nby = ceil_div(rows, rpb);
+      hipLaunchKernelGGL((k_gemv_tv<S, TC, MASK>), dim3(nbx, nby), dim3(256), 0, st, A, lda, rows, cols, d,
+                         alpha, yv, s, rpb);
+      return;
+    }
+  }
   const int nbx = ceil_div(cols, 16);
   int nby = ceil_div(rows, 256);
   const int want = ceil_div(2048, nbx);

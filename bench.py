@@ -47,7 +47,7 @@ KERNELS = {
     "wy_u": ("k_wy_u", "mfma", None, "TFLOP/s"),
     "wy_t": ("k_wy_t", "mfma", None, "TFLOP/s"),
     "dual_gemv": ("k_dual_gemv", "hbm", HBM_PEAK, "GB/s"),
-    "agg_gemv": ("k_gemv_t / k_gemv_n (aggregated reflector blocks)", "hbm", HBM_PEAK, "GB/s"),
+    "agg_gemv": ("k_gemv_tv / k_gemv_n (aggregated reflector blocks)", "hbm", HBM_PEAK, "GB/s"),
 }
 KERNEL_SOURCES = ["paper_2406_16499_amd/csrc/qr.hip", "paper_2406_16499_amd/csrc/wg64.hpp",
                   "paper_2406_16499_amd/csrc/vec.hip", "paper_2406_16499_amd/csrc/blas.hip",

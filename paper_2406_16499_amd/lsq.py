@@ -512,13 +512,16 @@ class Handle:
             raise RuntimeError(f"gls_factor = {rc}: {self.last_error()}")
         return Factors(self, f, "gls", (n, m, p), (W, V))
 
-    def lsq_solve_batched(self, problems, opts: Optional[Opts] = None, which: str = "lsq"):
-        arr = (Problem * len(problems))(*problems)
-        res = (Result * len(problems))()
+    def lsq_solve_batched(self, problems, opts: Optional[Opts] = None, which: str = "lsq", raw: bool = False):
+        """(rc, results) of one batched call.  problems: descriptors, or the
+        array problem_array() built from them once (no per-call marshalling);
+        raw: the results as the ctypes array instead of a list."""
+        arr = problems if isinstance(problems, ctypes.Array) else problem_array(problems)
+        res = (Result * len(arr))()
         fn = {"lsq": self.lib.lsq_solve_batched, "lse": self.lib.lse_solve_batched,
               "gls": self.lib.gls_solve_batched}[which]
-        rc = fn(self.h, len(problems), arr, ctypes.byref(opts) if opts is not None else None, res)
-        return rc, list(res)
+        rc = fn(self.h, len(arr), arr, ctypes.byref(opts) if opts is not None else None, res)
+        return rc, (res if raw else list(res))
 
     def batch_plan(self, problems, opts: Optional[Opts] = None, keep=None) -> "BatchPlan":
         return BatchPlan(self, problems, opts, keep)
@@ -724,6 +727,11 @@ class Handle:
                                              n, m, p, _ptr(W), _ld(W), _ptr(V), _ld(V), _ptr(f1),
                                              _ptr(f2), _ptr(f3), _ptr(dy), _ptr(dz), _ptr(dx))
         return rc, dy, dz, dx
+
+
+def problem_array(problems):
+    """The C array of batch descriptors that the batched entry points read."""
+    return (Problem * len(problems))(*problems)
 
 
 def make_problem(kind, tensors, x, y=None) -> Problem:

@@ -127,6 +127,25 @@ def test_batched_matches_single_instance_calls(h):
             assert r1.prec_used == r.prec_used and r1.solver_used == r.solver_used
 
 
+def test_batched_prebuilt_array_and_raw_results(h):
+    # the descriptors marshalled once and the results as the C array: the same
+    # rungs and certified results as the list form, on repeated calls
+    note("batched prebuilt descriptor array, raw results")
+    probs = list(wl.batch_instances(seed=43, count=12, kappa_max=1e6, m_range=(64, 300)))
+    keep, descs = _descriptors(probs)
+    arr = lsq.problem_array(descs)
+    assert len(arr) == len(descs)
+    opts = lsq.default_opts(prec="fp32", escalate=1)
+    rc, ref = h.lsq_solve_batched(descs, opts)
+    assert rc == 0 and isinstance(ref, list)
+    for _ in range(2):
+        rc, res = h.lsq_solve_batched(arr, opts, raw=True)
+        assert rc == 0 and len(res) == len(probs) and not isinstance(res, list)
+        for P, (t, x, y), r, r0 in zip(probs, keep, res, ref):
+            _check(P, x.cpu().numpy(), None if y is None else y.cpu().numpy(), r)
+            assert (r.prec_used, r.solver_used, r.attempts) == (r0.prec_used, r0.solver_used, r0.attempts)
+
+
 def test_batched_rejects_invalid_descriptor(h):
     note("batched invalid descriptor")
     probs = list(wl.batch_instances(seed=43, count=2, kappa_max=1e2, m_range=(64, 100)))

@@ -369,7 +369,7 @@ def batched(args):
     tg = time.perf_counter()
     resg_all = []
     for _ in range(args.steps):
-        rcg, resg = plan.run()
+        rcg, resg = plan.run(raw=True)
         resg_all.append(resg)
     torch.cuda.synchronize()
     dtg = time.perf_counter() - tg

@@ -368,11 +368,11 @@ class BatchPlan:
         self.p = ptr
         _LIVE_FACTORS.add(self)
 
-    def run(self):
-        """Replay; (rc, [Result] in the order of creation)."""
+    def run(self, raw: bool = False):
+        """Replay; (rc, [Result] in the order of creation; raw: the ctypes array)."""
         res = (Result * self.count)()
         rc = self.handle.lib.lsq_batch_plan_run(self.p, res)
-        return rc, list(res)
+        return rc, (res if raw else list(res))
 
     def close(self):
         if self.p:

@@ -371,7 +371,8 @@ int lsq_set_batch_mode(lsq_handle handle, int mode);
    the concurrent FP64 rung starts on (lsq_dbg_batch_split), pre[i] in [0, 8]
    the number of the longest instances, per work-group of that rung, that it
    solves in FP64 from the start instead of after an FP32 attempt
-   (lsq_dbg_batch_pre).  A batch no entry covers uses those three settings.
+   (lsq_dbg_batch_pre; at most 7/8 of the batch's instances, so the FP32 rung
+   always sees part of it).  A batch no entry covers uses those three settings.
    n = 0 clears the table.  Returns -2 for n < 0 or NULL arrays with n > 0,
    -3 for an entry out of range (the table is then unchanged). */
 int lsq_batch_tuning(lsq_handle handle, int n, const int* max_dim, const double* route,

@@ -160,7 +160,7 @@ int lsq_dbg_batch_split(lsq_handle h, double fp64_share);
 
 /* Longest instances of the concurrent persistent batch (the head of its
    longest-first order), per work-group of the FP64 rung, that the rung solves
-   in FP64 from the start (default 0; rounded to a count, at most the batch).
+   in FP64 from the start (default 0; rounded to a count, at most 7/8 of the batch).
    The largest instances take about as long in FP32 as in FP64 on one
    work-group, so one that escalates would put both attempts on the launch's
    critical path.  Such an instance reports one attempt.  Returns -2 outside

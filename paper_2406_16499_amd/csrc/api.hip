@@ -1602,7 +1602,9 @@ std::vector<int> batch_persistent(lsq_handle h, const lsq_problem* probs, const 
     // the longest instances (the head of the order) that the FP64 rung takes
     // at once: an FP32 attempt that escalates would put both attempts of one
     // of them on the launch's critical path
-    const int pre = std::min(n, (int)std::lround(pre_share * g64a));
+    // at most 7/8 of the batch: the FP32 rung always sees part of it, where
+    // the escalation fraction that picks the next call's table entry is measured
+    const int pre = std::min(n - (n + 7) / 8, (int)std::lround(pre_share * g64a));
     // the FP32 launch's work for its timer: the instances it factors
     double flops = 0.0;
     for (int i = pre; i < n; ++i) flops += batch_factor_flops(hp[cur[i]]);
